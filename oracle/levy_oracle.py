@@ -1,0 +1,317 @@
+"""Plain CPU FP64 oracle for the Crank-Nicolson / Levy-generator path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The product path
+(the HIP library and its Python binding) never imports, calls or links it, and
+this module imports nothing from the product package.
+
+What it computes (Xu & Darve, arXiv 1812.08324):
+
+* the discrete generator ``G`` of the model equation (Sec. 3.1, eq. equ:ut):
+  diffusion ``a*Laplacian_h``, drift ``b*D_h`` (central difference), killing
+  ``c``, and the jump operator discretised by singularity subtraction
+  (Sec. 4, eqs. equ:evalIx1d, equ:I1approx, equ:I2approx, equ:I3approx),
+  as a plain dense matrix, one row at a time;
+* the Crank-Nicolson recursion (Sec. 3.2, eq. equ:scheme) with the
+  trapezoidal forcing term, solved by dense LU with partial pivoting
+  (LAPACK getrf/getrs through scipy).
+
+Nothing here is blocked, compressed or reordered: the H-matrix method must
+reproduce these results up to its truncation tolerance.
+
+Readings of the paper taken here (the paper is garbled or silent on them):
+
+* Sign convention.  The paper writes ``A = -G``; here ``G`` is the generator,
+  ``M = I - dt/2 G`` and ``Mp = I + dt/2 G`` (Sec. 3.2, eq. equ:Aij).
+* Window ``rho``: the indicator of the infinity-norm ball of radius
+  ``r = m*h`` with ``m = round(r0/h)``, weight 1/2 on its boundary nodes
+  (Sec. 4, eq. equ:rho_condition leaves the shape open).  In 2D it is the
+  product of the 1D node weights.
+* The u'' term of equ:I1approx carries the trapezoid weights ``w_j``
+  (dimensionally required); the u' term vanishes for the symmetric kernels
+  used here.  Net local term: ``(C2 - S2)/2 * Laplacian_h u``.
+* The window half-width ``L_W`` equals the domain extent, so every in-domain
+  offset lies inside the window and the far field ``f^{L_W}`` is zero under
+  the zero-exterior condition (Sec. 4, closing remark).
+* In 2D the singularity subtraction uses ``int rho nu y_i y_j = delta_ij C2``
+  (radial kernel, square window), giving the 5-point Laplacian.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.integrate as integrate
+import scipy.linalg as sla
+import scipy.special as sp
+
+__all__ = [
+    "Problem", "frac_const", "ball_const", "gauss_const", "grid", "h_of",
+    "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
+    "cn_run", "kernel_nu",
+]
+
+
+# ---------------------------------------------------------------------------
+# Closed-form constants
+# ---------------------------------------------------------------------------
+def frac_const(d: int, s: float) -> float:
+    """c_{d,s} = 4^s Gamma(d/2+s) / (pi^{d/2} |Gamma(-s)|)  (Sec. 1, Sec. 4)."""
+    return 4.0 ** s * sp.gamma(d / 2.0 + s) / (math.pi ** (d / 2.0) * abs(sp.gamma(-s)))
+
+
+def ball_const(d: int, s: float) -> float:
+    """(-Delta)^s (1-|x|^2)_+^s on the unit ball:
+    2^{2s} Gamma(1+s) Gamma(d/2+s) / Gamma(d/2)  (Sec. 5.3, eq. equ:u1)."""
+    return 4.0 ** s * sp.gamma(1.0 + s) * sp.gamma(d / 2.0 + s) / sp.gamma(d / 2.0)
+
+
+def gauss_const(d: int, s: float) -> float:
+    """(-Delta)^s exp(-|x|^2) at x = 0: 4^s Gamma(d/2+s)/Gamma(d/2)
+    (Sec. 5.3, eq. equ:u0 for d = 1)."""
+    return 4.0 ** s * sp.gamma(d / 2.0 + s) / sp.gamma(d / 2.0)
+
+
+# ---------------------------------------------------------------------------
+# Problem description
+# ---------------------------------------------------------------------------
+@dataclass
+class Problem:
+    """Model equation u_t = a Lap u + b.grad u + c u + L u on a box with zero
+    exterior (Sec. 3.1 eq. equ:ut; Sec. 4 closing remark).
+
+    Jump kernel nu(y) = C exp(-lam |y|) / |y|^{d+2s}; C = None selects c_{d,s}
+    (then lam = 0 is exactly the fractional Laplacian, Sec. 4).
+    """
+    dim: int
+    n: int                       # interior points per axis
+    lo: float = -1.0
+    hi: float = 1.0
+    a: float = 0.0
+    b: tuple = (0.0, 0.0)
+    c: float = 0.0
+    s: float = 0.5
+    lam: float = 0.0
+    C: float | None = None
+    r0: float = 0.2              # window radius before snapping to the grid
+    jumps: bool = True           # False drops the jump operator (nu = 0)
+
+    @property
+    def N(self) -> int:
+        return self.n if self.dim == 1 else self.n * self.n
+
+    @property
+    def Cval(self) -> float:
+        return frac_const(self.dim, self.s) if self.C is None else float(self.C)
+
+
+def h_of(p: Problem) -> float:
+    return (p.hi - p.lo) / (p.n + 1)
+
+
+def grid(p: Problem) -> np.ndarray:
+    """Interior grid points, lexicographic order (first coordinate slowest).
+    Returns an (N, dim) array."""
+    h = h_of(p)
+    x1 = p.lo + h * np.arange(1, p.n + 1, dtype=np.float64)
+    if p.dim == 1:
+        return x1[:, None]
+    X, Y = np.meshgrid(x1, x1, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def kernel_nu(p: Problem, r):
+    """nu at distance r > 0."""
+    r = np.asarray(r, dtype=np.float64)
+    return p.Cval * np.exp(-p.lam * r) / r ** (p.dim + 2.0 * p.s)
+
+
+# ---------------------------------------------------------------------------
+# Quadrature constants of the singularity subtraction (Sec. 4)
+# ---------------------------------------------------------------------------
+def _trap_w(k, NW, h):
+    """Trapezoid weights on the window grid: h inside, h/2 at |k| = NW."""
+    k = np.abs(k)
+    return np.where(k == NW, 0.5 * h, h)
+
+
+def _rho_w(k, m):
+    """Grid window weights: 1 inside, 1/2 on the boundary |k| = m, 0 outside."""
+    k = np.abs(k)
+    return np.where(k < m, 1.0, np.where(k == m, 0.5, 0.0))
+
+
+def _Rtheta(theta):
+    return 1.0 / np.maximum(np.abs(np.cos(theta)), np.abs(np.sin(theta)))
+
+
+def _quad_theta(f):
+    """int_0^{2 pi} f(theta) d theta, split at the corners of the square."""
+    tot = 0.0
+    for q in range(8):
+        val, _ = integrate.quad(f, q * math.pi / 4, (q + 1) * math.pi / 4,
+                                epsabs=0.0, epsrel=1e-13, limit=200)
+        tot += val
+    return tot
+
+
+def quadrature_constants(p: Problem) -> dict:
+    """S0, S2 (grid sums, zero offset excluded), C2 = int rho nu y_1^2 and
+    T = int_{outside window} nu  (Sec. 4, equ:I1approx..equ:I3approx).
+
+    S0 = sum' W_k nu(kh)                   (coefficient of -u_i in I1)
+    S2 = sum' W_k rho_k nu(kh) (k_1 h)^2    (coefficient of the u'' term in I1)
+    C2 = int rho(y) nu(y) y_1^2 dy          (local diffusion term I3)
+    T  = int_{|y|_inf > L_W} nu(y) dy       (I2 with zero far field)
+    """
+    h = h_of(p)
+    NW = p.n + 1                     # L_W = (n+1) h = domain extent
+    LW = NW * h
+    m = int(round(p.r0 / h))
+    r = m * h
+    C, s, lam, d = p.Cval, p.s, p.lam, p.dim
+    if not p.jumps:
+        return dict(S0=0.0, S2=0.0, C2=0.0, T=0.0, h=h, NW=NW, m=m, r=r, LW=LW)
+    k = np.arange(-NW, NW + 1)
+    nz = k != 0
+    if d == 1:
+        kk = k[nz]
+        w = _trap_w(kk, NW, h)
+        nu = kernel_nu(p, np.abs(kk) * h)
+        S0 = math.fsum(w * nu)
+        S2 = math.fsum(w * _rho_w(kk, m) * nu * (kk * h) ** 2)
+        if lam == 0.0:
+            C2 = 2.0 * C * r ** (2.0 - 2.0 * s) / (2.0 - 2.0 * s)
+            T = C * LW ** (-2.0 * s) / s
+        else:
+            a2 = 2.0 - 2.0 * s
+            C2 = 2.0 * C * lam ** (-a2) * sp.gammainc(a2, lam * r) * sp.gamma(a2)
+            val, _ = integrate.quad(lambda y: np.exp(-lam * y) * y ** (-1.0 - 2.0 * s),
+                                    LW, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
+            T = 2.0 * C * val
+    else:
+        K1, K2 = np.meshgrid(k, k, indexing="ij")
+        K1 = K1.ravel(); K2 = K2.ravel()
+        nz2 = (K1 != 0) | (K2 != 0)
+        K1 = K1[nz2]; K2 = K2[nz2]
+        W = _trap_w(K1, NW, h) * _trap_w(K2, NW, h)
+        rr = np.hypot(K1 * h, K2 * h)
+        nu = kernel_nu(p, rr)
+        S0 = math.fsum(W * nu)
+        S2 = math.fsum(W * _rho_w(K1, m) * _rho_w(K2, m) * nu * (K1 * h) ** 2)
+        if lam == 0.0:
+            C2 = C * r ** (2.0 - 2.0 * s) / (2.0 - 2.0 * s) * _quad_theta(
+                lambda t: math.cos(t) ** 2 * _Rtheta(t) ** (2.0 - 2.0 * s))
+            T = C * LW ** (-2.0 * s) / (2.0 * s) * _quad_theta(
+                lambda t: _Rtheta(t) ** (-2.0 * s))
+        else:
+            a2 = 2.0 - 2.0 * s
+
+            def inner_c2(t):
+                R = r * _Rtheta(t)
+                return math.cos(t) ** 2 * lam ** (-a2) * sp.gammainc(a2, lam * R) * sp.gamma(a2)
+
+            def inner_t(t):
+                R = LW * _Rtheta(t)
+                v, _ = integrate.quad(lambda q: np.exp(-lam * q) * q ** (-1.0 - 2.0 * s),
+                                      R, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
+                return v
+
+            C2 = C * _quad_theta(inner_c2)
+            T = C * _quad_theta(inner_t)
+    return dict(S0=S0, S2=S2, C2=C2, T=T, h=h, NW=NW, m=m, r=r, LW=LW)
+
+
+# ---------------------------------------------------------------------------
+# Dense generator, row by row
+# ---------------------------------------------------------------------------
+def generator_row(p: Problem, i: int, consts: dict | None = None) -> np.ndarray:
+    """Row i of the dense generator G (length N) for the zero-exterior box.
+
+    Off-diagonal: the trapezoid jump entry W_k nu(kh) for every in-domain
+    offset k (Sec. 4: far entries stay nu_j h), plus the local terms on the
+    nearest neighbours: (C2-S2)/(2h^2) from equ:I1approx/equ:I3approx,
+    a/h^2 (diffusion) and +-b/(2h) (central drift).
+    Diagonal: -S0 - T (equ:I1approx, equ:I2approx), -d (C2-S2)/h^2 from the
+    local Laplacian, -2 d a/h^2, and c.
+    """
+    if consts is None:
+        consts = quadrature_constants(p)
+    h = consts["h"]
+    n, d = p.n, p.dim
+    N = p.N
+    row = np.zeros(N, dtype=np.float64)
+    beta = 0.5 * (consts["C2"] - consts["S2"])
+    if d == 1:
+        j = np.arange(n)
+        k = j - i
+        if p.jumps:
+            off = k != 0
+            row[off] = h * kernel_nu(p, np.abs(k[off]) * h)
+        for kk, sgn in ((-1, -1.0), (1, 1.0)):
+            jj = i + kk
+            if 0 <= jj < n:
+                row[jj] += (beta + p.a) / h ** 2 + sgn * p.b[0] / (2.0 * h)
+        row[i] = -consts["S0"] - consts["T"] - 2.0 * (beta + p.a) / h ** 2 + p.c
+        return row
+    # 2D, index = p1*n + q1 (first coordinate slowest)
+    p1, q1 = divmod(i, n)
+    P, Q = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    K1 = (P - p1).ravel(); K2 = (Q - q1).ravel()
+    if p.jumps:
+        off = (K1 != 0) | (K2 != 0)
+        row[off] = h * h * kernel_nu(p, np.hypot(K1[off] * h, K2[off] * h))
+    for axis in (0, 1):
+        for sgn in (-1, 1):
+            pp, qq = p1 + (sgn if axis == 0 else 0), q1 + (sgn if axis == 1 else 0)
+            if 0 <= pp < n and 0 <= qq < n:
+                row[pp * n + qq] += (beta + p.a) / h ** 2 + sgn * p.b[axis] / (2.0 * h)
+    row[i] = -consts["S0"] - consts["T"] - 4.0 * (beta + p.a) / h ** 2 + p.c
+    return row
+
+
+def generator_dense(p: Problem) -> np.ndarray:
+    """The full N x N generator, stacked from generator_row."""
+    consts = quadrature_constants(p)
+    G = np.empty((p.N, p.N), dtype=np.float64)
+    for i in range(p.N):
+        G[i] = generator_row(p, i, consts)
+    return G
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson (Sec. 3.2, eq. equ:scheme) with trapezoidal forcing
+# ---------------------------------------------------------------------------
+def cn_matrices(G: np.ndarray, dt: float):
+    """M = I - dt/2 G (left side), Mp = I + dt/2 G (right side)."""
+    I = np.eye(G.shape[0])
+    return I - 0.5 * dt * G, I + 0.5 * dt * G
+
+
+@dataclass
+class CNResult:
+    u: np.ndarray
+    norms: list = field(default_factory=list)
+
+
+def cn_run(G: np.ndarray, dt: float, steps: int, u0: np.ndarray,
+           g: np.ndarray | None = None, phi: np.ndarray | None = None,
+           keep_norms: bool = False) -> CNResult:
+    """u^{n+1} = M^{-1} (Mp u^n + dt/2 (f^n + f^{n+1})),  f^n = phi[n] g.
+
+    M is factored once with LAPACK getrf (partial pivoting); each step is one
+    dense product and one getrs.
+    """
+    M, Mp = cn_matrices(G, dt)
+    lu = sla.lu_factor(M)
+    u = np.array(u0, dtype=np.float64, copy=True)
+    norms = [float(np.linalg.norm(u))] if keep_norms else []
+    for n in range(steps):
+        rhs = Mp @ u
+        if g is not None:
+            rhs = rhs + 0.5 * dt * (phi[n] + phi[n + 1]) * g
+        u = sla.lu_solve(lu, rhs)
+        if keep_norms:
+            norms.append(float(np.linalg.norm(u)))
+    return CNResult(u=u, norms=norms)

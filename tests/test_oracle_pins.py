@@ -1,0 +1,326 @@
+"""Pins of the CPU oracle against facts it does not compute itself: closed
+forms, Fourier symbols, special cases with exact solutions, invariants.
+
+Each test would fail under a plausible slip in the oracle: a dropped window
+weight, a wrong sign of T, C2 or the drift, a wrong Laplacian coefficient, a
+transposed drift, a wrong forcing average, a wrong c_{d,s}.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as integrate
+import scipy.linalg as sla
+import scipy.special as sp
+
+from oracle.levy_oracle import (Problem, ball_const, cn_run, frac_const,
+                                gauss_const, generator_dense, generator_row,
+                                grid, quadrature_constants)
+
+
+def _order(e1, e2):
+    return math.log(abs(e1) / abs(e2), 2.0)
+
+
+# ---------------------------------------------------------------------------
+# constants
+# ---------------------------------------------------------------------------
+def test_frac_const_half_is_one_over_pi():
+    # the s = 1/2 fractional Laplacian in 1D has kernel 1/(pi y^2)
+    assert frac_const(1, 0.5) == pytest.approx(1.0 / math.pi, rel=1e-14)
+
+
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75])
+def test_frac_const_fourier_symbol(s):
+    # c_{1,s} int (1 - cos y) / |y|^{1+2s} dy = |xi|^{2s} at xi = 1
+    f1 = lambda y: 2.0 * math.sin(0.5 * y) ** 2 / (y * y) if y > 0 else 0.5   # smooth near 0
+    a, _ = integrate.quad(f1, 0.0, 1.0, weight="alg", wvar=(1.0 - 2.0 * s, 0.0),
+                          epsabs=0, epsrel=1e-12)
+    b, _ = integrate.quad(lambda y: y ** (-1.0 - 2.0 * s), 1.0, np.inf, epsabs=0, epsrel=1e-12)
+    c, _ = integrate.quad(lambda y: y ** (-1.0 - 2.0 * s), 1.0, np.inf, weight="cos", wvar=1.0)
+    integral = 2.0 * (a + b - c)
+    assert frac_const(1, s) * integral == pytest.approx(1.0, rel=1e-8)
+
+
+def test_ball_const_values():
+    # K(1, 1/2) = 1 (the forcing amplitude of the s = 1/2 workload)
+    assert ball_const(1, 0.5) == pytest.approx(1.0, rel=1e-14)
+    # d = 2: 4^s Gamma(1+s)^2
+    for s in (0.25, 0.75):
+        assert ball_const(2, s) == pytest.approx(4 ** s * math.gamma(1 + s) ** 2, rel=1e-14)
+
+
+def test_tempered_constants_limits_and_recurrence():
+    # lambda -> 0 of the tempered quadrature constants is the fractional case
+    p0 = Problem(dim=1, n=255, s=0.75, lam=0.0)
+    p1 = Problem(dim=1, n=255, s=0.75, lam=1e-9)
+    c0, c1 = quadrature_constants(p0), quadrature_constants(p1)
+    for key in ("S0", "S2", "C2", "T"):
+        assert c1[key] == pytest.approx(c0[key], rel=1e-7)
+    # lambda > 0: T = 2C lam^{2s} Gamma(-2s, lam L_W), evaluated here through the
+    # recurrence Gamma(a, x) = (Gamma(a+1, x) - x^a e^{-x}) / a
+    for s in (0.3, 0.75):
+        p = Problem(dim=1, n=255, s=s, lam=1.3)
+        cc = quadrature_constants(p)
+        x = p.lam * cc["LW"]
+
+        def upper(a):
+            if a > 0:
+                return sp.gammaincc(a, x) * sp.gamma(a)
+            return (upper(a + 1.0) - x ** a * math.exp(-x)) / a
+
+        T = 2.0 * p.Cval * p.lam ** (2 * s) * upper(-2.0 * s)
+        assert cc["T"] == pytest.approx(T, rel=1e-10)
+        # C2 = 2C int_0^r y^{1-2s} e^{-lam y} dy by direct quadrature
+        v, _ = integrate.quad(lambda y: math.exp(-p.lam * y), 0.0, cc["r"], weight="alg",
+                              wvar=(1.0 - 2.0 * s, 0.0), epsabs=0, epsrel=1e-13)
+        assert cc["C2"] == pytest.approx(2.0 * p.Cval * v, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# operator against closed forms (Sec. 5.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75])
+def test_ball_pin_1d(s):
+    """(-Delta)^s (1-x^2)_+^s = K(1,s) on (-1,1); zero exterior is exact here.
+    Observed order at x = 0 and 0.5 about 1 + s (solution only C^s)."""
+    errs = []
+    for n in (511, 1023):
+        p = Problem(dim=1, n=n, s=s)
+        x = grid(p)[:, 0]
+        u = np.maximum(1 - x * x, 0.0) ** s
+        idx = [int(np.argmin(abs(x))), int(np.argmin(abs(x - 0.5)))]
+        cst = quadrature_constants(p)
+        v = np.array([-(generator_row(p, i, cst) @ u) for i in idx])
+        errs.append(v - ball_const(1, s))
+    e1, e2 = np.abs(errs[0]), np.abs(errs[1])
+    assert np.all(e2 < 1.5e-4)
+    orders = np.log2(e1 / e2)
+    assert np.all(orders > 1.0 + s - 0.3), orders
+
+
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75, 0.9])
+def test_gaussian_pin_1d(s):
+    """(-Delta)^s e^{-x^2}(0) = 4^s Gamma(1/2+s)/sqrt(pi) (equ:u0): O(h^2)."""
+    errs = []
+    for n in (999, 1999):
+        p = Problem(dim=1, n=n, lo=-5.0, hi=5.0, s=s)
+        x = grid(p)[:, 0]
+        i0 = n // 2
+        assert x[i0] == pytest.approx(0.0, abs=1e-12)
+        v = -(generator_row(p, i0) @ np.exp(-x * x))
+        errs.append(v - gauss_const(1, s))
+    assert abs(errs[1]) < 1e-5
+    assert _order(*errs) > (1.5 if s > 0.85 else 1.85)
+
+
+@pytest.mark.parametrize("s,lam", [(0.3, 0.7), (0.75, 1.0)])
+def test_tempered_gaussian_pin_1d(s, lam):
+    """Tempered kernel: the continuum value int (e^{-y^2} - 1) nu(y) dy at x = 0
+    by adaptive quadrature; the discrete operator converges at O(h^2)."""
+    C = frac_const(1, s)
+    F = lambda y: (math.exp(-y * y) - 1.0) / (y * y) * math.exp(-lam * y) if y > 0 else -1.0
+    a, _ = integrate.quad(F, 0.0, 1.0, weight="alg", wvar=(1.0 - 2.0 * s, 0.0),
+                          epsabs=0, epsrel=1e-13)
+    b, _ = integrate.quad(lambda y: (math.exp(-y * y) - 1.0) * math.exp(-lam * y) * y ** (-1 - 2 * s),
+                          1.0, np.inf, epsabs=0, epsrel=1e-13, limit=200)
+    exact = 2.0 * C * (a + b)
+    errs = []
+    for n in (999, 1999):
+        p = Problem(dim=1, n=n, lo=-5.0, hi=5.0, s=s, lam=lam)
+        x = grid(p)[:, 0]
+        v = generator_row(p, n // 2) @ np.exp(-x * x)
+        errs.append(v - exact)
+    assert abs(errs[1]) < 1e-5
+    assert _order(*errs) > 1.8
+
+
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_gaussian_pin_2d(s):
+    """(-Delta)^s e^{-|x|^2}(0) = 4^s Gamma(1+s) in 2D: O(h^2) (square window,
+    5-point local term)."""
+    errs = []
+    for n in (159, 319):
+        p = Problem(dim=2, n=n, lo=-4.0, hi=4.0, s=s)
+        X = grid(p)
+        i0 = (n // 2) * n + n // 2
+        assert np.allclose(X[i0], 0.0)
+        v = -(generator_row(p, i0) @ np.exp(-(X * X).sum(1)))
+        errs.append(v - gauss_const(2, s))
+    assert _order(*errs) > 1.85
+    assert abs(errs[1]) < (4e-5 if s < 0.5 else 1e-3)
+
+
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_ball_pin_2d_centre(s):
+    """(-Delta)^s (1-|x|^2)_+^s = K(2,s) at the centre of the unit disc; the
+    paper reports a 4e-2 centre error for this test."""
+    errs = []
+    for n in (63, 127):
+        p = Problem(dim=2, n=n, lo=-1.0, hi=1.0, s=s)
+        X = grid(p)
+        i0 = (n // 2) * n + n // 2
+        v = -(generator_row(p, i0) @ np.maximum(1 - (X * X).sum(1), 0.0) ** s)
+        errs.append(v - ball_const(2, s))
+    assert abs(errs[1]) < abs(errs[0]) < 4e-2
+
+
+# ---------------------------------------------------------------------------
+# structure and invariants
+# ---------------------------------------------------------------------------
+def test_jump_part_symmetric_toeplitz_1d():
+    p = Problem(dim=1, n=200, s=0.75, lam=1.0, a=0.05, b=(0.0, 0.0))
+    G = generator_dense(p)
+    assert np.array_equal(G, G.T)
+    # Toeplitz: every diagonal is constant
+    for k in (0, 1, 2, 17, 150):
+        d = np.diagonal(G, k)
+        assert np.all(d == d[0])
+
+
+def test_jump_part_symmetric_bttb_2d():
+    p = Problem(dim=2, n=12, lo=0.0, hi=1.0, s=0.25)
+    G = generator_dense(p)
+    assert np.allclose(G, G.T, rtol=0, atol=0)
+    n = p.n
+    # block Toeplitz with Toeplitz blocks: G[(p,q),(p',q')] depends on p'-p, q'-q
+    B = G.reshape(n, n, n, n)
+    for dp in (0, 1, 5):
+        for dq in (-3, 0, 2):
+            vals = [B[i, j, i + dp, j + dq] for i in range(n - dp) for j in range(max(0, -dq), min(n, n - dq))]
+            assert np.allclose(vals, vals[0], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("dim,n,s,lam", [(1, 301, 0.4, 0.0), (1, 301, 0.8, 1.5), (2, 21, 0.6, 0.0)])
+def test_generator_annihilates_constants(dim, n, s, lam):
+    """Applied to u = 1 on the whole window grid with the far field
+    f = int_{outside} nu * 1, the discrete operator gives 0.  On the box the
+    row sum therefore equals -(T + weights of the offsets that leave the box)."""
+    lo, hi = (-1.0, 1.0) if dim == 1 else (0.0, 1.0)
+    p = Problem(dim=dim, n=n, lo=lo, hi=hi, s=s, lam=lam)
+    cst = quadrature_constants(p)
+    h, NW = cst["h"], cst["NW"]
+    i = n // 3 if dim == 1 else (n // 3) * n + n // 5
+    row = generator_row(p, i, cst)
+    k = np.arange(-NW, NW + 1)
+    w = np.where(np.abs(k) == NW, 0.5 * h, h)
+    if dim == 1:
+        j = i + k
+        out = ((j < 0) | (j >= n)) & (k != 0)
+        lost = np.sum(w[out] * p.Cval * np.exp(-lam * np.abs(k[out]) * h) / (np.abs(k[out]) * h) ** (1 + 2 * s))
+    else:
+        p1, q1 = divmod(i, n)
+        K1, K2 = np.meshgrid(k, k, indexing="ij")
+        W = np.outer(w, w)
+        out = ((p1 + K1 < 0) | (p1 + K1 >= n) | (q1 + K2 < 0) | (q1 + K2 >= n))
+        rr = np.hypot(K1[out] * h, K2[out] * h)
+        lost = np.sum(W[out] * p.Cval / rr ** (2 + 2 * s))
+    total = row.sum() + lost + cst["T"]
+    assert abs(total) < 1e-11 * cst["S0"]
+
+
+@pytest.mark.parametrize("dim,n", [(1, 256), (2, 14)])
+def test_symmetric_part_nonpositive(dim, n):
+    """sym(G) <= 0 (discrete analogue of the stability lemma of Sec. 3.4), hence
+    sym(M) >= I for M = I - dt/2 G."""
+    if dim == 1:
+        p = Problem(dim=1, n=n, s=0.75, lam=1.0, a=0.05, b=(0.5, 0.0), c=-0.3)
+    else:
+        p = Problem(dim=2, n=n, lo=0.0, hi=1.0, s=0.25, b=(0.3, -0.2))
+    G = generator_dense(p)
+    ev = np.linalg.eigvalsh(0.5 * (G + G.T))
+    assert ev.max() <= 1e-9 * abs(ev).max()
+
+
+def test_cn_contraction_with_drift():
+    p = Problem(dim=1, n=256, s=0.75, lam=1.0, a=0.05, b=(0.5, 0.0))
+    G = generator_dense(p)
+    x = grid(p)
+    u0 = np.exp(-x[:, 0] ** 2 / 0.02)
+    res = cn_run(G, 1e-3, 40, u0, keep_norms=True)
+    norms = np.array(res.norms)
+    assert np.all(np.diff(norms) <= 1e-14 * norms[0])
+    assert norms[-1] < norms[0]
+
+
+def test_cn_second_order_in_time_vs_expm():
+    """CN against the exact semi-discrete solution exp(T G) u0: error ratio ~4
+    per halving of dt (consistency lemma, time part)."""
+    p = Problem(dim=1, n=64, s=0.5, lam=0.5, a=0.01, b=(0.3, 0.0))
+    G = generator_dense(p)
+    x = grid(p)
+    u0 = np.exp(-x[:, 0] ** 2 / 0.02)
+    Tf = 0.02
+    exact = sla.expm(Tf * G) @ u0
+    errs = []
+    for steps in (20, 40, 80):
+        u = cn_run(G, Tf / steps, steps, u0).u
+        errs.append(np.linalg.norm(u - exact))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.8 < r2 < 4.2, (errs, r1, r2)
+
+
+def test_cn_forcing_vs_expm():
+    """Trapezoidal forcing: with f = phi(t) g and phi(t) = e^{-t}, the
+    semi-discrete solution is exp(TG)u0 + int_0^T e^{(T-t)G} e^{-t} g dt,
+    which for this phi has the closed form (G + I)^{-1}(e^{TG} - e^{-T}) g."""
+    p = Problem(dim=1, n=48, s=0.5)
+    G = generator_dense(p)
+    x = grid(p)
+    u0 = np.maximum(1 - x[:, 0] ** 2, 0) ** 0.5
+    g = np.full(p.N, ball_const(1, 0.5))
+    Tf = 0.05
+    E = sla.expm(Tf * G)
+    exact = E @ u0 + np.linalg.solve(G + np.eye(p.N), (E - math.exp(-Tf) * np.eye(p.N)) @ g)
+    errs = []
+    for steps in (25, 50):
+        dt = Tf / steps
+        u = cn_run(G, dt, steps, u0, g=g, phi=np.exp(-dt * np.arange(steps + 1))).u
+        errs.append(np.linalg.norm(u - exact) / np.linalg.norm(exact))
+    assert errs[1] < 1e-5
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_drift_diffusion_killing_exact_solution():
+    """No jumps: u_t = a u_xx + b u_x + c u on (-1,1), u = 0 outside, has the
+    exact solution exp(-b x/(2a)) exp((c - b^2/(4a) - a (k pi/2)^2) t)
+    sin(k pi (x+1)/2).  CN must converge to it at O(h^2 + dt^2); a wrong sign
+    of b or c, or a wrong Laplacian, fails by O(1)."""
+    a, b, c, k = 0.05, 0.4, -0.7, 1
+    Tf = 0.2
+    def exact(x, t):
+        return np.exp(-b * x / (2 * a)) * np.exp((c - b * b / (4 * a) - a * (k * math.pi / 2) ** 2) * t) \
+            * np.sin(k * math.pi * (x + 1) / 2)
+    errs = []
+    for n in (63, 127):
+        p = Problem(dim=1, n=n, a=a, b=(b, 0.0), c=c, jumps=False)
+        G = generator_dense(p)
+        x = grid(p)[:, 0]
+        steps = 4 * (n + 1)
+        u = cn_run(G, Tf / steps, steps, exact(x, 0.0)).u
+        errs.append(np.max(np.abs(u - exact(x, Tf))) / np.max(np.abs(exact(x, Tf))))
+    assert errs[1] < 2e-3
+    assert 3.3 < errs[0] / errs[1] < 4.7
+
+
+def test_manufactured_ball_solution():
+    """u = e^{-t} (1-x^2)_+^s solves u_t = -(-Delta)^s u + e^{-t}(K - (1-x^2)^s)
+    on (-1,1) with zero exterior.  The CN solution of the discrete problem
+    tracks it to the spatial error of the ball pin."""
+    s = 0.5
+    errs = []
+    for n in (255, 511):
+        p = Problem(dim=1, n=n, s=s)
+        G = generator_dense(p)
+        x = grid(p)[:, 0]
+        phi0 = np.maximum(1 - x * x, 0) ** s
+        dt, steps = 1e-3, 50
+        t = dt * np.arange(steps + 1)
+        # f(x,t) = e^{-t} (K - phi0(x)): separable as phi(t) g(x)
+        g = ball_const(1, s) - phi0
+        u = cn_run(G, dt, steps, phi0, g=g, phi=np.exp(-t)).u
+        ex = math.exp(-t[-1]) * phi0
+        mid = np.abs(x) < 0.6
+        errs.append(np.max(np.abs(u - ex)[mid]))
+    assert errs[1] < 1.2e-4
+    assert errs[1] < errs[0]

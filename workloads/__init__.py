@@ -1,0 +1,151 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and smoke().
+
+This module holds problem descriptions and input arrays only: grid sizes,
+operator parameters, initial conditions, forcing vectors and the seeded
+random draws of the batched workload.  It contains none of the method's
+arithmetic (no quadrature, no matrices, no time stepping) and imports
+neither the oracle nor the HIP library, so both sides can consume it.
+
+Domains follow the problem statement: 1D problems live on [-1, 1], 2D ones
+on the unit square, both with zero exterior; the grid has ``n`` interior
+points per axis with spacing ``h = (hi - lo)/(n + 1)``.  2D vectors are in
+lexicographic order with the first coordinate slowest.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+__all__ = ["Workload", "config1", "config2", "config3", "config4_instances",
+           "grid_points", "bump_1d", "ball_power", "gaussians_2d"]
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    n: int
+    lo: float
+    hi: float
+    s: float
+    lam: float = 0.0
+    C: float | None = None           # None: the fractional-Laplacian constant c_{d,s}
+    a: float = 0.0                   # diffusion coefficient (sigma^2 / 2)
+    b: tuple = (0.0, 0.0)            # drift
+    c: float = 0.0                   # killing rate (<= 0)
+    r0: float = 0.2                  # singular-window radius
+    dt: float = 1e-3
+    steps: int = 100
+    leaf: int = 64
+    eta: float = 1.0
+    n_block: int = 4
+    aca_tol: float = 1e-10
+    max_rank: int = 32
+    lu_tol: float = 1e-12
+    u0: np.ndarray | None = None
+    g: np.ndarray | None = None      # spatial forcing profile (f(x,t) = phi(t) g(x))
+    phi: np.ndarray | None = None    # phi at t_0 .. t_steps
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.n if self.dim == 1 else self.n * self.n
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def grid_points(dim: int, n: int, lo: float, hi: float) -> np.ndarray:
+    h = (hi - lo) / (n + 1)
+    x1 = lo + h * np.arange(1, n + 1, dtype=np.float64)
+    if dim == 1:
+        return x1[:, None]
+    X, Y = np.meshgrid(x1, x1, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def ball_power(x: np.ndarray, s: float) -> np.ndarray:
+    """(1 - |x|^2)_+^s."""
+    r2 = (x * x).sum(axis=1)
+    return np.maximum(1.0 - r2, 0.0) ** s
+
+
+def bump_1d(x: np.ndarray, std: float = 0.1) -> np.ndarray:
+    """Unit-peak Gaussian bump, mean 0."""
+    return np.exp(-x[:, 0] ** 2 / (2.0 * std * std))
+
+
+def gaussians_2d(x: np.ndarray, seed: int, count: int = 8, std: float = 0.05):
+    """Sum of ``count`` Gaussians, centres U([0.2,0.8]^2) then amplitudes U(0,1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = rng.uniform(0.2, 0.8, size=(count, 2))
+    amps = rng.uniform(0.0, 1.0, size=count)
+    u = np.zeros(x.shape[0])
+    for cj, aj in zip(centres, amps):
+        d2 = ((x - cj) ** 2).sum(axis=1)
+        u += aj * np.exp(-d2 / (2.0 * std * std))
+    return u
+
+
+def _ball_forcing_constant(d: int, s: float) -> float:
+    # closed-form value of (-Delta)^s (1-|x|^2)_+^s on the ball: it is the
+    # problem statement's forcing amplitude, not something the solver derives
+    return 4.0 ** s * math.gamma(1.0 + s) * math.gamma(d / 2.0 + s) / math.gamma(d / 2.0)
+
+
+def config1(n: int = 1024, steps: int = 100) -> Workload:
+    """1D fractional Laplacian, s = 0.5, N = 1024, dt = 1e-3, 100 steps, FP64;
+    u0 = (1 - x^2)_+^s, forcing K e^{-t} with K the ball constant."""
+    w = Workload(name="frac1d_s0.5_n%d" % n, dim=1, n=n, lo=-1.0, hi=1.0, s=0.5,
+                 dt=1e-3, steps=steps, aca_tol=1e-10, lu_tol=1e-12)
+    x = grid_points(1, n, w.lo, w.hi)
+    w.u0 = ball_power(x, w.s)
+    K = _ball_forcing_constant(1, w.s)
+    w.g = np.full(n, K)
+    w.phi = np.exp(-w.dt * np.arange(steps + 1))
+    return w
+
+
+def config2(n: int = 65536, steps: int = 1000) -> Workload:
+    """1D full Levy generator: tempered-stable jumps s = 0.75, lambda = 1,
+    drift 0.5, sigma^2 = 0.1 (a = sigma^2/2), dt = 1e-4, 1000 steps,
+    Gaussian bump u0 with std 0.1."""
+    w = Workload(name="tempered1d_s0.75_n%d" % n, dim=1, n=n, lo=-1.0, hi=1.0,
+                 s=0.75, lam=1.0, a=0.05, b=(0.5, 0.0), c=0.0, dt=1e-4,
+                 steps=steps, aca_tol=1e-10, lu_tol=1e-12)
+    x = grid_points(1, n, w.lo, w.hi)
+    w.u0 = bump_1d(x, 0.1)
+    return w
+
+
+def config3(s: float = 0.75, n: int = 256, steps: int = 200, seed: int = 1812) -> Workload:
+    """2D fractional Laplacian on the unit square, n x n grid, dt = 1e-3,
+    200 steps, ACA rank <= 32 at 1e-8, seeded 8-Gaussian u0."""
+    w = Workload(name="frac2d_s%g_%dx%d" % (s, n, n), dim=2, n=n, lo=0.0, hi=1.0,
+                 s=s, dt=1e-3, steps=steps, aca_tol=1e-8, max_rank=32,
+                 lu_tol=1e-10)
+    x = grid_points(2, n, w.lo, w.hi)
+    w.u0 = gaussians_2d(x, seed)
+    return w
+
+
+def config4_instances(count: int = 512, seed: int = 8324, nmin_log2: float = 10.0,
+                      nmax_log2: float = 15.0, steps: int = 100) -> list:
+    """Independent 1D tempered instances: N log-uniform, s ~ U(0.1, 0.9),
+    drift ~ U(-1, 1), sigma^2 ~ U(0, 0.2), lambda ~ U(0, 2); Gaussian-bump u0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        n = int(round(2.0 ** rng.uniform(nmin_log2, nmax_log2)))
+        s = float(rng.uniform(0.1, 0.9))
+        b = float(rng.uniform(-1.0, 1.0))
+        sig2 = float(rng.uniform(0.0, 0.2))
+        lam = float(rng.uniform(0.0, 2.0))
+        w = Workload(name="inst%d" % i, dim=1, n=n, lo=-1.0, hi=1.0, s=s, lam=lam,
+                     a=0.5 * sig2, b=(b, 0.0), dt=1e-3, steps=steps,
+                     aca_tol=1e-10, lu_tol=1e-12)
+        w.u0 = bump_1d(grid_points(1, n, -1.0, 1.0), 0.1)
+        out.append(w)
+    return out
