@@ -24,7 +24,7 @@ Readings of the paper taken here (the paper is garbled or silent on them):
 * Sign convention.  The paper writes ``A = -G``; here ``G`` is the generator,
   ``M = I - dt/2 G`` and ``Mp = I + dt/2 G`` (Sec. 3.2, eq. equ:Aij).
 * Window ``rho``: the indicator of the infinity-norm ball of radius
-  ``r = m*h`` with ``m = round(r0/h)``, weight 1/2 on its boundary nodes
+  ``r = m*h`` with ``m = floor(r0/h + 1/2)``, weight 1/2 on its boundary nodes
   (Sec. 4, eq. equ:rho_condition leaves the shape open).  In 2D it is the
   product of the 1D node weights.
 * The u'' term of equ:I1approx carries the trapezoid weights ``w_j``
@@ -168,7 +168,7 @@ def quadrature_constants(p: Problem) -> dict:
     h = h_of(p)
     NW = p.n + 1                     # L_W = (n+1) h = domain extent
     LW = NW * h
-    m = int(round(p.r0 / h))
+    m = int(math.floor(p.r0 / h + 0.5))   # nearest grid multiple, ties rounded up
     r = m * h
     C, s, lam, d = p.Cval, p.s, p.lam, p.dim
     if not p.jumps:
