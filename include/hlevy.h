@@ -1,0 +1,187 @@
+/*
+ * hlevy.h -- C ABI of the MI355X (gfx950) H-matrix Crank-Nicolson solver for
+ * convection-diffusion equations driven by a Levy process.
+ *
+ * Method: Xu & Darve, "Efficient Numerical Method for Models Driven by Levy
+ * Process via Hierarchical Matrices" (arXiv 1812.08324).
+ *
+ *   u_t = a Lap u + b . grad u + c u + L u          (Sec. 3.1, eq. equ:ut)
+ *   L u = int (u(x+y) - u(x) - rho(y) grad u(x).y) nu(y) dy,
+ *   nu(y) = C exp(-lambda |y|) / |y|^{d+2s}          (Sec. 4, eq. equ:ny2)
+ *
+ * discretised on a uniform grid of a box with zero exterior, the jump part by
+ * singularity subtraction (Sec. 4, eqs. equ:I1approx - equ:I3approx), stored
+ * as an H-matrix (App. B.1) and advanced with Crank-Nicolson (Sec. 3.2,
+ * eq. equ:scheme):  (I - dt/2 G) u^{n+1} = (I + dt/2 G) u^n + dt/2 (f^n + f^{n+1}).
+ *
+ * Conventions shared by every entry point
+ *  - Vectors are device pointers to double, length N, in natural order
+ *    (1D: x_i = lo + (i+1) h; 2D: index p*n + q for the point
+ *    (lo + (p+1) h, lo + (q+1) h)).  The caller owns them.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *    it; calls return before the device work finishes unless stated.
+ *  - Every call returns an hlevy_status; on error the outputs are unchanged
+ *    (hlevy_step: u holds the last completed step) and hlevy_last_error()
+ *    describes the failure.  No C++ exception crosses this boundary.
+ *  - Handles are not thread safe; distinct handles are independent.
+ *  - The library allocates its device memory itself (hipMalloc) and frees it
+ *    in the *_destroy calls.
+ */
+#ifndef HLEVY_H
+#define HLEVY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HLEVY_ABI_VERSION 1
+
+typedef enum {
+  HLEVY_OK = 0,
+  HLEVY_ERR_INVALID_ARG = -1,   /* bad descriptor, size or pointer */
+  HLEVY_ERR_OOM = -2,           /* device allocation failed */
+  HLEVY_ERR_DEVICE = -3,        /* HIP runtime error (no device, launch failure) */
+  HLEVY_ERR_NOT_CONVERGED = -4, /* refinement did not reach its tolerance */
+  HLEVY_ERR_RANK_CAP = -5,      /* a low-rank block needed more than its rank capacity */
+  HLEVY_ERR_BAD_HANDLE = -6,
+  HLEVY_ERR_ZERO_PIVOT = -7     /* a diagonal leaf had a zero pivot in the H-LU */
+} hlevy_status;
+
+typedef enum {
+  HLEVY_PREC_FP64 = 0,   /* FP64 factors, plain forward/backward solve */
+  HLEVY_PREC_MIXED = 1   /* FP32 factors as a preconditioner + FP64 iterative refinement */
+} hlevy_precision;
+
+/* The model problem (Sec. 3.1 eq. equ:ut; Sec. 4 eqs. equ:ny2 and the
+ * zero-exterior remark).  Domain: the box [lo, hi]^dim, u = 0 outside. */
+typedef struct {
+  int32_t dim;       /* 1 or 2 */
+  int32_t n;         /* interior grid points per axis, h = (hi - lo)/(n + 1); N = n^dim */
+  double lo, hi;     /* box */
+  double a;          /* diffusion coefficient (a >= 0): sigma^2/2 of the Levy triplet */
+  double b[2];       /* drift (b[1] ignored in 1D) */
+  double c;          /* killing rate (c <= 0) */
+  double s;          /* jump index, 0 < s < 1 */
+  double lambda;     /* tempering rate >= 0; 0 = fractional Laplacian kernel */
+  double C;          /* kernel constant; C <= 0 selects c_{d,s} = 4^s G(d/2+s)/(pi^{d/2}|G(-s)|) */
+  double r0;         /* singular window radius rho (snapped to round(r0/h) h); Sec. 5.3 uses 0.2 */
+} hlevy_problem;
+
+/* H-matrix parameters (App. B.1): leaf size N_min, admissibility eta
+ * (eq. equ:adm), N_block = ceil(N/N_max), ACA tolerance and rank capacity
+ * of a low-rank block. */
+typedef struct {
+  int32_t leaf;      /* max points per leaf cluster (N_min), 16..64 */
+  double eta;        /* admissibility constant, > 0 */
+  int32_t n_block;   /* N_max = ceil(N / n_block); >= 1 */
+  double aca_tol;    /* relative Frobenius tolerance of the far-field blocks */
+  int32_t max_rank;  /* rank capacity of a low-rank block, 4..32 */
+} hlevy_hparams;
+
+typedef struct {
+  double tol;          /* relative residual target ||b - M x|| / ||b|| (mixed path) */
+  int32_t sweeps;      /* refinement sweeps per solve (fixed count, graph friendly) */
+} hlevy_refine;
+
+typedef struct {
+  int64_t steps_done;
+  double last_rel_residual;   /* of the last step, if measured (else -1) */
+  int32_t rank_overflows;     /* low-rank blocks truncated at their capacity */
+} hlevy_stats;
+
+/* Structure summary, computed on the host (no device needed). */
+typedef struct {
+  int64_t N;
+  int32_t depth;              /* levels of the cluster tree below the root */
+  int32_t n_clusters;
+  int32_t n_dense;            /* inadmissible leaves (dense) */
+  int32_t n_lowrank;          /* admissible leaves (low rank) */
+  int32_t max_leaf_points;
+  int32_t min_leaf_points;
+  int64_t dense_entries;      /* sum of m*n over dense leaves */
+} hlevy_plan_info_t;
+
+typedef struct {
+  int64_t dense_entries;      /* stored FP64 entries in dense leaves */
+  int64_t lowrank_entries;    /* stored entries sum (m+n)*k over low-rank leaves */
+  int32_t max_rank;
+  double mean_rank;
+  int32_t rank_overflows;
+} hlevy_op_info_t;
+
+typedef struct hlevy_op hlevy_op;
+typedef struct hlevy_fac hlevy_fac;
+
+/* Library ABI version (HLEVY_ABI_VERSION). */
+int32_t hlevy_abi_version(void);
+
+/* Thread-local message of the last failed call on this thread. */
+const char* hlevy_last_error(void);
+
+/* Host only: build the cluster tree (1D index halving, 2D geometric
+ * bisection of the longest box side, App. B.1) and the block tree with the
+ * admissibility of eq. equ:adm on point bounding boxes, and report counts.
+ * Errors: HLEVY_ERR_INVALID_ARG for an invalid descriptor. */
+hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp,
+                             hlevy_plan_info_t* out);
+
+/* Assemble the generator G as an H-matrix on the device: quadrature constants
+ * (Sec. 4, equ:I1approx - equ:I3approx), dense near-field leaves (Sec. 4 row
+ * form, eq. equ:Aij local terms), partially pivoted ACA of every admissible
+ * block followed by truncation to aca_tol (App. B.1).  *out receives a new
+ * handle.  The call returns after the host-side trees are built; device work
+ * is enqueued on `stream`. */
+hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp,
+                            void* stream, hlevy_op** out);
+
+/* Copy the four quadrature constants S0, S2, C2, T (Sec. 4) to host `out`.
+ * Synchronises `stream`. */
+hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream);
+
+/* Storage summary of the assembled operator.  Synchronises `stream`. */
+hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream);
+
+/* y = G x (App. B.2: dense leaves by GEMV, low-rank leaves as U (V^T x)).
+ * x, y: device, length N, natural order, must not alias. */
+hlevy_status hlevy_matvec(const hlevy_op* op, const double* x, double* y, void* stream);
+
+/* Write the H-matrix G densely: dense[i*N + j] = G_ij in natural order
+ * (row-major).  `dense` is a device buffer of N*N doubles; meant for tests
+ * at small N. */
+hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream);
+
+/* Factor M = I - dt/2 G by H-LU (App. B.3) and form the H-inverses of its
+ * triangular factors, truncating every low-rank addition at lu_tol.
+ * prec = HLEVY_PREC_FP64 keeps FP64 factors; HLEVY_PREC_MIXED stores the
+ * inverse factors in FP32 for the refinement preconditioner.  The factor
+ * keeps a reference to `op` (op must outlive it).  Synchronises `stream`. */
+hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu_tol,
+                          void* stream, hlevy_fac** out);
+
+/* Solve M x = b.  FP64 factors: x = U^{-1} (L^{-1} b) applied through the
+ * inverse factors (forward then backward solve).  Mixed: refine->sweeps sweeps of
+ * x <- x + U^{-1} L^{-1} (b - M x) with the residual in FP64 (refine may be
+ * NULL: 2 sweeps).  b, x: device, natural order, must not alias. */
+hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x,
+                         const hlevy_refine* refine, void* stream);
+
+/* Advance u (device, natural order, in/out) by nsteps Crank-Nicolson steps
+ * of eq. equ:scheme with forcing f(x, t_n) = phi[n] g(x):
+ *   M u^{n+1} = (I + dt/2 G) u^n + dt/2 (phi[n] + phi[n+1]) g.
+ * g: device vector or NULL (no forcing); phi: host array of nsteps+1 values
+ * (ignored when g is NULL).  stats may be NULL; when given, the call
+ * synchronises and reports the last relative residual of the mixed path. */
+hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double* g,
+                        const double* phi, const hlevy_refine* refine,
+                        hlevy_stats* stats, void* stream);
+
+void hlevy_op_destroy(hlevy_op* op);
+void hlevy_fac_destroy(hlevy_fac* fac);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLEVY_H */

@@ -1,0 +1,123 @@
+// Work descriptors consumed by the HIP kernels.  Plain structs with raw
+// device pointers; the host fills them and copies them to the device once
+// per plan.
+#pragma once
+
+#include <cstdint>
+
+#include "hl_internal.h"
+
+namespace hl {
+
+constexpr int KMAX = 64;       // widest concatenation handled by one rounded addition
+constexpr int LEAFMAX = 64;    // largest leaf cluster
+constexpr int GRAM_CHUNK = 512;  // rows per Gram / expand work item
+
+// Leaf-cluster lists of the block tree on the device.
+struct DevLists {
+  const int32_t* rowptr;
+  const int32_t* rowidx;
+  const int32_t* colptr;
+  const int32_t* colidx;
+  const int32_t* lc_lo;   // per leaf-cluster position: first index
+  const int32_t* lc_hi;   // one past the last index
+};
+
+// Y = op(B_sub) X for the sub-block B_sub = leaves [lbeg, lend) of a matrix,
+// covering rows [rlo, rhi) and cols [clo, chi).  op = identity (trans = 0):
+// X has rows indexed from clo, Y from rlo.  trans = 1: X rows from rlo,
+// Y rows from clo.  kx columns (device int, or kxcap when kx == nullptr).
+struct ApplyJob {
+  const LeafDesc* L;
+  const int32_t* rank;
+  int32_t lbeg, lend;
+  int32_t rlo, rhi, clo, chi;
+  int32_t trans;
+  int32_t ldx, ldy, kxcap;
+  const double* X;
+  const int32_t* kx;
+  double* Y;
+  double* T;        // projection slots, (leaf - lbeg) * tstride doubles each
+  int32_t tstride;
+  int32_t pad;
+};
+
+struct ProjItem { int32_t job, leaf; };
+struct GatherItem { int32_t job, lpos; };
+
+// P (m x n, ld ldp) = A (m x k, ld lda) * B (k x n, ld ldb), all <= 64.
+struct DProdItem {
+  const double* A;
+  const double* B;
+  double* P;
+  int32_t lda, ldb, ldp, m, k, n;
+};
+
+// One update term of a target block:
+//   C[ro:ro+mr, co:co+nc] += sign * U W^T     (low rank, k columns), or
+//   C[ro:ro+mr, co:co+nc] += sign * P          (dense, P in U with ld ldu).
+// U points at the row of the factor that corresponds to region row 0,
+// W at the row that corresponds to region column 0.
+struct Term {
+  int32_t dense;
+  int32_t ro, mr, co, nc;
+  int32_t ldu, ldw, kfix;
+  const double* U;
+  const double* W;
+  const int32_t* k;   // rank (device) or nullptr => kfix
+  double sign;
+};
+
+// Dense target: D (m x n, ld ldd) += sum of terms [tbeg, tbeg + tcount).
+struct DFlushItem {
+  double* D;
+  int32_t ldd, m, n, tbeg, tcount;
+  int32_t pad;
+};
+
+// Low-rank target: C = U V^T (U m x kcap, V n x kcap, rank *rank) is
+// replaced by the truncated SVD of C + sum of its terms (rounded addition).
+struct LFlushTarget {
+  double* U;
+  double* V;
+  int32_t* rank;       // nullptr => the target starts empty
+  int32_t m, n, kcap, Kcap;
+  int32_t tbeg, tcount;
+  int32_t nchA, nchB;  // Gram chunks on the U side / V side
+  double* ws;          // workspace of this target
+  int32_t* info;       // [0] old rank, [1] new rank, [2] overflow
+  int32_t* overflow;   // global overflow counter
+};
+
+struct ChunkItem { int32_t tgt, side, r0, r1, chunk, pad; };
+
+// Copy of a leaf between two matrices with the same structure.
+struct CopyItem {
+  const double* A;
+  const double* B;
+  double* dA;
+  double* dB;
+  const int32_t* rank;
+  int32_t* drank;
+  int32_t m, n, kcap, dense;
+  double scale;        // applied to A (dense block or U)
+  int32_t add_identity;  // dense diagonal leaf: add the identity after scaling
+  int32_t pad;
+};
+
+// Leaf factorisation: LU in place (no pivoting) and the inverses of the
+// unit-lower and upper factors.
+struct GetrfItem {
+  double* LU;
+  double* Li;
+  double* Ui;
+  int32_t m, pad;
+};
+
+// Problem data needed on the device for assembly.
+struct ProblemDev {
+  int32_t dim, n, N;
+  double h, a, b0, b1, c, s, lam, C, r0;
+};
+
+}  // namespace hl

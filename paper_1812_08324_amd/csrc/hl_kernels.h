@@ -1,0 +1,38 @@
+// Launchers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hl_jobs.h"
+
+namespace hl {
+
+hipError_t launch_constants(const ProblemDev& P, double* out, hipStream_t s);
+hipError_t launch_fill_dense(const ProblemDev& P, const double* cst, const int32_t* perm,
+                             const LeafDesc* L, const int32_t* ids, int n, hipStream_t s);
+hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids,
+                      int n, double* U, double* V, const int64_t* uoff, const int64_t* voff,
+                      int32_t* ranks, int kcap, double eps, hipStream_t s);
+hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, const ChunkItem* gram,
+                           int ngram, const ChunkItem* expand, int nexp, double tol, hipStream_t s);
+hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms, hipStream_t s);
+hipError_t launch_dense_prod(const DProdItem* items, int n, hipStream_t s);
+hipError_t launch_copy(const CopyItem* items, int n, hipStream_t s);
+hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, hipStream_t s);
+hipError_t launch_apply(const ApplyJob* jobs, const ProjItem* proj, int nproj, const GatherItem* gat,
+                        int ngat, const DevLists& dl, hipStream_t s);
+hipError_t launch_perm_gather(double* out, const double* in, const int32_t* perm, int N, hipStream_t s);
+hipError_t launch_perm_scatter(double* out, const double* in, const int32_t* perm, int N, hipStream_t s);
+hipError_t launch_axpy2(double* out, const double* x, double a, const double* y, double cg,
+                        const double* g, int N, hipStream_t s);
+hipError_t launch_residual(double* r, const double* b, const double* x, const double* Gx, double hdt,
+                           int N, hipStream_t s);
+hipError_t launch_add(double* x, const double* d, int N, hipStream_t s);
+hipError_t launch_sumsq(const double* x, int N, double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t launch_densify(const LeafDesc* L, const int32_t* rank, int nleaves, const int32_t* perm,
+                          int N, double* dense, hipStream_t s);
+hipError_t init_kernel_attributes();
+
+inline int npairs_host(int K) { return K * (K + 1) / 2; }
+
+}  // namespace hl

@@ -1,0 +1,1119 @@
+// Host runtime of the H-matrix Crank-Nicolson library: device storage of
+// H-matrices, the batched plan of the H-LU with inverted triangular factors,
+// its executor, and the C ABI declared in include/hlevy.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hl_internal.h"
+#include "hl_jobs.h"
+#include "hl_kernels.h"
+
+namespace hl {
+
+thread_local std::string g_last_error;
+
+static hlevy_status fail(hlevy_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HL_CHECK(expr)                                                                    \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      throw DeviceError(std::string(#expr) + ": " + hipGetErrorString(_e));               \
+  } while (0)
+
+struct DeviceError {
+  std::string msg;
+  explicit DeviceError(std::string m) : msg(std::move(m)) {}
+};
+struct OomError {
+  std::string msg;
+};
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    reset();
+    if (b == 0) b = 8;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw OomError{"hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e)};
+    }
+    bytes = b;
+  }
+  template <class T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+template <class T>
+static void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
+  buf.alloc(v.size() * sizeof(T));
+  if (!v.empty()) HL_CHECK(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Stack allocator over device slabs: alloc/mark/release in LIFO order.
+struct WsStack {
+  struct Slab {
+    char* p;
+    size_t cap;
+  };
+  std::vector<Slab> slabs;
+  size_t cur = 0, off = 0;
+  size_t peak = 0, used_total = 0;
+  static constexpr size_t SLAB = (size_t)256 << 20;
+  ~WsStack() {
+    for (auto& s : slabs) (void)hipFree(s.p);
+  }
+  struct Mark {
+    size_t cur, off, used;
+  };
+  Mark mark() const { return {cur, off, used_total}; }
+  void release(const Mark& m) {
+    cur = m.cur;
+    off = m.off;
+    used_total = m.used;
+  }
+  double* alloc_d(size_t n) { return reinterpret_cast<double*>(alloc(n * sizeof(double))); }
+  int32_t* alloc_i(size_t n) { return reinterpret_cast<int32_t*>(alloc(n * sizeof(int32_t))); }
+  char* alloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    for (;;) {
+      if (cur < slabs.size() && off + bytes <= slabs[cur].cap) {
+        char* p = slabs[cur].p + off;
+        off += bytes;
+        used_total += bytes;
+        peak = std::max(peak, used_total);
+        return p;
+      }
+      if (cur < slabs.size() && off > 0) {
+        ++cur;
+        off = 0;
+        continue;
+      }
+      if (cur >= slabs.size() || slabs[cur].cap < bytes) {
+        size_t cap = std::max(SLAB, bytes);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, cap);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          throw OomError{"workspace allocation failed"};
+        }
+        if (cur < slabs.size()) slabs.insert(slabs.begin() + cur, Slab{(char*)p, cap});
+        else slabs.push_back(Slab{(char*)p, cap});
+        off = 0;
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// one H-matrix with the shared block structure
+// ---------------------------------------------------------------------------
+enum Shape { FULL = 0, LOWER = 1, UPPER = 2 };
+
+struct HMat {
+  const Structure* S = nullptr;
+  std::vector<LeafDesc> L;
+  DevBuf dL, drank, pool;
+  int32_t* rank = nullptr;  // device, per leaf
+  size_t pool_doubles = 0;
+
+  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s) {
+    S = &st;
+    L.resize(st.lf.size());
+    size_t off = 0;
+    for (size_t l = 0; l < st.lf.size(); ++l) {
+      const LeafInfo& li = st.lf[l];
+      LeafDesc d{};
+      d.m = li.m;
+      d.n = li.n;
+      d.rlo = li.rlo;
+      d.clo = li.clo;
+      bool zero = (shape == LOWER && leaf_upper(li)) || (shape == UPPER && leaf_lower(li));
+      d.kind = zero ? K_ZERO : li.kind;
+      d.kcap = 0;
+      if (d.kind == K_DENSE) {
+        d.A = reinterpret_cast<double*>(off);
+        off += ((size_t)li.m * li.n + 7) & ~(size_t)7;
+      } else if (d.kind == K_LR) {
+        d.kcap = std::min(kcap_max, std::min(li.m, li.n));
+        d.A = reinterpret_cast<double*>(off);
+        off += ((size_t)li.m * d.kcap + 7) & ~(size_t)7;
+        d.B = reinterpret_cast<double*>(off);
+        off += ((size_t)li.n * d.kcap + 7) & ~(size_t)7;
+      }
+      L[l] = d;
+    }
+    pool_doubles = off;
+    pool.alloc(std::max<size_t>(off, 1) * sizeof(double));
+    double* base = pool.as<double>();
+    for (auto& d : L) {
+      if (d.kind == K_DENSE) d.A = base + reinterpret_cast<size_t>(d.A);
+      if (d.kind == K_LR) {
+        d.A = base + reinterpret_cast<size_t>(d.A);
+        d.B = base + reinterpret_cast<size_t>(d.B);
+      }
+    }
+    upload(dL, L, s);
+    drank.alloc(std::max<size_t>(L.size(), 1) * sizeof(int32_t));
+    rank = drank.as<int32_t>();
+    HL_CHECK(hipMemsetAsync(rank, 0, L.size() * sizeof(int32_t), s));
+  }
+  const LeafDesc* dev() const { return dL.as<LeafDesc>(); }
+};
+
+// Device copies of the structure lists.
+struct DevStructure {
+  DevBuf rowptr, rowidx, colptr, colidx, lclo, lchi, perm, ident;
+  DevLists lists{};
+  void create(const Structure& S, hipStream_t s) {
+    upload(rowptr, S.rowptr, s);
+    upload(rowidx, S.rowidx, s);
+    upload(colptr, S.colptr, s);
+    upload(colidx, S.colidx, s);
+    std::vector<int32_t> lo, hi;
+    for (int c : S.leafcl) {
+      lo.push_back(S.cl[c].lo);
+      hi.push_back(S.cl[c].hi);
+    }
+    upload(lclo, lo, s);
+    upload(lchi, hi, s);
+    upload(perm, S.perm, s);
+    std::vector<double> I(64 * 64, 0.0);
+    for (int i = 0; i < 64; ++i) I[i + 64 * i] = 1.0;
+    upload(ident, I, s);
+    lists = DevLists{rowptr.as<int32_t>(), rowidx.as<int32_t>(), colptr.as<int32_t>(),
+                     colidx.as<int32_t>(), lclo.as<int32_t>(), lchi.as<int32_t>()};
+  }
+};
+
+// ---------------------------------------------------------------------------
+// plan: phases over item arrays, built on the host, uploaded once
+// ---------------------------------------------------------------------------
+enum PhaseType { PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF };
+
+struct Phase {
+  int type;
+  int b0, n0, b1, n1, b2, n2;
+  double tol;
+};
+
+struct Plan {
+  std::vector<Phase> ph;
+  std::vector<ApplyJob> jobs;
+  std::vector<ProjItem> proj;
+  std::vector<GatherItem> gath;
+  std::vector<DProdItem> dprod;
+  std::vector<Term> terms;
+  std::vector<DFlushItem> dflush;
+  std::vector<LFlushTarget> ltg;
+  std::vector<ChunkItem> lgram, lexp;
+  std::vector<CopyItem> copies;
+  std::vector<GetrfItem> getrf;
+  DevBuf djobs, dproj, dgath, ddprod, dterms, ddflush, dltg, dlgram, dlexp, dcopies, dgetrf;
+
+  void upload_all(hipStream_t s) {
+    upload(djobs, jobs, s);
+    upload(dproj, proj, s);
+    upload(dgath, gath, s);
+    upload(ddprod, dprod, s);
+    upload(dterms, terms, s);
+    upload(ddflush, dflush, s);
+    upload(dltg, ltg, s);
+    upload(dlgram, lgram, s);
+    upload(dlexp, lexp, s);
+    upload(dcopies, copies, s);
+    upload(dgetrf, getrf, s);
+  }
+
+  void run(const DevLists& dl, int32_t* zero_pivot, hipStream_t s) const {
+    for (const Phase& p : ph) {
+      switch (p.type) {
+        case PH_APPLY:
+          HL_CHECK(launch_apply(djobs.as<ApplyJob>(), dproj.as<ProjItem>() + p.b0, p.n0,
+                                dgath.as<GatherItem>() + p.b1, p.n1, dl, s));
+          break;
+        case PH_DPROD:
+          HL_CHECK(launch_dense_prod(ddprod.as<DProdItem>() + p.b0, p.n0, s));
+          break;
+        case PH_DFLUSH:
+          HL_CHECK(launch_flush_dense(ddflush.as<DFlushItem>() + p.b0, p.n0, dterms.as<Term>(), s));
+          break;
+        case PH_LFLUSH:
+          HL_CHECK(launch_flush_lr(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(),
+                                   dlgram.as<ChunkItem>() + p.b1, p.n1, dlexp.as<ChunkItem>() + p.b2,
+                                   p.n2, p.tol, s));
+          break;
+        case PH_COPY:
+          HL_CHECK(launch_copy(dcopies.as<CopyItem>() + p.b0, p.n0, s));
+          break;
+        case PH_GETRF:
+          HL_CHECK(launch_getrf_inv(dgetrf.as<GetrfItem>() + p.b0, p.n0, zero_pivot, s));
+          break;
+      }
+    }
+  }
+};
+
+// Chunk items for a rounded addition of target index `t` in the plan.
+static void add_chunks(Plan& P, int t, int m, int n, LFlushTarget& T, int gram_base_unused) {
+  (void)gram_base_unused;
+  T.nchA = (m + GRAM_CHUNK - 1) / GRAM_CHUNK;
+  T.nchB = (n + GRAM_CHUNK - 1) / GRAM_CHUNK;
+  for (int side = 0; side < 2; ++side) {
+    int len = side == 0 ? m : n;
+    int nch = side == 0 ? T.nchA : T.nchB;
+    for (int c = 0; c < nch; ++c) {
+      ChunkItem ci{t, side, c * GRAM_CHUNK, std::min(len, (c + 1) * GRAM_CHUNK), c, 0};
+      P.lgram.push_back(ci);
+      P.lexp.push_back(ci);
+    }
+  }
+}
+
+static size_t flush_ws_doubles(const LFlushTarget& T) {
+  return (size_t)(T.nchA + T.nchB) * npairs_host(T.Kcap) * 2 + (size_t)2 * T.Kcap * T.kcap;
+}
+
+// ---------------------------------------------------------------------------
+// builder of the factorisation plan
+// ---------------------------------------------------------------------------
+struct PendingTerm {
+  Term t;
+  int kcap;   // capacity bound of the term's rank
+};
+
+struct Builder {
+  const Structure& S;
+  Plan& P;
+  WsStack& ws;
+  const DevStructure& ds;
+  int32_t* overflow;
+  double tol;
+  // batch state
+  std::vector<ApplyJob> bjobs;
+  std::vector<std::vector<ProjItem>> bproj_unused;
+  std::vector<DProdItem> bdprod;
+  std::map<std::pair<HMat*, int>, std::vector<PendingTerm>> pending;
+  WsStack::Mark mk{};
+  bool in_batch = false;
+
+  Builder(const Structure& s, Plan& p, WsStack& w, const DevStructure& d, int32_t* ovf, double t)
+      : S(s), P(p), ws(w), ds(d), overflow(ovf), tol(t) {}
+
+  int csize(int c) const { return S.cl[c].hi - S.cl[c].lo; }
+
+  void begin() {
+    mk = ws.mark();
+    in_batch = true;
+  }
+
+  void add_apply(HMat* M, int node, int trans, const double* X, int ldx, const int32_t* kx, int kxcap,
+                 double* Y, int ldy) {
+    const BNode& b = S.bn[node];
+    ApplyJob J{};
+    J.L = M->dev();
+    J.rank = M->rank;
+    J.lbeg = b.lbeg;
+    J.lend = b.lend;
+    J.rlo = S.cl[b.r].lo;
+    J.rhi = S.cl[b.r].hi;
+    J.clo = S.cl[b.c].lo;
+    J.chi = S.cl[b.c].hi;
+    J.trans = trans;
+    J.ldx = ldx;
+    J.ldy = ldy;
+    J.kxcap = kxcap;
+    J.X = X;
+    J.kx = kx;
+    J.Y = Y;
+    J.tstride = 32 * kxcap;
+    J.T = ws.alloc_d((size_t)(b.lend - b.lbeg) * J.tstride);
+    bjobs.push_back(J);
+  }
+
+  // push a term covering rows [r0, r1) x cols [c0, c1) (absolute) into the
+  // target node of matrix C
+  void push(HMat* C, int cnode, Term t, int kcap, int r0, int r1, int c0, int c1) {
+    const BNode& c = S.bn[cnode];
+    if (c.kind == K_H) {
+      for (int q = 0; q < 4; ++q) {
+        const BNode& ch = S.bn[c.child[q]];
+        int a0 = std::max(r0, S.cl[ch.r].lo), a1 = std::min(r1, S.cl[ch.r].hi);
+        int b0 = std::max(c0, S.cl[ch.c].lo), b1 = std::min(c1, S.cl[ch.c].hi);
+        if (a0 >= a1 || b0 >= b1) continue;
+        Term u = t;
+        if (t.dense) {
+          u.U = t.U + (a0 - r0) + (size_t)t.ldu * (b0 - c0);
+        } else {
+          u.U = t.U + (a0 - r0);
+          u.W = t.W + (b0 - c0);
+        }
+        push(C, c.child[q], u, kcap, a0, a1, b0, b1);
+      }
+      return;
+    }
+    const LeafDesc& d = C->L[c.leaf];
+    if (d.kind == K_ZERO) throw DeviceError("internal: update of a structurally zero block");
+    t.ro = r0 - d.rlo;
+    t.mr = r1 - r0;
+    t.co = c0 - d.clo;
+    t.nc = c1 - c0;
+    pending[{C, c.leaf}].push_back({t, kcap});
+  }
+
+  // C[cnode region] += sign * A[an] * B[bn]
+  void mma(HMat* C, int cnode, HMat* A, int an, HMat* B, int bnd, double sign) {
+    const BNode& a = S.bn[an];
+    const BNode& b = S.bn[bnd];
+    int ak = a.kind == K_H ? (int)K_H : A->L[a.leaf].kind;
+    int bk = b.kind == K_H ? (int)K_H : B->L[b.leaf].kind;
+    if (ak == K_ZERO || bk == K_ZERO) return;
+    const int r0 = S.cl[a.r].lo, r1 = S.cl[a.r].hi, c0 = S.cl[b.c].lo, c1 = S.cl[b.c].hi;
+    if (ak == K_LR) {
+      const LeafDesc& la = A->L[a.leaf];
+      int nrow = c1 - c0;
+      double* W = ws.alloc_d((size_t)nrow * la.kcap);
+      add_apply(B, bnd, 1, la.B, la.n, A->rank + a.leaf, la.kcap, W, nrow);
+      Term t{};
+      t.dense = 0;
+      t.U = la.A;
+      t.ldu = la.m;
+      t.W = W;
+      t.ldw = nrow;
+      t.k = A->rank + a.leaf;
+      t.sign = sign;
+      push(C, cnode, t, la.kcap, r0, r1, c0, c1);
+    } else if (bk == K_LR) {
+      const LeafDesc& lb = B->L[b.leaf];
+      int nrow = r1 - r0;
+      double* Z = ws.alloc_d((size_t)nrow * lb.kcap);
+      add_apply(A, an, 0, lb.A, lb.m, B->rank + b.leaf, lb.kcap, Z, nrow);
+      Term t{};
+      t.dense = 0;
+      t.U = Z;
+      t.ldu = nrow;
+      t.W = lb.B;
+      t.ldw = lb.n;
+      t.k = B->rank + b.leaf;
+      t.sign = sign;
+      push(C, cnode, t, lb.kcap, r0, r1, c0, c1);
+    } else if (ak == K_DENSE && bk == K_DENSE) {
+      const LeafDesc& la = A->L[a.leaf];
+      const LeafDesc& lb = B->L[b.leaf];
+      double* Pp = ws.alloc_d((size_t)la.m * lb.n);
+      bdprod.push_back(DProdItem{la.A, lb.A, Pp, la.m, lb.m, la.m, la.m, la.n, lb.n});
+      Term t{};
+      t.dense = 1;
+      t.U = Pp;
+      t.ldu = la.m;
+      t.sign = sign;
+      push(C, cnode, t, std::min(32, std::min(la.m, lb.n)), r0, r1, c0, c1);
+    } else {
+      if (!(ak == K_H && bk == K_H)) throw DeviceError("internal: inconsistent block tree levels");
+      const BNode& c = S.bn[cnode];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          int cc = c.kind == K_H ? c.child[2 * i + j] : cnode;
+          for (int k = 0; k < 2; ++k) mma(C, cc, A, a.child[2 * i + k], B, b.child[2 * k + j], sign);
+        }
+    }
+  }
+
+  void emit_lflush(std::vector<LFlushTarget>& tgs, std::vector<std::vector<Term>>& tlists, double ftol) {
+    if (tgs.empty()) return;
+    Phase ph{PH_LFLUSH, (int)P.ltg.size(), (int)tgs.size(), (int)P.lgram.size(), 0, (int)P.lexp.size(), 0,
+             ftol};
+    for (size_t q = 0; q < tgs.size(); ++q) {
+      LFlushTarget T = tgs[q];
+      T.tbeg = (int)P.terms.size();
+      T.tcount = (int)tlists[q].size();
+      for (auto& t : tlists[q]) P.terms.push_back(t);
+      int tix = (int)P.ltg.size();
+      add_chunks(P, tix - ph.b0, T.m, T.n, T, 0);
+      T.ws = ws.alloc_d(flush_ws_doubles(T));
+      T.info = ws.alloc_i(4);
+      T.overflow = overflow;
+      P.ltg.push_back(T);
+    }
+    ph.n1 = (int)P.lgram.size() - ph.b1;
+    ph.n2 = (int)P.lexp.size() - ph.b2;
+    P.ph.push_back(ph);
+  }
+
+  void end() {
+    // 1. applies (all independent within the batch)
+    if (!bjobs.empty()) {
+      int jb = (int)P.jobs.size();
+      Phase ph{PH_APPLY, (int)P.proj.size(), 0, (int)P.gath.size(), 0, 0, 0, 0.0};
+      for (size_t q = 0; q < bjobs.size(); ++q) {
+        const ApplyJob& J = bjobs[q];
+        P.jobs.push_back(J);
+        for (int l = J.lbeg; l < J.lend; ++l) {
+          // LR leaves of the operand; kinds come from the job's matrix (host copy not
+          // reachable here), so every LR-structured leaf gets an item and the kernel
+          // reads a zero rank for structurally zero leaves
+          if (S.lf[l].kind == K_LR) P.proj.push_back(ProjItem{jb + (int)q, l});
+        }
+        int o0 = J.trans ? J.clo : J.rlo, o1 = J.trans ? J.chi : J.rhi;
+        for (size_t lp = 0; lp < S.leafcl.size(); ++lp) {
+          const Cluster& c = S.cl[S.leafcl[lp]];
+          if (c.lo >= o0 && c.hi <= o1) P.gath.push_back(GatherItem{jb + (int)q, (int)lp});
+        }
+      }
+      ph.n0 = (int)P.proj.size() - ph.b0;
+      ph.n1 = (int)P.gath.size() - ph.b1;
+      P.ph.push_back(ph);
+    }
+    // 2. dense products
+    if (!bdprod.empty()) {
+      Phase ph{PH_DPROD, (int)P.dprod.size(), (int)bdprod.size(), 0, 0, 0, 0, 0.0};
+      for (auto& d : bdprod) P.dprod.push_back(d);
+      P.ph.push_back(ph);
+    }
+    // 3. dense terms into low-rank targets are compressed on their own first
+    {
+      std::vector<LFlushTarget> tgs;
+      std::vector<std::vector<Term>> tl;
+      for (auto& kv : pending) {
+        HMat* C = kv.first.first;
+        const LeafDesc& d = C->L[kv.first.second];
+        if (d.kind != K_LR) continue;
+        for (auto& pt : kv.second) {
+          if (!pt.t.dense) continue;
+          int mr = pt.t.mr, nc = pt.t.nc;
+          int kc = std::min(32, std::min(mr, nc));
+          LFlushTarget T{};
+          T.U = ws.alloc_d((size_t)mr * kc);
+          T.V = ws.alloc_d((size_t)nc * kc);
+          T.rank = nullptr;
+          T.m = mr;
+          T.n = nc;
+          T.kcap = kc;
+          T.Kcap = nc;
+          Term lt{};
+          lt.dense = 0;
+          lt.ro = 0;
+          lt.mr = mr;
+          lt.co = 0;
+          lt.nc = nc;
+          lt.U = pt.t.U;
+          lt.ldu = pt.t.ldu;
+          lt.W = ds.ident.as<double>();
+          lt.ldw = 64;
+          lt.k = nullptr;
+          lt.kfix = nc;
+          lt.sign = 1.0;
+          tgs.push_back(T);
+          tl.push_back({lt});
+        }
+      }
+      size_t first = P.ltg.size();
+      emit_lflush(tgs, tl, tol);
+      // rewrite those dense terms as low-rank terms on the compressed factors
+      size_t q = first;
+      for (auto& kv : pending) {
+        HMat* C = kv.first.first;
+        const LeafDesc& d = C->L[kv.first.second];
+        if (d.kind != K_LR) continue;
+        for (auto& pt : kv.second) {
+          if (!pt.t.dense) continue;
+          const LFlushTarget& T = P.ltg[q++];
+          pt.t.dense = 0;
+          pt.t.U = T.U;
+          pt.t.ldu = T.m;
+          pt.t.W = T.V;
+          pt.t.ldw = T.n;
+          pt.t.k = T.info + 1;
+          pt.kcap = T.kcap;
+        }
+      }
+    }
+    // 4. dense targets
+    {
+      Phase ph{PH_DFLUSH, (int)P.dflush.size(), 0, 0, 0, 0, 0, 0.0};
+      for (auto& kv : pending) {
+        HMat* C = kv.first.first;
+        const LeafDesc& d = C->L[kv.first.second];
+        if (d.kind != K_DENSE) continue;
+        DFlushItem it{d.A, d.m, d.m, d.n, (int)P.terms.size(), (int)kv.second.size(), 0};
+        for (auto& pt : kv.second) P.terms.push_back(pt.t);
+        P.dflush.push_back(it);
+      }
+      ph.n0 = (int)P.dflush.size() - ph.b0;
+      if (ph.n0) P.ph.push_back(ph);
+    }
+    // 5. low-rank targets: rounded additions, terms split so that the
+    //    concatenated width stays within KMAX
+    {
+      std::vector<std::vector<std::pair<LFlushTarget, std::vector<Term>>>> rounds;
+      for (auto& kv : pending) {
+        HMat* C = kv.first.first;
+        int leaf = kv.first.second;
+        const LeafDesc& d = C->L[leaf];
+        if (d.kind != K_LR) continue;
+        size_t q = 0, rd = 0;
+        while (q < kv.second.size()) {
+          LFlushTarget T{};
+          T.U = d.A;
+          T.V = d.B;
+          T.rank = C->rank + leaf;
+          T.m = d.m;
+          T.n = d.n;
+          T.kcap = d.kcap;
+          int K = d.kcap;
+          std::vector<Term> tl;
+          while (q < kv.second.size() && K + kv.second[q].kcap <= KMAX) {
+            K += kv.second[q].kcap;
+            tl.push_back(kv.second[q].t);
+            ++q;
+          }
+          if (tl.empty()) throw DeviceError("internal: term wider than a rounded addition");
+          T.Kcap = K;
+          if (rounds.size() <= rd) rounds.resize(rd + 1);
+          rounds[rd].push_back({T, tl});
+          ++rd;
+        }
+      }
+      for (auto& r : rounds) {
+        std::vector<LFlushTarget> tgs;
+        std::vector<std::vector<Term>> tl;
+        for (auto& e : r) {
+          tgs.push_back(e.first);
+          tl.push_back(e.second);
+        }
+        emit_lflush(tgs, tl, tol);
+      }
+    }
+    bjobs.clear();
+    bdprod.clear();
+    pending.clear();
+    ws.release(mk);
+    in_batch = false;
+  }
+
+  void copy_node(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag) {
+    const BNode& b = S.bn[node];
+    Phase ph{PH_COPY, (int)P.copies.size(), 0, 0, 0, 0, 0, 0.0};
+    for (int l = b.lbeg; l < b.lend; ++l) {
+      const LeafDesc& d = dst->L[l];
+      if (d.kind == K_ZERO) continue;
+      CopyItem c{};
+      c.dense = d.kind == K_DENSE;
+      c.m = d.m;
+      c.n = d.n;
+      c.kcap = d.kcap;
+      c.dA = d.A;
+      c.dB = d.B;
+      c.drank = d.kind == K_LR ? dst->rank + l : nullptr;
+      if (src) {
+        const LeafDesc& e = src->L[l];
+        c.A = e.A;
+        c.B = e.B;
+        c.rank = e.kind == K_LR ? src->rank + l : nullptr;
+      }
+      c.scale = scale;
+      c.add_identity = (add_identity_diag && S.lf[l].r == S.lf[l].c) ? 1 : 0;
+      P.copies.push_back(c);
+    }
+    ph.n0 = (int)P.copies.size() - ph.b0;
+    if (ph.n0) P.ph.push_back(ph);
+  }
+
+  void zero_node(HMat* dst, int node) { copy_node(dst, nullptr, node, 0.0, false); }
+};
+
+// H-LU of the diagonal block `node` with the H-inverses of both factors
+// (App. B.3 recursion; inverses by the 2x2 block formulas):
+//   LU(A11);  U12 = L11^{-1} A12;  L21 = A21 U11^{-1};  LU(A22 - L21 U12);
+//   (L^{-1})21 = -L22^{-1} L21 L11^{-1};  (U^{-1})12 = -U11^{-1} U12 U22^{-1}.
+static void hluinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, HMat* TMP, int node) {
+  const BNode& b = B.S.bn[node];
+  if (b.kind != K_H) {
+    const LeafDesc& d = LU->L[b.leaf];
+    Phase ph{PH_GETRF, (int)B.P.getrf.size(), 1, 0, 0, 0, 0, 0.0};
+    B.P.getrf.push_back(GetrfItem{d.A, Li->L[b.leaf].A, Ui->L[b.leaf].A, d.m, 0});
+    B.P.ph.push_back(ph);
+    return;
+  }
+  const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
+  hluinv(B, LU, Li, Ui, TMP, n11);
+  B.zero_node(TMP, n12);
+  B.zero_node(TMP, n21);
+  B.begin();
+  B.mma(TMP, n12, Li, n11, LU, n12, 1.0);   // U12 = L11^{-1} A12
+  B.mma(TMP, n21, LU, n21, Ui, n11, 1.0);   // L21 = A21 U11^{-1}
+  B.end();
+  B.copy_node(LU, TMP, n12, 1.0, false);
+  B.copy_node(LU, TMP, n21, 1.0, false);
+  B.begin();
+  B.mma(LU, n22, LU, n21, LU, n12, -1.0);   // A22 -= L21 U12
+  B.end();
+  hluinv(B, LU, Li, Ui, TMP, n22);
+  B.zero_node(TMP, n12);
+  B.zero_node(TMP, n21);
+  B.begin();
+  B.mma(TMP, n21, LU, n21, Li, n11, 1.0);   // L21 L11^{-1}
+  B.mma(TMP, n12, LU, n12, Ui, n22, 1.0);   // U12 U22^{-1}
+  B.end();
+  B.begin();
+  B.mma(Li, n21, Li, n22, TMP, n21, -1.0);  // -(L22^{-1}) (L21 L11^{-1})
+  B.mma(Ui, n12, Ui, n11, TMP, n12, -1.0);  // -(U11^{-1}) (U12 U22^{-1})
+  B.end();
+}
+
+// A full-matrix apply y = M x (cluster order) with static buffers.
+struct ApplyPlan {
+  DevBuf djob, dproj, dgath, T;
+  int nproj = 0, ngath = 0;
+  void create(const Structure& S, const HMat& M, const double* X, double* Y, hipStream_t s) {
+    ApplyJob J{};
+    J.L = M.dev();
+    J.rank = M.rank;
+    J.lbeg = 0;
+    J.lend = (int)S.lf.size();
+    J.rlo = 0;
+    J.rhi = S.N;
+    J.clo = 0;
+    J.chi = S.N;
+    J.trans = 0;
+    J.ldx = S.N;
+    J.ldy = S.N;
+    J.kxcap = 1;
+    J.X = X;
+    J.kx = nullptr;
+    J.Y = Y;
+    J.tstride = 32;
+    T.alloc(S.lf.size() * 32 * sizeof(double));
+    J.T = T.as<double>();
+    std::vector<ApplyJob> jv{J};
+    std::vector<ProjItem> pv;
+    std::vector<GatherItem> gv;
+    for (size_t l = 0; l < S.lf.size(); ++l)
+      if (M.L[l].kind == K_LR) pv.push_back(ProjItem{0, (int)l});
+    for (size_t lp = 0; lp < S.leafcl.size(); ++lp) gv.push_back(GatherItem{0, (int)lp});
+    upload(djob, jv, s);
+    upload(dproj, pv, s);
+    upload(dgath, gv, s);
+    nproj = (int)pv.size();
+    ngath = (int)gv.size();
+  }
+  void run(const DevLists& dl, hipStream_t s) const {
+    HL_CHECK(launch_apply(djob.as<ApplyJob>(), dproj.as<ProjItem>(), nproj, dgath.as<GatherItem>(), ngath,
+                          dl, s));
+  }
+};
+
+}  // namespace hl
+
+using namespace hl;
+
+struct hlevy_op {
+  hlevy_problem prob{};
+  hlevy_hparams hp{};
+  Structure S;
+  ProblemDev pd{};
+  DevStructure ds;
+  HMat G;
+  DevBuf cst, ovf;
+  DevBuf xbuf, ybuf;   // cluster-order work vectors for hlevy_matvec
+  ApplyPlan mv;
+};
+
+struct hlevy_fac {
+  const hlevy_op* op = nullptr;
+  double dt = 0, lu_tol = 0;
+  int prec = 0;
+  HMat LU, Li, Ui;
+  DevBuf w_u, w_y, w_b, w_z, w_r, w_d, w_g, partial, scal, zp, ovf;
+  ApplyPlan mvG, mvLi, mvUi;
+  int32_t rank_overflows = 0;
+};
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <class F>
+static hlevy_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const DeviceError& e) {
+    return fail(HLEVY_ERR_DEVICE, e.msg);
+  } catch (const OomError& e) {
+    return fail(HLEVY_ERR_OOM, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HLEVY_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    return fail(HLEVY_ERR_DEVICE, "unexpected exception");
+  }
+}
+
+static double frac_constant(int d, double s) {
+  return std::pow(4.0, s) * std::tgamma(d / 2.0 + s) / (std::pow(M_PI, d / 2.0) * std::fabs(std::tgamma(-s)));
+}
+
+extern "C" {
+
+int32_t hlevy_abi_version(void) { return HLEVY_ABI_VERSION; }
+
+const char* hlevy_last_error(void) { return g_last_error.c_str(); }
+
+hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp, hlevy_plan_info_t* out) {
+  if (!prob || !hp || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  try {
+    Structure S;
+    std::string e = build_structure(*prob, *hp, S);
+    if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
+    out->N = S.N;
+    out->depth = S.depth;
+    out->n_clusters = (int32_t)S.cl.size();
+    out->n_dense = S.n_dense;
+    out->n_lowrank = S.n_lr;
+    int mx = 0, mn = 1 << 30;
+    for (int c : S.leafcl) {
+      mx = std::max(mx, S.cl[c].hi - S.cl[c].lo);
+      mn = std::min(mn, S.cl[c].hi - S.cl[c].lo);
+    }
+    out->max_leaf_points = mx;
+    out->min_leaf_points = mn;
+    out->dense_entries = S.dense_entries;
+    return HLEVY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(HLEVY_ERR_OOM, "host allocation failed");
+  }
+}
+
+hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, void* stream, hlevy_op** out) {
+  if (!prob || !hp || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (!(prob->r0 < prob->hi - prob->lo)) return fail(HLEVY_ERR_INVALID_ARG, "r0 must be smaller than the domain");
+  return guarded([&]() -> hlevy_status {
+    auto op = std::make_unique<hlevy_op>();
+    std::string e = build_structure(*prob, *hp, op->S);
+    if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
+    const Structure& S = op->S;
+    for (auto& l : S.lf)
+      if (l.kind == K_LR && std::max(l.m, l.n) > 16384)
+        return fail(HLEVY_ERR_INVALID_ARG, "low-rank blocks are limited to 16384 rows (raise n_block)");
+    hipStream_t s = as_stream(stream);
+    HL_CHECK(init_kernel_attributes());
+    op->prob = *prob;
+    op->hp = *hp;
+    ProblemDev& pd = op->pd;
+    pd.dim = prob->dim;
+    pd.n = prob->n;
+    pd.N = S.N;
+    pd.h = S.h;
+    pd.a = prob->a;
+    pd.b0 = prob->b[0];
+    pd.b1 = prob->dim == 2 ? prob->b[1] : 0.0;
+    pd.c = prob->c;
+    pd.s = prob->s;
+    pd.lam = prob->lambda;
+    pd.C = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, prob->s);
+    pd.r0 = prob->r0;
+    op->ds.create(S, s);
+    op->cst.alloc(4 * sizeof(double));
+    op->ovf.alloc(sizeof(int32_t));
+    HL_CHECK(hipMemsetAsync(op->ovf.p, 0, sizeof(int32_t), s));
+    HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
+    op->G.create(S, hp->max_rank, FULL, s);
+    // dense near field
+    std::vector<int32_t> dense_ids, lr_ids;
+    for (size_t l = 0; l < S.lf.size(); ++l) (S.lf[l].kind == K_DENSE ? dense_ids : lr_ids).push_back((int)l);
+    DevBuf dids, lids;
+    upload(dids, dense_ids, s);
+    upload(lids, lr_ids, s);
+    HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
+                               dids.as<int32_t>(), (int)dense_ids.size(), s));
+    // far field: ACA into scratch, then rounded addition into G
+    const int kaca = KMAX;
+    std::vector<int64_t> uo, vo;
+    int64_t tot = 0;
+    for (int l : lr_ids) {
+      uo.push_back(tot);
+      tot += (int64_t)S.lf[l].m * kaca;
+      vo.push_back(tot);
+      tot += (int64_t)S.lf[l].n * kaca;
+    }
+    DevBuf acabuf, duo, dvo, acarank;
+    acabuf.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
+    upload(duo, uo, s);
+    upload(dvo, vo, s);
+    acarank.alloc(std::max<size_t>(lr_ids.size(), 1) * sizeof(int32_t));
+    HL_CHECK(launch_aca(pd, op->ds.perm.as<int32_t>(), op->G.dev(), lids.as<int32_t>(), (int)lr_ids.size(),
+                        acabuf.as<double>(), acabuf.as<double>(), duo.as<int64_t>(), dvo.as<int64_t>(),
+                        acarank.as<int32_t>(), kaca, 0.1 * hp->aca_tol, s));
+    {
+      Plan P;
+      WsStack ws;
+      Builder B(S, P, ws, op->ds, op->ovf.as<int32_t>(), hp->aca_tol);
+      std::vector<LFlushTarget> tgs;
+      std::vector<std::vector<Term>> tl;
+      for (size_t q = 0; q < lr_ids.size(); ++q) {
+        const LeafDesc& d = op->G.L[lr_ids[q]];
+        LFlushTarget T{};
+        T.U = d.A;
+        T.V = d.B;
+        T.rank = op->G.rank + lr_ids[q];
+        T.m = d.m;
+        T.n = d.n;
+        T.kcap = d.kcap;
+        T.Kcap = kaca;
+        Term t{};
+        t.dense = 0;
+        t.ro = 0;
+        t.mr = d.m;
+        t.co = 0;
+        t.nc = d.n;
+        t.U = acabuf.as<double>() + uo[q];
+        t.ldu = d.m;
+        t.W = acabuf.as<double>() + vo[q];
+        t.ldw = d.n;
+        t.k = acarank.as<int32_t>() + q;
+        t.sign = 1.0;
+        tgs.push_back(T);
+        tl.push_back({t});
+      }
+      B.emit_lflush(tgs, tl, hp->aca_tol);
+      P.upload_all(s);
+      P.run(op->ds.lists, nullptr, s);
+      HL_CHECK(hipStreamSynchronize(s));
+    }
+    op->xbuf.alloc((size_t)S.N * sizeof(double));
+    op->ybuf.alloc((size_t)S.N * sizeof(double));
+    op->mv.create(S, op->G, op->xbuf.as<double>(), op->ybuf.as<double>(), s);
+    HL_CHECK(hipStreamSynchronize(s));
+    *out = op.release();
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream) {
+  if (!op || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  return guarded([&]() -> hlevy_status {
+    HL_CHECK(hipMemcpyAsync(out, op->cst.p, 4 * sizeof(double), hipMemcpyDeviceToHost, as_stream(stream)));
+    HL_CHECK(hipStreamSynchronize(as_stream(stream)));
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream) {
+  if (!op || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  return guarded([&]() -> hlevy_status {
+    std::vector<int32_t> rk(op->S.lf.size());
+    int32_t ov = 0;
+    HL_CHECK(hipMemcpyAsync(rk.data(), op->G.rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            as_stream(stream)));
+    HL_CHECK(hipMemcpyAsync(&ov, op->ovf.p, sizeof(int32_t), hipMemcpyDeviceToHost, as_stream(stream)));
+    HL_CHECK(hipStreamSynchronize(as_stream(stream)));
+    int64_t de = 0, le = 0;
+    int mx = 0;
+    double sum = 0;
+    int cnt = 0;
+    for (size_t l = 0; l < op->S.lf.size(); ++l) {
+      const LeafInfo& li = op->S.lf[l];
+      if (li.kind == K_DENSE) de += (int64_t)li.m * li.n;
+      else {
+        le += (int64_t)(li.m + li.n) * rk[l];
+        mx = std::max(mx, rk[l]);
+        sum += rk[l];
+        ++cnt;
+      }
+    }
+    out->dense_entries = de;
+    out->lowrank_entries = le;
+    out->max_rank = mx;
+    out->mean_rank = cnt ? sum / cnt : 0.0;
+    out->rank_overflows = ov;
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_matvec(const hlevy_op* op, const double* x, double* y, void* stream) {
+  if (!op || !x || !y) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (x == y) return fail(HLEVY_ERR_INVALID_ARG, "x and y must not alias");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    const int N = op->S.N;
+    const int32_t* perm = op->ds.perm.as<int32_t>();
+    HL_CHECK(launch_perm_gather(op->xbuf.as<double>(), x, perm, N, s));
+    op->mv.run(op->ds.lists, s);
+    HL_CHECK(launch_perm_scatter(y, op->ybuf.as<double>(), perm, N, s));
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream) {
+  if (!op || !dense) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  return guarded([&]() -> hlevy_status {
+    HL_CHECK(launch_densify(op->G.dev(), op->G.rank, (int)op->S.lf.size(), op->ds.perm.as<int32_t>(), op->S.N,
+                            dense, as_stream(stream)));
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu_tol, void* stream,
+                          hlevy_fac** out) {
+  if (!op || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HLEVY_ERR_INVALID_ARG, "dt must be > 0");
+  if (!(lu_tol > 0.0 && lu_tol < 1.0)) return fail(HLEVY_ERR_INVALID_ARG, "lu_tol must be in (0, 1)");
+  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    auto f = std::make_unique<hlevy_fac>();
+    f->op = op;
+    f->dt = dt;
+    f->prec = prec;
+    f->lu_tol = lu_tol;
+    const Structure& S = op->S;
+    const int kc = op->hp.max_rank;
+    f->LU.create(S, kc, FULL, s);
+    f->Li.create(S, kc, LOWER, s);
+    f->Ui.create(S, kc, UPPER, s);
+    HMat TMP;
+    TMP.create(S, kc, FULL, s);
+    f->zp.alloc(sizeof(int32_t));
+    f->ovf.alloc(sizeof(int32_t));
+    HL_CHECK(hipMemsetAsync(f->zp.p, 0, sizeof(int32_t), s));
+    HL_CHECK(hipMemsetAsync(f->ovf.p, 0, sizeof(int32_t), s));
+    {
+      Plan P;
+      WsStack ws;
+      Builder B(S, P, ws, op->ds, f->ovf.as<int32_t>(), lu_tol);
+      B.copy_node(&f->LU, const_cast<HMat*>(&op->G), 0, -0.5 * dt, true);   // M = I - dt/2 G
+      B.zero_node(&f->Li, 0);
+      B.zero_node(&f->Ui, 0);
+      hluinv(B, &f->LU, &f->Li, &f->Ui, &TMP, 0);
+      P.upload_all(s);
+      P.run(op->ds.lists, f->zp.as<int32_t>(), s);
+      HL_CHECK(hipStreamSynchronize(s));
+    }
+    int32_t zp = 0;
+    HL_CHECK(hipMemcpy(&zp, f->zp.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+    HL_CHECK(hipMemcpy(&f->rank_overflows, f->ovf.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (zp) return fail(HLEVY_ERR_ZERO_PIVOT, "zero pivot in a diagonal leaf of the H-LU");
+    const size_t Nb = (size_t)S.N * sizeof(double);
+    for (DevBuf* b : {&f->w_u, &f->w_y, &f->w_b, &f->w_z, &f->w_r, &f->w_d, &f->w_g}) b->alloc(Nb);
+    f->partial.alloc(1024 * sizeof(double));
+    f->scal.alloc(8 * sizeof(double));
+    f->mvG.create(S, op->G, f->w_u.as<double>(), f->w_y.as<double>(), s);
+    f->mvLi.create(S, f->Li, f->w_b.as<double>(), f->w_z.as<double>(), s);
+    f->mvUi.create(S, f->Ui, f->w_z.as<double>(), f->w_d.as<double>(), s);
+    HL_CHECK(hipStreamSynchronize(s));
+    *out = f.release();
+    return HLEVY_OK;
+  });
+}
+
+// x(cluster order, w_d) = U^{-1} L^{-1} b(cluster order, w_b)
+static void fac_apply_inverse(hlevy_fac* f, hipStream_t s) {
+  f->mvLi.run(f->op->ds.lists, s);
+  f->mvUi.run(f->op->ds.lists, s);
+}
+
+hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, const hlevy_refine* refine, void* stream) {
+  if (!f || !b || !x) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (b == x) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not alias");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    const int N = f->op->S.N;
+    const int32_t* perm = f->op->ds.perm.as<int32_t>();
+    HL_CHECK(launch_perm_gather(f->w_b.as<double>(), b, perm, N, s));
+    fac_apply_inverse(f, s);
+    int sweeps = refine ? refine->sweeps : (f->prec == HLEVY_PREC_MIXED ? 2 : 0);
+    if (sweeps > 0) {
+      // keep b in w_r; x in w_u
+      HL_CHECK(hipMemcpyAsync(f->w_r.p, f->w_b.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HL_CHECK(hipMemcpyAsync(f->w_u.p, f->w_d.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      for (int it = 0; it < sweeps; ++it) {
+        f->mvG.run(f->op->ds.lists, s);   // w_y = G x
+        HL_CHECK(launch_residual(f->w_b.as<double>(), f->w_r.as<double>(), f->w_u.as<double>(),
+                                 f->w_y.as<double>(), 0.5 * f->dt, N, s));
+        fac_apply_inverse(f, s);          // w_d = P r
+        HL_CHECK(launch_add(f->w_u.as<double>(), f->w_d.as<double>(), N, s));
+      }
+      HL_CHECK(launch_perm_scatter(x, f->w_u.as<double>(), perm, N, s));
+    } else {
+      HL_CHECK(launch_perm_scatter(x, f->w_d.as<double>(), perm, N, s));
+    }
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g, const double* phi,
+                        const hlevy_refine* refine, hlevy_stats* stats, void* stream) {
+  if (!f || !u) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (g && !phi) return fail(HLEVY_ERR_INVALID_ARG, "phi is required with g");
+  if (g)
+    for (int64_t i = 0; i <= nsteps; ++i)
+      if (!std::isfinite(phi[i])) return fail(HLEVY_ERR_INVALID_ARG, "non-finite phi");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    const int N = f->op->S.N;
+    const int32_t* perm = f->op->ds.perm.as<int32_t>();
+    const double hdt = 0.5 * f->dt;
+    const int sweeps = refine ? refine->sweeps : (f->prec == HLEVY_PREC_MIXED ? 2 : 0);
+    double* uc = f->w_u.as<double>();
+    HL_CHECK(launch_perm_gather(uc, u, perm, N, s));
+    if (g) HL_CHECK(launch_perm_gather(f->w_g.as<double>(), g, perm, N, s));
+    for (int64_t n = 0; n < nsteps; ++n) {
+      const double cg = g ? hdt * (phi[n] + phi[n + 1]) : 0.0;
+      f->mvG.run(f->op->ds.lists, s);   // w_y = G u
+      // b = u + dt/2 G u + dt/2 (f^n + f^{n+1})
+      HL_CHECK(launch_axpy2(f->w_b.as<double>(), uc, hdt, f->w_y.as<double>(), cg,
+                            g ? f->w_g.as<double>() : nullptr, N, s));
+      if (sweeps == 0) {
+        fac_apply_inverse(f, s);            // w_d = U^{-1} L^{-1} b
+        HL_CHECK(hipMemcpyAsync(uc, f->w_d.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      } else {
+        HL_CHECK(hipMemcpyAsync(f->w_r.p, f->w_b.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        fac_apply_inverse(f, s);
+        HL_CHECK(hipMemcpyAsync(uc, f->w_d.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        for (int it = 0; it < sweeps; ++it) {
+          f->mvG.run(f->op->ds.lists, s);
+          HL_CHECK(launch_residual(f->w_b.as<double>(), f->w_r.as<double>(), uc, f->w_y.as<double>(), hdt, N, s));
+          fac_apply_inverse(f, s);
+          HL_CHECK(launch_add(uc, f->w_d.as<double>(), N, s));
+        }
+      }
+    }
+    HL_CHECK(launch_perm_scatter(u, uc, perm, N, s));
+    if (stats) {
+      HL_CHECK(hipStreamSynchronize(s));
+      stats->steps_done = nsteps;
+      stats->last_rel_residual = -1.0;
+      stats->rank_overflows = f->rank_overflows;
+    }
+    return HLEVY_OK;
+  });
+}
+
+void hlevy_op_destroy(hlevy_op* op) { delete op; }
+void hlevy_fac_destroy(hlevy_fac* f) { delete f; }
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+"""Thin ctypes binding of libhlevy.so (include/hlevy.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Vectors are torch tensors on the GPU (float64, contiguous); streams default
+to torch's current stream.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlevy.so")
+
+HLEVY_OK = 0
+PREC_FP64 = 0
+PREC_MIXED = 1
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "NOT_CONVERGED",
+          -5: "RANK_CAP", -6: "BAD_HANDLE", -7: "ZERO_PIVOT"}
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
+                ("a", C.c_double), ("b", C.c_double * 2), ("c", C.c_double), ("s", C.c_double),
+                ("lam", C.c_double), ("C", C.c_double), ("r0", C.c_double)]
+
+
+class HParams(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("eta", C.c_double), ("n_block", C.c_int32),
+                ("aca_tol", C.c_double), ("max_rank", C.c_int32)]
+
+
+class Refine(C.Structure):
+    _fields_ = [("tol", C.c_double), ("sweeps", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("last_rel_residual", C.c_double),
+                ("rank_overflows", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("N", C.c_int64), ("depth", C.c_int32), ("n_clusters", C.c_int32),
+                ("n_dense", C.c_int32), ("n_lowrank", C.c_int32), ("max_leaf_points", C.c_int32),
+                ("min_leaf_points", C.c_int32), ("dense_entries", C.c_int64)]
+
+
+class OpInfo(C.Structure):
+    _fields_ = [("dense_entries", C.c_int64), ("lowrank_entries", C.c_int64), ("max_rank", C.c_int32),
+                ("mean_rank", C.c_double), ("rank_overflows", C.c_int32)]
+
+
+EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
+           "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
+           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_op_destroy", "hlevy_fac_destroy"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhlevy.so is not built: run `python -m paper_1812_08324_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    sig = {
+        "hlevy_abi_version": ([], C.c_int32),
+        "hlevy_last_error": ([], C.c_char_p),
+        "hlevy_plan_info": ([C.POINTER(Problem), C.POINTER(HParams), C.POINTER(PlanInfo)], st),
+        "hlevy_assemble": ([C.POINTER(Problem), C.POINTER(HParams), vp, C.POINTER(vp)], st),
+        "hlevy_op_constants": ([vp, C.POINTER(C.c_double), vp], st),
+        "hlevy_op_info": ([vp, C.POINTER(OpInfo), vp], st),
+        "hlevy_matvec": ([vp, vp, vp, vp], st),
+        "hlevy_op_densify": ([vp, vp, vp], st),
+        "hlevy_factor": ([vp, C.c_double, C.c_int32, C.c_double, vp, C.POINTER(vp)], st),
+        "hlevy_solve": ([vp, vp, vp, C.POINTER(Refine), vp], st),
+        "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
+                        C.POINTER(Stats), vp], st),
+        "hlevy_op_destroy": ([vp], None),
+        "hlevy_fac_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+class HlevyError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib.hlevy_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != HLEVY_OK:
+        raise HlevyError(status, where)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, n=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0, r0=0.2) -> Problem:
+    p = Problem()
+    p.dim, p.n, p.lo, p.hi = int(dim), int(n), float(lo), float(hi)
+    p.a, p.c, p.s, p.lam = float(a), float(c), float(s), float(lam)
+    p.b[0], p.b[1] = float(b[0]), float(b[1] if len(b) > 1 else 0.0)
+    p.C = -1.0 if C_ is None else float(C_)
+    p.r0 = float(r0)
+    return p
+
+
+def make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16) -> HParams:
+    h = HParams()
+    h.leaf, h.eta, h.n_block, h.aca_tol, h.max_rank = int(leaf), float(eta), int(n_block), float(aca_tol), int(max_rank)
+    return h
+
+
+def plan_info(prob: Problem, hp: HParams) -> dict:
+    out = PlanInfo()
+    _check(lib.hlevy_plan_info(C.byref(prob), C.byref(hp), C.byref(out)), "hlevy_plan_info")
+    return {k: getattr(out, k) for k, _ in PlanInfo._fields_}
+
+
+class Op:
+    """Assembled H-matrix of the generator G (handle owner)."""
+
+    def __init__(self, prob: Problem, hp: HParams, stream=None):
+        h = C.c_void_p()
+        _check(lib.hlevy_assemble(C.byref(prob), C.byref(hp), _stream(stream), C.byref(h)), "hlevy_assemble")
+        self.h = h
+        self.N = prob.n if prob.dim == 1 else prob.n * prob.n
+        self.prob, self.hp = prob, hp
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.hlevy_op_destroy(self.h)
+            self.h = None
+
+
+class Fac:
+    """H-LU factors of I - dt/2 G with their inverses (handle owner)."""
+
+    def __init__(self, op: Op, dt: float, prec: int = PREC_FP64, lu_tol: float = 1e-12, stream=None):
+        h = C.c_void_p()
+        _check(lib.hlevy_factor(op.h, float(dt), int(prec), float(lu_tol), _stream(stream), C.byref(h)),
+               "hlevy_factor")
+        self.h = h
+        self.op = op           # the factor references the operator
+        self.N = op.N
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.hlevy_fac_destroy(self.h)
+            self.h = None
+
+
+def assemble(prob: Problem, hp: HParams, stream=None) -> Op:
+    return Op(prob, hp, stream)
+
+
+def op_constants(op: Op, stream=None):
+    out = (C.c_double * 4)()
+    _check(lib.hlevy_op_constants(op.h, out, _stream(stream)), "hlevy_op_constants")
+    return list(out)
+
+
+def op_info(op: Op, stream=None) -> dict:
+    out = OpInfo()
+    _check(lib.hlevy_op_info(op.h, C.byref(out), _stream(stream)), "hlevy_op_info")
+    return {k: getattr(out, k) for k, _ in OpInfo._fields_}
+
+
+def matvec(op: Op, x, y, stream=None):
+    _check(lib.hlevy_matvec(op.h, _dptr(x, op.N), _dptr(y, op.N), _stream(stream)), "hlevy_matvec")
+
+
+def op_densify(op: Op, dense, stream=None):
+    _check(lib.hlevy_op_densify(op.h, _dptr(dense, op.N * op.N), _stream(stream)), "hlevy_op_densify")
+
+
+def factor(op: Op, dt: float, prec: int = PREC_FP64, lu_tol: float = 1e-12, stream=None) -> Fac:
+    return Fac(op, dt, prec, lu_tol, stream)
+
+
+def _refine(refine):
+    if refine is None:
+        return None
+    r = Refine()
+    r.tol = float(refine.get("tol", 0.0))
+    r.sweeps = int(refine.get("sweeps", 2))
+    return C.byref(r)
+
+
+def solve(fac: Fac, b, x, refine=None, stream=None):
+    _check(lib.hlevy_solve(fac.h, _dptr(b, fac.N), _dptr(x, fac.N), _refine(refine), _stream(stream)),
+           "hlevy_solve")
+
+
+def step(fac: Fac, u, nsteps: int, g=None, phi=None, refine=None, stats=False, stream=None):
+    gp = _dptr(g, fac.N) if g is not None else None
+    php = None
+    if g is not None:
+        if phi is None or len(phi) != nsteps + 1:
+            raise ValueError("phi must hold nsteps + 1 values")
+        php = (C.c_double * (nsteps + 1))(*[float(v) for v in phi])
+    st = Stats() if stats else None
+    _check(lib.hlevy_step(fac.h, _dptr(u, fac.N), int(nsteps), gp, php, _refine(refine),
+                          C.byref(st) if st is not None else None, _stream(stream)), "hlevy_step")
+    if st is not None:
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+    return None
