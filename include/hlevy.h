@@ -178,6 +178,15 @@ hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double*
                         const double* phi, const hlevy_refine* refine,
                         hlevy_stats* stats, void* stream);
 
+/* Per-step kernel timing of the factor's matrix-vector products (for
+ * roofline reporting): runs `reps` products with the matrix `which`
+ * (0 = G, 1 = L^{-1}, 2 = U^{-1}) on internal vectors, timing the
+ * projection and gather kernels separately with HIP events on `stream`.
+ * out[0] = mean projection kernel ms, out[1] = mean gather kernel ms,
+ * out[2] = stored matrix bytes read per product, out[3] = low-rank leaf
+ * bytes (U and V), out[4] = dense leaf bytes, out[5] = N.  Synchronises. */
+hlevy_status hlevy_fac_time_apply(hlevy_fac* fac, int32_t which, int32_t reps, void* stream, double out[6]);
+
 void hlevy_op_destroy(hlevy_op* op);
 void hlevy_fac_destroy(hlevy_fac* fac);
 

@@ -102,7 +102,7 @@ struct CopyItem {
   int32_t m, n, kcap, dense;
   double scale;        // applied to A (dense block or U)
   int32_t add_identity;  // dense diagonal leaf: add the identity after scaling
-  int32_t pad;
+  int32_t expand;        // destination dense, source low rank: dA = scale * U V^T
 };
 
 // Leaf factorisation: LU in place (no pivoting) and the inverses of the

@@ -14,7 +14,7 @@ hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* 
                       int n, double* U, double* V, const int64_t* uoff, const int64_t* voff,
                       int32_t* ranks, int kcap, double eps, hipStream_t s);
 hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, const ChunkItem* gram,
-                           int ngram, const ChunkItem* expand, int nexp, double tol, hipStream_t s);
+                           int ngram, const ChunkItem* expand, int nexp, double tol, int ks, hipStream_t s);
 hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms, hipStream_t s);
 hipError_t launch_dense_prod(const DProdItem* items, int n, hipStream_t s);
 hipError_t launch_copy(const CopyItem* items, int n, hipStream_t s);

@@ -500,56 +500,79 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg,
   }
 }
 
-// pivoted Cholesky (double-double) of the Gram G (K x K, full, in Gh/Gl);
-// writes R (rank x K, original column order, row-major stride KMAX) and
-// returns the rank.
-__device__ int pivoted_cholesky(double* Gh, double* Gl, double* R, int K, int* sel, double* rowh,
-                                double* rowl, int* shared_int, double* shared_d) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < KMAX * KMAX; e += HL_BLOCK) R[e] = 0.0;
+// Pivoted Cholesky (double-double) of the Gram G (K x K, stride ks, in
+// Gh/Gl), one block of 256 threads, every step parallel.  Writes R (rank x K,
+// original column order, row stride ks) and returns the rank; columns whose
+// remaining diagonal falls below 1e-32 of the largest initial diagonal are
+// dropped.  Pivot = largest remaining diagonal (ties: lowest index).
+__device__ int pivoted_cholesky(double* Gh, double* Gl, double* R, int K, int ks, int* sel, double* rowh,
+                                double* rowl, int* sint, double cut2, bool use_dd) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int e = tid; e < ks * ks; e += HL_BLOCK) R[e] = 0.0;
   if (tid < KMAX) sel[tid] = 0;
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int p = 0; p < K; ++p) mx = fmax(mx, Gh[p * KMAX + p]);
-    shared_d[0] = mx;
-  }
   __syncthreads();
-  const double dmax0 = shared_d[0];
+  double dmax0 = 0.0;
+  if (tid < 64) {
+    double v = lane < K ? Gh[lane * ks + lane] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    dmax0 = v;
+  }
+  __shared__ double s_dmax0;
+  if (tid == 0) s_dmax0 = dmax0;
+  __syncthreads();
+  dmax0 = s_dmax0;
   int r = 0;
   for (int j = 0; j < K; ++j) {
-    if (tid == 0) {
-      int best = -1;
-      dd bv = {-1.0, 0.0};
-      for (int p = 0; p < K; ++p) {
-        if (sel[p]) continue;
-        dd v = {Gh[p * KMAX + p], Gl[p * KMAX + p]};
-        if (v.hi > bv.hi || (v.hi == bv.hi && v.lo > bv.lo)) { bv = v; best = p; }
+    if (tid < 64) {
+      // argmax of the remaining diagonal over the first wavefront
+      double vh = -1.0, vl = 0.0;
+      int idx = 0x7fffffff;
+      if (lane < K && !sel[lane]) { vh = Gh[lane * ks + lane]; vl = use_dd ? Gl[lane * ks + lane] : 0.0; idx = lane; }
+      for (int o = 32; o > 0; o >>= 1) {
+        double oh = __shfl_xor(vh, o, 64), ol = __shfl_xor(vl, o, 64);
+        int oi = __shfl_xor(idx, o, 64);
+        if (oh > vh || (oh == vh && (ol > vl || (ol == vl && oi < idx)))) { vh = oh; vl = ol; idx = oi; }
       }
-      if (best < 0 || !(bv.hi > 1e-32 * dmax0) || !(bv.hi > 0.0)) best = -1;
-      shared_int[0] = best;
-      if (best >= 0) sel[best] = 1;
+      if (tid == 0) {
+        int best = (idx < K && vh > cut2 * dmax0 && vh > 0.0) ? idx : -1;
+        sint[0] = best;
+        if (best >= 0) sel[best] = 1;
+      }
     }
     __syncthreads();
-    const int p = shared_int[0];
+    const int p = sint[0];
     if (p < 0) break;
-    const dd rjj = dd_sqrt({Gh[p * KMAX + p], Gl[p * KMAX + p]});
+    const dd gpp = {Gh[p * ks + p], use_dd ? Gl[p * ks + p] : 0.0};
+    const dd rjj = use_dd ? dd_sqrt(gpp) : dd{sqrt(gpp.hi), 0.0};
+    const dd rinv = use_dd ? dd_div({1.0, 0.0}, rjj) : dd{1.0 / rjj.hi, 0.0};
     for (int q = tid; q < K; q += HL_BLOCK) {
       dd v;
+      const int a = min(p, q), b = max(p, q);   // upper triangle holds G
       if (q == p) v = rjj;
       else if (sel[q]) v = {0.0, 0.0};
-      else v = dd_div({Gh[p * KMAX + q], Gl[p * KMAX + q]}, rjj);
+      else if (use_dd) v = dd_mul({Gh[a * ks + b], Gl[a * ks + b]}, rinv);
+      else v = {Gh[a * ks + b] * rinv.hi, 0.0};
       rowh[q] = v.hi;
       rowl[q] = v.lo;
-      R[j * KMAX + q] = v.hi + v.lo;
+      R[j * ks + q] = v.hi + v.lo;
     }
     __syncthreads();
-    for (int e = tid; e < K * K; e += HL_BLOCK) {
-      int q1 = e / K, q2 = e % K;
-      if (sel[q1] || sel[q2]) continue;
-      dd g = {Gh[q1 * KMAX + q2], Gl[q1 * KMAX + q2]};
-      g = dd_add(g, dd_neg(dd_mul({rowh[q1], rowl[q1]}, {rowh[q2], rowl[q2]})));
-      Gh[q1 * KMAX + q2] = g.hi;
-      Gl[q1 * KMAX + q2] = g.lo;
+    // Schur complement update of the upper triangle (q1 <= q2), 16 x 16
+    // thread grid; the lower triangle is read through the symmetry
+    for (int q1 = tid >> 4; q1 < K; q1 += 16) {
+      if (sel[q1]) continue;
+      const dd a = {rowh[q1], rowl[q1]};
+      for (int q2 = q1 + (tid & 15); q2 < K; q2 += 16) {
+        if (sel[q2]) continue;
+        if (use_dd) {
+          dd gv = {Gh[q1 * ks + q2], Gl[q1 * ks + q2]};
+          gv = dd_add(gv, dd_neg(dd_mul(a, {rowh[q2], rowl[q2]})));
+          Gh[q1 * ks + q2] = gv.hi;
+          Gl[q1 * ks + q2] = gv.lo;
+        } else {
+          Gh[q1 * ks + q2] -= a.hi * rowh[q2];
+        }
+      }
     }
     __syncthreads();
     r = j + 1;
@@ -558,21 +581,23 @@ __device__ int pivoted_cholesky(double* Gh, double* Gl, double* R, int K, int* s
   return r;
 }
 
-// One block per target: Gram sums -> R_A, R_B -> M = R_A R_B^T -> one-sided
-// Jacobi SVD -> truncation (relative Frobenius tol) -> Y_U = R_B^T Z_r and
+// One block per target: Gram sums -> R_A, R_B (pivoted Cholesky in
+// double-double) -> M = R_A R_B^T -> one-sided Jacobi SVD -> truncation at
+// the relative Frobenius tolerance -> Y_U = R_B^T Z_r and
 // Y_V = R_A^T W_r Sigma_r^{-1}, so that U_new = A Y_U and V_new = B Y_V.
-__global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg, const Term* terms,
-                                                         double tol) {
+// Dynamic LDS: 4 ks^2 doubles, ks >= the widest concatenation of the launch.
+__global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg, const Term* terms, double tol,
+                                                         int ks) {
   extern __shared__ double smem[];
-  double* Gh = smem;                     // KMAX*KMAX
-  double* Gl = Gh + KMAX * KMAX;         // KMAX*KMAX
-  double* RA = Gl + KMAX * KMAX;         // KMAX*KMAX
-  double* RB = RA + KMAX * KMAX;         // KMAX*KMAX
+  const int ld = ks + 1;   // odd column stride for M and Z: no bank conflicts between pairs
+  double* Gh = smem;
+  double* Gl = Gh + ks * ld;
+  double* RA = Gl + ks * ld;
+  double* RB = RA + ks * ks;
   __shared__ ColMap cm;
   __shared__ int sel[KMAX];
   __shared__ double rowh[KMAX], rowl[KMAX];
   __shared__ int sint[4];
-  __shared__ double sdbl[4];
   __shared__ double sig[KMAX];
   __shared__ int order[KMAX];
   __shared__ int rot_count;
@@ -588,49 +613,70 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
   for (int side = 0; side < 2; ++side) {
     const int nch = side == 0 ? T.nchA : T.nchB;
     const double* src = T.ws + (size_t)(side == 0 ? 0 : T.nchA) * np * 2;
-    for (int e = tid; e < K * K; e += HL_BLOCK) {
-      int p = e / K, q = e % K;
-      int a = min(p, q), b = max(p, q);
-      int idx = pair_index(a, b);
-      dd s = {0.0, 0.0};
-      for (int c = 0; c < nch; ++c) s = dd_add(s, {src[(size_t)c * np * 2 + 2 * idx], src[(size_t)c * np * 2 + 2 * idx + 1]});
-      Gh[p * KMAX + q] = s.hi;
-      Gl[p * KMAX + q] = s.lo;
+    const int npk = npairs(K);
+    for (int idx = tid; idx < npk; idx += HL_BLOCK) {
+      int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (q * (q + 1) / 2 > idx) --q;
+      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
+      const int p = idx - q * (q + 1) / 2;
+      dd s = {src[2 * idx], src[2 * idx + 1]};
+      for (int c = 1; c < nch; c += 4) {
+        double h[4], l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          h[u] = 0.0;
+          l[u] = 0.0;
+          if (c + u < nch) {
+            h[u] = src[(size_t)(c + u) * np * 2 + 2 * idx];
+            l[u] = src[(size_t)(c + u) * np * 2 + 2 * idx + 1];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = dd_add(s, {h[u], l[u]});
+      }
+      Gh[p * ks + q] = s.hi;
+      Gl[p * ks + q] = s.lo;
+      Gh[q * ks + p] = s.hi;
+      Gl[q * ks + p] = s.lo;
     }
     __syncthreads();
-    rk[side] = pivoted_cholesky(Gh, Gl, side == 0 ? RA : RB, K, sel, rowh, rowl, sint, sdbl);
-    __syncthreads();
+    // directions of a factor below 1e-2 tol of its largest column cannot
+    // change the truncated product beyond the tolerance: stop there
+    const double cut = fmax(1e-16, 1e-2 * tol);
+    // double-double only where the tolerance needs digits below sqrt(eps)
+    rk[side] = pivoted_cholesky(Gh, Gl, side == 0 ? RA : RB, K, ks, sel, rowh, rowl, sint,
+                                fmax(cut * cut, 1e-32), tol < 1e-9);
   }
   const int rA = rk[0], rB = rk[1];
-  // M (rA x rB) column-major with stride KMAX, Z (rB x rB)
+  // M (rA x rB) and Z (rB x rB), column-major with stride ld
   double* M = Gh;
   double* Z = Gl;
-  for (int e = tid; e < KMAX * KMAX; e += HL_BLOCK) { M[e] = 0.0; Z[e] = 0.0; }
+  for (int e = tid; e < ks * ld; e += HL_BLOCK) { M[e] = 0.0; Z[e] = 0.0; }
   __syncthreads();
   for (int e = tid; e < rA * rB; e += HL_BLOCK) {
     int i = e % rA, j = e / rA;
     double s = 0.0;
-    for (int q = 0; q < K; ++q) s += RA[i * KMAX + q] * RB[j * KMAX + q];
-    M[i + KMAX * j] = s;
+    for (int q = 0; q < K; ++q) s += RA[i * ks + q] * RB[j * ks + q];
+    M[i + ld * j] = s;
   }
-  for (int e = tid; e < rB; e += HL_BLOCK) Z[e + KMAX * e] = 1.0;
+  for (int e = tid; e < rB; e += HL_BLOCK) Z[e + ld * e] = 1.0;
   __syncthreads();
-  // one-sided Jacobi on the columns of M; disjoint pairs per round
+  // one-sided Jacobi on the columns of M, disjoint pairs per round
   const int nn = rB + (rB & 1);
   const int g = tid >> 3, l8 = tid & 7;
-  for (int sweep = 0; sweep < 60 && nn >= 2; ++sweep) {
+  for (int sweep = 0; sweep < 40 && nn >= 2; ++sweep) {
     if (tid == 0) rot_count = 0;
     __syncthreads();
     for (int rd = 0; rd < nn - 1; ++rd) {
       if (g < nn / 2) {
         int a = (rd + g) % (nn - 1);
         int b = (g == 0) ? nn - 1 : (rd - g + nn - 1) % (nn - 1);
-        if (a > b) { int t = a; a = b; b = t; }
-        bool active = (b < rB);
+        if (a > b) { int tt = a; a = b; b = tt; }
+        const bool active = (b < rB);
         double al = 0.0, be = 0.0, ga = 0.0;
         if (active) {
           for (int i = l8; i < rA; i += 8) {
-            double x = M[i + KMAX * a], y = M[i + KMAX * b];
+            double x = M[i + ld * a], y = M[i + ld * b];
             al += x * x; be += y * y; ga += x * y;
           }
         }
@@ -639,59 +685,76 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
           be += __shfl_xor(be, o, 8);
           ga += __shfl_xor(ga, o, 8);
         }
-        if (active && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        // rotate while the pair is not orthogonal to working accuracy
+        if (active && ga != 0.0 && fabs(ga) > 4e-15 * sqrt(al * be)) {
           double zeta = (be - al) / (2.0 * ga);
-          double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          double tq = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + tq * tq), s = c * tq;
           for (int i = l8; i < rA; i += 8) {
-            double x = M[i + KMAX * a], y = M[i + KMAX * b];
-            M[i + KMAX * a] = c * x - s * y;
-            M[i + KMAX * b] = s * x + c * y;
+            double x = M[i + ld * a], y = M[i + ld * b];
+            M[i + ld * a] = c * x - s * y;
+            M[i + ld * b] = s * x + c * y;
           }
           for (int i = l8; i < rB; i += 8) {
-            double x = Z[i + KMAX * a], y = Z[i + KMAX * b];
-            Z[i + KMAX * a] = c * x - s * y;
-            Z[i + KMAX * b] = s * x + c * y;
+            double x = Z[i + ld * a], y = Z[i + ld * b];
+            Z[i + ld * a] = c * x - s * y;
+            Z[i + ld * b] = s * x + c * y;
           }
           if (l8 == 0) atomicAdd(&rot_count, 1);
         }
       }
       __syncthreads();
     }
-    int rc = rot_count;
+    const int rc = rot_count;
     __syncthreads();
     if (rc == 0) break;
   }
   for (int c = tid; c < rB; c += HL_BLOCK) {
     double s = 0.0;
-    for (int i = 0; i < rA; ++i) s += M[i + KMAX * c] * M[i + KMAX * c];
+    for (int i = 0; i < rA; ++i) s += M[i + ld * c] * M[i + ld * c];
     sig[c] = sqrt(s);
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int c = 0; c < rB; ++c) order[c] = c;
-    for (int a = 1; a < rB; ++a) {  // insertion sort, descending
-      int v = order[a], b = a - 1;
-      while (b >= 0 && sig[order[b]] < sig[v]) { order[b + 1] = order[b]; --b; }
-      order[b + 1] = v;
+  // rank-based sort (descending, ties by index) and truncation via a suffix
+  // sum of squared singular values, both in the first wavefront
+  if (tid < 64) {
+    const int c = tid;
+    double sc = c < rB ? sig[c] : -1.0;
+    if (c < rB) {
+      int pos = 0;
+      for (int c2 = 0; c2 < rB; ++c2) {
+        double s2 = sig[c2];
+        pos += (s2 > sc || (s2 == sc && c2 < c)) ? 1 : 0;
+      }
+      order[pos] = c;
     }
-    double tot = 0.0;
-    for (int c = 0; c < rB; ++c) tot += sig[c] * sig[c];
-    int r = rB;
-    double tail = 0.0;
-    while (r > 0) {
-      double sgm = sig[order[r - 1]];
-      if (tail + sgm * sgm <= tol * tol * tot) { tail += sgm * sgm; --r; } else break;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    double v = lane < rB ? sig[order[lane]] : 0.0;
+    double sq = v * v;
+    // suffix sum: suf[lane] = sum_{c >= lane} sq[c]
+    double suf = sq;
+    for (int o = 1; o < 64; o <<= 1) {
+      double w = __shfl_down(suf, o, 64);
+      if (lane + o < 64) suf += w;
     }
-    if (!(tot > 0.0)) r = 0;
-    int ovf = 0;
-    if (r > T.kcap) { r = T.kcap; ovf = 1; }
-    sint[0] = r;
-    T.info[0] = kC;
-    T.info[1] = r;
-    T.info[2] = ovf;
-    if (ovf && T.overflow) atomicAdd(T.overflow, 1);
-    if (T.rank) *T.rank = r;
+    double tot = __shfl(suf, 0, 64);
+    // keep column c unless the tail starting at c fits within tol^2 * tot
+    int keep = (lane < rB && suf > tol * tol * tot) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) keep += __shfl_xor(keep, o, 64);
+    if (lane == 0) {
+      int r = (tot > 0.0) ? keep : 0;
+      int ovf = 0;
+      if (r > T.kcap) { r = T.kcap; ovf = 1; }
+      sint[0] = r;
+      T.info[0] = kC;
+      T.info[1] = r;
+      T.info[2] = ovf;
+      if (ovf && T.overflow) atomicAdd(T.overflow, 1);
+      if (T.rank) *T.rank = r;
+    }
   }
   __syncthreads();
   const int r = sint[0];
@@ -701,11 +764,243 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
     int q = e % K, c = e / K;
     int oc = order[c];
     double su = 0.0, sv = 0.0;
-    for (int i = 0; i < rB; ++i) su += RB[i * KMAX + q] * Z[i + KMAX * oc];
-    for (int i = 0; i < rA; ++i) sv += RA[i * KMAX + q] * M[i + KMAX * oc];
+    for (int i = 0; i < rB; ++i) su += RB[i * ks + q] * Z[i + ld * oc];
+    for (int i = 0; i < rA; ++i) sv += RA[i * ks + q] * M[i + ld * oc];
     double sg = sig[oc];
     YU[q + (size_t)Kc * c] = su;
     YV[q + (size_t)Kc * c] = sv / (sg * sg);
+  }
+}
+
+// Fast rounded addition for concatenations of at most 48 columns.
+//
+// With A (m x K) and B (n x K) the concatenated factors of C = A B^T,
+// G_A = A^T A, G_B = B^T B (double-double):
+//  1. pivoted Cholesky G_B = R_B^T R_B  (B = Q_B R_B, rank rB)
+//  2. T1 = G_A R_B^T (K x rB) and G_M = R_B T1 = M^T M for M = R_A R_B^T
+//  3. pivoted Cholesky of G_M, stopped as soon as the trace of the
+//     remaining Schur complement (= ||M - M_J T||_F^2, the squared error of
+//     the column-subset approximation) is <= tol^2 trace(G_M) or the rank
+//     capacity is reached: pivots J, upper factor R_MJ (r x r)
+//  4. U_new = A Y_U, Y_U = R_B[J,:]^T R_MJ^{-1}  (orthonormal columns: Q_A M_J R_MJ^{-1})
+//     V_new = B Y_V, Y_V = T1[:, J] R_MJ^{-1}    (= C^T U_new)
+// so C - U_new V_new^T = (I - P) C with P the projector on span(U_new) and
+// ||C - U_new V_new^T||_F = ||M - M_J T||_F <= tol ||C||_F.
+// Schur complements are stored in their upper triangle; row j of each
+// Cholesky factor is written into the storage row of its pivot.
+__device__ int pchol_inplace(double* Sh, double* Sl, int K, int ks, int* sel, int* piv, double* rowh,
+                             double* rowl, int* sint, double* sdbl, int mode, double thr, int rmax, bool use_dd) {
+  // mode 0: stop when the largest remaining diagonal <= thr * (initial largest diagonal)
+  // mode 1: stop when the remaining trace <= thr * (initial trace)
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < KMAX) sel[tid] = 0;
+  __syncthreads();
+  if (tid < 64) {
+    double d = lane < K ? Sh[lane * ks + lane] : 0.0;
+    double mx = d, sm = d;
+    for (int o = 32; o > 0; o >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, o, 64));
+      sm += __shfl_xor(sm, o, 64);
+    }
+    if (tid == 0) sdbl[0] = mode == 0 ? mx : sm;
+  }
+  __syncthreads();
+  const double ref = sdbl[0];
+  int r = 0;
+  for (int j = 0; j < K && j < rmax; ++j) {
+    if (tid < 64) {
+      double vh = -1.0, vl = 0.0, tr = 0.0;
+      int idx = 0x7fffffff;
+      if (lane < K && !sel[lane]) {
+        vh = Sh[lane * ks + lane];
+        vl = use_dd ? Sl[lane * ks + lane] : 0.0;
+        idx = lane;
+        tr = vh;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        double oh = __shfl_xor(vh, o, 64), ol = __shfl_xor(vl, o, 64);
+        int oi = __shfl_xor(idx, o, 64);
+        tr += __shfl_xor(tr, o, 64);
+        if (oh > vh || (oh == vh && (ol > vl || (ol == vl && oi < idx)))) { vh = oh; vl = ol; idx = oi; }
+      }
+      if (tid == 0) {
+        bool stop = !(vh > 0.0) || idx >= K;
+        if (mode == 0) stop = stop || !(vh > thr * ref);
+        else stop = stop || !(tr > thr * ref);
+        sint[0] = stop ? -1 : idx;
+        if (!stop) { sel[idx] = 1; piv[j] = idx; }
+      }
+    }
+    __syncthreads();
+    const int p = sint[0];
+    if (p < 0) break;
+    const dd gpp = {Sh[p * ks + p], use_dd ? Sl[p * ks + p] : 0.0};
+    const dd rjj = use_dd ? dd_sqrt(gpp) : dd{sqrt(gpp.hi), 0.0};
+    const dd rinv = use_dd ? dd_div({1.0, 0.0}, rjj) : dd{1.0 / rjj.hi, 0.0};
+    for (int q = tid; q < K; q += HL_BLOCK) {
+      dd v;
+      const int a = min(p, q), b = max(p, q);
+      if (q == p) v = rjj;
+      else if (sel[q]) v = {0.0, 0.0};
+      else if (use_dd) v = dd_mul({Sh[a * ks + b], Sl[a * ks + b]}, rinv);
+      else v = {Sh[a * ks + b] * rinv.hi, 0.0};
+      rowh[q] = v.hi;
+      rowl[q] = v.lo;
+    }
+    __syncthreads();
+    for (int q1 = tid >> 4; q1 < K; q1 += 16) {
+      if (sel[q1]) continue;
+      const dd a = {rowh[q1], rowl[q1]};
+      for (int q2 = q1 + (tid & 15); q2 < K; q2 += 16) {
+        if (sel[q2]) continue;
+        if (use_dd) {
+          dd gv = {Sh[q1 * ks + q2], Sl[q1 * ks + q2]};
+          gv = dd_add(gv, dd_neg(dd_mul(a, {rowh[q2], rowl[q2]})));
+          Sh[q1 * ks + q2] = gv.hi;
+          Sl[q1 * ks + q2] = gv.lo;
+        } else {
+          Sh[q1 * ks + q2] -= a.hi * rowh[q2];
+        }
+      }
+    }
+    // the pivot row is no longer part of the Schur complement: it now holds
+    // row j of the factor (original column order)
+    for (int q = tid; q < K; q += HL_BLOCK) {
+      Sh[p * ks + q] = rowh[q];
+      Sl[p * ks + q] = rowl[q];
+    }
+    __syncthreads();
+    r = j + 1;
+  }
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget* tg, const Term* terms,
+                                                              double tol, int ks) {
+  extern __shared__ double smem[];
+  double* Xh = smem;                 // G_B, then R_B (rows at pivot positions)
+  double* Xl = Xh + ks * ks;
+  double* Yh = Xl + ks * ks;         // G_A, then G_M / R_M
+  double* Yl = Yh + ks * ks;
+  double* Zh = Yl + ks * ks;         // T1 = G_A R_B^T (K x rB, row q col j at q * ks + j)
+  double* Zl = Zh + ks * ks;
+  __shared__ ColMap cm;
+  __shared__ int sel[KMAX], pivB[KMAX], pivM[KMAX];
+  __shared__ double rowh[KMAX], rowl[KMAX];
+  __shared__ int sint[4];
+  __shared__ double sdbl[4];
+  const LFlushTarget T = tg[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int kC = T.rank ? *T.rank : 0;
+  if (tid == 0) build_colmap(T, terms, kC, cm);
+  __syncthreads();
+  const int K = cm.K;
+  const int Kc = T.Kcap;
+  const int np = npairs(Kc);
+  const bool use_dd = tol < 1e-9;
+  // Gram matrices (sum of the chunk partials), full symmetric storage
+  for (int side = 0; side < 2; ++side) {
+    double* Gh = side == 0 ? Yh : Xh;
+    double* Gl = side == 0 ? Yl : Xl;
+    const int nch = side == 0 ? T.nchA : T.nchB;
+    const double* src = T.ws + (size_t)(side == 0 ? 0 : T.nchA) * np * 2;
+    const int npk = npairs(K);
+    for (int idx = tid; idx < npk; idx += HL_BLOCK) {
+      int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (q * (q + 1) / 2 > idx) --q;
+      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
+      const int p = idx - q * (q + 1) / 2;
+      dd s = {src[2 * idx], src[2 * idx + 1]};
+      for (int c = 1; c < nch; c += 4) {
+        double h[4], l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          h[u] = 0.0;
+          l[u] = 0.0;
+          if (c + u < nch) {
+            h[u] = src[(size_t)(c + u) * np * 2 + 2 * idx];
+            l[u] = src[(size_t)(c + u) * np * 2 + 2 * idx + 1];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = dd_add(s, {h[u], l[u]});
+      }
+      Gh[p * ks + q] = s.hi;
+      Gl[p * ks + q] = s.lo;
+      Gh[q * ks + p] = s.hi;
+      Gl[q * ks + p] = s.lo;
+    }
+  }
+  __syncthreads();
+  // 1. G_B = R_B^T R_B; directions below 1e-2 tol of the largest are dropped
+  const double cut = fmax(1e-16, 1e-2 * tol);
+  const int rB = pchol_inplace(Xh, Xl, K, ks, sel, pivB, rowh, rowl, sint, sdbl, 0, fmax(cut * cut, 1e-32),
+                               KMAX, use_dd);
+  // 2. T1[q][j] = sum_p G_A[q][p] R_B[j][p]
+  for (int e = tid; e < K * rB; e += HL_BLOCK) {
+    const int q = e / rB, j = e - q * rB;
+    const double* rb_h = Xh + pivB[j] * ks;
+    const double* rb_l = Xl + pivB[j] * ks;
+    dd s = {0.0, 0.0};
+    for (int p = 0; p < K; ++p) {
+      if (use_dd) s = dd_add(s, dd_mul({Yh[q * ks + p], Yl[q * ks + p]}, {rb_h[p], rb_l[p]}));
+      else s.hi += Yh[q * ks + p] * rb_h[p];
+    }
+    Zh[q * ks + j] = s.hi;
+    Zl[q * ks + j] = s.lo;
+  }
+  __syncthreads();
+  // G_M[i][j] = sum_p R_B[i][p] T1[p][j]  (overwrites G_A)
+  for (int e = tid; e < rB * rB; e += HL_BLOCK) {
+    const int i = e / rB, j = e - i * rB;
+    const double* rb_h = Xh + pivB[i] * ks;
+    const double* rb_l = Xl + pivB[i] * ks;
+    dd s = {0.0, 0.0};
+    for (int p = 0; p < K; ++p) {
+      if (use_dd) s = dd_add(s, dd_mul({rb_h[p], rb_l[p]}, {Zh[p * ks + j], Zl[p * ks + j]}));
+      else s.hi += rb_h[p] * Zh[p * ks + j];
+    }
+    Yh[i * ks + j] = s.hi;
+    Yl[i * ks + j] = s.lo;
+  }
+  __syncthreads();
+  // 3. rank-revealing Cholesky of G_M with the truncation tolerance
+  const int r = pchol_inplace(Yh, Yl, rB, ks, sel, pivM, rowh, rowl, sint, sdbl, 1, tol * tol, T.kcap, use_dd);
+  if (tid == 0) {
+    int ovf = 0;
+    if (r == T.kcap && r < rB) {
+      // capacity reached: flag it if the remaining trace still exceeds the tolerance
+      double tr = 0.0;
+      for (int q = 0; q < rB; ++q)
+        if (!sel[q]) tr += Yh[q * ks + q];
+      ovf = tr > tol * tol * sdbl[0] ? 1 : 0;
+    }
+    T.info[0] = kC;
+    T.info[1] = r;
+    T.info[2] = ovf;
+    if (ovf && T.overflow) atomicAdd(T.overflow, 1);
+    if (T.rank) *T.rank = r;
+  }
+  // 4. Y_U^T = R_MJ^{-T} R_B[J,:]  and  Y_V = T1[:, J] R_MJ^{-1}, column by
+  //    column (R_MJ[i][c] = row pivM[i] of the in-place factor at column pivM[c])
+  double* YU = T.ws + (size_t)(T.nchA + T.nchB) * np * 2;
+  double* YV = YU + (size_t)Kc * T.kcap;
+  for (int c = 0; c < r; ++c) {
+    const double dinv = 1.0 / Yh[pivM[c] * ks + pivM[c]];
+    for (int q = tid; q < K; q += HL_BLOCK) {
+      // row q of Y_U, column c
+      double u = Xh[pivB[pivM[c]] * ks + q];
+      double v = Zh[q * ks + pivM[c]];
+      for (int i = 0; i < c; ++i) {
+        const double rmic = Yh[pivM[i] * ks + pivM[c]];
+        u -= rmic * YU[q + (size_t)Kc * i];
+        v -= rmic * YV[q + (size_t)Kc * i];
+      }
+      YU[q + (size_t)Kc * c] = u * dinv;
+      YV[q + (size_t)Kc * c] = v * dinv;
+    }
+    __syncthreads();
   }
 }
 
@@ -777,6 +1072,17 @@ __global__ void __launch_bounds__(HL_BLOCK) k_dense_prod(const DProdItem* items)
 
 __global__ void __launch_bounds__(HL_BLOCK) k_copy_leaf(const CopyItem* items) {
   const CopyItem it = items[blockIdx.x];
+  if (it.dense && it.expand) {
+    const int k = (it.A && it.rank) ? *it.rank : 0;
+    const int tot = it.m * it.n;
+    for (int e = threadIdx.x; e < tot; e += HL_BLOCK) {
+      const int i = e % it.m, j = e / it.m;
+      double v = 0.0;
+      for (int p = 0; p < k; ++p) v += it.A[i + (size_t)it.m * p] * it.B[j + (size_t)it.n * p];
+      it.dA[e] = it.scale * v;
+    }
+    return;
+  }
   if (it.dense) {
     const int tot = it.m * it.n;
     for (int e = threadIdx.x; e < tot; e += HL_BLOCK) {
@@ -795,54 +1101,61 @@ __global__ void __launch_bounds__(HL_BLOCK) k_copy_leaf(const CopyItem* items) {
 // LU without pivoting of a diagonal leaf (in place), then the inverses of the
 // unit-lower factor and of the upper factor.
 __global__ void __launch_bounds__(HL_BLOCK) k_getrf_inv(const GetrfItem* items, int32_t* zero_pivot) {
-  __shared__ double A[64 * 64];
-  __shared__ double X[64 * 64];
+  // column stride 65 for both arrays: no LDS bank conflicts when threads
+  // walk different columns
+  __shared__ double Ap[64 * 65];
+  __shared__ double X[64 * 65];
   const GetrfItem it = items[blockIdx.x];
   const int m = it.m;
-  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) A[e] = it.LU[e];
+#define A(i, j) Ap[(i) + 65 * (j)]
+  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) A(e % m, e / m) = it.LU[e];
   __syncthreads();
   for (int kk = 0; kk < m; ++kk) {
-    const double piv = A[kk + m * kk];
+    const double piv = A(kk, kk);
     if (piv == 0.0) {
       if (threadIdx.x == 0) atomicAdd(zero_pivot, 1);
       return;
     }
-    for (int i = kk + 1 + threadIdx.x; i < m; i += HL_BLOCK) A[i + m * kk] /= piv;
+    for (int i = kk + 1 + threadIdx.x; i < m; i += HL_BLOCK) A(i, kk) /= piv;
     __syncthreads();
     const int rem = m - kk - 1;
     for (int e = threadIdx.x; e < rem * rem; e += HL_BLOCK) {
       int i = kk + 1 + e % rem, j = kk + 1 + e / rem;
-      A[i + m * j] -= A[i + m * kk] * A[kk + m * j];
+      A(i, j) -= A(i, kk) * A(kk, j);
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) it.LU[e] = A[e];
-  // inverse of the unit lower factor: column c by forward substitution
-  for (int c = threadIdx.x; c < m; c += HL_BLOCK) {
-    for (int i = 0; i < m; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      if (i > c)
-        for (int j = c; j < i; ++j) v -= A[i + m * j] * X[j + m * c];
-      X[i + m * c] = (i < c) ? 0.0 : v;
+  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) it.LU[e] = A(e % m, e / m);
+  // inverse of the unit lower factor, right-looking: X = I; for each k,
+  // X[i, :] -= L[i, k] X[k, :] for i > k (all (i, c) in parallel)
+  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) X[(e % m) + 65 * (e / m)] = (e % m) == (e / m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = 0; k < m - 1; ++k) {
+    const int rem = m - k - 1;
+    for (int e = threadIdx.x; e < rem * (k + 1); e += HL_BLOCK) {
+      const int i = k + 1 + e % rem, c = e / rem;   // X[k, c] = 0 for c > k
+      X[i + 65 * c] -= A(i, k) * X[k + 65 * c];
     }
+    __syncthreads();
   }
+  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) it.Li[e] = X[(e % m) + 65 * (e / m)];
   __syncthreads();
-  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) it.Li[e] = X[e];
+  // inverse of the upper factor, right-looking from the bottom: X = I; for
+  // k = m-1 .. 0: X[k, :] /= U[k, k]; X[i, :] -= U[i, k] X[k, :] for i < k
+  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) X[(e % m) + 65 * (e / m)] = (e % m) == (e / m) ? 1.0 : 0.0;
   __syncthreads();
-  // inverse of the upper factor: column c by backward substitution
-  for (int c = threadIdx.x; c < m; c += HL_BLOCK) {
-    for (int i = m - 1; i >= 0; --i) {
-      double v = 0.0;
-      if (i <= c) {
-        v = (i == c) ? 1.0 : 0.0;
-        for (int j = i + 1; j <= c; ++j) v -= A[i + m * j] * X[j + m * c];
-        v /= A[i + m * i];
-      }
-      X[i + m * c] = v;
+  for (int k = m - 1; k >= 0; --k) {
+    const double inv = 1.0 / A(k, k);
+    for (int c = threadIdx.x; c < m; c += HL_BLOCK) X[k + 65 * c] *= inv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * m; e += HL_BLOCK) {
+      const int i = e % k, c = e / k;
+      X[i + 65 * c] -= A(i, k) * X[k + 65 * c];
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) it.Ui[e] = X[e];
+  for (int e = threadIdx.x; e < m * m; e += HL_BLOCK) it.Ui[e] = X[(e % m) + 65 * (e / m)];
+#undef A
 }
 
 // ---------------------------------------------------------------------------
@@ -1019,11 +1332,16 @@ hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* 
   return post();
 }
 hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, const ChunkItem* gram,
-                           int ngram, const ChunkItem* expand, int nexp, double tol, hipStream_t s) {
+                           int ngram, const ChunkItem* expand, int nexp, double tol, int ks, hipStream_t s) {
   if (ntg == 0) return hipSuccess;
   hipLaunchKernelGGL(k_flush_gram, dim3(ngram), dim3(HL_BLOCK), 0, s, tg, terms, gram);
-  size_t shm = 4 * KMAX * KMAX * sizeof(double);
-  hipLaunchKernelGGL(k_flush_core, dim3(ntg), dim3(HL_BLOCK), shm, s, tg, terms, tol);
+  if (ks <= 48) {
+    size_t shm = 6 * (size_t)ks * ks * sizeof(double);
+    hipLaunchKernelGGL(k_flush_core_fast, dim3(ntg), dim3(HL_BLOCK), shm, s, tg, terms, tol, ks);
+  } else {
+    size_t shm = (4 * (size_t)ks * ks + 2 * (size_t)ks) * sizeof(double);
+    hipLaunchKernelGGL(k_flush_core, dim3(ntg), dim3(HL_BLOCK), shm, s, tg, terms, tol, ks);
+  }
   hipLaunchKernelGGL(k_flush_expand, dim3(nexp), dim3(HL_BLOCK), 0, s, tg, terms, expand);
   return post();
 }
@@ -1091,7 +1409,10 @@ hipError_t launch_densify(const LeafDesc* L, const int32_t* rank, int nleaves, c
 
 namespace hl {
 hipError_t init_kernel_attributes() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_flush_core_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     6 * 48 * 48 * (int)sizeof(double));
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_flush_core, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             4 * KMAX * KMAX * (int)sizeof(double));
+                             (4 * KMAX * KMAX + 2 * KMAX) * (int)sizeof(double));
 }
 }  // namespace hl

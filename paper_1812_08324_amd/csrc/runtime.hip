@@ -10,15 +10,31 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <chrono>
+#include <cstdlib>
 #include <vector>
 
 #include "hl_internal.h"
 #include "hl_jobs.h"
 #include "hl_kernels.h"
+#include "hl_mv.h"
 
 namespace hl {
 
 thread_local std::string g_last_error;
+
+// Optional host-side phase timing on stderr (HLEVY_VERBOSE=1).
+static bool verbose() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("HLEVY_VERBOSE");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 static hlevy_status fail(hlevy_status st, const std::string& msg) {
   g_last_error = msg;
@@ -143,7 +159,10 @@ struct HMat {
   int32_t* rank = nullptr;  // device, per leaf
   size_t pool_doubles = 0;
 
-  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s) {
+  // dense_leaf_level: admissible blocks between two leaf clusters are held
+  // dense in this matrix (the factorisation workspace), so that updates of
+  // leaf-level blocks need no rounded addition.
+  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s, bool dense_leaf_level = false) {
     S = &st;
     L.resize(st.lf.size());
     size_t off = 0;
@@ -156,6 +175,7 @@ struct HMat {
       d.clo = li.clo;
       bool zero = (shape == LOWER && leaf_upper(li)) || (shape == UPPER && leaf_lower(li));
       d.kind = zero ? K_ZERO : li.kind;
+      if (d.kind == K_LR && dense_leaf_level && st.leafpos[li.r] >= 0 && st.leafpos[li.c] >= 0) d.kind = K_DENSE;
       d.kcap = 0;
       if (d.kind == K_DENSE) {
         d.A = reinterpret_cast<double*>(off);
@@ -221,6 +241,7 @@ struct Phase {
   int type;
   int b0, n0, b1, n1, b2, n2;
   double tol;
+  int ks;   // PH_LFLUSH: LDS stride, >= the widest concatenation of the phase
 };
 
 struct Plan {
@@ -267,7 +288,7 @@ struct Plan {
         case PH_LFLUSH:
           HL_CHECK(launch_flush_lr(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(),
                                    dlgram.as<ChunkItem>() + p.b1, p.n1, dlexp.as<ChunkItem>() + p.b2,
-                                   p.n2, p.tol, s));
+                                   p.n2, p.tol, p.ks, s));
           break;
         case PH_COPY:
           HL_CHECK(launch_copy(dcopies.as<CopyItem>() + p.b0, p.n0, s));
@@ -317,7 +338,7 @@ struct Builder {
   double tol;
   // batch state
   std::vector<ApplyJob> bjobs;
-  std::vector<std::vector<ProjItem>> bproj_unused;
+  std::vector<const HMat*> bjob_mat;
   std::vector<DProdItem> bdprod;
   std::map<std::pair<HMat*, int>, std::vector<PendingTerm>> pending;
   WsStack::Mark mk{};
@@ -355,6 +376,7 @@ struct Builder {
     J.tstride = 32 * kxcap;
     J.T = ws.alloc_d((size_t)(b.lend - b.lbeg) * J.tstride);
     bjobs.push_back(J);
+    bjob_mat.push_back(M);
   }
 
   // push a term covering rows [r0, r1) x cols [c0, c1) (absolute) into the
@@ -445,25 +467,37 @@ struct Builder {
     }
   }
 
-  void emit_lflush(std::vector<LFlushTarget>& tgs, std::vector<std::vector<Term>>& tlists, double ftol) {
-    if (tgs.empty()) return;
-    Phase ph{PH_LFLUSH, (int)P.ltg.size(), (int)tgs.size(), (int)P.lgram.size(), 0, (int)P.lexp.size(), 0,
-             ftol};
-    for (size_t q = 0; q < tgs.size(); ++q) {
-      LFlushTarget T = tgs[q];
-      T.tbeg = (int)P.terms.size();
-      T.tcount = (int)tlists[q].size();
-      for (auto& t : tlists[q]) P.terms.push_back(t);
-      int tix = (int)P.ltg.size();
-      add_chunks(P, tix - ph.b0, T.m, T.n, T, 0);
-      T.ws = ws.alloc_d(flush_ws_doubles(T));
-      T.info = ws.alloc_i(4);
-      T.overflow = overflow;
-      P.ltg.push_back(T);
+  // Emit rounded additions for the given targets, one phase per width
+  // bucket (16, 32, 48, 64 columns) so that the LDS of the core kernel is
+  // sized to the bucket.  Returns each target's index in P.ltg.
+  std::vector<int> emit_lflush(std::vector<LFlushTarget>& tgs, std::vector<std::vector<Term>>& tlists,
+                               double ftol) {
+    std::vector<int> where(tgs.size(), -1);
+    for (int bucket = 16; bucket <= KMAX; bucket += 16) {
+      std::vector<size_t> sel;
+      for (size_t q = 0; q < tgs.size(); ++q)
+        if (tgs[q].Kcap <= bucket && tgs[q].Kcap > bucket - 16) sel.push_back(q);
+      if (sel.empty()) continue;
+      Phase ph{PH_LFLUSH, (int)P.ltg.size(), (int)sel.size(), (int)P.lgram.size(), 0, (int)P.lexp.size(), 0,
+               ftol, bucket};
+      for (size_t q : sel) {
+        LFlushTarget T = tgs[q];
+        T.tbeg = (int)P.terms.size();
+        T.tcount = (int)tlists[q].size();
+        for (auto& tm : tlists[q]) P.terms.push_back(tm);
+        int tix = (int)P.ltg.size();
+        add_chunks(P, tix - ph.b0, T.m, T.n, T, 0);
+        T.ws = ws.alloc_d(flush_ws_doubles(T));
+        T.info = ws.alloc_i(4);
+        T.overflow = overflow;
+        where[q] = tix;
+        P.ltg.push_back(T);
+      }
+      ph.n1 = (int)P.lgram.size() - ph.b1;
+      ph.n2 = (int)P.lexp.size() - ph.b2;
+      P.ph.push_back(ph);
     }
-    ph.n1 = (int)P.lgram.size() - ph.b1;
-    ph.n2 = (int)P.lexp.size() - ph.b2;
-    P.ph.push_back(ph);
+    return where;
   }
 
   void end() {
@@ -474,12 +508,8 @@ struct Builder {
       for (size_t q = 0; q < bjobs.size(); ++q) {
         const ApplyJob& J = bjobs[q];
         P.jobs.push_back(J);
-        for (int l = J.lbeg; l < J.lend; ++l) {
-          // LR leaves of the operand; kinds come from the job's matrix (host copy not
-          // reachable here), so every LR-structured leaf gets an item and the kernel
-          // reads a zero rank for structurally zero leaves
-          if (S.lf[l].kind == K_LR) P.proj.push_back(ProjItem{jb + (int)q, l});
-        }
+        for (int l = J.lbeg; l < J.lend; ++l)
+          if (bjob_mat[q]->L[l].kind == K_LR) P.proj.push_back(ProjItem{jb + (int)q, l});
         int o0 = J.trans ? J.clo : J.rlo, o1 = J.trans ? J.chi : J.rhi;
         for (size_t lp = 0; lp < S.leafcl.size(); ++lp) {
           const Cluster& c = S.cl[S.leafcl[lp]];
@@ -496,61 +526,92 @@ struct Builder {
       for (auto& d : bdprod) P.dprod.push_back(d);
       P.ph.push_back(ph);
     }
-    // 3. dense terms into low-rank targets are compressed on their own first
+    // 3. dense terms into low-rank targets are compressed on their own
+    //    first, 32 columns at a time (P = [P1 P2] = P1 I1^T + P2 I2^T), so
+    //    that every rounded addition stays within 48 columns
     {
-      std::vector<LFlushTarget> tgs;
-      std::vector<std::vector<Term>> tl;
+      struct Comp {
+        LFlushTarget T;
+        Term src;     // the dense term
+        int kc;
+      };
+      std::vector<Comp> comps;
       for (auto& kv : pending) {
         HMat* C = kv.first.first;
         const LeafDesc& d = C->L[kv.first.second];
         if (d.kind != K_LR) continue;
         for (auto& pt : kv.second) {
           if (!pt.t.dense) continue;
-          int mr = pt.t.mr, nc = pt.t.nc;
-          int kc = std::min(32, std::min(mr, nc));
-          LFlushTarget T{};
-          T.U = ws.alloc_d((size_t)mr * kc);
-          T.V = ws.alloc_d((size_t)nc * kc);
-          T.rank = nullptr;
-          T.m = mr;
-          T.n = nc;
-          T.kcap = kc;
-          T.Kcap = nc;
-          Term lt{};
-          lt.dense = 0;
-          lt.ro = 0;
-          lt.mr = mr;
-          lt.co = 0;
-          lt.nc = nc;
-          lt.U = pt.t.U;
-          lt.ldu = pt.t.ldu;
-          lt.W = ds.ident.as<double>();
-          lt.ldw = 64;
-          lt.k = nullptr;
-          lt.kfix = nc;
-          lt.sign = 1.0;
-          tgs.push_back(T);
-          tl.push_back({lt});
+          const int mr = pt.t.mr, nc = pt.t.nc;
+          const int kc = std::min(std::min(d.kcap, 32), std::min(mr, nc));
+          Comp c{};
+          c.T.U = ws.alloc_d((size_t)mr * kc);
+          c.T.V = ws.alloc_d((size_t)nc * kc);
+          c.T.rank = ws.alloc_i(1);
+          c.T.m = mr;
+          c.T.n = nc;
+          c.T.kcap = kc;
+          c.src = pt.t;
+          c.kc = kc;
+          comps.push_back(c);
         }
       }
-      size_t first = P.ltg.size();
-      emit_lflush(tgs, tl, tol);
-      // rewrite those dense terms as low-rank terms on the compressed factors
-      size_t q = first;
-      for (auto& kv : pending) {
-        HMat* C = kv.first.first;
-        const LeafDesc& d = C->L[kv.first.second];
-        if (d.kind != K_LR) continue;
-        for (auto& pt : kv.second) {
-          if (!pt.t.dense) continue;
-          const LFlushTarget& T = P.ltg[q++];
-          pt.t.dense = 0;
-          pt.t.U = T.U;
-          pt.t.ldu = T.m;
-          pt.t.W = T.V;
-          pt.t.ldw = T.n;
-          pt.t.k = T.info + 1;
-          pt.kcap = T.kcap;
+      if (!comps.empty()) {
+        // the temporary targets start empty: their rank counters are zeroed
+        // by the first round (which ignores them) and then carried forward
+        for (int half = 0; half < 2; ++half) {
+          std::vector<LFlushTarget> tgs;
+          std::vector<std::vector<Term>> tl;
+          for (auto& c : comps) {
+            const int nc = c.src.nc;
+            const int c0 = half * 32, c1 = std::min(nc, c0 + 32);
+            if (c0 >= c1) continue;
+            LFlushTarget T = c.T;
+            if (half == 0) T.rank = nullptr;   // start empty; the new rank goes to info[1]
+            T.Kcap = (half == 0 ? 0 : c.kc) + (c1 - c0);
+            Term lt{};
+            lt.dense = 0;
+            lt.ro = 0;
+            lt.mr = c.src.mr;
+            lt.co = c0;
+            lt.nc = c1 - c0;
+            lt.U = c.src.U + (size_t)c.src.ldu * c0;
+            lt.ldu = c.src.ldu;
+            lt.W = ds.ident.as<double>();
+            lt.ldw = 64;
+            lt.kfix = c1 - c0;
+            lt.sign = 1.0;
+            tgs.push_back(T);
+            tl.push_back({lt});
+          }
+          std::vector<int> where = emit_lflush(tgs, tl, tol);
+          // after the first round the rank of each temporary is in info[1]:
+          // copy the pointer so that the second round reads it as its rank
+          size_t q = 0;
+          for (auto& c : comps) {
+            const int c0 = half * 32;
+            if (c0 >= std::min(c.src.nc, c0 + 32)) continue;
+            if (half == 0) c.T.rank = P.ltg[where[q]].info + 1;
+            ++q;
+          }
+        }
+        // rewrite those dense terms as low-rank terms on the compressed factors
+        size_t q = 0;
+        for (auto& kv : pending) {
+          HMat* C = kv.first.first;
+          const LeafDesc& d = C->L[kv.first.second];
+          if (d.kind != K_LR) continue;
+          for (auto& pt : kv.second) {
+            if (!pt.t.dense) continue;
+            const Comp& c = comps[q++];
+            pt.t.dense = 0;
+            pt.t.U = c.T.U;
+            pt.t.ldu = c.T.m;
+            pt.t.W = c.T.V;
+            pt.t.ldw = c.T.n;
+            pt.t.k = c.T.rank;
+            pt.kcap = c.kc;
+          }
         }
       }
     }
@@ -587,13 +648,15 @@ struct Builder {
           T.n = d.n;
           T.kcap = d.kcap;
           int K = d.kcap;
+          // concatenations of at most 48 columns use the faster core kernel
+          const int lim = (d.kcap <= 16) ? 48 : KMAX;
           std::vector<Term> tl;
-          while (q < kv.second.size() && K + kv.second[q].kcap <= KMAX) {
+          while (q < kv.second.size() && (K + kv.second[q].kcap <= lim || tl.empty())) {
             K += kv.second[q].kcap;
             tl.push_back(kv.second[q].t);
             ++q;
           }
-          if (tl.empty()) throw DeviceError("internal: term wider than a rounded addition");
+          if (K > KMAX) throw DeviceError("internal: term wider than a rounded addition");
           T.Kcap = K;
           if (rounds.size() <= rd) rounds.resize(rd + 1);
           rounds[rd].push_back({T, tl});
@@ -611,18 +674,21 @@ struct Builder {
       }
     }
     bjobs.clear();
+    bjob_mat.clear();
     bdprod.clear();
     pending.clear();
     ws.release(mk);
     in_batch = false;
   }
 
-  void copy_node(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag) {
+  void copy_node(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag,
+                 bool skip_compress = false) {
     const BNode& b = S.bn[node];
     Phase ph{PH_COPY, (int)P.copies.size(), 0, 0, 0, 0, 0, 0.0};
     for (int l = b.lbeg; l < b.lend; ++l) {
       const LeafDesc& d = dst->L[l];
       if (d.kind == K_ZERO) continue;
+      if (skip_compress && src && d.kind == K_LR && src->L[l].kind == K_DENSE) continue;
       CopyItem c{};
       c.dense = d.kind == K_DENSE;
       c.m = d.m;
@@ -636,6 +702,8 @@ struct Builder {
         c.A = e.A;
         c.B = e.B;
         c.rank = e.kind == K_LR ? src->rank + l : nullptr;
+        c.expand = (d.kind == K_DENSE && e.kind == K_LR) ? 1 : 0;
+        if (d.kind == K_LR && e.kind != K_LR) throw DeviceError("internal: dense to low-rank copy");
       }
       c.scale = scale;
       c.add_identity = (add_identity_diag && S.lf[l].r == S.lf[l].c) ? 1 : 0;
@@ -729,6 +797,111 @@ struct ApplyPlan {
   }
 };
 
+// Per-step matrix-vector plan of one H-matrix: projection segments, the
+// per-leaf-cluster entry lists and (optionally) FP32 copies of the factors.
+struct MvPlan {
+  DevBuf dsegs, dents, drows, partial, f32pool;
+  MvDev dev{};
+  int64_t matrix_bytes = 0;   // stored bytes read per product
+  int64_t lr_bytes = 0, dense_bytes = 0;
+  int64_t lr_entries = 0, dense_entries = 0;
+
+  void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, bool lr_f32,
+              hipStream_t s) {
+    const double* base = M.pool.as<double>();
+    const float* fbase = nullptr;
+    if (dense_f32 || lr_f32) {
+      f32pool.alloc(std::max<size_t>(M.pool_doubles, 1) * sizeof(float));
+      HL_CHECK(launch_convert_f32(base, f32pool.as<float>(), M.pool_doubles, s));
+      fbase = f32pool.as<float>();
+    }
+    auto fptr = [&](const double* p) -> const void* { return fbase + (p - base); };
+    std::vector<MvSeg> segs;
+    std::vector<int32_t> sbeg(S.lf.size(), 0), nseg(S.lf.size(), 0);
+    for (size_t l = 0; l < S.lf.size(); ++l) {
+      const LeafDesc& d = M.L[l];
+      if (d.kind == K_DENSE) {
+        matrix_bytes += (int64_t)d.m * d.n * (dense_f32 ? 4 : 8);
+        dense_bytes += (int64_t)d.m * d.n * (dense_f32 ? 4 : 8);
+        dense_entries += (int64_t)d.m * d.n;
+      }
+      if (d.kind != K_LR || rk[l] == 0) continue;
+      const int k = rk[l];
+      matrix_bytes += (int64_t)(d.m + d.n) * k * (lr_f32 ? 4 : 8);
+      lr_bytes += (int64_t)(d.m + d.n) * k * (lr_f32 ? 4 : 8);
+      lr_entries += (int64_t)(d.m + d.n) * k;
+      sbeg[l] = (int)segs.size();
+      for (int r0 = 0; r0 < d.n; r0 += MV_SEG) {
+        MvSeg sg{};
+        sg.r0 = r0;
+        sg.r1 = std::min(d.n, r0 + MV_SEG);
+        sg.k = k;
+        sg.ld = d.n;
+        sg.xoff = d.clo;
+        sg.V = lr_f32 ? fptr(d.B) : (const void*)d.B;
+        segs.push_back(sg);
+      }
+      nseg[l] = (int)segs.size() - sbeg[l];
+    }
+    std::vector<MvEntry> ents;
+    std::vector<MvRow> rows;
+    for (size_t q = 0; q < S.leafcl.size(); ++q) {
+      const Cluster& c = S.cl[S.leafcl[q]];
+      MvRow R{c.lo, c.hi, (int)ents.size(), 0};
+      for (int e = S.rowptr[q]; e < S.rowptr[q + 1]; ++e) {
+        const int l = S.rowidx[e];
+        const LeafDesc& d = M.L[l];
+        MvEntry E{};
+        if (d.kind == K_DENSE) {
+          E.kind = 0;
+          E.n = d.n;
+          E.xoff = d.clo;
+          E.ld = d.m;
+          const double* p = d.A + (c.lo - d.rlo);
+          E.ptr = dense_f32 ? fptr(p) : (const void*)p;
+        } else if (d.kind == K_LR && rk[l] > 0) {
+          E.kind = 1;
+          E.k = rk[l];
+          E.sbeg = sbeg[l];
+          E.nseg = nseg[l];
+          E.ld = d.m;
+          const double* p = d.A + (c.lo - d.rlo);
+          E.ptr = lr_f32 ? fptr(p) : (const void*)p;
+        } else {
+          continue;
+        }
+        ents.push_back(E);
+      }
+      R.eend = (int)ents.size();
+      rows.push_back(R);
+    }
+    upload(dsegs, segs, s);
+    upload(dents, ents, s);
+    upload(drows, rows, s);
+    partial.alloc(std::max<size_t>(segs.size(), 1) * MV_KP * sizeof(double));
+    dev = MvDev{dsegs.as<MvSeg>(), dents.as<MvEntry>(), drows.as<MvRow>(), (int)segs.size(), (int)rows.size(),
+                dense_f32 ? 1 : 0, lr_f32 ? 1 : 0};
+  }
+  void run(const double* x, const MvEpi& e, hipStream_t s) const {
+    HL_CHECK(mv_launch(dev, x, partial.as<double>(), e, s));
+  }
+};
+
+static MvEpi epi_plain(double* y) {
+  MvEpi e{};
+  e.kind = MV_EPI_PLAIN;
+  e.y = y;
+  return e;
+}
+
+static std::vector<int32_t> read_ranks(const HMat& M, hipStream_t s) {
+  std::vector<int32_t> rk(M.L.size());
+  if (!rk.empty())
+    HL_CHECK(hipMemcpyAsync(rk.data(), M.rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HL_CHECK(hipStreamSynchronize(s));
+  return rk;
+}
+
 }  // namespace hl
 
 using namespace hl;
@@ -742,7 +915,7 @@ struct hlevy_op {
   HMat G;
   DevBuf cst, ovf;
   DevBuf xbuf, ybuf;   // cluster-order work vectors for hlevy_matvec
-  ApplyPlan mv;
+  MvPlan mv;           // FP64 product with G
 };
 
 struct hlevy_fac {
@@ -751,7 +924,7 @@ struct hlevy_fac {
   int prec = 0;
   HMat LU, Li, Ui;
   DevBuf w_u, w_y, w_b, w_z, w_r, w_d, w_g, partial, scal, zp, ovf;
-  ApplyPlan mvG, mvLi, mvUi;
+  MvPlan mvG, mvLi, mvUi;
   int32_t rank_overflows = 0;
 };
 
@@ -905,7 +1078,7 @@ hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, 
     }
     op->xbuf.alloc((size_t)S.N * sizeof(double));
     op->ybuf.alloc((size_t)S.N * sizeof(double));
-    op->mv.create(S, op->G, op->xbuf.as<double>(), op->ybuf.as<double>(), s);
+    op->mv.create(S, op->G, read_ranks(op->G, s), false, false, s);
     HL_CHECK(hipStreamSynchronize(s));
     *out = op.release();
     return HLEVY_OK;
@@ -961,7 +1134,7 @@ hlevy_status hlevy_matvec(const hlevy_op* op, const double* x, double* y, void* 
     const int N = op->S.N;
     const int32_t* perm = op->ds.perm.as<int32_t>();
     HL_CHECK(launch_perm_gather(op->xbuf.as<double>(), x, perm, N, s));
-    op->mv.run(op->ds.lists, s);
+    op->mv.run(op->xbuf.as<double>(), epi_plain(op->ybuf.as<double>()), s);
     HL_CHECK(launch_perm_scatter(y, op->ybuf.as<double>(), perm, N, s));
     return HLEVY_OK;
   });
@@ -991,11 +1164,14 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
     f->lu_tol = lu_tol;
     const Structure& S = op->S;
     const int kc = op->hp.max_rank;
-    f->LU.create(S, kc, FULL, s);
+    const bool dmax = true;   // leaf-level admissible blocks dense while factoring
+    f->LU.create(S, kc, FULL, s, dmax);
+    HMat Li, Ui, TMP;
+    Li.create(S, kc, LOWER, s, dmax);
+    Ui.create(S, kc, UPPER, s, dmax);
+    TMP.create(S, kc, FULL, s, dmax);
     f->Li.create(S, kc, LOWER, s);
     f->Ui.create(S, kc, UPPER, s);
-    HMat TMP;
-    TMP.create(S, kc, FULL, s);
     f->zp.alloc(sizeof(int32_t));
     f->ovf.alloc(sizeof(int32_t));
     HL_CHECK(hipMemsetAsync(f->zp.p, 0, sizeof(int32_t), s));
@@ -1005,12 +1181,58 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
       WsStack ws;
       Builder B(S, P, ws, op->ds, f->ovf.as<int32_t>(), lu_tol);
       B.copy_node(&f->LU, const_cast<HMat*>(&op->G), 0, -0.5 * dt, true);   // M = I - dt/2 G
-      B.zero_node(&f->Li, 0);
-      B.zero_node(&f->Ui, 0);
-      hluinv(B, &f->LU, &f->Li, &f->Ui, &TMP, 0);
+      B.zero_node(&Li, 0);
+      B.zero_node(&Ui, 0);
+      const double t0 = now_s();
+      hluinv(B, &f->LU, &Li, &Ui, &TMP, 0);
+      // inverse factors in the operator's block format: dense leaf-level
+      // blocks of the workspace are truncated back to low rank
+      for (int side = 0; side < 2; ++side) {
+        HMat& src = side == 0 ? Li : Ui;
+        HMat& dst = side == 0 ? f->Li : f->Ui;
+        B.copy_node(&dst, &src, 0, 1.0, false, /*skip_compress=*/true);
+        std::vector<LFlushTarget> tgs;
+        std::vector<std::vector<Term>> tl;
+        for (size_t l = 0; l < S.lf.size(); ++l) {
+          const LeafDesc& d = dst.L[l];
+          if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
+          LFlushTarget T{};
+          T.U = d.A;
+          T.V = d.B;
+          T.rank = dst.rank + l;
+          T.m = d.m;
+          T.n = d.n;
+          T.kcap = d.kcap;
+          T.Kcap = d.n;   // the target starts empty: the width is the term's
+          Term tm{};
+          tm.dense = 0;
+          tm.ro = 0;
+          tm.mr = d.m;
+          tm.co = 0;
+          tm.nc = d.n;
+          tm.U = src.L[l].A;
+          tm.ldu = d.m;
+          tm.W = op->ds.ident.as<double>();
+          tm.ldw = 64;
+          tm.kfix = d.n;
+          tm.sign = 1.0;
+          tgs.push_back(T);
+          tl.push_back({tm});
+        }
+        B.emit_lflush(tgs, tl, lu_tol);
+      }
+      const double t1 = now_s();
       P.upload_all(s);
-      P.run(op->ds.lists, f->zp.as<int32_t>(), s);
       HL_CHECK(hipStreamSynchronize(s));
+      const double t2 = now_s();
+      P.run(op->ds.lists, f->zp.as<int32_t>(), s);
+      const double t3 = now_s();
+      HL_CHECK(hipStreamSynchronize(s));
+      const double t4 = now_s();
+      if (verbose())
+        std::fprintf(stderr, "[hlevy] factor plan %.3fs (%zu phases, %zu lr targets, ws peak %.1f MB) upload %.3fs "
+                     "enqueue %.3fs device-tail %.3fs\n", t1 - t0, P.ph.size(), P.ltg.size(), ws.peak / 1048576.0,
+                     t2 - t1, t3 - t2, t4 - t3);
     }
     int32_t zp = 0;
     HL_CHECK(hipMemcpy(&zp, f->zp.p, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1020,46 +1242,65 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
     for (DevBuf* b : {&f->w_u, &f->w_y, &f->w_b, &f->w_z, &f->w_r, &f->w_d, &f->w_g}) b->alloc(Nb);
     f->partial.alloc(1024 * sizeof(double));
     f->scal.alloc(8 * sizeof(double));
-    f->mvG.create(S, op->G, f->w_u.as<double>(), f->w_y.as<double>(), s);
-    f->mvLi.create(S, f->Li, f->w_b.as<double>(), f->w_z.as<double>(), s);
-    f->mvUi.create(S, f->Ui, f->w_z.as<double>(), f->w_d.as<double>(), s);
+    {
+      const bool mixed = prec == HLEVY_PREC_MIXED;
+      // residual operator: FP64 near field, FP32 far field on the mixed path;
+      // preconditioner (inverse factors): FP32 on the mixed path
+      f->mvG.create(S, op->G, read_ranks(op->G, s), false, mixed, s);
+      f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s);
+      f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s);
+      f->LU.pool.reset();   // the per-step path needs only G and the inverse factors
+    }
     HL_CHECK(hipStreamSynchronize(s));
     *out = f.release();
     return HLEVY_OK;
   });
 }
 
-// x(cluster order, w_d) = U^{-1} L^{-1} b(cluster order, w_b)
-static void fac_apply_inverse(hlevy_fac* f, hipStream_t s) {
-  f->mvLi.run(f->op->ds.lists, s);
-  f->mvUi.run(f->op->ds.lists, s);
+// y = U^{-1} (L^{-1} x): forward then backward solve through the inverse
+// factors (cluster order); `add` accumulates into y instead (y = u + ...).
+static void fac_apply_inverse(hlevy_fac* f, const double* x, double* y, const double* add_to, hipStream_t s) {
+  f->mvLi.run(x, epi_plain(f->w_z.as<double>()), s);
+  MvEpi e = epi_plain(y);
+  if (add_to) {
+    e.kind = MV_EPI_ADD;
+    e.u = add_to;
+  }
+  f->mvUi.run(f->w_z.as<double>(), e, s);
+}
+
+// Refinement sweeps for M x = b (x in/out, cluster order):
+// x <- x + U^{-1} L^{-1} (b - M x), residual with the operator G.
+static void refine_sweeps(hlevy_fac* f, const double* b, double* x, int sweeps, hipStream_t s) {
+  for (int it = 0; it < sweeps; ++it) {
+    MvEpi r{};
+    r.kind = MV_EPI_RESID;
+    r.hdt = 0.5 * f->dt;
+    r.u = x;
+    r.b = b;
+    r.y = f->w_y.as<double>();
+    f->mvG.run(x, r, s);
+    fac_apply_inverse(f, f->w_y.as<double>(), x, x, s);
+  }
+}
+
+static int default_sweeps(const hlevy_fac* f, const hlevy_refine* refine) {
+  if (refine) return refine->sweeps;
+  return f->prec == HLEVY_PREC_MIXED ? 2 : 0;
 }
 
 hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, const hlevy_refine* refine, void* stream) {
   if (!f || !b || !x) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   if (b == x) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not alias");
+  if (refine && (refine->sweeps < 0 || refine->sweeps > 64)) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
     const int N = f->op->S.N;
     const int32_t* perm = f->op->ds.perm.as<int32_t>();
-    HL_CHECK(launch_perm_gather(f->w_b.as<double>(), b, perm, N, s));
-    fac_apply_inverse(f, s);
-    int sweeps = refine ? refine->sweeps : (f->prec == HLEVY_PREC_MIXED ? 2 : 0);
-    if (sweeps > 0) {
-      // keep b in w_r; x in w_u
-      HL_CHECK(hipMemcpyAsync(f->w_r.p, f->w_b.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      HL_CHECK(hipMemcpyAsync(f->w_u.p, f->w_d.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      for (int it = 0; it < sweeps; ++it) {
-        f->mvG.run(f->op->ds.lists, s);   // w_y = G x
-        HL_CHECK(launch_residual(f->w_b.as<double>(), f->w_r.as<double>(), f->w_u.as<double>(),
-                                 f->w_y.as<double>(), 0.5 * f->dt, N, s));
-        fac_apply_inverse(f, s);          // w_d = P r
-        HL_CHECK(launch_add(f->w_u.as<double>(), f->w_d.as<double>(), N, s));
-      }
-      HL_CHECK(launch_perm_scatter(x, f->w_u.as<double>(), perm, N, s));
-    } else {
-      HL_CHECK(launch_perm_scatter(x, f->w_d.as<double>(), perm, N, s));
-    }
+    HL_CHECK(launch_perm_gather(f->w_r.as<double>(), b, perm, N, s));
+    fac_apply_inverse(f, f->w_r.as<double>(), f->w_d.as<double>(), nullptr, s);
+    refine_sweeps(f, f->w_r.as<double>(), f->w_d.as<double>(), default_sweeps(f, refine), s);
+    HL_CHECK(launch_perm_scatter(x, f->w_d.as<double>(), perm, N, s));
     return HLEVY_OK;
   });
 }
@@ -1069,6 +1310,7 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
   if (!f || !u) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
   if (g && !phi) return fail(HLEVY_ERR_INVALID_ARG, "phi is required with g");
+  if (refine && (refine->sweeps < 0 || refine->sweeps > 64)) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
   if (g)
     for (int64_t i = 0; i <= nsteps; ++i)
       if (!std::isfinite(phi[i])) return fail(HLEVY_ERR_INVALID_ARG, "non-finite phi");
@@ -1077,30 +1319,24 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
     const int N = f->op->S.N;
     const int32_t* perm = f->op->ds.perm.as<int32_t>();
     const double hdt = 0.5 * f->dt;
-    const int sweeps = refine ? refine->sweeps : (f->prec == HLEVY_PREC_MIXED ? 2 : 0);
+    const int sweeps = default_sweeps(f, refine);
     double* uc = f->w_u.as<double>();
+    double* b = f->w_r.as<double>();
     HL_CHECK(launch_perm_gather(uc, u, perm, N, s));
     if (g) HL_CHECK(launch_perm_gather(f->w_g.as<double>(), g, perm, N, s));
     for (int64_t n = 0; n < nsteps; ++n) {
-      const double cg = g ? hdt * (phi[n] + phi[n + 1]) : 0.0;
-      f->mvG.run(f->op->ds.lists, s);   // w_y = G u
-      // b = u + dt/2 G u + dt/2 (f^n + f^{n+1})
-      HL_CHECK(launch_axpy2(f->w_b.as<double>(), uc, hdt, f->w_y.as<double>(), cg,
-                            g ? f->w_g.as<double>() : nullptr, N, s));
-      if (sweeps == 0) {
-        fac_apply_inverse(f, s);            // w_d = U^{-1} L^{-1} b
-        HL_CHECK(hipMemcpyAsync(uc, f->w_d.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      } else {
-        HL_CHECK(hipMemcpyAsync(f->w_r.p, f->w_b.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        fac_apply_inverse(f, s);
-        HL_CHECK(hipMemcpyAsync(uc, f->w_d.p, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        for (int it = 0; it < sweeps; ++it) {
-          f->mvG.run(f->op->ds.lists, s);
-          HL_CHECK(launch_residual(f->w_b.as<double>(), f->w_r.as<double>(), uc, f->w_y.as<double>(), hdt, N, s));
-          fac_apply_inverse(f, s);
-          HL_CHECK(launch_add(uc, f->w_d.as<double>(), N, s));
-        }
-      }
+      // b = (I + dt/2 G) u^n + dt/2 (phi_n + phi_{n+1}) g
+      MvEpi rhs{};
+      rhs.kind = MV_EPI_RHS;
+      rhs.hdt = hdt;
+      rhs.cg = g ? hdt * (phi[n] + phi[n + 1]) : 0.0;
+      rhs.u = uc;
+      rhs.g = g ? f->w_g.as<double>() : nullptr;
+      rhs.y = b;
+      f->mvG.run(uc, rhs, s);
+      // u^{n+1} = U^{-1} L^{-1} b, then refinement sweeps
+      fac_apply_inverse(f, b, uc, nullptr, s);
+      refine_sweeps(f, b, uc, sweeps, s);
     }
     HL_CHECK(launch_perm_scatter(u, uc, perm, N, s));
     if (stats) {
@@ -1109,6 +1345,46 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
       stats->last_rel_residual = -1.0;
       stats->rank_overflows = f->rank_overflows;
     }
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_fac_time_apply(hlevy_fac* f, int32_t which, int32_t reps, void* stream, double out[6]) {
+  if (!f || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (which < 0 || which > 2 || reps < 1 || reps > 100000) return fail(HLEVY_ERR_INVALID_ARG, "bad which/reps");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    const MvPlan& M = which == 0 ? f->mvG : (which == 1 ? f->mvLi : f->mvUi);
+    const double* x = f->w_u.as<double>();
+    double* y = f->w_y.as<double>();
+    hipEvent_t e0, e1, e2;
+    HL_CHECK(hipEventCreate(&e0));
+    HL_CHECK(hipEventCreate(&e1));
+    HL_CHECK(hipEventCreate(&e2));
+    double tp = 0.0, tg = 0.0;
+    MvEpi e = epi_plain(y);
+    for (int r = 0; r < reps; ++r) {
+      HL_CHECK(hipEventRecord(e0, s));
+      HL_CHECK(project_launch(M.dev, x, M.partial.as<double>(), s));
+      HL_CHECK(hipEventRecord(e1, s));
+      HL_CHECK(gather_launch(M.dev, x, M.partial.as<double>(), e, s));
+      HL_CHECK(hipEventRecord(e2, s));
+      HL_CHECK(hipEventSynchronize(e2));
+      float a = 0.f, b = 0.f;
+      HL_CHECK(hipEventElapsedTime(&a, e0, e1));
+      HL_CHECK(hipEventElapsedTime(&b, e1, e2));
+      tp += a;
+      tg += b;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    out[0] = tp / reps;
+    out[1] = tg / reps;
+    out[2] = (double)M.matrix_bytes;
+    out[3] = (double)M.lr_bytes;
+    out[4] = (double)M.dense_bytes;
+    out[5] = (double)f->op->S.N;
     return HLEVY_OK;
   });
 }

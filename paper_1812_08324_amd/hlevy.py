@@ -53,7 +53,8 @@ class OpInfo(C.Structure):
 
 EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
            "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
-           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_op_destroy", "hlevy_fac_destroy"]
+           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_fac_time_apply", "hlevy_op_destroy",
+           "hlevy_fac_destroy"]
 
 
 def _load():
@@ -74,6 +75,7 @@ def _load():
         "hlevy_solve": ([vp, vp, vp, C.POINTER(Refine), vp], st),
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
                         C.POINTER(Stats), vp], st),
+        "hlevy_fac_time_apply": ([vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double)], st),
         "hlevy_op_destroy": ([vp], None),
         "hlevy_fac_destroy": ([vp], None),
     }
@@ -139,6 +141,15 @@ def plan_info(prob: Problem, hp: HParams) -> dict:
     return {k: getattr(out, k) for k, _ in PlanInfo._fields_}
 
 
+def fac_time_apply(fac, which: int, reps: int = 20, stream=None) -> dict:
+    """HIP-event timing of one matrix-vector product of the factor:
+    which = 0 (G), 1 (L^{-1}), 2 (U^{-1})."""
+    out = (C.c_double * 6)()
+    _check(lib.hlevy_fac_time_apply(fac.h, int(which), int(reps), _stream(stream), out), "hlevy_fac_time_apply")
+    keys = ("project_ms", "gather_ms", "matrix_bytes", "lowrank_bytes", "dense_bytes", "N")
+    return dict(zip(keys, list(out)))
+
+
 class Op:
     """Assembled H-matrix of the generator G (handle owner)."""
 
@@ -150,7 +161,7 @@ class Op:
         self.prob, self.hp = prob, hp
 
     def __del__(self):
-        if getattr(self, "h", None) and self.h.value:
+        if getattr(self, "h", None) and self.h.value and lib is not None:
             lib.hlevy_op_destroy(self.h)
             self.h = None
 
@@ -167,7 +178,7 @@ class Fac:
         self.N = op.N
 
     def __del__(self):
-        if getattr(self, "h", None) and self.h.value:
+        if getattr(self, "h", None) and self.h.value and lib is not None:
             lib.hlevy_fac_destroy(self.h)
             self.h = None
 
