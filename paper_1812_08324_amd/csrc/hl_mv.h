@@ -8,20 +8,29 @@
 namespace hl {
 
 constexpr int MV_KP = 32;     // partial stride (>= largest rank)
-constexpr int MV_SEG = 1024;  // rows per projection segment
+constexpr int MV_SMALL = 1024;   // leaves with more rows are split over a whole projection block
 
-// One wavefront: partial[seg][p] = sum_{j in [r0, r1)} V[j + ld p] x[xoff + j], p < k.
+// Projection of one low-rank leaf: t[tb][p] = sum_{j < n} V[j + ld p] x[xoff + j], p < k.
 struct MvSeg {
-  int32_t r0, r1, k, ld, xoff, pad;
+  int32_t n, k, ld, xoff;
+  int32_t tb;       // slot of the leaf's final projection
+  int32_t pad;
   const void* V;
+};
+
+// A projection block (1024 threads = 16 wavefronts): `count` small leaves,
+// one wavefront each, or one large leaf (big = 1) split over the 16
+// wavefronts and reduced in LDS.
+struct MvProjBlock {
+  int32_t first, count, big, pad;
 };
 
 // A leaf seen from one leaf cluster rho: dense block rows of rho (ptr at row
 // rho.lo of the leaf, ld rows, n cols, x offset xoff) or the rows of U for
-// rho (ptr at that row, ld, rank k, projection segments [sbeg, sbeg + nseg)).
+// rho (ptr at that row, ld, rank k, projection slot tb).
 struct MvEntry {
   int32_t kind;   // 0 dense, 1 low rank
-  int32_t n, xoff, k, sbeg, nseg, ld, pad;
+  int32_t n, xoff, k, tb, pad, ld, pad2;
   const void* ptr;
 };
 
@@ -42,9 +51,11 @@ struct MvEpi {
 
 struct MvDev {
   const MvSeg* segs;
+  const MvProjBlock* pblk;
   const MvEntry* ents;
   const MvRow* rows;
-  int32_t nseg, nrows;
+  double* tb;          // projections t_b, MV_KP per low-rank leaf
+  int32_t npblk, nrows;
   int32_t dense_f32, lr_f32;
 };
 

@@ -800,7 +800,7 @@ struct ApplyPlan {
 // Per-step matrix-vector plan of one H-matrix: projection segments, the
 // per-leaf-cluster entry lists and (optionally) FP32 copies of the factors.
 struct MvPlan {
-  DevBuf dsegs, dents, drows, partial, f32pool;
+  DevBuf dsegs, dpblk, dents, drows, partial, tbuf, f32pool;
   MvDev dev{};
   int64_t matrix_bytes = 0;   // stored bytes read per product
   int64_t lr_bytes = 0, dense_bytes = 0;
@@ -817,7 +817,8 @@ struct MvPlan {
     }
     auto fptr = [&](const double* p) -> const void* { return fbase + (p - base); };
     std::vector<MvSeg> segs;
-    std::vector<int32_t> sbeg(S.lf.size(), 0), nseg(S.lf.size(), 0);
+    std::vector<int32_t> sbeg(S.lf.size(), 0);
+    int nlr = 0;
     for (size_t l = 0; l < S.lf.size(); ++l) {
       const LeafDesc& d = M.L[l];
       if (d.kind == K_DENSE) {
@@ -830,18 +831,33 @@ struct MvPlan {
       matrix_bytes += (int64_t)(d.m + d.n) * k * (lr_f32 ? 4 : 8);
       lr_bytes += (int64_t)(d.m + d.n) * k * (lr_f32 ? 4 : 8);
       lr_entries += (int64_t)(d.m + d.n) * k;
-      sbeg[l] = (int)segs.size();
-      for (int r0 = 0; r0 < d.n; r0 += MV_SEG) {
-        MvSeg sg{};
-        sg.r0 = r0;
-        sg.r1 = std::min(d.n, r0 + MV_SEG);
-        sg.k = k;
-        sg.ld = d.n;
-        sg.xoff = d.clo;
-        sg.V = lr_f32 ? fptr(d.B) : (const void*)d.B;
-        segs.push_back(sg);
+      sbeg[l] = nlr++;   // projection slot of the leaf
+      MvSeg sg{};
+      sg.n = d.n;
+      sg.k = k;
+      sg.ld = d.n;
+      sg.xoff = d.clo;
+      sg.tb = sbeg[l];
+      sg.V = lr_f32 ? fptr(d.B) : (const void*)d.B;
+      segs.push_back(sg);
+    }
+    // projection blocks: a large leaf per block, small leaves 16 per block
+    std::vector<MvSeg> ordered;
+    std::vector<MvProjBlock> pb;
+    for (const MvSeg& sg : segs)
+      if (sg.n > MV_SMALL) {
+        pb.push_back(MvProjBlock{(int)ordered.size(), 1, 1, 0});
+        ordered.push_back(sg);
       }
-      nseg[l] = (int)segs.size() - sbeg[l];
+    {
+      std::vector<MvSeg> small;
+      for (const MvSeg& sg : segs)
+        if (sg.n <= MV_SMALL) small.push_back(sg);
+      for (size_t q = 0; q < small.size(); q += 16) {
+        const int cnt = (int)std::min<size_t>(16, small.size() - q);
+        pb.push_back(MvProjBlock{(int)ordered.size(), cnt, 0, 0});
+        for (int c = 0; c < cnt; ++c) ordered.push_back(small[q + c]);
+      }
     }
     std::vector<MvEntry> ents;
     std::vector<MvRow> rows;
@@ -862,8 +878,7 @@ struct MvPlan {
         } else if (d.kind == K_LR && rk[l] > 0) {
           E.kind = 1;
           E.k = rk[l];
-          E.sbeg = sbeg[l];
-          E.nseg = nseg[l];
+          E.tb = sbeg[l];
           E.ld = d.m;
           const double* p = d.A + (c.lo - d.rlo);
           E.ptr = lr_f32 ? fptr(p) : (const void*)p;
@@ -875,12 +890,14 @@ struct MvPlan {
       R.eend = (int)ents.size();
       rows.push_back(R);
     }
-    upload(dsegs, segs, s);
+    upload(dsegs, ordered, s);
+    upload(dpblk, pb, s);
     upload(dents, ents, s);
     upload(drows, rows, s);
-    partial.alloc(std::max<size_t>(segs.size(), 1) * MV_KP * sizeof(double));
-    dev = MvDev{dsegs.as<MvSeg>(), dents.as<MvEntry>(), drows.as<MvRow>(), (int)segs.size(), (int)rows.size(),
-                dense_f32 ? 1 : 0, lr_f32 ? 1 : 0};
+    tbuf.alloc(std::max(nlr, 1) * MV_KP * sizeof(double));
+    partial.alloc(8);
+    dev = MvDev{dsegs.as<MvSeg>(), dpblk.as<MvProjBlock>(), dents.as<MvEntry>(), drows.as<MvRow>(),
+                tbuf.as<double>(), (int)pb.size(), (int)rows.size(), dense_f32 ? 1 : 0, lr_f32 ? 1 : 0};
   }
   void run(const double* x, const MvEpi& e, hipStream_t s) const {
     HL_CHECK(mv_launch(dev, x, partial.as<double>(), e, s));

@@ -122,3 +122,38 @@ def test_config1_cn_trajectory(H):
     ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0, g=w.g, phi=w.phi).u
     err = np.linalg.norm(host(u) - ref) / np.linalg.norm(ref)
     assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("name", ["frac1d_s0.5_n1024", "tempered1d_n2000", "frac2d_s0.75_33x33"])
+def test_mixed_solve_with_refinement(H, name):
+    """FP32 inverse factors at a loose truncation, FP64 residual refinement:
+    two sweeps bring the solve to FP64 accuracy."""
+    w = SMALL[name]()
+    op = H.assemble(lib_problem(H, w), lib_hparams(H, w))
+    fac = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    G = generator_dense(oracle_problem(w))
+    M = np.eye(w.N) - 0.5 * w.dt * G
+    rng = np.random.Generator(np.random.PCG64(13))
+    xt = rng.standard_normal(w.N)
+    b = M @ xt
+    x = torch.empty(w.N, dtype=torch.float64, device="cuda")
+    errs = []
+    for sweeps in (0, 1, 3):
+        H.solve(fac, dev(b), x, refine={"sweeps": sweeps})
+        errs.append(np.linalg.norm(host(x) - xt) / np.linalg.norm(xt))
+    assert errs[0] < 1e-4, errs
+    assert errs[2] < 1e-10, errs
+    # refinement converges to the accuracy floor of the H-approximated operator
+    assert errs[1] < errs[0] and errs[2] <= 1.01 * errs[1], errs
+
+
+def test_config1_mixed_trajectory(H):
+    """Mixed path on the N = 1024 workload: rel-L2 <= 1e-8 after refinement."""
+    w = W.config1()
+    op = H.assemble(lib_problem(H, w), lib_hparams(H, w))
+    fac = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    u = dev(w.u0)
+    H.step(fac, u, w.steps, g=dev(w.g), phi=list(w.phi), refine={"sweeps": 2})
+    ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0, g=w.g, phi=w.phi).u
+    err = np.linalg.norm(host(u) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, err
