@@ -146,8 +146,8 @@ def main():
     s3 = time.perf_counter()
     steady_mixed = w.steps / (s3 - s2)
 
-    # per-kernel HIP-event timing of the per-step products (live, same build)
-    kt = {name: H.fac_time_apply(fac, which, reps=20) for which, name in enumerate(("G", "Linv", "Uinv"))}
+    # per-kernel HIP-event timing of the per-step products, in stepping order
+    kt = H.fac_kernel_times(fac, reps=20)
 
     extra = {}
     if not args.no_fp64:
@@ -169,17 +169,31 @@ def main():
         }
         del fac64, op64
 
-    # roofline of the dominant per-step kernel: the gather of the operator
-    # product (algorithmic bytes: the stored leaves it reads + vectors)
-    kg = kt["G"]
-    N = kg["N"]
-    # dense leaves, the U half of the low-rank leaves, x read once, y written once
-    gather_bytes = kg["dense_bytes"] + kg["lowrank_bytes"] / 2.0 + 8.0 * N * 2
-    achieved = gather_bytes / (kg["gather_ms"] * 1e-3) / 1e9
+    # roofline of the dominant per-step kernel (largest share of a step's
+    # kernel time; a mixed step with one sweep runs each product twice).
+    # Algorithmic bytes: the stored data the kernel reads once + vectors.
+    N = kt["N"]
+    kernels = {}
+    for name in ("G", "Linv", "Uinv"):
+        k = kt[name]
+        kernels[f"gather[{name}]"] = (k["gather_ms"], k["dense_bytes"] + k["u_bytes"] + 16.0 * N)
+        kernels[f"project[{name}]"] = (k["project_ms"], k["v_bytes"] + 8.0 * N + k["partial_bytes"])
+    dom = max(kernels, key=lambda n: kernels[n][0])
+    ms, nbytes = kernels[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    prec_tag = {"G": "FP64 dense + FP32 low rank", "Linv": "FP32", "Uinv": "FP32"}
+    mat = dom[dom.index("[") + 1:-1]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_mv_gather<double,float> (operator product, mixed path)",
-                "bytes_per_launch": gather_bytes, "avg_launch_ms": kg["gather_ms"]}
+                "kernel": ("k_mv_gather" if dom.startswith("gather") else "k_mv_project")
+                + f" ({mat} product, {prec_tag[mat]})",
+                "bytes_per_launch": nbytes, "avg_launch_ms": ms}
+    # whole H-matvec of the operator (both kernels)
+    g = kt["G"]
+    mv_bytes = g["dense_bytes"] + g["u_bytes"] + g["v_bytes"] + 24.0 * N
+    mv_ms = g["project_ms"] + g["gather_ms"]
+    matvec = {"operator": "G (FP64 dense + FP32 low rank)", "bytes": mv_bytes, "ms": mv_ms,
+              "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9, "frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     line = {
         "metric": "CN steps/s at N=65536 (mixed-precision H-solve, whole job)",
@@ -200,9 +214,11 @@ def main():
                    "max_rank": args.max_rank},
         "phases_s": {"assemble": s1 - s0, "factor_mixed": s2 - s1, "steps_mixed": s3 - s2},
         "steady_cn_steps_per_s_mixed": steady_mixed,
-        "kernel_ms": {k: {"project": v["project_ms"], "gather": v["gather_ms"],
-                          "matrix_MB": v["matrix_bytes"] / 1e6} for k, v in kt.items()},
+        "kernel_ms": {k: {"project": kt[k]["project_ms"], "gather": kt[k]["gather_ms"],
+                          "matrix_MB": (kt[k]["dense_bytes"] + kt[k]["u_bytes"] + kt[k]["v_bytes"]) / 1e6}
+                      for k in ("G", "Linv", "Uinv")},
         "roofline": roofline,
+        "matvec_G": matvec,
     }
     line.update(extra)
     if not args.no_cpu_baseline:

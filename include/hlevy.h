@@ -178,14 +178,26 @@ hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double*
                         const double* phi, const hlevy_refine* refine,
                         hlevy_stats* stats, void* stream);
 
-/* Per-step kernel timing of the factor's matrix-vector products (for
- * roofline reporting): runs `reps` products with the matrix `which`
- * (0 = G, 1 = L^{-1}, 2 = U^{-1}) on internal vectors, timing the
- * projection and gather kernels separately with HIP events on `stream`.
- * out[0] = mean projection kernel ms, out[1] = mean gather kernel ms,
- * out[2] = stored matrix bytes read per product, out[3] = low-rank leaf
- * bytes (U and V), out[4] = dense leaf bytes, out[5] = N.  Synchronises. */
-hlevy_status hlevy_fac_time_apply(hlevy_fac* fac, int32_t which, int32_t reps, void* stream, double out[6]);
+/* Kernel timing of the per-step matrix-vector products (roofline
+ * reporting).  Runs `reps` rounds of the three products of a Crank-Nicolson
+ * step in stepping order -- G, L^{-1}, U^{-1} -- on internal vectors, each
+ * product's two kernels (projection t = V^T x of the low-rank leaves, then
+ * the gather y = D x + U t per leaf cluster) bracketed by HIP events on
+ * `stream`.  Index w of each array: 0 = G, 1 = L^{-1}, 2 = U^{-1}.
+ * Synchronises `stream`; errors: HLEVY_ERR_INVALID_ARG for reps outside
+ * [1, 100000]. */
+typedef struct {
+  int64_t N;
+  int32_t reps, pad;
+  double project_ms[3];     /* mean projection kernel time */
+  double gather_ms[3];      /* mean gather kernel time */
+  double dense_bytes[3];    /* stored dense-leaf bytes (read by the gather) */
+  double u_bytes[3];        /* low-rank U factor bytes (read by the gather) */
+  double v_bytes[3];        /* low-rank V factor bytes (read by the projection) */
+  double partial_bytes[3];  /* projection partials (written, then read by the gather) */
+} hlevy_kernel_times;
+
+hlevy_status hlevy_fac_kernel_times(hlevy_fac* fac, int32_t reps, void* stream, hlevy_kernel_times* out);
 
 void hlevy_op_destroy(hlevy_op* op);
 void hlevy_fac_destroy(hlevy_fac* fac);

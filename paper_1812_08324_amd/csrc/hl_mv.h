@@ -7,30 +7,27 @@
 
 namespace hl {
 
-constexpr int MV_KP = 32;     // partial stride (>= largest rank)
-constexpr int MV_SMALL = 1024;   // leaves with more rows are split over a whole projection block
+constexpr int MV_PMAX = 16;   // at most this many projection tiles (partials) per low-rank leaf
+constexpr int MV_EMAX = 128;  // entries staged in LDS per gather round
 
-// Projection of one low-rank leaf: t[tb][p] = sum_{j < n} V[j + ld p] x[xoff + j], p < k.
-struct MvSeg {
+// One wavefront of the projection: rows [r0, r0 + n) of the V factor of a
+// low-rank leaf, V column-major with leading dimension ld and rank k.  The
+// wavefront writes the k partial sums sum_j V[j, p] x[xoff + j] to slot
+// `slot` of the partial buffer (stride kb doubles per slot).
+struct MvTile {
   int32_t n, k, ld, xoff;
-  int32_t tb;       // slot of the leaf's final projection
-  int32_t pad;
-  const void* V;
+  int32_t slot, pad;
+  const void* V;   // first row of the tile
 };
 
-// A projection block (1024 threads = 16 wavefronts): `count` small leaves,
-// one wavefront each, or one large leaf (big = 1) split over the 16
-// wavefronts and reduced in LDS.
-struct MvProjBlock {
-  int32_t first, count, big, pad;
-};
-
-// A leaf seen from one leaf cluster rho: dense block rows of rho (ptr at row
-// rho.lo of the leaf, ld rows, n cols, x offset xoff) or the rows of U for
-// rho (ptr at that row, ld, rank k, projection slot tb).
+// A leaf seen from one leaf cluster rho.  Dense: block rows of rho (ptr at
+// row rho.lo of the leaf, leading dimension ld, n columns, x offset xoff).
+// Low rank: rows of U for rho (ptr at that row, ld, rank k); its projection
+// t = V^T x is the sum of np partials starting at slot `slot`.
 struct MvEntry {
   int32_t kind;   // 0 dense, 1 low rank
-  int32_t n, xoff, k, tb, pad, ld, pad2;
+  int32_t n;      // dense: columns; low rank: number of partials
+  int32_t xoff, k, slot, pad, ld, pad2;
   const void* ptr;
 };
 
@@ -43,26 +40,28 @@ enum { MV_EPI_PLAIN = 0, MV_EPI_RHS = 1, MV_EPI_RESID = 2, MV_EPI_ADD = 3 };
 struct MvEpi {
   int32_t kind, pad;
   double hdt, cg;
-  const double* u;   // RHS: u;  RESID: x
+  const double* u;   // RHS: u;  RESID: x;  ADD: u
   const double* g;   // RHS forcing profile or nullptr
   const double* b;   // RESID: b
   double* y;
 };
 
 struct MvDev {
-  const MvSeg* segs;
-  const MvProjBlock* pblk;
+  const MvTile* tiles;
   const MvEntry* ents;
   const MvRow* rows;
-  double* tb;          // projections t_b, MV_KP per low-rank leaf
-  int32_t npblk, nrows;
+  double* part;        // projection partials, kb doubles per slot
+  int32_t ntiles, nrows;
+  int32_t kb;          // rank bucket of the matrix: 8, 16 or 32 (>= every leaf rank)
   int32_t dense_f32, lr_f32;
 };
 
-hipError_t mv_launch(const MvDev& M, const double* x, double* partial, const MvEpi& epi, hipStream_t s);
+hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
 // the two kernels of mv_launch separately (timing)
-hipError_t project_launch(const MvDev& M, const double* x, double* partial, hipStream_t s);
-hipError_t gather_launch(const MvDev& M, const double* x, const double* partial, const MvEpi& epi, hipStream_t s);
+hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s);
+hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
+// rows of V one projection wavefront covers per pass (64 lanes x rows per lane)
+int project_rows_per_pass(int kb, bool lr_f32);
 hipError_t launch_convert_f32(const double* in, float* out, size_t n, hipStream_t s);
 
 }  // namespace hl

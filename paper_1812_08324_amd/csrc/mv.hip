@@ -2,155 +2,196 @@
 // leaves as U (V^T x)), the HBM-bound hot loop of every Crank-Nicolson step.
 //
 // Two launches, no atomics, fixed summation order:
-//  1. k_mv_project (blocks of 16 wavefronts): t_b = V_b^T x for every
-//     low-rank leaf b.  A small leaf (<= MV_SMALL rows) is one wavefront;
-//     a large one is split over the 16 wavefronts of a block and reduced in
-//     LDS.  Lanes run along the rows (coalesced); a lane issues the loads of
-//     8 columns and two rows before accumulating.
+//  1. k_mv_project: every wavefront owns one tile (a row range of one V
+//     factor; a leaf has at most MV_PMAX tiles).  Lanes run along the rows
+//     (coalesced), each lane issues the loads of RPL rows x all k columns
+//     before accumulating, and a transposed butterfly reduces the k column
+//     sums across the 64 lanes with k + log steps instead of 6 k.  The k
+//     partial sums of the tile go to its slot of the partial buffer.
 //  2. k_mv_gather: one workgroup per leaf cluster rho (owner computes):
-//     y_rho = sum_dense D x + sum_lowrank U[rho, :] t_b; the row's entry list
-//     is staged in LDS, the four wavefronts take entries round-robin, then
-//     reduce in LDS and apply the Crank-Nicolson epilogue.
+//     y_rho = sum_dense D x + sum_lowrank U[rho, :] t_b.  The entry list is
+//     staged in LDS, t_b = sum of the leaf's partials is formed in LDS in a
+//     fixed order, the wavefronts take entries round-robin (the host sorts
+//     each list by bytes), then reduce in LDS and apply the Crank-Nicolson
+//     epilogue.
 #include <hip/hip_runtime.h>
 
 #include "hl_mv.h"
 
 namespace hl {
 
-__device__ __forceinline__ double mv_warp_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// ---------------------------------------------------------------------------
+// transposed butterfly: a[0..W) per lane -> lane holds, in a[0], the sum over
+// all 64 lanes of column (lane / (64 / W)) of the original arrays.
+// ---------------------------------------------------------------------------
+template <int W, int O>
+struct ColReduce {
+  static __device__ __forceinline__ void run(double* a, int lane) {
+    constexpr int H = W / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? a[i] : a[i + H];
+      const double keep = up ? a[i + H] : a[i];
+      a[i] = keep + __shfl_xor(send, O, 64);
+    }
+    ColReduce<H, O / 2>::run(a, lane);
+  }
+};
+template <int O>
+struct ColReduce<1, O> {
+  static __device__ __forceinline__ void run(double* a, int lane) {
+    a[0] += __shfl_xor(a[0], O, 64);
+    ColReduce<1, O / 2>::run(a, lane);
+  }
+};
+template <>
+struct ColReduce<1, 0> {
+  static __device__ __forceinline__ void run(double*, int) {}
+};
+
+// value of `v` in lane l (l uniform across the wavefront)
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// sum_{j in [r0, r1)} V[j, cg + q] x[j] for q < 8, this lane's share (rows lane + 64 i)
-template <typename TL>
-__device__ __forceinline__ void proj_part(const TL* V, int ld, const double* xs, int r0, int r1, int k, int cg,
-                                          int lane, double acc[8]) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  int j = r0 + lane;
-  for (; j + 64 < r1; j += 128) {
-    const double x0 = xs[j], x1 = xs[j + 64];
-    double v0[8], v1[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      v0[q] = cg + q < k ? (double)V[j + (size_t)ld * (cg + q)] : 0.0;
-      v1[q] = cg + q < k ? (double)V[j + 64 + (size_t)ld * (cg + q)] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] += v0[q] * x0 + v1[q] * x1;
-  }
-  if (j < r1) {
-    const double x0 = xs[j];
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (cg + q < k) acc[q] += (double)V[j + (size_t)ld * (cg + q)] * x0;
-  }
+// wavefront-uniform copies (scalar registers) of values the compiler cannot
+// prove uniform
+__device__ __forceinline__ int wuni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Leaf data lives in device global memory: addressing it through the global
+// address space lets the loads take a scalar base plus a 32-bit lane offset.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> wuni_ptr(const void* p) {
+  const unsigned long long b = (unsigned long long)p;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
 }
 
-template <typename TL>
-__global__ void __launch_bounds__(1024) k_mv_project(const MvSeg* segs, const MvProjBlock* pblk, const double* x,
-                                                     double* tb) {
-  __shared__ double red[16][MV_KP];
-  const MvProjBlock B = pblk[blockIdx.x];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (!B.big) {
-    if (w >= B.count) return;
-    const MvSeg S = segs[B.first + w];
-    const TL* V = reinterpret_cast<const TL*>(S.V);
-    for (int cg = 0; cg < S.k; cg += 8) {
-      double acc[8];
-      proj_part<TL>(V, S.ld, x + S.xoff, 0, S.n, S.k, cg, lane, acc);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (cg + q < S.k) {
-          const double s = mv_warp_sum(acc[q]);
-          if (lane == 0) tb[(size_t)S.tb * MV_KP + cg + q] = s;
-        }
-      }
-    }
-    return;
-  }
-  const MvSeg S = segs[B.first];
-  const TL* V = reinterpret_cast<const TL*>(S.V);
-  const int chunk = (((S.n + 15) / 16) + 63) & ~63;   // rows per wavefront, multiple of 64
-  const int r0 = min(S.n, w * chunk), r1 = min(S.n, r0 + chunk);
-  for (int cg = 0; cg < S.k; cg += 8) {
-    double acc[8];
-    proj_part<TL>(V, S.ld, x + S.xoff, r0, r1, S.k, cg, lane, acc);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double s = mv_warp_sum(acc[q]);
-      if (lane == 0 && cg + q < MV_KP) red[w][cg + q] = s;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < S.k) {
-    double s = 0.0;
-    for (int g = 0; g < 16; ++g) s += red[g][threadIdx.x];
-    tb[(size_t)S.tb * MV_KP + threadIdx.x] = s;
-  }
+template <typename TL, int KB>
+constexpr int rows_per_lane() {
+  // 64 VGPRs of loads in flight per lane
+  return (sizeof(TL) == 4 ? 64 : 32) / KB;
 }
 
-template <typename TD, typename TL>
-__global__ void __launch_bounds__(256) k_mv_gather(const MvRow* rows, const MvEntry* ents, const double* x,
-                                                   const double* tb, MvEpi epi) {
-  constexpr int EMAX = 128;
-  __shared__ double red[4][64];
-  __shared__ MvEntry se[EMAX];
+template <typename TL, int KB>
+__global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ tiles, int ntiles,
+                                                    const double* __restrict__ x, double* __restrict__ part) {
+  constexpr int RPL = rows_per_lane<TL, KB>();
+  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= ntiles) return;   // the whole wavefront leaves; no block barrier below
+  const int lane = threadIdx.x & 63;
+  const MvTile T = tiles[wid];
+  const gptr<TL> V = wuni_ptr<TL>(T.V);
+  const double* __restrict__ xs = x + T.xoff;
+  double acc[KB];
+#pragma unroll
+  for (int q = 0; q < KB; ++q) acc[q] = 0.0;
+  for (int r = 0; r < T.n; r += 64 * RPL) {
+    TL v[RPL][KB];
+    double xv[RPL];
+    // Every load is unconditional, so all of them are in flight before the
+    // first use: rows past the tile read row 0 (x weight 0) and columns past
+    // the rank re-read column k-1 (their sums land in columns >= k, which
+    // are never stored).
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int j = r + u * 64 + lane;
+      const bool ok = j < T.n;
+      const int jj = ok ? j : 0;
+      const double xr = xs[jj];
+      xv[u] = ok ? xr : 0.0;
+#pragma unroll
+      for (int q = 0; q < KB; ++q) v[u][q] = V[(unsigned)(jj + T.ld * min(q, T.k - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+#pragma unroll
+      for (int q = 0; q < KB; ++q) acc[q] += (double)v[u][q] * xv[u];
+  }
+  ColReduce<KB, 32>::run(acc, lane);
+  constexpr int G = 64 / KB;
+  const int col = lane / G;
+  if (lane % G == 0 && col < T.k) part[(size_t)T.slot * KB + col] = acc[0];
+}
+
+constexpr int MV_GW = 8;   // wavefronts per gather workgroup
+
+template <typename TD, typename TL, int KB>
+__global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restrict__ rows,
+                                                          const MvEntry* __restrict__ ents,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ part, MvEpi epi) {
+  __shared__ double red[MV_GW][64];
+  __shared__ MvEntry se[MV_EMAX];
+  __shared__ double ts[MV_EMAX * KB];
   const MvRow R = rows[blockIdx.x];
-  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = threadIdx.x & 63, g = wuni(threadIdx.x >> 6);
   const int mr = R.hi - R.lo;
   const int ii = i < mr ? i : mr - 1;   // clamped row: loads stay in bounds, result discarded
   double acc = 0.0;
-  for (int base = R.ebeg; base < R.eend; base += EMAX) {
-    const int cnt = min(EMAX, R.eend - base);
+  for (int base = R.ebeg; base < R.eend; base += MV_EMAX) {
+    const int cnt = min(MV_EMAX, R.eend - base);
     __syncthreads();
     {
       // stage the entry list (8-byte words) in LDS
       const long long* src = reinterpret_cast<const long long*>(ents + base);
       long long* dst = reinterpret_cast<long long*>(se);
       const int words = cnt * (int)(sizeof(MvEntry) / 8);
-      for (int e = threadIdx.x; e < words; e += 256) dst[e] = src[e];
+      for (int e = threadIdx.x; e < words; e += 64 * MV_GW) dst[e] = src[e];
     }
     __syncthreads();
-    for (int e = g; e < cnt; e += 4) {
-      const MvEntry E = se[e];
-      if (E.kind == 0) {
-        const TD* D = reinterpret_cast<const TD*>(E.ptr) + ii;
-        const double* xs = x + E.xoff;
+    // t_b of the low-rank entries: sum of the leaf's partials, in slot order
+    for (int it = threadIdx.x; it < cnt * KB; it += 64 * MV_GW) {
+      const int e = it / KB, q = it % KB;
+      const MvEntry& E = se[e];
+      double s = 0.0;   // zero past the rank: the products below multiply by it
+      if (E.kind == 1 && q < E.k) {
+        const double* p = part + (size_t)E.slot * KB + q;
+        for (int c = 0; c < E.n; ++c) s += p[(size_t)c * KB];
+      }
+      ts[it] = s;
+    }
+    __syncthreads();
+    for (int e = g; e < cnt; e += MV_GW) {
+      const int kind = wuni(se[e].kind), en = wuni(se[e].n), ek = wuni(se[e].k), ld = wuni(se[e].ld);
+      if (kind == 0) {
+        const gptr<TD> D = wuni_ptr<TD>(se[e].ptr);
+        const double xl = i < en ? x[wuni(se[e].xoff) + i] : 0.0;
         int j = 0;
-        for (; j + 16 <= E.n; j += 16) {
-          double dv[16], xv[16];
+        for (; j + 16 <= en; j += 16) {
+          double dv[16];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            dv[q] = (double)D[(size_t)E.ld * (j + q)];
-            xv[q] = xs[j + q];
-          }
+          for (int q = 0; q < 16; ++q) dv[q] = (double)D[(unsigned)(ii + ld * (j + q))];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) acc += dv[q] * xv[q];
+          for (int q = 0; q < 16; ++q) acc += dv[q] * bcast_lane(xl, j + q);
         }
-        for (; j < E.n; ++j) acc += (double)D[(size_t)E.ld * j] * xs[j];
+        for (; j < en; ++j) acc += (double)D[(unsigned)(ii + ld * j)] * bcast_lane(xl, j);
       } else {
-        const TL* U = reinterpret_cast<const TL*>(E.ptr) + ii;
-        const double* t = tb + (size_t)E.tb * MV_KP;
-        for (int p = 0; p < E.k; p += 8) {
-          double uv[8], tv[8];
+        const gptr<TL> U = wuni_ptr<TL>(se[e].ptr);
+        const double* t = ts + e * KB;
+        double uv[KB];
+        // unconditional loads (columns past the rank re-read column k-1 and
+        // meet t = 0), so all of them are in flight together
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            uv[q] = p + q < E.k ? (double)U[(size_t)E.ld * (p + q)] : 0.0;
-            tv[q] = p + q < E.k ? t[p + q] : 0.0;
-          }
+        for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) acc += uv[q] * tv[q];
-        }
+        for (int q = 0; q < KB; ++q) acc += uv[q] * t[q];
       }
     }
   }
   red[g][i] = acc;
   __syncthreads();
   if (g == 0 && i < mr) {
-    const double v = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < MV_GW; w += 2) v += red[w][i] + red[w + 1][i];
     const int r = R.lo + i;
     double out;
     switch (epi.kind) {
@@ -170,43 +211,71 @@ __global__ void __launch_bounds__(256) k_mv_gather(const MvRow* rows, const MvEn
   }
 }
 
+int project_rows_per_pass(int kb, bool lr_f32) {
+  const int vals = lr_f32 ? 64 : 32;
+  return 64 * (vals / kb);
+}
+
+template <typename TL, int KB>
+static void project_t(const MvDev& M, const double* x, hipStream_t s) {
+  if (M.ntiles > 0)
+    hipLaunchKernelGGL((k_mv_project<TL, KB>), dim3((M.ntiles + 3) / 4), dim3(256), 0, s, M.tiles, M.ntiles, x,
+                       M.part);
+}
+
+template <typename TD, typename TL, int KB>
+static void gather_t(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
+  if (M.nrows > 0)
+    hipLaunchKernelGGL((k_mv_gather<TD, TL, KB>), dim3(M.nrows), dim3(64 * MV_GW), 0, s, M.rows, M.ents, x,
+                       M.part, epi);
+}
+
+template <typename TL>
+static void project_kb(const MvDev& M, const double* x, hipStream_t s) {
+  if (M.kb <= 8)
+    project_t<TL, 8>(M, x, s);
+  else if (M.kb <= 16)
+    project_t<TL, 16>(M, x, s);
+  else
+    project_t<TL, 32>(M, x, s);
+}
+
 template <typename TD, typename TL>
-hipError_t mv_launch_t(const MvDev& M, const double* x, double* tb, const MvEpi& epi, hipStream_t s) {
-  if (M.npblk > 0)
-    hipLaunchKernelGGL(k_mv_project<TL>, dim3(M.npblk), dim3(1024), 0, s, M.segs, M.pblk, x, M.tb);
-  hipLaunchKernelGGL((k_mv_gather<TD, TL>), dim3(M.nrows), dim3(256), 0, s, M.rows, M.ents, x, M.tb, epi);
-  return hipGetLastError();
+static void gather_kb(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
+  if (M.kb <= 8)
+    gather_t<TD, TL, 8>(M, x, epi, s);
+  else if (M.kb <= 16)
+    gather_t<TD, TL, 16>(M, x, epi, s);
+  else
+    gather_t<TD, TL, 32>(M, x, epi, s);
 }
 
-hipError_t mv_launch(const MvDev& M, const double* x, double* partial, const MvEpi& epi, hipStream_t s) {
-  if (M.dense_f32) {
-    if (M.lr_f32) return mv_launch_t<float, float>(M, x, partial, epi, s);
-    return mv_launch_t<float, double>(M, x, partial, epi, s);
-  }
-  if (M.lr_f32) return mv_launch_t<double, float>(M, x, partial, epi, s);
-  return mv_launch_t<double, double>(M, x, partial, epi, s);
-}
-
-hipError_t project_launch(const MvDev& M, const double* x, double* tb, hipStream_t s) {
-  (void)tb;
-  if (M.npblk == 0) return hipSuccess;
+hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s) {
+  if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
   if (M.lr_f32)
-    hipLaunchKernelGGL(k_mv_project<float>, dim3(M.npblk), dim3(1024), 0, s, M.segs, M.pblk, x, M.tb);
+    project_kb<float>(M, x, s);
   else
-    hipLaunchKernelGGL(k_mv_project<double>, dim3(M.npblk), dim3(1024), 0, s, M.segs, M.pblk, x, M.tb);
+    project_kb<double>(M, x, s);
   return hipGetLastError();
 }
 
-hipError_t gather_launch(const MvDev& M, const double* x, const double* partial, const MvEpi& epi, hipStream_t s) {
+hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
+  if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
   if (M.dense_f32 && M.lr_f32)
-    hipLaunchKernelGGL((k_mv_gather<float, float>), dim3(M.nrows), dim3(256), 0, s, M.rows, M.ents, x, M.tb, epi);
+    gather_kb<float, float>(M, x, epi, s);
   else if (M.dense_f32)
-    hipLaunchKernelGGL((k_mv_gather<float, double>), dim3(M.nrows), dim3(256), 0, s, M.rows, M.ents, x, M.tb, epi);
+    gather_kb<float, double>(M, x, epi, s);
   else if (M.lr_f32)
-    hipLaunchKernelGGL((k_mv_gather<double, float>), dim3(M.nrows), dim3(256), 0, s, M.rows, M.ents, x, M.tb, epi);
+    gather_kb<double, float>(M, x, epi, s);
   else
-    hipLaunchKernelGGL((k_mv_gather<double, double>), dim3(M.nrows), dim3(256), 0, s, M.rows, M.ents, x, M.tb, epi);
+    gather_kb<double, double>(M, x, epi, s);
   return hipGetLastError();
+}
+
+hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
+  hipError_t e = project_launch(M, x, s);
+  if (e != hipSuccess) return e;
+  return gather_launch(M, x, epi, s);
 }
 
 __global__ void k_convert_f32(const double* in, float* out, size_t n) {

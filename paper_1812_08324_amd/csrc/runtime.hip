@@ -797,14 +797,16 @@ struct ApplyPlan {
   }
 };
 
-// Per-step matrix-vector plan of one H-matrix: projection segments, the
+// Per-step matrix-vector plan of one H-matrix: projection tiles, the
 // per-leaf-cluster entry lists and (optionally) FP32 copies of the factors.
 struct MvPlan {
-  DevBuf dsegs, dpblk, dents, drows, partial, tbuf, f32pool;
+  DevBuf dtiles, dents, drows, dpart, f32pool;
   MvDev dev{};
   int64_t matrix_bytes = 0;   // stored bytes read per product
   int64_t lr_bytes = 0, dense_bytes = 0;
+  int64_t u_bytes = 0, v_bytes = 0;   // low-rank factors read by the gather / the projection
   int64_t lr_entries = 0, dense_entries = 0;
+  int64_t nslots = 0;
 
   void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, bool lr_f32,
               hipStream_t s) {
@@ -816,58 +818,63 @@ struct MvPlan {
       fbase = f32pool.as<float>();
     }
     auto fptr = [&](const double* p) -> const void* { return fbase + (p - base); };
-    std::vector<MvSeg> segs;
-    std::vector<int32_t> sbeg(S.lf.size(), 0);
-    int nlr = 0;
+    const size_t lr_elt = lr_f32 ? sizeof(float) : sizeof(double);
+    const size_t d_elt = dense_f32 ? sizeof(float) : sizeof(double);
+    int kmax = 0;
+    for (size_t l = 0; l < S.lf.size(); ++l)
+      if (M.L[l].kind == K_LR) kmax = std::max(kmax, rk[l]);
+    if (kmax > 32) throw std::runtime_error("internal: rank above 32 in a product plan");
+    const int kb = kmax <= 8 ? 8 : (kmax <= 16 ? 16 : 32);
+    const int rpp = project_rows_per_pass(kb, lr_f32);
+    // projection tiles: a leaf's V rows split into at most MV_PMAX tiles of
+    // whole passes; partial slots of one leaf are consecutive
+    std::vector<MvTile> tiles;
+    std::vector<int32_t> slot0(S.lf.size(), 0), np(S.lf.size(), 0);
     for (size_t l = 0; l < S.lf.size(); ++l) {
       const LeafDesc& d = M.L[l];
       if (d.kind == K_DENSE) {
-        matrix_bytes += (int64_t)d.m * d.n * (dense_f32 ? 4 : 8);
-        dense_bytes += (int64_t)d.m * d.n * (dense_f32 ? 4 : 8);
+        dense_bytes += (int64_t)d.m * d.n * d_elt;
         dense_entries += (int64_t)d.m * d.n;
       }
       if (d.kind != K_LR || rk[l] == 0) continue;
       const int k = rk[l];
-      matrix_bytes += (int64_t)(d.m + d.n) * k * (lr_f32 ? 4 : 8);
-      lr_bytes += (int64_t)(d.m + d.n) * k * (lr_f32 ? 4 : 8);
+      lr_bytes += (int64_t)(d.m + d.n) * k * lr_elt;
+      u_bytes += (int64_t)d.m * k * lr_elt;
+      v_bytes += (int64_t)d.n * k * lr_elt;
       lr_entries += (int64_t)(d.m + d.n) * k;
-      sbeg[l] = nlr++;   // projection slot of the leaf
-      MvSeg sg{};
-      sg.n = d.n;
-      sg.k = k;
-      sg.ld = d.n;
-      sg.xoff = d.clo;
-      sg.tb = sbeg[l];
-      sg.V = lr_f32 ? fptr(d.B) : (const void*)d.B;
-      segs.push_back(sg);
-    }
-    // projection blocks: a large leaf per block, small leaves 16 per block
-    std::vector<MvSeg> ordered;
-    std::vector<MvProjBlock> pb;
-    for (const MvSeg& sg : segs)
-      if (sg.n > MV_SMALL) {
-        pb.push_back(MvProjBlock{(int)ordered.size(), 1, 1, 0});
-        ordered.push_back(sg);
+      const int npass = (d.n + rpp - 1) / rpp;
+      const int per = (npass + MV_PMAX - 1) / MV_PMAX;   // passes per tile
+      const int P = (npass + per - 1) / per;
+      slot0[l] = (int32_t)nslots;
+      np[l] = P;
+      for (int t = 0; t < P; ++t) {
+        const int r0 = t * per * rpp, r1 = std::min(d.n, r0 + per * rpp);
+        MvTile T{};
+        T.n = r1 - r0;
+        T.k = k;
+        T.ld = d.n;
+        T.xoff = d.clo + r0;
+        T.slot = (int32_t)(nslots + t);
+        const double* p = d.B + r0;
+        T.V = lr_f32 ? fptr(p) : (const void*)p;
+        tiles.push_back(T);
       }
-    {
-      std::vector<MvSeg> small;
-      for (const MvSeg& sg : segs)
-        if (sg.n <= MV_SMALL) small.push_back(sg);
-      for (size_t q = 0; q < small.size(); q += 16) {
-        const int cnt = (int)std::min<size_t>(16, small.size() - q);
-        pb.push_back(MvProjBlock{(int)ordered.size(), cnt, 0, 0});
-        for (int c = 0; c < cnt; ++c) ordered.push_back(small[q + c]);
-      }
+      nslots += P;
     }
+    matrix_bytes = dense_bytes + lr_bytes;
+    // longest tiles first
+    std::stable_sort(tiles.begin(), tiles.end(), [](const MvTile& a, const MvTile& b) { return a.n > b.n; });
     std::vector<MvEntry> ents;
     std::vector<MvRow> rows;
+    std::vector<std::pair<int64_t, MvEntry>> row;
     for (size_t q = 0; q < S.leafcl.size(); ++q) {
       const Cluster& c = S.cl[S.leafcl[q]];
-      MvRow R{c.lo, c.hi, (int)ents.size(), 0};
+      row.clear();
       for (int e = S.rowptr[q]; e < S.rowptr[q + 1]; ++e) {
         const int l = S.rowidx[e];
         const LeafDesc& d = M.L[l];
         MvEntry E{};
+        int64_t bytes = 0;
         if (d.kind == K_DENSE) {
           E.kind = 0;
           E.n = d.n;
@@ -875,33 +882,39 @@ struct MvPlan {
           E.ld = d.m;
           const double* p = d.A + (c.lo - d.rlo);
           E.ptr = dense_f32 ? fptr(p) : (const void*)p;
+          bytes = (int64_t)d.n * d_elt;
         } else if (d.kind == K_LR && rk[l] > 0) {
           E.kind = 1;
+          E.n = np[l];
           E.k = rk[l];
-          E.tb = sbeg[l];
+          E.slot = slot0[l];
           E.ld = d.m;
           const double* p = d.A + (c.lo - d.rlo);
           E.ptr = lr_f32 ? fptr(p) : (const void*)p;
+          bytes = (int64_t)rk[l] * lr_elt;
         } else {
           continue;
         }
-        ents.push_back(E);
+        row.emplace_back(bytes, E);
       }
+      // most bytes first: the wavefronts take entries round-robin
+      std::stable_sort(row.begin(), row.end(),
+                       [](const std::pair<int64_t, MvEntry>& a, const std::pair<int64_t, MvEntry>& b) {
+                         return a.first > b.first;
+                       });
+      MvRow R{c.lo, c.hi, (int)ents.size(), 0};
+      for (auto& pe : row) ents.push_back(pe.second);
       R.eend = (int)ents.size();
       rows.push_back(R);
     }
-    upload(dsegs, ordered, s);
-    upload(dpblk, pb, s);
+    upload(dtiles, tiles, s);
     upload(dents, ents, s);
     upload(drows, rows, s);
-    tbuf.alloc(std::max(nlr, 1) * MV_KP * sizeof(double));
-    partial.alloc(8);
-    dev = MvDev{dsegs.as<MvSeg>(), dpblk.as<MvProjBlock>(), dents.as<MvEntry>(), drows.as<MvRow>(),
-                tbuf.as<double>(), (int)pb.size(), (int)rows.size(), dense_f32 ? 1 : 0, lr_f32 ? 1 : 0};
+    dpart.alloc(std::max<int64_t>(nslots, 1) * kb * sizeof(double));
+    dev = MvDev{dtiles.as<MvTile>(), dents.as<MvEntry>(), drows.as<MvRow>(), dpart.as<double>(),
+                (int)tiles.size(), (int)rows.size(), kb, dense_f32 ? 1 : 0, lr_f32 ? 1 : 0};
   }
-  void run(const double* x, const MvEpi& e, hipStream_t s) const {
-    HL_CHECK(mv_launch(dev, x, partial.as<double>(), e, s));
-  }
+  void run(const double* x, const MvEpi& e, hipStream_t s) const { HL_CHECK(mv_launch(dev, x, e, s)); }
 };
 
 static MvEpi epi_plain(double* y) {
@@ -1366,42 +1379,49 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
   });
 }
 
-hlevy_status hlevy_fac_time_apply(hlevy_fac* f, int32_t which, int32_t reps, void* stream, double out[6]) {
+hlevy_status hlevy_fac_kernel_times(hlevy_fac* f, int32_t reps, void* stream, hlevy_kernel_times* out) {
   if (!f || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (which < 0 || which > 2 || reps < 1 || reps > 100000) return fail(HLEVY_ERR_INVALID_ARG, "bad which/reps");
+  if (reps < 1 || reps > 100000) return fail(HLEVY_ERR_INVALID_ARG, "reps must be in [1, 100000]");
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
-    const MvPlan& M = which == 0 ? f->mvG : (which == 1 ? f->mvLi : f->mvUi);
+    const MvPlan* plans[3] = {&f->mvG, &f->mvLi, &f->mvUi};
     const double* x = f->w_u.as<double>();
     double* y = f->w_y.as<double>();
-    hipEvent_t e0, e1, e2;
-    HL_CHECK(hipEventCreate(&e0));
-    HL_CHECK(hipEventCreate(&e1));
-    HL_CHECK(hipEventCreate(&e2));
-    double tp = 0.0, tg = 0.0;
-    MvEpi e = epi_plain(y);
-    for (int r = 0; r < reps; ++r) {
-      HL_CHECK(hipEventRecord(e0, s));
-      HL_CHECK(project_launch(M.dev, x, M.partial.as<double>(), s));
-      HL_CHECK(hipEventRecord(e1, s));
-      HL_CHECK(gather_launch(M.dev, x, M.partial.as<double>(), e, s));
-      HL_CHECK(hipEventRecord(e2, s));
-      HL_CHECK(hipEventSynchronize(e2));
-      float a = 0.f, b = 0.f;
-      HL_CHECK(hipEventElapsedTime(&a, e0, e1));
-      HL_CHECK(hipEventElapsedTime(&b, e1, e2));
-      tp += a;
-      tg += b;
+    std::vector<hipEvent_t> ev((size_t)reps * 9);
+    for (auto& e : ev) HL_CHECK(hipEventCreate(&e));
+    const MvEpi e = epi_plain(y);
+    // the products in the order of a Crank-Nicolson step (G, L^{-1}, U^{-1}),
+    // so the three matrices stream through the caches as they do when stepping
+    for (int r = 0; r < reps; ++r)
+      for (int w = 0; w < 3; ++w) {
+        hipEvent_t* E = &ev[((size_t)r * 3 + w) * 3];
+        HL_CHECK(hipEventRecord(E[0], s));
+        HL_CHECK(project_launch(plans[w]->dev, x, s));
+        HL_CHECK(hipEventRecord(E[1], s));
+        HL_CHECK(gather_launch(plans[w]->dev, x, e, s));
+        HL_CHECK(hipEventRecord(E[2], s));
+      }
+    HL_CHECK(hipStreamSynchronize(s));
+    std::memset(out, 0, sizeof(*out));
+    for (int r = 0; r < reps; ++r)
+      for (int w = 0; w < 3; ++w) {
+        hipEvent_t* E = &ev[((size_t)r * 3 + w) * 3];
+        float a = 0.f, b = 0.f;
+        HL_CHECK(hipEventElapsedTime(&a, E[0], E[1]));
+        HL_CHECK(hipEventElapsedTime(&b, E[1], E[2]));
+        out->project_ms[w] += a / reps;
+        out->gather_ms[w] += b / reps;
+      }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int w = 0; w < 3; ++w) {
+      const MvPlan& M = *plans[w];
+      out->dense_bytes[w] = (double)M.dense_bytes;
+      out->u_bytes[w] = (double)M.u_bytes;
+      out->v_bytes[w] = (double)M.v_bytes;
+      out->partial_bytes[w] = (double)M.nslots * M.dev.kb * sizeof(double);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
-    out[0] = tp / reps;
-    out[1] = tg / reps;
-    out[2] = (double)M.matrix_bytes;
-    out[3] = (double)M.lr_bytes;
-    out[4] = (double)M.dense_bytes;
-    out[5] = (double)f->op->S.N;
+    out->N = f->op->S.N;
+    out->reps = reps;
     return HLEVY_OK;
   });
 }

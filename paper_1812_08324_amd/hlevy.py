@@ -51,9 +51,16 @@ class OpInfo(C.Structure):
                 ("mean_rank", C.c_double), ("rank_overflows", C.c_int32)]
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [("N", C.c_int64), ("reps", C.c_int32), ("pad", C.c_int32),
+                ("project_ms", C.c_double * 3), ("gather_ms", C.c_double * 3),
+                ("dense_bytes", C.c_double * 3), ("u_bytes", C.c_double * 3),
+                ("v_bytes", C.c_double * 3), ("partial_bytes", C.c_double * 3)]
+
+
 EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
            "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
-           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_fac_time_apply", "hlevy_op_destroy",
+           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_fac_kernel_times", "hlevy_op_destroy",
            "hlevy_fac_destroy"]
 
 
@@ -75,7 +82,7 @@ def _load():
         "hlevy_solve": ([vp, vp, vp, C.POINTER(Refine), vp], st),
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
                         C.POINTER(Stats), vp], st),
-        "hlevy_fac_time_apply": ([vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double)], st),
+        "hlevy_fac_kernel_times": ([vp, C.c_int32, vp, C.POINTER(KernelTimes)], st),
         "hlevy_op_destroy": ([vp], None),
         "hlevy_fac_destroy": ([vp], None),
     }
@@ -141,13 +148,17 @@ def plan_info(prob: Problem, hp: HParams) -> dict:
     return {k: getattr(out, k) for k, _ in PlanInfo._fields_}
 
 
-def fac_time_apply(fac, which: int, reps: int = 20, stream=None) -> dict:
-    """HIP-event timing of one matrix-vector product of the factor:
-    which = 0 (G), 1 (L^{-1}), 2 (U^{-1})."""
-    out = (C.c_double * 6)()
-    _check(lib.hlevy_fac_time_apply(fac.h, int(which), int(reps), _stream(stream), out), "hlevy_fac_time_apply")
-    keys = ("project_ms", "gather_ms", "matrix_bytes", "lowrank_bytes", "dense_bytes", "N")
-    return dict(zip(keys, list(out)))
+def fac_kernel_times(fac, reps: int = 20, stream=None) -> dict:
+    """HIP-event timing of the per-step products in stepping order; returns
+    {"G"|"Linv"|"Uinv": {project_ms, gather_ms, dense_bytes, u_bytes, v_bytes,
+    partial_bytes}, "N": N}."""
+    out = KernelTimes()
+    _check(lib.hlevy_fac_kernel_times(fac.h, int(reps), _stream(stream), C.byref(out)), "hlevy_fac_kernel_times")
+    res = {"N": out.N}
+    for w, name in enumerate(("G", "Linv", "Uinv")):
+        res[name] = {k: getattr(out, k)[w] for k in ("project_ms", "gather_ms", "dense_bytes", "u_bytes",
+                                                      "v_bytes", "partial_bytes")}
+    return res
 
 
 class Op:
