@@ -107,6 +107,24 @@ struct CopyItem {
 
 // Leaf factorisation: LU in place (no pivoting) and the inverses of the
 // unit-lower and upper factors.
+// Dense diagonal block of at most 2 x 2 leaf tiles, n = m1 + m2 <= LUINV_N
+// (m2 = 0: a single leaf): LU without pivoting and the inverses of both
+// factors.  Tiles are column-major with leading dimension = their row count.
+constexpr int LUINV_N = 128;
+struct LuInvItem {
+  const double* A11;
+  const double* A12;
+  const double* A21;
+  const double* A22;
+  double* L11;   // blocks of L^{-1} (L12 = 0)
+  double* L21;
+  double* L22;
+  double* U11;   // blocks of U^{-1} (U21 = 0)
+  double* U12;
+  double* U22;
+  int32_t m1, m2;
+};
+
 struct GetrfItem {
   double* LU;
   double* Li;

@@ -19,6 +19,7 @@ hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms,
 hipError_t launch_dense_prod(const DProdItem* items, int n, hipStream_t s);
 hipError_t launch_copy(const CopyItem* items, int n, hipStream_t s);
 hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, hipStream_t s);
+hipError_t launch_lu_inv(const LuInvItem* items, int n, int32_t* zero_pivot, hipStream_t s);
 hipError_t launch_apply(const ApplyJob* jobs, const ProjItem* proj, int nproj, const GatherItem* gat,
                         int ngat, const DevLists& dl, hipStream_t s);
 hipError_t launch_perm_gather(double* out, const double* in, const int32_t* perm, int N, hipStream_t s);

@@ -1159,6 +1159,218 @@ __global__ void __launch_bounds__(HL_BLOCK) k_getrf_inv(const GetrfItem* items, 
 }
 
 // ---------------------------------------------------------------------------
+// Dense diagonal block of up to 2 x 2 leaf tiles (App. B.3 at the bottom of
+// the recursion): LU without pivoting, then the inverses of the unit lower
+// factor L and of the upper factor U, all in one workgroup of 1024 threads.
+// The block, padded with the identity to LUINV_N = 128, lives in registers
+// with a cyclic layout: thread (ty, tx) owns rows ty + 32 r and columns
+// tx + 32 c (r, c < 4), so the owner of column k holds it in register
+// column k / 32 -- a constant over 32 consecutive steps, which keeps every
+// register index static.  Each elimination step publishes one column and
+// one row through LDS (double buffered, one barrier per step).
+// The inverses use the right-looking forms X = L^{-1}:
+// X[i, :] -= L[i, k] X[k, :] (i > k), and Y = U'^{-1} for the unit upper
+// U' = D^{-1} U from the bottom, U^{-1} = Y D^{-1}; X is strictly lower and
+// Y strictly upper, so both share one register array and advance together.
+// ---------------------------------------------------------------------------
+constexpr int LI_G = 32;                  // thread grid is LI_G x LI_G
+constexpr int LI_T = LI_G * LI_G;         // 1024 threads
+constexpr int LI_R = LUINV_N / LI_G;      // 4 x 4 entries per thread
+constexpr int LI_S = LUINV_N + 1;         // LDS stage stride (odd: fewer bank conflicts)
+
+size_t luinv_lds_bytes() { return sizeof(double) * ((size_t)LUINV_N * LI_S + 9 * LUINV_N); }
+
+__global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t* zero_pivot) {
+  extern __shared__ double lds[];
+  double* stage = lds;                          // LUINV_N x LI_S
+  double* pub = lds + (size_t)LUINV_N * LI_S;   // [2][4][LUINV_N]
+  double* dinv = pub + 8 * LUINV_N;             // 1 / U[k, k]
+  const LuInvItem it = items[blockIdx.x];
+  const int m1 = it.m1, m2 = it.m2, n = m1 + m2;
+  const int tid = threadIdx.x, ty = tid / LI_G, tx = tid % LI_G;
+
+  for (int e = tid; e < LUINV_N * LUINV_N; e += LI_T) {
+    const int i = e % LUINV_N, j = e / LUINV_N;
+    double v = i == j ? 1.0 : 0.0;
+    if (i < n && j < n) {
+      if (i < m1)
+        v = j < m1 ? it.A11[i + m1 * j] : it.A12[i + m1 * (j - m1)];
+      else
+        v = j < m1 ? it.A21[(i - m1) + m2 * j] : it.A22[(i - m1) + m2 * (j - m1)];
+    }
+    stage[i + LI_S * j] = v;
+  }
+  __syncthreads();
+  double a[LI_R][LI_R], z[LI_R][LI_R];
+#pragma unroll
+  for (int r = 0; r < LI_R; ++r)
+#pragma unroll
+    for (int c = 0; c < LI_R; ++c) {
+      a[r][c] = stage[(ty + LI_G * r) + LI_S * (tx + LI_G * c)];
+      z[r][c] = 0.0;
+    }
+
+  // LU: step k publishes column k (rows >= k) and row k (columns > k)
+  bool zp = false;
+#pragma unroll
+  for (int cb = 0; cb < LI_R; ++cb) {
+    const int kend = min(n, LI_G * (cb + 1));
+    for (int k = LI_G * cb; k < kend; ++k) {
+      const int kk = k - LI_G * cb;
+      double* col = pub + (k & 1) * 4 * LUINV_N;
+      double* row = col + LUINV_N;
+      if (tx == kk) {
+#pragma unroll
+        for (int r = 0; r < LI_R; ++r)
+          if (ty + LI_G * r >= k) col[ty + LI_G * r] = a[r][cb];
+      }
+      if (ty == kk) {
+#pragma unroll
+        for (int c = 0; c < LI_R; ++c)
+          if (tx + LI_G * c > k) row[tx + LI_G * c] = a[cb][c];
+      }
+      __syncthreads();
+      const double piv = col[k];
+      zp = zp || piv == 0.0;
+      const double rinv = 1.0 / piv;
+      if (tid == 0) dinv[k] = rinv;
+      double l[LI_R], u[LI_R];
+#pragma unroll
+      for (int r = 0; r < LI_R; ++r) {
+        const double cv = col[ty + LI_G * r];
+        l[r] = ty + LI_G * r > k ? cv * rinv : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < LI_R; ++c) {
+        const double rv = row[tx + LI_G * c];
+        u[c] = tx + LI_G * c > k ? rv : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < LI_R; ++r)
+#pragma unroll
+        for (int c = 0; c < LI_R; ++c) a[r][c] -= l[r] * u[c];
+      if (tx == kk) {
+        // the multipliers replace column k below the diagonal
+#pragma unroll
+        for (int r = 0; r < LI_R; ++r)
+          if (ty + LI_G * r > k) a[r][cb] = l[r];
+      }
+    }
+  }
+  if (tid >= n && tid < LUINV_N) dinv[tid] = 1.0;   // identity padding
+  __syncthreads();
+
+  // inverses on the padded block: step s advances X (k = s) and Y
+  // (k2 = LUINV_N - 1 - s); beyond n both steps are no-ops
+#pragma unroll
+  for (int cb = 0; cb < LI_R; ++cb) {
+    const int cb2 = LI_R - 1 - cb;
+    for (int kk = 0; kk < LI_G; ++kk) {
+      const int k = LI_G * cb + kk, kk2 = LI_G - 1 - kk, k2 = LI_G * cb2 + kk2;
+      double* lc = pub + (k & 1) * 4 * LUINV_N;
+      double* xr = lc + LUINV_N;
+      double* uc = xr + LUINV_N;
+      double* yr = uc + LUINV_N;
+      if (tx == kk) {
+#pragma unroll
+        for (int r = 0; r < LI_R; ++r)
+          if (ty + LI_G * r > k) lc[ty + LI_G * r] = a[r][cb];
+      }
+      if (ty == kk) {
+#pragma unroll
+        for (int c = 0; c < LI_R; ++c) {
+          const int j = tx + LI_G * c;
+          if (j <= k) xr[j] = j == k ? 1.0 : z[cb][c];
+        }
+      }
+      if (tx == kk2) {
+#pragma unroll
+        for (int r = 0; r < LI_R; ++r) {
+          const int i = ty + LI_G * r;
+          if (i < k2) uc[i] = a[r][cb2] * dinv[i];
+        }
+      }
+      if (ty == kk2) {
+#pragma unroll
+        for (int c = 0; c < LI_R; ++c) {
+          const int j = tx + LI_G * c;
+          if (j >= k2) yr[j] = j == k2 ? 1.0 : z[cb2][c];
+        }
+      }
+      __syncthreads();
+      double li[LI_R], ui[LI_R], xj[LI_R], yj[LI_R];
+#pragma unroll
+      for (int r = 0; r < LI_R; ++r) {
+        const int i = ty + LI_G * r;
+        const double lv = lc[i], uv = uc[i];
+        li[r] = i > k ? lv : 0.0;
+        ui[r] = i < k2 ? uv : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < LI_R; ++c) {
+        const int j = tx + LI_G * c;
+        const double xv = xr[j], yv = yr[j];
+        xj[c] = j <= k ? xv : 0.0;
+        yj[c] = j >= k2 ? yv : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < LI_R; ++r)
+#pragma unroll
+        for (int c = 0; c < LI_R; ++c) z[r][c] -= li[r] * xj[c] + ui[r] * yj[c];
+    }
+  }
+  __syncthreads();
+
+  // L^{-1}: strictly lower part of z, unit diagonal
+#pragma unroll
+  for (int r = 0; r < LI_R; ++r)
+#pragma unroll
+    for (int c = 0; c < LI_R; ++c) {
+      const int i = ty + LI_G * r, j = tx + LI_G * c;
+      stage[i + LI_S * j] = i > j ? z[r][c] : (i == j ? 1.0 : 0.0);
+    }
+  __syncthreads();
+  for (int e = tid; e < LUINV_N * LUINV_N; e += LI_T) {
+    const int i = e % LUINV_N, j = e / LUINV_N;
+    if (i >= n || j >= n) continue;
+    const double v = stage[i + LI_S * j];
+    if (i < m1) {
+      if (j < m1) it.L11[i + m1 * j] = v;
+    } else {
+      if (j < m1)
+        it.L21[(i - m1) + m2 * j] = v;
+      else
+        it.L22[(i - m1) + m2 * (j - m1)] = v;
+    }
+  }
+  __syncthreads();
+  // U^{-1} = Y D^{-1}: strictly upper part of z, column j scaled by 1 / U[j, j]
+#pragma unroll
+  for (int r = 0; r < LI_R; ++r)
+#pragma unroll
+    for (int c = 0; c < LI_R; ++c) {
+      const int i = ty + LI_G * r, j = tx + LI_G * c;
+      const double dj = dinv[j];
+      stage[i + LI_S * j] = i < j ? z[r][c] * dj : (i == j ? dj : 0.0);
+    }
+  __syncthreads();
+  for (int e = tid; e < LUINV_N * LUINV_N; e += LI_T) {
+    const int i = e % LUINV_N, j = e / LUINV_N;
+    if (i >= n || j >= n) continue;
+    const double v = stage[i + LI_S * j];
+    if (j < m1) {
+      if (i < m1) it.U11[i + m1 * j] = v;
+    } else {
+      if (i < m1)
+        it.U12[i + m1 * (j - m1)] = v;
+      else
+        it.U22[(i - m1) + m2 * (j - m1)] = v;
+    }
+  }
+  if (tid == 0 && zp) atomicAdd(zero_pivot, 1);
+}
+
+// ---------------------------------------------------------------------------
 // H-block times multi-vector: projections of the low-rank leaves, then
 // owner-computes gather per output leaf cluster (no atomics, fixed order).
 // ---------------------------------------------------------------------------
@@ -1360,6 +1572,11 @@ hipError_t launch_copy(const CopyItem* items, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_leaf, dim3(n), dim3(HL_BLOCK), 0, s, items);
   return post();
 }
+hipError_t launch_lu_inv(const LuInvItem* items, int n, int32_t* zero_pivot, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lu_inv, dim3(n), dim3(LI_T), luinv_lds_bytes(), s, items, zero_pivot);
+  return post();
+}
 hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_getrf_inv, dim3(n), dim3(HL_BLOCK), 0, s, items, zero_pivot);
@@ -1411,6 +1628,9 @@ namespace hl {
 hipError_t init_kernel_attributes() {
   hipError_t e = hipFuncSetAttribute((const void*)k_flush_core_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      6 * 48 * 48 * (int)sizeof(double));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_lu_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)luinv_lds_bytes());
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_flush_core, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (4 * KMAX * KMAX + 2 * KMAX) * (int)sizeof(double));

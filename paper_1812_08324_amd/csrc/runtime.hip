@@ -235,7 +235,7 @@ struct DevStructure {
 // ---------------------------------------------------------------------------
 // plan: phases over item arrays, built on the host, uploaded once
 // ---------------------------------------------------------------------------
-enum PhaseType { PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF };
+enum PhaseType { PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF, PH_LUINV };
 
 struct Phase {
   int type;
@@ -256,7 +256,8 @@ struct Plan {
   std::vector<ChunkItem> lgram, lexp;
   std::vector<CopyItem> copies;
   std::vector<GetrfItem> getrf;
-  DevBuf djobs, dproj, dgath, ddprod, dterms, ddflush, dltg, dlgram, dlexp, dcopies, dgetrf;
+  std::vector<LuInvItem> luinv;
+  DevBuf djobs, dproj, dgath, ddprod, dterms, ddflush, dltg, dlgram, dlexp, dcopies, dgetrf, dluinv;
 
   void upload_all(hipStream_t s) {
     upload(djobs, jobs, s);
@@ -270,6 +271,7 @@ struct Plan {
     upload(dlexp, lexp, s);
     upload(dcopies, copies, s);
     upload(dgetrf, getrf, s);
+    upload(dluinv, luinv, s);
   }
 
   void run(const DevLists& dl, int32_t* zero_pivot, hipStream_t s) const {
@@ -295,6 +297,9 @@ struct Plan {
           break;
         case PH_GETRF:
           HL_CHECK(launch_getrf_inv(dgetrf.as<GetrfItem>() + p.b0, p.n0, zero_pivot, s));
+          break;
+        case PH_LUINV:
+          HL_CHECK(launch_lu_inv(dluinv.as<LuInvItem>() + p.b0, p.n0, zero_pivot, s));
           break;
       }
     }
@@ -720,8 +725,54 @@ struct Builder {
 // (App. B.3 recursion; inverses by the 2x2 block formulas):
 //   LU(A11);  U12 = L11^{-1} A12;  L21 = A21 U11^{-1};  LU(A22 - L21 U12);
 //   (L^{-1})21 = -L22^{-1} L21 L11^{-1};  (U^{-1})12 = -U11^{-1} U12 U22^{-1}.
+// A diagonal node that is one dense leaf, or 2 x 2 dense leaves of at most
+// LUINV_N rows in all, is factored with its inverses by one fused kernel.
+static bool emit_dense_luinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, int node) {
+  const Structure& S = B.S;
+  const BNode& b = S.bn[node];
+  if (B.csize(b.r) > LUINV_N) return false;
+  LuInvItem it{};
+  if (b.kind != K_H) {
+    const int l = b.leaf;
+    if (LU->L[l].kind != K_DENSE || Li->L[l].kind != K_DENSE || Ui->L[l].kind != K_DENSE) return false;
+    it.A11 = LU->L[l].A;
+    it.L11 = Li->L[l].A;
+    it.U11 = Ui->L[l].A;
+    it.m1 = LU->L[l].m;
+    it.m2 = 0;
+  } else {
+    int lf[4];
+    for (int q = 0; q < 4; ++q) {
+      const BNode& c = S.bn[b.child[q]];
+      if (c.kind == K_H || LU->L[c.leaf].kind != K_DENSE) return false;
+      lf[q] = c.leaf;
+    }
+    // Li: 11, 21, 22 dense (12 structurally zero); Ui: 11, 12, 22 dense
+    if (Li->L[lf[0]].kind != K_DENSE || Li->L[lf[2]].kind != K_DENSE || Li->L[lf[3]].kind != K_DENSE ||
+        Ui->L[lf[0]].kind != K_DENSE || Ui->L[lf[1]].kind != K_DENSE || Ui->L[lf[3]].kind != K_DENSE)
+      return false;
+    it.A11 = LU->L[lf[0]].A;
+    it.A12 = LU->L[lf[1]].A;
+    it.A21 = LU->L[lf[2]].A;
+    it.A22 = LU->L[lf[3]].A;
+    it.L11 = Li->L[lf[0]].A;
+    it.L21 = Li->L[lf[2]].A;
+    it.L22 = Li->L[lf[3]].A;
+    it.U11 = Ui->L[lf[0]].A;
+    it.U12 = Ui->L[lf[1]].A;
+    it.U22 = Ui->L[lf[3]].A;
+    it.m1 = LU->L[lf[0]].m;
+    it.m2 = LU->L[lf[3]].m;
+  }
+  Phase ph{PH_LUINV, (int)B.P.luinv.size(), 1, 0, 0, 0, 0, 0.0};
+  B.P.luinv.push_back(it);
+  B.P.ph.push_back(ph);
+  return true;
+}
+
 static void hluinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, HMat* TMP, int node) {
   const BNode& b = B.S.bn[node];
+  if (emit_dense_luinv(B, LU, Li, Ui, node)) return;
   if (b.kind != K_H) {
     const LeafDesc& d = LU->L[b.leaf];
     Phase ph{PH_GETRF, (int)B.P.getrf.size(), 1, 0, 0, 0, 0, 0.0};
@@ -1221,35 +1272,41 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
         HMat& src = side == 0 ? Li : Ui;
         HMat& dst = side == 0 ? f->Li : f->Ui;
         B.copy_node(&dst, &src, 0, 1.0, false, /*skip_compress=*/true);
-        std::vector<LFlushTarget> tgs;
-        std::vector<std::vector<Term>> tl;
-        for (size_t l = 0; l < S.lf.size(); ++l) {
-          const LeafDesc& d = dst.L[l];
-          if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
-          LFlushTarget T{};
-          T.U = d.A;
-          T.V = d.B;
-          T.rank = dst.rank + l;
-          T.m = d.m;
-          T.n = d.n;
-          T.kcap = d.kcap;
-          T.Kcap = d.n;   // the target starts empty: the width is the term's
-          Term tm{};
-          tm.dense = 0;
-          tm.ro = 0;
-          tm.mr = d.m;
-          tm.co = 0;
-          tm.nc = d.n;
-          tm.U = src.L[l].A;
-          tm.ldu = d.m;
-          tm.W = op->ds.ident.as<double>();
-          tm.ldw = 64;
-          tm.kfix = d.n;
-          tm.sign = 1.0;
-          tgs.push_back(T);
-          tl.push_back({tm});
+        // 32 columns per round, so that every rounded addition stays within
+        // 48 columns (the targets start at rank 0)
+        for (int c0 = 0; c0 < 64; c0 += 32) {
+          std::vector<LFlushTarget> tgs;
+          std::vector<std::vector<Term>> tl;
+          for (size_t l = 0; l < S.lf.size(); ++l) {
+            const LeafDesc& d = dst.L[l];
+            if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
+            const int c1 = std::min(d.n, c0 + 32);
+            if (c0 >= c1) continue;
+            LFlushTarget T{};
+            T.U = d.A;
+            T.V = d.B;
+            T.rank = dst.rank + l;
+            T.m = d.m;
+            T.n = d.n;
+            T.kcap = d.kcap;
+            T.Kcap = (c0 == 0 ? 0 : d.kcap) + (c1 - c0);
+            Term tm{};
+            tm.dense = 0;
+            tm.ro = 0;
+            tm.mr = d.m;
+            tm.co = c0;
+            tm.nc = c1 - c0;
+            tm.U = src.L[l].A + (size_t)d.m * c0;
+            tm.ldu = d.m;
+            tm.W = op->ds.ident.as<double>();
+            tm.ldw = 64;
+            tm.kfix = c1 - c0;
+            tm.sign = 1.0;
+            tgs.push_back(T);
+            tl.push_back({tm});
+          }
+          B.emit_lflush(tgs, tl, lu_tol);
         }
-        B.emit_lflush(tgs, tl, lu_tol);
       }
       const double t1 = now_s();
       P.upload_all(s);
