@@ -57,9 +57,12 @@ struct MvDev {
 };
 
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
-// the two kernels of mv_launch separately (timing)
-hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s);
-hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
+// the two kernels of mv_launch separately; non-null events are attached to
+// the dispatch (start, stop) for timing
+hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // rows of V one projection wavefront covers per pass (64 lanes x rows per lane)
 int project_rows_per_pass(int kb, bool lr_f32);
 hipError_t launch_convert_f32(const double* in, float* out, size_t n, hipStream_t s);

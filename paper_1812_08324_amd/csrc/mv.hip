@@ -14,6 +14,7 @@
 //     fixed order, the wavefronts take entries round-robin (the host sorts
 //     each list by bytes), then reduce in LDS and apply the Crank-Nicolson
 //     epilogue.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "hl_mv.h"
@@ -216,59 +217,71 @@ int project_rows_per_pass(int kb, bool lr_f32) {
   return 64 * (vals / kb);
 }
 
+// Launches; with events, the events are attached to the dispatch itself
+// (hipExtLaunchKernelGGL) and time exactly that kernel.
 template <typename TL, int KB>
-static void project_t(const MvDev& M, const double* x, hipStream_t s) {
-  if (M.ntiles > 0)
-    hipLaunchKernelGGL((k_mv_project<TL, KB>), dim3((M.ntiles + 3) / 4), dim3(256), 0, s, M.tiles, M.ntiles, x,
-                       M.part);
+static void project_t(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (M.ntiles <= 0) return;
+  const dim3 grid((M.ntiles + 3) / 4);
+  if (e0)
+    hipExtLaunchKernelGGL((k_mv_project<TL, KB>), grid, dim3(256), 0, s, e0, e1, 0, M.tiles, M.ntiles, x, M.part);
+  else
+    hipLaunchKernelGGL((k_mv_project<TL, KB>), grid, dim3(256), 0, s, M.tiles, M.ntiles, x, M.part);
 }
 
 template <typename TD, typename TL, int KB>
-static void gather_t(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
-  if (M.nrows > 0)
-    hipLaunchKernelGGL((k_mv_gather<TD, TL, KB>), dim3(M.nrows), dim3(64 * MV_GW), 0, s, M.rows, M.ents, x,
-                       M.part, epi);
+static void gather_t(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1) {
+  if (M.nrows <= 0) return;
+  const dim3 grid(M.nrows), block(64 * MV_GW);
+  const double* part = M.part;
+  if (e0)
+    hipExtLaunchKernelGGL((k_mv_gather<TD, TL, KB>), grid, block, 0, s, e0, e1, 0, M.rows, M.ents, x, part, epi);
+  else
+    hipLaunchKernelGGL((k_mv_gather<TD, TL, KB>), grid, block, 0, s, M.rows, M.ents, x, part, epi);
 }
 
 template <typename TL>
-static void project_kb(const MvDev& M, const double* x, hipStream_t s) {
+static void project_kb(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (M.kb <= 8)
-    project_t<TL, 8>(M, x, s);
+    project_t<TL, 8>(M, x, s, e0, e1);
   else if (M.kb <= 16)
-    project_t<TL, 16>(M, x, s);
+    project_t<TL, 16>(M, x, s, e0, e1);
   else
-    project_t<TL, 32>(M, x, s);
+    project_t<TL, 32>(M, x, s, e0, e1);
 }
 
 template <typename TD, typename TL>
-static void gather_kb(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
+static void gather_kb(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1) {
   if (M.kb <= 8)
-    gather_t<TD, TL, 8>(M, x, epi, s);
+    gather_t<TD, TL, 8>(M, x, epi, s, e0, e1);
   else if (M.kb <= 16)
-    gather_t<TD, TL, 16>(M, x, epi, s);
+    gather_t<TD, TL, 16>(M, x, epi, s, e0, e1);
   else
-    gather_t<TD, TL, 32>(M, x, epi, s);
+    gather_t<TD, TL, 32>(M, x, epi, s, e0, e1);
 }
 
-hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s) {
+hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
   if (M.lr_f32)
-    project_kb<float>(M, x, s);
+    project_kb<float>(M, x, s, e0, e1);
   else
-    project_kb<double>(M, x, s);
+    project_kb<double>(M, x, s, e0, e1);
   return hipGetLastError();
 }
 
-hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
+hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
   if (M.dense_f32 && M.lr_f32)
-    gather_kb<float, float>(M, x, epi, s);
+    gather_kb<float, float>(M, x, epi, s, e0, e1);
   else if (M.dense_f32)
-    gather_kb<float, double>(M, x, epi, s);
+    gather_kb<float, double>(M, x, epi, s, e0, e1);
   else if (M.lr_f32)
-    gather_kb<double, float>(M, x, epi, s);
+    gather_kb<double, float>(M, x, epi, s, e0, e1);
   else
-    gather_kb<double, double>(M, x, epi, s);
+    gather_kb<double, double>(M, x, epi, s, e0, e1);
   return hipGetLastError();
 }
 

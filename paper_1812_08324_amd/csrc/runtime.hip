@@ -1444,28 +1444,26 @@ hlevy_status hlevy_fac_kernel_times(hlevy_fac* f, int32_t reps, void* stream, hl
     const MvPlan* plans[3] = {&f->mvG, &f->mvLi, &f->mvUi};
     const double* x = f->w_u.as<double>();
     double* y = f->w_y.as<double>();
-    std::vector<hipEvent_t> ev((size_t)reps * 9);
+    std::vector<hipEvent_t> ev((size_t)reps * 12);
     for (auto& e : ev) HL_CHECK(hipEventCreate(&e));
     const MvEpi e = epi_plain(y);
     // the products in the order of a Crank-Nicolson step (G, L^{-1}, U^{-1}),
-    // so the three matrices stream through the caches as they do when stepping
+    // so the three matrices stream through the caches as they do when
+    // stepping; each kernel carries its own start/stop events
     for (int r = 0; r < reps; ++r)
       for (int w = 0; w < 3; ++w) {
-        hipEvent_t* E = &ev[((size_t)r * 3 + w) * 3];
-        HL_CHECK(hipEventRecord(E[0], s));
-        HL_CHECK(project_launch(plans[w]->dev, x, s));
-        HL_CHECK(hipEventRecord(E[1], s));
-        HL_CHECK(gather_launch(plans[w]->dev, x, e, s));
-        HL_CHECK(hipEventRecord(E[2], s));
+        hipEvent_t* E = &ev[((size_t)r * 3 + w) * 4];
+        HL_CHECK(project_launch(plans[w]->dev, x, s, E[0], E[1]));
+        HL_CHECK(gather_launch(plans[w]->dev, x, e, s, E[2], E[3]));
       }
     HL_CHECK(hipStreamSynchronize(s));
     std::memset(out, 0, sizeof(*out));
     for (int r = 0; r < reps; ++r)
       for (int w = 0; w < 3; ++w) {
-        hipEvent_t* E = &ev[((size_t)r * 3 + w) * 3];
+        hipEvent_t* E = &ev[((size_t)r * 3 + w) * 4];
         float a = 0.f, b = 0.f;
-        HL_CHECK(hipEventElapsedTime(&a, E[0], E[1]));
-        HL_CHECK(hipEventElapsedTime(&b, E[1], E[2]));
+        if (plans[w]->dev.ntiles > 0) HL_CHECK(hipEventElapsedTime(&a, E[0], E[1]));
+        HL_CHECK(hipEventElapsedTime(&b, E[2], E[3]));
         out->project_ms[w] += a / reps;
         out->gather_ms[w] += b / reps;
       }
