@@ -19,6 +19,8 @@ hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms,
 hipError_t launch_dense_prod(const DProdItem* items, int n, hipStream_t s);
 hipError_t launch_copy(const CopyItem* items, int n, hipStream_t s);
 hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, hipStream_t s);
+// whole rounded additions (targets of at most GRAM_CHUNK rows per side, ks <= 48)
+hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s);
 hipError_t launch_lu_inv(const LuInvItem* items, int n, int32_t* zero_pivot, hipStream_t s);
 hipError_t launch_apply(const ApplyJob* jobs, const ProjItem* proj, int nproj, const GatherItem* gat,
                         int ngat, const DevLists& dl, hipStream_t s);

@@ -405,8 +405,10 @@ __global__ void __launch_bounds__(HL_BLOCK) k_aca(ProblemDev P, const int32_t* p
 // ---------------------------------------------------------------------------
 // rounded addition: Gram (double-double) -> pivoted Cholesky -> Jacobi SVD
 // ---------------------------------------------------------------------------
+constexpr int RA_YS = 32;   // row stride of Y_U / Y_V (>= every rank capacity)
+
 struct ColMap {
-  int K, kC, nt;
+  int K, kC, nt, tb;   // tb: first term of this concatenation (relative to T.tbeg)
   int off[KMAX + 1];
   int kt[KMAX];
 };
@@ -414,6 +416,7 @@ struct ColMap {
 __device__ void build_colmap(const LFlushTarget& T, const Term* terms, int kC, ColMap& cm) {
   cm.kC = kC;
   cm.nt = T.tcount;
+  cm.tb = 0;
   int K = kC;
   for (int t = 0; t < T.tcount; ++t) {
     const Term& tm = terms[T.tbeg + t];
@@ -426,13 +429,35 @@ __device__ void build_colmap(const LFlushTarget& T, const Term* terms, int kC, C
   cm.K = K;
 }
 
+// The next concatenation of a long term list: the target's kC columns and
+// terms [t0, t1) with t1 as large as the width limit allows (at least one
+// term; every term is at most 32 columns wide and kC <= 16 in the fused
+// kernel, so limit 48 always admits one).
+__device__ void build_colmap_chunk(const LFlushTarget& T, const Term* terms, int kC, int t0, int limit, ColMap& cm) {
+  cm.kC = kC;
+  cm.tb = t0;
+  int K = kC, t = 0;
+  while (t0 + t < T.tcount && t < KMAX) {
+    const Term& tm = terms[T.tbeg + t0 + t];
+    const int kt = tm.k ? *tm.k : tm.kfix;
+    if (t > 0 && K + kt > limit) break;
+    cm.off[t] = K;
+    cm.kt[t] = kt;
+    K += kt;
+    ++t;
+  }
+  cm.nt = t;
+  cm.off[t] = K;
+  cm.K = K;
+}
+
 // value of column j of the concatenated factor on side 0 (U side) or 1 (V side)
 __device__ __forceinline__ double side_val(const LFlushTarget& T, const Term* terms, const ColMap& cm,
                                            int side, int row, int j) {
   if (j < cm.kC) return side == 0 ? T.U[row + (size_t)T.m * j] : T.V[row + (size_t)T.n * j];
   int t = 0;
   while (j >= cm.off[t + 1]) ++t;
-  const Term& tm = terms[T.tbeg + t];
+  const Term& tm = terms[T.tbeg + cm.tb + t];
   int c = j - cm.off[t];
   if (side == 0) {
     int rr = row - tm.ro;
@@ -758,17 +783,21 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
   }
   __syncthreads();
   const int r = sint[0];
+  // Y_U, Y_V: K x RA_YS each, row q at q * RA_YS, zero beyond r (k_flush_expand)
   double* YU = T.ws + (size_t)(T.nchA + T.nchB) * np * 2;
-  double* YV = YU + (size_t)Kc * T.kcap;
-  for (int e = tid; e < K * r; e += HL_BLOCK) {
-    int q = e % K, c = e / K;
-    int oc = order[c];
+  double* YV = YU + (size_t)K * RA_YS;
+  for (int e = tid; e < K * RA_YS; e += HL_BLOCK) {
+    const int q = e / RA_YS, c = e % RA_YS;
     double su = 0.0, sv = 0.0;
-    for (int i = 0; i < rB; ++i) su += RB[i * ks + q] * Z[i + ld * oc];
-    for (int i = 0; i < rA; ++i) sv += RA[i * ks + q] * M[i + ld * oc];
-    double sg = sig[oc];
-    YU[q + (size_t)Kc * c] = su;
-    YV[q + (size_t)Kc * c] = sv / (sg * sg);
+    if (c < r) {
+      const int oc = order[c];
+      for (int i = 0; i < rB; ++i) su += RB[i * ks + q] * Z[i + ld * oc];
+      for (int i = 0; i < rA; ++i) sv += RA[i * ks + q] * M[i + ld * oc];
+      const double sg = sig[oc];
+      sv /= sg * sg;
+    }
+    YU[e] = su;
+    YV[e] = sv;
   }
 }
 
@@ -788,155 +817,126 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
 // ||C - U_new V_new^T||_F = ||M - M_J T||_F <= tol ||C||_F.
 // Schur complements are stored in their upper triangle; row j of each
 // Cholesky factor is written into the storage row of its pivot.
-__device__ int pchol_inplace(double* Sh, double* Sl, int K, int ks, int* sel, int* piv, double* rowh,
-                             double* rowl, int* sint, double* sdbl, int mode, double thr, int rmax, bool use_dd) {
-  // mode 0: stop when the largest remaining diagonal <= thr * (initial largest diagonal)
-  // mode 1: stop when the remaining trace <= thr * (initial trace)
+// One barrier per step: every wavefront selects the pivot itself from the
+// remaining diagonal (largest, ties to the lowest index; identical in all
+// wavefronts), the selected set is a register bit mask, and the factor row
+// of step j is written into its storage row p_j during step j + 1, when no
+// thread reads row p_j any more (reads and the Schur update touch only
+// unselected rows and columns).  Row p_j then holds rjj at p_j, 0 at the
+// columns selected before p_j and S[p_j, q] / rjj elsewhere.  Stops after
+// rmax steps, at a non-positive pivot, or when
+//   mode 0: the largest remaining diagonal <= thr * (initial largest),
+//   mode 1: the remaining trace <= thr * (initial trace).
+// piv[j] = pivot of step j; *ref_out = the initial reference.  Returns the
+// rank (the same value in every thread).
+__device__ __forceinline__ void pchol_row(double* Sh, double* Sl, int K, int ls, int p, unsigned long long before,
+                                          dd rjj, dd rinv, bool use_dd) {
+  for (int q = threadIdx.x; q < K; q += HL_BLOCK) {
+    dd v;
+    if (q == p) {
+      v = rjj;
+    } else if ((before >> q) & 1ull) {
+      v = {0.0, 0.0};
+    } else {
+      const int a = min(p, q), b = max(p, q);
+      v = use_dd ? dd_mul({Sh[a * ls + b], Sl[a * ls + b]}, rinv) : dd{Sh[a * ls + b] * rinv.hi, 0.0};
+    }
+    Sh[p * ls + q] = v.hi;
+    Sl[p * ls + q] = v.lo;
+  }
+}
+
+__device__ int pchol_inplace(double* Sh, double* Sl, int K, int ls, int* piv, double* ref_out, int mode,
+                             double thr, int rmax, bool use_dd) {
   const int tid = threadIdx.x, lane = tid & 63;
-  if (tid < KMAX) sel[tid] = 0;
-  __syncthreads();
-  if (tid < 64) {
-    double d = lane < K ? Sh[lane * ks + lane] : 0.0;
+  double ref;
+  {
+    const double d = lane < K ? Sh[lane * ls + lane] : 0.0;
     double mx = d, sm = d;
     for (int o = 32; o > 0; o >>= 1) {
       mx = fmax(mx, __shfl_xor(mx, o, 64));
       sm += __shfl_xor(sm, o, 64);
     }
-    if (tid == 0) sdbl[0] = mode == 0 ? mx : sm;
+    ref = mode == 0 ? mx : sm;
   }
-  __syncthreads();
-  const double ref = sdbl[0];
-  int r = 0;
+  if (tid == 0) *ref_out = ref;
+  unsigned long long selm = 0ull;
+  int r = 0, pprev = -1;
+  dd rjj_prev{0.0, 0.0}, rinv_prev{0.0, 0.0};
   for (int j = 0; j < K && j < rmax; ++j) {
-    if (tid < 64) {
-      double vh = -1.0, vl = 0.0, tr = 0.0;
-      int idx = 0x7fffffff;
-      if (lane < K && !sel[lane]) {
-        vh = Sh[lane * ks + lane];
-        vl = use_dd ? Sl[lane * ks + lane] : 0.0;
-        idx = lane;
-        tr = vh;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        double oh = __shfl_xor(vh, o, 64), ol = __shfl_xor(vl, o, 64);
-        int oi = __shfl_xor(idx, o, 64);
-        tr += __shfl_xor(tr, o, 64);
-        if (oh > vh || (oh == vh && (ol > vl || (ol == vl && oi < idx)))) { vh = oh; vl = ol; idx = oi; }
-      }
-      if (tid == 0) {
-        bool stop = !(vh > 0.0) || idx >= K;
-        if (mode == 0) stop = stop || !(vh > thr * ref);
-        else stop = stop || !(tr > thr * ref);
-        sint[0] = stop ? -1 : idx;
-        if (!stop) { sel[idx] = 1; piv[j] = idx; }
+    if (pprev >= 0) {
+      pchol_row(Sh, Sl, K, ls, pprev, selm & ~(1ull << pprev), rjj_prev, rinv_prev, use_dd);
+      pprev = -1;
+    }
+    double vh = -1.0, vl = 0.0, tr = 0.0;
+    int idx = 0x7fffffff;
+    if (lane < K && !((selm >> lane) & 1ull)) {
+      vh = Sh[lane * ls + lane];
+      vl = use_dd ? Sl[lane * ls + lane] : 0.0;
+      idx = lane;
+      tr = vh;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double oh = __shfl_xor(vh, o, 64), ol = __shfl_xor(vl, o, 64);
+      const int oi = __shfl_xor(idx, o, 64);
+      tr += __shfl_xor(tr, o, 64);
+      if (oh > vh || (oh == vh && (ol > vl || (ol == vl && oi < idx)))) {
+        vh = oh;
+        vl = ol;
+        idx = oi;
       }
     }
-    __syncthreads();
-    const int p = sint[0];
-    if (p < 0) break;
-    const dd gpp = {Sh[p * ks + p], use_dd ? Sl[p * ks + p] : 0.0};
+    bool stop = !(vh > 0.0) || idx >= K;
+    stop = stop || (mode == 0 ? !(vh > thr * ref) : !(tr > thr * ref));
+    if (stop) break;
+    const int p = idx;
+    if (tid == 0) piv[j] = p;
+    selm |= 1ull << p;
+    const dd gpp = {Sh[p * ls + p], use_dd ? Sl[p * ls + p] : 0.0};
     const dd rjj = use_dd ? dd_sqrt(gpp) : dd{sqrt(gpp.hi), 0.0};
     const dd rinv = use_dd ? dd_div({1.0, 0.0}, rjj) : dd{1.0 / rjj.hi, 0.0};
-    for (int q = tid; q < K; q += HL_BLOCK) {
-      dd v;
-      const int a = min(p, q), b = max(p, q);
-      if (q == p) v = rjj;
-      else if (sel[q]) v = {0.0, 0.0};
-      else if (use_dd) v = dd_mul({Sh[a * ks + b], Sl[a * ks + b]}, rinv);
-      else v = {Sh[a * ks + b] * rinv.hi, 0.0};
-      rowh[q] = v.hi;
-      rowl[q] = v.lo;
-    }
-    __syncthreads();
-    for (int q1 = tid >> 4; q1 < K; q1 += 16) {
-      if (sel[q1]) continue;
-      const dd a = {rowh[q1], rowl[q1]};
+    // Schur complement of the unselected rows and columns (upper triangle)
+    for (int q1 = tid >> 4; q1 < K; q1 += HL_BLOCK / 16) {
+      if ((selm >> q1) & 1ull) continue;
+      const int a1 = min(p, q1), b1 = max(p, q1);
+      const dd x1 = use_dd ? dd_mul({Sh[a1 * ls + b1], Sl[a1 * ls + b1]}, rinv) : dd{Sh[a1 * ls + b1] * rinv.hi, 0.0};
       for (int q2 = q1 + (tid & 15); q2 < K; q2 += 16) {
-        if (sel[q2]) continue;
+        if ((selm >> q2) & 1ull) continue;
+        const int a2 = min(p, q2), b2 = max(p, q2);
         if (use_dd) {
-          dd gv = {Sh[q1 * ks + q2], Sl[q1 * ks + q2]};
-          gv = dd_add(gv, dd_neg(dd_mul(a, {rowh[q2], rowl[q2]})));
-          Sh[q1 * ks + q2] = gv.hi;
-          Sl[q1 * ks + q2] = gv.lo;
+          const dd x2 = dd_mul({Sh[a2 * ls + b2], Sl[a2 * ls + b2]}, rinv);
+          dd gv = {Sh[q1 * ls + q2], Sl[q1 * ls + q2]};
+          gv = dd_add(gv, dd_neg(dd_mul(x1, x2)));
+          Sh[q1 * ls + q2] = gv.hi;
+          Sl[q1 * ls + q2] = gv.lo;
         } else {
-          Sh[q1 * ks + q2] -= a.hi * rowh[q2];
+          Sh[q1 * ls + q2] -= x1.hi * (Sh[a2 * ls + b2] * rinv.hi);
         }
       }
     }
-    // the pivot row is no longer part of the Schur complement: it now holds
-    // row j of the factor (original column order)
-    for (int q = tid; q < K; q += HL_BLOCK) {
-      Sh[p * ks + q] = rowh[q];
-      Sl[p * ks + q] = rowl[q];
-    }
     __syncthreads();
+    pprev = p;
+    rjj_prev = rjj;
+    rinv_prev = rinv;
     r = j + 1;
   }
+  if (pprev >= 0) pchol_row(Sh, Sl, K, ls, pprev, selm & ~(1ull << pprev), rjj_prev, rinv_prev, use_dd);
   __syncthreads();
   return r;
 }
 
-__global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget* tg, const Term* terms,
-                                                              double tol, int ks) {
-  extern __shared__ double smem[];
-  double* Xh = smem;                 // G_B, then R_B (rows at pivot positions)
-  double* Xl = Xh + ks * ks;
-  double* Yh = Xl + ks * ks;         // G_A, then G_M / R_M
-  double* Yl = Yh + ks * ks;
-  double* Zh = Yl + ks * ks;         // T1 = G_A R_B^T (K x rB, row q col j at q * ks + j)
-  double* Zl = Zh + ks * ks;
-  __shared__ ColMap cm;
-  __shared__ int sel[KMAX], pivB[KMAX], pivM[KMAX];
-  __shared__ double rowh[KMAX], rowl[KMAX];
-  __shared__ int sint[4];
-  __shared__ double sdbl[4];
-  const LFlushTarget T = tg[blockIdx.x];
+// Steps 1-4 of the fast rounded addition on the Gram matrices G_A (in Y) and
+// G_B (in X), all with row stride ks (odd: no LDS bank conflicts between
+// rows); Y_U and Y_V (K x r, row q at q * RA_YS, zero beyond r) go to LDS.
+// Writes the target's info / rank and returns r.
+__device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int ks, double* Xh, double* Xl,
+                         double* Yh, double* Yl, double* Zh, double* Zl, double* YU, double* YV, int* pivB,
+                         int* pivM, double* sref) {
   const int tid = threadIdx.x;
-  const int kC = T.rank ? *T.rank : 0;
-  if (tid == 0) build_colmap(T, terms, kC, cm);
-  __syncthreads();
-  const int K = cm.K;
-  const int Kc = T.Kcap;
-  const int np = npairs(Kc);
   const bool use_dd = tol < 1e-9;
-  // Gram matrices (sum of the chunk partials), full symmetric storage
-  for (int side = 0; side < 2; ++side) {
-    double* Gh = side == 0 ? Yh : Xh;
-    double* Gl = side == 0 ? Yl : Xl;
-    const int nch = side == 0 ? T.nchA : T.nchB;
-    const double* src = T.ws + (size_t)(side == 0 ? 0 : T.nchA) * np * 2;
-    const int npk = npairs(K);
-    for (int idx = tid; idx < npk; idx += HL_BLOCK) {
-      int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-      while (q * (q + 1) / 2 > idx) --q;
-      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
-      const int p = idx - q * (q + 1) / 2;
-      dd s = {src[2 * idx], src[2 * idx + 1]};
-      for (int c = 1; c < nch; c += 4) {
-        double h[4], l[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          h[u] = 0.0;
-          l[u] = 0.0;
-          if (c + u < nch) {
-            h[u] = src[(size_t)(c + u) * np * 2 + 2 * idx];
-            l[u] = src[(size_t)(c + u) * np * 2 + 2 * idx + 1];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s = dd_add(s, {h[u], l[u]});
-      }
-      Gh[p * ks + q] = s.hi;
-      Gl[p * ks + q] = s.lo;
-      Gh[q * ks + p] = s.hi;
-      Gl[q * ks + p] = s.lo;
-    }
-  }
-  __syncthreads();
   // 1. G_B = R_B^T R_B; directions below 1e-2 tol of the largest are dropped
   const double cut = fmax(1e-16, 1e-2 * tol);
-  const int rB = pchol_inplace(Xh, Xl, K, ks, sel, pivB, rowh, rowl, sint, sdbl, 0, fmax(cut * cut, 1e-32),
-                               KMAX, use_dd);
+  const int rB = pchol_inplace(Xh, Xl, K, ks, pivB, sref, 0, fmax(cut * cut, 1e-32), KMAX, use_dd);
   // 2. T1[q][j] = sum_p G_A[q][p] R_B[j][p]
   for (int e = tid; e < K * rB; e += HL_BLOCK) {
     const int q = e / rB, j = e - q * rB;
@@ -966,15 +966,17 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
   }
   __syncthreads();
   // 3. rank-revealing Cholesky of G_M with the truncation tolerance
-  const int r = pchol_inplace(Yh, Yl, rB, ks, sel, pivM, rowh, rowl, sint, sdbl, 1, tol * tol, T.kcap, use_dd);
+  const int r = pchol_inplace(Yh, Yl, rB, ks, pivM, sref + 1, 1, tol * tol, T.kcap, use_dd);
   if (tid == 0) {
     int ovf = 0;
     if (r == T.kcap && r < rB) {
       // capacity reached: flag it if the remaining trace still exceeds the tolerance
+      unsigned long long sel = 0ull;
+      for (int c = 0; c < r; ++c) sel |= 1ull << pivM[c];
       double tr = 0.0;
       for (int q = 0; q < rB; ++q)
-        if (!sel[q]) tr += Yh[q * ks + q];
-      ovf = tr > tol * tol * sdbl[0] ? 1 : 0;
+        if (!((sel >> q) & 1ull)) tr += Yh[q * ks + q];
+      ovf = tr > tol * tol * sref[1] ? 1 : 0;
     }
     T.info[0] = kC;
     T.info[1] = r;
@@ -982,25 +984,124 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
     if (ovf && T.overflow) atomicAdd(T.overflow, 1);
     if (T.rank) *T.rank = r;
   }
-  // 4. Y_U^T = R_MJ^{-T} R_B[J,:]  and  Y_V = T1[:, J] R_MJ^{-1}, column by
-  //    column (R_MJ[i][c] = row pivM[i] of the in-place factor at column pivM[c])
-  double* YU = T.ws + (size_t)(T.nchA + T.nchB) * np * 2;
-  double* YV = YU + (size_t)Kc * T.kcap;
-  for (int c = 0; c < r; ++c) {
-    const double dinv = 1.0 / Yh[pivM[c] * ks + pivM[c]];
-    for (int q = tid; q < K; q += HL_BLOCK) {
-      // row q of Y_U, column c
-      double u = Xh[pivB[pivM[c]] * ks + q];
-      double v = Zh[q * ks + pivM[c]];
+  // 4. Y_U^T = R_MJ^{-T} R_B[J,:]  and  Y_V = T1[:, J] R_MJ^{-1}; each thread
+  //    solves for its own rows q (R_MJ[i][c] = row pivM[i] of the in-place
+  //    factor at column pivM[c]), no barrier between the columns
+  for (int q = tid; q < K; q += HL_BLOCK) {
+    double* yu = YU + q * RA_YS;
+    double* yv = YV + q * RA_YS;
+    for (int c = 0; c < r; ++c) {
+      const int pc = pivM[c];
+      const double dinv = 1.0 / Yh[pc * ks + pc];
+      double u = Xh[pivB[pc] * ks + q];
+      double v = Zh[q * ks + pc];
       for (int i = 0; i < c; ++i) {
-        const double rmic = Yh[pivM[i] * ks + pivM[c]];
-        u -= rmic * YU[q + (size_t)Kc * i];
-        v -= rmic * YV[q + (size_t)Kc * i];
+        const double rmic = Yh[pivM[i] * ks + pc];
+        u -= rmic * yu[i];
+        v -= rmic * yv[i];
       }
-      YU[q + (size_t)Kc * c] = u * dinv;
-      YV[q + (size_t)Kc * c] = v * dinv;
+      yu[c] = u * dinv;
+      yv[c] = v * dinv;
     }
-    __syncthreads();
+    for (int c = r; c < RA_YS; ++c) {
+      yu[c] = 0.0;
+      yv[c] = 0.0;
+    }
+  }
+  __syncthreads();
+  return r;
+}
+
+// LDS of the core for concatenations of at most ks columns: six (ks + 1)^2
+// matrices (row stride ks + 1) and Y_U, Y_V
+__host__ __device__ inline size_t radd_core_lds(int ks) {
+  return (6 * (size_t)(ks + 1) * (ks + 1) + 2 * (size_t)ks * RA_YS) * sizeof(double);
+}
+
+// Gram sums of the chunk partials (k_flush_gram) -> radd_core -> Y_U, Y_V to
+// the target's workspace for k_flush_expand.  Dynamic LDS: radd_core_lds(ks).
+__global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget* tg, const Term* terms,
+                                                              double tol, int ks) {
+  extern __shared__ double smem[];
+  const int ls = ks + 1;             // row stride of the LDS matrices
+  double* Xh = smem;                 // G_B, then R_B (rows at pivot positions)
+  double* Xl = Xh + ls * ls;
+  double* Yh = Xl + ls * ls;         // G_A, then G_M / R_M
+  double* Yl = Yh + ls * ls;
+  double* Zh = Yl + ls * ls;         // T1 = G_A R_B^T (K x rB, row q col j at q * ls + j)
+  double* Zl = Zh + ls * ls;
+  double* YU = Zl + ls * ls;
+  double* YV = YU + ks * RA_YS;
+  __shared__ ColMap cm;
+  __shared__ int pivB[KMAX], pivM[KMAX];
+  __shared__ double sref[2];
+  const LFlushTarget T = tg[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int kC = T.rank ? *T.rank : 0;
+  if (tid == 0) build_colmap(T, terms, kC, cm);
+  __syncthreads();
+  const int K = cm.K;
+  const int Kc = T.Kcap;
+  const int np = npairs(Kc);
+  // Gram matrices (sum of the chunk partials), full symmetric storage
+  for (int side = 0; side < 2; ++side) {
+    double* Gh = side == 0 ? Yh : Xh;
+    double* Gl = side == 0 ? Yl : Xl;
+    const int nch = side == 0 ? T.nchA : T.nchB;
+    const double* src = T.ws + (size_t)(side == 0 ? 0 : T.nchA) * np * 2;
+    const int npk = npairs(K);
+    for (int idx = tid; idx < npk; idx += HL_BLOCK) {
+      int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (q * (q + 1) / 2 > idx) --q;
+      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
+      const int p = idx - q * (q + 1) / 2;
+      dd s = {src[2 * idx], src[2 * idx + 1]};
+      for (int c = 1; c < nch; c += 4) {
+        double h[4], l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          h[u] = 0.0;
+          l[u] = 0.0;
+          if (c + u < nch) {
+            h[u] = src[(size_t)(c + u) * np * 2 + 2 * idx];
+            l[u] = src[(size_t)(c + u) * np * 2 + 2 * idx + 1];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = dd_add(s, {h[u], l[u]});
+      }
+      Gh[p * ls + q] = s.hi;
+      Gl[p * ls + q] = s.lo;
+      Gh[q * ls + p] = s.hi;
+      Gl[q * ls + p] = s.lo;
+    }
+  }
+  __syncthreads();
+  radd_core(T, kC, K, tol, ls, Xh, Xl, Yh, Yl, Zh, Zl, YU, YV, pivB, pivM, sref);
+  // Y_U, Y_V (K x RA_YS each) to the workspace
+  double* dst = T.ws + (size_t)(T.nchA + T.nchB) * np * 2;
+  for (int e = tid; e < 2 * K * RA_YS; e += HL_BLOCK) dst[e] = e < K * RA_YS ? YU[e] : YV[e - K * RA_YS];
+}
+
+// new factor rows: out[row, c] = sum_j side(row, j) Y[j, c], c < r (row-local:
+// the rows read and written belong to this thread, so in-place is safe)
+__device__ __forceinline__ void radd_expand_rows(const LFlushTarget& T, const Term* terms, const ColMap& cm, int side,
+                                                 int r0, int r1, const double* Y, int r) {
+  double* out = side == 0 ? T.U : T.V;
+  const int ld = side == 0 ? T.m : T.n;
+  const int K = cm.K;
+  for (int row = r0 + threadIdx.x; row < r1; row += HL_BLOCK) {
+    double acc[RA_YS];
+#pragma unroll
+    for (int c = 0; c < RA_YS; ++c) acc[c] = 0.0;
+    for (int j = 0; j < K; ++j) {
+      const double a = side_val(T, terms, cm, side, row, j);
+#pragma unroll
+      for (int c = 0; c < RA_YS; ++c) acc[c] += a * Y[j * RA_YS + c];
+    }
+#pragma unroll
+    for (int c = 0; c < RA_YS; ++c)
+      if (c < r) out[row + (size_t)ld * c] = acc[c];
   }
 }
 
@@ -1008,7 +1109,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
 __global__ void __launch_bounds__(HL_BLOCK) k_flush_expand(const LFlushTarget* tg, const Term* terms,
                                                            const ChunkItem* items) {
   __shared__ ColMap cm;
-  __shared__ double Y[KMAX * 32];
+  __shared__ double Y[KMAX * RA_YS];
   const ChunkItem it = items[blockIdx.x];
   const LFlushTarget T = tg[it.tgt];
   const int kC = T.info[0], r = T.info[1];
@@ -1016,20 +1117,193 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_expand(const LFlushTarget* t
   __syncthreads();
   const int K = cm.K, Kc = T.Kcap;
   const int np = npairs(Kc);
-  const double* Ys = T.ws + (size_t)(T.nchA + T.nchB) * np * 2 + (it.side == 0 ? 0 : (size_t)Kc * T.kcap);
-  for (int e = threadIdx.x; e < K * r; e += HL_BLOCK) Y[e] = Ys[(e % K) + (size_t)Kc * (e / K)];
+  const double* Ys = T.ws + (size_t)(T.nchA + T.nchB) * np * 2 + (it.side == 0 ? 0 : (size_t)K * RA_YS);
+  for (int e = threadIdx.x; e < K * RA_YS; e += HL_BLOCK) Y[e] = Ys[e];
   __syncthreads();
-  double* out = it.side == 0 ? T.U : T.V;
-  const int ld = it.side == 0 ? T.m : T.n;
-  for (int row = it.r0 + threadIdx.x; row < it.r1; row += HL_BLOCK) {
-    double acc[32];
-    for (int c = 0; c < 32; ++c) acc[c] = 0.0;
-    for (int j = 0; j < K; ++j) {
-      double a = side_val(T, terms, cm, it.side, row, j);
-      for (int c = 0; c < r; ++c) acc[c] += a * Y[j + K * c];
+  radd_expand_rows(T, terms, cm, it.side, it.r0, it.r1, Y, r);
+}
+
+// Column sources of the concatenated factors of a target (side 0: U side,
+// side 1: V side): column j is sign * p[row - off] for row - off in [0, len),
+// zero elsewhere.
+struct RaddCols {
+  const double* p[2][KMAX];
+  int off[2][KMAX], len[2][KMAX];
+  double sign[2][KMAX];
+};
+
+__device__ void radd_cols(const LFlushTarget& T, const Term* terms, const ColMap& cm, RaddCols& cs) {
+  for (int e = threadIdx.x; e < 2 * cm.K; e += HL_BLOCK) {
+    const int side = e / cm.K, j = e - side * cm.K;
+    if (j < cm.kC) {
+      cs.p[side][j] = side == 0 ? T.U + (size_t)T.m * j : T.V + (size_t)T.n * j;
+      cs.off[side][j] = 0;
+      cs.len[side][j] = side == 0 ? T.m : T.n;
+      cs.sign[side][j] = 1.0;
+    } else {
+      int t = 0;
+      while (j >= cm.off[t + 1]) ++t;
+      const Term& tm = terms[T.tbeg + cm.tb + t];
+      const int c = j - cm.off[t];
+      cs.p[side][j] = side == 0 ? tm.U + (size_t)tm.ldu * c : tm.W + (size_t)tm.ldw * c;
+      cs.off[side][j] = side == 0 ? tm.ro : tm.co;
+      cs.len[side][j] = side == 0 ? tm.mr : tm.nc;
+      cs.sign[side][j] = side == 0 ? tm.sign : 1.0;
     }
-    for (int c = 0; c < r; ++c) out[row + (size_t)ld * c] = acc[c];
   }
+}
+
+// rows [base, base + 64) of one side, all K columns, into tile[rr + 64 j]
+// (zero past the rows); all loads of a thread are issued before any store
+__device__ __forceinline__ void radd_load_tile(const RaddCols& cs, int side, int base, int rows, int K,
+                                               double* tile) {
+  constexpr int NE = 64 * KMAX / HL_BLOCK;
+  double v[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = threadIdx.x + u * HL_BLOCK;
+    const int rr = e & 63, j = e >> 6;
+    const int jj = j < K ? j : 0;
+    const int len = cs.len[side][jj];
+    int i = base + rr - cs.off[side][jj];
+    const bool ok = j < K && rr < rows && i >= 0 && i < len;
+    i = min(max(i, 0), len - 1);   // every column has len >= 1: the load stays in bounds
+    const double x = cs.p[side][jj][i];
+    v[u] = ok ? cs.sign[side][jj] * x : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = threadIdx.x + u * HL_BLOCK;
+    if ((e >> 6) < K) tile[e] = v[u];
+  }
+}
+
+// Whole rounded additions in one workgroup for a target of at most
+// GRAM_CHUNK rows on each side and any number of terms: the terms are taken
+// in concatenations of at most ks columns (actual ranks, known only here),
+// each one a rounded addition into the target: Gram matrices straight from
+// the factors, radd_core, then the new factors in place, 64 rows at a time
+// (a row block is staged in LDS before any of its rows is overwritten).
+// Dynamic LDS: radd_fused_lds(ks).
+__global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg, const Term* terms, double tol,
+                                                         int ks) {
+  extern __shared__ double smem[];
+  const int ls = ks + 1;   // row stride of the LDS matrices
+  double* Xh = smem;
+  double* Xl = Xh + ls * ls;
+  double* Yh = Xl + ls * ls;
+  double* Yl = Yh + ls * ls;
+  double* Zh = Yl + ls * ls;
+  double* Zl = Zh + ls * ls;
+  double* YU = Zl + ls * ls;
+  double* YV = YU + ks * RA_YS;
+  double* tile = Zh;   // 64 x K: Z holds 2 ls^2 >= 64 ks doubles (ks >= 32)
+  __shared__ ColMap cm;
+  __shared__ RaddCols cs;
+  __shared__ int pivB[KMAX], pivM[KMAX];
+  __shared__ double sref[2];
+  const LFlushTarget T = tg[blockIdx.x];
+  const int tid = threadIdx.x;
+  const bool use_dd = tol < 1e-9;
+  constexpr int PPT = (KMAX * (KMAX + 1) / 2 + HL_BLOCK - 1) / HL_BLOCK;
+  int r = T.rank ? *T.rank : 0;
+  // the term list in concatenations of at most ks columns, each one a whole
+  // rounded addition into the target
+  for (int t0 = 0; t0 < T.tcount;) {
+    __syncthreads();
+    if (tid == 0) build_colmap_chunk(T, terms, r, t0, ks, cm);
+    __syncthreads();
+    const int K = cm.K, kC = r;
+    if (K > ks) {
+      // a single term wider than the LDS matrices (excluded by the planner):
+      // flag it and leave the target
+      if (tid == 0) {
+        T.info[2] = 1;
+        if (T.overflow) atomicAdd(T.overflow, 1);
+      }
+      break;
+    }
+    radd_cols(T, terms, cm, cs);
+    const int np = npairs(K);
+    int pp[PPT], qq[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int idx = tid + u * HL_BLOCK;
+      pp[u] = qq[u] = 0;
+      if (idx < np) {
+        int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+        while (q * (q + 1) / 2 > idx) --q;
+        while ((q + 1) * (q + 2) / 2 <= idx) ++q;
+        pp[u] = idx - q * (q + 1) / 2;
+        qq[u] = q;
+      }
+    }
+    for (int side = 0; side < 2; ++side) {
+      const int len = side == 0 ? T.m : T.n;
+      dd accv[PPT];
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) accv[u] = {0.0, 0.0};
+      for (int base = 0; base < len; base += 64) {
+        __syncthreads();
+        radd_load_tile(cs, side, base, min(64, len - base), K, tile);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+          if (tid + u * HL_BLOCK >= np) continue;
+          const double* a = tile + 64 * pp[u];
+          const double* b = tile + 64 * qq[u];
+          if (use_dd) {
+            dd acc = accv[u];
+            for (int rr = 0; rr < 64; ++rr) acc = dd_add(acc, dd_mul_d(a[rr], b[rr]));
+            accv[u] = acc;
+          } else {
+            double acc = accv[u].hi;
+#pragma unroll 8
+            for (int rr = 0; rr < 64; ++rr) acc += a[rr] * b[rr];
+            accv[u].hi = acc;
+          }
+        }
+      }
+      double* Gh = side == 0 ? Yh : Xh;
+      double* Gl = side == 0 ? Yl : Xl;
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        if (tid + u * HL_BLOCK >= np) continue;
+        Gh[pp[u] * ls + qq[u]] = accv[u].hi;
+        Gl[pp[u] * ls + qq[u]] = accv[u].lo;
+        Gh[qq[u] * ls + pp[u]] = accv[u].hi;
+        Gl[qq[u] * ls + pp[u]] = accv[u].lo;
+      }
+    }
+    __syncthreads();
+    r = radd_core(T, kC, K, tol, ls, Xh, Xl, Yh, Yl, Zh, Zl, YU, YV, pivB, pivM, sref);
+    // new factors: U_new = A Y_U, V_new = B Y_V
+    for (int side = 0; side < 2; ++side) {
+      const int len = side == 0 ? T.m : T.n;
+      double* out = side == 0 ? T.U : T.V;
+      const double* Y = side == 0 ? YU : YV;
+      for (int base = 0; base < len; base += 64) {
+        const int rows = min(64, len - base);
+        __syncthreads();
+        radd_load_tile(cs, side, base, rows, K, tile);
+        __syncthreads();
+        for (int o = tid; o < 64 * RA_YS; o += HL_BLOCK) {
+          const int rr = o & 63, c = o >> 6;
+          if (c >= r || rr >= rows) continue;
+          double acc = 0.0;
+          for (int j = 0; j < K; ++j) acc += tile[rr + 64 * j] * Y[j * RA_YS + c];
+          out[(base + rr) + (size_t)len * c] = acc;
+        }
+      }
+    }
+    t0 += cm.nt;
+  }
+}
+
+__host__ __device__ inline size_t radd_fused_lds(int ks) {
+  // the Gram tile (64 x ks) lives in Z (2 ks^2 doubles): ks >= 32
+  const int k = ks < 32 ? 32 : ks;
+  return radd_core_lds(k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1548,13 +1822,19 @@ hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, c
   if (ntg == 0) return hipSuccess;
   hipLaunchKernelGGL(k_flush_gram, dim3(ngram), dim3(HL_BLOCK), 0, s, tg, terms, gram);
   if (ks <= 48) {
-    size_t shm = 6 * (size_t)ks * ks * sizeof(double);
-    hipLaunchKernelGGL(k_flush_core_fast, dim3(ntg), dim3(HL_BLOCK), shm, s, tg, terms, tol, ks);
+    hipLaunchKernelGGL(k_flush_core_fast, dim3(ntg), dim3(HL_BLOCK), radd_core_lds(ks), s, tg, terms, tol, ks);
   } else {
     size_t shm = (4 * (size_t)ks * ks + 2 * (size_t)ks) * sizeof(double);
     hipLaunchKernelGGL(k_flush_core, dim3(ntg), dim3(HL_BLOCK), shm, s, tg, terms, tol, ks);
   }
   hipLaunchKernelGGL(k_flush_expand, dim3(nexp), dim3(HL_BLOCK), 0, s, tg, terms, expand);
+  return post();
+}
+hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s) {
+  if (ntg == 0) return hipSuccess;
+  if (ks > 48) return hipErrorInvalidValue;
+  const int k = ks < 32 ? 32 : ks;
+  hipLaunchKernelGGL(k_radd_fused, dim3(ntg), dim3(HL_BLOCK), radd_fused_lds(ks), s, tg, terms, tol, k);
   return post();
 }
 hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms, hipStream_t s) {
@@ -1627,7 +1907,10 @@ hipError_t launch_densify(const LeafDesc* L, const int32_t* rank, int nleaves, c
 namespace hl {
 hipError_t init_kernel_attributes() {
   hipError_t e = hipFuncSetAttribute((const void*)k_flush_core_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     6 * 48 * 48 * (int)sizeof(double));
+                                     (int)radd_core_lds(48));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_radd_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)radd_fused_lds(48));
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_lu_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)luinv_lds_bytes());

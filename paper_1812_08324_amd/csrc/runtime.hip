@@ -235,7 +235,7 @@ struct DevStructure {
 // ---------------------------------------------------------------------------
 // plan: phases over item arrays, built on the host, uploaded once
 // ---------------------------------------------------------------------------
-enum PhaseType { PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF, PH_LUINV };
+enum PhaseType { PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF, PH_LUINV, PH_RADD };
 
 struct Phase {
   int type;
@@ -298,6 +298,9 @@ struct Plan {
         case PH_GETRF:
           HL_CHECK(launch_getrf_inv(dgetrf.as<GetrfItem>() + p.b0, p.n0, zero_pivot, s));
           break;
+        case PH_RADD:
+          HL_CHECK(launch_radd_fused(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(), p.tol, p.ks, s));
+          break;
         case PH_LUINV:
           HL_CHECK(launch_lu_inv(dluinv.as<LuInvItem>() + p.b0, p.n0, zero_pivot, s));
           break;
@@ -323,7 +326,7 @@ static void add_chunks(Plan& P, int t, int m, int n, LFlushTarget& T, int gram_b
 }
 
 static size_t flush_ws_doubles(const LFlushTarget& T) {
-  return (size_t)(T.nchA + T.nchB) * npairs_host(T.Kcap) * 2 + (size_t)2 * T.Kcap * T.kcap;
+  return (size_t)(T.nchA + T.nchB) * npairs_host(T.Kcap) * 2 + (size_t)2 * T.Kcap * 32;
 }
 
 // ---------------------------------------------------------------------------
@@ -472,16 +475,41 @@ struct Builder {
     }
   }
 
-  // Emit rounded additions for the given targets, one phase per width
-  // bucket (16, 32, 48, 64 columns) so that the LDS of the core kernel is
-  // sized to the bucket.  Returns each target's index in P.ltg.
+  // Emit rounded additions for the given targets.  Targets of at most
+  // GRAM_CHUNK rows on both sides and at most 48 columns in all go to one
+  // fused launch; the others get one phase per width bucket (16, 32, 48, 64
+  // columns) so that the LDS of the core kernel is sized to the bucket.
+  // Returns each target's index in P.ltg.
   std::vector<int> emit_lflush(std::vector<LFlushTarget>& tgs, std::vector<std::vector<Term>>& tlists,
                                double ftol) {
     std::vector<int> where(tgs.size(), -1);
+    std::vector<size_t> fused;
+    int fks = 16;
+    for (size_t q = 0; q < tgs.size(); ++q)
+      if (tgs[q].m <= GRAM_CHUNK && tgs[q].n <= GRAM_CHUNK && tgs[q].Kcap <= 48) {
+        fused.push_back(q);
+        fks = std::max(fks, (tgs[q].Kcap + 15) / 16 * 16);
+      }
+    if (!fused.empty()) {
+      Phase ph{PH_RADD, (int)P.ltg.size(), (int)fused.size(), 0, 0, 0, 0, ftol, fks};
+      for (size_t q : fused) {
+        LFlushTarget T = tgs[q];
+        T.tbeg = (int)P.terms.size();
+        T.tcount = (int)tlists[q].size();
+        for (auto& tm : tlists[q]) P.terms.push_back(tm);
+        T.nchA = T.nchB = 1;
+        T.ws = nullptr;
+        T.info = ws.alloc_i(4);
+        T.overflow = overflow;
+        where[q] = (int)P.ltg.size();
+        P.ltg.push_back(T);
+      }
+      P.ph.push_back(ph);
+    }
     for (int bucket = 16; bucket <= KMAX; bucket += 16) {
       std::vector<size_t> sel;
       for (size_t q = 0; q < tgs.size(); ++q)
-        if (tgs[q].Kcap <= bucket && tgs[q].Kcap > bucket - 16) sel.push_back(q);
+        if (where[q] < 0 && tgs[q].Kcap <= bucket && tgs[q].Kcap > bucket - 16) sel.push_back(q);
       if (sel.empty()) continue;
       Phase ph{PH_LFLUSH, (int)P.ltg.size(), (int)sel.size(), (int)P.lgram.size(), 0, (int)P.lexp.size(), 0,
                ftol, bucket};
@@ -503,6 +531,17 @@ struct Builder {
       P.ph.push_back(ph);
     }
     return where;
+  }
+
+  // A low-rank target whose rounded additions all run in one fused launch:
+  // at most GRAM_CHUNK rows per side, rank capacity <= 16 and every term of
+  // rank capacity <= 32, so that each concatenation of the fused kernel stays
+  // within 48 columns (called after the dense terms became low-rank terms).
+  bool fused_target(const LeafDesc& d, const std::vector<PendingTerm>& terms) const {
+    if (d.kind != K_LR || d.m > GRAM_CHUNK || d.n > GRAM_CHUNK || d.kcap > 16) return false;
+    for (const auto& pt : terms)
+      if (pt.t.dense || pt.kcap > 32) return false;
+    return true;
   }
 
   void end() {
@@ -562,18 +601,19 @@ struct Builder {
         }
       }
       if (!comps.empty()) {
-        // the temporary targets start empty: their rank counters are zeroed
-        // by the first round (which ignores them) and then carried forward
-        for (int half = 0; half < 2; ++half) {
-          std::vector<LFlushTarget> tgs;
-          std::vector<std::vector<Term>> tl;
-          for (auto& c : comps) {
-            const int nc = c.src.nc;
-            const int c0 = half * 32, c1 = std::min(nc, c0 + 32);
-            if (c0 >= c1) continue;
-            LFlushTarget T = c.T;
-            if (half == 0) T.rank = nullptr;   // start empty; the new rank goes to info[1]
-            T.Kcap = (half == 0 ? 0 : c.kc) + (c1 - c0);
+        // every temporary in one fused launch: it starts empty (rank pointer
+        // null, the kernel keeps the rank and leaves it in info[1]) and takes
+        // the dense block as terms P[:, c0:c1] I^T of w columns, kc + w <= 48
+        std::vector<LFlushTarget> tgs;
+        std::vector<std::vector<Term>> tl;
+        for (auto& c : comps) {
+          LFlushTarget T = c.T;
+          T.rank = nullptr;
+          T.Kcap = 48;
+          const int w = c.kc <= 16 ? 32 : 16;
+          std::vector<Term> terms;
+          for (int c0 = 0; c0 < c.src.nc; c0 += w) {
+            const int c1 = std::min(c.src.nc, c0 + w);
             Term lt{};
             lt.dense = 0;
             lt.ro = 0;
@@ -586,20 +626,18 @@ struct Builder {
             lt.ldw = 64;
             lt.kfix = c1 - c0;
             lt.sign = 1.0;
-            tgs.push_back(T);
-            tl.push_back({lt});
+            terms.push_back(lt);
           }
-          std::vector<int> where = emit_lflush(tgs, tl, tol);
-          // after the first round the rank of each temporary is in info[1]:
-          // copy the pointer so that the second round reads it as its rank
-          size_t q = 0;
-          for (auto& c : comps) {
-            const int c0 = half * 32;
-            if (c0 >= std::min(c.src.nc, c0 + 32)) continue;
-            if (half == 0) c.T.rank = P.ltg[where[q]].info + 1;
-            ++q;
-          }
+          tgs.push_back(T);
+          tl.push_back(terms);
         }
+        std::vector<int> where = emit_lflush(tgs, tl, tol);
+        for (size_t q = 0; q < comps.size(); ++q) {
+          if (P.ltg[where[q]].ws != nullptr) throw DeviceError("internal: dense compression outside the fused kernel");
+          comps[q].T.rank = P.ltg[where[q]].info + 1;
+        }
+      }
+      if (!comps.empty()) {
         // rewrite those dense terms as low-rank terms on the compressed factors
         size_t q = 0;
         for (auto& kv : pending) {
@@ -643,6 +681,23 @@ struct Builder {
         int leaf = kv.first.second;
         const LeafDesc& d = C->L[leaf];
         if (d.kind != K_LR) continue;
+        if (fused_target(d, kv.second)) {
+          // one fused target with the whole term list (dense terms were
+          // compressed to low-rank temporaries above)
+          LFlushTarget T{};
+          T.U = d.A;
+          T.V = d.B;
+          T.rank = C->rank + leaf;
+          T.m = d.m;
+          T.n = d.n;
+          T.kcap = d.kcap;
+          T.Kcap = 48;
+          std::vector<Term> tl;
+          for (auto& pt : kv.second) tl.push_back(pt.t);
+          if (rounds.empty()) rounds.resize(1);
+          rounds[0].push_back({T, tl});
+          continue;
+        }
         size_t q = 0, rd = 0;
         while (q < kv.second.size()) {
           LFlushTarget T{};
@@ -1272,24 +1327,27 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
         HMat& src = side == 0 ? Li : Ui;
         HMat& dst = side == 0 ? f->Li : f->Ui;
         B.copy_node(&dst, &src, 0, 1.0, false, /*skip_compress=*/true);
-        // 32 columns per round, so that every rounded addition stays within
-        // 48 columns (the targets start at rank 0)
-        for (int c0 = 0; c0 < 64; c0 += 32) {
-          std::vector<LFlushTarget> tgs;
-          std::vector<std::vector<Term>> tl;
-          for (size_t l = 0; l < S.lf.size(); ++l) {
-            const LeafDesc& d = dst.L[l];
-            if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
-            const int c1 = std::min(d.n, c0 + 32);
-            if (c0 >= c1) continue;
-            LFlushTarget T{};
-            T.U = d.A;
-            T.V = d.B;
-            T.rank = dst.rank + l;
-            T.m = d.m;
-            T.n = d.n;
-            T.kcap = d.kcap;
-            T.Kcap = (c0 == 0 ? 0 : d.kcap) + (c1 - c0);
+        // one target per block with its dense content as 32-column terms
+        // (the fused rounded addition takes them one concatenation at a time;
+        // the targets start at rank 0)
+        std::vector<LFlushTarget> tgs;
+        std::vector<std::vector<Term>> tl;
+        for (size_t l = 0; l < S.lf.size(); ++l) {
+          const LeafDesc& d = dst.L[l];
+          if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
+          LFlushTarget T{};
+          T.U = d.A;
+          T.V = d.B;
+          T.rank = dst.rank + l;
+          T.m = d.m;
+          T.n = d.n;
+          T.kcap = d.kcap;
+          T.Kcap = 48;
+          std::vector<Term> terms;
+          const int w = d.kcap <= 16 ? 32 : 16;   // kcap + w <= 48
+          if (d.kcap > 32) throw DeviceError("internal: rank capacity above 32");
+          for (int c0 = 0; c0 < d.n; c0 += w) {
+            const int c1 = std::min(d.n, c0 + w);
             Term tm{};
             tm.dense = 0;
             tm.ro = 0;
@@ -1302,11 +1360,12 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
             tm.ldw = 64;
             tm.kfix = c1 - c0;
             tm.sign = 1.0;
-            tgs.push_back(T);
-            tl.push_back({tm});
+            terms.push_back(tm);
           }
-          B.emit_lflush(tgs, tl, lu_tol);
+          tgs.push_back(T);
+          tl.push_back(terms);
         }
+        B.emit_lflush(tgs, tl, lu_tol);
       }
       const double t1 = now_s();
       P.upload_all(s);
