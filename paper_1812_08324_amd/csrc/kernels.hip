@@ -819,7 +819,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
 // Cholesky factor is written into the storage row of its pivot.
 // One barrier per step: every wavefront selects the pivot itself from the
 // remaining diagonal (largest, ties to the lowest index; identical in all
-// wavefronts), the selected set is a register bit mask, and the factor row
+// wavefronts: a DPP max-reduction and a ballot), the selected set is a register bit mask, and the factor row
 // of step j is written into its storage row p_j during step j + 1, when no
 // thread reads row p_j any more (reads and the Schur update touch only
 // unselected rows and columns).  Row p_j then holds rjj at p_j, 0 at the
@@ -846,18 +846,45 @@ __device__ __forceinline__ void pchol_row(double* Sh, double* Sl, int K, int ls,
   }
 }
 
+// Wavefront reductions with DPP moves inside each 16-lane row (quad
+// permutations, then row rotations by 4 and 8) and readlane across the four
+// rows; every lane gets the same value, computed in the same order in every
+// wavefront.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double rdlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));    // quad_perm 1,0,3,2
+  v = fmax(v, dpp_d<0x4E>(v));    // quad_perm 2,3,0,1
+  v = fmax(v, dpp_d<0x124>(v));   // row_ror 4
+  v = fmax(v, dpp_d<0x128>(v));   // row_ror 8: every lane holds its row maximum
+  return fmax(fmax(rdlane_d(v, 0), rdlane_d(v, 16)), fmax(rdlane_d(v, 32), rdlane_d(v, 48)));
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x128>(v);   // lane 16 i holds the sum of row i
+  return (rdlane_d(v, 0) + rdlane_d(v, 16)) + (rdlane_d(v, 32) + rdlane_d(v, 48));
+}
+
 __device__ int pchol_inplace(double* Sh, double* Sl, int K, int ls, int* piv, double* ref_out, int mode,
                              double thr, int rmax, bool use_dd) {
   const int tid = threadIdx.x, lane = tid & 63;
   double ref;
   {
     const double d = lane < K ? Sh[lane * ls + lane] : 0.0;
-    double mx = d, sm = d;
-    for (int o = 32; o > 0; o >>= 1) {
-      mx = fmax(mx, __shfl_xor(mx, o, 64));
-      sm += __shfl_xor(sm, o, 64);
-    }
-    ref = mode == 0 ? mx : sm;
+    ref = mode == 0 ? wave_max_dpp(d) : wave_sum_dpp(d);
   }
   if (tid == 0) *ref_out = ref;
   unsigned long long selm = 0ull;
@@ -868,28 +895,22 @@ __device__ int pchol_inplace(double* Sh, double* Sl, int K, int ls, int* piv, do
       pchol_row(Sh, Sl, K, ls, pprev, selm & ~(1ull << pprev), rjj_prev, rinv_prev, use_dd);
       pprev = -1;
     }
-    double vh = -1.0, vl = 0.0, tr = 0.0;
-    int idx = 0x7fffffff;
-    if (lane < K && !((selm >> lane) & 1ull)) {
-      vh = Sh[lane * ls + lane];
-      vl = use_dd ? Sl[lane * ls + lane] : 0.0;
-      idx = lane;
-      tr = vh;
+    // pivot: the largest remaining diagonal (double-double: then the
+    // largest low part), ties to the lowest index
+    const bool un = lane < K && !((selm >> lane) & 1ull);
+    const double vh = un ? Sh[lane * ls + lane] : -1.0;
+    const double mx = wave_max_dpp(vh);
+    unsigned long long cand = __ballot(un && vh == mx);
+    if (use_dd) {
+      const double vl = un ? Sl[lane * ls + lane] : 0.0;
+      const double ml = wave_max_dpp(((cand >> lane) & 1ull) ? vl : -INFINITY);
+      cand &= __ballot(vl == ml);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double oh = __shfl_xor(vh, o, 64), ol = __shfl_xor(vl, o, 64);
-      const int oi = __shfl_xor(idx, o, 64);
-      tr += __shfl_xor(tr, o, 64);
-      if (oh > vh || (oh == vh && (ol > vl || (ol == vl && oi < idx)))) {
-        vh = oh;
-        vl = ol;
-        idx = oi;
-      }
-    }
-    bool stop = !(vh > 0.0) || idx >= K;
-    stop = stop || (mode == 0 ? !(vh > thr * ref) : !(tr > thr * ref));
+    const double tr = mode == 1 ? wave_sum_dpp(un ? vh : 0.0) : 0.0;
+    bool stop = cand == 0ull || !(mx > 0.0);
+    stop = stop || (mode == 0 ? !(mx > thr * ref) : !(tr > thr * ref));
     if (stop) break;
-    const int p = idx;
+    const int p = __ffsll((long long)cand) - 1;
     if (tid == 0) piv[j] = p;
     selm |= 1ull << p;
     const dd gpp = {Sh[p * ls + p], use_dd ? Sl[p * ls + p] : 0.0};
@@ -1153,14 +1174,15 @@ __device__ void radd_cols(const LFlushTarget& T, const Term* terms, const ColMap
   }
 }
 
-// rows [base, base + 64) of one side, all K columns, into tile[rr + 64 j]
-// (zero past the rows); all loads of a thread are issued before any store
-__device__ __forceinline__ void radd_load_tile(const RaddCols& cs, int side, int base, int rows, int K,
-                                               double* tile) {
-  constexpr int NE = 64 * KMAX / HL_BLOCK;
-  double v[NE];
+// rows [base, base + 64) of one side, all K columns: radd_fetch_tile issues
+// the loads into registers (zero past the rows), radd_store_tile writes them
+// to tile[rr + 64 j]; fetching the next block before working on the current
+// one keeps a block's loads in flight during the work
+constexpr int RA_NE = 64 * KMAX / HL_BLOCK;
+__device__ __forceinline__ void radd_fetch_tile(const RaddCols& cs, int side, int base, int rows, int K,
+                                                double (&v)[RA_NE]) {
 #pragma unroll
-  for (int u = 0; u < NE; ++u) {
+  for (int u = 0; u < RA_NE; ++u) {
     const int e = threadIdx.x + u * HL_BLOCK;
     const int rr = e & 63, j = e >> 6;
     const int jj = j < K ? j : 0;
@@ -1171,8 +1193,10 @@ __device__ __forceinline__ void radd_load_tile(const RaddCols& cs, int side, int
     const double x = cs.p[side][jj][i];
     v[u] = ok ? cs.sign[side][jj] * x : 0.0;
   }
+}
+__device__ __forceinline__ void radd_store_tile(const double (&v)[RA_NE], int K, double* tile) {
 #pragma unroll
-  for (int u = 0; u < NE; ++u) {
+  for (int u = 0; u < RA_NE; ++u) {
     const int e = threadIdx.x + u * HL_BLOCK;
     if ((e >> 6) < K) tile[e] = v[u];
   }
@@ -1224,6 +1248,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
       break;
     }
     radd_cols(T, terms, cm, cs);
+    __syncthreads();   // the column sources are read by every thread below
     const int np = npairs(K);
     int pp[PPT], qq[PPT];
 #pragma unroll
@@ -1238,6 +1263,8 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
         qq[u] = q;
       }
     }
+    double v[RA_NE];
+    radd_fetch_tile(cs, 0, 0, min(64, T.m), K, v);
     for (int side = 0; side < 2; ++side) {
       const int len = side == 0 ? T.m : T.n;
       dd accv[PPT];
@@ -1245,8 +1272,13 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
       for (int u = 0; u < PPT; ++u) accv[u] = {0.0, 0.0};
       for (int base = 0; base < len; base += 64) {
         __syncthreads();
-        radd_load_tile(cs, side, base, min(64, len - base), K, tile);
+        radd_store_tile(v, K, tile);
         __syncthreads();
+        // next block: this side's, else the first of the V side
+        if (base + 64 < len)
+          radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
+        else if (side == 0)
+          radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
           if (tid + u * HL_BLOCK >= np) continue;
@@ -1278,6 +1310,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
     __syncthreads();
     r = radd_core(T, kC, K, tol, ls, Xh, Xl, Yh, Yl, Zh, Zl, YU, YV, pivB, pivM, sref);
     // new factors: U_new = A Y_U, V_new = B Y_V
+    radd_fetch_tile(cs, 0, 0, min(64, T.m), K, v);
     for (int side = 0; side < 2; ++side) {
       const int len = side == 0 ? T.m : T.n;
       double* out = side == 0 ? T.U : T.V;
@@ -1285,8 +1318,13 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
       for (int base = 0; base < len; base += 64) {
         const int rows = min(64, len - base);
         __syncthreads();
-        radd_load_tile(cs, side, base, rows, K, tile);
+        radd_store_tile(v, K, tile);
         __syncthreads();
+        // the next block is read before this one is overwritten: rows differ
+        if (base + 64 < len)
+          radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
+        else if (side == 0)
+          radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
         for (int o = tid; o < 64 * RA_YS; o += HL_BLOCK) {
           const int rr = o & 63, c = o >> 6;
           if (c >= r || rr >= rows) continue;
