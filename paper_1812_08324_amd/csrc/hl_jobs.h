@@ -58,6 +58,10 @@ struct DProdItem {
 //   C[ro:ro+mr, co:co+nc] += sign * P          (dense, P in U with ld ldu).
 // U points at the row of the factor that corresponds to region row 0,
 // W at the row that corresponds to region column 0.
+// An update term over rows [ro, ro + mr) x columns [co, co + nc) of a target:
+//   dense = 0: sign * U W^T, U mr x k (ld ldu), W nc x k (ld ldw), k = *k or kfix
+//   dense = 1: sign * P, P mr x nc (U, ld ldu)
+//   dense = 2: sign * A B, A mr x kfix (U, ld ldu), B kfix x nc (W, ld ldw)
 struct Term {
   int32_t dense;
   int32_t ro, mr, co, nc;

@@ -1347,25 +1347,107 @@ __host__ __device__ inline size_t radd_fused_lds(int ks) {
 // ---------------------------------------------------------------------------
 // dense targets, products, copies, leaf factorisation
 // ---------------------------------------------------------------------------
+// Dense target (at most 64 x 64): D += sum of its terms.  Thread (ty, tx)
+// of the 16 x 16 grid accumulates rows 4 ty .. 4 ty + 3 and columns
+// 4 tx .. 4 tx + 3 in registers.  Product and low-rank terms are taken in
+// 32-column slices of the inner dimension staged in LDS at target
+// positions (zero outside the term's rows / columns), the next slice
+// fetched into registers while the current one is used.
+constexpr int DF_KC = 32;
+constexpr int DF_NE = 2 * 64 * DF_KC / HL_BLOCK;   // staged values per thread and slice
+
+__device__ __forceinline__ int term_inner(const Term& tm) {
+  return tm.dense == 2 ? tm.kfix : (tm.k ? *tm.k : tm.kfix);
+}
+
+// slice [q0, q0 + DF_KC) of the inner dimension: element e < 64 * DF_KC is
+// A(i, q) (i = e % 64), the rest B(q, j) (j = e' % 64), zero outside the term
+__device__ __forceinline__ void df_fetch(const Term& tm, int kin, int q0, double (&v)[DF_NE]) {
+  // unconditional loads at clamped (in-bounds) indices, so that all of a
+  // thread's loads are in flight together; masked values become zero
+#pragma unroll
+  for (int u = 0; u < DF_NE; ++u) {
+    const int e = threadIdx.x + u * HL_BLOCK;
+    const bool left = e < 64 * DF_KC;
+    const int f = left ? e : e - 64 * DF_KC;
+    const int x = f & 63, q = q0 + (f >> 6);
+    const int qc = min(q, kin - 1);
+    double val;
+    bool ok;
+    if (left) {
+      const int i = x - tm.ro;
+      ok = i >= 0 && i < tm.mr && q < kin;
+      val = tm.U[min(max(i, 0), tm.mr - 1) + (size_t)tm.ldu * qc];
+      val *= tm.sign;
+    } else {
+      const int j = x - tm.co;
+      ok = j >= 0 && j < tm.nc && q < kin;
+      const int jc = min(max(j, 0), tm.nc - 1);
+      val = tm.dense == 2 ? tm.W[qc + (size_t)tm.ldw * jc] : tm.W[jc + (size_t)tm.ldw * qc];
+    }
+    v[u] = ok ? val : 0.0;
+  }
+}
+
 __global__ void __launch_bounds__(HL_BLOCK) k_flush_dense(const DFlushItem* items, const Term* terms) {
+  __shared__ double As[DF_KC * 64], Bs[DF_KC * 64];   // A(i, q) at i + 64 q, B(q, j) at j + 64 q
   const DFlushItem it = items[blockIdx.x];
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int i0 = ty * 4, j0 = tx * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + r, j = j0 + c;
+      acc[r][c] = (i < it.m && j < it.n) ? it.D[i + (size_t)it.ldd * j] : 0.0;
+    }
   for (int t = 0; t < it.tcount; ++t) {
     const Term tm = terms[it.tbeg + t];
-    const int k = tm.dense ? 0 : (tm.k ? *tm.k : tm.kfix);
-    const int tot = tm.mr * tm.nc;
-    for (int e = threadIdx.x; e < tot; e += HL_BLOCK) {
-      int i = e % tm.mr, j = e / tm.mr;
-      double v;
-      if (tm.dense) {
-        v = tm.U[i + (size_t)tm.ldu * j];
-      } else {
-        v = 0.0;
-        for (int p = 0; p < k; ++p) v += tm.U[i + (size_t)tm.ldu * p] * tm.W[j + (size_t)tm.ldw * p];
-      }
-      it.D[(tm.ro + i) + (size_t)it.ldd * (tm.co + j)] += tm.sign * v;
+    if (tm.dense == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = i0 + r - tm.ro, j = j0 + c - tm.co;
+          if (i >= 0 && i < tm.mr && j >= 0 && j < tm.nc) acc[r][c] += tm.sign * tm.U[i + (size_t)tm.ldu * j];
+        }
+      continue;
     }
-    __syncthreads();
+    const int kin = term_inner(tm);
+    double v[DF_NE];
+    if (kin > 0) df_fetch(tm, kin, 0, v);
+    for (int q0 = 0; q0 < kin; q0 += DF_KC) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < DF_NE; ++u) {
+        const int e = tid + u * HL_BLOCK;
+        if (e < 64 * DF_KC) As[e] = v[u];
+        else Bs[e - 64 * DF_KC] = v[u];
+      }
+      __syncthreads();
+      if (q0 + DF_KC < kin) df_fetch(tm, kin, q0 + DF_KC, v);
+      const int qn = min(DF_KC, kin - q0);
+      for (int q = 0; q < qn; ++q) {
+        double a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = As[i0 + r + 64 * q];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = Bs[j0 + c + 64 * q];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+      }
+    }
   }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + r, j = j0 + c;
+      if (i < it.m && j < it.n) it.D[i + (size_t)it.ldd * j] = acc[r][c];
+    }
 }
 
 __global__ void __launch_bounds__(HL_BLOCK) k_dense_prod(const DProdItem* items) {

@@ -398,8 +398,11 @@ struct Builder {
         int b0 = std::max(c0, S.cl[ch.c].lo), b1 = std::min(c1, S.cl[ch.c].hi);
         if (a0 >= a1 || b0 >= b1) continue;
         Term u = t;
-        if (t.dense) {
+        if (t.dense == 1) {
           u.U = t.U + (a0 - r0) + (size_t)t.ldu * (b0 - c0);
+        } else if (t.dense == 2) {
+          u.U = t.U + (a0 - r0);                       // rows of the left factor
+          u.W = t.W + (size_t)t.ldw * (b0 - c0);       // columns of the right factor
         } else {
           u.U = t.U + (a0 - r0);
           u.W = t.W + (b0 - c0);
@@ -454,14 +457,17 @@ struct Builder {
       t.sign = sign;
       push(C, cnode, t, lb.kcap, r0, r1, c0, c1);
     } else if (ak == K_DENSE && bk == K_DENSE) {
+      // a product term: dense targets take it as it is, low-rank targets
+      // get the product formed first (end())
       const LeafDesc& la = A->L[a.leaf];
       const LeafDesc& lb = B->L[b.leaf];
-      double* Pp = ws.alloc_d((size_t)la.m * lb.n);
-      bdprod.push_back(DProdItem{la.A, lb.A, Pp, la.m, lb.m, la.m, la.m, la.n, lb.n});
       Term t{};
-      t.dense = 1;
-      t.U = Pp;
+      t.dense = 2;
+      t.U = la.A;
       t.ldu = la.m;
+      t.W = lb.A;
+      t.ldw = lb.m;
+      t.kfix = la.n;
       t.sign = sign;
       push(C, cnode, t, std::min(32, std::min(la.m, lb.n)), r0, r1, c0, c1);
     } else {
@@ -564,7 +570,22 @@ struct Builder {
       ph.n1 = (int)P.gath.size() - ph.b1;
       P.ph.push_back(ph);
     }
-    // 2. dense products
+    // 2. products into low-rank targets are formed densely (workspace),
+    //    then compressed below; dense targets take product terms as they are
+    for (auto& kv : pending) {
+      HMat* C = kv.first.first;
+      if (C->L[kv.first.second].kind != K_LR) continue;
+      for (auto& pt : kv.second) {
+        if (pt.t.dense != 2) continue;
+        Term& t = pt.t;
+        double* Pp = ws.alloc_d((size_t)t.mr * t.nc);
+        bdprod.push_back(DProdItem{t.U, t.W, Pp, t.ldu, t.ldw, t.mr, t.mr, t.kfix, t.nc});
+        t.dense = 1;
+        t.U = Pp;
+        t.ldu = t.mr;
+        t.W = nullptr;
+      }
+    }
     if (!bdprod.empty()) {
       Phase ph{PH_DPROD, (int)P.dprod.size(), (int)bdprod.size(), 0, 0, 0, 0, 0.0};
       for (auto& d : bdprod) P.dprod.push_back(d);
