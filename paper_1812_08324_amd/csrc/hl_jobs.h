@@ -107,6 +107,8 @@ struct CopyItem {
   double scale;        // applied to A (dense block or U)
   int32_t add_identity;  // dense diagonal leaf: add the identity after scaling
   int32_t expand;        // destination dense, source low rank: dA = scale * U V^T
+  double* zA;            // move: the dense source (zeroed after the copy) or nullptr
+  int32_t* zrank;        // move: the low-rank source's rank (set to 0) or nullptr
 };
 
 // Leaf factorisation: LU in place (no pivoting) and the inverses of the

@@ -1483,6 +1483,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_copy_leaf(const CopyItem* items) {
       double v = it.A ? it.scale * it.A[e] : 0.0;
       if (it.add_identity && (e % it.m) == (e / it.m)) v += 1.0;
       it.dA[e] = v;
+      if (it.zA) it.zA[e] = 0.0;   // move: each element is read before it is cleared, by the same thread
     }
     return;
   }
@@ -1490,6 +1491,10 @@ __global__ void __launch_bounds__(HL_BLOCK) k_copy_leaf(const CopyItem* items) {
   for (int e = threadIdx.x; e < it.m * k; e += HL_BLOCK) it.dA[e] = it.scale * it.A[e];
   for (int e = threadIdx.x; e < it.n * k; e += HL_BLOCK) it.dB[e] = it.B[e];
   if (threadIdx.x == 0 && it.drank) *it.drank = k;
+  if (it.zrank) {
+    __syncthreads();   // every thread has read the source rank
+    if (threadIdx.x == 0) *it.zrank = 0;
+  }
 }
 
 // LU without pivoting of a diagonal leaf (in place), then the inverses of the

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <string>
@@ -762,10 +763,26 @@ struct Builder {
     in_batch = false;
   }
 
+  // Copies of the leaves of `nodes` (src null: zero) in one phase; move =
+  // clear the source after the copy.
+  void copy_nodes(HMat* dst, HMat* src, std::initializer_list<int> nodes, bool move) {
+    Phase ph{PH_COPY, (int)P.copies.size(), 0, 0, 0, 0, 0, 0.0};
+    for (int node : nodes) add_copies(dst, src, node, 1.0, false, false, move);
+    ph.n0 = (int)P.copies.size() - ph.b0;
+    if (ph.n0) P.ph.push_back(ph);
+  }
+
   void copy_node(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag,
                  bool skip_compress = false) {
-    const BNode& b = S.bn[node];
     Phase ph{PH_COPY, (int)P.copies.size(), 0, 0, 0, 0, 0, 0.0};
+    add_copies(dst, src, node, scale, add_identity_diag, skip_compress, false);
+    ph.n0 = (int)P.copies.size() - ph.b0;
+    if (ph.n0) P.ph.push_back(ph);
+  }
+
+  void add_copies(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag, bool skip_compress,
+                  bool move) {
+    const BNode& b = S.bn[node];
     for (int l = b.lbeg; l < b.lend; ++l) {
       const LeafDesc& d = dst->L[l];
       if (d.kind == K_ZERO) continue;
@@ -785,13 +802,16 @@ struct Builder {
         c.rank = e.kind == K_LR ? src->rank + l : nullptr;
         c.expand = (d.kind == K_DENSE && e.kind == K_LR) ? 1 : 0;
         if (d.kind == K_LR && e.kind != K_LR) throw DeviceError("internal: dense to low-rank copy");
+        if (move) {
+          if (c.expand) throw DeviceError("internal: move with expansion");
+          if (e.kind == K_DENSE) c.zA = e.A;
+          if (e.kind == K_LR) c.zrank = src->rank + l;
+        }
       }
       c.scale = scale;
       c.add_identity = (add_identity_diag && S.lf[l].r == S.lf[l].c) ? 1 : 0;
       P.copies.push_back(c);
     }
-    ph.n0 = (int)P.copies.size() - ph.b0;
-    if (ph.n0) P.ph.push_back(ph);
   }
 
   void zero_node(HMat* dst, int node) { copy_node(dst, nullptr, node, 0.0, false); }
@@ -801,6 +821,8 @@ struct Builder {
 // (App. B.3 recursion; inverses by the 2x2 block formulas):
 //   LU(A11);  U12 = L11^{-1} A12;  L21 = A21 U11^{-1};  LU(A22 - L21 U12);
 //   (L^{-1})21 = -L22^{-1} L21 L11^{-1};  (U^{-1})12 = -U11^{-1} U12 U22^{-1}.
+// T21 = L21 L11^{-1} and S12 = U11^{-1} U12 are formed together with the
+// Schur update, so that each level takes three batches of products.
 // A diagonal node that is one dense leaf, or 2 x 2 dense leaves of at most
 // LUINV_N rows in all, is factored with its inverses by one fused kernel.
 static bool emit_dense_luinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, int node) {
@@ -858,27 +880,21 @@ static void hluinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, HMat* TMP, int node
   }
   const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
   hluinv(B, LU, Li, Ui, TMP, n11);
-  B.zero_node(TMP, n12);
-  B.zero_node(TMP, n21);
+  // TMP blocks start (and are left by the move below) at zero
   B.begin();
   B.mma(TMP, n12, Li, n11, LU, n12, 1.0);   // U12 = L11^{-1} A12
   B.mma(TMP, n21, LU, n21, Ui, n11, 1.0);   // L21 = A21 U11^{-1}
   B.end();
-  B.copy_node(LU, TMP, n12, 1.0, false);
-  B.copy_node(LU, TMP, n21, 1.0, false);
+  B.copy_nodes(LU, TMP, {n12, n21}, /*move=*/true);
   B.begin();
   B.mma(LU, n22, LU, n21, LU, n12, -1.0);   // A22 -= L21 U12
+  B.mma(TMP, n21, LU, n21, Li, n11, 1.0);   // T21 = L21 L11^{-1}
+  B.mma(TMP, n12, Ui, n11, LU, n12, 1.0);   // S12 = U11^{-1} U12
   B.end();
   hluinv(B, LU, Li, Ui, TMP, n22);
-  B.zero_node(TMP, n12);
-  B.zero_node(TMP, n21);
   B.begin();
-  B.mma(TMP, n21, LU, n21, Li, n11, 1.0);   // L21 L11^{-1}
-  B.mma(TMP, n12, LU, n12, Ui, n22, 1.0);   // U12 U22^{-1}
-  B.end();
-  B.begin();
-  B.mma(Li, n21, Li, n22, TMP, n21, -1.0);  // -(L22^{-1}) (L21 L11^{-1})
-  B.mma(Ui, n12, Ui, n11, TMP, n12, -1.0);  // -(U11^{-1}) (U12 U22^{-1})
+  B.mma(Li, n21, Li, n22, TMP, n21, -1.0);  // (L^{-1})21 = -L22^{-1} T21
+  B.mma(Ui, n12, TMP, n12, Ui, n22, -1.0);  // (U^{-1})12 = -S12 U22^{-1}
   B.end();
 }
 
@@ -1340,6 +1356,7 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
       B.copy_node(&f->LU, const_cast<HMat*>(&op->G), 0, -0.5 * dt, true);   // M = I - dt/2 G
       B.zero_node(&Li, 0);
       B.zero_node(&Ui, 0);
+      B.zero_node(&TMP, 0);
       const double t0 = now_s();
       hluinv(B, &f->LU, &Li, &Ui, &TMP, 0);
       // inverse factors in the operator's block format: dense leaf-level
