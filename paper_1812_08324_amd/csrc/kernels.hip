@@ -476,7 +476,7 @@ __host__ __device__ inline int npairs(int K) { return K * (K + 1) / 2; }
 __global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg, const Term* terms,
                                                          const ChunkItem* items) {
   __shared__ ColMap cm;
-  __shared__ double tile[64 * KMAX];
+  __shared__ double tile[65 * KMAX];   // column stride 65: no LDS bank conflicts across columns
   const ChunkItem it = items[blockIdx.x];
   const LFlushTarget T = tg[it.tgt];
   if (threadIdx.x == 0) build_colmap(T, terms, T.rank ? *T.rank : 0, cm);
@@ -503,13 +503,13 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg,
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * K; e += HL_BLOCK) {
       int rr = e % 64, j = e / 64;
-      tile[rr + 64 * j] = rr < rows ? side_val(T, terms, cm, it.side, base + rr, j) : 0.0;
+      tile[rr + 65 * j] = rr < rows ? side_val(T, terms, cm, it.side, base + rr, j) : 0.0;
     }
     __syncthreads();
     for (int u = 0; u < PPT; ++u) {
       if (pp[u] < 0) continue;
-      const double* a = tile + 64 * pp[u];
-      const double* b = tile + 64 * qq[u];
+      const double* a = tile + 65 * pp[u];
+      const double* b = tile + 65 * qq[u];
       dd s = accv[u];
       for (int rr = 0; rr < rows; ++rr) s = dd_add(s, dd_mul_d(a[rr], b[rr]));
       accv[u] = s;
@@ -964,9 +964,16 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
     const double* rb_h = Xh + pivB[j] * ks;
     const double* rb_l = Xl + pivB[j] * ks;
     dd s = {0.0, 0.0};
-    for (int p = 0; p < K; ++p) {
-      if (use_dd) s = dd_add(s, dd_mul({Yh[q * ks + p], Yl[q * ks + p]}, {rb_h[p], rb_l[p]}));
-      else s.hi += Yh[q * ks + p] * rb_h[p];
+    if (use_dd) {
+      for (int p = 0; p < K; ++p) s = dd_add(s, dd_mul({Yh[q * ks + p], Yl[q * ks + p]}, {rb_h[p], rb_l[p]}));
+    } else {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int p = 0;
+      for (; p + 4 <= K; p += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s4[u] += Yh[q * ks + p + u] * rb_h[p + u];
+      for (; p < K; ++p) s4[0] += Yh[q * ks + p] * rb_h[p];
+      s.hi = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     Zh[q * ks + j] = s.hi;
     Zl[q * ks + j] = s.lo;
@@ -978,9 +985,16 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
     const double* rb_h = Xh + pivB[i] * ks;
     const double* rb_l = Xl + pivB[i] * ks;
     dd s = {0.0, 0.0};
-    for (int p = 0; p < K; ++p) {
-      if (use_dd) s = dd_add(s, dd_mul({rb_h[p], rb_l[p]}, {Zh[p * ks + j], Zl[p * ks + j]}));
-      else s.hi += rb_h[p] * Zh[p * ks + j];
+    if (use_dd) {
+      for (int p = 0; p < K; ++p) s = dd_add(s, dd_mul({rb_h[p], rb_l[p]}, {Zh[p * ks + j], Zl[p * ks + j]}));
+    } else {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int p = 0;
+      for (; p + 4 <= K; p += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s4[u] += rb_h[p + u] * Zh[(p + u) * ks + j];
+      for (; p < K; ++p) s4[0] += rb_h[p] * Zh[p * ks + j];
+      s.hi = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     Yh[i * ks + j] = s.hi;
     Yl[i * ks + j] = s.lo;
@@ -1176,7 +1190,7 @@ __device__ void radd_cols(const LFlushTarget& T, const Term* terms, const ColMap
 
 // rows [base, base + 64) of one side, all K columns: radd_fetch_tile issues
 // the loads into registers (zero past the rows), radd_store_tile writes them
-// to tile[rr + 64 j]; fetching the next block before working on the current
+// to tile[rr + RA_TS j]; fetching the next block before working on the current
 // one keeps a block's loads in flight during the work
 constexpr int RA_NE = 64 * KMAX / HL_BLOCK;
 __device__ __forceinline__ void radd_fetch_tile(const RaddCols& cs, int side, int base, int rows, int K,
@@ -1194,11 +1208,12 @@ __device__ __forceinline__ void radd_fetch_tile(const RaddCols& cs, int side, in
     v[u] = ok ? cs.sign[side][jj] * x : 0.0;
   }
 }
+constexpr int RA_TS = 65;   // column stride of a staged row block (odd: no LDS bank conflicts across columns)
 __device__ __forceinline__ void radd_store_tile(const double (&v)[RA_NE], int K, double* tile) {
 #pragma unroll
   for (int u = 0; u < RA_NE; ++u) {
     const int e = threadIdx.x + u * HL_BLOCK;
-    if ((e >> 6) < K) tile[e] = v[u];
+    if ((e >> 6) < K) tile[(e & 63) + RA_TS * (e >> 6)] = v[u];
   }
 }
 
@@ -1221,7 +1236,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
   double* Zl = Zh + ls * ls;
   double* YU = Zl + ls * ls;
   double* YV = YU + ks * RA_YS;
-  double* tile = Zh;   // 64 x K: Z holds 2 ls^2 >= 64 ks doubles (ks >= 32)
+  double* tile = Zh;   // 64 x K, column stride RA_TS: Z holds 2 ls^2 >= RA_TS ks doubles (ks >= 32)
   __shared__ ColMap cm;
   __shared__ RaddCols cs;
   __shared__ int pivB[KMAX], pivM[KMAX];
@@ -1282,8 +1297,8 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
           if (tid + u * HL_BLOCK >= np) continue;
-          const double* a = tile + 64 * pp[u];
-          const double* b = tile + 64 * qq[u];
+          const double* a = tile + RA_TS * pp[u];
+          const double* b = tile + RA_TS * qq[u];
           if (use_dd) {
             dd acc = accv[u];
             for (int rr = 0; rr < 64; ++rr) acc = dd_add(acc, dd_mul_d(a[rr], b[rr]));
@@ -1329,7 +1344,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
           const int rr = o & 63, c = o >> 6;
           if (c >= r || rr >= rows) continue;
           double acc = 0.0;
-          for (int j = 0; j < K; ++j) acc += tile[rr + 64 * j] * Y[j * RA_YS + c];
+          for (int j = 0; j < K; ++j) acc += tile[rr + RA_TS * j] * Y[j * RA_YS + c];
           out[(base + rr) + (size_t)len * c] = acc;
         }
       }
