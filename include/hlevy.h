@@ -161,10 +161,14 @@ hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream);
 hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu_tol,
                           void* stream, hlevy_fac** out);
 
-/* Solve M x = b.  FP64 factors: x = U^{-1} (L^{-1} b) applied through the
- * inverse factors (forward then backward solve).  Mixed: refine->sweeps sweeps of
- * x <- x + U^{-1} L^{-1} (b - M x) with the residual in FP64 (refine may be
- * NULL: 2 sweeps).  b, x: device, natural order, must not alias. */
+/* Solve M x = b: x = U^{-1} (L^{-1} b) through the inverse factors (forward
+ * then backward solve), then refine->sweeps sweeps of
+ * x <- x + U^{-1} L^{-1} (b - M x) with the residual in FP64.  refine may
+ * be NULL: 2 sweeps (mixed)
+ * or 1 sweep (FP64; products with explicit inverse factors lose accuracy
+ * like eps cond(L) cond(U), about 1e-6 relative residual at N = 65536, and
+ * one sweep restores about 1e-12).  b, x: device, natural order, must not
+ * alias. */
 hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x,
                          const hlevy_refine* refine, void* stream);
 
@@ -177,6 +181,15 @@ hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x,
 hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double* g,
                         const double* phi, const hlevy_refine* refine,
                         hlevy_stats* stats, void* stream);
+
+/* y = A x with one of the matrices the factor applies every step, in the
+ * storage precision of the factor: which = 0: the generator G of the
+ * residual operator (FP64 on both paths), 1: L^{-1}, 2: U^{-1} (App. B.2
+ * product on the H-inverses of the factors of M = I - dt/2 G; FP32 on the
+ * mixed path).
+ * x, y: device, length N, natural order, must not alias.
+ * Errors: HLEVY_ERR_INVALID_ARG for null pointers, aliasing or a bad `which`. */
+hlevy_status hlevy_fac_apply(hlevy_fac* fac, int32_t which, const double* x, double* y, void* stream);
 
 /* Kernel timing of the per-step matrix-vector products (roofline
  * reporting).  Runs `reps` rounds of the three products of a Crank-Nicolson

@@ -16,8 +16,8 @@ constexpr int MV_EMAX = 128;  // entries staged in LDS per gather round
 // `slot` of the partial buffer (stride kb doubles per slot).
 struct MvTile {
   int32_t n, k, ld, xoff;
-  int32_t slot, pad;
-  const void* V;   // first row of the tile
+  int32_t slot, f32;   // f32: V stored in FP32 (else FP64)
+  const void* V;       // first row of the tile
 };
 
 // A leaf seen from one leaf cluster rho.  Dense: block rows of rho (ptr at
@@ -25,7 +25,7 @@ struct MvTile {
 // Low rank: rows of U for rho (ptr at that row, ld, rank k); its projection
 // t = V^T x is the sum of np partials starting at slot `slot`.
 struct MvEntry {
-  int32_t kind;   // 0 dense, 1 low rank
+  int32_t kind;   // 0 dense, 1 low rank (FP64 U), 2 low rank (FP32 U)
   int32_t n;      // dense: columns; low rank: number of partials
   int32_t xoff, k, slot, pad, ld, pad2;
   const void* ptr;
@@ -53,7 +53,7 @@ struct MvDev {
   double* part;        // projection partials, kb doubles per slot
   int32_t ntiles, nrows;
   int32_t kb;          // rank bucket of the matrix: 8, 16 or 32 (>= every leaf rank)
-  int32_t dense_f32, lr_f32;
+  int32_t dense_f32;   // dense leaves stored in FP32 (else FP64)
 };
 
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
@@ -64,7 +64,7 @@ hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEve
 hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // rows of V one projection wavefront covers per pass (64 lanes x rows per lane)
-int project_rows_per_pass(int kb, bool lr_f32);
+int project_rows_per_pass(int kb, bool f32);
 hipError_t launch_convert_f32(const double* in, float* out, size_t n, hipStream_t s);
 
 }  // namespace hl

@@ -81,14 +81,12 @@ constexpr int rows_per_lane() {
   return (sizeof(TL) == 4 ? 64 : 32) / KB;
 }
 
+// one projection tile (V in precision TL): the k partial sums of the
+// wavefront's rows, written to the tile's slot
 template <typename TL, int KB>
-__global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ tiles, int ntiles,
-                                                    const double* __restrict__ x, double* __restrict__ part) {
+__device__ __forceinline__ void project_tile(const MvTile& T, const double* __restrict__ x, double* __restrict__ part,
+                                             int lane) {
   constexpr int RPL = rows_per_lane<TL, KB>();
-  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= ntiles) return;   // the whole wavefront leaves; no block barrier below
-  const int lane = threadIdx.x & 63;
-  const MvTile T = tiles[wid];
   const gptr<TL> V = wuni_ptr<TL>(T.V);
   const double* __restrict__ xs = x + T.xoff;
   double acc[KB];
@@ -122,9 +120,36 @@ __global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ t
   if (lane % G == 0 && col < T.k) part[(size_t)T.slot * KB + col] = acc[0];
 }
 
+template <int KB>
+__global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ tiles, int ntiles,
+                                                    const double* __restrict__ x, double* __restrict__ part) {
+  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= ntiles) return;   // the whole wavefront leaves; no block barrier below
+  const int lane = threadIdx.x & 63;
+  const MvTile T = tiles[wid];
+  if (wuni(T.f32))
+    project_tile<float, KB>(T, x, part, lane);
+  else
+    project_tile<double, KB>(T, x, part, lane);
+}
+
 constexpr int MV_GW = 8;   // wavefronts per gather workgroup
 
-template <typename TD, typename TL, int KB>
+template <typename TL, int KB>
+__device__ __forceinline__ double gather_lowrank(const void* p, int ii, int ld, int ek, const double* t) {
+  const gptr<TL> U = wuni_ptr<TL>(p);
+  // unconditional loads (columns past the rank re-read column k-1 and meet
+  // t = 0), so all of them are in flight together
+  double uv[KB];
+#pragma unroll
+  for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < KB; ++q) acc += uv[q] * t[q];
+  return acc;
+}
+
+template <typename TD, int KB>
 __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restrict__ rows,
                                                           const MvEntry* __restrict__ ents,
                                                           const double* __restrict__ x,
@@ -153,7 +178,7 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
       const int e = it / KB, q = it % KB;
       const MvEntry& E = se[e];
       double s = 0.0;   // zero past the rank: the products below multiply by it
-      if (E.kind == 1 && q < E.k) {
+      if (E.kind != 0 && q < E.k) {
         const double* p = part + (size_t)E.slot * KB + q;
         for (int c = 0; c < E.n; ++c) s += p[(size_t)c * KB];
       }
@@ -174,16 +199,10 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
           for (int q = 0; q < 16; ++q) acc += dv[q] * bcast_lane(xl, j + q);
         }
         for (; j < en; ++j) acc += (double)D[(unsigned)(ii + ld * j)] * bcast_lane(xl, j);
+      } else if (kind == 1) {
+        acc += gather_lowrank<double, KB>(se[e].ptr, ii, ld, ek, ts + e * KB);
       } else {
-        const gptr<TL> U = wuni_ptr<TL>(se[e].ptr);
-        const double* t = ts + e * KB;
-        double uv[KB];
-        // unconditional loads (columns past the rank re-read column k-1 and
-        // meet t = 0), so all of them are in flight together
-#pragma unroll
-        for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
-#pragma unroll
-        for (int q = 0; q < KB; ++q) acc += uv[q] * t[q];
+        acc += gather_lowrank<float, KB>(se[e].ptr, ii, ld, ek, ts + e * KB);
       }
     }
   }
@@ -212,76 +231,65 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
   }
 }
 
-int project_rows_per_pass(int kb, bool lr_f32) {
-  const int vals = lr_f32 ? 64 : 32;
+int project_rows_per_pass(int kb, bool f32) {
+  const int vals = f32 ? 64 : 32;
   return 64 * (vals / kb);
 }
 
 // Launches; with events, the events are attached to the dispatch itself
 // (hipExtLaunchKernelGGL) and time exactly that kernel.
-template <typename TL, int KB>
+template <int KB>
 static void project_t(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (M.ntiles <= 0) return;
   const dim3 grid((M.ntiles + 3) / 4);
   if (e0)
-    hipExtLaunchKernelGGL((k_mv_project<TL, KB>), grid, dim3(256), 0, s, e0, e1, 0, M.tiles, M.ntiles, x, M.part);
+    hipExtLaunchKernelGGL((k_mv_project<KB>), grid, dim3(256), 0, s, e0, e1, 0, M.tiles, M.ntiles, x, M.part);
   else
-    hipLaunchKernelGGL((k_mv_project<TL, KB>), grid, dim3(256), 0, s, M.tiles, M.ntiles, x, M.part);
+    hipLaunchKernelGGL((k_mv_project<KB>), grid, dim3(256), 0, s, M.tiles, M.ntiles, x, M.part);
 }
 
-template <typename TD, typename TL, int KB>
+template <typename TD, int KB>
 static void gather_t(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
                      hipEvent_t e1) {
   if (M.nrows <= 0) return;
   const dim3 grid(M.nrows), block(64 * MV_GW);
   const double* part = M.part;
   if (e0)
-    hipExtLaunchKernelGGL((k_mv_gather<TD, TL, KB>), grid, block, 0, s, e0, e1, 0, M.rows, M.ents, x, part, epi);
+    hipExtLaunchKernelGGL((k_mv_gather<TD, KB>), grid, block, 0, s, e0, e1, 0, M.rows, M.ents, x, part, epi);
   else
-    hipLaunchKernelGGL((k_mv_gather<TD, TL, KB>), grid, block, 0, s, M.rows, M.ents, x, part, epi);
+    hipLaunchKernelGGL((k_mv_gather<TD, KB>), grid, block, 0, s, M.rows, M.ents, x, part, epi);
 }
 
-template <typename TL>
-static void project_kb(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (M.kb <= 8)
-    project_t<TL, 8>(M, x, s, e0, e1);
-  else if (M.kb <= 16)
-    project_t<TL, 16>(M, x, s, e0, e1);
-  else
-    project_t<TL, 32>(M, x, s, e0, e1);
-}
-
-template <typename TD, typename TL>
+template <typename TD>
 static void gather_kb(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
                       hipEvent_t e1) {
   if (M.kb <= 8)
-    gather_t<TD, TL, 8>(M, x, epi, s, e0, e1);
+    gather_t<TD, 8>(M, x, epi, s, e0, e1);
   else if (M.kb <= 16)
-    gather_t<TD, TL, 16>(M, x, epi, s, e0, e1);
+    gather_t<TD, 16>(M, x, epi, s, e0, e1);
   else
-    gather_t<TD, TL, 32>(M, x, epi, s, e0, e1);
+    gather_t<TD, 32>(M, x, epi, s, e0, e1);
 }
 
 hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
-  if (M.lr_f32)
-    project_kb<float>(M, x, s, e0, e1);
+  if (M.kb == 8)
+    project_t<8>(M, x, s, e0, e1);
+  else if (M.kb == 16)
+    project_t<16>(M, x, s, e0, e1);
+  else if (M.kb == 32)
+    project_t<32>(M, x, s, e0, e1);
   else
-    project_kb<double>(M, x, s, e0, e1);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
   if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
-  if (M.dense_f32 && M.lr_f32)
-    gather_kb<float, float>(M, x, epi, s, e0, e1);
-  else if (M.dense_f32)
-    gather_kb<float, double>(M, x, epi, s, e0, e1);
-  else if (M.lr_f32)
-    gather_kb<double, float>(M, x, epi, s, e0, e1);
+  if (M.dense_f32)
+    gather_kb<float>(M, x, epi, s, e0, e1);
   else
-    gather_kb<double, double>(M, x, epi, s, e0, e1);
+    gather_kb<double>(M, x, epi, s, e0, e1);
   return hipGetLastError();
 }
 

@@ -951,8 +951,10 @@ struct MvPlan {
   int64_t lr_entries = 0, dense_entries = 0;
   int64_t nslots = 0;
 
+  // lr_f32: low-rank leaves in FP32, except those with at most lr64_rows
+  // rows and columns, which stay FP64
   void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, bool lr_f32,
-              hipStream_t s) {
+              hipStream_t s, int lr64_rows = 0) {
     const double* base = M.pool.as<double>();
     const float* fbase = nullptr;
     if (dense_f32 || lr_f32) {
@@ -961,14 +963,13 @@ struct MvPlan {
       fbase = f32pool.as<float>();
     }
     auto fptr = [&](const double* p) -> const void* { return fbase + (p - base); };
-    const size_t lr_elt = lr_f32 ? sizeof(float) : sizeof(double);
     const size_t d_elt = dense_f32 ? sizeof(float) : sizeof(double);
+    auto leaf_f32 = [&](const LeafDesc& d) { return lr_f32 && std::max(d.m, d.n) > lr64_rows; };
     int kmax = 0;
     for (size_t l = 0; l < S.lf.size(); ++l)
       if (M.L[l].kind == K_LR) kmax = std::max(kmax, rk[l]);
     if (kmax > 32) throw std::runtime_error("internal: rank above 32 in a product plan");
     const int kb = kmax <= 8 ? 8 : (kmax <= 16 ? 16 : 32);
-    const int rpp = project_rows_per_pass(kb, lr_f32);
     // projection tiles: a leaf's V rows split into at most MV_PMAX tiles of
     // whole passes; partial slots of one leaf are consecutive
     std::vector<MvTile> tiles;
@@ -981,6 +982,9 @@ struct MvPlan {
       }
       if (d.kind != K_LR || rk[l] == 0) continue;
       const int k = rk[l];
+      const bool f32 = leaf_f32(d);
+      const size_t lr_elt = f32 ? sizeof(float) : sizeof(double);
+      const int rpp = project_rows_per_pass(kb, f32);
       lr_bytes += (int64_t)(d.m + d.n) * k * lr_elt;
       u_bytes += (int64_t)d.m * k * lr_elt;
       v_bytes += (int64_t)d.n * k * lr_elt;
@@ -998,8 +1002,9 @@ struct MvPlan {
         T.ld = d.n;
         T.xoff = d.clo + r0;
         T.slot = (int32_t)(nslots + t);
+        T.f32 = f32 ? 1 : 0;
         const double* p = d.B + r0;
-        T.V = lr_f32 ? fptr(p) : (const void*)p;
+        T.V = f32 ? fptr(p) : (const void*)p;
         tiles.push_back(T);
       }
       nslots += P;
@@ -1027,14 +1032,15 @@ struct MvPlan {
           E.ptr = dense_f32 ? fptr(p) : (const void*)p;
           bytes = (int64_t)d.n * d_elt;
         } else if (d.kind == K_LR && rk[l] > 0) {
-          E.kind = 1;
+          const bool f32 = leaf_f32(d);
+          E.kind = f32 ? 2 : 1;
           E.n = np[l];
           E.k = rk[l];
           E.slot = slot0[l];
           E.ld = d.m;
           const double* p = d.A + (c.lo - d.rlo);
-          E.ptr = lr_f32 ? fptr(p) : (const void*)p;
-          bytes = (int64_t)rk[l] * lr_elt;
+          E.ptr = f32 ? fptr(p) : (const void*)p;
+          bytes = (int64_t)rk[l] * (f32 ? sizeof(float) : sizeof(double));
         } else {
           continue;
         }
@@ -1055,7 +1061,7 @@ struct MvPlan {
     upload(drows, rows, s);
     dpart.alloc(std::max<int64_t>(nslots, 1) * kb * sizeof(double));
     dev = MvDev{dtiles.as<MvTile>(), dents.as<MvEntry>(), drows.as<MvRow>(), dpart.as<double>(),
-                (int)tiles.size(), (int)rows.size(), kb, dense_f32 ? 1 : 0, lr_f32 ? 1 : 0};
+                (int)tiles.size(), (int)rows.size(), kb, dense_f32 ? 1 : 0};
   }
   void run(const double* x, const MvEpi& e, hipStream_t s) const { HL_CHECK(mv_launch(dev, x, e, s)); }
 };
@@ -1428,9 +1434,12 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
     f->scal.alloc(8 * sizeof(double));
     {
       const bool mixed = prec == HLEVY_PREC_MIXED;
-      // residual operator: FP64 near field, FP32 far field on the mixed path;
-      // preconditioner (inverse factors): FP32 on the mixed path
-      f->mvG.create(S, op->G, read_ranks(op->G, s), false, mixed, s);
+      // residual operator in FP64 on both paths: with the far field in FP32
+      // the operator applied to smooth states is off by ~1e-7 relative (the
+      // far-field sums are large and cancel against the near field), which
+      // adds up to ~1e-8..1e-7 over 1000 steps; preconditioner (inverse
+      // factors): FP32 on the mixed path
+      f->mvG.create(S, op->G, read_ranks(op->G, s), false, false, s);
       f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s);
       f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s);
       f->LU.pool.reset();   // the per-step path needs only G and the inverse factors
@@ -1468,9 +1477,14 @@ static void refine_sweeps(hlevy_fac* f, const double* b, double* x, int sweeps, 
   }
 }
 
+// Refinement sweeps when the caller gives none.  FP64 factors take one
+// sweep too: products with the explicit inverse factors lose accuracy like
+// eps * cond(L) * cond(U), which grows like N^2 on diffusion-dominated
+// operators (about 1e-6 relative residual at N = 65536); one sweep with the
+// FP64 operator brings the residual back to about 1e-12.
 static int default_sweeps(const hlevy_fac* f, const hlevy_refine* refine) {
   if (refine) return refine->sweeps;
-  return f->prec == HLEVY_PREC_MIXED ? 2 : 0;
+  return f->prec == HLEVY_PREC_MIXED ? 2 : 1;
 }
 
 hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, const hlevy_refine* refine, void* stream) {
@@ -1529,6 +1543,22 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
       stats->last_rel_residual = -1.0;
       stats->rank_overflows = f->rank_overflows;
     }
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_fac_apply(hlevy_fac* f, int32_t which, const double* x, double* y, void* stream) {
+  if (!f || !x || !y) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (x == y) return fail(HLEVY_ERR_INVALID_ARG, "x and y must not alias");
+  if (which < 0 || which > 2) return fail(HLEVY_ERR_INVALID_ARG, "which must be 0, 1 or 2");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    const int N = f->op->S.N;
+    const int32_t* perm = f->op->ds.perm.as<int32_t>();
+    const MvPlan& M = which == 0 ? f->mvG : (which == 1 ? f->mvLi : f->mvUi);
+    HL_CHECK(launch_perm_gather(f->w_z.as<double>(), x, perm, N, s));
+    M.run(f->w_z.as<double>(), epi_plain(f->w_y.as<double>()), s);
+    HL_CHECK(launch_perm_scatter(y, f->w_y.as<double>(), perm, N, s));
     return HLEVY_OK;
   });
 }

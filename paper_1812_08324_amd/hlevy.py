@@ -60,7 +60,7 @@ class KernelTimes(C.Structure):
 
 EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
            "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
-           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_fac_kernel_times", "hlevy_op_destroy",
+           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy",
            "hlevy_fac_destroy"]
 
 
@@ -83,6 +83,7 @@ def _load():
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
                         C.POINTER(Stats), vp], st),
         "hlevy_fac_kernel_times": ([vp, C.c_int32, vp, C.POINTER(KernelTimes)], st),
+        "hlevy_fac_apply": ([vp, C.c_int32, vp, vp, vp], st),
         "hlevy_op_destroy": ([vp], None),
         "hlevy_fac_destroy": ([vp], None),
     }
@@ -229,6 +230,13 @@ def _refine(refine):
     r.tol = float(refine.get("tol", 0.0))
     r.sweeps = int(refine.get("sweeps", 2))
     return C.byref(r)
+
+
+def fac_apply(fac: Fac, which: int, x, y, stream=None):
+    """y = A x with the factor's per-step matrix: 0 = G (residual operator),
+    1 = L^{-1}, 2 = U^{-1}."""
+    _check(lib.hlevy_fac_apply(fac.h, int(which), _dptr(x, fac.N), _dptr(y, fac.N), _stream(stream)),
+           "hlevy_fac_apply")
 
 
 def solve(fac: Fac, b, x, refine=None, stream=None):

@@ -1,0 +1,145 @@
+"""GPU parity at the sizes the benchmark runs (through the C ABI).
+
+The dense oracle cannot factor N = 65536 in seconds, so at that size the
+operator is compared with the oracle row by row on sampled rows, and the
+solves and the trajectory through properties that hold at any size: the
+residual of M x = b measured with that operator, and the mixed-precision
+trajectory against the FP64 one.  The full CN trajectory is compared with
+the dense oracle at N = 4096 with the same operator parameters (tempered
+s = 0.75, lambda = 1, drift 0.5, sigma^2 = 0.1, dt = 1e-4).
+"""
+import numpy as np
+import pytest
+
+from oracle.levy_oracle import Problem, cn_run, generator_dense, generator_row, quadrature_constants
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_08324_amd import hlevy
+    return hlevy
+
+
+def oracle_problem(w):
+    return Problem(dim=w.dim, n=w.n, lo=w.lo, hi=w.hi, a=w.a, b=tuple(w.b), c=w.c, s=w.s,
+                   lam=w.lam, C=w.C, r0=w.r0)
+
+
+def lib(H, w, max_rank=16):
+    p = H.make_problem(w.dim, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
+    hp = H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol, max_rank=max_rank)
+    return p, hp
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def full(H):
+    """The N = 65536 tempered workload: operator, FP64 and mixed factors."""
+    w = W.config2()
+    p, hp = lib(H, w)
+    op = H.assemble(p, hp)
+    f64 = H.factor(op, w.dt, H.PREC_FP64, 1e-12)
+    fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    return w, op, f64, fmx
+
+
+def residual(H, w, op, x, b):
+    y = torch.empty_like(x)
+    H.matvec(op, x, y)
+    r = b - (x - 0.5 * w.dt * y)
+    return float(torch.linalg.norm(r) / torch.linalg.norm(b))
+
+
+def test_operator_rows_at_full_size(H, full):
+    """y = G x at N = 65536 against oracle rows (sampled, boundaries included):
+    each row within the ACA tolerance, |y_i - g_i . x| <= 10 aca_tol |g_i| |x|."""
+    w, op, _, _ = full
+    rng = np.random.Generator(np.random.PCG64(65536))
+    x = rng.standard_normal(w.N)
+    y = torch.empty(w.N, dtype=torch.float64, device="cuda")
+    H.matvec(op, dev(x), y)
+    y = host(y)
+    p = oracle_problem(w)
+    consts = quadrature_constants(p)
+    rows = np.unique(np.concatenate([[0, 1, 63, 64, w.N // 2, w.N - 65, w.N - 2, w.N - 1],
+                                     rng.integers(0, w.N, 40)]))
+    nx = np.linalg.norm(x)
+    for i in rows:
+        g = generator_row(p, int(i), consts)
+        ref = float(g @ x)
+        assert abs(y[i] - ref) <= 10 * w.aca_tol * np.linalg.norm(g) * nx, (int(i), y[i], ref)
+
+
+@pytest.mark.parametrize("kind", ["smooth", "random"])
+def test_fp64_solve_residual_at_full_size(H, full, kind):
+    """FP64 factors with the default refinement sweep: relative residual of
+    M x = b at N = 65536 below 1e-10."""
+    w, op, f64, _ = full
+    if kind == "smooth":
+        b = dev(w.u0)
+    else:
+        b = dev(np.random.Generator(np.random.PCG64(7)).standard_normal(w.N))
+    x = torch.empty_like(b)
+    H.solve(f64, b, x)
+    assert residual(H, w, op, x, b) < 1e-10
+
+
+def test_mixed_solve_residual_at_full_size(H, full):
+    """Mixed factors (FP32 inverse factors at 1e-6): one sweep reaches the
+    floor set by the FP32 far field of the residual operator."""
+    w, op, _, fmx = full
+    b = dev(np.random.Generator(np.random.PCG64(8)).standard_normal(w.N))
+    x = torch.empty_like(b)
+    res = []
+    for sweeps in (0, 1, 2):
+        H.solve(fmx, b, x, refine={"sweeps": sweeps})
+        res.append(residual(H, w, op, x, b))
+    assert res[0] < 1e-4, res
+    assert res[1] < 1e-9 and res[2] < 1e-9, res
+
+
+def test_mixed_trajectory_at_full_size(H, full):
+    """1000 CN steps at N = 65536: the mixed path (one sweep per step) within
+    rel-L2 1e-8 of the FP64 path."""
+    w, op, f64, fmx = full
+    ua = dev(w.u0)
+    ub = dev(w.u0)
+    H.step(f64, ua, w.steps)
+    H.step(fmx, ub, w.steps, refine={"sweeps": 1})
+    err = float(torch.linalg.norm(ua - ub) / torch.linalg.norm(ua))
+    assert err <= 1e-8, err
+
+
+def test_tempered_trajectory_vs_oracle_n4096(H):
+    """The tempered workload's operator at N = 4096, 200 CN steps: FP64 path
+    within 1e-10 and mixed path within 1e-8 of the dense oracle."""
+    w = W.config2(n=4096, steps=200)
+    p, hp = lib(H, w)
+    op = H.assemble(p, hp)
+    ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0).u
+    nref = np.linalg.norm(ref)
+    f64 = H.factor(op, w.dt, H.PREC_FP64, 1e-12)
+    u = dev(w.u0)
+    H.step(f64, u, w.steps)
+    e64 = np.linalg.norm(host(u) - ref) / nref
+    fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    u = dev(w.u0)
+    H.step(fmx, u, w.steps, refine={"sweeps": 1})
+    emx = np.linalg.norm(host(u) - ref) / nref
+    assert e64 <= 1e-10, e64
+    assert emx <= 1e-8, emx
