@@ -35,14 +35,27 @@ struct MvRow {
   int32_t lo, hi, ebeg, eend;
 };
 
-enum { MV_EPI_PLAIN = 0, MV_EPI_RHS = 1, MV_EPI_RESID = 2, MV_EPI_ADD = 3 };
+// Epilogues of the gather (v = the product's row value, r = the row):
+//   PLAIN: y = v
+//   RHS:   y = u + hdt v + cg g            (right side (I + dt/2 G) u + forcing)
+//   RESID: y = b - (u - hdt v)             (residual of M x = b, x in u)
+//   ADD:   y = u + v                       (refinement update)
+//   AXPY:  y = hdt v + cg g                (g may be null)
+//   CNRES: y = 2 u + cg g - (b - hdt v)    (residual of M w = 2 u + cg g, w in b)
+//   NEXT:  y = b + v - u                   (u^{n+1} = w - u^n after the last update)
+//   SUB:   y = v - u
+// y may alias u or b: every row is read and written by the same thread.
+enum {
+  MV_EPI_PLAIN = 0, MV_EPI_RHS = 1, MV_EPI_RESID = 2, MV_EPI_ADD = 3,
+  MV_EPI_AXPY = 4, MV_EPI_CNRES = 5, MV_EPI_NEXT = 6, MV_EPI_SUB = 7
+};
 
 struct MvEpi {
   int32_t kind, pad;
   double hdt, cg;
-  const double* u;   // RHS: u;  RESID: x;  ADD: u
-  const double* g;   // RHS forcing profile or nullptr
-  const double* b;   // RESID: b
+  const double* u;
+  const double* g;   // forcing profile or nullptr
+  const double* b;
   double* y;
 };
 

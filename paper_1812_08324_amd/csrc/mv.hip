@@ -224,6 +224,18 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
       case MV_EPI_ADD:    // y = u + A x (refinement update)
         out = epi.u[r] + v;
         break;
+      case MV_EPI_AXPY:
+        out = epi.hdt * v + (epi.g ? epi.cg * epi.g[r] : 0.0);
+        break;
+      case MV_EPI_CNRES:
+        out = (2.0 * epi.u[r] + (epi.g ? epi.cg * epi.g[r] : 0.0)) - (epi.b[r] - epi.hdt * v);
+        break;
+      case MV_EPI_NEXT:
+        out = (epi.b[r] + v) - epi.u[r];
+        break;
+      case MV_EPI_SUB:
+        out = v - epi.u[r];
+        break;
       default:
         out = v;
     }

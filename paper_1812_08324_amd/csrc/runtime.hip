@@ -1518,23 +1518,63 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
     const int32_t* perm = f->op->ds.perm.as<int32_t>();
     const double hdt = 0.5 * f->dt;
     const int sweeps = default_sweeps(f, refine);
-    double* uc = f->w_u.as<double>();
-    double* b = f->w_r.as<double>();
+    // Since I + dt/2 G = 2 I - M, each step solves M w = 2 u^n + F_n
+    // (F_n = dt/2 (phi_n + phi_{n+1}) g) and sets u^{n+1} = w - u^n: one
+    // product with G per refinement sweep and none for the right side.
+    double* uc = f->w_u.as<double>();   // u^n
+    double* w = f->w_d.as<double>();    // iterate of M w = 2 u^n + F_n
+    double* z = f->w_z.as<double>();
+    double* r = f->w_y.as<double>();
+    double* gc = f->w_g.as<double>();   // g (cluster order)
+    double* lg = f->w_b.as<double>();   // L^{-1} g
     HL_CHECK(launch_perm_gather(uc, u, perm, N, s));
-    if (g) HL_CHECK(launch_perm_gather(f->w_g.as<double>(), g, perm, N, s));
+    if (g) {
+      HL_CHECK(launch_perm_gather(gc, g, perm, N, s));
+      f->mvLi.run(gc, epi_plain(lg), s);
+    }
     for (int64_t n = 0; n < nsteps; ++n) {
-      // b = (I + dt/2 G) u^n + dt/2 (phi_n + phi_{n+1}) g
-      MvEpi rhs{};
-      rhs.kind = MV_EPI_RHS;
-      rhs.hdt = hdt;
-      rhs.cg = g ? hdt * (phi[n] + phi[n + 1]) : 0.0;
-      rhs.u = uc;
-      rhs.g = g ? f->w_g.as<double>() : nullptr;
-      rhs.y = b;
-      f->mvG.run(uc, rhs, s);
-      // u^{n+1} = U^{-1} L^{-1} b, then refinement sweeps
-      fac_apply_inverse(f, b, uc, nullptr, s);
-      refine_sweeps(f, b, uc, sweeps, s);
+      const double cg = g ? hdt * (phi[n] + phi[n + 1]) : 0.0;
+      // z = L^{-1} (2 u^n + F_n) = 2 L^{-1} u^n + cg L^{-1} g
+      MvEpi e{};
+      e.kind = MV_EPI_AXPY;
+      e.hdt = 2.0;
+      e.cg = cg;
+      e.g = g ? lg : nullptr;
+      e.y = z;
+      f->mvLi.run(uc, e, s);
+      if (sweeps == 0) {
+        MvEpi e2{};
+        e2.kind = MV_EPI_SUB;   // u^{n+1} = U^{-1} z - u^n
+        e2.u = uc;
+        e2.y = uc;
+        f->mvUi.run(z, e2, s);
+        continue;
+      }
+      f->mvUi.run(z, epi_plain(w), s);
+      for (int it = 0; it < sweeps; ++it) {
+        MvEpi e3{};
+        e3.kind = MV_EPI_CNRES;   // r = 2 u^n + F_n - (w - dt/2 G w)
+        e3.hdt = hdt;
+        e3.cg = cg;
+        e3.u = uc;
+        e3.g = g ? gc : nullptr;
+        e3.b = w;
+        e3.y = r;
+        f->mvG.run(w, e3, s);
+        f->mvLi.run(r, epi_plain(z), s);
+        MvEpi e4{};
+        if (it + 1 < sweeps) {
+          e4.kind = MV_EPI_ADD;   // w += U^{-1} L^{-1} r
+          e4.u = w;
+          e4.y = w;
+        } else {
+          e4.kind = MV_EPI_NEXT;   // u^{n+1} = w + U^{-1} L^{-1} r - u^n
+          e4.b = w;
+          e4.u = uc;
+          e4.y = uc;
+        }
+        f->mvUi.run(z, e4, s);
+      }
     }
     HL_CHECK(launch_perm_scatter(u, uc, perm, N, s));
     if (stats) {
