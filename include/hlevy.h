@@ -161,6 +161,21 @@ hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream);
 hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu_tol,
                           void* stream, hlevy_fac** out);
 
+/* Batched worklist: factor M_i = I - dt[i]/2 G_i of `count` independent
+ * problems (ops[i], each assembled by hlevy_assemble) in one plan.  The H-LU
+ * recursion of App. B.3 runs jointly over the problems, aligned from the
+ * leaves upwards, so every batch of products, copies and rounded additions
+ * is one launch for all of them (a problem's result is the same as with
+ * hlevy_factor).  Problems are taken in groups whose factorisation memory
+ * fits `workspace_bytes` (0 = 48 GiB); each group is one plan.  prec and
+ * lu_tol as for hlevy_factor, common to all problems.  out[i] receives
+ * problem i's factor (each used and destroyed on its own).  A group shares
+ * its zero-pivot flag and rank-overflow count.  On error every out[i] is
+ * NULL and nothing is leaked.  Synchronises `stream`. */
+hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, int32_t count,
+                                  int32_t prec, double lu_tol, size_t workspace_bytes,
+                                  void* stream, hlevy_fac** out);
+
 /* Solve M x = b: x = U^{-1} (L^{-1} b) through the inverse factors (forward
  * then backward solve), then refine->sweeps sweeps of
  * x <- x + U^{-1} L^{-1} (b - M x) with the residual in FP64.  refine may
@@ -181,6 +196,18 @@ hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x,
 hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double* g,
                         const double* phi, const hlevy_refine* refine,
                         hlevy_stats* stats, void* stream);
+
+/* Batched worklist: advance u[i] (device, natural order, in/out) of the
+ * `count` problems facs[i] by nsteps Crank-Nicolson steps each, without
+ * forcing (eq. equ:scheme with f = 0), each with its own dt.  Every product
+ * of a step is one projection and one gather launch over all problems (per
+ * group of equal rank bucket), so small problems share the chip.  Sweeps
+ * per step: refine->sweeps, or when refine is NULL the largest default of
+ * hlevy_step among the factors.  The factors must be distinct (each one's
+ * work vectors are used); the result of each problem is the same as
+ * hlevy_step on it alone.  Synchronises `stream`. */
+hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_t count,
+                                int64_t nsteps, const hlevy_refine* refine, void* stream);
 
 /* y = A x with one of the matrices the factor applies every step, in the
  * storage precision of the factor: which = 0: the generator G of the

@@ -27,7 +27,10 @@ struct DevLists {
 // covering rows [rlo, rhi) and cols [clo, chi).  op = identity (trans = 0):
 // X has rows indexed from clo, Y from rlo.  trans = 1: X rows from rlo,
 // Y rows from clo.  kx columns (device int, or kxcap when kx == nullptr).
+// dl: the leaf-cluster lists of the matrix's block tree (jobs of one launch
+// may belong to different problems).
 struct ApplyJob {
+  DevLists dl;
   const LeafDesc* L;
   const int32_t* rank;
   int32_t lbeg, lend;

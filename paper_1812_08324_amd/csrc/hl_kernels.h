@@ -23,7 +23,7 @@ hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, 
 hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s);
 hipError_t launch_lu_inv(const LuInvItem* items, int n, int32_t* zero_pivot, hipStream_t s);
 hipError_t launch_apply(const ApplyJob* jobs, const ProjItem* proj, int nproj, const GatherItem* gat,
-                        int ngat, const DevLists& dl, hipStream_t s);
+                        int ngat, hipStream_t s);
 hipError_t launch_perm_gather(double* out, const double* in, const int32_t* perm, int N, hipStream_t s);
 hipError_t launch_perm_scatter(double* out, const double* in, const int32_t* perm, int N, hipStream_t s);
 hipError_t launch_axpy2(double* out, const double* x, double a, const double* y, double cg,

@@ -69,7 +69,20 @@ struct MvDev {
   int32_t dense_f32;   // dense leaves stored in FP32 (else FP64)
 };
 
+// One problem of a batched product: its plan, input and epilogue.
+struct MvInst {
+  MvDev dev;
+  const double* x;
+  MvEpi epi;
+};
+
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
+// Batched product over problems of one rank bucket kb and dense precision:
+// wmap[w] = (problem, tile) for the nw projection wavefronts, rmap[b] =
+// (problem, leaf cluster) for the nr gather workgroups; every problem's
+// partials go to its own buffer.
+hipError_t mv_batch_launch(const MvInst* inst, const int2* wmap, int nw, const int2* rmap, int nr, int kb,
+                           bool dense_f32, hipStream_t s);
 // the two kernels of mv_launch separately; non-null events are attached to
 // the dispatch (start, stop) for timing
 hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0 = nullptr,

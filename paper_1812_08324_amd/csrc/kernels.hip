@@ -1808,11 +1808,11 @@ __global__ void __launch_bounds__(HL_BLOCK) k_apply_proj(const ApplyJob* jobs, c
   }
 }
 
-__global__ void __launch_bounds__(HL_BLOCK) k_apply_gather(const ApplyJob* jobs, const GatherItem* items,
-                                                           DevLists dl) {
+__global__ void __launch_bounds__(HL_BLOCK) k_apply_gather(const ApplyJob* jobs, const GatherItem* items) {
   __shared__ double Xs[64 * KMAX];
   const GatherItem it = items[blockIdx.x];
   const ApplyJob J = jobs[it.job];
+  const DevLists& dl = J.dl;
   const int lo = dl.lc_lo[it.lpos], hi = dl.lc_hi[it.lpos];
   const int mr = hi - lo;
   const int kx = J.kx ? *J.kx : J.kxcap;
@@ -2003,9 +2003,9 @@ hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, 
   return post();
 }
 hipError_t launch_apply(const ApplyJob* jobs, const ProjItem* proj, int nproj, const GatherItem* gat,
-                        int ngat, const DevLists& dl, hipStream_t s) {
+                        int ngat, hipStream_t s) {
   if (nproj > 0) hipLaunchKernelGGL(k_apply_proj, dim3(nproj), dim3(HL_BLOCK), 0, s, jobs, proj);
-  if (ngat > 0) hipLaunchKernelGGL(k_apply_gather, dim3(ngat), dim3(HL_BLOCK), 0, s, jobs, gat, dl);
+  if (ngat > 0) hipLaunchKernelGGL(k_apply_gather, dim3(ngat), dim3(HL_BLOCK), 0, s, jobs, gat);
   return post();
 }
 static inline dim3 grid1(int N) { return dim3((N + HL_BLOCK - 1) / HL_BLOCK); }

@@ -121,16 +121,33 @@ __device__ __forceinline__ void project_tile(const MvTile& T, const double* __re
 }
 
 template <int KB>
-__global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ tiles, int ntiles,
-                                                    const double* __restrict__ x, double* __restrict__ part) {
-  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= ntiles) return;   // the whole wavefront leaves; no block barrier below
-  const int lane = threadIdx.x & 63;
-  const MvTile T = tiles[wid];
+__device__ __forceinline__ void project_any(const MvTile& T, const double* __restrict__ x,
+                                            double* __restrict__ part, int lane) {
   if (wuni(T.f32))
     project_tile<float, KB>(T, x, part, lane);
   else
     project_tile<double, KB>(T, x, part, lane);
+}
+
+template <int KB>
+__global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ tiles, int ntiles,
+                                                    const double* __restrict__ x, double* __restrict__ part) {
+  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= ntiles) return;   // the whole wavefront leaves; no block barrier below
+  const MvTile T = tiles[wid];
+  project_any<KB>(T, x, part, threadIdx.x & 63);
+}
+
+// batched: wavefront w takes tile map[w].y of problem map[w].x
+template <int KB>
+__global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__ inst,
+                                                      const int2* __restrict__ map, int nw) {
+  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= nw) return;
+  const int2 m = map[wid];
+  const MvInst& P = inst[wuni(m.x)];
+  const MvTile T = P.dev.tiles[wuni(m.y)];
+  project_any<KB>(T, P.x, P.dev.part, threadIdx.x & 63);
 }
 
 constexpr int MV_GW = 8;   // wavefronts per gather workgroup
@@ -149,15 +166,21 @@ __device__ __forceinline__ double gather_lowrank(const void* p, int ii, int ld, 
   return acc;
 }
 
+template <int KB>
+struct GatherLds {
+  double red[MV_GW][64];
+  MvEntry se[MV_EMAX];
+  double ts[MV_EMAX * KB];
+};
+
+// one leaf cluster: y[R] = epilogue(sum over the entries of R)
 template <typename TD, int KB>
-__global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restrict__ rows,
-                                                          const MvEntry* __restrict__ ents,
-                                                          const double* __restrict__ x,
-                                                          const double* __restrict__ part, MvEpi epi) {
-  __shared__ double red[MV_GW][64];
-  __shared__ MvEntry se[MV_EMAX];
-  __shared__ double ts[MV_EMAX * KB];
-  const MvRow R = rows[blockIdx.x];
+__device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __restrict__ ents,
+                                            const double* __restrict__ x, const double* __restrict__ part,
+                                            const MvEpi& epi, GatherLds<KB>& L) {
+  auto& red = L.red;
+  auto& se = L.se;
+  auto& ts = L.ts;
   const int i = threadIdx.x & 63, g = wuni(threadIdx.x >> 6);
   const int mr = R.hi - R.lo;
   const int ii = i < mr ? i : mr - 1;   // clamped row: loads stay in bounds, result discarded
@@ -243,6 +266,28 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
   }
 }
 
+template <typename TD, int KB>
+__global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restrict__ rows,
+                                                          const MvEntry* __restrict__ ents,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ part, MvEpi epi) {
+  __shared__ GatherLds<KB> L;
+  const MvRow R = rows[blockIdx.x];
+  gather_rows<TD, KB>(R, ents, x, part, epi, L);
+}
+
+// batched: workgroup b takes leaf cluster map[b].y of problem map[b].x
+template <typename TD, int KB>
+__global__ void __launch_bounds__(64 * MV_GW) k_mv_gather_b(const MvInst* __restrict__ inst,
+                                                            const int2* __restrict__ map) {
+  __shared__ GatherLds<KB> L;
+  const int2 m = map[blockIdx.x];
+  const MvInst& P = inst[wuni(m.x)];
+  const MvRow R = P.dev.rows[wuni(m.y)];
+  const MvEpi epi = P.epi;
+  gather_rows<TD, KB>(R, P.dev.ents, P.x, P.dev.part, epi, L);
+}
+
 int project_rows_per_pass(int kb, bool f32) {
   const int vals = f32 ? 64 : 32;
   return 64 * (vals / kb);
@@ -302,6 +347,31 @@ hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipS
     gather_kb<float>(M, x, epi, s, e0, e1);
   else
     gather_kb<double>(M, x, epi, s, e0, e1);
+  return hipGetLastError();
+}
+
+template <int KB>
+static void batch_t(const MvInst* inst, const int2* wmap, int nw, const int2* rmap, int nr, bool dense_f32,
+                    hipStream_t s) {
+  if (nw > 0) hipLaunchKernelGGL((k_mv_project_b<KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw);
+  if (nr > 0) {
+    if (dense_f32)
+      hipLaunchKernelGGL((k_mv_gather_b<float, KB>), dim3(nr), dim3(64 * MV_GW), 0, s, inst, rmap);
+    else
+      hipLaunchKernelGGL((k_mv_gather_b<double, KB>), dim3(nr), dim3(64 * MV_GW), 0, s, inst, rmap);
+  }
+}
+
+hipError_t mv_batch_launch(const MvInst* inst, const int2* wmap, int nw, const int2* rmap, int nr, int kb,
+                           bool dense_f32, hipStream_t s) {
+  if (kb == 8)
+    batch_t<8>(inst, wmap, nw, rmap, nr, dense_f32, s);
+  else if (kb == 16)
+    batch_t<16>(inst, wmap, nw, rmap, nr, dense_f32, s);
+  else if (kb == 32)
+    batch_t<32>(inst, wmap, nw, rmap, nr, dense_f32, s);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

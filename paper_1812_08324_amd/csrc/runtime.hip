@@ -9,6 +9,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <map>
+#include <set>
 #include <memory>
 #include <string>
 #include <chrono>
@@ -163,7 +164,9 @@ struct HMat {
   // dense_leaf_level: admissible blocks between two leaf clusters are held
   // dense in this matrix (the factorisation workspace), so that updates of
   // leaf-level blocks need no rounded addition.
-  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s, bool dense_leaf_level = false) {
+  // leaf descriptors with offsets into the pool (no allocation); returns
+  // the pool size in doubles
+  size_t layout(const Structure& st, int kcap_max, Shape shape, bool dense_leaf_level) {
     S = &st;
     L.resize(st.lf.size());
     size_t off = 0;
@@ -191,7 +194,11 @@ struct HMat {
       L[l] = d;
     }
     pool_doubles = off;
-    pool.alloc(std::max<size_t>(off, 1) * sizeof(double));
+    return off;
+  }
+  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s, bool dense_leaf_level = false) {
+    layout(st, kcap_max, shape, dense_leaf_level);
+    pool.alloc(std::max<size_t>(pool_doubles, 1) * sizeof(double));
     double* base = pool.as<double>();
     for (auto& d : L) {
       if (d.kind == K_DENSE) d.A = base + reinterpret_cast<size_t>(d.A);
@@ -275,12 +282,12 @@ struct Plan {
     upload(dluinv, luinv, s);
   }
 
-  void run(const DevLists& dl, int32_t* zero_pivot, hipStream_t s) const {
+  void run(int32_t* zero_pivot, hipStream_t s) const {
     for (const Phase& p : ph) {
       switch (p.type) {
         case PH_APPLY:
           HL_CHECK(launch_apply(djobs.as<ApplyJob>(), dproj.as<ProjItem>() + p.b0, p.n0,
-                                dgath.as<GatherItem>() + p.b1, p.n1, dl, s));
+                                dgath.as<GatherItem>() + p.b1, p.n1, s));
           break;
         case PH_DPROD:
           HL_CHECK(launch_dense_prod(ddprod.as<DProdItem>() + p.b0, p.n0, s));
@@ -338,13 +345,16 @@ struct PendingTerm {
   int kcap;   // capacity bound of the term's rank
 };
 
+// The builder takes work of several problems at once: every matrix carries its
+// own block structure, and the products, copies and rounded additions of one
+// batch land in the same phases whichever problem they belong to.
 struct Builder {
-  const Structure& S;
   Plan& P;
   WsStack& ws;
-  const DevStructure& ds;
+  const double* ident;   // 64 x 64 identity on the device
   int32_t* overflow;
   double tol;
+  std::map<const Structure*, DevLists> lists_of;
   // batch state
   std::vector<ApplyJob> bjobs;
   std::vector<const HMat*> bjob_mat;
@@ -353,10 +363,11 @@ struct Builder {
   WsStack::Mark mk{};
   bool in_batch = false;
 
-  Builder(const Structure& s, Plan& p, WsStack& w, const DevStructure& d, int32_t* ovf, double t)
-      : S(s), P(p), ws(w), ds(d), overflow(ovf), tol(t) {}
+  Builder(Plan& p, WsStack& w, const double* id, int32_t* ovf, double t)
+      : P(p), ws(w), ident(id), overflow(ovf), tol(t) {}
 
-  int csize(int c) const { return S.cl[c].hi - S.cl[c].lo; }
+  // registers the block structure of a problem (its leaf-cluster lists)
+  void add_problem(const Structure& S, const DevStructure& ds) { lists_of[&S] = ds.lists; }
 
   void begin() {
     mk = ws.mark();
@@ -365,8 +376,12 @@ struct Builder {
 
   void add_apply(HMat* M, int node, int trans, const double* X, int ldx, const int32_t* kx, int kxcap,
                  double* Y, int ldy) {
+    const Structure& S = *M->S;
     const BNode& b = S.bn[node];
     ApplyJob J{};
+    auto li = lists_of.find(&S);
+    if (li == lists_of.end()) throw DeviceError("internal: unregistered block structure");
+    J.dl = li->second;
     J.L = M->dev();
     J.rank = M->rank;
     J.lbeg = b.lbeg;
@@ -391,6 +406,7 @@ struct Builder {
   // push a term covering rows [r0, r1) x cols [c0, c1) (absolute) into the
   // target node of matrix C
   void push(HMat* C, int cnode, Term t, int kcap, int r0, int r1, int c0, int c1) {
+    const Structure& S = *C->S;
     const BNode& c = S.bn[cnode];
     if (c.kind == K_H) {
       for (int q = 0; q < 4; ++q) {
@@ -423,6 +439,8 @@ struct Builder {
 
   // C[cnode region] += sign * A[an] * B[bn]
   void mma(HMat* C, int cnode, HMat* A, int an, HMat* B, int bnd, double sign) {
+    const Structure& S = *C->S;
+    if (A->S != C->S || B->S != C->S) throw DeviceError("internal: product across problems");
     const BNode& a = S.bn[an];
     const BNode& b = S.bn[bnd];
     int ak = a.kind == K_H ? (int)K_H : A->L[a.leaf].kind;
@@ -558,6 +576,7 @@ struct Builder {
       Phase ph{PH_APPLY, (int)P.proj.size(), 0, (int)P.gath.size(), 0, 0, 0, 0.0};
       for (size_t q = 0; q < bjobs.size(); ++q) {
         const ApplyJob& J = bjobs[q];
+        const Structure& S = *bjob_mat[q]->S;
         P.jobs.push_back(J);
         for (int l = J.lbeg; l < J.lend; ++l)
           if (bjob_mat[q]->L[l].kind == K_LR) P.proj.push_back(ProjItem{jb + (int)q, l});
@@ -644,7 +663,7 @@ struct Builder {
             lt.nc = c1 - c0;
             lt.U = c.src.U + (size_t)c.src.ldu * c0;
             lt.ldu = c.src.ldu;
-            lt.W = ds.ident.as<double>();
+            lt.W = ident;
             lt.ldw = 64;
             lt.kfix = c1 - c0;
             lt.sign = 1.0;
@@ -763,25 +782,20 @@ struct Builder {
     in_batch = false;
   }
 
-  // Copies of the leaves of `nodes` (src null: zero) in one phase; move =
-  // clear the source after the copy.
-  void copy_nodes(HMat* dst, HMat* src, std::initializer_list<int> nodes, bool move) {
-    Phase ph{PH_COPY, (int)P.copies.size(), 0, 0, 0, 0, 0, 0.0};
-    for (int node : nodes) add_copies(dst, src, node, 1.0, false, false, move);
-    ph.n0 = (int)P.copies.size() - ph.b0;
+  // Copies of leaves (add_copies) between copy_begin() and copy_end() go to
+  // one phase.
+  int copy_begin() const { return (int)P.copies.size(); }
+  void copy_end(int b0) {
+    Phase ph{PH_COPY, b0, (int)P.copies.size() - b0, 0, 0, 0, 0, 0.0};
     if (ph.n0) P.ph.push_back(ph);
   }
 
-  void copy_node(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag,
-                 bool skip_compress = false) {
-    Phase ph{PH_COPY, (int)P.copies.size(), 0, 0, 0, 0, 0, 0.0};
-    add_copies(dst, src, node, scale, add_identity_diag, skip_compress, false);
-    ph.n0 = (int)P.copies.size() - ph.b0;
-    if (ph.n0) P.ph.push_back(ph);
-  }
-
+  // Copies the leaves of `node` of src (null: zeros) into dst, scaled;
+  // add_identity_diag adds I to dense diagonal leaves; skip_compress leaves
+  // out low-rank destinations of dense sources; move clears the source.
   void add_copies(HMat* dst, HMat* src, int node, double scale, bool add_identity_diag, bool skip_compress,
                   bool move) {
+    const Structure& S = *dst->S;
     const BNode& b = S.bn[node];
     for (int l = b.lbeg; l < b.lend; ++l) {
       const LeafDesc& d = dst->L[l];
@@ -814,21 +828,29 @@ struct Builder {
     }
   }
 
-  void zero_node(HMat* dst, int node) { copy_node(dst, nullptr, node, 0.0, false); }
 };
 
-// H-LU of the diagonal block `node` with the H-inverses of both factors
-// (App. B.3 recursion; inverses by the 2x2 block formulas):
+// H-LU of a diagonal block with the H-inverses of both factors (App. B.3
+// recursion; inverses by the 2x2 block formulas):
 //   LU(A11);  U12 = L11^{-1} A12;  L21 = A21 U11^{-1};  LU(A22 - L21 U12);
 //   (L^{-1})21 = -L22^{-1} L21 L11^{-1};  (U^{-1})12 = -U11^{-1} U12 U22^{-1}.
 // T21 = L21 L11^{-1} and S12 = U11^{-1} U12 are formed together with the
 // Schur update, so that each level takes three batches of products.
+struct LuCtx {
+  HMat *LU, *Li, *Ui, *TMP;
+};
+struct LuNode {
+  const LuCtx* c;
+  int node;
+};
+
 // A diagonal node that is one dense leaf, or 2 x 2 dense leaves of at most
 // LUINV_N rows in all, is factored with its inverses by one fused kernel.
-static bool emit_dense_luinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, int node) {
-  const Structure& S = B.S;
+static bool luinv_item(const LuCtx& c, int node, LuInvItem* out) {
+  const Structure& S = *c.LU->S;
+  const HMat *LU = c.LU, *Li = c.Li, *Ui = c.Ui;
   const BNode& b = S.bn[node];
-  if (B.csize(b.r) > LUINV_N) return false;
+  if (S.cl[b.r].hi - S.cl[b.r].lo > LUINV_N) return false;
   LuInvItem it{};
   if (b.kind != K_H) {
     const int l = b.leaf;
@@ -841,9 +863,9 @@ static bool emit_dense_luinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, int node)
   } else {
     int lf[4];
     for (int q = 0; q < 4; ++q) {
-      const BNode& c = S.bn[b.child[q]];
-      if (c.kind == K_H || LU->L[c.leaf].kind != K_DENSE) return false;
-      lf[q] = c.leaf;
+      const BNode& ch = S.bn[b.child[q]];
+      if (ch.kind == K_H || LU->L[ch.leaf].kind != K_DENSE) return false;
+      lf[q] = ch.leaf;
     }
     // Li: 11, 21, 22 dense (12 structurally zero); Ui: 11, 12, 22 dense
     if (Li->L[lf[0]].kind != K_DENSE || Li->L[lf[2]].kind != K_DENSE || Li->L[lf[3]].kind != K_DENSE ||
@@ -862,83 +884,88 @@ static bool emit_dense_luinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, int node)
     it.m1 = LU->L[lf[0]].m;
     it.m2 = LU->L[lf[3]].m;
   }
-  Phase ph{PH_LUINV, (int)B.P.luinv.size(), 1, 0, 0, 0, 0, 0.0};
-  B.P.luinv.push_back(it);
-  B.P.ph.push_back(ph);
+  if (out) *out = it;
   return true;
 }
 
-static void hluinv(Builder& B, HMat* LU, HMat* Li, HMat* Ui, HMat* TMP, int node) {
-  const BNode& b = B.S.bn[node];
-  if (emit_dense_luinv(B, LU, Li, Ui, node)) return;
-  if (b.kind != K_H) {
-    const LeafDesc& d = LU->L[b.leaf];
-    Phase ph{PH_GETRF, (int)B.P.getrf.size(), 1, 0, 0, 0, 0, 0.0};
-    B.P.getrf.push_back(GetrfItem{d.A, Li->L[b.leaf].A, Ui->L[b.leaf].A, d.m, 0});
-    B.P.ph.push_back(ph);
-    return;
-  }
-  const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
-  hluinv(B, LU, Li, Ui, TMP, n11);
-  // TMP blocks start (and are left by the move below) at zero
-  B.begin();
-  B.mma(TMP, n12, Li, n11, LU, n12, 1.0);   // U12 = L11^{-1} A12
-  B.mma(TMP, n21, LU, n21, Ui, n11, 1.0);   // L21 = A21 U11^{-1}
-  B.end();
-  B.copy_nodes(LU, TMP, {n12, n21}, /*move=*/true);
-  B.begin();
-  B.mma(LU, n22, LU, n21, LU, n12, -1.0);   // A22 -= L21 U12
-  B.mma(TMP, n21, LU, n21, Li, n11, 1.0);   // T21 = L21 L11^{-1}
-  B.mma(TMP, n12, Ui, n11, LU, n12, 1.0);   // S12 = U11^{-1} U12
-  B.end();
-  hluinv(B, LU, Li, Ui, TMP, n22);
-  B.begin();
-  B.mma(Li, n21, Li, n22, TMP, n21, -1.0);  // (L^{-1})21 = -L22^{-1} T21
-  B.mma(Ui, n12, TMP, n12, Ui, n22, -1.0);  // (U^{-1})12 = -S12 U22^{-1}
-  B.end();
+// levels of the recursion below a diagonal node (0: factored by one kernel)
+static int lu_height(const LuCtx& c, int node) {
+  const BNode& b = c.LU->S->bn[node];
+  if (b.kind != K_H || luinv_item(c, node, nullptr)) return 0;
+  return 1 + std::max(lu_height(c, b.child[0]), lu_height(c, b.child[3]));
 }
 
-// A full-matrix apply y = M x (cluster order) with static buffers.
-struct ApplyPlan {
-  DevBuf djob, dproj, dgath, T;
-  int nproj = 0, ngath = 0;
-  void create(const Structure& S, const HMat& M, const double* X, double* Y, hipStream_t s) {
-    ApplyJob J{};
-    J.L = M.dev();
-    J.rank = M.rank;
-    J.lbeg = 0;
-    J.lend = (int)S.lf.size();
-    J.rlo = 0;
-    J.rhi = S.N;
-    J.clo = 0;
-    J.chi = S.N;
-    J.trans = 0;
-    J.ldx = S.N;
-    J.ldy = S.N;
-    J.kxcap = 1;
-    J.X = X;
-    J.kx = nullptr;
-    J.Y = Y;
-    J.tstride = 32;
-    T.alloc(S.lf.size() * 32 * sizeof(double));
-    J.T = T.as<double>();
-    std::vector<ApplyJob> jv{J};
-    std::vector<ProjItem> pv;
-    std::vector<GatherItem> gv;
-    for (size_t l = 0; l < S.lf.size(); ++l)
-      if (M.L[l].kind == K_LR) pv.push_back(ProjItem{0, (int)l});
-    for (size_t lp = 0; lp < S.leafcl.size(); ++lp) gv.push_back(GatherItem{0, (int)lp});
-    upload(djob, jv, s);
-    upload(dproj, pv, s);
-    upload(dgath, gv, s);
-    nproj = (int)pv.size();
-    ngath = (int)gv.size();
+// The recursion over several diagonal nodes at once (of one or of several
+// problems), aligned from the bottom: the nodes of height H take the three
+// batches of their level together, and nodes of smaller height wait inside
+// the first sub-recursion until their own level comes.  With one node this
+// is the plain recursion.
+static void hluinv_joint(Builder& B, const std::vector<LuNode>& items, int H) {
+  if (items.empty()) return;
+  if (H == 0) {
+    Phase pl{PH_LUINV, (int)B.P.luinv.size(), 0, 0, 0, 0, 0, 0.0};
+    std::vector<GetrfItem> gi;
+    for (const LuNode& it : items) {
+      LuInvItem li;
+      if (luinv_item(*it.c, it.node, &li)) {
+        B.P.luinv.push_back(li);
+        continue;
+      }
+      const BNode& b = it.c->LU->S->bn[it.node];
+      const LeafDesc& d = it.c->LU->L[b.leaf];
+      gi.push_back(GetrfItem{d.A, it.c->Li->L[b.leaf].A, it.c->Ui->L[b.leaf].A, d.m, 0});
+    }
+    pl.n0 = (int)B.P.luinv.size() - pl.b0;
+    if (pl.n0) B.P.ph.push_back(pl);
+    if (!gi.empty()) {
+      B.P.ph.push_back(Phase{PH_GETRF, (int)B.P.getrf.size(), (int)gi.size(), 0, 0, 0, 0, 0.0});
+      for (auto& g : gi) B.P.getrf.push_back(g);
+    }
+    return;
   }
-  void run(const DevLists& dl, hipStream_t s) const {
-    HL_CHECK(launch_apply(djob.as<ApplyJob>(), dproj.as<ProjItem>(), nproj, dgath.as<GatherItem>(), ngath,
-                          dl, s));
+  std::vector<LuNode> act, sub;
+  for (const LuNode& it : items) (lu_height(*it.c, it.node) == H ? act : sub).push_back(it);
+  for (const LuNode& a : act) sub.push_back({a.c, a.c->LU->S->bn[a.node].child[0]});
+  hluinv_joint(B, sub, H - 1);
+  // TMP blocks start (and are left by the move below) at zero
+  B.begin();
+  for (const LuNode& a : act) {
+    const BNode& b = a.c->LU->S->bn[a.node];
+    const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2];
+    const LuCtx& c = *a.c;
+    B.mma(c.TMP, n12, c.Li, n11, c.LU, n12, 1.0);   // U12 = L11^{-1} A12
+    B.mma(c.TMP, n21, c.LU, n21, c.Ui, n11, 1.0);   // L21 = A21 U11^{-1}
   }
-};
+  B.end();
+  const int cb = B.copy_begin();
+  for (const LuNode& a : act) {
+    const BNode& b = a.c->LU->S->bn[a.node];
+    for (int q : {1, 2}) B.add_copies(a.c->LU, a.c->TMP, b.child[q], 1.0, false, false, /*move=*/true);
+  }
+  B.copy_end(cb);
+  B.begin();
+  for (const LuNode& a : act) {
+    const BNode& b = a.c->LU->S->bn[a.node];
+    const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
+    const LuCtx& c = *a.c;
+    B.mma(c.LU, n22, c.LU, n21, c.LU, n12, -1.0);   // A22 -= L21 U12
+    B.mma(c.TMP, n21, c.LU, n21, c.Li, n11, 1.0);   // T21 = L21 L11^{-1}
+    B.mma(c.TMP, n12, c.Ui, n11, c.LU, n12, 1.0);   // S12 = U11^{-1} U12
+  }
+  B.end();
+  std::vector<LuNode> sub2;
+  for (const LuNode& a : act) sub2.push_back({a.c, a.c->LU->S->bn[a.node].child[3]});
+  hluinv_joint(B, sub2, H - 1);
+  B.begin();
+  for (const LuNode& a : act) {
+    const BNode& b = a.c->LU->S->bn[a.node];
+    const int n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
+    const LuCtx& c = *a.c;
+    B.mma(c.Li, n21, c.Li, n22, c.TMP, n21, -1.0);  // (L^{-1})21 = -L22^{-1} T21
+    B.mma(c.Ui, n12, c.TMP, n12, c.Ui, n22, -1.0);  // (U^{-1})12 = -S12 U22^{-1}
+  }
+  B.end();
+}
 
 // Per-step matrix-vector plan of one H-matrix: projection tiles, the
 // per-leaf-cluster entry lists and (optionally) FP32 copies of the factors.
@@ -1066,6 +1093,46 @@ struct MvPlan {
   void run(const double* x, const MvEpi& e, hipStream_t s) const { HL_CHECK(mv_launch(dev, x, e, s)); }
 };
 
+// Products with one matrix kind (G, L^{-1} or U^{-1}) of every problem of a
+// batch: problems grouped by rank bucket and dense precision, one projection
+// and one gather launch per group.  Tiles and leaf clusters of the problems
+// are interleaved, so each launch's work is spread over the whole chip.
+struct MvBatch {
+  struct Group {
+    int kb, f32, w0, nw, r0, nr;
+  };
+  std::vector<Group> groups;
+  DevBuf dw, dr;
+  void create(const std::vector<const MvPlan*>& plans, hipStream_t s) {
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (size_t i = 0; i < plans.size(); ++i) by[{plans[i]->dev.kb, plans[i]->dev.dense_f32}].push_back((int)i);
+    std::vector<int2> w, r;
+    for (auto& kv : by) {
+      Group g{kv.first.first, kv.first.second, (int)w.size(), 0, (int)r.size(), 0};
+      int tmax = 0, rmax = 0;
+      for (int i : kv.second) {
+        tmax = std::max(tmax, plans[i]->dev.ntiles);
+        rmax = std::max(rmax, plans[i]->dev.nrows);
+      }
+      for (int t = 0; t < tmax; ++t)
+        for (int i : kv.second)
+          if (t < plans[i]->dev.ntiles) w.push_back(make_int2(i, t));
+      for (int q = 0; q < rmax; ++q)
+        for (int i : kv.second)
+          if (q < plans[i]->dev.nrows) r.push_back(make_int2(i, q));
+      g.nw = (int)w.size() - g.w0;
+      g.nr = (int)r.size() - g.r0;
+      groups.push_back(g);
+    }
+    upload(dw, w, s);
+    upload(dr, r, s);
+  }
+  void run(const MvInst* inst, hipStream_t s) const {
+    for (const Group& g : groups)
+      HL_CHECK(mv_batch_launch(inst, dw.as<int2>() + g.w0, g.nw, dr.as<int2>() + g.r0, g.nr, g.kb, g.f32 != 0, s));
+  }
+};
+
 static MvEpi epi_plain(double* y) {
   MvEpi e{};
   e.kind = MV_EPI_PLAIN;
@@ -1102,7 +1169,7 @@ struct hlevy_fac {
   double dt = 0, lu_tol = 0;
   int prec = 0;
   HMat LU, Li, Ui;
-  DevBuf w_u, w_y, w_b, w_z, w_r, w_d, w_g, partial, scal, zp, ovf;
+  DevBuf w_u, w_y, w_b, w_z, w_r, w_d, w_g;
   MvPlan mvG, mvLi, mvUi;
   int32_t rank_overflows = 0;
 };
@@ -1126,6 +1193,164 @@ static hlevy_status guarded(F&& f) {
 
 static double frac_constant(int d, double s) {
   return std::pow(4.0, s) * std::tgamma(d / 2.0 + s) / (std::pow(M_PI, d / 2.0) * std::fabs(std::tgamma(-s)));
+}
+
+// Factorisation memory (bytes) of one problem while it is being factored:
+// the LU workspace, the workspace inverse factors and the temporary (leaf-
+// level blocks dense), the final inverse factors and, roughly, the product
+// workspace of the recursion.
+static constexpr size_t kDefaultFactorWorkspace = (size_t)48 << 30;
+
+static size_t factor_footprint(const hlevy_op& op) {
+  const int kc = op.hp.max_rank;
+  HMat t;
+  size_t d = 0;
+  d += 2 * t.layout(op.S, kc, FULL, true);
+  d += 2 * t.layout(op.S, kc, LOWER, true);
+  d += t.layout(op.S, kc, LOWER, false) + t.layout(op.S, kc, UPPER, false);
+  return d * sizeof(double) + (d * sizeof(double)) / 2;
+}
+
+// H-LU with inverse factors of every problem of `fs` in one plan: the
+// recursion runs jointly over the problems (hluinv_joint), so each batch of
+// products, copies and rounded additions is one launch for all of them.
+// Problems share the zero-pivot flag and the rank-overflow counter of the
+// group.
+static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, hipStream_t s) {
+  const double lu_tol = fs[0]->lu_tol;
+  const int prec = fs[0]->prec;
+  struct Work {
+    HMat Li, Ui, TMP;
+    LuCtx ctx;
+  };
+  std::vector<std::unique_ptr<Work>> wk;
+  DevBuf zpb, ovfb;
+  zpb.alloc(sizeof(int32_t));
+  ovfb.alloc(sizeof(int32_t));
+  HL_CHECK(hipMemsetAsync(zpb.p, 0, sizeof(int32_t), s));
+  HL_CHECK(hipMemsetAsync(ovfb.p, 0, sizeof(int32_t), s));
+  const double t0 = now_s();
+  for (hlevy_fac* f : fs) {
+    const Structure& S = f->op->S;
+    const int kc = f->op->hp.max_rank;
+    const bool dmax = true;   // leaf-level admissible blocks dense while factoring
+    auto w = std::make_unique<Work>();
+    f->LU.create(S, kc, FULL, s, dmax);
+    w->Li.create(S, kc, LOWER, s, dmax);
+    w->Ui.create(S, kc, UPPER, s, dmax);
+    w->TMP.create(S, kc, FULL, s, dmax);
+    f->Li.create(S, kc, LOWER, s);
+    f->Ui.create(S, kc, UPPER, s);
+    w->ctx = LuCtx{&f->LU, &w->Li, &w->Ui, &w->TMP};
+    wk.push_back(std::move(w));
+  }
+  {
+    Plan P;
+    WsStack ws;
+    Builder B(P, ws, fs[0]->op->ds.ident.as<double>(), ovfb.as<int32_t>(), lu_tol);
+    for (hlevy_fac* f : fs) B.add_problem(f->op->S, f->op->ds);
+    int cb = B.copy_begin();
+    for (hlevy_fac* f : fs)   // M = I - dt/2 G
+      B.add_copies(&f->LU, const_cast<HMat*>(&f->op->G), 0, -0.5 * f->dt, true, false, false);
+    B.copy_end(cb);
+    cb = B.copy_begin();
+    for (auto& w : wk)
+      for (HMat* z : {&w->Li, &w->Ui, &w->TMP}) B.add_copies(z, nullptr, 0, 0.0, false, false, false);
+    B.copy_end(cb);
+    std::vector<LuNode> roots;
+    int H = 0;
+    for (auto& w : wk) {
+      roots.push_back({&w->ctx, 0});
+      H = std::max(H, lu_height(w->ctx, 0));
+    }
+    hluinv_joint(B, roots, H);
+    // inverse factors in the operator's block format: dense leaf-level
+    // blocks of the workspace are truncated back to low rank
+    cb = B.copy_begin();
+    for (size_t q = 0; q < fs.size(); ++q)
+      for (int side = 0; side < 2; ++side)
+        B.add_copies(side == 0 ? &fs[q]->Li : &fs[q]->Ui, side == 0 ? &wk[q]->Li : &wk[q]->Ui, 0, 1.0, false,
+                     /*skip_compress=*/true, false);
+    B.copy_end(cb);
+    // one target per block with its dense content as 32-column terms (the
+    // fused rounded addition takes them one concatenation at a time; the
+    // targets start at rank 0)
+    std::vector<LFlushTarget> tgs;
+    std::vector<std::vector<Term>> tl;
+    for (size_t q = 0; q < fs.size(); ++q)
+      for (int side = 0; side < 2; ++side) {
+        const HMat& src = side == 0 ? wk[q]->Li : wk[q]->Ui;
+        HMat& dst = side == 0 ? fs[q]->Li : fs[q]->Ui;
+        for (size_t l = 0; l < dst.L.size(); ++l) {
+          const LeafDesc& d = dst.L[l];
+          if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
+          LFlushTarget T{};
+          T.U = d.A;
+          T.V = d.B;
+          T.rank = dst.rank + l;
+          T.m = d.m;
+          T.n = d.n;
+          T.kcap = d.kcap;
+          T.Kcap = 48;
+          std::vector<Term> terms;
+          const int w = d.kcap <= 16 ? 32 : 16;   // kcap + w <= 48
+          if (d.kcap > 32) throw DeviceError("internal: rank capacity above 32");
+          for (int c0 = 0; c0 < d.n; c0 += w) {
+            const int c1 = std::min(d.n, c0 + w);
+            Term tm{};
+            tm.dense = 0;
+            tm.ro = 0;
+            tm.mr = d.m;
+            tm.co = c0;
+            tm.nc = c1 - c0;
+            tm.U = src.L[l].A + (size_t)d.m * c0;
+            tm.ldu = d.m;
+            tm.W = B.ident;
+            tm.ldw = 64;
+            tm.kfix = c1 - c0;
+            tm.sign = 1.0;
+            terms.push_back(tm);
+          }
+          tgs.push_back(T);
+          tl.push_back(terms);
+        }
+      }
+    B.emit_lflush(tgs, tl, lu_tol);
+    const double t1 = now_s();
+    P.upload_all(s);
+    HL_CHECK(hipStreamSynchronize(s));
+    const double t2 = now_s();
+    P.run(zpb.as<int32_t>(), s);
+    const double t3 = now_s();
+    HL_CHECK(hipStreamSynchronize(s));
+    const double t4 = now_s();
+    if (verbose())
+      std::fprintf(stderr, "[hlevy] factor %zu problem(s): plan %.3fs (%zu phases, %zu lr targets, ws peak %.1f MB) "
+                   "upload %.3fs enqueue %.3fs device-tail %.3fs\n", fs.size(), t1 - t0, P.ph.size(), P.ltg.size(),
+                   ws.peak / 1048576.0, t2 - t1, t3 - t2, t4 - t3);
+  }
+  int32_t zp = 0, ovf = 0;
+  HL_CHECK(hipMemcpy(&zp, zpb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HL_CHECK(hipMemcpy(&ovf, ovfb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (zp) return fail(HLEVY_ERR_ZERO_PIVOT, "zero pivot in a diagonal leaf of the H-LU");
+  const bool mixed = prec == HLEVY_PREC_MIXED;
+  for (hlevy_fac* f : fs) {
+    f->rank_overflows = ovf;
+    const Structure& S = f->op->S;
+    const size_t Nb = (size_t)S.N * sizeof(double);
+    for (DevBuf* b : {&f->w_u, &f->w_y, &f->w_b, &f->w_z, &f->w_r, &f->w_d, &f->w_g}) b->alloc(Nb);
+    // residual operator in FP64 on both paths: with the far field in FP32
+    // the operator applied to smooth states is off by ~1e-7 relative (the
+    // far-field sums are large and cancel against the near field), which
+    // adds up to ~1e-8..1e-7 over 1000 steps; preconditioner (inverse
+    // factors): FP32 on the mixed path
+    f->mvG.create(S, f->op->G, read_ranks(f->op->G, s), false, false, s);
+    f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s);
+    f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s);
+    f->LU.pool.reset();   // the per-step path needs only G and the inverse factors
+  }
+  HL_CHECK(hipStreamSynchronize(s));
+  return HLEVY_OK;
 }
 
 extern "C" {
@@ -1222,7 +1447,8 @@ hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, 
     {
       Plan P;
       WsStack ws;
-      Builder B(S, P, ws, op->ds, op->ovf.as<int32_t>(), hp->aca_tol);
+      Builder B(P, ws, op->ds.ident.as<double>(), op->ovf.as<int32_t>(), hp->aca_tol);
+      B.add_problem(S, op->ds);
       std::vector<LFlushTarget> tgs;
       std::vector<std::vector<Term>> tl;
       for (size_t q = 0; q < lr_ids.size(); ++q) {
@@ -1252,7 +1478,7 @@ hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, 
       }
       B.emit_lflush(tgs, tl, hp->aca_tol);
       P.upload_all(s);
-      P.run(op->ds.lists, nullptr, s);
+      P.run(nullptr, s);
       HL_CHECK(hipStreamSynchronize(s));
     }
     op->xbuf.alloc((size_t)S.N * sizeof(double));
@@ -1331,123 +1557,53 @@ hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream) {
 hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu_tol, void* stream,
                           hlevy_fac** out) {
   if (!op || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HLEVY_ERR_INVALID_ARG, "dt must be > 0");
+  return hlevy_factor_batched(&op, &dt, 1, prec, lu_tol, 0, stream, out);
+}
+
+hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, int32_t count, int32_t prec,
+                                  double lu_tol, size_t workspace_bytes, void* stream, hlevy_fac** out) {
+  if (!ops || !dt || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (count < 1) return fail(HLEVY_ERR_INVALID_ARG, "count must be >= 1");
+  for (int32_t i = 0; i < count; ++i) {
+    out[i] = nullptr;
+    if (!ops[i]) return fail(HLEVY_ERR_INVALID_ARG, "null operator");
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(HLEVY_ERR_INVALID_ARG, "dt must be > 0");
+  }
   if (!(lu_tol > 0.0 && lu_tol < 1.0)) return fail(HLEVY_ERR_INVALID_ARG, "lu_tol must be in (0, 1)");
   if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
-  return guarded([&]() -> hlevy_status {
+  const size_t budget = workspace_bytes ? workspace_bytes : kDefaultFactorWorkspace;
+  std::vector<std::unique_ptr<hlevy_fac>> fs(count);
+  hlevy_status st = guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
-    auto f = std::make_unique<hlevy_fac>();
-    f->op = op;
-    f->dt = dt;
-    f->prec = prec;
-    f->lu_tol = lu_tol;
-    const Structure& S = op->S;
-    const int kc = op->hp.max_rank;
-    const bool dmax = true;   // leaf-level admissible blocks dense while factoring
-    f->LU.create(S, kc, FULL, s, dmax);
-    HMat Li, Ui, TMP;
-    Li.create(S, kc, LOWER, s, dmax);
-    Ui.create(S, kc, UPPER, s, dmax);
-    TMP.create(S, kc, FULL, s, dmax);
-    f->Li.create(S, kc, LOWER, s);
-    f->Ui.create(S, kc, UPPER, s);
-    f->zp.alloc(sizeof(int32_t));
-    f->ovf.alloc(sizeof(int32_t));
-    HL_CHECK(hipMemsetAsync(f->zp.p, 0, sizeof(int32_t), s));
-    HL_CHECK(hipMemsetAsync(f->ovf.p, 0, sizeof(int32_t), s));
-    {
-      Plan P;
-      WsStack ws;
-      Builder B(S, P, ws, op->ds, f->ovf.as<int32_t>(), lu_tol);
-      B.copy_node(&f->LU, const_cast<HMat*>(&op->G), 0, -0.5 * dt, true);   // M = I - dt/2 G
-      B.zero_node(&Li, 0);
-      B.zero_node(&Ui, 0);
-      B.zero_node(&TMP, 0);
-      const double t0 = now_s();
-      hluinv(B, &f->LU, &Li, &Ui, &TMP, 0);
-      // inverse factors in the operator's block format: dense leaf-level
-      // blocks of the workspace are truncated back to low rank
-      for (int side = 0; side < 2; ++side) {
-        HMat& src = side == 0 ? Li : Ui;
-        HMat& dst = side == 0 ? f->Li : f->Ui;
-        B.copy_node(&dst, &src, 0, 1.0, false, /*skip_compress=*/true);
-        // one target per block with its dense content as 32-column terms
-        // (the fused rounded addition takes them one concatenation at a time;
-        // the targets start at rank 0)
-        std::vector<LFlushTarget> tgs;
-        std::vector<std::vector<Term>> tl;
-        for (size_t l = 0; l < S.lf.size(); ++l) {
-          const LeafDesc& d = dst.L[l];
-          if (!(d.kind == K_LR && src.L[l].kind == K_DENSE)) continue;
-          LFlushTarget T{};
-          T.U = d.A;
-          T.V = d.B;
-          T.rank = dst.rank + l;
-          T.m = d.m;
-          T.n = d.n;
-          T.kcap = d.kcap;
-          T.Kcap = 48;
-          std::vector<Term> terms;
-          const int w = d.kcap <= 16 ? 32 : 16;   // kcap + w <= 48
-          if (d.kcap > 32) throw DeviceError("internal: rank capacity above 32");
-          for (int c0 = 0; c0 < d.n; c0 += w) {
-            const int c1 = std::min(d.n, c0 + w);
-            Term tm{};
-            tm.dense = 0;
-            tm.ro = 0;
-            tm.mr = d.m;
-            tm.co = c0;
-            tm.nc = c1 - c0;
-            tm.U = src.L[l].A + (size_t)d.m * c0;
-            tm.ldu = d.m;
-            tm.W = op->ds.ident.as<double>();
-            tm.ldw = 64;
-            tm.kfix = c1 - c0;
-            tm.sign = 1.0;
-            terms.push_back(tm);
-          }
-          tgs.push_back(T);
-          tl.push_back(terms);
-        }
-        B.emit_lflush(tgs, tl, lu_tol);
+    for (int32_t i = 0; i < count; ++i) {
+      fs[i] = std::make_unique<hlevy_fac>();
+      fs[i]->op = ops[i];
+      fs[i]->dt = dt[i];
+      fs[i]->prec = prec;
+      fs[i]->lu_tol = lu_tol;
+    }
+    // groups of consecutive problems whose factorisation memory fits the budget
+    int32_t i0 = 0;
+    while (i0 < count) {
+      int32_t i1 = i0;
+      size_t used = 0;
+      while (i1 < count) {
+        const size_t b = factor_footprint(*ops[i1]);
+        if (i1 > i0 && used + b > budget) break;
+        used += b;
+        ++i1;
       }
-      const double t1 = now_s();
-      P.upload_all(s);
-      HL_CHECK(hipStreamSynchronize(s));
-      const double t2 = now_s();
-      P.run(op->ds.lists, f->zp.as<int32_t>(), s);
-      const double t3 = now_s();
-      HL_CHECK(hipStreamSynchronize(s));
-      const double t4 = now_s();
-      if (verbose())
-        std::fprintf(stderr, "[hlevy] factor plan %.3fs (%zu phases, %zu lr targets, ws peak %.1f MB) upload %.3fs "
-                     "enqueue %.3fs device-tail %.3fs\n", t1 - t0, P.ph.size(), P.ltg.size(), ws.peak / 1048576.0,
-                     t2 - t1, t3 - t2, t4 - t3);
+      std::vector<hlevy_fac*> grp;
+      for (int32_t i = i0; i < i1; ++i) grp.push_back(fs[i].get());
+      hlevy_status e = factor_group(grp, s);
+      if (e != HLEVY_OK) return e;
+      i0 = i1;
     }
-    int32_t zp = 0;
-    HL_CHECK(hipMemcpy(&zp, f->zp.p, sizeof(int32_t), hipMemcpyDeviceToHost));
-    HL_CHECK(hipMemcpy(&f->rank_overflows, f->ovf.p, sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (zp) return fail(HLEVY_ERR_ZERO_PIVOT, "zero pivot in a diagonal leaf of the H-LU");
-    const size_t Nb = (size_t)S.N * sizeof(double);
-    for (DevBuf* b : {&f->w_u, &f->w_y, &f->w_b, &f->w_z, &f->w_r, &f->w_d, &f->w_g}) b->alloc(Nb);
-    f->partial.alloc(1024 * sizeof(double));
-    f->scal.alloc(8 * sizeof(double));
-    {
-      const bool mixed = prec == HLEVY_PREC_MIXED;
-      // residual operator in FP64 on both paths: with the far field in FP32
-      // the operator applied to smooth states is off by ~1e-7 relative (the
-      // far-field sums are large and cancel against the near field), which
-      // adds up to ~1e-8..1e-7 over 1000 steps; preconditioner (inverse
-      // factors): FP32 on the mixed path
-      f->mvG.create(S, op->G, read_ranks(op->G, s), false, false, s);
-      f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s);
-      f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s);
-      f->LU.pool.reset();   // the per-step path needs only G and the inverse factors
-    }
-    HL_CHECK(hipStreamSynchronize(s));
-    *out = f.release();
     return HLEVY_OK;
   });
+  if (st != HLEVY_OK) return st;
+  for (int32_t i = 0; i < count; ++i) out[i] = fs[i].release();
+  return HLEVY_OK;
 }
 
 // y = U^{-1} (L^{-1} x): forward then backward solve through the inverse
@@ -1583,6 +1739,115 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
       stats->last_rel_residual = -1.0;
       stats->rank_overflows = f->rank_overflows;
     }
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_t count, int64_t nsteps,
+                                const hlevy_refine* refine, void* stream) {
+  if (!facs || !u) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (count < 1) return fail(HLEVY_ERR_INVALID_ARG, "count must be >= 1");
+  if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (refine && (refine->sweeps < 0 || refine->sweeps > 64)) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
+  {
+    std::set<const hlevy_fac*> seen;
+    for (int32_t i = 0; i < count; ++i) {
+      if (!facs[i] || !u[i]) return fail(HLEVY_ERR_INVALID_ARG, "null factor or vector");
+      if (!seen.insert(facs[i]).second) return fail(HLEVY_ERR_INVALID_ARG, "a factor appears twice in the batch");
+    }
+  }
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    int sweeps = 0;
+    for (int32_t i = 0; i < count; ++i) sweeps = std::max(sweeps, default_sweeps(facs[i], refine));
+    std::vector<const MvPlan*> pg, pl, pu;
+    for (int32_t i = 0; i < count; ++i) {
+      pg.push_back(&facs[i]->mvG);
+      pl.push_back(&facs[i]->mvLi);
+      pu.push_back(&facs[i]->mvUi);
+    }
+    MvBatch bG, bL, bU;
+    bG.create(pg, s);
+    bL.create(pl, s);
+    bU.create(pu, s);
+    // the products of a step (as in hlevy_step), one table of problems each
+    enum { T_AXPY, T_SUB, T_W, T_RES, T_LI, T_ADD, T_NEXT, T_COUNT };
+    std::vector<std::vector<MvInst>> tab(T_COUNT);
+    for (int32_t i = 0; i < count; ++i) {
+      hlevy_fac* f = facs[i];
+      double* uc = f->w_u.as<double>();
+      double* w = f->w_d.as<double>();
+      double* z = f->w_z.as<double>();
+      double* r = f->w_y.as<double>();
+      MvInst t{};
+      t.dev = f->mvLi.dev;   // z = 2 L^{-1} u^n
+      t.x = uc;
+      t.epi = MvEpi{};
+      t.epi.kind = MV_EPI_AXPY;
+      t.epi.hdt = 2.0;
+      t.epi.y = z;
+      tab[T_AXPY].push_back(t);
+      t.dev = f->mvUi.dev;   // u^{n+1} = U^{-1} z - u^n
+      t.x = z;
+      t.epi = MvEpi{};
+      t.epi.kind = MV_EPI_SUB;
+      t.epi.u = uc;
+      t.epi.y = uc;
+      tab[T_SUB].push_back(t);
+      t.epi = epi_plain(w);  // w = U^{-1} z
+      tab[T_W].push_back(t);
+      t.dev = f->mvG.dev;    // r = 2 u^n - (w - dt/2 G w)
+      t.x = w;
+      t.epi = MvEpi{};
+      t.epi.kind = MV_EPI_CNRES;
+      t.epi.hdt = 0.5 * f->dt;
+      t.epi.u = uc;
+      t.epi.b = w;
+      t.epi.y = r;
+      tab[T_RES].push_back(t);
+      t.dev = f->mvLi.dev;   // z = L^{-1} r
+      t.x = r;
+      t.epi = epi_plain(z);
+      tab[T_LI].push_back(t);
+      t.dev = f->mvUi.dev;   // w += U^{-1} z
+      t.x = z;
+      t.epi = MvEpi{};
+      t.epi.kind = MV_EPI_ADD;
+      t.epi.u = w;
+      t.epi.y = w;
+      tab[T_ADD].push_back(t);
+      t.epi = MvEpi{};       // u^{n+1} = w + U^{-1} z - u^n
+      t.epi.kind = MV_EPI_NEXT;
+      t.epi.b = w;
+      t.epi.u = uc;
+      t.epi.y = uc;
+      tab[T_NEXT].push_back(t);
+    }
+    std::vector<DevBuf> dtab(T_COUNT);
+    for (int k = 0; k < T_COUNT; ++k) upload(dtab[k], tab[k], s);
+    auto T = [&](int k) { return dtab[k].as<MvInst>(); };
+    for (int32_t i = 0; i < count; ++i)
+      HL_CHECK(launch_perm_gather(facs[i]->w_u.as<double>(), u[i], facs[i]->op->ds.perm.as<int32_t>(),
+                                  facs[i]->op->S.N, s));
+    for (int64_t n = 0; n < nsteps; ++n) {
+      bL.run(T(T_AXPY), s);
+      if (sweeps == 0) {
+        bU.run(T(T_SUB), s);
+        continue;
+      }
+      bU.run(T(T_W), s);
+      for (int it = 0; it < sweeps; ++it) {
+        bG.run(T(T_RES), s);
+        bL.run(T(T_LI), s);
+        bU.run(T(it + 1 < sweeps ? T_ADD : T_NEXT), s);
+      }
+    }
+    for (int32_t i = 0; i < count; ++i)
+      HL_CHECK(launch_perm_scatter(u[i], facs[i]->w_u.as<double>(), facs[i]->op->ds.perm.as<int32_t>(),
+                                   facs[i]->op->S.N, s));
+    // the tables and maps are freed when this call returns: wait for the
+    // device to finish with them
+    HL_CHECK(hipStreamSynchronize(s));
     return HLEVY_OK;
   });
 }

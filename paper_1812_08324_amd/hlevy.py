@@ -60,8 +60,8 @@ class KernelTimes(C.Structure):
 
 EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
            "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
-           "hlevy_factor", "hlevy_solve", "hlevy_step", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy",
-           "hlevy_fac_destroy"]
+           "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_step", "hlevy_step_batched",
+           "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy"]
 
 
 def _load():
@@ -79,7 +79,10 @@ def _load():
         "hlevy_matvec": ([vp, vp, vp, vp], st),
         "hlevy_op_densify": ([vp, vp, vp], st),
         "hlevy_factor": ([vp, C.c_double, C.c_int32, C.c_double, vp, C.POINTER(vp)], st),
+        "hlevy_factor_batched": ([C.POINTER(vp), C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_double,
+                                  C.c_size_t, vp, C.POINTER(vp)], st),
         "hlevy_solve": ([vp, vp, vp, C.POINTER(Refine), vp], st),
+        "hlevy_step_batched": ([C.POINTER(vp), C.POINTER(vp), C.c_int32, C.c_int64, C.POINTER(Refine), vp], st),
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
                         C.POINTER(Stats), vp], st),
         "hlevy_fac_kernel_times": ([vp, C.c_int32, vp, C.POINTER(KernelTimes)], st),
@@ -181,13 +184,16 @@ class Op:
 class Fac:
     """H-LU factors of I - dt/2 G with their inverses (handle owner)."""
 
-    def __init__(self, op: Op, dt: float, prec: int = PREC_FP64, lu_tol: float = 1e-12, stream=None):
-        h = C.c_void_p()
-        _check(lib.hlevy_factor(op.h, float(dt), int(prec), float(lu_tol), _stream(stream), C.byref(h)),
-               "hlevy_factor")
-        self.h = h
+    def __init__(self, op: Op, dt: float, prec: int = PREC_FP64, lu_tol: float = 1e-12, stream=None,
+                 handle=None):
+        if handle is None:
+            handle = C.c_void_p()
+            _check(lib.hlevy_factor(op.h, float(dt), int(prec), float(lu_tol), _stream(stream),
+                                    C.byref(handle)), "hlevy_factor")
+        self.h = handle
         self.op = op           # the factor references the operator
         self.N = op.N
+        self.dt = float(dt)
 
     def __del__(self):
         if getattr(self, "h", None) and self.h.value and lib is not None:
@@ -221,6 +227,31 @@ def op_densify(op: Op, dense, stream=None):
 
 def factor(op: Op, dt: float, prec: int = PREC_FP64, lu_tol: float = 1e-12, stream=None) -> Fac:
     return Fac(op, dt, prec, lu_tol, stream)
+
+
+def factor_batched(ops, dts, prec: int = PREC_FP64, lu_tol: float = 1e-12, workspace_bytes: int = 0,
+                   stream=None) -> list:
+    """Factors of several problems from one joint plan (hlevy_factor_batched)."""
+    n = len(ops)
+    if len(dts) != n or n == 0:
+        raise ValueError("one dt per operator, at least one operator")
+    hs = (C.c_void_p * n)(*[o.h.value for o in ops])
+    dv = (C.c_double * n)(*[float(d) for d in dts])
+    out = (C.c_void_p * n)()
+    _check(lib.hlevy_factor_batched(hs, dv, n, int(prec), float(lu_tol), int(workspace_bytes), _stream(stream),
+                                    out), "hlevy_factor_batched")
+    return [Fac(o, d, prec, lu_tol, handle=C.c_void_p(out[i])) for i, (o, d) in enumerate(zip(ops, dts))]
+
+
+def step_batched(facs, us, nsteps: int, refine=None, stream=None):
+    """nsteps unforced Crank-Nicolson steps of every problem (hlevy_step_batched)."""
+    n = len(facs)
+    if len(us) != n or n == 0:
+        raise ValueError("one vector per factor, at least one factor")
+    hs = (C.c_void_p * n)(*[f.h.value for f in facs])
+    up = (C.c_void_p * n)(*[_dptr(u, f.N).value for f, u in zip(facs, us)])
+    _check(lib.hlevy_step_batched(hs, up, n, int(nsteps), _refine(refine), _stream(stream)),
+           "hlevy_step_batched")
 
 
 def _refine(refine):
