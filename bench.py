@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--max-rank", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison job")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-worklist measurement")
     ap.add_argument("--job-only", action="store_true", help="run warmup + timed jobs only (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain device copies of 2 GiB (HBM counter calibration)")
@@ -84,6 +85,7 @@ def cpu_baseline(w, sample_n=4096, sample_steps=50):
     r = w.N / sample_n
     t_full = (t1 - t0) * r ** 2 + (t2 - t1) * r ** 3 + (t3 - t2) / sample_steps * w.steps * r ** 2
     return {
+        "_parts": {"n": sample_n, "asm": t1 - t0, "lu": t2 - t1, "step": (t3 - t2) / sample_steps},
         "value": w.steps / t_full,
         "unit": "CN steps/s (whole job, extrapolated)",
         "cores": int(threads),
@@ -91,6 +93,65 @@ def cpu_baseline(w, sample_n=4096, sample_steps=50):
         "sample": (f"dense oracle at N={sample_n} (same operator parameters): assembly {t1 - t0:.2f}s, "
                    f"LU {t2 - t1:.2f}s, {sample_steps} steps {t3 - t2:.2f}s; extrapolated to N={w.N} "
                    f"with N^2 / N^3 / N^2 scaling ({t_full:.0f}s per job)"),
+    }
+
+
+def bench_batched(H, torch, sweeps, lu_tol):
+    """The batched worklist: 512 independent 1D tempered problems (N
+    log-uniform in [2^10, 2^15], s, drift, sigma^2, lambda drawn with PCG64
+    seed 8324), mixed precision, 100 CN steps of dt = 1e-3 each.  Whole job =
+    assembly of every operator, one joint factorisation plan, the batched
+    steps; inputs resident in HBM before timing."""
+    import workloads as W
+    ws = W.config4_instances()
+    hp = H.make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16)
+    probs = [H.make_problem(1, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
+             for w in ws]
+    u0 = [torch.tensor(w.u0, dtype=torch.float64, device="cuda") for w in ws]
+    steps = ws[0].steps
+    # warm the batched kernels on a few problems
+    ops = [H.assemble(p, hp) for p in probs[:4]]
+    fs = H.factor_batched(ops, [w.dt for w in ws[:4]], H.PREC_MIXED, lu_tol)
+    H.step_batched(fs, [u.clone() for u in u0[:4]], 2, refine={"sweeps": sweeps})
+    del fs, ops
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ops = [H.assemble(p, hp) for p in probs]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    facs = H.factor_batched(ops, [w.dt for w in ws], H.PREC_MIXED, lu_tol)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    us = [u.clone() for u in u0]
+    torch.cuda.synchronize()
+    t2b = time.perf_counter()
+    H.step_batched(facs, us, steps, refine={"sweeps": sweeps})
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    whole = (t1 - t0) + (t2 - t1) + (t3 - t2b)
+    # steady stepping and its algorithmic bytes (every stored matrix entry
+    # read once per product; one sweep: L^-1, U^-1, G, L^-1, U^-1)
+    H.step_batched(facs, us, steps, refine={"sweeps": sweeps})
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    mats = [0.0, 0.0, 0.0]
+    for f in facs:
+        kt = H.fac_kernel_times(f, reps=1)
+        for j, nm in enumerate(("G", "Linv", "Uinv")):
+            d = kt[nm]
+            mats[j] += d["dense_bytes"] + d["u_bytes"] + d["v_bytes"]
+    unknowns = sum(w.n for w in ws)
+    step_bytes = (sweeps * mats[0] + (1 + sweeps) * (mats[1] + mats[2])) + 10 * 8.0 * unknowns
+    gbps = steps * step_bytes / (t4 - t3) / 1e9
+    return {
+        "workload": "tempered1d_batch512",
+        "problems": len(ws), "unknowns": unknowns, "cn_steps": steps, "dt": ws[0].dt,
+        "value": len(ws) * steps / whole,
+        "unit": "problem CN steps/s (whole job)",
+        "phases_s": {"assemble": t1 - t0, "factor_batched": t2 - t1, "steps_batched": t3 - t2b},
+        "steady_problem_steps_per_s": len(ws) * steps / (t4 - t3),
+        "step": {"bytes": step_bytes, "ms": 1e3 * (t4 - t3) / steps, "GBps": gbps, "frac": gbps / HBM_PEAK_GBS,
+                 "note": "all kernels of a batched step (projections, gathers) over its algorithmic bytes"},
     }
 
 
@@ -234,8 +295,26 @@ def main():
         "matvec_G": matvec,
     }
     line.update(extra)
+    del fac, op
+    if not args.no_batched:
+        line["batched"] = bench_batched(H, torch, args.sweeps, args.lu_tol_mixed)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
+        if "batched" in line:
+            # the same oracle timings, scaled to every problem of the batch
+            # (dense costs depend on N only)
+            import workloads as W
+            cb = line["cpu_baseline"]
+            t = cb["_parts"]
+            tot = 0.0
+            for bw in W.config4_instances():
+                r = bw.n / t["n"]
+                tot += t["asm"] * r ** 2 + t["lu"] * r ** 3 + t["step"] * bw.steps * r ** 2
+            line["batched"]["cpu_baseline"] = {
+                "value": line["batched"]["problems"] * line["batched"]["cn_steps"] / tot,
+                "unit": "problem CN steps/s (whole job, extrapolated)", "cores": cb["cores"], "kind": "oracle",
+                "sample": f"dense oracle timings at N={t['n']} scaled to the 512 problems ({tot:.0f}s per job)"}
+        line["cpu_baseline"].pop("_parts", None)
     print(json.dumps(line))
 
 

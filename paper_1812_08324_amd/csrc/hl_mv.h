@@ -76,12 +76,19 @@ struct MvInst {
   MvEpi epi;
 };
 
+// Work item of a batched product: problem `inst` and the device address of
+// its MvTile (projection) or MvRow (gather).
+struct MvRef {
+  int32_t inst, pad;
+  const void* p;
+};
+
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
 // Batched product over problems of one rank bucket kb and dense precision:
-// wmap[w] = (problem, tile) for the nw projection wavefronts, rmap[b] =
-// (problem, leaf cluster) for the nr gather workgroups; every problem's
+// wmap[w] names the tile of projection wavefront w (nw of them), rmap[b]
+// the leaf cluster of gather workgroup b (nr of them); every problem's
 // partials go to its own buffer.
-hipError_t mv_batch_launch(const MvInst* inst, const int2* wmap, int nw, const int2* rmap, int nr, int kb,
+hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
                            bool dense_f32, hipStream_t s);
 // the two kernels of mv_launch separately; non-null events are attached to
 // the dispatch (start, stop) for timing

@@ -138,15 +138,15 @@ __global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ t
   project_any<KB>(T, x, part, threadIdx.x & 63);
 }
 
-// batched: wavefront w takes tile map[w].y of problem map[w].x
+// batched: wavefront w takes the tile map[w].p of problem map[w].inst
 template <int KB>
 __global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__ inst,
-                                                      const int2* __restrict__ map, int nw) {
+                                                      const MvRef* __restrict__ map, int nw) {
   const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (wid >= nw) return;
-  const int2 m = map[wid];
-  const MvInst& P = inst[wuni(m.x)];
-  const MvTile T = P.dev.tiles[wuni(m.y)];
+  const MvRef m = map[wid];
+  const MvTile T = *reinterpret_cast<const MvTile*>(m.p);
+  const MvInst& P = inst[wuni(m.inst)];
   project_any<KB>(T, P.x, P.dev.part, threadIdx.x & 63);
 }
 
@@ -166,18 +166,18 @@ __device__ __forceinline__ double gather_lowrank(const void* p, int ii, int ld, 
   return acc;
 }
 
-template <int KB>
+template <int KB, int GW = MV_GW>
 struct GatherLds {
-  double red[MV_GW][64];
+  double red[GW][64];
   MvEntry se[MV_EMAX];
   double ts[MV_EMAX * KB];
 };
 
 // one leaf cluster: y[R] = epilogue(sum over the entries of R)
-template <typename TD, int KB>
+template <typename TD, int KB, int GW = MV_GW>
 __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __restrict__ ents,
                                             const double* __restrict__ x, const double* __restrict__ part,
-                                            const MvEpi& epi, GatherLds<KB>& L) {
+                                            const MvEpi& epi, GatherLds<KB, GW>& L) {
   auto& red = L.red;
   auto& se = L.se;
   auto& ts = L.ts;
@@ -193,11 +193,11 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
       const long long* src = reinterpret_cast<const long long*>(ents + base);
       long long* dst = reinterpret_cast<long long*>(se);
       const int words = cnt * (int)(sizeof(MvEntry) / 8);
-      for (int e = threadIdx.x; e < words; e += 64 * MV_GW) dst[e] = src[e];
+      for (int e = threadIdx.x; e < words; e += 64 * GW) dst[e] = src[e];
     }
     __syncthreads();
     // t_b of the low-rank entries: sum of the leaf's partials, in slot order
-    for (int it = threadIdx.x; it < cnt * KB; it += 64 * MV_GW) {
+    for (int it = threadIdx.x; it < cnt * KB; it += 64 * GW) {
       const int e = it / KB, q = it % KB;
       const MvEntry& E = se[e];
       double s = 0.0;   // zero past the rank: the products below multiply by it
@@ -208,7 +208,7 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
       ts[it] = s;
     }
     __syncthreads();
-    for (int e = g; e < cnt; e += MV_GW) {
+    for (int e = g; e < cnt; e += GW) {
       const int kind = wuni(se[e].kind), en = wuni(se[e].n), ek = wuni(se[e].k), ld = wuni(se[e].ld);
       if (kind == 0) {
         const gptr<TD> D = wuni_ptr<TD>(se[e].ptr);
@@ -234,7 +234,7 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
   if (g == 0 && i < mr) {
     double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < MV_GW; w += 2) v += red[w][i] + red[w + 1][i];
+    for (int w = 0; w < GW; w += 2) v += red[w][i] + red[w + 1][i];
     const int r = R.lo + i;
     double out;
     switch (epi.kind) {
@@ -276,16 +276,21 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
   gather_rows<TD, KB>(R, ents, x, part, epi, L);
 }
 
-// batched: workgroup b takes leaf cluster map[b].y of problem map[b].x
+// batched: workgroup b takes the leaf cluster map[b].p of problem
+// map[b].inst.  Batches mostly hold small problems with a few entries per
+// leaf cluster, so the workgroups are half as wide as in the single-problem
+// kernel and twice as many stay resident per CU.
+constexpr int MV_GWB = 4;
+
 template <typename TD, int KB>
-__global__ void __launch_bounds__(64 * MV_GW) k_mv_gather_b(const MvInst* __restrict__ inst,
-                                                            const int2* __restrict__ map) {
-  __shared__ GatherLds<KB> L;
-  const int2 m = map[blockIdx.x];
-  const MvInst& P = inst[wuni(m.x)];
-  const MvRow R = P.dev.rows[wuni(m.y)];
+__global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __restrict__ inst,
+                                                             const MvRef* __restrict__ map) {
+  __shared__ GatherLds<KB, MV_GWB> L;
+  const MvRef m = map[blockIdx.x];
+  const MvRow R = *reinterpret_cast<const MvRow*>(m.p);
+  const MvInst& P = inst[wuni(m.inst)];
   const MvEpi epi = P.epi;
-  gather_rows<TD, KB>(R, P.dev.ents, P.x, P.dev.part, epi, L);
+  gather_rows<TD, KB, MV_GWB>(R, P.dev.ents, P.x, P.dev.part, epi, L);
 }
 
 int project_rows_per_pass(int kb, bool f32) {
@@ -351,18 +356,18 @@ hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipS
 }
 
 template <int KB>
-static void batch_t(const MvInst* inst, const int2* wmap, int nw, const int2* rmap, int nr, bool dense_f32,
+static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
                     hipStream_t s) {
   if (nw > 0) hipLaunchKernelGGL((k_mv_project_b<KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw);
   if (nr > 0) {
     if (dense_f32)
-      hipLaunchKernelGGL((k_mv_gather_b<float, KB>), dim3(nr), dim3(64 * MV_GW), 0, s, inst, rmap);
+      hipLaunchKernelGGL((k_mv_gather_b<float, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap);
     else
-      hipLaunchKernelGGL((k_mv_gather_b<double, KB>), dim3(nr), dim3(64 * MV_GW), 0, s, inst, rmap);
+      hipLaunchKernelGGL((k_mv_gather_b<double, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap);
   }
 }
 
-hipError_t mv_batch_launch(const MvInst* inst, const int2* wmap, int nw, const int2* rmap, int nr, int kb,
+hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
                            bool dense_f32, hipStream_t s) {
   if (kb == 8)
     batch_t<8>(inst, wmap, nw, rmap, nr, dense_f32, s);

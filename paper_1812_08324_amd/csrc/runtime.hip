@@ -154,12 +154,34 @@ struct WsStack {
 // ---------------------------------------------------------------------------
 enum Shape { FULL = 0, LOWER = 1, UPPER = 2 };
 
+// Bump allocator over one device buffer: the factorisation workspaces of a
+// group of problems, reused from group to group without new allocations.
+struct Arena {
+  DevBuf buf;
+  size_t off = 0;
+  static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+  void reserve(size_t bytes) {
+    if (buf.bytes < bytes) buf.alloc(bytes);
+    off = 0;
+  }
+  char* take(size_t bytes) {
+    bytes = round(std::max<size_t>(bytes, 8));
+    if (off + bytes > buf.bytes) throw DeviceError("internal: factorisation arena overflow");
+    char* p = reinterpret_cast<char*>(buf.p) + off;
+    off += bytes;
+    return p;
+  }
+};
+
 struct HMat {
   const Structure* S = nullptr;
   std::vector<LeafDesc> L;
-  DevBuf dL, drank, pool;
-  int32_t* rank = nullptr;  // device, per leaf
+  DevBuf dL, drank, pool;     // owned storage (create); empty for arena storage (create_in)
+  double* mem = nullptr;      // device leaf storage
+  LeafDesc* ldev = nullptr;   // device copy of L
+  int32_t* rank = nullptr;    // device, per leaf
   size_t pool_doubles = 0;
+  std::vector<int32_t> pend;   // plan building: slot of the leaf's pending terms, or -1
 
   // dense_leaf_level: admissible blocks between two leaf clusters are held
   // dense in this matrix (the factorisation workspace), so that updates of
@@ -169,6 +191,7 @@ struct HMat {
   size_t layout(const Structure& st, int kcap_max, Shape shape, bool dense_leaf_level) {
     S = &st;
     L.resize(st.lf.size());
+    pend.assign(st.lf.size(), -1);
     size_t off = 0;
     for (size_t l = 0; l < st.lf.size(); ++l) {
       const LeafInfo& li = st.lf[l];
@@ -196,10 +219,8 @@ struct HMat {
     pool_doubles = off;
     return off;
   }
-  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s, bool dense_leaf_level = false) {
-    layout(st, kcap_max, shape, dense_leaf_level);
-    pool.alloc(std::max<size_t>(pool_doubles, 1) * sizeof(double));
-    double* base = pool.as<double>();
+  void place(double* base) {
+    mem = base;
     for (auto& d : L) {
       if (d.kind == K_DENSE) d.A = base + reinterpret_cast<size_t>(d.A);
       if (d.kind == K_LR) {
@@ -207,12 +228,33 @@ struct HMat {
         d.B = base + reinterpret_cast<size_t>(d.B);
       }
     }
+  }
+  void create(const Structure& st, int kcap_max, Shape shape, hipStream_t s, bool dense_leaf_level = false) {
+    layout(st, kcap_max, shape, dense_leaf_level);
+    pool.alloc(std::max<size_t>(pool_doubles, 1) * sizeof(double));
+    place(pool.as<double>());
     upload(dL, L, s);
+    ldev = dL.as<LeafDesc>();
     drank.alloc(std::max<size_t>(L.size(), 1) * sizeof(int32_t));
     rank = drank.as<int32_t>();
     HL_CHECK(hipMemsetAsync(rank, 0, L.size() * sizeof(int32_t), s));
   }
-  const LeafDesc* dev() const { return dL.as<LeafDesc>(); }
+  // storage taken from an arena (the arena outlives every use)
+  static size_t arena_bytes(size_t pool_doubles, size_t nleaves) {
+    return Arena::round(pool_doubles * sizeof(double)) + Arena::round(nleaves * sizeof(LeafDesc)) +
+           Arena::round(nleaves * sizeof(int32_t)) + 3 * 256;
+  }
+  void create_in(Arena& a, const Structure& st, int kcap_max, Shape shape, hipStream_t s,
+                 bool dense_leaf_level = false) {
+    layout(st, kcap_max, shape, dense_leaf_level);
+    place(reinterpret_cast<double*>(a.take(pool_doubles * sizeof(double))));
+    ldev = reinterpret_cast<LeafDesc*>(a.take(L.size() * sizeof(LeafDesc)));
+    if (!L.empty())
+      HL_CHECK(hipMemcpyAsync(ldev, L.data(), L.size() * sizeof(LeafDesc), hipMemcpyHostToDevice, s));
+    rank = reinterpret_cast<int32_t*>(a.take(L.size() * sizeof(int32_t)));
+    HL_CHECK(hipMemsetAsync(rank, 0, L.size() * sizeof(int32_t), s));
+  }
+  const LeafDesc* dev() const { return ldev; }
 };
 
 // Device copies of the structure lists.
@@ -359,7 +401,13 @@ struct Builder {
   std::vector<ApplyJob> bjobs;
   std::vector<const HMat*> bjob_mat;
   std::vector<DProdItem> bdprod;
-  std::map<std::pair<HMat*, int>, std::vector<PendingTerm>> pending;
+  // pending update terms per target leaf, in slots (HMat::pend indexes them)
+  std::vector<std::pair<HMat*, int>> pkeys;
+  std::vector<std::vector<PendingTerm>> pterms;
+  struct PendView {
+    std::pair<HMat*, int> first;
+    std::vector<PendingTerm>& second;
+  };
   WsStack::Mark mk{};
   bool in_batch = false;
 
@@ -434,7 +482,13 @@ struct Builder {
     t.mr = r1 - r0;
     t.co = c0 - d.clo;
     t.nc = c1 - c0;
-    pending[{C, c.leaf}].push_back({t, kcap});
+    int32_t& slot = C->pend[c.leaf];
+    if (slot < 0) {
+      slot = (int32_t)pkeys.size();
+      pkeys.push_back({C, c.leaf});
+      pterms.emplace_back();
+    }
+    pterms[slot].push_back({t, kcap});
   }
 
   // C[cnode region] += sign * A[an] * B[bn]
@@ -580,15 +634,25 @@ struct Builder {
         P.jobs.push_back(J);
         for (int l = J.lbeg; l < J.lend; ++l)
           if (bjob_mat[q]->L[l].kind == K_LR) P.proj.push_back(ProjItem{jb + (int)q, l});
-        int o0 = J.trans ? J.clo : J.rlo, o1 = J.trans ? J.chi : J.rhi;
-        for (size_t lp = 0; lp < S.leafcl.size(); ++lp) {
-          const Cluster& c = S.cl[S.leafcl[lp]];
-          if (c.lo >= o0 && c.hi <= o1) P.gath.push_back(GatherItem{jb + (int)q, (int)lp});
-        }
+        // leaf clusters inside [o0, o1): a contiguous run of leafcl (index order)
+        const int o0 = J.trans ? J.clo : J.rlo, o1 = J.trans ? J.chi : J.rhi;
+        size_t lp = std::partition_point(S.leafcl.begin(), S.leafcl.end(),
+                                         [&](int32_t c) { return S.cl[c].lo < o0; }) - S.leafcl.begin();
+        for (; lp < S.leafcl.size() && S.cl[S.leafcl[lp]].hi <= o1; ++lp)
+          P.gath.push_back(GatherItem{jb + (int)q, (int)lp});
       }
       ph.n0 = (int)P.proj.size() - ph.b0;
       ph.n1 = (int)P.gath.size() - ph.b1;
       P.ph.push_back(ph);
+    }
+    // targets in (matrix, leaf) order
+    std::vector<PendView> pending;
+    {
+      std::vector<int> ord(pkeys.size());
+      for (size_t q = 0; q < ord.size(); ++q) ord[q] = (int)q;
+      std::sort(ord.begin(), ord.end(), [&](int a, int b) { return pkeys[a] < pkeys[b]; });
+      pending.reserve(ord.size());
+      for (int q : ord) pending.push_back(PendView{pkeys[q], pterms[q]});
     }
     // 2. products into low-rank targets are formed densely (workspace),
     //    then compressed below; dense targets take product terms as they are
@@ -778,6 +842,9 @@ struct Builder {
     bjob_mat.clear();
     bdprod.clear();
     pending.clear();
+    for (auto& k : pkeys) k.first->pend[k.second] = -1;
+    pkeys.clear();
+    pterms.clear();
     ws.release(mk);
     in_batch = false;
   }
@@ -982,7 +1049,7 @@ struct MvPlan {
   // rows and columns, which stay FP64
   void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, bool lr_f32,
               hipStream_t s, int lr64_rows = 0) {
-    const double* base = M.pool.as<double>();
+    const double* base = M.mem;
     const float* fbase = nullptr;
     if (dense_f32 || lr_f32) {
       f32pool.alloc(std::max<size_t>(M.pool_doubles, 1) * sizeof(float));
@@ -1106,7 +1173,7 @@ struct MvBatch {
   void create(const std::vector<const MvPlan*>& plans, hipStream_t s) {
     std::map<std::pair<int, int>, std::vector<int>> by;
     for (size_t i = 0; i < plans.size(); ++i) by[{plans[i]->dev.kb, plans[i]->dev.dense_f32}].push_back((int)i);
-    std::vector<int2> w, r;
+    std::vector<MvRef> w, r;
     for (auto& kv : by) {
       Group g{kv.first.first, kv.first.second, (int)w.size(), 0, (int)r.size(), 0};
       int tmax = 0, rmax = 0;
@@ -1116,10 +1183,10 @@ struct MvBatch {
       }
       for (int t = 0; t < tmax; ++t)
         for (int i : kv.second)
-          if (t < plans[i]->dev.ntiles) w.push_back(make_int2(i, t));
+          if (t < plans[i]->dev.ntiles) w.push_back(MvRef{i, 0, plans[i]->dev.tiles + t});
       for (int q = 0; q < rmax; ++q)
         for (int i : kv.second)
-          if (q < plans[i]->dev.nrows) r.push_back(make_int2(i, q));
+          if (q < plans[i]->dev.nrows) r.push_back(MvRef{i, 0, plans[i]->dev.rows + q});
       g.nw = (int)w.size() - g.w0;
       g.nr = (int)r.size() - g.r0;
       groups.push_back(g);
@@ -1129,7 +1196,8 @@ struct MvBatch {
   }
   void run(const MvInst* inst, hipStream_t s) const {
     for (const Group& g : groups)
-      HL_CHECK(mv_batch_launch(inst, dw.as<int2>() + g.w0, g.nw, dr.as<int2>() + g.r0, g.nr, g.kb, g.f32 != 0, s));
+      HL_CHECK(mv_batch_launch(inst, dw.as<MvRef>() + g.w0, g.nw, dr.as<MvRef>() + g.r0, g.nr, g.kb, g.f32 != 0,
+                               s));
   }
 };
 
@@ -1216,7 +1284,7 @@ static size_t factor_footprint(const hlevy_op& op) {
 // products, copies and rounded additions is one launch for all of them.
 // Problems share the zero-pivot flag and the rank-overflow counter of the
 // group.
-static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, hipStream_t s) {
+static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsStack& ws, hipStream_t s) {
   const double lu_tol = fs[0]->lu_tol;
   const int prec = fs[0]->prec;
   struct Work {
@@ -1229,24 +1297,40 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, hipStream_t s) {
   ovfb.alloc(sizeof(int32_t));
   HL_CHECK(hipMemsetAsync(zpb.p, 0, sizeof(int32_t), s));
   HL_CHECK(hipMemsetAsync(ovfb.p, 0, sizeof(int32_t), s));
-  const double t0 = now_s();
+  const double ta = now_s();
+  {
+    size_t need = 0;
+    for (hlevy_fac* f : fs) {
+      HMat t;
+      const size_t nl = f->op->S.lf.size();
+      const int kc = f->op->hp.max_rank;
+      need += 2 * HMat::arena_bytes(t.layout(f->op->S, kc, FULL, true), nl);
+      need += 2 * HMat::arena_bytes(t.layout(f->op->S, kc, LOWER, true), nl);
+    }
+    arena.reserve(need);
+  }
+  const WsStack::Mark ws0 = ws.mark();
   for (hlevy_fac* f : fs) {
     const Structure& S = f->op->S;
     const int kc = f->op->hp.max_rank;
     const bool dmax = true;   // leaf-level admissible blocks dense while factoring
     auto w = std::make_unique<Work>();
-    f->LU.create(S, kc, FULL, s, dmax);
-    w->Li.create(S, kc, LOWER, s, dmax);
-    w->Ui.create(S, kc, UPPER, s, dmax);
-    w->TMP.create(S, kc, FULL, s, dmax);
+    // workspaces in the arena (LU too: the per-step path needs only G and
+    // the inverse factors)
+    f->LU.create_in(arena, S, kc, FULL, s, dmax);
+    w->Li.create_in(arena, S, kc, LOWER, s, dmax);
+    w->Ui.create_in(arena, S, kc, UPPER, s, dmax);
+    w->TMP.create_in(arena, S, kc, FULL, s, dmax);
     f->Li.create(S, kc, LOWER, s);
     f->Ui.create(S, kc, UPPER, s);
     w->ctx = LuCtx{&f->LU, &w->Li, &w->Ui, &w->TMP};
     wk.push_back(std::move(w));
   }
+  HL_CHECK(hipStreamSynchronize(s));
+  const double t0 = now_s();
+  double tpost = 0.0;
   {
     Plan P;
-    WsStack ws;
     Builder B(P, ws, fs[0]->op->ds.ident.as<double>(), ovfb.as<int32_t>(), lu_tol);
     for (hlevy_fac* f : fs) B.add_problem(f->op->S, f->op->ds);
     int cb = B.copy_begin();
@@ -1325,9 +1409,10 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, hipStream_t s) {
     HL_CHECK(hipStreamSynchronize(s));
     const double t4 = now_s();
     if (verbose())
-      std::fprintf(stderr, "[hlevy] factor %zu problem(s): plan %.3fs (%zu phases, %zu lr targets, ws peak %.1f MB) "
-                   "upload %.3fs enqueue %.3fs device-tail %.3fs\n", fs.size(), t1 - t0, P.ph.size(), P.ltg.size(),
-                   ws.peak / 1048576.0, t2 - t1, t3 - t2, t4 - t3);
+      std::fprintf(stderr, "[hlevy] factor %zu problem(s): alloc %.3fs plan %.3fs (%zu phases, %zu lr targets, "
+                   "ws peak %.1f MB) upload %.3fs enqueue %.3fs device-tail %.3fs\n", fs.size(), t0 - ta, t1 - t0,
+                   P.ph.size(), P.ltg.size(), ws.peak / 1048576.0, t2 - t1, t3 - t2, t4 - t3);
+    tpost = now_s();
   }
   int32_t zp = 0, ovf = 0;
   HL_CHECK(hipMemcpy(&zp, zpb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1347,9 +1432,17 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, hipStream_t s) {
     f->mvG.create(S, f->op->G, read_ranks(f->op->G, s), false, false, s);
     f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s);
     f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s);
-    f->LU.pool.reset();   // the per-step path needs only G and the inverse factors
+    // the LU's storage is the arena's, reused by the next group
+    f->LU.L.clear();
+    f->LU.mem = nullptr;
+    f->LU.ldev = nullptr;
+    f->LU.rank = nullptr;
   }
+  ws.release(ws0);
   HL_CHECK(hipStreamSynchronize(s));
+  if (verbose())
+    std::fprintf(stderr, "[hlevy] factor %zu problem(s): workspace free + product plans %.3fs\n", fs.size(),
+                 now_s() - tpost);
   return HLEVY_OK;
 }
 
@@ -1582,7 +1675,10 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
       fs[i]->prec = prec;
       fs[i]->lu_tol = lu_tol;
     }
-    // groups of consecutive problems whose factorisation memory fits the budget
+    // groups of consecutive problems whose factorisation memory fits the
+    // budget; the groups share one arena and one product workspace
+    Arena arena;
+    WsStack ws;
     int32_t i0 = 0;
     while (i0 < count) {
       int32_t i1 = i0;
@@ -1595,7 +1691,7 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
       }
       std::vector<hlevy_fac*> grp;
       for (int32_t i = i0; i < i1; ++i) grp.push_back(fs[i].get());
-      hlevy_status e = factor_group(grp, s);
+      hlevy_status e = factor_group(grp, arena, ws, s);
       if (e != HLEVY_OK) return e;
       i0 = i1;
     }
