@@ -209,6 +209,67 @@ hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double*
 hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_t count,
                                 int64_t nsteps, const hlevy_refine* refine, void* stream);
 
+/* Serving loop.  Requests (a problem, dt, a horizon of nsteps unforced
+ * Crank-Nicolson steps, u0) arrive at any time; each hlevy_server_poll is
+ * one scheduling round:
+ *  1. admission in arrival order while the resident memory (cached
+ *     operators and factors, request state) fits hbm_budget; idle cached
+ *     operators are evicted least recently used first; a request waits
+ *     when memory is short (one request is always admitted when nothing
+ *     else is active);
+ *  2. operators not in the cache are assembled and factored in one joint
+ *     plan (hlevy_factor_batched); requests with equal problem, hparams and
+ *     dt share one cached factor;
+ *  3. every active request (at most max_active) advances by one chunk of
+ *     steps in one batched step (hlevy_step_batched's products; each
+ *     request keeps its own vectors), the chunk ending at the earliest
+ *     finishing request;
+ *  4. finished requests get u^{nsteps} written to their u_out.
+ * A request's result equals hlevy_step with a factor of the same
+ * parameters (same arithmetic, summation order of the batched products).
+ * The server's calls are not thread safe. */
+typedef struct {
+  size_t hbm_budget;   /* resident bytes allowed; 0 = 64 GiB */
+  int32_t prec;        /* HLEVY_PREC_MIXED or HLEVY_PREC_FP64 */
+  double lu_tol;       /* H-LU truncation of the factors */
+  int32_t sweeps;      /* refinement sweeps per step */
+  int32_t chunk;       /* CN steps per scheduling round, >= 1 */
+  int32_t max_active;  /* most requests advanced together, >= 1 */
+} hlevy_server_config;
+
+typedef struct {
+  int64_t submitted, completed, active, queued;
+  int64_t cache_hits, cache_misses, evictions, cached_operators;
+  int64_t problem_steps;        /* CN steps advanced, summed over requests */
+  size_t bytes_in_use;          /* resident bytes by the server's estimate */
+  double assemble_seconds, factor_seconds, step_seconds;
+} hlevy_server_stats;
+
+typedef struct hlevy_server hlevy_server;
+
+/* New server; its device work goes to `stream`.
+ * Errors: HLEVY_ERR_INVALID_ARG for a bad configuration. */
+hlevy_status hlevy_server_create(const hlevy_server_config* cfg, void* stream, hlevy_server** out);
+
+/* Queue a request.  u0: device, natural order, copied on `stream` before the
+ * call returns (the caller may reuse it); u_out: device, natural order,
+ * length N, must stay valid until the request is reported done.  *id
+ * receives the request's id.  Errors: HLEVY_ERR_INVALID_ARG for an invalid
+ * problem or dt. */
+hlevy_status hlevy_server_submit(hlevy_server* srv, const hlevy_problem* prob, const hlevy_hparams* hp,
+                                 double dt, int64_t nsteps, const double* u0, double* u_out, int64_t* id);
+
+/* One scheduling round (see above); synchronises the stream.  Writes up to
+ * `cap` ids of finished requests to done_ids and their count to *ndone
+ * (more are returned by later calls). */
+hlevy_status hlevy_server_poll(hlevy_server* srv, int64_t* done_ids, int32_t cap, int32_t* ndone);
+
+/* Counters of the server. */
+hlevy_status hlevy_server_stats_get(hlevy_server* srv, hlevy_server_stats* out);
+
+/* Frees every cached operator and factor and every queued request. */
+void hlevy_server_destroy(hlevy_server* srv);
+
 /* y = A x with one of the matrices the factor applies every step, in the
  * storage precision of the factor: which = 0: the generator G of the
  * residual operator (FP64 on both paths), 1: L^{-1}, 2: U^{-1} (App. B.2

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <deque>
 #include <map>
 #include <set>
 #include <memory>
@@ -1263,6 +1264,104 @@ static double frac_constant(int d, double s) {
   return std::pow(4.0, s) * std::tgamma(d / 2.0 + s) / (std::pow(M_PI, d / 2.0) * std::fabs(std::tgamma(-s)));
 }
 
+// One problem advanced by step_states: its factor, its vectors (cluster
+// order: u^n, the iterate w, two temporaries) and, optionally, its own
+// projection partial buffers for G, L^{-1}, U^{-1} (null: the plans' own).
+// Problems that share a factor in one batch need buffers of their own.
+struct StepState {
+  hlevy_fac* f;
+  double *uc, *w, *z, *r;
+  double *partG, *partL, *partU;
+};
+
+// Unforced Crank-Nicolson steps of every state (hlevy_step's recursion:
+// M w = 2 u^n, u^{n+1} = w - u^n, `sweeps` refinement sweeps), each product
+// one batched launch pair over all states.  Synchronises `s` before return
+// (the tables are freed here).
+static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sweeps, hipStream_t s) {
+  if (st.empty() || nsteps == 0) return;
+  std::vector<const MvPlan*> pg, pl, pu;
+  for (const StepState& x : st) {
+    pg.push_back(&x.f->mvG);
+    pl.push_back(&x.f->mvLi);
+    pu.push_back(&x.f->mvUi);
+  }
+  MvBatch bG, bL, bU;
+  bG.create(pg, s);
+  bL.create(pl, s);
+  bU.create(pu, s);
+  enum { T_AXPY, T_SUB, T_W, T_RES, T_LI, T_ADD, T_NEXT, T_COUNT };
+  std::vector<std::vector<MvInst>> tab(T_COUNT);
+  for (const StepState& x : st) {
+    hlevy_fac* f = x.f;
+    MvDev dG = f->mvG.dev, dL = f->mvLi.dev, dU = f->mvUi.dev;
+    if (x.partG) dG.part = x.partG;
+    if (x.partL) dL.part = x.partL;
+    if (x.partU) dU.part = x.partU;
+    MvInst t{};
+    t.dev = dL;   // z = 2 L^{-1} u^n
+    t.x = x.uc;
+    t.epi = MvEpi{};
+    t.epi.kind = MV_EPI_AXPY;
+    t.epi.hdt = 2.0;
+    t.epi.y = x.z;
+    tab[T_AXPY].push_back(t);
+    t.dev = dU;   // u^{n+1} = U^{-1} z - u^n
+    t.x = x.z;
+    t.epi = MvEpi{};
+    t.epi.kind = MV_EPI_SUB;
+    t.epi.u = x.uc;
+    t.epi.y = x.uc;
+    tab[T_SUB].push_back(t);
+    t.epi = epi_plain(x.w);  // w = U^{-1} z
+    tab[T_W].push_back(t);
+    t.dev = dG;   // r = 2 u^n - (w - dt/2 G w)
+    t.x = x.w;
+    t.epi = MvEpi{};
+    t.epi.kind = MV_EPI_CNRES;
+    t.epi.hdt = 0.5 * f->dt;
+    t.epi.u = x.uc;
+    t.epi.b = x.w;
+    t.epi.y = x.r;
+    tab[T_RES].push_back(t);
+    t.dev = dL;   // z = L^{-1} r
+    t.x = x.r;
+    t.epi = epi_plain(x.z);
+    tab[T_LI].push_back(t);
+    t.dev = dU;   // w += U^{-1} z
+    t.x = x.z;
+    t.epi = MvEpi{};
+    t.epi.kind = MV_EPI_ADD;
+    t.epi.u = x.w;
+    t.epi.y = x.w;
+    tab[T_ADD].push_back(t);
+    t.epi = MvEpi{};   // u^{n+1} = w + U^{-1} z - u^n
+    t.epi.kind = MV_EPI_NEXT;
+    t.epi.b = x.w;
+    t.epi.u = x.uc;
+    t.epi.y = x.uc;
+    tab[T_NEXT].push_back(t);
+  }
+  std::vector<DevBuf> dtab(T_COUNT);
+  for (int k = 0; k < T_COUNT; ++k) upload(dtab[k], tab[k], s);
+  auto T = [&](int k) { return dtab[k].as<MvInst>(); };
+  for (int64_t n = 0; n < nsteps; ++n) {
+    bL.run(T(T_AXPY), s);
+    if (sweeps == 0) {
+      bU.run(T(T_SUB), s);
+      continue;
+    }
+    bU.run(T(T_W), s);
+    for (int it = 0; it < sweeps; ++it) {
+      bG.run(T(T_RES), s);
+      bL.run(T(T_LI), s);
+      bU.run(T(it + 1 < sweeps ? T_ADD : T_NEXT), s);
+    }
+  }
+  // the tables and maps are freed on return: wait for the device first
+  HL_CHECK(hipStreamSynchronize(s));
+}
+
 // Factorisation memory (bytes) of one problem while it is being factored:
 // the LU workspace, the workspace inverse factors and the temporary (leaf-
 // level blocks dense), the final inverse factors and, roughly, the product
@@ -1856,94 +1955,16 @@ hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_
     hipStream_t s = as_stream(stream);
     int sweeps = 0;
     for (int32_t i = 0; i < count; ++i) sweeps = std::max(sweeps, default_sweeps(facs[i], refine));
-    std::vector<const MvPlan*> pg, pl, pu;
-    for (int32_t i = 0; i < count; ++i) {
-      pg.push_back(&facs[i]->mvG);
-      pl.push_back(&facs[i]->mvLi);
-      pu.push_back(&facs[i]->mvUi);
-    }
-    MvBatch bG, bL, bU;
-    bG.create(pg, s);
-    bL.create(pl, s);
-    bU.create(pu, s);
-    // the products of a step (as in hlevy_step), one table of problems each
-    enum { T_AXPY, T_SUB, T_W, T_RES, T_LI, T_ADD, T_NEXT, T_COUNT };
-    std::vector<std::vector<MvInst>> tab(T_COUNT);
+    std::vector<StepState> st;
     for (int32_t i = 0; i < count; ++i) {
       hlevy_fac* f = facs[i];
-      double* uc = f->w_u.as<double>();
-      double* w = f->w_d.as<double>();
-      double* z = f->w_z.as<double>();
-      double* r = f->w_y.as<double>();
-      MvInst t{};
-      t.dev = f->mvLi.dev;   // z = 2 L^{-1} u^n
-      t.x = uc;
-      t.epi = MvEpi{};
-      t.epi.kind = MV_EPI_AXPY;
-      t.epi.hdt = 2.0;
-      t.epi.y = z;
-      tab[T_AXPY].push_back(t);
-      t.dev = f->mvUi.dev;   // u^{n+1} = U^{-1} z - u^n
-      t.x = z;
-      t.epi = MvEpi{};
-      t.epi.kind = MV_EPI_SUB;
-      t.epi.u = uc;
-      t.epi.y = uc;
-      tab[T_SUB].push_back(t);
-      t.epi = epi_plain(w);  // w = U^{-1} z
-      tab[T_W].push_back(t);
-      t.dev = f->mvG.dev;    // r = 2 u^n - (w - dt/2 G w)
-      t.x = w;
-      t.epi = MvEpi{};
-      t.epi.kind = MV_EPI_CNRES;
-      t.epi.hdt = 0.5 * f->dt;
-      t.epi.u = uc;
-      t.epi.b = w;
-      t.epi.y = r;
-      tab[T_RES].push_back(t);
-      t.dev = f->mvLi.dev;   // z = L^{-1} r
-      t.x = r;
-      t.epi = epi_plain(z);
-      tab[T_LI].push_back(t);
-      t.dev = f->mvUi.dev;   // w += U^{-1} z
-      t.x = z;
-      t.epi = MvEpi{};
-      t.epi.kind = MV_EPI_ADD;
-      t.epi.u = w;
-      t.epi.y = w;
-      tab[T_ADD].push_back(t);
-      t.epi = MvEpi{};       // u^{n+1} = w + U^{-1} z - u^n
-      t.epi.kind = MV_EPI_NEXT;
-      t.epi.b = w;
-      t.epi.u = uc;
-      t.epi.y = uc;
-      tab[T_NEXT].push_back(t);
+      st.push_back(StepState{f, f->w_u.as<double>(), f->w_d.as<double>(), f->w_z.as<double>(), f->w_y.as<double>(),
+                             nullptr, nullptr, nullptr});
+      HL_CHECK(launch_perm_gather(st.back().uc, u[i], f->op->ds.perm.as<int32_t>(), f->op->S.N, s));
     }
-    std::vector<DevBuf> dtab(T_COUNT);
-    for (int k = 0; k < T_COUNT; ++k) upload(dtab[k], tab[k], s);
-    auto T = [&](int k) { return dtab[k].as<MvInst>(); };
+    step_states(st, nsteps, sweeps, s);
     for (int32_t i = 0; i < count; ++i)
-      HL_CHECK(launch_perm_gather(facs[i]->w_u.as<double>(), u[i], facs[i]->op->ds.perm.as<int32_t>(),
-                                  facs[i]->op->S.N, s));
-    for (int64_t n = 0; n < nsteps; ++n) {
-      bL.run(T(T_AXPY), s);
-      if (sweeps == 0) {
-        bU.run(T(T_SUB), s);
-        continue;
-      }
-      bU.run(T(T_W), s);
-      for (int it = 0; it < sweeps; ++it) {
-        bG.run(T(T_RES), s);
-        bL.run(T(T_LI), s);
-        bU.run(T(it + 1 < sweeps ? T_ADD : T_NEXT), s);
-      }
-    }
-    for (int32_t i = 0; i < count; ++i)
-      HL_CHECK(launch_perm_scatter(u[i], facs[i]->w_u.as<double>(), facs[i]->op->ds.perm.as<int32_t>(),
-                                   facs[i]->op->S.N, s));
-    // the tables and maps are freed when this call returns: wait for the
-    // device to finish with them
-    HL_CHECK(hipStreamSynchronize(s));
+      HL_CHECK(launch_perm_scatter(u[i], st[i].uc, facs[i]->op->ds.perm.as<int32_t>(), facs[i]->op->S.N, s));
     return HLEVY_OK;
   });
 }
@@ -2011,5 +2032,280 @@ hlevy_status hlevy_fac_kernel_times(hlevy_fac* f, int32_t reps, void* stream, hl
 
 void hlevy_op_destroy(hlevy_op* op) { delete op; }
 void hlevy_fac_destroy(hlevy_fac* f) { delete f; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving loop: requests (problem, dt, horizon, u0) arrive at any time; each
+// scheduling round admits queued requests in arrival order while the memory
+// of cached operators, factors and request state fits the budget (evicting
+// unused cached operators, least recently used first), assembles and
+// factors the operators not in the cache in one joint plan, and advances
+// every active request by one chunk of steps in one batched step.
+// Requests with equal operator parameters share one cached factor; each
+// request has its own vectors and projection partial buffers.
+// ---------------------------------------------------------------------------
+namespace hl {
+
+struct SrvEntry {
+  std::unique_ptr<hlevy_op, void (*)(hlevy_op*)> op{nullptr, hlevy_op_destroy};
+  std::unique_ptr<hlevy_fac, void (*)(hlevy_fac*)> fac{nullptr, hlevy_fac_destroy};
+  hlevy_problem prob{};
+  hlevy_hparams hp{};
+  double dt = 0;
+  size_t bytes = 0;
+  int refs = 0;
+  uint64_t last_use = 0;
+};
+
+struct SrvReq {
+  int64_t id = 0;
+  std::string key;
+  SrvEntry* e = nullptr;
+  int64_t nsteps = 0, done = 0;
+  int N = 0;
+  double* out = nullptr;
+  DevBuf u0;                   // staged initial condition (natural order)
+  DevBuf vec, pG, pL, pU;      // state while active
+  size_t bytes = 0;
+};
+
+static std::string srv_key(const hlevy_problem& p, const hlevy_hparams& hp, double dt) {
+  std::string k;
+  auto put = [&](const void* v, size_t n) { k.append(reinterpret_cast<const char*>(v), n); };
+  put(&p.dim, 4);
+  put(&p.n, 4);
+  for (double v : {p.lo, p.hi, p.a, p.b[0], p.dim == 2 ? p.b[1] : 0.0, p.c, p.s, p.lambda, p.C, p.r0}) put(&v, 8);
+  put(&hp.leaf, 4);
+  put(&hp.eta, 8);
+  put(&hp.n_block, 4);
+  put(&hp.aca_tol, 8);
+  put(&hp.max_rank, 4);
+  put(&dt, 8);
+  return k;
+}
+
+// resident bytes of an operator and its factor (G, the inverse factors with
+// their FP32 copies on the mixed path, product plans, work vectors)
+static size_t srv_entry_bytes(const Structure& S, int max_rank, bool mixed) {
+  HMat t;
+  const size_t g = t.layout(S, max_rank, FULL, false);
+  const size_t lu = t.layout(S, max_rank, LOWER, false) + t.layout(S, max_rank, UPPER, false);
+  size_t b = g * 8 + lu * (mixed ? 12 : 8) + (size_t)S.N * 8 * 12 + S.lf.size() * 256;
+  return b + b / 16;
+}
+
+}  // namespace hl
+
+struct hlevy_server {
+  hlevy_server_config cfg{};
+  hipStream_t s = nullptr;
+  int64_t next_id = 1;
+  uint64_t tick = 0;
+  size_t used = 0;
+  std::map<std::string, std::unique_ptr<SrvEntry>> cache;
+  std::deque<std::unique_ptr<SrvReq>> queue;
+  std::vector<std::unique_ptr<SrvReq>> active;
+  std::deque<int64_t> finished;
+  hlevy_server_stats st{};
+};
+
+extern "C" {
+
+hlevy_status hlevy_server_create(const hlevy_server_config* cfg, void* stream, hlevy_server** out) {
+  if (!cfg || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (cfg->prec != HLEVY_PREC_FP64 && cfg->prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
+  if (!(cfg->lu_tol > 0.0 && cfg->lu_tol < 1.0)) return fail(HLEVY_ERR_INVALID_ARG, "lu_tol must be in (0, 1)");
+  if (cfg->sweeps < 0 || cfg->sweeps > 64) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
+  if (cfg->chunk < 1 || cfg->max_active < 1) return fail(HLEVY_ERR_INVALID_ARG, "chunk and max_active must be >= 1");
+  return guarded([&]() -> hlevy_status {
+    auto v = std::make_unique<hlevy_server>();
+    v->cfg = *cfg;
+    if (v->cfg.hbm_budget == 0) v->cfg.hbm_budget = (size_t)64 << 30;
+    v->s = as_stream(stream);
+    *out = v.release();
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_server_submit(hlevy_server* v, const hlevy_problem* prob, const hlevy_hparams* hp, double dt,
+                                 int64_t nsteps, const double* u0, double* u_out, int64_t* id) {
+  if (!v || !prob || !hp || !u0 || !u_out || !id) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HLEVY_ERR_INVALID_ARG, "dt must be > 0");
+  if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
+  return guarded([&]() -> hlevy_status {
+    Structure S;
+    std::string e = build_structure(*prob, *hp, S);
+    if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
+    auto r = std::make_unique<SrvReq>();
+    r->id = v->next_id++;
+    r->key = srv_key(*prob, *hp, dt);
+    r->nsteps = nsteps;
+    r->N = S.N;
+    r->out = u_out;
+    r->u0.alloc((size_t)S.N * sizeof(double));
+    HL_CHECK(hipMemcpyAsync(r->u0.p, u0, (size_t)S.N * sizeof(double), hipMemcpyDeviceToDevice, v->s));
+    auto it = v->cache.find(r->key);
+    if (it == v->cache.end()) {
+      auto en = std::make_unique<SrvEntry>();
+      en->prob = *prob;
+      en->hp = *hp;
+      en->dt = dt;
+      en->bytes = srv_entry_bytes(S, hp->max_rank, v->cfg.prec == HLEVY_PREC_MIXED);
+      // not resident until admitted; kept so that later requests find it
+      v->cache.emplace(r->key, std::move(en));
+    }
+    *id = r->id;
+    v->queue.push_back(std::move(r));
+    v->st.submitted++;
+    v->st.queued = (int64_t)v->queue.size();
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, int32_t* ndone) {
+  if (!v || !ndone || (cap > 0 && !done_ids) || cap < 0) return fail(HLEVY_ERR_INVALID_ARG, "bad argument");
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = v->s;
+    // 1. admission (arrival order) under the memory budget
+    std::vector<SrvEntry*> fresh;
+    while (!v->queue.empty() && (int)v->active.size() < v->cfg.max_active) {
+      SrvReq* r = v->queue.front().get();
+      SrvEntry* e = v->cache.at(r->key).get();
+      const size_t req_bytes = (size_t)r->N * 8 * 4 + 65536;
+      const bool pending_fresh = std::find(fresh.begin(), fresh.end(), e) != fresh.end();
+      const size_t need = req_bytes + ((e->op || pending_fresh) ? 0 : e->bytes);
+      while (v->used + need > v->cfg.hbm_budget) {
+        // evict the least recently used idle resident operator (not the
+        // request's own)
+        SrvEntry* lru = nullptr;
+        for (auto& kv : v->cache) {
+          SrvEntry* c = kv.second.get();
+          if (c != e && c->op && c->refs == 0 && (!lru || c->last_use < lru->last_use)) lru = c;
+        }
+        if (!lru) break;
+        lru->fac.reset();
+        lru->op.reset();
+        v->used -= lru->bytes;
+        v->st.evictions++;
+      }
+      const bool idle = v->active.empty() && fresh.empty();
+      if (v->used + need > v->cfg.hbm_budget && !idle) break;   // wait for memory
+      if (e->op || pending_fresh) {
+        v->st.cache_hits++;
+      } else {
+        v->st.cache_misses++;
+        fresh.push_back(e);
+      }
+      v->used += need;
+      e->refs++;
+      r->e = e;
+      r->bytes = req_bytes;
+      v->active.push_back(std::move(v->queue.front()));
+      v->queue.pop_front();
+    }
+    // 2. operators not in the cache: assembly, then one joint factorisation
+    if (!fresh.empty()) {
+      const double t0 = now_s();
+      for (SrvEntry* e : fresh) {
+        hlevy_op* op = nullptr;
+        hlevy_status st = hlevy_assemble(&e->prob, &e->hp, s, &op);
+        if (st != HLEVY_OK) return st;
+        e->op.reset(op);
+      }
+      const double t1 = now_s();
+      std::vector<const hlevy_op*> ops;
+      std::vector<double> dts;
+      for (SrvEntry* e : fresh) {
+        ops.push_back(e->op.get());
+        dts.push_back(e->dt);
+      }
+      std::vector<hlevy_fac*> fo(fresh.size(), nullptr);
+      hlevy_status st = hlevy_factor_batched(ops.data(), dts.data(), (int32_t)ops.size(), v->cfg.prec, v->cfg.lu_tol,
+                                             0, s, fo.data());
+      if (st != HLEVY_OK) return st;
+      for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->fac.reset(fo[q]);
+      v->st.assemble_seconds += t1 - t0;
+      v->st.factor_seconds += now_s() - t1;
+    }
+    // 3. state of newly active requests
+    for (auto& r : v->active) {
+      if (r->vec.p) continue;
+      hlevy_fac* f = r->e->fac.get();
+      r->vec.alloc((size_t)r->N * 4 * sizeof(double));
+      r->pG.alloc(std::max<int64_t>(f->mvG.nslots, 1) * f->mvG.dev.kb * sizeof(double));
+      r->pL.alloc(std::max<int64_t>(f->mvLi.nslots, 1) * f->mvLi.dev.kb * sizeof(double));
+      r->pU.alloc(std::max<int64_t>(f->mvUi.nslots, 1) * f->mvUi.dev.kb * sizeof(double));
+      HL_CHECK(launch_perm_gather(r->vec.as<double>(), r->u0.as<double>(), f->op->ds.perm.as<int32_t>(), r->N, s));
+      r->u0.reset();
+    }
+    // 4. one chunk of steps for every active request
+    if (!v->active.empty()) {
+      // the chunk stops at the earliest finishing request (requests with
+      // no steps left are not stepped)
+      int64_t c = v->cfg.chunk;
+      for (auto& r : v->active)
+        if (r->done < r->nsteps) c = std::min(c, r->nsteps - r->done);
+      if (c > 0) {
+        std::vector<StepState> sts;
+        for (auto& r : v->active) {
+          if (r->done >= r->nsteps) continue;
+          double* b = r->vec.as<double>();
+          sts.push_back(StepState{r->e->fac.get(), b, b + r->N, b + 2 * (size_t)r->N, b + 3 * (size_t)r->N,
+                                  r->pG.as<double>(), r->pL.as<double>(), r->pU.as<double>()});
+        }
+        const double t0 = now_s();
+        step_states(sts, c, v->cfg.sweeps, s);
+        v->st.step_seconds += now_s() - t0;
+        for (auto& r : v->active)
+          if (r->done < r->nsteps) r->done += c;
+        v->st.problem_steps += c * (int64_t)sts.size();
+      }
+    }
+    // 5. finished requests: result to the caller's vector, state released
+    ++v->tick;
+    std::vector<std::unique_ptr<SrvReq>> keep;
+    for (auto& r : v->active) {
+      if (r->done < r->nsteps) {
+        keep.push_back(std::move(r));
+        continue;
+      }
+      HL_CHECK(launch_perm_scatter(r->out, r->vec.as<double>(), r->e->fac->op->ds.perm.as<int32_t>(), r->N, s));
+      HL_CHECK(hipStreamSynchronize(s));
+      r->e->refs--;
+      r->e->last_use = v->tick;
+      v->used -= r->bytes;
+      v->finished.push_back(r->id);
+      v->st.completed++;
+    }
+    v->active.swap(keep);
+    HL_CHECK(hipStreamSynchronize(s));
+    int32_t n = 0;
+    while (n < cap && !v->finished.empty()) {
+      done_ids[n++] = v->finished.front();
+      v->finished.pop_front();
+    }
+    *ndone = n;
+    v->st.active = (int64_t)v->active.size();
+    v->st.queued = (int64_t)v->queue.size();
+    return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_server_stats_get(hlevy_server* v, hlevy_server_stats* out) {
+  if (!v || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  *out = v->st;
+  int64_t res = 0;
+  for (auto& kv : v->cache) res += kv.second->op ? 1 : 0;
+  out->cached_operators = res;
+  out->bytes_in_use = v->used;
+  return HLEVY_OK;
+}
+
+void hlevy_server_destroy(hlevy_server* v) {
+  if (!v) return;
+  (void)hipStreamSynchronize(v->s);
+  delete v;
+}
 
 }  // extern "C"

@@ -61,7 +61,21 @@ class KernelTimes(C.Structure):
 EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
            "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
            "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_step", "hlevy_step_batched",
-           "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy"]
+           "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
+           "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_stats_get",
+           "hlevy_server_destroy"]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("prec", C.c_int32), ("lu_tol", C.c_double), ("sweeps", C.c_int32),
+                ("chunk", C.c_int32), ("max_active", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("active", C.c_int64), ("queued", C.c_int64),
+                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("evictions", C.c_int64),
+                ("cached_operators", C.c_int64), ("problem_steps", C.c_int64), ("bytes_in_use", C.c_size_t),
+                ("assemble_seconds", C.c_double), ("factor_seconds", C.c_double), ("step_seconds", C.c_double)]
 
 
 def _load():
@@ -87,6 +101,12 @@ def _load():
                         C.POINTER(Stats), vp], st),
         "hlevy_fac_kernel_times": ([vp, C.c_int32, vp, C.POINTER(KernelTimes)], st),
         "hlevy_fac_apply": ([vp, C.c_int32, vp, vp, vp], st),
+        "hlevy_server_create": ([C.POINTER(ServerConfig), vp, C.POINTER(vp)], st),
+        "hlevy_server_submit": ([vp, C.POINTER(Problem), C.POINTER(HParams), C.c_double, C.c_int64, vp, vp,
+                                 C.POINTER(C.c_int64)], st),
+        "hlevy_server_poll": ([vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
+        "hlevy_server_stats_get": ([vp, C.POINTER(ServerStats)], st),
+        "hlevy_server_destroy": ([vp], None),
         "hlevy_op_destroy": ([vp], None),
         "hlevy_fac_destroy": ([vp], None),
     }
@@ -288,3 +308,43 @@ def step(fac: Fac, u, nsteps: int, g=None, phi=None, refine=None, stats=False, s
     if st is not None:
         return {k: getattr(st, k) for k, _ in Stats._fields_}
     return None
+
+
+class Server:
+    """Serving loop of the library (hlevy_server_*): submit requests, poll
+    scheduling rounds, collect finished ids."""
+
+    def __init__(self, prec: int = PREC_MIXED, lu_tol: float = 1e-6, sweeps: int = 1, chunk: int = 10,
+                 max_active: int = 256, hbm_budget: int = 0, stream=None):
+        cfg = ServerConfig(int(hbm_budget), int(prec), float(lu_tol), int(sweeps), int(chunk), int(max_active))
+        h = C.c_void_p()
+        _check(lib.hlevy_server_create(C.byref(cfg), _stream(stream), C.byref(h)), "hlevy_server_create")
+        self.h = h
+        self._keep = {}   # id -> (u0, u_out): the output must outlive the request
+
+    def submit(self, prob: Problem, hp: HParams, dt: float, nsteps: int, u0, u_out) -> int:
+        n = prob.n if prob.dim == 1 else prob.n * prob.n
+        rid = C.c_int64()
+        _check(lib.hlevy_server_submit(self.h, C.byref(prob), C.byref(hp), float(dt), int(nsteps),
+                                       _dptr(u0, n), _dptr(u_out, n), C.byref(rid)), "hlevy_server_submit")
+        self._keep[rid.value] = u_out
+        return rid.value
+
+    def poll(self, cap: int = 4096) -> list:
+        ids = (C.c_int64 * cap)()
+        nd = C.c_int32()
+        _check(lib.hlevy_server_poll(self.h, ids, int(cap), C.byref(nd)), "hlevy_server_poll")
+        out = [ids[i] for i in range(nd.value)]
+        for i in out:
+            self._keep.pop(i, None)
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib.hlevy_server_stats_get(self.h, C.byref(st)), "hlevy_server_stats_get")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and lib is not None:
+            lib.hlevy_server_destroy(self.h)
+            self.h = None

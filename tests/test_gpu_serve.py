@@ -1,0 +1,117 @@
+"""GPU tests of the serving loop (hlevy_server_*) through the C ABI.
+
+A served request must give what the single-problem path gives for the
+same problem, dt and horizon (1e-12 relative: the batched products sum in
+another order), must not depend on which other requests share its rounds
+(bit for bit), and must survive admission under a memory budget that
+forces eviction.  Two requests are also checked against the dense oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle.levy_oracle import Problem, cn_run, generator_dense
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_08324_amd import hlevy
+    return hlevy
+
+
+def oracle_problem(w):
+    return Problem(dim=w.dim, n=w.n, lo=w.lo, hi=w.hi, a=w.a, b=tuple(w.b), c=w.c, s=w.s,
+                   lam=w.lam, C=w.C, r0=w.r0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def small_trace():
+    """14 requests over a pool of three 1D and one 2D operator (so that
+    requests share cached factors), horizons 0..40 steps, close arrivals."""
+    pool = W.serving_pool(seed=356, size=3, n1d_log2=(8.5, 10.5), side=(36, 40))
+    pool["2d"] = pool["2d"][:1]
+    tr = W.serving_trace(rate=2000.0, duration=0.007, seed=355, frac_1d=0.75, horizon=(5, 40), pool=pool)
+    tr = tr[:13]
+    zero = dict(tr[0])
+    zero["steps"] = 0
+    zero["w"] = zero["w"].with_(steps=0)
+    return tr + [zero]
+
+
+def served(H, trace, **kw):
+    from paper_1812_08324_amd.serve import replay
+    kw.setdefault("prec", H.PREC_MIXED)
+    kw.setdefault("lu_tol", 1e-6)
+    kw.setdefault("sweeps", 1)
+    return replay(H, torch, trace, W.request_u0, keep_outputs=True, realtime=False, **kw)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def mixed_run(H):
+    tr = small_trace()
+    assert len(tr) >= 10
+    return tr, served(H, tr, chunk=7, max_active=4)
+
+
+def test_served_equals_single_path(H, mixed_run):
+    tr, res = mixed_run
+    assert res["server"]["completed"] == len(tr)
+    assert res["cache_hit_rate"] > 0.0
+    from paper_1812_08324_amd.serve import _problem
+    for i, r in enumerate(tr):
+        w = r["w"]
+        got = host(res["outputs"][i])
+        u0 = W.request_u0(r)
+        if r["steps"] == 0:
+            assert np.array_equal(got, u0)
+            continue
+        p, hp = _problem(H, w)
+        op = H.assemble(p, hp)
+        fac = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+        u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        H.step(fac, u, r["steps"], refine={"sweeps": 1})
+        assert rel(got, host(u)) <= 1e-12, (i, w.name, r["steps"])
+
+
+def test_served_against_oracle(H, mixed_run):
+    tr, res = mixed_run
+    checked = 0
+    for i, r in enumerate(tr):
+        if r["steps"] == 0 or checked == 2:
+            continue
+        w = r["w"]
+        ref = cn_run(generator_dense(oracle_problem(w)), w.dt, r["steps"], W.request_u0(r)).u
+        assert rel(host(res["outputs"][i]), ref) <= 1e-8, (i, w.name)
+        checked += 1
+
+
+def test_result_independent_of_company(H, mixed_run):
+    """Each request served alone gives bit for bit what it gave in the mix."""
+    tr, res = mixed_run
+    for i in (1, 4):
+        alone = served(H, [tr[i]], chunk=7, max_active=4)
+        assert np.array_equal(host(alone["outputs"][0]), host(res["outputs"][i]))
+
+
+def test_tiny_budget_evicts_and_serializes(H, mixed_run):
+    tr, res = mixed_run
+    tight = served(H, tr, chunk=5, max_active=8, hbm_budget=1)
+    st = tight["server"]
+    assert st["completed"] == len(tr)
+    assert st["evictions"] > 0
+    for i in range(len(tr)):
+        assert np.array_equal(host(tight["outputs"][i]), host(res["outputs"][i]))

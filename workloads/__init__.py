@@ -18,7 +18,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-__all__ = ["Workload", "config1", "config2", "config3", "config4_instances",
+__all__ = ["Workload", "config1", "config2", "config3", "config4_instances", "serving_pool", "serving_trace", "request_u0",
            "grid_points", "bump_1d", "ball_power", "gaussians_2d"]
 
 
@@ -149,3 +149,58 @@ def config4_instances(count: int = 512, seed: int = 8324, nmin_log2: float = 10.
         w.u0 = bump_1d(grid_points(1, n, -1.0, 1.0), 0.1)
         out.append(w)
     return out
+
+
+def serving_pool(seed: int = 356, size: int = 64, n1d_log2=(12.0, 16.0), side=(64, 256)) -> dict:
+    """Operator configurations requests draw from (so that parameter sets
+    repeat): `size` 1D tempered problems (N log-uniform, s, drift, sigma^2,
+    lambda as in the batched workload) and `size` 2D fractional problems on
+    the unit square (side uniform in [side[0], side[1]], s ~ U(0.1, 0.9),
+    ACA at 1e-8 with rank <= 32).  Returns {"1d": [...], "2d": [...]}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p1, p2 = [], []
+    for i in range(size):
+        n = int(round(2.0 ** rng.uniform(*n1d_log2)))
+        s = float(rng.uniform(0.1, 0.9))
+        b = float(rng.uniform(-1.0, 1.0))
+        sig2 = float(rng.uniform(0.0, 0.2))
+        lam = float(rng.uniform(0.0, 2.0))
+        p1.append(Workload(name="pool1d_%d" % i, dim=1, n=n, lo=-1.0, hi=1.0, s=s, lam=lam, a=0.5 * sig2,
+                           b=(b, 0.0), dt=1e-3, aca_tol=1e-10, max_rank=16, lu_tol=1e-6))
+    for i in range(size):
+        n = int(rng.integers(side[0], side[1] + 1))
+        s = float(rng.uniform(0.1, 0.9))
+        p2.append(Workload(name="pool2d_%d" % i, dim=2, n=n, lo=0.0, hi=1.0, s=s, dt=1e-3, aca_tol=1e-8,
+                           max_rank=32, lu_tol=1e-6))
+    return {"1d": p1, "2d": p2}
+
+
+def serving_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 355, frac_1d: float = 0.7,
+                  horizon=(50, 500), pool: dict | None = None) -> list:
+    """Poisson arrivals (exponential gaps of mean 1/rate) over `duration`
+    seconds; each request picks 1D with probability frac_1d, a pool entry
+    uniformly and a horizon uniform in [horizon[0], horizon[1]] steps.
+    Returns dicts {"t": arrival time, "w": Workload (without u0), "steps":
+    horizon, "seed": the request's seed}; request_u0() makes its u0."""
+    pool = pool if pool is not None else serving_pool()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, t = [], 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > duration:
+            break
+        one_d = bool(rng.uniform() < frac_1d)
+        lst = pool["1d"] if one_d else pool["2d"]
+        w = lst[int(rng.integers(0, len(lst)))]
+        steps = int(rng.integers(horizon[0], horizon[1] + 1))
+        rseed = int(rng.integers(0, 2 ** 31 - 1))
+        out.append({"t": t, "w": w.with_(steps=steps), "steps": steps, "seed": rseed})
+    return out
+
+
+def request_u0(req: dict) -> np.ndarray:
+    """Initial condition of a serving request: 1D the Gaussian bump, 2D eight
+    Gaussians drawn with the request's seed."""
+    w = req["w"]
+    x = grid_points(w.dim, w.n, w.lo, w.hi)
+    return bump_1d(x, 0.1) if w.dim == 1 else gaussians_2d(x, req["seed"])
