@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison job")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-worklist measurement")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="arrival window of the serving measurement (0 = skip)")
+    ap.add_argument("--serve-frac-1d", type=float, default=1.0,
+                    help="share of 1D requests in the served trace (the rest 2D)")
     ap.add_argument("--job-only", action="store_true", help="run warmup + timed jobs only (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain device copies of 2 GiB (HBM counter calibration)")
@@ -152,6 +156,36 @@ def bench_batched(H, torch, sweeps, lu_tol):
         "steady_problem_steps_per_s": len(ws) * steps / (t4 - t3),
         "step": {"bytes": step_bytes, "ms": 1e3 * (t4 - t3) / steps, "GBps": gbps, "frac": gbps / HBM_PEAK_GBS,
                  "note": "all kernels of a batched step (projections, gathers) over its algorithmic bytes"},
+    }
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_serving(H, torch, seconds, frac_1d, sweeps, lu_tol):
+    """The serving loop on a seeded Poisson trace (200 requests/s over
+    `seconds`; pool of 64 1D and 64 2D operator configurations, PCG64 seeds
+    355 and 356; horizons U{50..500} steps of dt = 1e-3), replayed on the
+    host clock; latency = arrival to result."""
+    import workloads as W
+    from paper_1812_08324_amd.serve import replay
+    tr = W.serving_trace(duration=seconds, frac_1d=frac_1d)
+    res = replay(H, torch, tr, W.request_u0, realtime=True, prec=H.PREC_MIXED, lu_tol=lu_tol, sweeps=sweeps,
+                 chunk=10, max_active=1024, log=progress)
+    st = res["server"]
+    offered = sum(r["steps"] for r in tr) / seconds
+    return {
+        "workload": f"serve_poisson200_{seconds:g}s_1d{frac_1d:g}",
+        "requests": res["requests"], "arrival_window_s": seconds, "wall_s": res["wall_s"],
+        "latency_p50_s": res["latency_p50_s"], "latency_p99_s": res["latency_p99_s"],
+        "latency_mean_s": res["latency_mean_s"],
+        "problem_steps_per_s": res["problem_steps_per_s"], "offered_problem_steps_per_s": offered,
+        "saturated": res["problem_steps_per_s"] < 0.95 * offered,
+        "cache_hit_rate": res["cache_hit_rate"],
+        "operators_factored": st["cache_misses"], "evictions": st["evictions"],
+        "server_seconds": {"assemble": st["assemble_seconds"], "factor": st["factor_seconds"],
+                           "steps": st["step_seconds"]},
     }
 
 
@@ -296,9 +330,16 @@ def main():
     }
     line.update(extra)
     del fac, op
+    progress("headline job done")
     if not args.no_batched:
         line["batched"] = bench_batched(H, torch, args.sweeps, args.lu_tol_mixed)
+        progress("batched workload done")
+    if args.serve_seconds > 0:
+        line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.sweeps,
+                                        args.lu_tol_mixed)
+        progress("serving done")
     if not args.no_cpu_baseline:
+        progress("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(w)
         if "batched" in line:
             # the same oracle timings, scaled to every problem of the batch

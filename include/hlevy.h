@@ -220,10 +220,10 @@ hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_
  *  2. operators not in the cache are assembled and factored in one joint
  *     plan (hlevy_factor_batched); requests with equal problem, hparams and
  *     dt share one cached factor;
- *  3. every active request (at most max_active) advances by one chunk of
- *     steps in one batched step (hlevy_step_batched's products; each
- *     request keeps its own vectors), the chunk ending at the earliest
- *     finishing request;
+ *  3. every active request (at most max_active) advances by
+ *     min(chunk, its steps left) steps in one batched loop
+ *     (hlevy_step_batched's products; each request keeps its own vectors;
+ *     a request whose steps are done sits out the rest of the loop);
  *  4. finished requests get u^{nsteps} written to their u_out.
  * A request's result equals hlevy_step with a factor of the same
  * parameters (same arithmetic, summation order of the batched products).

@@ -74,6 +74,7 @@ struct MvInst {
   MvDev dev;
   const double* x;
   MvEpi epi;
+  int32_t steps, pad;   // the problem takes part in steps 0 .. steps-1 of the launching loop
 };
 
 // Work item of a batched product: problem `inst` and the device address of
@@ -87,9 +88,9 @@ hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStrea
 // Batched product over problems of one rank bucket kb and dense precision:
 // wmap[w] names the tile of projection wavefront w (nw of them), rmap[b]
 // the leaf cluster of gather workgroup b (nr of them); every problem's
-// partials go to its own buffer.
+// partials go to its own buffer.  Problems with steps <= step sit out.
 hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
-                           bool dense_f32, hipStream_t s);
+                           bool dense_f32, int step, hipStream_t s);
 // the two kernels of mv_launch separately; non-null events are attached to
 // the dispatch (start, stop) for timing
 hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0 = nullptr,

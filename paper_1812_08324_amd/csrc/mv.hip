@@ -141,12 +141,13 @@ __global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ t
 // batched: wavefront w takes the tile map[w].p of problem map[w].inst
 template <int KB>
 __global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__ inst,
-                                                      const MvRef* __restrict__ map, int nw) {
+                                                      const MvRef* __restrict__ map, int nw, int step) {
   const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (wid >= nw) return;
   const MvRef m = map[wid];
   const MvTile T = *reinterpret_cast<const MvTile*>(m.p);
   const MvInst& P = inst[wuni(m.inst)];
+  if (wuni(P.steps) <= step) return;   // the problem's steps of this loop are done
   project_any<KB>(T, P.x, P.dev.part, threadIdx.x & 63);
 }
 
@@ -284,11 +285,12 @@ constexpr int MV_GWB = 4;
 
 template <typename TD, int KB>
 __global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __restrict__ inst,
-                                                             const MvRef* __restrict__ map) {
+                                                             const MvRef* __restrict__ map, int step) {
   __shared__ GatherLds<KB, MV_GWB> L;
   const MvRef m = map[blockIdx.x];
   const MvRow R = *reinterpret_cast<const MvRow*>(m.p);
   const MvInst& P = inst[wuni(m.inst)];
+  if (wuni(P.steps) <= step) return;   // whole workgroup, before any barrier
   const MvEpi epi = P.epi;
   gather_rows<TD, KB, MV_GWB>(R, P.dev.ents, P.x, P.dev.part, epi, L);
 }
@@ -357,24 +359,25 @@ hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipS
 
 template <int KB>
 static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
-                    hipStream_t s) {
-  if (nw > 0) hipLaunchKernelGGL((k_mv_project_b<KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw);
+                    int step, hipStream_t s) {
+  if (nw > 0)
+    hipLaunchKernelGGL((k_mv_project_b<KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
   if (nr > 0) {
     if (dense_f32)
-      hipLaunchKernelGGL((k_mv_gather_b<float, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap);
+      hipLaunchKernelGGL((k_mv_gather_b<float, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
     else
-      hipLaunchKernelGGL((k_mv_gather_b<double, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap);
+      hipLaunchKernelGGL((k_mv_gather_b<double, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
   }
 }
 
 hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
-                           bool dense_f32, hipStream_t s) {
+                           bool dense_f32, int step, hipStream_t s) {
   if (kb == 8)
-    batch_t<8>(inst, wmap, nw, rmap, nr, dense_f32, s);
+    batch_t<8>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
   else if (kb == 16)
-    batch_t<16>(inst, wmap, nw, rmap, nr, dense_f32, s);
+    batch_t<16>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
   else if (kb == 32)
-    batch_t<32>(inst, wmap, nw, rmap, nr, dense_f32, s);
+    batch_t<32>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

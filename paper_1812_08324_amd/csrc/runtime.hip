@@ -1195,10 +1195,10 @@ struct MvBatch {
     upload(dw, w, s);
     upload(dr, r, s);
   }
-  void run(const MvInst* inst, hipStream_t s) const {
+  void run(const MvInst* inst, int step, hipStream_t s) const {
     for (const Group& g : groups)
       HL_CHECK(mv_batch_launch(inst, dw.as<MvRef>() + g.w0, g.nw, dr.as<MvRef>() + g.r0, g.nr, g.kb, g.f32 != 0,
-                               s));
+                               step, s));
   }
 };
 
@@ -1265,13 +1265,15 @@ static double frac_constant(int d, double s) {
 }
 
 // One problem advanced by step_states: its factor, its vectors (cluster
-// order: u^n, the iterate w, two temporaries) and, optionally, its own
-// projection partial buffers for G, L^{-1}, U^{-1} (null: the plans' own).
-// Problems that share a factor in one batch need buffers of their own.
+// order: u^n, the iterate w, two temporaries), optionally its own
+// projection partial buffers for G, L^{-1}, U^{-1} (null: the plans' own;
+// problems that share a factor in one batch need buffers of their own) and
+// its number of steps (negative: all steps of the call).
 struct StepState {
   hlevy_fac* f;
   double *uc, *w, *z, *r;
   double *partG, *partL, *partU;
+  int64_t steps = -1;
 };
 
 // Unforced Crank-Nicolson steps of every state (hlevy_step's recursion:
@@ -1280,6 +1282,7 @@ struct StepState {
 // (the tables are freed here).
 static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sweeps, hipStream_t s) {
   if (st.empty() || nsteps == 0) return;
+  if (nsteps > INT32_MAX) throw DeviceError("internal: too many steps in one batched call");
   std::vector<const MvPlan*> pg, pl, pu;
   for (const StepState& x : st) {
     pg.push_back(&x.f->mvG);
@@ -1299,6 +1302,7 @@ static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sw
     if (x.partL) dL.part = x.partL;
     if (x.partU) dU.part = x.partU;
     MvInst t{};
+    t.steps = (int32_t)(x.steps < 0 ? nsteps : std::min<int64_t>(x.steps, nsteps));
     t.dev = dL;   // z = 2 L^{-1} u^n
     t.x = x.uc;
     t.epi = MvEpi{};
@@ -1346,16 +1350,17 @@ static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sw
   for (int k = 0; k < T_COUNT; ++k) upload(dtab[k], tab[k], s);
   auto T = [&](int k) { return dtab[k].as<MvInst>(); };
   for (int64_t n = 0; n < nsteps; ++n) {
-    bL.run(T(T_AXPY), s);
+    const int k = (int)n;
+    bL.run(T(T_AXPY), k, s);
     if (sweeps == 0) {
-      bU.run(T(T_SUB), s);
+      bU.run(T(T_SUB), k, s);
       continue;
     }
-    bU.run(T(T_W), s);
+    bU.run(T(T_W), k, s);
     for (int it = 0; it < sweeps; ++it) {
-      bG.run(T(T_RES), s);
-      bL.run(T(T_LI), s);
-      bU.run(T(it + 1 < sweeps ? T_ADD : T_NEXT), s);
+      bG.run(T(T_RES), k, s);
+      bL.run(T(T_LI), k, s);
+      bU.run(T(it + 1 < sweeps ? T_ADD : T_NEXT), k, s);
     }
   }
   // the tables and maps are freed on return: wait for the device first
@@ -2241,25 +2246,24 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
     }
     // 4. one chunk of steps for every active request
     if (!v->active.empty()) {
-      // the chunk stops at the earliest finishing request (requests with
-      // no steps left are not stepped)
-      int64_t c = v->cfg.chunk;
-      for (auto& r : v->active)
-        if (r->done < r->nsteps) c = std::min(c, r->nsteps - r->done);
+      // each request takes min(chunk, steps left) steps of the round
+      std::vector<StepState> sts;
+      int64_t c = 0, total = 0;
+      for (auto& r : v->active) {
+        const int64_t k = std::min<int64_t>(v->cfg.chunk, r->nsteps - r->done);
+        if (k <= 0) continue;
+        double* b = r->vec.as<double>();
+        sts.push_back(StepState{r->e->fac.get(), b, b + r->N, b + 2 * (size_t)r->N, b + 3 * (size_t)r->N,
+                                r->pG.as<double>(), r->pL.as<double>(), r->pU.as<double>(), k});
+        c = std::max(c, k);
+        total += k;
+      }
       if (c > 0) {
-        std::vector<StepState> sts;
-        for (auto& r : v->active) {
-          if (r->done >= r->nsteps) continue;
-          double* b = r->vec.as<double>();
-          sts.push_back(StepState{r->e->fac.get(), b, b + r->N, b + 2 * (size_t)r->N, b + 3 * (size_t)r->N,
-                                  r->pG.as<double>(), r->pL.as<double>(), r->pU.as<double>()});
-        }
         const double t0 = now_s();
         step_states(sts, c, v->cfg.sweeps, s);
         v->st.step_seconds += now_s() - t0;
-        for (auto& r : v->active)
-          if (r->done < r->nsteps) r->done += c;
-        v->st.problem_steps += c * (int64_t)sts.size();
+        for (auto& r : v->active) r->done += std::min<int64_t>(v->cfg.chunk, r->nsteps - r->done);
+        v->st.problem_steps += total;
       }
     }
     // 5. finished requests: result to the caller's vector, state released

@@ -20,7 +20,7 @@ def _problem(H, w):
     return p, hp
 
 
-def replay(H, torch, trace, make_u0, keep_outputs=False, realtime=True, **server_kw) -> dict:
+def replay(H, torch, trace, make_u0, keep_outputs=False, realtime=True, log=None, **server_kw) -> dict:
     """Serve `trace` (dicts with "t", "w", "steps") on a new Server.
 
     make_u0(req) -> numpy initial condition.  realtime=False submits every
@@ -39,7 +39,11 @@ def replay(H, torch, trace, make_u0, keep_outputs=False, realtime=True, **server
     t0 = time.perf_counter()
     nxt = 0
     finished = 0
+    last_log = 0.0
     while finished < n:
+        if log is not None and time.perf_counter() - t0 - last_log > 5.0:
+            last_log = time.perf_counter() - t0
+            log(f"serving: {finished}/{n} done, {nxt} submitted at t={last_log:.1f}s")
         now = time.perf_counter() - t0
         while nxt < n and arrival[nxt] <= now:
             r = trace[nxt]
