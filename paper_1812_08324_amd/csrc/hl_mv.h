@@ -69,12 +69,18 @@ struct MvDev {
   int32_t dense_f32;   // dense leaves stored in FP32 (else FP64)
 };
 
-// One problem of a batched product: its plan, input and epilogue.
+// One problem of a batched product: its plan and nr <= MV_RMAX members
+// (right-hand sides of the same operator), each with its input, partial
+// buffer, epilogue and step limit (the member takes part in steps
+// 0 .. steps-1 of the launching loop).
+constexpr int MV_RMAX = 4;
 struct MvInst {
   MvDev dev;
-  const double* x;
-  MvEpi epi;
-  int32_t steps, pad;   // the problem takes part in steps 0 .. steps-1 of the launching loop
+  int32_t nr, pad;
+  int32_t steps[MV_RMAX];
+  const double* x[MV_RMAX];
+  double* part[MV_RMAX];
+  MvEpi epi[MV_RMAX];
 };
 
 // Work item of a batched product: problem `inst` and the device address of
@@ -85,12 +91,15 @@ struct MvRef {
 };
 
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
-// Batched product over problems of one rank bucket kb and dense precision:
-// wmap[w] names the tile of projection wavefront w (nw of them), rmap[b]
-// the leaf cluster of gather workgroup b (nr of them); every problem's
-// partials go to its own buffer.  Problems with steps <= step sit out.
+// Batched product over problems of one rank bucket kb, dense precision and
+// member bound rmax (1, 2 or mv_batch_rmax(kb); every problem of the launch
+// has nr <= rmax): wmap[w] names the tile of projection wavefront w (nw of
+// them), rmap[b] the leaf cluster of gather workgroup b (nr of them).
+// Members with steps <= step sit out.
 hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
-                           bool dense_f32, int step, hipStream_t s);
+                           bool dense_f32, int rmax, int step, hipStream_t s);
+// largest member count of a batched problem with rank bucket kb
+int mv_batch_rmax(int kb);
 // the two kernels of mv_launch separately; non-null events are attached to
 // the dispatch (start, stop) for timing
 hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0 = nullptr,

@@ -138,19 +138,6 @@ __global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ t
   project_any<KB>(T, x, part, threadIdx.x & 63);
 }
 
-// batched: wavefront w takes the tile map[w].p of problem map[w].inst
-template <int KB>
-__global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__ inst,
-                                                      const MvRef* __restrict__ map, int nw, int step) {
-  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (wid >= nw) return;
-  const MvRef m = map[wid];
-  const MvTile T = *reinterpret_cast<const MvTile*>(m.p);
-  const MvInst& P = inst[wuni(m.inst)];
-  if (wuni(P.steps) <= step) return;   // the problem's steps of this loop are done
-  project_any<KB>(T, P.x, P.dev.part, threadIdx.x & 63);
-}
-
 constexpr int MV_GW = 8;   // wavefronts per gather workgroup
 
 template <typename TL, int KB>
@@ -165,6 +152,37 @@ __device__ __forceinline__ double gather_lowrank(const void* p, int ii, int ld, 
 #pragma unroll
   for (int q = 0; q < KB; ++q) acc += uv[q] * t[q];
   return acc;
+}
+
+// y[r] = epilogue of the product's row value v (see MvEpi)
+__device__ __forceinline__ void epilogue(const MvEpi& epi, int r, double v) {
+  double out;
+  switch (epi.kind) {
+    case MV_EPI_RHS:   // b = u + hdt * G u + cg * g
+      out = epi.u[r] + epi.hdt * v + (epi.g ? epi.cg * epi.g[r] : 0.0);
+      break;
+    case MV_EPI_RESID:  // r = b - (x - hdt * G x)
+      out = epi.b[r] - (epi.u[r] - epi.hdt * v);
+      break;
+    case MV_EPI_ADD:    // y = u + A x (refinement update)
+      out = epi.u[r] + v;
+      break;
+    case MV_EPI_AXPY:
+      out = epi.hdt * v + (epi.g ? epi.cg * epi.g[r] : 0.0);
+      break;
+    case MV_EPI_CNRES:
+      out = (2.0 * epi.u[r] + (epi.g ? epi.cg * epi.g[r] : 0.0)) - (epi.b[r] - epi.hdt * v);
+      break;
+    case MV_EPI_NEXT:
+      out = (epi.b[r] + v) - epi.u[r];
+      break;
+    case MV_EPI_SUB:
+      out = v - epi.u[r];
+      break;
+    default:
+      out = v;
+  }
+  epi.y[r] = out;
 }
 
 template <int KB, int GW = MV_GW>
@@ -236,34 +254,7 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
     double v = 0.0;
 #pragma unroll
     for (int w = 0; w < GW; w += 2) v += red[w][i] + red[w + 1][i];
-    const int r = R.lo + i;
-    double out;
-    switch (epi.kind) {
-      case MV_EPI_RHS:   // b = u + hdt * G u + cg * g
-        out = epi.u[r] + epi.hdt * v + (epi.g ? epi.cg * epi.g[r] : 0.0);
-        break;
-      case MV_EPI_RESID:  // r = b - (x - hdt * G x)
-        out = epi.b[r] - (epi.u[r] - epi.hdt * v);
-        break;
-      case MV_EPI_ADD:    // y = u + A x (refinement update)
-        out = epi.u[r] + v;
-        break;
-      case MV_EPI_AXPY:
-        out = epi.hdt * v + (epi.g ? epi.cg * epi.g[r] : 0.0);
-        break;
-      case MV_EPI_CNRES:
-        out = (2.0 * epi.u[r] + (epi.g ? epi.cg * epi.g[r] : 0.0)) - (epi.b[r] - epi.hdt * v);
-        break;
-      case MV_EPI_NEXT:
-        out = (epi.b[r] + v) - epi.u[r];
-        break;
-      case MV_EPI_SUB:
-        out = v - epi.u[r];
-        break;
-      default:
-        out = v;
-    }
-    epi.y[r] = out;
+    epilogue(epi, R.lo + i, v);
   }
 }
 
@@ -275,24 +266,6 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
   __shared__ GatherLds<KB> L;
   const MvRow R = rows[blockIdx.x];
   gather_rows<TD, KB>(R, ents, x, part, epi, L);
-}
-
-// batched: workgroup b takes the leaf cluster map[b].p of problem
-// map[b].inst.  Batches mostly hold small problems with a few entries per
-// leaf cluster, so the workgroups are half as wide as in the single-problem
-// kernel and twice as many stay resident per CU.
-constexpr int MV_GWB = 4;
-
-template <typename TD, int KB>
-__global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __restrict__ inst,
-                                                             const MvRef* __restrict__ map, int step) {
-  __shared__ GatherLds<KB, MV_GWB> L;
-  const MvRef m = map[blockIdx.x];
-  const MvRow R = *reinterpret_cast<const MvRow*>(m.p);
-  const MvInst& P = inst[wuni(m.inst)];
-  if (wuni(P.steps) <= step) return;   // whole workgroup, before any barrier
-  const MvEpi epi = P.epi;
-  gather_rows<TD, KB, MV_GWB>(R, P.dev.ents, P.x, P.dev.part, epi, L);
 }
 
 int project_rows_per_pass(int kb, bool f32) {
@@ -357,36 +330,250 @@ hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipS
   return hipGetLastError();
 }
 
-template <int KB>
-static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
-                    int step, hipStream_t s) {
-  if (nw > 0)
-    hipLaunchKernelGGL((k_mv_project_b<KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
-  if (nr > 0) {
-    if (dense_f32)
-      hipLaunchKernelGGL((k_mv_gather_b<float, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
-    else
-      hipLaunchKernelGGL((k_mv_gather_b<double, KB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
-  }
-}
-
-hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
-                           bool dense_f32, int step, hipStream_t s) {
-  if (kb == 8)
-    batch_t<8>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
-  else if (kb == 16)
-    batch_t<16>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
-  else if (kb == 32)
-    batch_t<32>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s) {
   hipError_t e = project_launch(M, x, s);
   if (e != hipSuccess) return e;
   return gather_launch(M, x, epi, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched products with up to R right-hand sides per problem (requests that
+// share one operator): every matrix value is loaded once and applied to all
+// member vectors.  A problem (MvInst) lists nr <= R members; member r takes
+// part while its step limit exceeds the loop's step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned member_mask(const MvInst& P, int step) {
+  unsigned m = 0;
+  const int nr = wuni(P.nr);
+  for (int r = 0; r < nr; ++r)
+    if (wuni(P.steps[r]) > step) m |= 1u << r;
+  return m;
+}
+
+// projection tile for the members in `mask`: k partial sums per member
+template <typename TL, int KB, int R>
+__device__ __forceinline__ void project_tile_r(const MvTile& T, const MvInst& P, unsigned mask, int lane) {
+  constexpr int RPL = rows_per_lane<TL, KB>();
+  const gptr<TL> V = wuni_ptr<TL>(T.V);
+  const double* xs[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) xs[r] = (mask >> r & 1u) ? P.x[r] + T.xoff : P.x[0] + T.xoff;
+  double acc[R][KB];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < KB; ++q) acc[r][q] = 0.0;
+  for (int r0 = 0; r0 < T.n; r0 += 64 * RPL) {
+    TL v[RPL][KB];
+    double xv[R][RPL];
+    // unconditional loads (see project_tile); inactive members read member
+    // 0's vector and are never stored
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int j = r0 + u * 64 + lane;
+      const bool ok = j < T.n;
+      const int jj = ok ? j : 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double xr = xs[r][jj];
+        xv[r][u] = ok ? xr : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < KB; ++q) v[u][q] = V[(unsigned)(jj + T.ld * min(q, T.k - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        const double vv = (double)v[u][q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][q] += vv * xv[r][u];
+      }
+  }
+  constexpr int G = 64 / KB;
+  const int col = lane / G;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!(mask >> r & 1u)) continue;
+    ColReduce<KB, 32>::run(acc[r], lane);
+    if (lane % G == 0 && col < T.k) P.part[r][(size_t)T.slot * KB + col] = acc[r][0];
+  }
+}
+
+template <int KB, int R>
+__global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__ inst,
+                                                      const MvRef* __restrict__ map, int nw, int step) {
+  const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (wid >= nw) return;   // whole wavefronts leave; no block barrier below
+  const MvRef m = map[wid];
+  const MvTile T = *reinterpret_cast<const MvTile*>(m.p);
+  const MvInst& P = inst[wuni(m.inst)];
+  const unsigned mask = member_mask(P, step);
+  if (mask == 0) return;
+  if (wuni(T.f32))
+    project_tile_r<float, KB, R>(T, P, mask, threadIdx.x & 63);
+  else
+    project_tile_r<double, KB, R>(T, P, mask, threadIdx.x & 63);
+}
+
+// Batches mostly hold small problems with a few entries per leaf cluster,
+// so the gather workgroups are half as wide as in the single-problem kernel
+// and twice as many stay resident per CU.
+constexpr int MV_GWB = 4;
+
+template <int KB, int R>
+struct GatherLdsR {
+  static constexpr int E = MV_EMAX / R;   // entries staged per round
+  double red[R][MV_GWB][64];
+  MvEntry se[E];
+  double ts[R][E * KB];
+};
+
+template <typename TD, int KB, int R>
+__global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __restrict__ inst,
+                                                             const MvRef* __restrict__ map, int step) {
+  __shared__ GatherLdsR<KB, R> L;
+  constexpr int E = GatherLdsR<KB, R>::E;
+  const MvRef m = map[blockIdx.x];
+  const MvRow Rw = *reinterpret_cast<const MvRow*>(m.p);
+  const MvInst& P = inst[wuni(m.inst)];
+  const unsigned mask = member_mask(P, step);
+  if (mask == 0) return;   // whole workgroup, before any barrier
+  const MvEntry* __restrict__ ents = P.dev.ents;
+  const int i = threadIdx.x & 63, g = wuni(threadIdx.x >> 6);
+  const int mr = Rw.hi - Rw.lo;
+  const int ii = i < mr ? i : mr - 1;   // clamped row: loads stay in bounds, result discarded
+  const double* xs[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) xs[r] = (mask >> r & 1u) ? P.x[r] : P.x[0];
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int base = Rw.ebeg; base < Rw.eend; base += E) {
+    const int cnt = min(E, Rw.eend - base);
+    __syncthreads();
+    {
+      const long long* src = reinterpret_cast<const long long*>(ents + base);
+      long long* dst = reinterpret_cast<long long*>(L.se);
+      const int words = cnt * (int)(sizeof(MvEntry) / 8);
+      for (int e = threadIdx.x; e < words; e += 64 * MV_GWB) dst[e] = src[e];
+    }
+    __syncthreads();
+    // t_b of the low-rank entries per member: sum of its partials in slot order
+    for (int it = threadIdx.x; it < R * cnt * KB; it += 64 * MV_GWB) {
+      const int r = it / (cnt * KB), rem = it % (cnt * KB);
+      const int e = rem / KB, q = rem % KB;
+      const MvEntry& En = L.se[e];
+      double s = 0.0;
+      if ((mask >> r & 1u) && En.kind != 0 && q < En.k) {
+        const double* p = P.part[r] + (size_t)En.slot * KB + q;
+        for (int c = 0; c < En.n; ++c) s += p[(size_t)c * KB];
+      }
+      L.ts[r][rem] = s;
+    }
+    __syncthreads();
+    for (int e = g; e < cnt; e += MV_GWB) {
+      const int kind = wuni(L.se[e].kind), en = wuni(L.se[e].n), ek = wuni(L.se[e].k), ld = wuni(L.se[e].ld);
+      if (kind == 0) {
+        const gptr<TD> D = wuni_ptr<TD>(L.se[e].ptr);
+        const int xo = wuni(L.se[e].xoff);
+        double xl[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) xl[r] = i < en ? xs[r][xo + i] : 0.0;
+        int j = 0;
+        for (; j + 16 <= en; j += 16) {
+          double dv[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) dv[q] = (double)D[(unsigned)(ii + ld * (j + q))];
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += dv[q] * bcast_lane(xl[r], j + q);
+        }
+        for (; j < en; ++j) {
+          const double dv = (double)D[(unsigned)(ii + ld * j)];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] += dv * bcast_lane(xl[r], j);
+        }
+      } else {
+        double uv[KB];
+        if (kind == 1) {
+          const gptr<double> U = wuni_ptr<double>(L.se[e].ptr);
+#pragma unroll
+          for (int q = 0; q < KB; ++q) uv[q] = U[(unsigned)(ii + ld * min(q, ek - 1))];
+        } else {
+          const gptr<float> U = wuni_ptr<float>(L.se[e].ptr);
+#pragma unroll
+          for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double* t = L.ts[r] + e * KB;
+          double a = 0.0;
+#pragma unroll
+          for (int q = 0; q < KB; ++q) a += uv[q] * t[q];
+          acc[r] += a;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) L.red[r][g][i] = acc[r];
+  __syncthreads();
+  if (g == 0 && i < mr) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!(mask >> r & 1u)) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < MV_GWB; w += 2) v += L.red[r][w][i] + L.red[r][w + 1][i];
+      epilogue(P.epi[r], Rw.lo + i, v);
+    }
+  }
+}
+
+template <int KB, int R>
+static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
+                    int step, hipStream_t s) {
+  if (nw > 0)
+    hipLaunchKernelGGL((k_mv_project_b<KB, R>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
+  if (nr > 0) {
+    if (dense_f32)
+      hipLaunchKernelGGL((k_mv_gather_b<float, KB, R>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
+    else
+      hipLaunchKernelGGL((k_mv_gather_b<double, KB, R>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
+  }
+}
+
+template <int KB>
+static hipError_t batch_r(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
+                          int rmax, int step, hipStream_t s) {
+  if (rmax == 1)
+    batch_t<KB, 1>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
+  else if (rmax == 2)
+    batch_t<KB, 2>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
+  else if (rmax == 4 && KB <= 16)
+    batch_t<KB, (KB <= 16 ? 4 : 2)>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
+  else
+    return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+int mv_batch_rmax(int kb) { return kb <= 16 ? 4 : 2; }
+
+hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
+                           bool dense_f32, int rmax, int step, hipStream_t s) {
+  hipError_t e;
+  if (kb == 8)
+    e = batch_r<8>(inst, wmap, nw, rmap, nr, dense_f32, rmax, step, s);
+  else if (kb == 16)
+    e = batch_r<16>(inst, wmap, nw, rmap, nr, dense_f32, rmax, step, s);
+  else if (kb == 32)
+    e = batch_r<32>(inst, wmap, nw, rmap, nr, dense_f32, rmax, step, s);
+  else
+    return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
 }
 
 __global__ void k_convert_f32(const double* in, float* out, size_t n) {

@@ -13,6 +13,7 @@
 #include <set>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <chrono>
 #include <cstdlib>
 #include <vector>
@@ -1162,21 +1163,28 @@ struct MvPlan {
 };
 
 // Products with one matrix kind (G, L^{-1} or U^{-1}) of every problem of a
-// batch: problems grouped by rank bucket and dense precision, one projection
-// and one gather launch per group.  Tiles and leaf clusters of the problems
-// are interleaved, so each launch's work is spread over the whole chip.
+// batch: problems grouped by rank bucket, dense precision and member bound
+// (1, 2 or the most a launch takes), one projection and one gather launch
+// per group.  Tiles and leaf clusters of the problems are interleaved, so
+// each launch's work is spread over the whole chip.
 struct MvBatch {
   struct Group {
-    int kb, f32, w0, nw, r0, nr;
+    int kb, f32, rmax, w0, nw, r0, nr;
   };
   std::vector<Group> groups;
   DevBuf dw, dr;
-  void create(const std::vector<const MvPlan*>& plans, hipStream_t s) {
-    std::map<std::pair<int, int>, std::vector<int>> by;
-    for (size_t i = 0; i < plans.size(); ++i) by[{plans[i]->dev.kb, plans[i]->dev.dense_f32}].push_back((int)i);
+  void create(const std::vector<const MvPlan*>& plans, const std::vector<int>& nrs, hipStream_t s) {
+    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    for (size_t i = 0; i < plans.size(); ++i) {
+      const int kb = plans[i]->dev.kb;
+      const int rb = nrs[i] <= 1 ? 1 : (nrs[i] <= 2 ? 2 : mv_batch_rmax(kb));
+      if (nrs[i] > rb) throw DeviceError("internal: too many members in a batched problem");
+      by[{kb, plans[i]->dev.dense_f32, rb}].push_back((int)i);
+    }
     std::vector<MvRef> w, r;
     for (auto& kv : by) {
-      Group g{kv.first.first, kv.first.second, (int)w.size(), 0, (int)r.size(), 0};
+      Group g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), (int)w.size(), 0,
+              (int)r.size(), 0};
       int tmax = 0, rmax = 0;
       for (int i : kv.second) {
         tmax = std::max(tmax, plans[i]->dev.ntiles);
@@ -1198,7 +1206,7 @@ struct MvBatch {
   void run(const MvInst* inst, int step, hipStream_t s) const {
     for (const Group& g : groups)
       HL_CHECK(mv_batch_launch(inst, dw.as<MvRef>() + g.w0, g.nw, dr.as<MvRef>() + g.r0, g.nr, g.kb, g.f32 != 0,
-                               step, s));
+                               g.rmax, step, s));
   }
 };
 
@@ -1278,73 +1286,109 @@ struct StepState {
 
 // Unforced Crank-Nicolson steps of every state (hlevy_step's recursion:
 // M w = 2 u^n, u^{n+1} = w - u^n, `sweeps` refinement sweeps), each product
-// one batched launch pair over all states.  Synchronises `s` before return
-// (the tables are freed here).
+// one batched launch pair over all states.  States of one factor that have
+// partial buffers of their own are taken as members of one batched problem
+// (up to the launch's member bound, longest remaining first), so that their
+// products read the factor once.  Synchronises `s` before return (the
+// tables are freed here).
 static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sweeps, hipStream_t s) {
   if (st.empty() || nsteps == 0) return;
   if (nsteps > INT32_MAX) throw DeviceError("internal: too many steps in one batched call");
+  auto steps_of = [&](const StepState& x) {
+    return (int32_t)(x.steps < 0 ? nsteps : std::min<int64_t>(x.steps, nsteps));
+  };
+  // problems: lists of member states
+  std::vector<std::vector<int>> probs;
+  {
+    std::map<hlevy_fac*, std::vector<int>> byfac;
+    std::vector<hlevy_fac*> order;
+    for (size_t i = 0; i < st.size(); ++i) {
+      const StepState& x = st[i];
+      if (!x.partG || !x.partL || !x.partU) {
+        probs.push_back({(int)i});   // uses the plans' own partial buffers: alone
+        continue;
+      }
+      if (!byfac.count(x.f)) order.push_back(x.f);
+      byfac[x.f].push_back((int)i);
+    }
+    for (hlevy_fac* f : order) {
+      std::vector<int>& v = byfac[f];
+      std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return steps_of(st[a]) > steps_of(st[b]); });
+      const int rm = std::min({mv_batch_rmax(f->mvG.dev.kb), mv_batch_rmax(f->mvLi.dev.kb),
+                               mv_batch_rmax(f->mvUi.dev.kb), MV_RMAX});
+      for (size_t q = 0; q < v.size(); q += rm)
+        probs.emplace_back(v.begin() + q, v.begin() + std::min(v.size(), q + rm));
+    }
+  }
   std::vector<const MvPlan*> pg, pl, pu;
-  for (const StepState& x : st) {
-    pg.push_back(&x.f->mvG);
-    pl.push_back(&x.f->mvLi);
-    pu.push_back(&x.f->mvUi);
+  std::vector<int> nrs;
+  for (auto& pr : probs) {
+    hlevy_fac* f = st[pr[0]].f;
+    pg.push_back(&f->mvG);
+    pl.push_back(&f->mvLi);
+    pu.push_back(&f->mvUi);
+    nrs.push_back((int)pr.size());
   }
   MvBatch bG, bL, bU;
-  bG.create(pg, s);
-  bL.create(pl, s);
-  bU.create(pu, s);
+  bG.create(pg, nrs, s);
+  bL.create(pl, nrs, s);
+  bU.create(pu, nrs, s);
   enum { T_AXPY, T_SUB, T_W, T_RES, T_LI, T_ADD, T_NEXT, T_COUNT };
   std::vector<std::vector<MvInst>> tab(T_COUNT);
-  for (const StepState& x : st) {
-    hlevy_fac* f = x.f;
-    MvDev dG = f->mvG.dev, dL = f->mvLi.dev, dU = f->mvUi.dev;
-    if (x.partG) dG.part = x.partG;
-    if (x.partL) dL.part = x.partL;
-    if (x.partU) dU.part = x.partU;
-    MvInst t{};
-    t.steps = (int32_t)(x.steps < 0 ? nsteps : std::min<int64_t>(x.steps, nsteps));
-    t.dev = dL;   // z = 2 L^{-1} u^n
-    t.x = x.uc;
-    t.epi = MvEpi{};
-    t.epi.kind = MV_EPI_AXPY;
-    t.epi.hdt = 2.0;
-    t.epi.y = x.z;
-    tab[T_AXPY].push_back(t);
-    t.dev = dU;   // u^{n+1} = U^{-1} z - u^n
-    t.x = x.z;
-    t.epi = MvEpi{};
-    t.epi.kind = MV_EPI_SUB;
-    t.epi.u = x.uc;
-    t.epi.y = x.uc;
-    tab[T_SUB].push_back(t);
-    t.epi = epi_plain(x.w);  // w = U^{-1} z
-    tab[T_W].push_back(t);
-    t.dev = dG;   // r = 2 u^n - (w - dt/2 G w)
-    t.x = x.w;
-    t.epi = MvEpi{};
-    t.epi.kind = MV_EPI_CNRES;
-    t.epi.hdt = 0.5 * f->dt;
-    t.epi.u = x.uc;
-    t.epi.b = x.w;
-    t.epi.y = x.r;
-    tab[T_RES].push_back(t);
-    t.dev = dL;   // z = L^{-1} r
-    t.x = x.r;
-    t.epi = epi_plain(x.z);
-    tab[T_LI].push_back(t);
-    t.dev = dU;   // w += U^{-1} z
-    t.x = x.z;
-    t.epi = MvEpi{};
-    t.epi.kind = MV_EPI_ADD;
-    t.epi.u = x.w;
-    t.epi.y = x.w;
-    tab[T_ADD].push_back(t);
-    t.epi = MvEpi{};   // u^{n+1} = w + U^{-1} z - u^n
-    t.epi.kind = MV_EPI_NEXT;
-    t.epi.b = x.w;
-    t.epi.u = x.uc;
-    t.epi.y = x.uc;
-    tab[T_NEXT].push_back(t);
+  for (auto& pr : probs) {
+    hlevy_fac* f = st[pr[0]].f;
+    std::vector<MvInst> t(T_COUNT);
+    for (int k = 0; k < T_COUNT; ++k) {
+      t[k] = MvInst{};
+      t[k].nr = (int32_t)pr.size();
+      t[k].dev = (k == T_RES) ? f->mvG.dev : ((k == T_AXPY || k == T_LI) ? f->mvLi.dev : f->mvUi.dev);
+    }
+    for (size_t m = 0; m < pr.size(); ++m) {
+      const StepState& x = st[pr[m]];
+      double* pG = x.partG ? x.partG : f->mvG.dev.part;
+      double* pL = x.partL ? x.partL : f->mvLi.dev.part;
+      double* pU = x.partU ? x.partU : f->mvUi.dev.part;
+      for (int k = 0; k < T_COUNT; ++k) {
+        t[k].steps[m] = steps_of(x);
+        t[k].part[m] = (k == T_RES) ? pG : ((k == T_AXPY || k == T_LI) ? pL : pU);
+        t[k].epi[m] = MvEpi{};
+      }
+      // z = 2 L^{-1} u^n
+      t[T_AXPY].x[m] = x.uc;
+      t[T_AXPY].epi[m].kind = MV_EPI_AXPY;
+      t[T_AXPY].epi[m].hdt = 2.0;
+      t[T_AXPY].epi[m].y = x.z;
+      // u^{n+1} = U^{-1} z - u^n
+      t[T_SUB].x[m] = x.z;
+      t[T_SUB].epi[m].kind = MV_EPI_SUB;
+      t[T_SUB].epi[m].u = x.uc;
+      t[T_SUB].epi[m].y = x.uc;
+      // w = U^{-1} z
+      t[T_W].x[m] = x.z;
+      t[T_W].epi[m] = epi_plain(x.w);
+      // r = 2 u^n - (w - dt/2 G w)
+      t[T_RES].x[m] = x.w;
+      t[T_RES].epi[m].kind = MV_EPI_CNRES;
+      t[T_RES].epi[m].hdt = 0.5 * f->dt;
+      t[T_RES].epi[m].u = x.uc;
+      t[T_RES].epi[m].b = x.w;
+      t[T_RES].epi[m].y = x.r;
+      // z = L^{-1} r
+      t[T_LI].x[m] = x.r;
+      t[T_LI].epi[m] = epi_plain(x.z);
+      // w += U^{-1} z
+      t[T_ADD].x[m] = x.z;
+      t[T_ADD].epi[m].kind = MV_EPI_ADD;
+      t[T_ADD].epi[m].u = x.w;
+      t[T_ADD].epi[m].y = x.w;
+      // u^{n+1} = w + U^{-1} z - u^n
+      t[T_NEXT].x[m] = x.z;
+      t[T_NEXT].epi[m].kind = MV_EPI_NEXT;
+      t[T_NEXT].epi[m].b = x.w;
+      t[T_NEXT].epi[m].u = x.uc;
+      t[T_NEXT].epi[m].y = x.uc;
+    }
+    for (int k = 0; k < T_COUNT; ++k) tab[k].push_back(t[k]);
   }
   std::vector<DevBuf> dtab(T_COUNT);
   for (int k = 0; k < T_COUNT; ++k) upload(dtab[k], tab[k], s);
