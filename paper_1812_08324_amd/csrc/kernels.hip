@@ -842,7 +842,7 @@ __device__ __forceinline__ void pchol_row(double* Sh, double* Sl, int K, int ls,
       v = use_dd ? dd_mul({Sh[a * ls + b], Sl[a * ls + b]}, rinv) : dd{Sh[a * ls + b] * rinv.hi, 0.0};
     }
     Sh[p * ls + q] = v.hi;
-    Sl[p * ls + q] = v.lo;
+    if (use_dd) Sl[p * ls + q] = v.lo;
   }
 }
 
@@ -976,7 +976,7 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
       s.hi = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     Zh[q * ks + j] = s.hi;
-    Zl[q * ks + j] = s.lo;
+    if (use_dd) Zl[q * ks + j] = s.lo;
   }
   __syncthreads();
   // G_M[i][j] = sum_p R_B[i][p] T1[p][j]  (overwrites G_A)
@@ -997,7 +997,7 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
       s.hi = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     Yh[i * ks + j] = s.hi;
-    Yl[i * ks + j] = s.lo;
+    if (use_dd) Yl[i * ks + j] = s.lo;
   }
   __syncthreads();
   // 3. rank-revealing Cholesky of G_M with the truncation tolerance
@@ -1048,10 +1048,12 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
 }
 
 // LDS of the core for concatenations of at most ks columns: six (ks + 1)^2
-// matrices (row stride ks + 1) and Y_U, Y_V
-__host__ __device__ inline size_t radd_core_lds(int ks) {
-  return (6 * (size_t)(ks + 1) * (ks + 1) + 2 * (size_t)ks * RA_YS) * sizeof(double);
+// matrices (row stride ks + 1; the low parts of double-double only when the
+// tolerance needs them, else three) and Y_U, Y_V
+__host__ __device__ inline size_t radd_core_lds(int ks, bool dd_parts = true) {
+  return ((dd_parts ? 6 : 3) * (size_t)(ks + 1) * (ks + 1) + 2 * (size_t)ks * RA_YS) * sizeof(double);
 }
+__host__ __device__ inline bool radd_needs_dd(double tol) { return tol < 1e-9; }
 
 // Gram sums of the chunk partials (k_flush_gram) -> radd_core -> Y_U, Y_V to
 // the target's workspace for k_flush_expand.  Dynamic LDS: radd_core_lds(ks).
@@ -1059,13 +1061,16 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
                                                               double tol, int ks) {
   extern __shared__ double smem[];
   const int ls = ks + 1;             // row stride of the LDS matrices
+  const bool use_dd = radd_needs_dd(tol);
+  // without double-double the low parts are neither read nor written; their
+  // pointers alias the high parts
   double* Xh = smem;                 // G_B, then R_B (rows at pivot positions)
-  double* Xl = Xh + ls * ls;
-  double* Yh = Xl + ls * ls;         // G_A, then G_M / R_M
-  double* Yl = Yh + ls * ls;
-  double* Zh = Yl + ls * ls;         // T1 = G_A R_B^T (K x rB, row q col j at q * ls + j)
-  double* Zl = Zh + ls * ls;
-  double* YU = Zl + ls * ls;
+  double* Yh = Xh + ls * ls;         // G_A, then G_M / R_M
+  double* Zh = Yh + ls * ls;         // T1 = G_A R_B^T (K x rB, row q col j at q * ls + j)
+  double* Xl = use_dd ? Zh + ls * ls : Xh;
+  double* Yl = use_dd ? Xl + ls * ls : Yh;
+  double* Zl = use_dd ? Yl + ls * ls : Zh;
+  double* YU = use_dd ? Zl + ls * ls : Zh + ls * ls;
   double* YV = YU + ks * RA_YS;
   __shared__ ColMap cm;
   __shared__ int pivB[KMAX], pivM[KMAX];
@@ -1106,9 +1111,11 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
         for (int u = 0; u < 4; ++u) s = dd_add(s, {h[u], l[u]});
       }
       Gh[p * ls + q] = s.hi;
-      Gl[p * ls + q] = s.lo;
       Gh[q * ls + p] = s.hi;
-      Gl[q * ls + p] = s.lo;
+      if (use_dd) {
+        Gl[p * ls + q] = s.lo;
+        Gl[q * ls + p] = s.lo;
+      }
     }
   }
   __syncthreads();
@@ -1961,8 +1968,11 @@ hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, c
                            int ngram, const ChunkItem* expand, int nexp, double tol, int ks, hipStream_t s) {
   if (ntg == 0) return hipSuccess;
   hipLaunchKernelGGL(k_flush_gram, dim3(ngram), dim3(HL_BLOCK), 0, s, tg, terms, gram);
-  if (ks <= 48) {
-    hipLaunchKernelGGL(k_flush_core_fast, dim3(ntg), dim3(HL_BLOCK), radd_core_lds(ks), s, tg, terms, tol, ks);
+  // the pivoted-Cholesky core: up to 48 columns with double-double parts,
+  // up to KMAX without (tolerances >= 1e-9)
+  if (ks <= 48 || (!radd_needs_dd(tol) && ks <= KMAX)) {
+    hipLaunchKernelGGL(k_flush_core_fast, dim3(ntg), dim3(HL_BLOCK), radd_core_lds(ks, radd_needs_dd(tol)), s, tg,
+                       terms, tol, ks);
   } else {
     size_t shm = (4 * (size_t)ks * ks + 2 * (size_t)ks) * sizeof(double);
     hipLaunchKernelGGL(k_flush_core, dim3(ntg), dim3(HL_BLOCK), shm, s, tg, terms, tol, ks);

@@ -157,3 +157,28 @@ def test_config1_mixed_trajectory(H):
     ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0, g=w.g, phi=w.phi).u
     err = np.linalg.norm(host(u) - ref) / np.linalg.norm(ref)
     assert err <= 1e-8, err
+
+
+def test_frac2d_64x64_trajectories():
+    """2D fractional Laplacian (s = 0.75) on a 64 x 64 grid, 20 CN steps:
+    FP64 path within 1e-10 and mixed path (FP32 inverse factors at 1e-6, two
+    refinement sweeps) within 1e-8 of the dense oracle.  The mixed
+    factorisation runs rounded additions of up to 64 columns without
+    double-double parts."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_08324_amd import hlevy as H
+    w = W.config3(s=0.75, n=64, steps=20)
+    ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0).u
+    nref = np.linalg.norm(ref)
+    op = H.assemble(lib_problem(H, w), lib_hparams(H, w))
+    f64 = H.factor(op, w.dt, H.PREC_FP64, w.lu_tol)
+    u = dev(w.u0)
+    H.step(f64, u, w.steps)
+    e64 = np.linalg.norm(host(u) - ref) / nref
+    fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    u = dev(w.u0)
+    H.step(fmx, u, w.steps, refine={"sweeps": 2})
+    emx = np.linalg.norm(host(u) - ref) / nref
+    assert e64 <= 1e-10, e64
+    assert emx <= 1e-8, emx
