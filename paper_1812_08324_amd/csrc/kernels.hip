@@ -1053,7 +1053,7 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
 __host__ __device__ inline size_t radd_core_lds(int ks, bool dd_parts = true) {
   return ((dd_parts ? 6 : 3) * (size_t)(ks + 1) * (ks + 1) + 2 * (size_t)ks * RA_YS) * sizeof(double);
 }
-__host__ __device__ inline bool radd_needs_dd(double tol) { return tol < 1e-9; }
+__host__ __device__ inline bool radd_needs_dd(double tol) { return radd_dd(tol); }
 
 // Gram sums of the chunk partials (k_flush_gram) -> radd_core -> Y_U, Y_V to
 // the target's workspace for k_flush_expand.  Dynamic LDS: radd_core_lds(ks).
@@ -1235,22 +1235,37 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
                                                          int ks) {
   extern __shared__ double smem[];
   const int ls = ks + 1;   // row stride of the LDS matrices
-  double* Xh = smem;
-  double* Xl = Xh + ls * ls;
-  double* Yh = Xl + ls * ls;
-  double* Yl = Yh + ls * ls;
-  double* Zh = Yl + ls * ls;
-  double* Zl = Zh + ls * ls;
-  double* YU = Zl + ls * ls;
+  const bool use_dd = radd_needs_dd(tol);
+  // with double-double parts: X, Y, Z high and low (the 64 x K tile of a
+  // row block lives in Z, 2 ls^2 >= RA_TS ks doubles for ks >= 32); without:
+  // X, Y high only (low pointers alias them, never written) and Z sized for
+  // the tile
+  double *Xh, *Xl, *Yh, *Yl, *Zh, *Zl, *YU;
+  if (use_dd) {
+    Xh = smem;
+    Xl = Xh + ls * ls;
+    Yh = Xl + ls * ls;
+    Yl = Yh + ls * ls;
+    Zh = Yl + ls * ls;
+    Zl = Zh + ls * ls;
+    YU = Zl + ls * ls;
+  } else {
+    Xh = smem;
+    Xl = Xh;
+    Yh = Xh + ls * ls;
+    Yl = Yh;
+    Zh = Yh + ls * ls;
+    Zl = Zh;
+    YU = Zh + max(ls * ls, RA_TS * ks);
+  }
   double* YV = YU + ks * RA_YS;
-  double* tile = Zh;   // 64 x K, column stride RA_TS: Z holds 2 ls^2 >= RA_TS ks doubles (ks >= 32)
+  double* tile = Zh;   // 64 x K, column stride RA_TS
   __shared__ ColMap cm;
   __shared__ RaddCols cs;
   __shared__ int pivB[KMAX], pivM[KMAX];
   __shared__ double sref[2];
   const LFlushTarget T = tg[blockIdx.x];
   const int tid = threadIdx.x;
-  const bool use_dd = tol < 1e-9;
   constexpr int PPT = (KMAX * (KMAX + 1) / 2 + HL_BLOCK - 1) / HL_BLOCK;
   int r = T.rank ? *T.rank : 0;
   // the term list in concatenations of at most ks columns, each one a whole
@@ -1324,9 +1339,11 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
       for (int u = 0; u < PPT; ++u) {
         if (tid + u * HL_BLOCK >= np) continue;
         Gh[pp[u] * ls + qq[u]] = accv[u].hi;
-        Gl[pp[u] * ls + qq[u]] = accv[u].lo;
         Gh[qq[u] * ls + pp[u]] = accv[u].hi;
-        Gl[qq[u] * ls + pp[u]] = accv[u].lo;
+        if (use_dd) {
+          Gl[pp[u] * ls + qq[u]] = accv[u].lo;
+          Gl[qq[u] * ls + pp[u]] = accv[u].lo;
+        }
       }
     }
     __syncthreads();
@@ -1360,10 +1377,13 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
   }
 }
 
-__host__ __device__ inline size_t radd_fused_lds(int ks) {
-  // the Gram tile (64 x ks) lives in Z (2 ks^2 doubles): ks >= 32
+__host__ __device__ inline size_t radd_fused_lds(int ks, bool dd_parts = true) {
+  // with double-double parts the Gram tile (64 x ks) lives in Z (2 ks^2
+  // doubles): ks >= 32; without, Z is sized for the tile
   const int k = ks < 32 ? 32 : ks;
-  return radd_core_lds(k);
+  if (dd_parts) return radd_core_lds(k);
+  const size_t ls2 = (size_t)(k + 1) * (k + 1);
+  return (2 * ls2 + std::max(ls2, (size_t)RA_TS * k) + 2 * (size_t)k * RA_YS) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -1982,9 +2002,10 @@ hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, c
 }
 hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s) {
   if (ntg == 0) return hipSuccess;
-  if (ks > 48) return hipErrorInvalidValue;
+  if (ks > fused_width(tol)) return hipErrorInvalidValue;
   const int k = ks < 32 ? 32 : ks;
-  hipLaunchKernelGGL(k_radd_fused, dim3(ntg), dim3(HL_BLOCK), radd_fused_lds(ks), s, tg, terms, tol, k);
+  hipLaunchKernelGGL(k_radd_fused, dim3(ntg), dim3(HL_BLOCK), radd_fused_lds(k, radd_needs_dd(tol)), s, tg, terms,
+                     tol, k);
   return post();
 }
 hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms, hipStream_t s) {

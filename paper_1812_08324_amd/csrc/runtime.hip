@@ -557,9 +557,10 @@ struct Builder {
   }
 
   // Emit rounded additions for the given targets.  Targets of at most
-  // GRAM_CHUNK rows on both sides and at most 48 columns in all go to one
-  // fused launch; the others get one phase per width bucket (16, 32, 48, 64
-  // columns) so that the LDS of the core kernel is sized to the bucket.
+  // GRAM_CHUNK rows on both sides and at most fused_width(ftol) columns in
+  // all (48, or 64 without double-double parts) go to one fused launch; the
+  // others get one phase per width bucket (16, 32, 48, 64 columns) so that
+  // the LDS of the core kernel is sized to the bucket.
   // Returns each target's index in P.ltg.
   std::vector<int> emit_lflush(std::vector<LFlushTarget>& tgs, std::vector<std::vector<Term>>& tlists,
                                double ftol) {
@@ -567,7 +568,7 @@ struct Builder {
     std::vector<size_t> fused;
     int fks = 16;
     for (size_t q = 0; q < tgs.size(); ++q)
-      if (tgs[q].m <= GRAM_CHUNK && tgs[q].n <= GRAM_CHUNK && tgs[q].Kcap <= 48) {
+      if (tgs[q].m <= GRAM_CHUNK && tgs[q].n <= GRAM_CHUNK && tgs[q].Kcap <= fused_width(ftol)) {
         fused.push_back(q);
         fks = std::max(fks, (tgs[q].Kcap + 15) / 16 * 16);
       }
@@ -615,11 +616,14 @@ struct Builder {
   }
 
   // A low-rank target whose rounded additions all run in one fused launch:
-  // at most GRAM_CHUNK rows per side, rank capacity <= 16 and every term of
-  // rank capacity <= 32, so that each concatenation of the fused kernel stays
-  // within 48 columns (called after the dense terms became low-rank terms).
+  // at most GRAM_CHUNK rows per side and rank capacities such that each
+  // concatenation of the fused kernel (the target and one more term at
+  // least) stays within fused_width(tol): target <= 16 and terms <= 32 with
+  // double-double parts, both <= 32 without (called after the dense terms
+  // became low-rank terms).
   bool fused_target(const LeafDesc& d, const std::vector<PendingTerm>& terms) const {
-    if (d.kind != K_LR || d.m > GRAM_CHUNK || d.n > GRAM_CHUNK || d.kcap > 16) return false;
+    const int tcap = radd_dd(tol) ? 16 : 32;
+    if (d.kind != K_LR || d.m > GRAM_CHUNK || d.n > GRAM_CHUNK || d.kcap > tcap) return false;
     for (const auto& pt : terms)
       if (pt.t.dense || pt.kcap > 32) return false;
     return true;
@@ -798,7 +802,7 @@ struct Builder {
           T.m = d.m;
           T.n = d.n;
           T.kcap = d.kcap;
-          T.Kcap = 48;
+          T.Kcap = fused_width(tol);
           std::vector<Term> tl;
           for (auto& pt : kv.second) tl.push_back(pt.t);
           if (rounds.empty()) rounds.resize(1);
