@@ -147,6 +147,20 @@ def bench_batched(H, torch, sweeps, lu_tol):
     unknowns = sum(w.n for w in ws)
     step_bytes = (sweeps * mats[0] + (1 + sweeps) * (mats[1] + mats[2])) + 10 * 8.0 * unknowns
     gbps = steps * step_bytes / (t4 - t3) / 1e9
+    # the per-problem launch loop (hlevy_factor + hlevy_step one problem at a
+    # time) on every 16th problem, scaled to the batch by unknowns
+    sample = list(range(0, len(ws), 16))
+    torch.cuda.synchronize()
+    l0 = time.perf_counter()
+    for i in sample:
+        f = H.factor(ops[i], ws[i].dt, H.PREC_MIXED, lu_tol)
+        v = u0[i].clone()
+        H.step(f, v, steps, refine={"sweeps": sweeps})
+        del f
+    torch.cuda.synchronize()
+    l1 = time.perf_counter()
+    scale = unknowns / sum(ws[i].n for i in sample)
+    loop_s = (l1 - l0) * scale + (t1 - t0)   # plus the same assembly
     return {
         "workload": "tempered1d_batch512",
         "problems": len(ws), "unknowns": unknowns, "cn_steps": steps, "dt": ws[0].dt,
@@ -154,6 +168,10 @@ def bench_batched(H, torch, sweeps, lu_tol):
         "unit": "problem CN steps/s (whole job)",
         "phases_s": {"assemble": t1 - t0, "factor_batched": t2 - t1, "steps_batched": t3 - t2b},
         "steady_problem_steps_per_s": len(ws) * steps / (t4 - t3),
+        "per_problem_loop": {"value": len(ws) * steps / loop_s, "seconds": loop_s,
+                             "speedup_batched": loop_s / whole,
+                             "sample": f"hlevy_factor + hlevy_step on {len(sample)} of the problems, "
+                                       f"scaled by unknowns ({l1 - l0:.2f}s measured)"},
         "step": {"bytes": step_bytes, "ms": 1e3 * (t4 - t3) / steps, "GBps": gbps, "frac": gbps / HBM_PEAK_GBS,
                  "note": "all kernels of a batched step (projections, gathers) over its algorithmic bytes"},
     }

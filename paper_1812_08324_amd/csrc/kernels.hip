@@ -1607,12 +1607,12 @@ __global__ void __launch_bounds__(HL_BLOCK) k_getrf_inv(const GetrfItem* items, 
 // with a cyclic layout: thread (ty, tx) owns rows ty + 32 r and columns
 // tx + 32 c (r, c < 4), so the owner of column k holds it in register
 // column k / 32 -- a constant over 32 consecutive steps, which keeps every
-// register index static.  Each elimination step publishes one column and
-// one row through LDS (double buffered, one barrier per step).
-// The inverses use the right-looking forms X = L^{-1}:
-// X[i, :] -= L[i, k] X[k, :] (i > k), and Y = U'^{-1} for the unit upper
-// U' = D^{-1} U from the bottom, U^{-1} = Y D^{-1}; X is strictly lower and
-// Y strictly upper, so both share one register array and advance together.
+// register index static.  One pass of n elimination steps advances the LU
+// and both inverses together, each step publishing two columns and two rows
+// through LDS (double buffered, one barrier per step): X = L^{-1} by the
+// step's row operations applied to I, Y = U'^{-1} (U' = D^{-1} U, unit
+// upper) by its column operations applied to I, U^{-1} = Y D^{-1}; X is
+// strictly lower and Y strictly upper, so both share one register array.
 // ---------------------------------------------------------------------------
 constexpr int LI_G = 32;                  // thread grid is LI_G x LI_G
 constexpr int LI_T = LI_G * LI_G;         // 1024 threads
@@ -1651,7 +1651,15 @@ __global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t
       z[r][c] = 0.0;
     }
 
-  // LU: step k publishes column k (rows >= k) and row k (columns > k)
+  // One pass of n elimination steps.  Step k publishes column k of the
+  // active matrix (rows >= k), its row k (columns > k), row k of X = L^{-1}
+  // (columns < k) and column k of Y = U'^{-1} (rows < k), all final at step
+  // k, then every thread applies
+  //   A[i, j] -= l_ik u_kj           (i, j > k; the Schur complement)
+  //   X[i, c] -= l_ik X[k, c]         (i > k, c <= k; row operations on I)
+  //   Y[r, j] -= Y[r, k] u_kj / u_kk  (r <= k, j > k; column operations on I)
+  // with l_ik = A[i, k] / u_kk, X[k, k] = Y[k, k] = 1.  X (strictly lower)
+  // and Y (strictly upper) share the register array z.
   bool zp = false;
 #pragma unroll
   for (int cb = 0; cb < LI_R; ++cb) {
@@ -1660,106 +1668,55 @@ __global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t
       const int kk = k - LI_G * cb;
       double* col = pub + (k & 1) * 4 * LUINV_N;
       double* row = col + LUINV_N;
+      double* xr = row + LUINV_N;
+      double* yc = xr + LUINV_N;
       if (tx == kk) {
 #pragma unroll
-        for (int r = 0; r < LI_R; ++r)
-          if (ty + LI_G * r >= k) col[ty + LI_G * r] = a[r][cb];
+        for (int r = 0; r < LI_R; ++r) {
+          const int i = ty + LI_G * r;
+          if (i >= k) col[i] = a[r][cb];
+          if (i < k) yc[i] = z[r][cb];
+        }
       }
       if (ty == kk) {
 #pragma unroll
-        for (int c = 0; c < LI_R; ++c)
-          if (tx + LI_G * c > k) row[tx + LI_G * c] = a[cb][c];
+        for (int c = 0; c < LI_R; ++c) {
+          const int j = tx + LI_G * c;
+          if (j > k) row[j] = a[cb][c];
+          if (j < k) xr[j] = z[cb][c];
+        }
       }
       __syncthreads();
       const double piv = col[k];
       zp = zp || piv == 0.0;
       const double rinv = 1.0 / piv;
       if (tid == 0) dinv[k] = rinv;
-      double l[LI_R], u[LI_R];
-#pragma unroll
-      for (int r = 0; r < LI_R; ++r) {
-        const double cv = col[ty + LI_G * r];
-        l[r] = ty + LI_G * r > k ? cv * rinv : 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < LI_R; ++c) {
-        const double rv = row[tx + LI_G * c];
-        u[c] = tx + LI_G * c > k ? rv : 0.0;
-      }
-#pragma unroll
-      for (int r = 0; r < LI_R; ++r)
-#pragma unroll
-        for (int c = 0; c < LI_R; ++c) a[r][c] -= l[r] * u[c];
-      if (tx == kk) {
-        // the multipliers replace column k below the diagonal
-#pragma unroll
-        for (int r = 0; r < LI_R; ++r)
-          if (ty + LI_G * r > k) a[r][cb] = l[r];
-      }
-    }
-  }
-  if (tid >= n && tid < LUINV_N) dinv[tid] = 1.0;   // identity padding
-  __syncthreads();
-
-  // inverses on the padded block: step s advances X (k = s) and Y
-  // (k2 = LUINV_N - 1 - s); beyond n both steps are no-ops
-#pragma unroll
-  for (int cb = 0; cb < LI_R; ++cb) {
-    const int cb2 = LI_R - 1 - cb;
-    for (int kk = 0; kk < LI_G; ++kk) {
-      const int k = LI_G * cb + kk, kk2 = LI_G - 1 - kk, k2 = LI_G * cb2 + kk2;
-      double* lc = pub + (k & 1) * 4 * LUINV_N;
-      double* xr = lc + LUINV_N;
-      double* uc = xr + LUINV_N;
-      double* yr = uc + LUINV_N;
-      if (tx == kk) {
-#pragma unroll
-        for (int r = 0; r < LI_R; ++r)
-          if (ty + LI_G * r > k) lc[ty + LI_G * r] = a[r][cb];
-      }
-      if (ty == kk) {
-#pragma unroll
-        for (int c = 0; c < LI_R; ++c) {
-          const int j = tx + LI_G * c;
-          if (j <= k) xr[j] = j == k ? 1.0 : z[cb][c];
-        }
-      }
-      if (tx == kk2) {
-#pragma unroll
-        for (int r = 0; r < LI_R; ++r) {
-          const int i = ty + LI_G * r;
-          if (i < k2) uc[i] = a[r][cb2] * dinv[i];
-        }
-      }
-      if (ty == kk2) {
-#pragma unroll
-        for (int c = 0; c < LI_R; ++c) {
-          const int j = tx + LI_G * c;
-          if (j >= k2) yr[j] = j == k2 ? 1.0 : z[cb2][c];
-        }
-      }
-      __syncthreads();
-      double li[LI_R], ui[LI_R], xj[LI_R], yj[LI_R];
+      double l[LI_R], yk[LI_R], u[LI_R], ub[LI_R], xk[LI_R];
 #pragma unroll
       for (int r = 0; r < LI_R; ++r) {
         const int i = ty + LI_G * r;
-        const double lv = lc[i], uv = uc[i];
-        li[r] = i > k ? lv : 0.0;
-        ui[r] = i < k2 ? uv : 0.0;
+        const double cv = col[i], yv = yc[i];
+        l[r] = i > k ? cv * rinv : 0.0;
+        yk[r] = i < k ? yv : (i == k ? 1.0 : 0.0);
       }
 #pragma unroll
       for (int c = 0; c < LI_R; ++c) {
         const int j = tx + LI_G * c;
-        const double xv = xr[j], yv = yr[j];
-        xj[c] = j <= k ? xv : 0.0;
-        yj[c] = j >= k2 ? yv : 0.0;
+        const double rv = row[j], xv = xr[j];
+        u[c] = j > k ? rv : 0.0;
+        ub[c] = u[c] * rinv;
+        xk[c] = j < k ? xv : (j == k ? 1.0 : 0.0);
       }
 #pragma unroll
       for (int r = 0; r < LI_R; ++r)
 #pragma unroll
-        for (int c = 0; c < LI_R; ++c) z[r][c] -= li[r] * xj[c] + ui[r] * yj[c];
+        for (int c = 0; c < LI_R; ++c) {
+          a[r][c] -= l[r] * u[c];
+          z[r][c] -= l[r] * xk[c] + yk[r] * ub[c];
+        }
     }
   }
+  if (tid >= n && tid < LUINV_N) dinv[tid] = 1.0;   // identity padding
   __syncthreads();
 
   // L^{-1}: strictly lower part of z, unit diagonal
