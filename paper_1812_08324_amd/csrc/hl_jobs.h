@@ -71,6 +71,9 @@ struct DProdItem {
 //   dense = 0: sign * U W^T, U mr x k (ld ldu), W nc x k (ld ldw), k = *k or kfix
 //   dense = 1: sign * P, P mr x nc (U, ld ldu)
 //   dense = 2: sign * A B, A mr x kfix (U, ld ldu), B kfix x nc (W, ld ldw)
+// klim > 0 (dense = 0): the term is columns [kofs, kofs + klim) of a wider
+// low-rank term (U and W already point at column kofs): its rank is
+// clamp(k - kofs, 0, klim).
 struct Term {
   int32_t dense;
   int32_t ro, mr, co, nc;
@@ -79,6 +82,7 @@ struct Term {
   const double* W;
   const int32_t* k;   // rank (device) or nullptr => kfix
   double sign;
+  int32_t kofs, klim;
 };
 
 // Dense target: D (m x n, ld ldd) += sum of terms [tbeg, tbeg + tcount).

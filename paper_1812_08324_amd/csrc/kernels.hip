@@ -407,6 +407,12 @@ __global__ void __launch_bounds__(HL_BLOCK) k_aca(ProblemDev P, const int32_t* p
 // ---------------------------------------------------------------------------
 constexpr int RA_YS = 32;   // row stride of Y_U / Y_V (>= every rank capacity)
 
+// columns of a low-rank term (its rank, or its share of a split term)
+__device__ __forceinline__ int term_rank(const Term& tm) {
+  const int k = tm.k ? *tm.k : tm.kfix;
+  return tm.klim > 0 ? min(max(k - tm.kofs, 0), tm.klim) : k;
+}
+
 struct ColMap {
   int K, kC, nt, tb;   // tb: first term of this concatenation (relative to T.tbeg)
   int off[KMAX + 1];
@@ -420,7 +426,7 @@ __device__ void build_colmap(const LFlushTarget& T, const Term* terms, int kC, C
   int K = kC;
   for (int t = 0; t < T.tcount; ++t) {
     const Term& tm = terms[T.tbeg + t];
-    int kt = tm.k ? *tm.k : tm.kfix;
+    int kt = term_rank(tm);
     cm.off[t] = K;
     cm.kt[t] = kt;
     K += kt;
@@ -439,7 +445,7 @@ __device__ void build_colmap_chunk(const LFlushTarget& T, const Term* terms, int
   int K = kC, t = 0;
   while (t0 + t < T.tcount && t < KMAX) {
     const Term& tm = terms[T.tbeg + t0 + t];
-    const int kt = tm.k ? *tm.k : tm.kfix;
+    const int kt = term_rank(tm);
     if (t > 0 && K + kt > limit) break;
     cm.off[t] = K;
     cm.kt[t] = kt;
@@ -1399,7 +1405,7 @@ constexpr int DF_KC = 32;
 constexpr int DF_NE = 2 * 64 * DF_KC / HL_BLOCK;   // staged values per thread and slice
 
 __device__ __forceinline__ int term_inner(const Term& tm) {
-  return tm.dense == 2 ? tm.kfix : (tm.k ? *tm.k : tm.kfix);
+  return tm.dense == 2 ? tm.kfix : term_rank(tm);
 }
 
 // slice [q0, q0 + DF_KC) of the inner dimension: element e < 64 * DF_KC is

@@ -809,8 +809,32 @@ struct Builder {
           rounds[0].push_back({T, tl});
           continue;
         }
+        // with double-double parts the fast core takes 48 columns: terms
+        // wider than 48 - kcap are split into column pieces that fit
+        std::vector<PendingTerm> split;
+        const std::vector<PendingTerm>* tl_src = &kv.second;
+        if (radd_dd(tol) && d.kcap <= 32) {
+          const int w = 48 - d.kcap;
+          for (const PendingTerm& pt : kv.second) {
+            if (pt.kcap <= w || pt.t.dense != 0 || pt.t.klim > 0) {
+              split.push_back(pt);
+              continue;
+            }
+            for (int c0 = 0; c0 < pt.kcap; c0 += w) {
+              PendingTerm sp = pt;
+              sp.t.U = pt.t.U + (size_t)pt.t.ldu * c0;
+              sp.t.W = pt.t.W + (size_t)pt.t.ldw * c0;
+              sp.t.kofs = c0;
+              sp.t.klim = std::min(w, pt.kcap - c0);
+              sp.kcap = sp.t.klim;
+              split.push_back(sp);
+            }
+          }
+          tl_src = &split;
+        }
+        const std::vector<PendingTerm>& tsrc = *tl_src;
         size_t q = 0, rd = 0;
-        while (q < kv.second.size()) {
+        while (q < tsrc.size()) {
           LFlushTarget T{};
           T.U = d.A;
           T.V = d.B;
@@ -820,11 +844,12 @@ struct Builder {
           T.kcap = d.kcap;
           int K = d.kcap;
           // concatenations of at most 48 columns use the faster core kernel
-          const int lim = (d.kcap <= 16) ? 48 : KMAX;
+          // (without double-double parts it takes KMAX)
+          const int lim = radd_dd(tol) ? 48 : KMAX;
           std::vector<Term> tl;
-          while (q < kv.second.size() && (K + kv.second[q].kcap <= lim || tl.empty())) {
-            K += kv.second[q].kcap;
-            tl.push_back(kv.second[q].t);
+          while (q < tsrc.size() && (K + tsrc[q].kcap <= lim || tl.empty())) {
+            K += tsrc[q].kcap;
+            tl.push_back(tsrc[q].t);
             ++q;
           }
           if (K > KMAX) throw DeviceError("internal: term wider than a rounded addition");
