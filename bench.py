@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison job")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-worklist measurement")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival window of the serving measurement (0 = skip)")
     ap.add_argument("--serve-frac-1d", type=float, default=1.0,
@@ -175,6 +176,52 @@ def bench_batched(H, torch, sweeps, lu_tol):
         "step": {"bytes": step_bytes, "ms": 1e3 * (t4 - t3) / steps, "GBps": gbps, "frac": gbps / HBM_PEAK_GBS,
                  "note": "all kernels of a batched step (projections, gathers) over its algorithmic bytes"},
     }
+
+
+def bench_2d(H, torch, sweeps, lu_tol_mixed):
+    """The 2D fractional-Laplacian workload: unit square, 256 x 256 grid
+    (N = 65536), s = 0.75, ACA rank <= 32 at 1e-8, dt = 1e-3, 200 CN steps,
+    seeded 8-Gaussian u0; mixed precision (FP32 inverse factors at 1e-6, FP64
+    refinement) against the FP64 factors (lu_tol 1e-10)."""
+    import workloads as W
+    w = W.config3(s=0.75, n=256)
+    prob = H.make_problem(2, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
+    hp = H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol, max_rank=w.max_rank)
+    u0 = torch.tensor(w.u0, dtype=torch.float64, device="cuda")
+    out = {"workload": "frac2d_s0.75_256x256", "N": w.N, "cn_steps": w.steps, "dt": w.dt}
+    res = {}
+    for name, prec, tol, sw in (("mixed", H.PREC_MIXED, lu_tol_mixed, sweeps), ("fp64", H.PREC_FP64, w.lu_tol, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = H.assemble(prob, hp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fac = H.factor(op, w.dt, prec, tol)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        u = u0.clone()
+        H.step(fac, u, w.steps, refine={"sweeps": sw})
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        res[name] = u
+        out[name] = {"cn_steps_per_s": w.steps / (t3 - t0), "lu_tol": tol, "sweeps": sw,
+                     "phases_s": {"assemble": t1 - t0, "factor": t2 - t1, "steps": t3 - t2},
+                     "steady_cn_steps_per_s": w.steps / (t3 - t2)}
+        if name == "mixed":
+            kt = H.fac_kernel_times(fac, reps=5)
+            g = kt["G"]
+            gb = g["dense_bytes"] + g["u_bytes"] + 16.0 * w.N
+            mvb = g["dense_bytes"] + g["u_bytes"] + g["v_bytes"] + 24.0 * w.N
+            out["gather_G"] = {"bytes": gb, "ms": g["gather_ms"], "GBps": gb / (g["gather_ms"] * 1e-3) / 1e9,
+                               "frac": gb / (g["gather_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            mvms = g["project_ms"] + g["gather_ms"]
+            out["matvec_G"] = {"bytes": mvb, "ms": mvms, "GBps": mvb / (mvms * 1e-3) / 1e9,
+                               "frac": mvb / (mvms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del fac, op
+        progress(f"2D {name} job done")
+    out["rel_l2_mixed_vs_fp64"] = float(torch.linalg.norm(res["mixed"] - res["fp64"]) / torch.linalg.norm(res["fp64"]))
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["cn_steps_per_s"] / out["fp64"]["cn_steps_per_s"]
+    return out
 
 
 def progress(msg):
@@ -352,6 +399,8 @@ def main():
     if not args.no_batched:
         line["batched"] = bench_batched(H, torch, args.sweeps, args.lu_tol_mixed)
         progress("batched workload done")
+    if not args.no_2d:
+        line["frac2d"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed)
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.sweeps,
                                         args.lu_tol_mixed)

@@ -143,3 +143,61 @@ def test_tempered_trajectory_vs_oracle_n4096(H):
     emx = np.linalg.norm(host(u) - ref) / nref
     assert e64 <= 1e-10, e64
     assert emx <= 1e-8, emx
+
+
+@pytest.fixture(scope="module")
+def full2d(H):
+    """The 2D workload at full size: 256 x 256 grid, s = 0.75, ACA rank <= 32
+    at 1e-8; FP64 factors (lu_tol 1e-10) and mixed factors (1e-6)."""
+    w = W.config3(s=0.75, n=256)
+    p, hp = lib(H, w, max_rank=w.max_rank)
+    op = H.assemble(p, hp)
+    f64 = H.factor(op, w.dt, H.PREC_FP64, w.lu_tol)
+    fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    return w, op, f64, fmx
+
+
+def test_2d_operator_rows_at_full_size(H, full2d):
+    """y = G x on the 256 x 256 grid against oracle rows (sampled: corners,
+    edges, centre and seeded interior points), each within 10 aca_tol
+    |g_i| |x|."""
+    w, op, _, _ = full2d
+    rng = np.random.Generator(np.random.PCG64(256))
+    x = rng.standard_normal(w.N)
+    y = torch.empty(w.N, dtype=torch.float64, device="cuda")
+    H.matvec(op, dev(x), y)
+    y = host(y)
+    p = oracle_problem(w)
+    consts = quadrature_constants(p)
+    n = w.n
+    rows = np.unique(np.concatenate([[0, n - 1, n * (n - 1), w.N - 1, n // 2, n * (n // 2) + n // 2,
+                                      n * 17 + 1], rng.integers(0, w.N, 25)]))
+    nx = np.linalg.norm(x)
+    for i in rows:
+        g = generator_row(p, int(i), consts)
+        ref = float(g @ x)
+        assert abs(y[i] - ref) <= 10 * w.aca_tol * np.linalg.norm(g) * nx, (int(i), y[i], ref)
+
+
+def test_2d_solve_residuals_at_full_size(H, full2d):
+    """M x = b on the 256 x 256 grid: FP64 factors (one default sweep) and
+    mixed factors (one sweep) both below 1e-10 relative residual."""
+    w, op, f64, fmx = full2d
+    b = dev(np.random.Generator(np.random.PCG64(9)).standard_normal(w.N))
+    x = torch.empty_like(b)
+    H.solve(f64, b, x)
+    assert residual(H, w, op, x, b) < 1e-10
+    H.solve(fmx, b, x, refine={"sweeps": 1})
+    assert residual(H, w, op, x, b) < 1e-10
+
+
+def test_2d_mixed_trajectory_at_full_size(H, full2d):
+    """200 CN steps on the 256 x 256 grid: the mixed path (one sweep) within
+    1e-8 of the FP64 path."""
+    w, op, f64, fmx = full2d
+    ua = dev(w.u0)
+    ub = dev(w.u0)
+    H.step(f64, ua, w.steps)
+    H.step(fmx, ub, w.steps, refine={"sweeps": 1})
+    err = float(torch.linalg.norm(ua - ub) / torch.linalg.norm(ua))
+    assert err <= 1e-8, err
