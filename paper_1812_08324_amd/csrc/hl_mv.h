@@ -10,14 +10,18 @@ namespace hl {
 constexpr int MV_PMAX = 16;   // at most this many projection tiles (partials) per low-rank leaf
 constexpr int MV_EMAX = 128;  // entries staged in LDS per gather round
 
-// One wavefront of the projection: rows [r0, r0 + n) of the V factor of a
-// low-rank leaf, V column-major with leading dimension ld and rank k.  The
-// wavefront writes the k partial sums sum_j V[j, p] x[xoff + j] to slot
-// `slot` of the partial buffer (stride kb doubles per slot).
+// One wavefront of the projection: rows [r0, r0 + n) and columns
+// [col0, col0 + k) of the V factor of a low-rank leaf (V column-major with
+// leading dimension ld; the pointer is at row r0 of column col0).  The
+// wavefront writes the k partial sums sum_j V[j, col0 + p] x[xoff + j] to
+// slot `slot` of the partial buffer (stride kb doubles per slot), at
+// columns col0 .. col0 + k - 1.  Rank bucket 32 takes two 16-column tiles
+// per row range.
 struct MvTile {
   int32_t n, k, ld, xoff;
   int32_t slot, f32;   // f32: V stored in FP32 (else FP64)
-  const void* V;       // first row of the tile
+  int32_t col0, pad;
+  const void* V;       // row r0, column col0
 };
 
 // A leaf seen from one leaf cluster rho.  Dense: block rows of rho (ptr at

@@ -83,7 +83,7 @@ constexpr int rows_per_lane() {
 
 // one projection tile (V in precision TL): the k partial sums of the
 // wavefront's rows, written to the tile's slot
-template <typename TL, int KB>
+template <typename TL, int KB, int SB = KB>
 __device__ __forceinline__ void project_tile(const MvTile& T, const double* __restrict__ x, double* __restrict__ part,
                                              int lane) {
   constexpr int RPL = rows_per_lane<TL, KB>();
@@ -117,25 +117,27 @@ __device__ __forceinline__ void project_tile(const MvTile& T, const double* __re
   ColReduce<KB, 32>::run(acc, lane);
   constexpr int G = 64 / KB;
   const int col = lane / G;
-  if (lane % G == 0 && col < T.k) part[(size_t)T.slot * KB + col] = acc[0];
+  if (lane % G == 0 && col < T.k) part[(size_t)T.slot * SB + T.col0 + col] = acc[0];
 }
 
-template <int KB>
+template <int KB, int SB = KB>
 __device__ __forceinline__ void project_any(const MvTile& T, const double* __restrict__ x,
                                             double* __restrict__ part, int lane) {
   if (wuni(T.f32))
-    project_tile<float, KB>(T, x, part, lane);
+    project_tile<float, KB, SB>(T, x, part, lane);
   else
-    project_tile<double, KB>(T, x, part, lane);
+    project_tile<double, KB, SB>(T, x, part, lane);
 }
 
-template <int KB>
+// KB: columns per wavefront (registers); SB: partial slot stride (the
+// plan's rank bucket)
+template <int KB, int SB>
 __global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ tiles, int ntiles,
                                                     const double* __restrict__ x, double* __restrict__ part) {
   const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (wid >= ntiles) return;   // the whole wavefront leaves; no block barrier below
   const MvTile T = tiles[wid];
-  project_any<KB>(T, x, part, threadIdx.x & 63);
+  project_any<KB, SB>(T, x, part, threadIdx.x & 63);
 }
 
 constexpr int MV_GW = 8;   // wavefronts per gather workgroup
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
 
 int project_rows_per_pass(int kb, bool f32) {
   const int vals = f32 ? 64 : 32;
-  return 64 * (vals / kb);
+  return 64 * (vals / (kb < 16 ? kb : 16));   // rank bucket 32 runs 16-column tiles
 }
 
 // Launches; with events, the events are attached to the dispatch itself
@@ -278,11 +280,13 @@ int project_rows_per_pass(int kb, bool f32) {
 template <int KB>
 static void project_t(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (M.ntiles <= 0) return;
+  // rank bucket 32: 16-column tiles (two per row range) into 32-wide slots
+  constexpr int PK = KB < 16 ? KB : 16;
   const dim3 grid((M.ntiles + 3) / 4);
   if (e0)
-    hipExtLaunchKernelGGL((k_mv_project<KB>), grid, dim3(256), 0, s, e0, e1, 0, M.tiles, M.ntiles, x, M.part);
+    hipExtLaunchKernelGGL((k_mv_project<PK, KB>), grid, dim3(256), 0, s, e0, e1, 0, M.tiles, M.ntiles, x, M.part);
   else
-    hipLaunchKernelGGL((k_mv_project<KB>), grid, dim3(256), 0, s, M.tiles, M.ntiles, x, M.part);
+    hipLaunchKernelGGL((k_mv_project<PK, KB>), grid, dim3(256), 0, s, M.tiles, M.ntiles, x, M.part);
 }
 
 template <typename TD, int KB>
@@ -351,7 +355,7 @@ __device__ __forceinline__ unsigned member_mask(const MvInst& P, int step) {
 }
 
 // projection tile for the members in `mask`: k partial sums per member
-template <typename TL, int KB, int R>
+template <typename TL, int KB, int R, int SB>
 __device__ __forceinline__ void project_tile_r(const MvTile& T, const MvInst& P, unsigned mask, int lane) {
   constexpr int RPL = rows_per_lane<TL, KB>();
   const gptr<TL> V = wuni_ptr<TL>(T.V);
@@ -396,11 +400,11 @@ __device__ __forceinline__ void project_tile_r(const MvTile& T, const MvInst& P,
   for (int r = 0; r < R; ++r) {
     if (!(mask >> r & 1u)) continue;
     ColReduce<KB, 32>::run(acc[r], lane);
-    if (lane % G == 0 && col < T.k) P.part[r][(size_t)T.slot * KB + col] = acc[r][0];
+    if (lane % G == 0 && col < T.k) P.part[r][(size_t)T.slot * SB + T.col0 + col] = acc[r][0];
   }
 }
 
-template <int KB, int R>
+template <int KB, int R, int SB>
 __global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__ inst,
                                                       const MvRef* __restrict__ map, int nw, int step) {
   const int wid = wuni(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -411,9 +415,9 @@ __global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__
   const unsigned mask = member_mask(P, step);
   if (mask == 0) return;
   if (wuni(T.f32))
-    project_tile_r<float, KB, R>(T, P, mask, threadIdx.x & 63);
+    project_tile_r<float, KB, R, SB>(T, P, mask, threadIdx.x & 63);
   else
-    project_tile_r<double, KB, R>(T, P, mask, threadIdx.x & 63);
+    project_tile_r<double, KB, R, SB>(T, P, mask, threadIdx.x & 63);
 }
 
 // Batches mostly hold small problems with a few entries per leaf cluster,
@@ -535,8 +539,10 @@ __global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __res
 template <int KB, int R>
 static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
                     int step, hipStream_t s) {
+  // rank bucket 32: 16-column tiles (two per row range) into 32-wide slots
+  constexpr int PK = KB < 16 ? KB : 16;
   if (nw > 0)
-    hipLaunchKernelGGL((k_mv_project_b<KB, R>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
+    hipLaunchKernelGGL((k_mv_project_b<PK, R, KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
   if (nr > 0) {
     if (dense_f32)
       hipLaunchKernelGGL((k_mv_gather_b<float, KB, R>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);

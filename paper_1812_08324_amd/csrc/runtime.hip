@@ -1121,16 +1121,20 @@ struct MvPlan {
       np[l] = P;
       for (int t = 0; t < P; ++t) {
         const int r0 = t * per * rpp, r1 = std::min(d.n, r0 + per * rpp);
-        MvTile T{};
-        T.n = r1 - r0;
-        T.k = k;
-        T.ld = d.n;
-        T.xoff = d.clo + r0;
-        T.slot = (int32_t)(nslots + t);
-        T.f32 = f32 ? 1 : 0;
-        const double* p = d.B + r0;
-        T.V = f32 ? fptr(p) : (const void*)p;
-        tiles.push_back(T);
+        // rank bucket 32: one tile per 16 columns
+        for (int c0 = 0; c0 < k; c0 += (kb > 16 ? 16 : kb)) {
+          MvTile T{};
+          T.n = r1 - r0;
+          T.k = std::min(k - c0, kb > 16 ? 16 : kb);
+          T.ld = d.n;
+          T.xoff = d.clo + r0;
+          T.slot = (int32_t)(nslots + t);
+          T.f32 = f32 ? 1 : 0;
+          T.col0 = c0;
+          const double* p = d.B + r0 + (size_t)d.n * c0;
+          T.V = f32 ? fptr(p) : (const void*)p;
+          tiles.push_back(T);
+        }
       }
       nslots += P;
     }
