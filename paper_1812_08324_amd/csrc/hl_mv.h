@@ -15,8 +15,11 @@ constexpr int MV_EMAX = 128;  // entries staged in LDS per gather round
 // leading dimension ld; the pointer is at row r0 of column col0).  The
 // wavefront writes the k partial sums sum_j V[j, col0 + p] x[xoff + j] to
 // slot `slot` of the partial buffer (stride kb doubles per slot), at
-// columns col0 .. col0 + k - 1.  Rank bucket 32 takes two 16-column tiles
-// per row range.
+// columns col0 .. col0 + k - 1.  A tile is project_width(kb) columns wide:
+// a row range of a leaf of rank k takes ceil(k / width) tiles.
+// columns of one projection tile for a plan of rank bucket kb
+constexpr int project_width(int kb) { return kb <= 8 ? kb : (kb == 16 ? 8 : 16); }
+
 struct MvTile {
   int32_t n, k, ld, xoff;
   int32_t slot, f32;   // f32: V stored in FP32 (else FP64)

@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
 
 int project_rows_per_pass(int kb, bool f32) {
   const int vals = f32 ? 64 : 32;
-  return 64 * (vals / (kb < 16 ? kb : 16));   // rank bucket 32 runs 16-column tiles
+  return 64 * (vals / project_width(kb));
 }
 
 // Launches; with events, the events are attached to the dispatch itself
@@ -280,8 +280,8 @@ int project_rows_per_pass(int kb, bool f32) {
 template <int KB>
 static void project_t(const MvDev& M, const double* x, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (M.ntiles <= 0) return;
-  // rank bucket 32: 16-column tiles (two per row range) into 32-wide slots
-  constexpr int PK = KB < 16 ? KB : 16;
+  // tiles of project_width(KB) columns into KB-wide partial slots
+  constexpr int PK = project_width(KB);
   const dim3 grid((M.ntiles + 3) / 4);
   if (e0)
     hipExtLaunchKernelGGL((k_mv_project<PK, KB>), grid, dim3(256), 0, s, e0, e1, 0, M.tiles, M.ntiles, x, M.part);
@@ -539,8 +539,8 @@ __global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __res
 template <int KB, int R>
 static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
                     int step, hipStream_t s) {
-  // rank bucket 32: 16-column tiles (two per row range) into 32-wide slots
-  constexpr int PK = KB < 16 ? KB : 16;
+  // tiles of project_width(KB) columns into KB-wide partial slots
+  constexpr int PK = project_width(KB);
   if (nw > 0)
     hipLaunchKernelGGL((k_mv_project_b<PK, R, KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
   if (nr > 0) {

@@ -1121,11 +1121,12 @@ struct MvPlan {
       np[l] = P;
       for (int t = 0; t < P; ++t) {
         const int r0 = t * per * rpp, r1 = std::min(d.n, r0 + per * rpp);
-        // rank bucket 32: one tile per 16 columns
-        for (int c0 = 0; c0 < k; c0 += (kb > 16 ? 16 : kb)) {
+        // one tile per project_width(kb) columns
+        const int tw = project_width(kb);
+        for (int c0 = 0; c0 < k; c0 += tw) {
           MvTile T{};
           T.n = r1 - r0;
-          T.k = std::min(k - c0, kb > 16 ? 16 : kb);
+          T.k = std::min(k - c0, tw);
           T.ld = d.n;
           T.xoff = d.clo + r0;
           T.slot = (int32_t)(nslots + t);
