@@ -419,42 +419,42 @@ struct ColMap {
   int kt[KMAX];
 };
 
-__device__ void build_colmap(const LFlushTarget& T, const Term* terms, int kC, ColMap& cm) {
-  cm.kC = kC;
-  cm.nt = T.tcount;
-  cm.tb = 0;
-  int K = kC;
-  for (int t = 0; t < T.tcount; ++t) {
-    const Term& tm = terms[T.tbeg + t];
-    int kt = term_rank(tm);
-    cm.off[t] = K;
-    cm.kt[t] = kt;
-    K += kt;
+// The next concatenation of a target's term list: the target's kC columns
+// and terms [t0, t0 + nt), nt as large as the width limit allows (at least
+// one term, at most 64).  Run by the 64 lanes of the first wavefront: each
+// lane reads one term's rank, a shuffle prefix sum gives the column
+// offsets, and the terms that fit form a run from lane 0.
+__device__ void build_colmap_chunk(const LFlushTarget& T, const Term* terms, int kC, int t0, int limit, ColMap& cm) {
+  const int lane = threadIdx.x & 63;
+  const int avail = min(64, T.tcount - t0);
+  const int kt = lane < avail ? term_rank(terms[T.tbeg + t0 + lane]) : 0;
+  int incl = kt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
   }
-  cm.off[T.tcount] = K;
-  cm.K = K;
+  const bool take = lane < avail && (lane == 0 || kC + incl <= limit);
+  const int nt = __popcll(__ballot(take));
+  if (take) {
+    cm.off[lane] = kC + incl - kt;
+    cm.kt[lane] = kt;
+  }
+  if (lane == nt - 1) {
+    cm.off[nt] = kC + incl;
+    cm.K = kC + incl;
+  }
+  if (lane == 0) {
+    cm.kC = kC;
+    cm.tb = t0;
+    cm.nt = nt;
+  }
 }
 
-// The next concatenation of a long term list: the target's kC columns and
-// terms [t0, t1) with t1 as large as the width limit allows (at least one
-// term; every term is at most 32 columns wide and kC <= 16 in the fused
-// kernel, so limit 48 always admits one).
-__device__ void build_colmap_chunk(const LFlushTarget& T, const Term* terms, int kC, int t0, int limit, ColMap& cm) {
-  cm.kC = kC;
-  cm.tb = t0;
-  int K = kC, t = 0;
-  while (t0 + t < T.tcount && t < KMAX) {
-    const Term& tm = terms[T.tbeg + t0 + t];
-    const int kt = term_rank(tm);
-    if (t > 0 && K + kt > limit) break;
-    cm.off[t] = K;
-    cm.kt[t] = kt;
-    K += kt;
-    ++t;
-  }
-  cm.nt = t;
-  cm.off[t] = K;
-  cm.K = K;
+// the whole term list of one rounded addition (at most 64 terms: every
+// term has at least one column and a concatenation at most KMAX)
+__device__ void build_colmap(const LFlushTarget& T, const Term* terms, int kC, ColMap& cm) {
+  build_colmap_chunk(T, terms, kC, 0, 1 << 30, cm);
 }
 
 // value of column j of the concatenated factor on side 0 (U side) or 1 (V side)
@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg,
   __shared__ double tile[65 * KMAX];   // column stride 65: no LDS bank conflicts across columns
   const ChunkItem it = items[blockIdx.x];
   const LFlushTarget T = tg[it.tgt];
-  if (threadIdx.x == 0) build_colmap(T, terms, T.rank ? *T.rank : 0, cm);
+  if (threadIdx.x < 64) build_colmap(T, terms, T.rank ? *T.rank : 0, cm);
   __syncthreads();
   const int K = cm.K;
   const int np = npairs(K);
@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
   const LFlushTarget T = tg[blockIdx.x];
   const int tid = threadIdx.x;
   const int kC = T.rank ? *T.rank : 0;
-  if (tid == 0) build_colmap(T, terms, kC, cm);
+  if (tid < 64) build_colmap(T, terms, kC, cm);
   __syncthreads();
   const int K = cm.K;
   const int Kc = T.Kcap;
@@ -1084,7 +1084,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
   const LFlushTarget T = tg[blockIdx.x];
   const int tid = threadIdx.x;
   const int kC = T.rank ? *T.rank : 0;
-  if (tid == 0) build_colmap(T, terms, kC, cm);
+  if (tid < 64) build_colmap(T, terms, kC, cm);
   __syncthreads();
   const int K = cm.K;
   const int Kc = T.Kcap;
@@ -1161,7 +1161,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_expand(const LFlushTarget* t
   const ChunkItem it = items[blockIdx.x];
   const LFlushTarget T = tg[it.tgt];
   const int kC = T.info[0], r = T.info[1];
-  if (threadIdx.x == 0) build_colmap(T, terms, kC, cm);
+  if (threadIdx.x < 64) build_colmap(T, terms, kC, cm);
   __syncthreads();
   const int K = cm.K, Kc = T.Kcap;
   const int np = npairs(Kc);
@@ -1278,7 +1278,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
   // rounded addition into the target
   for (int t0 = 0; t0 < T.tcount;) {
     __syncthreads();
-    if (tid == 0) build_colmap_chunk(T, terms, r, t0, ks, cm);
+    if (tid < 64) build_colmap_chunk(T, terms, r, t0, ks, cm);
     __syncthreads();
     const int K = cm.K, kC = r;
     if (K > ks) {

@@ -599,6 +599,7 @@ struct Builder {
         LFlushTarget T = tgs[q];
         T.tbeg = (int)P.terms.size();
         T.tcount = (int)tlists[q].size();
+        if (T.tcount > 64) throw DeviceError("internal: more than 64 terms in one rounded addition");
         for (auto& tm : tlists[q]) P.terms.push_back(tm);
         int tix = (int)P.ltg.size();
         add_chunks(P, tix - ph.b0, T.m, T.n, T, 0);
