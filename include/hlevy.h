@@ -137,6 +137,15 @@ hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp,
 hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp,
                             void* stream, hlevy_op** out);
 
+/* Batched worklist: assemble `count` problems (probs[i] with hps[i]) as
+ * hlevy_assemble does, with the quadrature, near-field and ACA kernels of
+ * all problems enqueued back to back and the truncation of every ACA block
+ * in one plan (problems of equal aca_tol share its launches); each out[i]
+ * is the same operator hlevy_assemble gives.  On error every out[i] is NULL
+ * and nothing is leaked.  Synchronises `stream`. */
+hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hparams* hps, int32_t count,
+                                    void* stream, hlevy_op** out);
+
 /* Copy the four quadrature constants S0, S2, C2, T (Sec. 4) to host `out`.
  * Synchronises `stream`. */
 hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream);

@@ -1662,108 +1662,159 @@ hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp,
 
 hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, void* stream, hlevy_op** out) {
   if (!prob || !hp || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (!(prob->r0 < prob->hi - prob->lo)) return fail(HLEVY_ERR_INVALID_ARG, "r0 must be smaller than the domain");
-  return guarded([&]() -> hlevy_status {
-    auto op = std::make_unique<hlevy_op>();
-    std::string e = build_structure(*prob, *hp, op->S);
-    if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
-    const Structure& S = op->S;
-    for (auto& l : S.lf)
-      if (l.kind == K_LR && std::max(l.m, l.n) > 16384)
-        return fail(HLEVY_ERR_INVALID_ARG, "low-rank blocks are limited to 16384 rows (raise n_block)");
+  return hlevy_assemble_batched(prob, hp, 1, stream, out);
+}
+
+hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hparams* hps, int32_t count,
+                                    void* stream, hlevy_op** out) {
+  if (!probs || !hps || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (count < 1) return fail(HLEVY_ERR_INVALID_ARG, "count must be >= 1");
+  for (int32_t i = 0; i < count; ++i) out[i] = nullptr;
+  std::vector<std::unique_ptr<hlevy_op>> ops(count);
+  hlevy_status st = guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
     HL_CHECK(init_kernel_attributes());
-    op->prob = *prob;
-    op->hp = *hp;
-    ProblemDev& pd = op->pd;
-    pd.dim = prob->dim;
-    pd.n = prob->n;
-    pd.N = S.N;
-    pd.h = S.h;
-    pd.a = prob->a;
-    pd.b0 = prob->b[0];
-    pd.b1 = prob->dim == 2 ? prob->b[1] : 0.0;
-    pd.c = prob->c;
-    pd.s = prob->s;
-    pd.lam = prob->lambda;
-    pd.C = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, prob->s);
-    pd.r0 = prob->r0;
-    op->ds.create(S, s);
-    op->cst.alloc(4 * sizeof(double));
-    op->ovf.alloc(sizeof(int32_t));
-    HL_CHECK(hipMemsetAsync(op->ovf.p, 0, sizeof(int32_t), s));
-    HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
-    op->G.create(S, hp->max_rank, FULL, s);
-    // dense near field
-    std::vector<int32_t> dense_ids, lr_ids;
-    for (size_t l = 0; l < S.lf.size(); ++l) (S.lf[l].kind == K_DENSE ? dense_ids : lr_ids).push_back((int)l);
-    DevBuf dids, lids;
-    upload(dids, dense_ids, s);
-    upload(lids, lr_ids, s);
-    HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
-                               dids.as<int32_t>(), (int)dense_ids.size(), s));
-    // far field: ACA into scratch, then rounded addition into G
+    // 1. trees on the host; constants, near field and ACA of every problem
+    //    enqueued back to back
+    struct Aca {
+      std::vector<int32_t> lr_ids;
+      std::vector<int64_t> uo, vo;
+      DevBuf buf, rank, dids, lids, duo, dvo;
+    };
+    std::vector<std::unique_ptr<Aca>> aca(count);
     const int kaca = KMAX;
-    std::vector<int64_t> uo, vo;
-    int64_t tot = 0;
-    for (int l : lr_ids) {
-      uo.push_back(tot);
-      tot += (int64_t)S.lf[l].m * kaca;
-      vo.push_back(tot);
-      tot += (int64_t)S.lf[l].n * kaca;
+    for (int32_t i = 0; i < count; ++i) {
+      const hlevy_problem* prob = probs + i;
+      const hlevy_hparams* hp = hps + i;
+      if (!(prob->r0 < prob->hi - prob->lo)) return fail(HLEVY_ERR_INVALID_ARG, "r0 must be smaller than the domain");
+      auto op = std::make_unique<hlevy_op>();
+      std::string e = build_structure(*prob, *hp, op->S);
+      if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
+      const Structure& S = op->S;
+      for (auto& l : S.lf)
+        if (l.kind == K_LR && std::max(l.m, l.n) > 16384)
+          return fail(HLEVY_ERR_INVALID_ARG, "low-rank blocks are limited to 16384 rows (raise n_block)");
+      op->prob = *prob;
+      op->hp = *hp;
+      ProblemDev& pd = op->pd;
+      pd.dim = prob->dim;
+      pd.n = prob->n;
+      pd.N = S.N;
+      pd.h = S.h;
+      pd.a = prob->a;
+      pd.b0 = prob->b[0];
+      pd.b1 = prob->dim == 2 ? prob->b[1] : 0.0;
+      pd.c = prob->c;
+      pd.s = prob->s;
+      pd.lam = prob->lambda;
+      pd.C = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, prob->s);
+      pd.r0 = prob->r0;
+      op->ds.create(S, s);
+      op->cst.alloc(4 * sizeof(double));
+      op->ovf.alloc(sizeof(int32_t));
+      HL_CHECK(hipMemsetAsync(op->ovf.p, 0, sizeof(int32_t), s));
+      HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
+      op->G.create(S, hp->max_rank, FULL, s);
+      // dense near field
+      auto A = std::make_unique<Aca>();
+      std::vector<int32_t> dense_ids;
+      for (size_t l = 0; l < S.lf.size(); ++l) (S.lf[l].kind == K_DENSE ? dense_ids : A->lr_ids).push_back((int)l);
+      upload(A->dids, dense_ids, s);
+      upload(A->lids, A->lr_ids, s);
+      HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
+                                 A->dids.as<int32_t>(), (int)dense_ids.size(), s));
+      // far field: ACA into scratch (truncated into G below)
+      int64_t tot = 0;
+      for (int l : A->lr_ids) {
+        A->uo.push_back(tot);
+        tot += (int64_t)S.lf[l].m * kaca;
+        A->vo.push_back(tot);
+        tot += (int64_t)S.lf[l].n * kaca;
+      }
+      A->buf.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
+      upload(A->duo, A->uo, s);
+      upload(A->dvo, A->vo, s);
+      A->rank.alloc(std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t));
+      HL_CHECK(launch_aca(pd, op->ds.perm.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(), (int)A->lr_ids.size(),
+                          A->buf.as<double>(), A->buf.as<double>(), A->duo.as<int64_t>(), A->dvo.as<int64_t>(),
+                          A->rank.as<int32_t>(), kaca, 0.1 * hp->aca_tol, s));
+      aca[i] = std::move(A);
+      ops[i] = std::move(op);
     }
-    DevBuf acabuf, duo, dvo, acarank;
-    acabuf.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
-    upload(duo, uo, s);
-    upload(dvo, vo, s);
-    acarank.alloc(std::max<size_t>(lr_ids.size(), 1) * sizeof(int32_t));
-    HL_CHECK(launch_aca(pd, op->ds.perm.as<int32_t>(), op->G.dev(), lids.as<int32_t>(), (int)lr_ids.size(),
-                        acabuf.as<double>(), acabuf.as<double>(), duo.as<int64_t>(), dvo.as<int64_t>(),
-                        acarank.as<int32_t>(), kaca, 0.1 * hp->aca_tol, s));
+    // 2. truncation of every ACA block to its tolerance: one plan for all
+    //    problems (problems of equal tolerance share launches)
     {
+      std::map<double, std::vector<int32_t>> by_tol;
+      for (int32_t i = 0; i < count; ++i) by_tol[ops[i]->hp.aca_tol].push_back(i);
       Plan P;
       WsStack ws;
-      Builder B(P, ws, op->ds.ident.as<double>(), op->ovf.as<int32_t>(), hp->aca_tol);
-      B.add_problem(S, op->ds);
-      std::vector<LFlushTarget> tgs;
-      std::vector<std::vector<Term>> tl;
-      for (size_t q = 0; q < lr_ids.size(); ++q) {
-        const LeafDesc& d = op->G.L[lr_ids[q]];
-        LFlushTarget T{};
-        T.U = d.A;
-        T.V = d.B;
-        T.rank = op->G.rank + lr_ids[q];
-        T.m = d.m;
-        T.n = d.n;
-        T.kcap = d.kcap;
-        T.Kcap = kaca;
-        Term t{};
-        t.dense = 0;
-        t.ro = 0;
-        t.mr = d.m;
-        t.co = 0;
-        t.nc = d.n;
-        t.U = acabuf.as<double>() + uo[q];
-        t.ldu = d.m;
-        t.W = acabuf.as<double>() + vo[q];
-        t.ldw = d.n;
-        t.k = acarank.as<int32_t>() + q;
-        t.sign = 1.0;
-        tgs.push_back(T);
-        tl.push_back({t});
+      Builder B(P, ws, ops[0]->ds.ident.as<double>(), ops[0]->ovf.as<int32_t>(), hps[0].aca_tol);
+      for (auto& kv : by_tol) {
+        std::vector<LFlushTarget> tgs;
+        std::vector<std::vector<Term>> tl;
+        for (int32_t i : kv.second) {
+          hlevy_op* op = ops[i].get();
+          const Aca& A = *aca[i];
+          for (size_t q = 0; q < A.lr_ids.size(); ++q) {
+            const LeafDesc& d = op->G.L[A.lr_ids[q]];
+            LFlushTarget T{};
+            T.U = d.A;
+            T.V = d.B;
+            T.rank = op->G.rank + A.lr_ids[q];
+            T.m = d.m;
+            T.n = d.n;
+            T.kcap = d.kcap;
+            T.Kcap = kaca;
+            Term t{};
+            t.dense = 0;
+            t.ro = 0;
+            t.mr = d.m;
+            t.co = 0;
+            t.nc = d.n;
+            t.U = A.buf.as<double>() + A.uo[q];
+            t.ldu = d.m;
+            t.W = A.buf.as<double>() + A.vo[q];
+            t.ldw = d.n;
+            t.k = A.rank.as<int32_t>() + q;
+            t.sign = 1.0;
+            tgs.push_back(T);
+            tl.push_back({t});
+          }
+        }
+        // every problem's overflow counter: targets carry their own below
+        std::vector<int> where = B.emit_lflush(tgs, tl, kv.first);
+        size_t q0 = 0;
+        for (int32_t i : kv.second) {
+          for (size_t q = 0; q < aca[i]->lr_ids.size(); ++q) P.ltg[where[q0 + q]].overflow = ops[i]->ovf.as<int32_t>();
+          q0 += aca[i]->lr_ids.size();
+        }
       }
-      B.emit_lflush(tgs, tl, hp->aca_tol);
       P.upload_all(s);
       P.run(nullptr, s);
       HL_CHECK(hipStreamSynchronize(s));
     }
-    op->xbuf.alloc((size_t)S.N * sizeof(double));
-    op->ybuf.alloc((size_t)S.N * sizeof(double));
-    op->mv.create(S, op->G, read_ranks(op->G, s), false, false, s);
+    // 3. ranks back in one round, then the per-step product plans
+    std::vector<std::vector<int32_t>> rk(count);
+    for (int32_t i = 0; i < count; ++i) {
+      rk[i].resize(ops[i]->G.L.size());
+      if (!rk[i].empty())
+        HL_CHECK(hipMemcpyAsync(rk[i].data(), ops[i]->G.rank, rk[i].size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                s));
+    }
     HL_CHECK(hipStreamSynchronize(s));
-    *out = op.release();
+    for (int32_t i = 0; i < count; ++i) {
+      hlevy_op* op = ops[i].get();
+      op->xbuf.alloc((size_t)op->S.N * sizeof(double));
+      op->ybuf.alloc((size_t)op->S.N * sizeof(double));
+      op->mv.create(op->S, op->G, rk[i], false, false, s);
+    }
+    aca.clear();
+    HL_CHECK(hipStreamSynchronize(s));
     return HLEVY_OK;
   });
+  if (st != HLEVY_OK) return st;
+  for (int32_t i = 0; i < count; ++i) out[i] = ops[i].release();
+  return HLEVY_OK;
 }
 
 hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream) {
@@ -2291,11 +2342,17 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
     // 2. operators not in the cache: assembly, then one joint factorisation
     if (!fresh.empty()) {
       const double t0 = now_s();
-      for (SrvEntry* e : fresh) {
-        hlevy_op* op = nullptr;
-        hlevy_status st = hlevy_assemble(&e->prob, &e->hp, s, &op);
+      {
+        std::vector<hlevy_problem> pr;
+        std::vector<hlevy_hparams> hv;
+        for (SrvEntry* e : fresh) {
+          pr.push_back(e->prob);
+          hv.push_back(e->hp);
+        }
+        std::vector<hlevy_op*> oo(fresh.size(), nullptr);
+        hlevy_status st = hlevy_assemble_batched(pr.data(), hv.data(), (int32_t)pr.size(), s, oo.data());
         if (st != HLEVY_OK) return st;
-        e->op.reset(op);
+        for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->op.reset(oo[q]);
       }
       const double t1 = now_s();
       std::vector<const hlevy_op*> ops;

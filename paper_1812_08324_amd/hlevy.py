@@ -58,7 +58,7 @@ class KernelTimes(C.Structure):
                 ("v_bytes", C.c_double * 3), ("partial_bytes", C.c_double * 3)]
 
 
-EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble",
+EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble", "hlevy_assemble_batched",
            "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
            "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_step", "hlevy_step_batched",
            "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
@@ -88,6 +88,7 @@ def _load():
         "hlevy_last_error": ([], C.c_char_p),
         "hlevy_plan_info": ([C.POINTER(Problem), C.POINTER(HParams), C.POINTER(PlanInfo)], st),
         "hlevy_assemble": ([C.POINTER(Problem), C.POINTER(HParams), vp, C.POINTER(vp)], st),
+        "hlevy_assemble_batched": ([C.POINTER(Problem), C.POINTER(HParams), C.c_int32, vp, C.POINTER(vp)], st),
         "hlevy_op_constants": ([vp, C.POINTER(C.c_double), vp], st),
         "hlevy_op_info": ([vp, C.POINTER(OpInfo), vp], st),
         "hlevy_matvec": ([vp, vp, vp, vp], st),
@@ -188,10 +189,12 @@ def fac_kernel_times(fac, reps: int = 20, stream=None) -> dict:
 class Op:
     """Assembled H-matrix of the generator G (handle owner)."""
 
-    def __init__(self, prob: Problem, hp: HParams, stream=None):
-        h = C.c_void_p()
-        _check(lib.hlevy_assemble(C.byref(prob), C.byref(hp), _stream(stream), C.byref(h)), "hlevy_assemble")
-        self.h = h
+    def __init__(self, prob: Problem, hp: HParams, stream=None, handle=None):
+        if handle is None:
+            handle = C.c_void_p()
+            _check(lib.hlevy_assemble(C.byref(prob), C.byref(hp), _stream(stream), C.byref(handle)),
+                   "hlevy_assemble")
+        self.h = handle
         self.N = prob.n if prob.dim == 1 else prob.n * prob.n
         self.prob, self.hp = prob, hp
 
@@ -223,6 +226,19 @@ class Fac:
 
 def assemble(prob: Problem, hp: HParams, stream=None) -> Op:
     return Op(prob, hp, stream)
+
+
+def assemble_batched(probs, hps, stream=None) -> list:
+    """Operators of several problems from one batched assembly
+    (hlevy_assemble_batched)."""
+    n = len(probs)
+    if len(hps) != n or n == 0:
+        raise ValueError("one hparams per problem, at least one problem")
+    pa = (Problem * n)(*probs)
+    ha = (HParams * n)(*hps)
+    out = (C.c_void_p * n)()
+    _check(lib.hlevy_assemble_batched(pa, ha, n, _stream(stream), out), "hlevy_assemble_batched")
+    return [Op(p, hp, handle=C.c_void_p(out[i])) for i, (p, hp) in enumerate(zip(probs, hps))]
 
 
 def op_constants(op: Op, stream=None):

@@ -157,3 +157,23 @@ def test_full_batch_sampled(H, full_batch):
         assert rel(host(us[i]), host(v)) <= 1e-12, (i, w.n)
     for u in us:
         assert torch.isfinite(u).all()
+
+
+def test_batched_assembly_equals_single(H):
+    """hlevy_assemble_batched gives, problem by problem, the operator
+    hlevy_assemble gives (bit for bit: the same kernels per problem), also
+    with two different ACA tolerances in one batch."""
+    ws = small_batch(steps=1)[:5]
+    ws[1] = ws[1].with_(aca_tol=1e-8)
+    probs, hps = [], []
+    for w in ws:
+        probs.append(H.make_problem(w.dim, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0))
+        hps.append(H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol, max_rank=16))
+    ops = H.assemble_batched(probs, hps)
+    for w, p, hp, ob in zip(ws, probs, hps, ops):
+        os_ = H.assemble(p, hp)
+        da = torch.empty(w.N * w.N, dtype=torch.float64, device="cuda")
+        db = torch.empty_like(da)
+        H.op_densify(ob, da)
+        H.op_densify(os_, db)
+        assert torch.equal(da, db), w.name
