@@ -1713,12 +1713,16 @@ __global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t
         ub[c] = u[c] * rinv;
         xk[c] = j < k ? xv : (j == k ? 1.0 : 0.0);
       }
+      // register block (r, c) holds rows ty + 32 r, columns tx + 32 c: rows
+      // of blocks r < cb and columns of blocks c < cb are <= k, those of
+      // blocks > cb are > k, so the zero products drop out at compile time
 #pragma unroll
       for (int r = 0; r < LI_R; ++r)
 #pragma unroll
         for (int c = 0; c < LI_R; ++c) {
-          a[r][c] -= l[r] * u[c];
-          z[r][c] -= l[r] * xk[c] + yk[r] * ub[c];
+          if (r >= cb && c >= cb) a[r][c] -= l[r] * u[c];
+          if (r >= cb && c <= cb) z[r][c] -= l[r] * xk[c];   // X: rows > k, columns <= k
+          if (r <= cb && c >= cb) z[r][c] -= yk[r] * ub[c];  // Y: rows <= k, columns > k
         }
     }
   }
