@@ -1828,20 +1828,23 @@ __global__ void __launch_bounds__(HL_BLOCK) k_apply_gather(const ApplyJob* jobs,
         Xs[e2] = X[(e2 % len) + (size_t)J.ldx * (e2 / len)];
       __syncthreads();
       if (i < mr) {
-        if (!J.trans) {
-          const double* D = d.A + (lo - d.rlo);
-          for (int u = 0; qg + 4 * u < kx; ++u) {
-            int q = qg + 4 * u;
+        // row i of the block in 16-column chunks, each chunk loaded once
+        // and applied to every column q = qg + 4 u of X (wavefront-uniform
+        // guards keep the accumulator indices static)
+        const double* D = J.trans ? d.A + (size_t)d.m * (lo - d.clo) : d.A + (lo - d.rlo);
+        const size_t si = J.trans ? (size_t)d.m : 1, sj = J.trans ? 1 : (size_t)d.m;
+        for (int j0 = 0; j0 < len; j0 += 16) {
+          const int jn = min(16, len - j0);
+          double dv[16];
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) dv[jj] = jj < jn ? D[si * i + sj * (j0 + jj)] : 0.0;
+#pragma unroll
+          for (int u = 0; u < KMAX / 4; ++u) {
+            if (qg + 4 * u >= kx) break;
+            const double* xq = Xs + len * (qg + 4 * u) + j0;
             double s = 0.0;
-            for (int j = 0; j < len; ++j) s += D[i + (size_t)d.m * j] * Xs[j + len * q];
-            acc[u] += s;
-          }
-        } else {
-          const double* D = d.A + (size_t)d.m * (lo - d.clo);
-          for (int u = 0; qg + 4 * u < kx; ++u) {
-            int q = qg + 4 * u;
-            double s = 0.0;
-            for (int j = 0; j < len; ++j) s += D[j + (size_t)d.m * i] * Xs[j + len * q];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) s += dv[jj] * (jj < jn ? xq[jj] : 0.0);
             acc[u] += s;
           }
         }
@@ -1850,13 +1853,23 @@ __global__ void __launch_bounds__(HL_BLOCK) k_apply_gather(const ApplyJob* jobs,
       const int k = J.rank[l];
       const double* Tl = J.T + (size_t)(l - J.lbeg) * J.tstride;
       if (i < mr) {
+        // row i of the factor loaded once, applied to every column q
         const double* F = J.trans ? d.B + (lo - d.clo) : d.A + (lo - d.rlo);
         const int ld = J.trans ? d.n : d.m;
-        for (int u = 0; qg + 4 * u < kx; ++u) {
-          int q = qg + 4 * u;
-          double s = 0.0;
-          for (int p = 0; p < k; ++p) s += F[i + (size_t)ld * p] * Tl[p + d.kcap * q];
-          acc[u] += s;
+        for (int p0 = 0; p0 < k; p0 += 16) {
+          const int pn = min(16, k - p0);
+          double fv[16];
+#pragma unroll
+          for (int pp = 0; pp < 16; ++pp) fv[pp] = pp < pn ? F[i + (size_t)ld * (p0 + pp)] : 0.0;
+#pragma unroll
+          for (int u = 0; u < KMAX / 4; ++u) {
+            if (qg + 4 * u >= kx) break;
+            const double* tq = Tl + d.kcap * (qg + 4 * u) + p0;
+            double s = 0.0;
+#pragma unroll
+            for (int pp = 0; pp < 16; ++pp) s += fv[pp] * (pp < pn ? tq[pp] : 0.0);
+            acc[u] += s;
+          }
         }
       }
     }
