@@ -9,6 +9,8 @@
 
 namespace hl {
 
+typedef double double4v __attribute__((ext_vector_type(4)));
+
 #define HL_BLOCK 256
 
 // ---------------------------------------------------------------------------
@@ -1310,6 +1312,68 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
     radd_fetch_tile(cs, 0, 0, min(64, T.m), K, v);
     for (int side = 0; side < 2; ++side) {
       const int len = side == 0 ? T.m : T.n;
+      double* Gh = side == 0 ? Yh : Xh;
+      double* Gl = side == 0 ? Yl : Xl;
+      if (!use_dd) {
+        // Gram on the matrix cores: the upper 16 x 16 tiles (TI <= TJ) of
+        // the K x K Gram, at most 3 per wavefront; per 64-row block 16
+        // steps of v_mfma_f64_16x16x4f64 with A = tile^T (16 columns x 4
+        // rows: A[i][k] in lane i + 16 k) and B = tile (4 rows x 16
+        // columns: B[k][j] in lane j + 16 k); D[i][j] sits in lane
+        // 16 (i % 4) + j, register i / 4
+        const int nT = (K + 15) / 16, nUp = nT * (nT + 1) / 2;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        int tI[3], tJ[3];
+        double4v gacc[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          gacc[u] = double4v{0.0, 0.0, 0.0, 0.0};
+          int idx = wv + 4 * u, a = 0;
+          while (a < nT && idx >= nT - a) {   // upper tile number idx -> (a, b)
+            idx -= nT - a;
+            ++a;
+          }
+          tI[u] = a;
+          tJ[u] = a + idx;
+        }
+        for (int base = 0; base < len; base += 64) {
+          __syncthreads();
+          radd_store_tile(v, K, tile);
+          __syncthreads();
+          if (base + 64 < len)
+            radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
+          else if (side == 0)
+            radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            if (wv + 4 * u >= nUp) break;
+            const int ca = 16 * tI[u] + (lane & 15), cb = 16 * tJ[u] + (lane & 15);
+            const double* ta = tile + RA_TS * min(ca, K - 1);
+            const double* tb = tile + RA_TS * min(cb, K - 1);
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+              const int rr = 4 * kk + (lane >> 4);
+              const double a = ca < K ? ta[rr] : 0.0;
+              const double b = cb < K ? tb[rr] : 0.0;
+              gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          if (wv + 4 * u >= nUp) break;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int p = 16 * tI[u] + 4 * r + (lane >> 4), q = 16 * tJ[u] + (lane & 15);
+            // diagonal tiles: one writer per symmetric pair
+            if (p < K && q < K && (tI[u] < tJ[u] || p <= q)) {
+              Gh[p * ls + q] = gacc[u][r];
+              Gh[q * ls + p] = gacc[u][r];
+            }
+          }
+        }
+        continue;
+      }
       dd accv[PPT];
 #pragma unroll
       for (int u = 0; u < PPT; ++u) accv[u] = {0.0, 0.0};
@@ -1327,29 +1391,18 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
           if (tid + u * HL_BLOCK >= np) continue;
           const double* a = tile + RA_TS * pp[u];
           const double* b = tile + RA_TS * qq[u];
-          if (use_dd) {
-            dd acc = accv[u];
-            for (int rr = 0; rr < 64; ++rr) acc = dd_add(acc, dd_mul_d(a[rr], b[rr]));
-            accv[u] = acc;
-          } else {
-            double acc = accv[u].hi;
-#pragma unroll 8
-            for (int rr = 0; rr < 64; ++rr) acc += a[rr] * b[rr];
-            accv[u].hi = acc;
-          }
+          dd acc = accv[u];
+          for (int rr = 0; rr < 64; ++rr) acc = dd_add(acc, dd_mul_d(a[rr], b[rr]));
+          accv[u] = acc;
         }
       }
-      double* Gh = side == 0 ? Yh : Xh;
-      double* Gl = side == 0 ? Yl : Xl;
 #pragma unroll
       for (int u = 0; u < PPT; ++u) {
         if (tid + u * HL_BLOCK >= np) continue;
         Gh[pp[u] * ls + qq[u]] = accv[u].hi;
         Gh[qq[u] * ls + pp[u]] = accv[u].hi;
-        if (use_dd) {
-          Gl[pp[u] * ls + qq[u]] = accv[u].lo;
-          Gl[qq[u] * ls + pp[u]] = accv[u].lo;
-        }
+        Gl[pp[u] * ls + qq[u]] = accv[u].lo;
+        Gl[qq[u] * ls + pp[u]] = accv[u].lo;
       }
     }
     __syncthreads();
