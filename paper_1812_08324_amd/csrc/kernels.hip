@@ -1423,12 +1423,36 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
           radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
         else if (side == 0)
           radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
-        for (int o = tid; o < 64 * RA_YS; o += HL_BLOCK) {
-          const int rr = o & 63, c = o >> 6;
-          if (c >= r || rr >= rows) continue;
-          double acc = 0.0;
-          for (int j = 0; j < K; ++j) acc += tile[rr + RA_TS * j] * Y[j * RA_YS + c];
-          out[(base + rr) + (size_t)len * c] = acc;
+        // on the matrix cores: wavefront w takes rows 16 w .. 16 w + 15 of
+        // the block and the (at most two) 16-column tiles of the r new
+        // columns: A[i][k] = tile row 16 w + i, column 4 kk + k (lane
+        // i + 16 k), B[k][j] = Y[4 kk + k][16 cj + j] (lane j + 16 k);
+        // D[i][j] in lane 16 (i % 4) + j, register i / 4
+        {
+          const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+          const int nC = (r + 15) / 16;
+          double4v eacc[2] = {double4v{0.0, 0.0, 0.0, 0.0}, double4v{0.0, 0.0, 0.0, 0.0}};
+          const double* ta = tile + 16 * wv + (lane & 15);
+          for (int kk = 0; kk < (K + 3) / 4; ++kk) {
+            const int j = 4 * kk + (lane >> 4);
+            const double a = j < K ? ta[RA_TS * j] : 0.0;
+#pragma unroll
+            for (int cj = 0; cj < 2; ++cj) {
+              if (cj >= nC) break;
+              const double b = j < K ? Y[j * RA_YS + 16 * cj + (lane & 15)] : 0.0;
+              eacc[cj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, eacc[cj], 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int cj = 0; cj < 2; ++cj) {
+            if (cj >= nC) break;
+            const int c = 16 * cj + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * wv + 4 * q + (lane >> 4);
+              if (row < rows && c < r) out[(base + row) + (size_t)len * c] = eacc[cj][q];
+            }
+          }
         }
       }
     }
