@@ -480,58 +480,6 @@ __device__ __forceinline__ double side_val(const LFlushTarget& T, const Term* te
 __device__ __forceinline__ int pair_index(int p, int q) { return q * (q + 1) / 2 + p; }  // p <= q
 __host__ __device__ inline int npairs(int K) { return K * (K + 1) / 2; }
 
-// partial Gram of rows [r0, r1) of one side, double-double, packed upper triangle
-__global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg, const Term* terms,
-                                                         const ChunkItem* items) {
-  __shared__ ColMap cm;
-  __shared__ double tile[65 * KMAX];   // column stride 65: no LDS bank conflicts across columns
-  const ChunkItem it = items[blockIdx.x];
-  const LFlushTarget T = tg[it.tgt];
-  if (threadIdx.x < 64) build_colmap(T, terms, T.rank ? *T.rank : 0, cm);
-  __syncthreads();
-  const int K = cm.K;
-  const int np = npairs(K);
-  constexpr int PPT = (KMAX * (KMAX + 1) / 2 + HL_BLOCK - 1) / HL_BLOCK;  // pairs per thread
-  dd accv[PPT];
-  int pp[PPT], qq[PPT];
-  for (int u = 0; u < PPT; ++u) {
-    accv[u] = {0.0, 0.0};
-    int idx = threadIdx.x + u * HL_BLOCK;
-    pp[u] = qq[u] = -1;
-    if (idx < np) {
-      int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-      while (q * (q + 1) / 2 > idx) --q;
-      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
-      pp[u] = idx - q * (q + 1) / 2;
-      qq[u] = q;
-    }
-  }
-  for (int base = it.r0; base < it.r1; base += 64) {
-    int rows = min(64, it.r1 - base);
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * K; e += HL_BLOCK) {
-      int rr = e % 64, j = e / 64;
-      tile[rr + 65 * j] = rr < rows ? side_val(T, terms, cm, it.side, base + rr, j) : 0.0;
-    }
-    __syncthreads();
-    for (int u = 0; u < PPT; ++u) {
-      if (pp[u] < 0) continue;
-      const double* a = tile + 65 * pp[u];
-      const double* b = tile + 65 * qq[u];
-      dd s = accv[u];
-      for (int rr = 0; rr < rows; ++rr) s = dd_add(s, dd_mul_d(a[rr], b[rr]));
-      accv[u] = s;
-    }
-  }
-  const int Kc = T.Kcap;
-  double* dst = T.ws + (size_t)(it.side == 0 ? it.chunk : T.nchA + it.chunk) * npairs(Kc) * 2;
-  for (int u = 0; u < PPT; ++u) {
-    if (pp[u] < 0) continue;
-    int idx = pair_index(pp[u], qq[u]);
-    dst[2 * idx] = accv[u].hi;
-    dst[2 * idx + 1] = accv[u].lo;
-  }
-}
 
 // Pivoted Cholesky (double-double) of the Gram G (K x K, stride ks, in
 // Gh/Gl), one block of 256 threads, every step parallel.  Writes R (rank x K,
@@ -1133,45 +1081,8 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core_fast(const LFlushTarget
   for (int e = tid; e < 2 * K * RA_YS; e += HL_BLOCK) dst[e] = e < K * RA_YS ? YU[e] : YV[e - K * RA_YS];
 }
 
-// new factor rows: out[row, c] = sum_j side(row, j) Y[j, c], c < r (row-local:
-// the rows read and written belong to this thread, so in-place is safe)
-__device__ __forceinline__ void radd_expand_rows(const LFlushTarget& T, const Term* terms, const ColMap& cm, int side,
-                                                 int r0, int r1, const double* Y, int r) {
-  double* out = side == 0 ? T.U : T.V;
-  const int ld = side == 0 ? T.m : T.n;
-  const int K = cm.K;
-  for (int row = r0 + threadIdx.x; row < r1; row += HL_BLOCK) {
-    double acc[RA_YS];
-#pragma unroll
-    for (int c = 0; c < RA_YS; ++c) acc[c] = 0.0;
-    for (int j = 0; j < K; ++j) {
-      const double a = side_val(T, terms, cm, side, row, j);
-#pragma unroll
-      for (int c = 0; c < RA_YS; ++c) acc[c] += a * Y[j * RA_YS + c];
-    }
-#pragma unroll
-    for (int c = 0; c < RA_YS; ++c)
-      if (c < r) out[row + (size_t)ld * c] = acc[c];
-  }
-}
 
 // U_new = A Y_U (side 0) or V_new = B Y_V (side 1) for rows [r0, r1)
-__global__ void __launch_bounds__(HL_BLOCK) k_flush_expand(const LFlushTarget* tg, const Term* terms,
-                                                           const ChunkItem* items) {
-  __shared__ ColMap cm;
-  __shared__ double Y[KMAX * RA_YS];
-  const ChunkItem it = items[blockIdx.x];
-  const LFlushTarget T = tg[it.tgt];
-  const int kC = T.info[0], r = T.info[1];
-  if (threadIdx.x < 64) build_colmap(T, terms, kC, cm);
-  __syncthreads();
-  const int K = cm.K, Kc = T.Kcap;
-  const int np = npairs(Kc);
-  const double* Ys = T.ws + (size_t)(T.nchA + T.nchB) * np * 2 + (it.side == 0 ? 0 : (size_t)K * RA_YS);
-  for (int e = threadIdx.x; e < K * RA_YS; e += HL_BLOCK) Y[e] = Ys[e];
-  __syncthreads();
-  radd_expand_rows(T, terms, cm, it.side, it.r0, it.r1, Y, r);
-}
 
 // Column sources of the concatenated factors of a target (side 0: U side,
 // side 1: V side): column j is sign * p[row - off] for row - off in [0, len),
@@ -1229,6 +1140,202 @@ __device__ __forceinline__ void radd_store_tile(const double (&v)[RA_NE], int K,
   for (int u = 0; u < RA_NE; ++u) {
     const int e = threadIdx.x + u * HL_BLOCK;
     if ((e >> 6) < K) tile[(e & 63) + RA_TS * (e >> 6)] = v[u];
+  }
+}
+
+// Gram of staged 64-row blocks on the matrix cores: the upper 16 x 16 tiles
+// (TI <= TJ) of the K x K Gram, at most 3 per wavefront of a 256-thread
+// block; per block 16 steps of v_mfma_f64_16x16x4f64 with A = tile^T
+// (A[i][k] in lane i + 16 k) and B = tile (B[k][j] in lane j + 16 k); D[i][j]
+// sits in lane 16 (i % 4) + j, register i / 4.  Columns >= K count as zero.
+struct GramTiles {
+  int tI[3], tJ[3], nup;
+  double4v acc[3];
+};
+__device__ __forceinline__ void gram_tiles_init(GramTiles& g, int K, int wv) {
+  const int nT = (K + 15) / 16;
+  g.nup = nT * (nT + 1) / 2;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    g.acc[u] = double4v{0.0, 0.0, 0.0, 0.0};
+    int idx = wv + 4 * u, a = 0;
+    while (a < nT && idx >= nT - a) {   // upper tile number idx -> (a, b)
+      idx -= nT - a;
+      ++a;
+    }
+    g.tI[u] = a;
+    g.tJ[u] = a + idx;
+  }
+}
+__device__ __forceinline__ void gram_tiles_add(GramTiles& g, const double* tile, int K, int wv, int lane) {
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (wv + 4 * u >= g.nup) break;
+    const int ca = 16 * g.tI[u] + (lane & 15), cb = 16 * g.tJ[u] + (lane & 15);
+    const double* ta = tile + RA_TS * min(ca, K - 1);
+    const double* tb = tile + RA_TS * min(cb, K - 1);
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int rr = 4 * kk + (lane >> 4);
+      const double a = ca < K ? ta[rr] : 0.0;
+      const double b = cb < K ? tb[rr] : 0.0;
+      g.acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, g.acc[u], 0, 0, 0);
+    }
+  }
+}
+// store(p, q, value) once per pair p <= q < K
+template <class F>
+__device__ __forceinline__ void gram_tiles_store(const GramTiles& g, int K, int wv, int lane, F&& store) {
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (wv + 4 * u >= g.nup) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = 16 * g.tI[u] + 4 * r + (lane >> 4), q = 16 * g.tJ[u] + (lane & 15);
+      if (p < K && q < K && (g.tI[u] < g.tJ[u] || p <= q)) store(p, q, g.acc[u][r]);
+    }
+  }
+}
+
+// rows of a staged 64-row block times Y (K x r, row stride RA_YS) on the
+// matrix cores: wavefront wv takes rows 16 wv .. 16 wv + 15 and the (at
+// most two) 16-column tiles of the r columns; out[row + ld c] for the
+// block's first `rows` rows
+__device__ __forceinline__ void expand_block_mfma(const double* tile, const double* Y, int K, int r, int rows,
+                                                  int wv, int lane, double* out, size_t ld) {
+  const int nC = (r + 15) / 16;
+  double4v eacc[2] = {double4v{0.0, 0.0, 0.0, 0.0}, double4v{0.0, 0.0, 0.0, 0.0}};
+  const double* ta = tile + 16 * wv + (lane & 15);
+  for (int kk = 0; kk < (K + 3) / 4; ++kk) {
+    const int j = 4 * kk + (lane >> 4);
+    const double a = j < K ? ta[RA_TS * j] : 0.0;
+#pragma unroll
+    for (int cj = 0; cj < 2; ++cj) {
+      if (cj >= nC) break;
+      const double b = j < K ? Y[j * RA_YS + 16 * cj + (lane & 15)] : 0.0;
+      eacc[cj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, eacc[cj], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int cj = 0; cj < 2; ++cj) {
+    if (cj >= nC) break;
+    const int c = 16 * cj + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * wv + 4 * q + (lane >> 4);
+      if (row < rows && c < r) out[row + ld * c] = eacc[cj][q];
+    }
+  }
+}
+
+// Partial Gram of rows [r0, r1) of one side of a bucketed rounded
+// addition, packed upper triangle (double-double below 1e-9, else on the
+// matrix cores).
+__global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg, const Term* terms,
+                                                         const ChunkItem* items, double tol) {
+  __shared__ ColMap cm;
+  __shared__ RaddCols cs;
+  __shared__ double tile[RA_TS * KMAX];   // 64 x K, column stride RA_TS
+  const ChunkItem it = items[blockIdx.x];
+  const LFlushTarget T = tg[it.tgt];
+  if (threadIdx.x < 64) build_colmap(T, terms, T.rank ? *T.rank : 0, cm);
+  __syncthreads();
+  radd_cols(T, terms, cm, cs);
+  __syncthreads();
+  const int K = cm.K;
+  const int Kc = T.Kcap;
+  double* dst = T.ws + (size_t)(it.side == 0 ? it.chunk : T.nchA + it.chunk) * npairs(Kc) * 2;
+  double v[RA_NE];
+  radd_fetch_tile(cs, it.side, it.r0, min(64, it.r1 - it.r0), K, v);
+  if (!radd_needs_dd(tol)) {
+    // on the matrix cores (low parts zero)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    GramTiles gt;
+    gram_tiles_init(gt, K, wv);
+    for (int base = it.r0; base < it.r1; base += 64) {
+      __syncthreads();
+      radd_store_tile(v, K, tile);
+      __syncthreads();
+      if (base + 64 < it.r1) radd_fetch_tile(cs, it.side, base + 64, min(64, it.r1 - base - 64), K, v);
+      gram_tiles_add(gt, tile, K, wv, lane);
+    }
+    gram_tiles_store(gt, K, wv, lane, [&](int pp, int qq, double x) {
+      const int idx = pair_index(pp, qq);
+      dst[2 * idx] = x;
+      dst[2 * idx + 1] = 0.0;
+    });
+    return;
+  }
+  const int np = npairs(K);
+  constexpr int PPT = (KMAX * (KMAX + 1) / 2 + HL_BLOCK - 1) / HL_BLOCK;  // pairs per thread
+  dd accv[PPT];
+  int pp[PPT], qq[PPT];
+  for (int u = 0; u < PPT; ++u) {
+    accv[u] = {0.0, 0.0};
+    int idx = threadIdx.x + u * HL_BLOCK;
+    pp[u] = qq[u] = -1;
+    if (idx < np) {
+      int q = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (q * (q + 1) / 2 > idx) --q;
+      while ((q + 1) * (q + 2) / 2 <= idx) ++q;
+      pp[u] = idx - q * (q + 1) / 2;
+      qq[u] = q;
+    }
+  }
+  for (int base = it.r0; base < it.r1; base += 64) {
+    __syncthreads();
+    radd_store_tile(v, K, tile);
+    __syncthreads();
+    if (base + 64 < it.r1) radd_fetch_tile(cs, it.side, base + 64, min(64, it.r1 - base - 64), K, v);
+    for (int u = 0; u < PPT; ++u) {
+      if (pp[u] < 0) continue;
+      const double* a = tile + RA_TS * pp[u];
+      const double* b = tile + RA_TS * qq[u];
+      dd s = accv[u];
+      for (int rr = 0; rr < 64; ++rr) s = dd_add(s, dd_mul_d(a[rr], b[rr]));
+      accv[u] = s;
+    }
+  }
+  for (int u = 0; u < PPT; ++u) {
+    if (pp[u] < 0) continue;
+    int idx = pair_index(pp[u], qq[u]);
+    dst[2 * idx] = accv[u].hi;
+    dst[2 * idx + 1] = accv[u].lo;
+  }
+}
+
+// New factor rows [r0, r1) of one side of a bucketed rounded addition.
+__global__ void __launch_bounds__(HL_BLOCK) k_flush_expand(const LFlushTarget* tg, const Term* terms,
+                                                           const ChunkItem* items) {
+  __shared__ ColMap cm;
+  __shared__ RaddCols cs;
+  __shared__ double Y[KMAX * RA_YS];
+  __shared__ double tile[RA_TS * KMAX];
+  const ChunkItem it = items[blockIdx.x];
+  const LFlushTarget T = tg[it.tgt];
+  const int kC = T.info[0], r = T.info[1];
+  if (threadIdx.x < 64) build_colmap(T, terms, kC, cm);
+  __syncthreads();
+  radd_cols(T, terms, cm, cs);
+  const int K = cm.K, Kc = T.Kcap;
+  const int np = npairs(Kc);
+  const double* Ys = T.ws + (size_t)(T.nchA + T.nchB) * np * 2 + (it.side == 0 ? 0 : (size_t)K * RA_YS);
+  for (int e = threadIdx.x; e < K * RA_YS; e += HL_BLOCK) Y[e] = Ys[e];
+  __syncthreads();
+  // new factor rows [r0, r1) = concatenation rows times Y (row-local: the
+  // next block is fetched before this one is written)
+  double* out = it.side == 0 ? T.U : T.V;
+  const size_t ld = it.side == 0 ? T.m : T.n;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  double v[RA_NE];
+  radd_fetch_tile(cs, it.side, it.r0, min(64, it.r1 - it.r0), K, v);
+  for (int base = it.r0; base < it.r1; base += 64) {
+    const int rows = min(64, it.r1 - base);
+    __syncthreads();
+    radd_store_tile(v, K, tile);
+    __syncthreads();
+    if (base + 64 < it.r1) radd_fetch_tile(cs, it.side, base + 64, min(64, it.r1 - base - 64), K, v);
+    expand_block_mfma(tile, Y, K, r, rows, wv, lane, out + base, ld);
   }
 }
 
@@ -1315,27 +1422,10 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
       double* Gh = side == 0 ? Yh : Xh;
       double* Gl = side == 0 ? Yl : Xl;
       if (!use_dd) {
-        // Gram on the matrix cores: the upper 16 x 16 tiles (TI <= TJ) of
-        // the K x K Gram, at most 3 per wavefront; per 64-row block 16
-        // steps of v_mfma_f64_16x16x4f64 with A = tile^T (16 columns x 4
-        // rows: A[i][k] in lane i + 16 k) and B = tile (4 rows x 16
-        // columns: B[k][j] in lane j + 16 k); D[i][j] sits in lane
-        // 16 (i % 4) + j, register i / 4
-        const int nT = (K + 15) / 16, nUp = nT * (nT + 1) / 2;
+        // Gram on the matrix cores
         const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-        int tI[3], tJ[3];
-        double4v gacc[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          gacc[u] = double4v{0.0, 0.0, 0.0, 0.0};
-          int idx = wv + 4 * u, a = 0;
-          while (a < nT && idx >= nT - a) {   // upper tile number idx -> (a, b)
-            idx -= nT - a;
-            ++a;
-          }
-          tI[u] = a;
-          tJ[u] = a + idx;
-        }
+        GramTiles gt;
+        gram_tiles_init(gt, K, wv);
         for (int base = 0; base < len; base += 64) {
           __syncthreads();
           radd_store_tile(v, K, tile);
@@ -1344,34 +1434,12 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
             radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
           else if (side == 0)
             radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
-#pragma unroll
-          for (int u = 0; u < 3; ++u) {
-            if (wv + 4 * u >= nUp) break;
-            const int ca = 16 * tI[u] + (lane & 15), cb = 16 * tJ[u] + (lane & 15);
-            const double* ta = tile + RA_TS * min(ca, K - 1);
-            const double* tb = tile + RA_TS * min(cb, K - 1);
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-              const int rr = 4 * kk + (lane >> 4);
-              const double a = ca < K ? ta[rr] : 0.0;
-              const double b = cb < K ? tb[rr] : 0.0;
-              gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
-            }
-          }
+          gram_tiles_add(gt, tile, K, wv, lane);
         }
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          if (wv + 4 * u >= nUp) break;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int p = 16 * tI[u] + 4 * r + (lane >> 4), q = 16 * tJ[u] + (lane & 15);
-            // diagonal tiles: one writer per symmetric pair
-            if (p < K && q < K && (tI[u] < tJ[u] || p <= q)) {
-              Gh[p * ls + q] = gacc[u][r];
-              Gh[q * ls + p] = gacc[u][r];
-            }
-          }
-        }
+        gram_tiles_store(gt, K, wv, lane, [&](int p, int q, double x) {
+          Gh[p * ls + q] = x;
+          Gh[q * ls + p] = x;
+        });
         continue;
       }
       dd accv[PPT];
@@ -1423,37 +1491,8 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
           radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
         else if (side == 0)
           radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
-        // on the matrix cores: wavefront w takes rows 16 w .. 16 w + 15 of
-        // the block and the (at most two) 16-column tiles of the r new
-        // columns: A[i][k] = tile row 16 w + i, column 4 kk + k (lane
-        // i + 16 k), B[k][j] = Y[4 kk + k][16 cj + j] (lane j + 16 k);
-        // D[i][j] in lane 16 (i % 4) + j, register i / 4
-        {
-          const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-          const int nC = (r + 15) / 16;
-          double4v eacc[2] = {double4v{0.0, 0.0, 0.0, 0.0}, double4v{0.0, 0.0, 0.0, 0.0}};
-          const double* ta = tile + 16 * wv + (lane & 15);
-          for (int kk = 0; kk < (K + 3) / 4; ++kk) {
-            const int j = 4 * kk + (lane >> 4);
-            const double a = j < K ? ta[RA_TS * j] : 0.0;
-#pragma unroll
-            for (int cj = 0; cj < 2; ++cj) {
-              if (cj >= nC) break;
-              const double b = j < K ? Y[j * RA_YS + 16 * cj + (lane & 15)] : 0.0;
-              eacc[cj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, eacc[cj], 0, 0, 0);
-            }
-          }
-#pragma unroll
-          for (int cj = 0; cj < 2; ++cj) {
-            if (cj >= nC) break;
-            const int c = 16 * cj + (lane & 15);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int row = 16 * wv + 4 * q + (lane >> 4);
-              if (row < rows && c < r) out[(base + row) + (size_t)len * c] = eacc[cj][q];
-            }
-          }
-        }
+        expand_block_mfma(tile, Y, K, r, rows, __builtin_amdgcn_readfirstlane(tid >> 6), tid & 63, out + base,
+                          (size_t)len);
       }
     }
     t0 += cm.nt;
@@ -2044,7 +2083,7 @@ hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* 
 hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, const ChunkItem* gram,
                            int ngram, const ChunkItem* expand, int nexp, double tol, int ks, hipStream_t s) {
   if (ntg == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_flush_gram, dim3(ngram), dim3(HL_BLOCK), 0, s, tg, terms, gram);
+  hipLaunchKernelGGL(k_flush_gram, dim3(ngram), dim3(HL_BLOCK), 0, s, tg, terms, gram, tol);
   // the pivoted-Cholesky core: up to 48 columns with double-double parts,
   // up to KMAX without (tolerances >= 1e-9)
   if (ks <= 48 || (!radd_needs_dd(tol) && ks <= KMAX)) {
