@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_mv_gather_G_tempered1d_n65536.txt")
 WORKLOADS = {
     "tempered1d_n65536": dict(kind="config2", n=65536, steps=1000),
     "tempered1d_n16384": dict(kind="config2", n=16384, steps=1000),
@@ -48,6 +49,10 @@ def parse():
     ap.add_argument("--serve-frac-1d", type=float, default=1.0,
                     help="share of 1D requests in the served trace (the rest 2D)")
     ap.add_argument("--job-only", action="store_true", help="run warmup + timed jobs only (profiling)")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="with --factor-only: CN steps of the mixed path after the factorisation")
+    ap.add_argument("--factor-only", action="store_true",
+                    help="one assembly and one mixed factorisation of the workload (counter profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain device copies of 2 GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -225,6 +230,23 @@ def bench_2d(H, torch, sweeps, lu_tol_mixed):
     return out
 
 
+def counted_traffic(key):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the product kernels' sources have changed since
+    the counters were taken (their hash no longer matches)."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_PROFILE).read().splitlines() if ": " in l)
+        h = hashlib.sha256()
+        for f in fields["kernel_sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != fields["kernel_source_sha256"].strip():
+            return None
+        return float(fields[key])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -282,6 +304,22 @@ def main():
     g = torch.tensor(w.g, dtype=torch.float64, device="cuda") if w.g is not None else None
     phi = list(w.phi) if w.phi is not None else None
     torch.cuda.synchronize()
+
+    if args.factor_only:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = H.assemble(prob, hp)
+        fac = H.factor(op, w.dt, H.PREC_MIXED, args.lu_tol_mixed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        progress("factorisation done")
+        if args.profile_steps > 0:
+            u = u0.clone()
+            H.step(fac, u, args.profile_steps, g=g, phi=phi, refine={"sweeps": args.sweeps})
+            torch.cuda.synchronize()
+        print(json.dumps({"factor_only_s": t1 - t0, "steps": args.profile_steps,
+                          "steps_s": time.perf_counter() - t1, "workload": args.workload}))
+        return
 
     def job(prec, lu_tol, sweeps, keep=False):
         op = H.assemble(prob, hp)
@@ -357,7 +395,9 @@ def main():
     prec_tag = {"G": "FP64", "Linv": "FP32", "Uinv": "FP32"}
     mat = dom[dom.index("[") + 1:-1]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": counted_traffic({"gather[G]": "gather_G_traffic_bytes",
+                                            "project[G]": "project_G_traffic_bytes"}.get(dom, "-")),
                 "kernel": ("k_mv_gather" if dom.startswith("gather") else "k_mv_project")
                 + f" ({mat} product, {prec_tag[mat]})",
                 "bytes_per_launch": nbytes, "avg_launch_ms": ms}
