@@ -104,6 +104,10 @@ struct LFlushTarget {
   double* ws;          // workspace of this target
   int32_t* info;       // [0] old rank, [1] new rank, [2] overflow
   int32_t* overflow;   // global overflow counter
+  int32_t borth;       // 1: every term's right factor is a set of unit columns, disjoint
+                       // across the terms (a dense block split by columns), so the
+                       // concatenated B of an empty target has B^T B = I
+  int32_t pad;
 };
 
 struct ChunkItem { int32_t tgt, side, r0, r1, chunk, pad; };

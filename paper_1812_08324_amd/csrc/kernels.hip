@@ -908,14 +908,33 @@ __device__ int pchol_inplace(double* Sh, double* Sl, int K, int ls, int* piv, do
 // Writes the target's info / rank and returns r.
 __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int ks, double* Xh, double* Xl,
                          double* Yh, double* Yl, double* Zh, double* Zl, double* YU, double* YV, int* pivB,
-                         int* pivM, double* sref) {
+                         int* pivM, double* sref, bool b_orth = false) {
   const int tid = threadIdx.x;
   const bool use_dd = tol < 1e-9;
   // 1. G_B = R_B^T R_B; directions below 1e-2 tol of the largest are dropped
   const double cut = fmax(1e-16, 1e-2 * tol);
-  const int rB = pchol_inplace(Xh, Xl, K, ks, pivB, sref, 0, fmax(cut * cut, 1e-32), KMAX, use_dd);
+  int rB;
+  if (b_orth) {
+    // G_B = I (G_B is not formed): the pivoted Cholesky of the identity
+    // selects 0, 1, .. K-1 and leaves R_B = I, so T1 = G_M = G_A
+    for (int e = tid; e < K * K; e += HL_BLOCK) {
+      const int q = e / K, p = e - q * K;
+      Xh[q * ks + p] = q == p ? 1.0 : 0.0;
+      Zh[q * ks + p] = Yh[q * ks + p];
+      if (use_dd) {
+        Xl[q * ks + p] = 0.0;
+        Zl[q * ks + p] = Yl[q * ks + p];
+      }
+    }
+    for (int j = tid; j < K; j += HL_BLOCK) pivB[j] = j;
+    if (tid == 0) sref[0] = 1.0;
+    __syncthreads();
+    rB = K;
+  } else {
+    rB = pchol_inplace(Xh, Xl, K, ks, pivB, sref, 0, fmax(cut * cut, 1e-32), KMAX, use_dd);
+  }
   // 2. T1[q][j] = sum_p G_A[q][p] R_B[j][p]
-  for (int e = tid; e < K * rB; e += HL_BLOCK) {
+  for (int e = tid; e < K * rB && !b_orth; e += HL_BLOCK) {
     const int q = e / rB, j = e - q * rB;
     const double* rb_h = Xh + pivB[j] * ks;
     const double* rb_l = Xl + pivB[j] * ks;
@@ -936,7 +955,7 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
   }
   __syncthreads();
   // G_M[i][j] = sum_p R_B[i][p] T1[p][j]  (overwrites G_A)
-  for (int e = tid; e < rB * rB; e += HL_BLOCK) {
+  for (int e = tid; e < rB * rB && !b_orth; e += HL_BLOCK) {
     const int i = e / rB, j = e - i * rB;
     const double* rb_h = Xh + pivB[i] * ks;
     const double* rb_l = Xl + pivB[i] * ks;
@@ -1415,9 +1434,12 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
         qq[u] = q;
       }
     }
+    // an empty target whose terms are unit-column pieces: G_B = I is known
+    const bool b_orth = T.borth && kC == 0;
+    const int nside = b_orth ? 1 : 2;
     double v[RA_NE];
     radd_fetch_tile(cs, 0, 0, min(64, T.m), K, v);
-    for (int side = 0; side < 2; ++side) {
+    for (int side = 0; side < nside; ++side) {
       const int len = side == 0 ? T.m : T.n;
       double* Gh = side == 0 ? Yh : Xh;
       double* Gl = side == 0 ? Yl : Xl;
@@ -1432,7 +1454,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
           __syncthreads();
           if (base + 64 < len)
             radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
-          else if (side == 0)
+          else if (side + 1 < nside)
             radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
           gram_tiles_add(gt, tile, K, wv, lane);
         }
@@ -1452,7 +1474,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
         // next block: this side's, else the first of the V side
         if (base + 64 < len)
           radd_fetch_tile(cs, side, base + 64, min(64, len - base - 64), K, v);
-        else if (side == 0)
+        else if (side + 1 < nside)
           radd_fetch_tile(cs, 1, 0, min(64, T.n), K, v);
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -1474,7 +1496,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
       }
     }
     __syncthreads();
-    r = radd_core(T, kC, K, tol, ls, Xh, Xl, Yh, Yl, Zh, Zl, YU, YV, pivB, pivM, sref);
+    r = radd_core(T, kC, K, tol, ls, Xh, Xl, Yh, Yl, Zh, Zl, YU, YV, pivB, pivM, sref, b_orth);
     // new factors: U_new = A Y_U, V_new = B Y_V
     radd_fetch_tile(cs, 0, 0, min(64, T.m), K, v);
     for (int side = 0; side < 2; ++side) {

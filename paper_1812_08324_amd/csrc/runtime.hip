@@ -27,15 +27,17 @@ namespace hl {
 
 thread_local std::string g_last_error;
 
-// Optional host-side phase timing on stderr (HLEVY_VERBOSE=1).
-static bool verbose() {
+// Optional host-side phase timing on stderr (HLEVY_VERBOSE=1); level 2
+// also prints the shape of every fused rounded-addition phase as planned.
+static int verbose_level() {
   static int v = -1;
   if (v < 0) {
     const char* e = std::getenv("HLEVY_VERBOSE");
-    v = (e && *e && *e != '0') ? 1 : 0;
+    v = (e && *e >= '1' && *e <= '9') ? *e - '0' : 0;
   }
-  return v == 1;
+  return v;
 }
+static bool verbose() { return verbose_level() >= 1; }
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -572,6 +574,16 @@ struct Builder {
         fused.push_back(q);
         fks = std::max(fks, (tgs[q].Kcap + 15) / 16 * 16);
       }
+    if (!fused.empty() && verbose_level() >= 2) {
+      int tmax = 0, tsum = 0, mmax = 0;
+      for (size_t q : fused) {
+        tmax = std::max(tmax, (int)tlists[q].size());
+        tsum += (int)tlists[q].size();
+        mmax = std::max(mmax, std::max(tgs[q].m, tgs[q].n));
+      }
+      std::fprintf(stderr, "[hlevy] radd phase: targets %zu terms max %d mean %.1f rows<= %d\n", fused.size(),
+                   tmax, (double)tsum / fused.size(), mmax);
+    }
     if (!fused.empty()) {
       Phase ph{PH_RADD, (int)P.ltg.size(), (int)fused.size(), 0, 0, 0, 0, ftol, fks};
       for (size_t q : fused) {
@@ -722,6 +734,7 @@ struct Builder {
           LFlushTarget T = c.T;
           T.rank = nullptr;
           T.Kcap = 48;
+          T.borth = 1;
           const int w = c.kc <= 16 ? 32 : 16;
           std::vector<Term> terms;
           for (int c0 = 0; c0 < c.src.nc; c0 += w) {
@@ -1559,6 +1572,7 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
           T.n = d.n;
           T.kcap = d.kcap;
           T.Kcap = 48;
+          T.borth = 1;
           std::vector<Term> terms;
           const int w = d.kcap <= 16 ? 32 : 16;   // kcap + w <= 48
           if (d.kcap > 32) throw DeviceError("internal: rank capacity above 32");
