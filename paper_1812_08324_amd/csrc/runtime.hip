@@ -733,7 +733,9 @@ struct Builder {
         for (auto& c : comps) {
           LFlushTarget T = c.T;
           T.rank = nullptr;
-          T.Kcap = 48;
+          // one concatenation takes the whole block when the fused kernel
+          // is 64 columns wide (no double-double parts)
+          T.Kcap = fused_width(tol);
           T.borth = 1;
           const int w = c.kc <= 16 ? 32 : 16;
           std::vector<Term> terms;
@@ -1553,8 +1555,9 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
                      /*skip_compress=*/true, false);
     B.copy_end(cb);
     // one target per block with its dense content as 32-column terms (the
-    // fused rounded addition takes them one concatenation at a time; the
-    // targets start at rank 0)
+    // targets start at rank 0; without double-double parts a 64-column
+    // block is one concatenation, with them the fused kernel takes the
+    // pieces in two)
     std::vector<LFlushTarget> tgs;
     std::vector<std::vector<Term>> tl;
     for (size_t q = 0; q < fs.size(); ++q)
@@ -1571,7 +1574,7 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
           T.m = d.m;
           T.n = d.n;
           T.kcap = d.kcap;
-          T.Kcap = 48;
+          T.Kcap = fused_width(lu_tol);
           T.borth = 1;
           std::vector<Term> terms;
           const int w = d.kcap <= 16 ? 32 : 16;   // kcap + w <= 48
