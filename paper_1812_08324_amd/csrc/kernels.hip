@@ -1533,12 +1533,12 @@ __host__ __device__ inline size_t radd_fused_lds(int ks, bool dd_parts = true) {
 // ---------------------------------------------------------------------------
 // dense targets, products, copies, leaf factorisation
 // ---------------------------------------------------------------------------
-// Dense target (at most 64 x 64): D += sum of its terms.  Thread (ty, tx)
-// of the 16 x 16 grid accumulates rows 4 ty .. 4 ty + 3 and columns
-// 4 tx .. 4 tx + 3 in registers.  Product and low-rank terms are taken in
-// 32-column slices of the inner dimension staged in LDS at target
-// positions (zero outside the term's rows / columns), the next slice
-// fetched into registers while the current one is used.
+// Dense target (at most 64 x 64): D += sum of its terms, accumulated in
+// the matrix-core registers of four 32 x 32 quadrants (one per wavefront).
+// Product and low-rank terms are taken in 32-column slices of the inner
+// dimension staged in LDS at target positions (zero outside the term's rows
+// / columns), the next slice fetched into registers while the current one
+// is used.
 constexpr int DF_KC = 32;
 constexpr int DF_NE = 2 * 64 * DF_KC / HL_BLOCK;   // staged values per thread and slice
 
@@ -1575,29 +1575,62 @@ __device__ __forceinline__ void df_fetch(const Term& tm, int kin, int q0, double
   }
 }
 
+// 64 x 64 block products on the matrix cores: wavefront wv of a 256-thread
+// block owns the 32 x 32 quadrant of row tiles 2 (wv >> 1) + {0, 1} and
+// column tiles 2 (wv & 1) + {0, 1}; acc[a][b][v] is C[i][j] with
+// i = 16 (2 (wv >> 1) + a) + 4 v + lane / 16, j = 16 (2 (wv & 1) + b) + lane % 16.
+// One step of v_mfma_f64_16x16x4f64 per tile and 4 inner indices, with
+// A(i, q) at As[i + 64 q] in lane i % 16 + 16 (q % 4) and B(q, j) at
+// Bs[j + 64 q] in lane j % 16 + 16 (q % 4).
+struct Quad64 {
+  double4v acc[2][2];
+};
+__device__ __forceinline__ int quad_row(int wv, int a, int v, int lane) {
+  return 16 * (2 * (wv >> 1) + a) + 4 * v + (lane >> 4);
+}
+__device__ __forceinline__ int quad_col(int wv, int b, int lane) { return 16 * (2 * (wv & 1) + b) + (lane & 15); }
+// C += A(:, 0 .. 4 n4) B(0 .. 4 n4, :) from the staged operands
+__device__ __forceinline__ void quad_mma(Quad64& Q, const double* As, const double* Bs, int n4, int wv,
+                                         int lane) {
+  const double* pa = As + 32 * (wv >> 1) + (lane & 15) + 64 * (lane >> 4);
+  const double* pb = Bs + 32 * (wv & 1) + (lane & 15) + 64 * (lane >> 4);
+  for (int kk = 0; kk < n4; ++kk) {
+    const double a0 = pa[256 * kk], a1 = pa[256 * kk + 16];
+    const double b0 = pb[256 * kk], b1 = pb[256 * kk + 16];
+    Q.acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, Q.acc[0][0], 0, 0, 0);
+    Q.acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, Q.acc[0][1], 0, 0, 0);
+    Q.acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, Q.acc[1][0], 0, 0, 0);
+    Q.acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, Q.acc[1][1], 0, 0, 0);
+  }
+}
+
 __global__ void __launch_bounds__(HL_BLOCK) k_flush_dense(const DFlushItem* items, const Term* terms) {
   __shared__ double As[DF_KC * 64], Bs[DF_KC * 64];   // A(i, q) at i + 64 q, B(q, j) at j + 64 q
   const DFlushItem it = items[blockIdx.x];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const int i0 = ty * 4, j0 = tx * 4;
-  double acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  Quad64 Q;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = i0 + r, j = j0 + c;
-      acc[r][c] = (i < it.m && j < it.n) ? it.D[i + (size_t)it.ldd * j] : 0.0;
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = quad_row(wv, a, v, lane), j = quad_col(wv, b, lane);
+        Q.acc[a][b][v] = (i < it.m && j < it.n) ? it.D[i + (size_t)it.ldd * j] : 0.0;
+      }
   for (int t = 0; t < it.tcount; ++t) {
     const Term tm = terms[it.tbeg + t];
     if (tm.dense == 1) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int i = i0 + r - tm.ro, j = j0 + c - tm.co;
-          if (i >= 0 && i < tm.mr && j >= 0 && j < tm.nc) acc[r][c] += tm.sign * tm.U[i + (size_t)tm.ldu * j];
-        }
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = quad_row(wv, a, v, lane) - tm.ro, j = quad_col(wv, b, lane) - tm.co;
+            if (i >= 0 && i < tm.mr && j >= 0 && j < tm.nc) Q.acc[a][b][v] += tm.sign * tm.U[i + (size_t)tm.ldu * j];
+          }
       continue;
     }
     const int kin = term_inner(tm);
@@ -1613,41 +1646,52 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_dense(const DFlushItem* item
       }
       __syncthreads();
       if (q0 + DF_KC < kin) df_fetch(tm, kin, q0 + DF_KC, v);
-      const int qn = min(DF_KC, kin - q0);
-      for (int q = 0; q < qn; ++q) {
-        double a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = As[i0 + r + 64 * q];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = Bs[j0 + c + 64 * q];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-      }
+      // inner indices past kin were staged as zeros
+      quad_mma(Q, As, Bs, (min(DF_KC, kin - q0) + 3) / 4, wv, lane);
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = i0 + r, j = j0 + c;
-      if (i < it.m && j < it.n) it.D[i + (size_t)it.ldd * j] = acc[r][c];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = quad_row(wv, a, v, lane), j = quad_col(wv, b, lane);
+        if (i < it.m && j < it.n) it.D[i + (size_t)it.ldd * j] = Q.acc[a][b][v];
+      }
 }
 
+// P = A B for blocks of at most 64 x 64 (inner dimension at most 64), on
+// the matrix cores; the operands are staged zero-padded to 64 x 64
 __global__ void __launch_bounds__(HL_BLOCK) k_dense_prod(const DProdItem* items) {
-  __shared__ double As[64 * 64], Bs[64 * 64];
+  __shared__ double As[64 * 64], Bs[64 * 64];   // A(i, q) at i + 64 q, B(q, j) at j + 64 q
   const DProdItem it = items[blockIdx.x];
-  for (int e = threadIdx.x; e < it.m * it.k; e += HL_BLOCK) As[e] = it.A[(e % it.m) + (size_t)it.lda * (e / it.m)];
-  for (int e = threadIdx.x; e < it.k * it.n; e += HL_BLOCK) Bs[e] = it.B[(e % it.k) + (size_t)it.ldb * (e / it.k)];
-  __syncthreads();
-  for (int e = threadIdx.x; e < it.m * it.n; e += HL_BLOCK) {
-    int i = e % it.m, j = e / it.m;
-    double s = 0.0;
-    for (int q = 0; q < it.k; ++q) s += As[i + it.m * q] * Bs[q + it.k * j];
-    it.P[i + (size_t)it.ldp * j] = s;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < 64 * 64; e += HL_BLOCK) {
+    const int i = e & 63, q = e >> 6;
+    As[e] = (i < it.m && q < it.k) ? it.A[i + (size_t)it.lda * q] : 0.0;
   }
+  for (int e = tid; e < 64 * 64; e += HL_BLOCK) {
+    const int q = e & 63, j = e >> 6;   // coalesced along q in global memory
+    Bs[j + 64 * q] = (q < it.k && j < it.n) ? it.B[q + (size_t)it.ldb * j] : 0.0;
+  }
+  __syncthreads();
+  Quad64 Q;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) Q.acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
+  quad_mma(Q, As, Bs, (it.k + 3) / 4, wv, lane);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = quad_row(wv, a, v, lane), j = quad_col(wv, b, lane);
+        if (i < it.m && j < it.n) it.P[i + (size_t)it.ldp * j] = Q.acc[a][b][v];
+      }
 }
 
 __global__ void __launch_bounds__(HL_BLOCK) k_copy_leaf(const CopyItem* items) {
