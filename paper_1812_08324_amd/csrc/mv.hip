@@ -187,6 +187,19 @@ __device__ __forceinline__ void epilogue(const MvEpi& epi, int r, double v) {
   epi.y[r] = out;
 }
 
+// t_b entry of a low-rank leaf: the sum of its n <= MV_PMAX partials (stride
+// apart) in slot order.  All loads are issued before the first add, so the
+// sum costs one memory round trip instead of n; the masked slots add zeros.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, int stride) {
+  double v[MV_PMAX];
+#pragma unroll
+  for (int c = 0; c < MV_PMAX; ++c) v[c] = c < n ? p[(size_t)c * stride] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < MV_PMAX; ++c) s += v[c];
+  return s;
+}
+
 template <int KB, int GW = MV_GW>
 struct GatherLds {
   double red[GW][64];
@@ -222,10 +235,7 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
       const int e = it / KB, q = it % KB;
       const MvEntry& E = se[e];
       double s = 0.0;   // zero past the rank: the products below multiply by it
-      if (E.kind != 0 && q < E.k) {
-        const double* p = part + (size_t)E.slot * KB + q;
-        for (int c = 0; c < E.n; ++c) s += p[(size_t)c * KB];
-      }
+      if (E.kind != 0 && q < E.k) s = sum_partials(part + (size_t)E.slot * KB + q, E.n, KB);
       ts[it] = s;
     }
     __syncthreads();
@@ -469,10 +479,8 @@ __global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __res
       const int e = rem / KB, q = rem % KB;
       const MvEntry& En = L.se[e];
       double s = 0.0;
-      if ((mask >> r & 1u) && En.kind != 0 && q < En.k) {
-        const double* p = P.part[r] + (size_t)En.slot * KB + q;
-        for (int c = 0; c < En.n; ++c) s += p[(size_t)c * KB];
-      }
+      if ((mask >> r & 1u) && En.kind != 0 && q < En.k)
+        s = sum_partials(P.part[r] + (size_t)En.slot * KB + q, En.n, KB);
       L.ts[r][rem] = s;
     }
     __syncthreads();
