@@ -1170,13 +1170,19 @@ struct MvPlan {
         MvEntry E{};
         int64_t bytes = 0;
         if (d.kind == K_DENSE) {
-          E.kind = 0;
-          E.n = d.n;
-          E.xoff = d.clo;
-          E.ld = d.m;
-          const double* p = d.A + (c.lo - d.rlo);
-          E.ptr = dense_f32 ? fptr(p) : (const void*)p;
-          bytes = (int64_t)d.n * d_elt;
+          // pieces of MV_DCOLS columns: the wavefronts of the gather share
+          // a dense leaf instead of one of them streaming all its columns
+          for (int c0 = 0; c0 < d.n; c0 += MV_DCOLS) {
+            MvEntry D{};
+            D.kind = 0;
+            D.n = std::min(MV_DCOLS, d.n - c0);
+            D.xoff = d.clo + c0;
+            D.ld = d.m;
+            const double* p = d.A + (c.lo - d.rlo) + (size_t)d.m * c0;
+            D.ptr = dense_f32 ? fptr(p) : (const void*)p;
+            row.emplace_back((int64_t)D.n * d_elt, D);
+          }
+          continue;
         } else if (d.kind == K_LR && rk[l] > 0) {
           const bool f32 = leaf_f32(d);
           E.kind = f32 ? 2 : 1;
