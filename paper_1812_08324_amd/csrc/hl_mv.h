@@ -7,7 +7,7 @@
 
 namespace hl {
 
-constexpr int MV_PMAX = 16;   // at most this many projection tiles (partials) per low-rank leaf
+constexpr int MV_PMAX = 32;   // at most this many projection tiles (partials) per low-rank leaf
 constexpr int MV_EMAX = 128;  // entries staged in LDS per gather round
 constexpr int MV_DCOLS = 16;  // columns per dense gather entry (a dense leaf is split into such pieces)
 

@@ -83,10 +83,9 @@ constexpr int rows_per_lane() {
 
 // one projection tile (V in precision TL): the k partial sums of the
 // wavefront's rows, written to the tile's slot
-template <typename TL, int KB, int SB = KB>
+template <typename TL, int KB, int SB = KB, int RPL = rows_per_lane<TL, KB>()>
 __device__ __forceinline__ void project_tile(const MvTile& T, const double* __restrict__ x, double* __restrict__ part,
                                              int lane) {
-  constexpr int RPL = rows_per_lane<TL, KB>();
   const gptr<TL> V = wuni_ptr<TL>(T.V);
   const double* __restrict__ xs = x + T.xoff;
   double acc[KB];
@@ -123,10 +122,13 @@ __device__ __forceinline__ void project_tile(const MvTile& T, const double* __re
 template <int KB, int SB = KB>
 __device__ __forceinline__ void project_any(const MvTile& T, const double* __restrict__ x,
                                             double* __restrict__ part, int lane) {
-  if (wuni(T.f32))
-    project_tile<float, KB, SB>(T, x, part, lane);
+  // tiles of at most 64 rows (leaves of the finest level) take one row per
+  // lane: the full pass would load RPL - 1 rows that are never used
+  const bool f32 = wuni(T.f32), short_tile = wuni(T.n) <= 64;
+  if (f32)
+    short_tile ? project_tile<float, KB, SB, 1>(T, x, part, lane) : project_tile<float, KB, SB>(T, x, part, lane);
   else
-    project_tile<double, KB, SB>(T, x, part, lane);
+    short_tile ? project_tile<double, KB, SB, 1>(T, x, part, lane) : project_tile<double, KB, SB>(T, x, part, lane);
 }
 
 // KB: columns per wavefront (registers); SB: partial slot stride (the
