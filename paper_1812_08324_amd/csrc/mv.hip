@@ -9,11 +9,11 @@
 //     sums across the 64 lanes with k + log steps instead of 6 k.  The k
 //     partial sums of the tile go to its slot of the partial buffer.
 //  2. k_mv_gather: one workgroup per leaf cluster rho (owner computes):
-//     y_rho = sum_dense D x + sum_lowrank U[rho, :] t_b.  The entry list is
-//     staged in LDS, t_b = sum of the leaf's partials is formed in LDS in a
-//     fixed order, the wavefronts take entries round-robin (the host sorts
-//     each list by bytes), then reduce in LDS and apply the Crank-Nicolson
-//     epilogue.
+//     y_rho = sum_dense D x + sum_lowrank U[rho, :] t_b.  The wavefronts take
+//     entries round-robin (the host sorts each list by bytes and splits dense
+//     leaves into 16-column pieces); a wavefront forms t_b = sum of the
+//     leaf's partials in a fixed order itself, with its U loads in flight.
+//     The wavefronts reduce in LDS and apply the Crank-Nicolson epilogue.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -144,20 +144,6 @@ __global__ void __launch_bounds__(256) k_mv_project(const MvTile* __restrict__ t
 
 constexpr int MV_GW = 8;   // wavefronts per gather workgroup
 
-template <typename TL, int KB>
-__device__ __forceinline__ double gather_lowrank(const void* p, int ii, int ld, int ek, const double* t) {
-  const gptr<TL> U = wuni_ptr<TL>(p);
-  // unconditional loads (columns past the rank re-read column k-1 and meet
-  // t = 0), so all of them are in flight together
-  double uv[KB];
-#pragma unroll
-  for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < KB; ++q) acc += uv[q] * t[q];
-  return acc;
-}
-
 // y[r] = epilogue of the product's row value v (see MvEpi)
 __device__ __forceinline__ void epilogue(const MvEpi& epi, int r, double v) {
   double out;
@@ -190,84 +176,108 @@ __device__ __forceinline__ void epilogue(const MvEpi& epi, int r, double v) {
 }
 
 // t_b entry of a low-rank leaf: the sum of its n <= MV_PMAX partials (stride
-// apart) in slot order.  All loads are issued before the first add, so the
-// sum costs one memory round trip instead of n; the masked slots add zeros.
+// apart) in slot order.  The loads of 16 slots are issued before their
+// adds, so the sum costs one memory round trip per 16 partials instead of
+// one per partial; the masked slots add zeros.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, int stride) {
-  double v[MV_PMAX];
-#pragma unroll
-  for (int c = 0; c < MV_PMAX; ++c) v[c] = c < n ? p[(size_t)c * stride] : 0.0;
   double s = 0.0;
+  for (int c0 = 0; c0 < n; c0 += 16) {
+    double v[16];
 #pragma unroll
-  for (int c = 0; c < MV_PMAX; ++c) s += v[c];
+    for (int u = 0; u < 16; ++u) v[u] = c0 + u < n ? p[(size_t)(c0 + u) * stride] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
   return s;
 }
 
-template <int KB, int GW = MV_GW>
+template <int GW = MV_GW>
 struct GatherLds {
   double red[GW][64];
-  MvEntry se[MV_EMAX];
-  double ts[MV_EMAX * KB];
 };
 
-// one leaf cluster: y[R] = epilogue(sum over the entries of R)
+// U rows of a low-rank entry times t_b, t_b formed by the wavefront itself
+// while its U loads are in flight: lane (q, g) = q + KB g sums the partials
+// g PPG .. g PPG + PPG - 1 of column q in slot order, a butterfly over the
+// groups g gives every lane of column q the same total (the tree order is
+// fixed), and the products are summed over q in order.
+template <typename TL, int KB>
+__device__ __forceinline__ double gather_lowrank_self(const MvEntry& E, int ii, int lane,
+                                                      const double* __restrict__ part) {
+  constexpr int NG = 64 / KB, PPG = MV_PMAX / NG;
+  static_assert(MV_PMAX % NG == 0, "partials per group");
+  const int ek = wuni(E.k), ld = wuni(E.ld), en = wuni(E.n);
+  const gptr<TL> U = wuni_ptr<TL>(E.ptr);
+  double uv[KB];
+#pragma unroll
+  for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
+  const int q = lane % KB, c0 = (lane / KB) * PPG;
+  const double* pp = part + (size_t)wuni(E.slot) * KB + q;
+  double t = 0.0;   // zero past the rank: the products below multiply by it
+  constexpr int PC = PPG < 8 ? PPG : 8;   // loads in flight per chunk (registers)
+#pragma unroll
+  for (int u0 = 0; u0 < PPG; u0 += PC) {
+    double pv[PC];
+#pragma unroll
+    for (int u = 0; u < PC; ++u) {
+      const int c = c0 + u0 + u;
+      pv[u] = (q < ek && c < en) ? pp[(size_t)c * KB] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PC; ++u) t += pv[u];
+  }
+#pragma unroll
+  for (int o = KB; o < 64; o <<= 1) t += __shfl_xor(t, o, 64);
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) acc += uv[k] * bcast_lane(t, k);
+  return acc;
+}
+
+// one leaf cluster: y[R] = epilogue(sum over the entries of R).  Wavefront
+// g takes entries g, g + GW, ... straight from the entry list (wavefront-
+// uniform loads, the next descriptor fetched while the current entry is
+// processed); no barrier until the final reduction across wavefronts.
 template <typename TD, int KB, int GW = MV_GW>
 __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __restrict__ ents,
                                             const double* __restrict__ x, const double* __restrict__ part,
-                                            const MvEpi& epi, GatherLds<KB, GW>& L) {
-  auto& red = L.red;
-  auto& se = L.se;
-  auto& ts = L.ts;
+                                            const MvEpi& epi, GatherLds<GW>& L) {
   const int i = threadIdx.x & 63, g = wuni(threadIdx.x >> 6);
   const int mr = R.hi - R.lo;
   const int ii = i < mr ? i : mr - 1;   // clamped row: loads stay in bounds, result discarded
+  const int eend = wuni(R.eend);
   double acc = 0.0;
-  for (int base = R.ebeg; base < R.eend; base += MV_EMAX) {
-    const int cnt = min(MV_EMAX, R.eend - base);
-    __syncthreads();
-    {
-      // stage the entry list (8-byte words) in LDS
-      const long long* src = reinterpret_cast<const long long*>(ents + base);
-      long long* dst = reinterpret_cast<long long*>(se);
-      const int words = cnt * (int)(sizeof(MvEntry) / 8);
-      for (int e = threadIdx.x; e < words; e += 64 * GW) dst[e] = src[e];
-    }
-    __syncthreads();
-    // t_b of the low-rank entries: sum of the leaf's partials, in slot order
-    for (int it = threadIdx.x; it < cnt * KB; it += 64 * GW) {
-      const int e = it / KB, q = it % KB;
-      const MvEntry& E = se[e];
-      double s = 0.0;   // zero past the rank: the products below multiply by it
-      if (E.kind != 0 && q < E.k) s = sum_partials(part + (size_t)E.slot * KB + q, E.n, KB);
-      ts[it] = s;
-    }
-    __syncthreads();
-    for (int e = g; e < cnt; e += GW) {
-      const int kind = wuni(se[e].kind), en = wuni(se[e].n), ek = wuni(se[e].k), ld = wuni(se[e].ld);
-      if (kind == 0) {
-        const gptr<TD> D = wuni_ptr<TD>(se[e].ptr);
-        const double xl = i < en ? x[wuni(se[e].xoff) + i] : 0.0;
-        int j = 0;
-        for (; j + 16 <= en; j += 16) {
-          double dv[16];
+  int e = wuni(R.ebeg) + g;
+  MvEntry En{};
+  if (e < eend) En = ents[e];
+  for (; e < eend; e += GW) {
+    const MvEntry E = En;
+    if (e + GW < eend) En = ents[e + GW];
+    const int kind = wuni(E.kind), en = wuni(E.n), ld = wuni(E.ld);
+    if (kind == 0) {
+      const gptr<TD> D = wuni_ptr<TD>(E.ptr);
+      const double xl = i < en ? x[wuni(E.xoff) + i] : 0.0;
+      int j = 0;
+      for (; j + 16 <= en; j += 16) {
+        double dv[16];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) dv[q] = (double)D[(unsigned)(ii + ld * (j + q))];
+        for (int q = 0; q < 16; ++q) dv[q] = (double)D[(unsigned)(ii + ld * (j + q))];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) acc += dv[q] * bcast_lane(xl, j + q);
-        }
-        for (; j < en; ++j) acc += (double)D[(unsigned)(ii + ld * j)] * bcast_lane(xl, j);
-      } else if (kind == 1) {
-        acc += gather_lowrank<double, KB>(se[e].ptr, ii, ld, ek, ts + e * KB);
-      } else {
-        acc += gather_lowrank<float, KB>(se[e].ptr, ii, ld, ek, ts + e * KB);
+        for (int q = 0; q < 16; ++q) acc += dv[q] * bcast_lane(xl, j + q);
       }
+      for (; j < en; ++j) acc += (double)D[(unsigned)(ii + ld * j)] * bcast_lane(xl, j);
+    } else if (kind == 1) {
+      acc += gather_lowrank_self<double, KB>(E, ii, i, part);
+    } else {
+      acc += gather_lowrank_self<float, KB>(E, ii, i, part);
     }
   }
-  red[g][i] = acc;
+  L.red[g][i] = acc;
   __syncthreads();
   if (g == 0 && i < mr) {
     double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < GW; w += 2) v += red[w][i] + red[w + 1][i];
+    for (int w = 0; w < GW; w += 2) v += L.red[w][i] + L.red[w + 1][i];
     epilogue(epi, R.lo + i, v);
   }
 }
@@ -277,7 +287,7 @@ __global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restric
                                                           const MvEntry* __restrict__ ents,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ part, MvEpi epi) {
-  __shared__ GatherLds<KB> L;
+  __shared__ GatherLds<> L;
   const MvRow R = rows[blockIdx.x];
   gather_rows<TD, KB>(R, ents, x, part, epi, L);
 }
