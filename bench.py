@@ -26,6 +26,8 @@ WORKLOADS = {
     "tempered1d_n65536": dict(kind="config2", n=65536, steps=1000),
     "tempered1d_n16384": dict(kind="config2", n=16384, steps=1000),
     "frac1d_n1024": dict(kind="config1", n=1024, steps=100),
+    # counter profiling only (--factor-only); the 2D measurement is bench_2d
+    "frac2d_s0.75_256x256": dict(kind="config3", n=256, steps=200),
 }
 
 
@@ -63,6 +65,8 @@ def make_workload(name):
     spec = WORKLOADS[name]
     if spec["kind"] == "config2":
         return W.config2(n=spec["n"], steps=spec["steps"])
+    if spec["kind"] == "config3":
+        return W.config3(s=0.75, n=spec["n"])
     return W.config1(n=spec["n"], steps=spec["steps"])
 
 
@@ -298,8 +302,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = make_workload(args.workload)
+    two_d = WORKLOADS[args.workload]["kind"] == "config3"
+    if two_d and not args.factor_only:
+        print(f"{args.workload} is measured by the 2D leg of the default run; here only with --factor-only",
+              file=sys.stderr)
+        sys.exit(2)
     prob = H.make_problem(w.dim, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
-    hp = H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol, max_rank=args.max_rank)
+    hp = H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol,
+                        max_rank=w.max_rank if two_d else args.max_rank)
     u0 = torch.tensor(w.u0, dtype=torch.float64, device="cuda")
     g = torch.tensor(w.g, dtype=torch.float64, device="cuda") if w.g is not None else None
     phi = list(w.phi) if w.phi is not None else None

@@ -20,7 +20,10 @@ hipError_t launch_dense_prod(const DProdItem* items, int n, hipStream_t s);
 hipError_t launch_copy(const CopyItem* items, int n, hipStream_t s);
 hipError_t launch_getrf_inv(const GetrfItem* items, int n, int32_t* zero_pivot, hipStream_t s);
 // whole rounded additions (targets of at most GRAM_CHUNK rows per side, ks <= 48)
-hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s);
+// the fused rounded additions of tg and, in the same launch, the dense
+// flushes dflush (independent leaves of the same batch)
+hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s,
+                             const DFlushItem* dflush = nullptr, int ndflush = 0, const Term* dterms = nullptr);
 hipError_t launch_lu_inv(const LuInvItem* items, int n, int32_t* zero_pivot, hipStream_t s);
 hipError_t launch_apply(const ApplyJob* jobs, const ProjItem* proj, int nproj, const GatherItem* gat,
                         int ngat, hipStream_t s);

@@ -1364,10 +1364,9 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_expand(const LFlushTarget* t
 // each one a rounded addition into the target: Gram matrices straight from
 // the factors, radd_core, then the new factors in place, 64 rows at a time
 // (a row block is staged in LDS before any of its rows is overwritten).
-// Dynamic LDS: radd_fused_lds(ks).
-__global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg, const Term* terms, double tol,
-                                                         int ks) {
-  extern __shared__ double smem[];
+// smem: radd_fused_lds(ks) bytes of dynamic LDS.
+__device__ __forceinline__ void radd_fused_target(const LFlushTarget& T, const Term* terms, double tol, int ks,
+                                                  double* smem) {
   const int ls = ks + 1;   // row stride of the LDS matrices
   const bool use_dd = radd_needs_dd(tol);
   // with double-double parts: X, Y, Z high and low (the 64 x K tile of a
@@ -1398,7 +1397,6 @@ __global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg,
   __shared__ RaddCols cs;
   __shared__ int pivB[KMAX], pivM[KMAX];
   __shared__ double sref[2];
-  const LFlushTarget T = tg[blockIdx.x];
   const int tid = threadIdx.x;
   constexpr int PPT = (KMAX * (KMAX + 1) / 2 + HL_BLOCK - 1) / HL_BLOCK;
   int r = T.rank ? *T.rank : 0;
@@ -1604,9 +1602,8 @@ __device__ __forceinline__ void quad_mma(Quad64& Q, const double* As, const doub
   }
 }
 
-__global__ void __launch_bounds__(HL_BLOCK) k_flush_dense(const DFlushItem* items, const Term* terms) {
-  __shared__ double As[DF_KC * 64], Bs[DF_KC * 64];   // A(i, q) at i + 64 q, B(q, j) at j + 64 q
-  const DFlushItem it = items[blockIdx.x];
+// As, Bs: DF_KC * 64 doubles each of LDS, A(i, q) at i + 64 q, B(q, j) at j + 64 q
+__device__ __forceinline__ void flush_dense_item(const DFlushItem& it, const Term* terms, double* As, double* Bs) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   Quad64 Q;
@@ -1659,6 +1656,26 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_dense(const DFlushItem* item
         const int i = quad_row(wv, a, v, lane), j = quad_col(wv, b, lane);
         if (i < it.m && j < it.n) it.D[i + (size_t)it.ldd * j] = Q.acc[a][b][v];
       }
+}
+
+__global__ void __launch_bounds__(HL_BLOCK) k_flush_dense(const DFlushItem* items, const Term* terms) {
+  __shared__ double As[DF_KC * 64], Bs[DF_KC * 64];
+  flush_dense_item(items[blockIdx.x], terms, As, Bs);
+}
+
+// The fused rounded additions of a batch (blocks 0 .. ntg-1) and, in the
+// same launch, the batch's dense-target flushes (blocks ntg ..): the two
+// write disjoint leaves and read none of each other's, so they overlap
+// instead of running back to back.  Dynamic LDS: radd_fused_dyn_lds(ks, tol).
+__global__ void __launch_bounds__(HL_BLOCK) k_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms,
+                                                         double tol, int ks, const DFlushItem* dfl,
+                                                         const Term* dterms) {
+  extern __shared__ double smem[];
+  if ((int)blockIdx.x >= ntg) {
+    flush_dense_item(dfl[blockIdx.x - ntg], dterms, smem, smem + DF_KC * 64);
+    return;
+  }
+  radd_fused_target(tg[blockIdx.x], terms, tol, ks, smem);
 }
 
 // P = A B for blocks of at most 64 x 64 (inner dimension at most 64), on
@@ -2162,12 +2179,16 @@ hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, c
   hipLaunchKernelGGL(k_flush_expand, dim3(nexp), dim3(HL_BLOCK), 0, s, tg, terms, expand);
   return post();
 }
-hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s) {
-  if (ntg == 0) return hipSuccess;
+static size_t radd_fused_dyn_lds(int k, double tol) {
+  return std::max(radd_fused_lds(k, radd_needs_dd(tol)), (size_t)2 * DF_KC * 64 * sizeof(double));
+}
+hipError_t launch_radd_fused(const LFlushTarget* tg, int ntg, const Term* terms, double tol, int ks, hipStream_t s,
+                             const DFlushItem* dflush, int ndflush, const Term* dterms) {
+  if (ntg == 0 && ndflush == 0) return hipSuccess;
   if (ks > fused_width(tol)) return hipErrorInvalidValue;
   const int k = ks < 32 ? 32 : ks;
-  hipLaunchKernelGGL(k_radd_fused, dim3(ntg), dim3(HL_BLOCK), radd_fused_lds(k, radd_needs_dd(tol)), s, tg, terms,
-                     tol, k);
+  hipLaunchKernelGGL(k_radd_fused, dim3(ntg + ndflush), dim3(HL_BLOCK), radd_fused_dyn_lds(k, tol), s, tg, ntg,
+                     terms, tol, k, dflush, dterms);
   return post();
 }
 hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms, hipStream_t s) {

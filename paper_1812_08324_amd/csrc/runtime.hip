@@ -353,7 +353,9 @@ struct Plan {
           HL_CHECK(launch_getrf_inv(dgetrf.as<GetrfItem>() + p.b0, p.n0, zero_pivot, s));
           break;
         case PH_RADD:
-          HL_CHECK(launch_radd_fused(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(), p.tol, p.ks, s));
+          // b1, n1: dense flushes of the same batch that share the launch
+          HL_CHECK(launch_radd_fused(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(), p.tol, p.ks, s,
+                                     ddflush.as<DFlushItem>() + p.b1, p.n1, dterms.as<Term>()));
           break;
         case PH_LUINV:
           HL_CHECK(launch_lu_inv(dluinv.as<LuInvItem>() + p.b0, p.n0, zero_pivot, s));
@@ -785,9 +787,10 @@ struct Builder {
         }
       }
     }
-    // 4. dense targets
+    // 4. dense targets: their flushes join the first fused rounded-addition
+    //    launch of step 5 (disjoint leaves), else get a phase of their own
+    Phase dph{PH_DFLUSH, (int)P.dflush.size(), 0, 0, 0, 0, 0, 0.0};
     {
-      Phase ph{PH_DFLUSH, (int)P.dflush.size(), 0, 0, 0, 0, 0, 0.0};
       for (auto& kv : pending) {
         HMat* C = kv.first.first;
         const LeafDesc& d = C->L[kv.first.second];
@@ -796,9 +799,9 @@ struct Builder {
         for (auto& pt : kv.second) P.terms.push_back(pt.t);
         P.dflush.push_back(it);
       }
-      ph.n0 = (int)P.dflush.size() - ph.b0;
-      if (ph.n0) P.ph.push_back(ph);
+      dph.n0 = (int)P.dflush.size() - dph.b0;
     }
+    const size_t ph_lr0 = P.ph.size();
     // 5. low-rank targets: rounded additions, terms split so that the
     //    concatenated width stays within KMAX
     {
@@ -883,6 +886,14 @@ struct Builder {
           tl.push_back(e.second);
         }
         emit_lflush(tgs, tl, tol);
+      }
+    }
+    if (dph.n0) {
+      if (P.ph.size() > ph_lr0 && P.ph[ph_lr0].type == PH_RADD) {
+        P.ph[ph_lr0].b1 = dph.b0;
+        P.ph[ph_lr0].n1 = dph.n0;
+      } else {
+        P.ph.insert(P.ph.begin() + ph_lr0, dph);
       }
     }
     bjobs.clear();
