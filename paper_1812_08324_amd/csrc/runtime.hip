@@ -295,8 +295,30 @@ struct Phase {
   int type;
   int b0, n0, b1, n1, b2, n2;
   double tol;
-  int ks;   // PH_LFLUSH: LDS stride, >= the widest concatenation of the phase
+  int ks;        // PH_LFLUSH: LDS stride, >= the widest concatenation of the phase
+  int par = 0;   // PH_RADD: the next `par` phases touch none of its leaves
 };
+
+// A second stream (default priority) and two events per device and host
+// thread, kept for the life of the thread: a fused rounded-addition launch
+// runs there while the independent phases after it run on the caller's
+// stream (one set per thread, so concurrent callers never share events).
+struct ForkJoin {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+static ForkJoin& fork_join() {
+  static thread_local std::map<int, ForkJoin> per_device;
+  int dev = 0;
+  HL_CHECK(hipGetDevice(&dev));
+  ForkJoin& f = per_device[dev];
+  if (!f.side) {
+    HL_CHECK(hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking));
+    HL_CHECK(hipEventCreateWithFlags(&f.fork, hipEventDisableTiming));
+    HL_CHECK(hipEventCreateWithFlags(&f.join, hipEventDisableTiming));
+  }
+  return f;
+}
 
 struct Plan {
   std::vector<Phase> ph;
@@ -329,7 +351,36 @@ struct Plan {
   }
 
   void run(int32_t* zero_pivot, hipStream_t s) const {
-    for (const Phase& p : ph) {
+    // a PH_RADD phase with par > 0 goes to the side stream; the join waits
+    // after the par phases that follow it
+    size_t join_at = (size_t)-1;
+    ForkJoin* fj = nullptr;
+    for (size_t q = 0; q < ph.size(); ++q) {
+      if (q == join_at) {
+        HL_CHECK(hipEventRecord(fj->join, fj->side));
+        HL_CHECK(hipStreamWaitEvent(s, fj->join, 0));
+        join_at = (size_t)-1;
+      }
+      const Phase& p = ph[q];
+      if (p.type == PH_RADD && p.par > 0 && join_at == (size_t)-1) {
+        fj = &fork_join();
+        HL_CHECK(hipEventRecord(fj->fork, s));
+        HL_CHECK(hipStreamWaitEvent(fj->side, fj->fork, 0));
+        HL_CHECK(launch_radd_fused(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(), p.tol, p.ks, fj->side,
+                                   ddflush.as<DFlushItem>() + p.b1, p.n1, dterms.as<Term>()));
+        join_at = q + 1 + (size_t)p.par;
+        continue;
+      }
+      run_phase(p, zero_pivot, s);
+    }
+    if (join_at != (size_t)-1) {
+      HL_CHECK(hipEventRecord(fj->join, fj->side));
+      HL_CHECK(hipStreamWaitEvent(s, fj->join, 0));
+    }
+  }
+
+  void run_phase(const Phase& p, int32_t* zero_pivot, hipStream_t s) const {
+    {
       switch (p.type) {
         case PH_APPLY:
           HL_CHECK(launch_apply(djobs.as<ApplyJob>(), dproj.as<ProjItem>() + p.b0, p.n0,
@@ -802,10 +853,13 @@ struct Builder {
       dph.n0 = (int)P.dflush.size() - dph.b0;
     }
     const size_t ph_lr0 = P.ph.size();
+    bool has_fused = false;
     // 5. low-rank targets: rounded additions, terms split so that the
     //    concatenated width stays within KMAX
     {
-      std::vector<std::vector<std::pair<LFlushTarget, std::vector<Term>>>> rounds;
+      // whole-list fused targets first, in a launch of their own (it may
+      // overlap the rounds of the other targets), then the rounds
+      std::vector<std::vector<std::pair<LFlushTarget, std::vector<Term>>>> rounds(1);
       for (auto& kv : pending) {
         HMat* C = kv.first.first;
         int leaf = kv.first.second;
@@ -824,7 +878,6 @@ struct Builder {
           T.Kcap = fused_width(tol);
           std::vector<Term> tl;
           for (auto& pt : kv.second) tl.push_back(pt.t);
-          if (rounds.empty()) rounds.resize(1);
           rounds[0].push_back({T, tl});
           continue;
         }
@@ -873,12 +926,14 @@ struct Builder {
           }
           if (K > KMAX) throw DeviceError("internal: term wider than a rounded addition");
           T.Kcap = K;
-          if (rounds.size() <= rd) rounds.resize(rd + 1);
-          rounds[rd].push_back({T, tl});
+          if (rounds.size() <= rd + 1) rounds.resize(rd + 2);
+          rounds[rd + 1].push_back({T, tl});
           ++rd;
         }
       }
+      has_fused = !rounds[0].empty();
       for (auto& r : rounds) {
+        if (r.empty()) continue;
         std::vector<LFlushTarget> tgs;
         std::vector<std::vector<Term>> tl;
         for (auto& e : r) {
@@ -896,6 +951,11 @@ struct Builder {
         P.ph.insert(P.ph.begin() + ph_lr0, dph);
       }
     }
+    // the whole-list fused targets (the first phase of step 5 when there
+    // are any) and the rounds of the other targets write different leaves:
+    // the fused launch overlaps the rounds
+    if (has_fused && P.ph.size() > ph_lr0 + 1)
+      P.ph[ph_lr0].par = (int)(P.ph.size() - ph_lr0 - 1);
     bjobs.clear();
     bjob_mat.clear();
     bdprod.clear();
