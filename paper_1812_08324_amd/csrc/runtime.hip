@@ -296,7 +296,10 @@ struct Phase {
   int b0, n0, b1, n1, b2, n2;
   double tol;
   int ks;        // PH_LFLUSH: LDS stride, >= the widest concatenation of the phase
-  int par = 0;   // PH_RADD: the next `par` phases touch none of its leaves
+  // side > 0: this phase and the next side - 1 run on the side stream, and
+  // the par phases after them (on the caller's stream) touch none of their
+  // data; the streams join after those
+  int side = 0, par = 0;
 };
 
 // A second stream (default priority) and two events per device and host
@@ -362,13 +365,13 @@ struct Plan {
         join_at = (size_t)-1;
       }
       const Phase& p = ph[q];
-      if (p.type == PH_RADD && p.par > 0 && join_at == (size_t)-1) {
+      if (p.side > 0 && p.par > 0 && join_at == (size_t)-1) {
         fj = &fork_join();
         HL_CHECK(hipEventRecord(fj->fork, s));
         HL_CHECK(hipStreamWaitEvent(fj->side, fj->fork, 0));
-        HL_CHECK(launch_radd_fused(dltg.as<LFlushTarget>() + p.b0, p.n0, dterms.as<Term>(), p.tol, p.ks, fj->side,
-                                   ddflush.as<DFlushItem>() + p.b1, p.n1, dterms.as<Term>()));
-        join_at = q + 1 + (size_t)p.par;
+        for (int u = 0; u < p.side; ++u) run_phase(ph[q + u], zero_pivot, fj->side);
+        join_at = q + (size_t)p.side + (size_t)p.par;
+        q += (size_t)p.side - 1;
         continue;
       }
       run_phase(p, zero_pivot, s);
@@ -697,6 +700,7 @@ struct Builder {
 
   void end() {
     // 1. applies (all independent within the batch)
+    const size_t ph_apply = bjobs.empty() ? (size_t)-1 : P.ph.size();
     if (!bjobs.empty()) {
       int jb = (int)P.jobs.size();
       Phase ph{PH_APPLY, (int)P.proj.size(), 0, (int)P.gath.size(), 0, 0, 0, 0.0};
@@ -742,6 +746,7 @@ struct Builder {
         t.W = nullptr;
       }
     }
+    const size_t ph_dprod = bdprod.empty() ? (size_t)-1 : P.ph.size();
     if (!bdprod.empty()) {
       Phase ph{PH_DPROD, (int)P.dprod.size(), (int)bdprod.size(), 0, 0, 0, 0, 0.0};
       for (auto& d : bdprod) P.dprod.push_back(d);
@@ -837,6 +842,15 @@ struct Builder {
           }
         }
       }
+    }
+    // the dense products and their compressions (steps 2-3) use none of the
+    // applies' data (step 1): they run on the side stream while the applies
+    // run, i.e. [products, compressions] forked, then the applies, then join
+    if (ph_apply != (size_t)-1 && ph_dprod == ph_apply + 1) {
+      const int chain = (int)(P.ph.size() - ph_dprod);
+      std::rotate(P.ph.begin() + ph_apply, P.ph.begin() + ph_apply + 1, P.ph.end());
+      P.ph[ph_apply].side = chain;
+      P.ph[ph_apply].par = 1;
     }
     // 4. dense targets: their flushes join the first fused rounded-addition
     //    launch of step 5 (disjoint leaves), else get a phase of their own
@@ -954,8 +968,10 @@ struct Builder {
     // the whole-list fused targets (the first phase of step 5 when there
     // are any) and the rounds of the other targets write different leaves:
     // the fused launch overlaps the rounds
-    if (has_fused && P.ph.size() > ph_lr0 + 1)
+    if (has_fused && P.ph.size() > ph_lr0 + 1) {
+      P.ph[ph_lr0].side = 1;
       P.ph[ph_lr0].par = (int)(P.ph.size() - ph_lr0 - 1);
+    }
     bjobs.clear();
     bjob_mat.clear();
     bdprod.clear();
