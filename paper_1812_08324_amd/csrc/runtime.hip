@@ -289,7 +289,13 @@ struct DevStructure {
 // ---------------------------------------------------------------------------
 // plan: phases over item arrays, built on the host, uploaded once
 // ---------------------------------------------------------------------------
-enum PhaseType { PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF, PH_LUINV, PH_RADD };
+enum PhaseType {
+  PH_APPLY, PH_DPROD, PH_DFLUSH, PH_LFLUSH, PH_COPY, PH_GETRF, PH_LUINV, PH_RADD,
+  // deferred work: the phases between DEFER_BEGIN and DEFER_END run on the
+  // deferred stream (after all earlier phases of the caller's stream); the
+  // caller's stream waits for them at DEFER_JOIN (strictly nested pairs)
+  PH_DEFER_BEGIN, PH_DEFER_END, PH_DEFER_JOIN
+};
 
 struct Phase {
   int type;
@@ -307,8 +313,8 @@ struct Phase {
 // runs there while the independent phases after it run on the caller's
 // stream (one set per thread, so concurrent callers never share events).
 struct ForkJoin {
-  hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t side = nullptr, deferred = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, dfork = nullptr, djoin = nullptr;
 };
 static ForkJoin& fork_join() {
   static thread_local std::map<int, ForkJoin> per_device;
@@ -317,8 +323,11 @@ static ForkJoin& fork_join() {
   ForkJoin& f = per_device[dev];
   if (!f.side) {
     HL_CHECK(hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking));
+    HL_CHECK(hipStreamCreateWithFlags(&f.deferred, hipStreamNonBlocking));
     HL_CHECK(hipEventCreateWithFlags(&f.fork, hipEventDisableTiming));
     HL_CHECK(hipEventCreateWithFlags(&f.join, hipEventDisableTiming));
+    HL_CHECK(hipEventCreateWithFlags(&f.dfork, hipEventDisableTiming));
+    HL_CHECK(hipEventCreateWithFlags(&f.djoin, hipEventDisableTiming));
   }
   return f;
 }
@@ -358,6 +367,7 @@ struct Plan {
     // after the par phases that follow it
     size_t join_at = (size_t)-1;
     ForkJoin* fj = nullptr;
+    bool in_deferred = false;
     for (size_t q = 0; q < ph.size(); ++q) {
       if (q == join_at) {
         HL_CHECK(hipEventRecord(fj->join, fj->side));
@@ -365,6 +375,27 @@ struct Plan {
         join_at = (size_t)-1;
       }
       const Phase& p = ph[q];
+      if (p.type == PH_DEFER_BEGIN) {
+        fj = &fork_join();
+        HL_CHECK(hipEventRecord(fj->dfork, s));
+        HL_CHECK(hipStreamWaitEvent(fj->deferred, fj->dfork, 0));
+        in_deferred = true;
+        continue;
+      }
+      if (p.type == PH_DEFER_END) {
+        in_deferred = false;
+        continue;
+      }
+      if (p.type == PH_DEFER_JOIN) {
+        fj = &fork_join();
+        HL_CHECK(hipEventRecord(fj->djoin, fj->deferred));
+        HL_CHECK(hipStreamWaitEvent(s, fj->djoin, 0));
+        continue;
+      }
+      if (in_deferred) {   // in order on the deferred stream, no side forks
+        run_phase(p, zero_pivot, fork_join().deferred);
+        continue;
+      }
       if (p.side > 0 && p.par > 0 && join_at == (size_t)-1) {
         fj = &fork_join();
         HL_CHECK(hipEventRecord(fj->fork, s));
@@ -380,6 +411,7 @@ struct Plan {
       HL_CHECK(hipEventRecord(fj->join, fj->side));
       HL_CHECK(hipStreamWaitEvent(s, fj->join, 0));
     }
+    if (in_deferred) throw DeviceError("internal: deferred phases without an end");
   }
 
   void run_phase(const Phase& p, int32_t* zero_pivot, hipStream_t s) const {
@@ -698,7 +730,10 @@ struct Builder {
     return true;
   }
 
-  void end() {
+  // keep_ws: leave the batch's workspace allocated (its phases run on the
+  // deferred stream and may still be running when later batches start); the
+  // caller releases it with release_kept(mark) once the stream has joined.
+  WsStack::Mark end(bool keep_ws = false) {
     // 1. applies (all independent within the batch)
     const size_t ph_apply = bjobs.empty() ? (size_t)-1 : P.ph.size();
     if (!bjobs.empty()) {
@@ -979,9 +1014,13 @@ struct Builder {
     for (auto& k : pkeys) k.first->pend[k.second] = -1;
     pkeys.clear();
     pterms.clear();
-    ws.release(mk);
+    if (!keep_ws) ws.release(mk);
     in_batch = false;
+    return mk;
   }
+
+  void release_kept(const WsStack::Mark& m) { ws.release(m); }
+  void phase_marker(int type) { P.ph.push_back(Phase{type, 0, 0, 0, 0, 0, 0, 0.0}); }
 
   // Copies of leaves (add_copies) between copy_begin() and copy_end() go to
   // one phase.
@@ -1147,16 +1186,30 @@ static void hluinv_joint(Builder& B, const std::vector<LuNode>& items, int H) {
   B.begin();
   for (const LuNode& a : act) {
     const BNode& b = a.c->LU->S->bn[a.node];
-    const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
+    const int n12 = b.child[1], n21 = b.child[2], n22 = b.child[3];
     const LuCtx& c = *a.c;
     B.mma(c.LU, n22, c.LU, n21, c.LU, n12, -1.0);   // A22 -= L21 U12
+  }
+  B.end();
+  // T21 and S12 are needed only after the recursion on A22 and touch none of
+  // its blocks (they read L21, U12 and the inverses of node 11, and write the
+  // TMP blocks 21 and 12): they run on the deferred stream meanwhile, their
+  // workspace kept until the join
+  B.phase_marker(PH_DEFER_BEGIN);
+  B.begin();
+  for (const LuNode& a : act) {
+    const BNode& b = a.c->LU->S->bn[a.node];
+    const int n11 = b.child[0], n12 = b.child[1], n21 = b.child[2];
+    const LuCtx& c = *a.c;
     B.mma(c.TMP, n21, c.LU, n21, c.Li, n11, 1.0);   // T21 = L21 L11^{-1}
     B.mma(c.TMP, n12, c.Ui, n11, c.LU, n12, 1.0);   // S12 = U11^{-1} U12
   }
-  B.end();
+  const WsStack::Mark kept = B.end(/*keep_ws=*/true);
+  B.phase_marker(PH_DEFER_END);
   std::vector<LuNode> sub2;
   for (const LuNode& a : act) sub2.push_back({a.c, a.c->LU->S->bn[a.node].child[3]});
   hluinv_joint(B, sub2, H - 1);
+  B.phase_marker(PH_DEFER_JOIN);
   B.begin();
   for (const LuNode& a : act) {
     const BNode& b = a.c->LU->S->bn[a.node];
@@ -1166,6 +1219,7 @@ static void hluinv_joint(Builder& B, const std::vector<LuNode>& items, int H) {
     B.mma(c.Ui, n12, c.TMP, n12, c.Ui, n22, -1.0);  // (U^{-1})12 = -S12 U22^{-1}
   }
   B.end();
+  B.release_kept(kept);
 }
 
 // Per-step matrix-vector plan of one H-matrix: projection tiles, the
