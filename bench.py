@@ -234,10 +234,11 @@ def bench_2d(H, torch, sweeps, lu_tol_mixed):
     return out
 
 
-def counted_traffic(key):
+def counted_traffic(key, algorithmic_bytes=None):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
     summary, or None when the product kernels' sources have changed since
-    the counters were taken (their hash no longer matches)."""
+    the counters were taken (their hash no longer matches) or the operator
+    has (its algorithmic bytes per launch differ from those counted)."""
     import hashlib
     try:
         fields = dict(l.split(": ", 1) for l in open(TRAFFIC_PROFILE).read().splitlines() if ": " in l)
@@ -245,6 +246,9 @@ def counted_traffic(key):
         for f in fields["kernel_sources"].split():
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest() != fields["kernel_source_sha256"].strip():
+            return None
+        if algorithmic_bytes is not None and \
+                round(float(fields[key.replace("traffic", "algorithmic")])) != round(algorithmic_bytes):
             return None
         return float(fields[key])
     except (OSError, KeyError, ValueError):
@@ -369,6 +373,7 @@ def main():
 
     # per-kernel HIP-event timing of the per-step products, in stepping order
     kt = H.fac_kernel_times(fac, reps=20)
+    opinfo = H.op_info(op)
 
     extra = {}
     if not args.no_fp64:
@@ -407,7 +412,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": counted_traffic({"gather[G]": "gather_G_traffic_bytes",
-                                            "project[G]": "project_G_traffic_bytes"}.get(dom, "-")),
+                                            "project[G]": "project_G_traffic_bytes"}.get(dom, "-"), nbytes),
                 "kernel": ("k_mv_gather" if dom.startswith("gather") else "k_mv_project")
                 + f" ({mat} product, {prec_tag[mat]})",
                 "bytes_per_launch": nbytes, "avg_launch_ms": ms}
@@ -438,6 +443,8 @@ def main():
                    "max_rank": args.max_rank},
         "phases_s": {"assemble": s1 - s0, "factor_mixed": s2 - s1, "steps_mixed": s3 - s2},
         "steady_cn_steps_per_s_mixed": steady_mixed,
+        "operator": {"max_rank": opinfo["max_rank"], "mean_rank": opinfo["mean_rank"],
+                     "dense_entries": opinfo["dense_entries"], "lowrank_entries": opinfo["lowrank_entries"]},
         "kernel_ms": {k: {"project": kt[k]["project_ms"], "gather": kt[k]["gather_ms"],
                           "matrix_MB": (kt[k]["dense_bytes"] + kt[k]["u_bytes"] + kt[k]["v_bytes"]) / 1e6}
                       for k in ("G", "Linv", "Uinv")},

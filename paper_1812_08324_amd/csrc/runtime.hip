@@ -1247,11 +1247,22 @@ struct MvPlan {
     auto fptr = [&](const double* p) -> const void* { return fbase + (p - base); };
     const size_t d_elt = dense_f32 ? sizeof(float) : sizeof(double);
     auto leaf_f32 = [&](const LeafDesc& d) { return lr_f32 && std::max(d.m, d.n) > lr64_rows; };
+    // rank bucket kb: 8 when leaves of higher rank (split below into
+    // kb-column chunks, each with its own tiles, partial slots and gather
+    // entries) add at most 50 % more low-rank entries, else 16 when they add
+    // at most 10 %, else 32.  A few ranks just above a bucket then cost an
+    // extra narrow entry instead of moving every entry to the wider kernels.
     int kmax = 0;
+    int64_t nlr = 0, extra8 = 0, extra16 = 0;
     for (size_t l = 0; l < S.lf.size(); ++l)
-      if (M.L[l].kind == K_LR) kmax = std::max(kmax, rk[l]);
+      if (M.L[l].kind == K_LR && rk[l] > 0) {
+        kmax = std::max(kmax, rk[l]);
+        ++nlr;
+        extra8 += (rk[l] + 7) / 8 - 1;
+        extra16 += (rk[l] + 15) / 16 - 1;
+      }
     if (kmax > 32) throw std::runtime_error("internal: rank above 32 in a product plan");
-    const int kb = kmax <= 8 ? 8 : (kmax <= 16 ? 16 : 32);
+    const int kb = 2 * extra8 <= nlr ? 8 : (10 * extra16 <= nlr ? 16 : 32);
     // projection tiles: a leaf's V rows split into at most MV_PMAX tiles of
     // whole passes; partial slots of one leaf are consecutive
     std::vector<MvTile> tiles;
@@ -1276,25 +1287,30 @@ struct MvPlan {
       const int P = (npass + per - 1) / per;
       slot0[l] = (int32_t)nslots;
       np[l] = P;
-      for (int t = 0; t < P; ++t) {
-        const int r0 = t * per * rpp, r1 = std::min(d.n, r0 + per * rpp);
-        // one tile per project_width(kb) columns
-        const int tw = project_width(kb);
-        for (int c0 = 0; c0 < k; c0 += tw) {
-          MvTile T{};
-          T.n = r1 - r0;
-          T.k = std::min(k - c0, tw);
-          T.ld = d.n;
-          T.xoff = d.clo + r0;
-          T.slot = (int32_t)(nslots + t);
-          T.f32 = f32 ? 1 : 0;
-          T.col0 = c0;
-          const double* p = d.B + r0 + (size_t)d.n * c0;
-          T.V = f32 ? fptr(p) : (const void*)p;
-          tiles.push_back(T);
+      // chunk ch (columns ch kb .. ch kb + kc - 1) owns slots slot0 + ch P ..
+      const int nch = (k + kb - 1) / kb;
+      for (int ch = 0; ch < nch; ++ch) {
+        const int kc = std::min(kb, k - ch * kb);
+        for (int t = 0; t < P; ++t) {
+          const int r0 = t * per * rpp, r1 = std::min(d.n, r0 + per * rpp);
+          // one tile per project_width(kb) columns
+          const int tw = project_width(kb);
+          for (int c0 = 0; c0 < kc; c0 += tw) {
+            MvTile T{};
+            T.n = r1 - r0;
+            T.k = std::min(kc - c0, tw);
+            T.ld = d.n;
+            T.xoff = d.clo + r0;
+            T.slot = (int32_t)(nslots + ch * P + t);
+            T.f32 = f32 ? 1 : 0;
+            T.col0 = c0;
+            const double* p = d.B + r0 + (size_t)d.n * (ch * kb + c0);
+            T.V = f32 ? fptr(p) : (const void*)p;
+            tiles.push_back(T);
+          }
         }
       }
-      nslots += P;
+      nslots += (int64_t)nch * P;
     }
     matrix_bytes = dense_bytes + lr_bytes;
     // longest tiles first
@@ -1308,8 +1324,6 @@ struct MvPlan {
       for (int e = S.rowptr[q]; e < S.rowptr[q + 1]; ++e) {
         const int l = S.rowidx[e];
         const LeafDesc& d = M.L[l];
-        MvEntry E{};
-        int64_t bytes = 0;
         if (d.kind == K_DENSE) {
           // pieces of MV_DCOLS columns: the wavefronts of the gather share
           // a dense leaf instead of one of them streaming all its columns
@@ -1323,21 +1337,21 @@ struct MvPlan {
             D.ptr = dense_f32 ? fptr(p) : (const void*)p;
             row.emplace_back((int64_t)D.n * d_elt, D);
           }
-          continue;
         } else if (d.kind == K_LR && rk[l] > 0) {
+          // one entry per kb-column chunk of the factor
           const bool f32 = leaf_f32(d);
-          E.kind = f32 ? 2 : 1;
-          E.n = np[l];
-          E.k = rk[l];
-          E.slot = slot0[l];
-          E.ld = d.m;
-          const double* p = d.A + (c.lo - d.rlo);
-          E.ptr = f32 ? fptr(p) : (const void*)p;
-          bytes = (int64_t)rk[l] * (f32 ? sizeof(float) : sizeof(double));
-        } else {
-          continue;
+          for (int ch = 0; ch * kb < rk[l]; ++ch) {
+            MvEntry L{};
+            L.kind = f32 ? 2 : 1;
+            L.n = np[l];
+            L.k = std::min(kb, rk[l] - ch * kb);
+            L.slot = slot0[l] + ch * np[l];
+            L.ld = d.m;
+            const double* p = d.A + (c.lo - d.rlo) + (size_t)d.m * ch * kb;
+            L.ptr = f32 ? fptr(p) : (const void*)p;
+            row.emplace_back((int64_t)L.k * (f32 ? sizeof(float) : sizeof(double)), L);
+          }
         }
-        row.emplace_back(bytes, E);
       }
       // most bytes first: the wavefronts take entries round-robin
       std::stable_sort(row.begin(), row.end(),
@@ -1906,7 +1920,19 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
       ops[i] = std::move(op);
     }
     // 2. truncation of every ACA block to its tolerance: one plan for all
-    //    problems (problems of equal tolerance share launches)
+    //    problems (problems of equal tolerance share launches).  The ACA
+    //    ranks come back first (one synchronisation): with double-double
+    //    parts the fast cores take 48 columns, so an ACA term of rank k is
+    //    split into ceil(k / (48 - kcap)) column pieces, piece p of every
+    //    block applied in round p.
+    std::vector<std::vector<int32_t>> aca_rank(count);
+    for (int32_t i = 0; i < count; ++i) {
+      aca_rank[i].resize(aca[i]->lr_ids.size());
+      if (!aca_rank[i].empty())
+        HL_CHECK(hipMemcpyAsync(aca_rank[i].data(), aca[i]->rank.as<int32_t>(), aca_rank[i].size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+    }
+    HL_CHECK(hipStreamSynchronize(s));
     {
       std::map<double, std::vector<int32_t>> by_tol;
       for (int32_t i = 0; i < count; ++i) by_tol[ops[i]->hp.aca_tol].push_back(i);
@@ -1914,43 +1940,62 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
       WsStack ws;
       Builder B(P, ws, ops[0]->ds.ident.as<double>(), ops[0]->ovf.as<int32_t>(), hps[0].aca_tol);
       for (auto& kv : by_tol) {
-        std::vector<LFlushTarget> tgs;
-        std::vector<std::vector<Term>> tl;
+        const bool split = radd_dd(kv.first);
+        std::vector<std::vector<LFlushTarget>> tgs(1);
+        std::vector<std::vector<std::vector<Term>>> tl(1);
+        std::vector<std::vector<int32_t*>> ovf(1);
         for (int32_t i : kv.second) {
           hlevy_op* op = ops[i].get();
           const Aca& A = *aca[i];
           for (size_t q = 0; q < A.lr_ids.size(); ++q) {
             const LeafDesc& d = op->G.L[A.lr_ids[q]];
-            LFlushTarget T{};
-            T.U = d.A;
-            T.V = d.B;
-            T.rank = op->G.rank + A.lr_ids[q];
-            T.m = d.m;
-            T.n = d.n;
-            T.kcap = d.kcap;
-            T.Kcap = kaca;
-            Term t{};
-            t.dense = 0;
-            t.ro = 0;
-            t.mr = d.m;
-            t.co = 0;
-            t.nc = d.n;
-            t.U = A.buf.as<double>() + A.uo[q];
-            t.ldu = d.m;
-            t.W = A.buf.as<double>() + A.vo[q];
-            t.ldw = d.n;
-            t.k = A.rank.as<int32_t>() + q;
-            t.sign = 1.0;
-            tgs.push_back(T);
-            tl.push_back({t});
+            const int w = split ? std::min(kaca, 48 - d.kcap) : kaca;
+            if (w <= 0) throw DeviceError("internal: rank capacity above 47 with double-double parts");
+            const int kr = aca_rank[i][q];
+            if (kr < 0 || kr > kaca) throw DeviceError("internal: ACA rank out of range");
+            // at least one piece: a block of rank 0 is still truncated (to rank 0)
+            const int kend = split ? std::max(kr, 1) : kaca;
+            for (int c0 = 0, piece = 0; c0 < kend; c0 += w, ++piece) {
+              LFlushTarget T{};
+              T.U = d.A;
+              T.V = d.B;
+              T.rank = op->G.rank + A.lr_ids[q];
+              T.m = d.m;
+              T.n = d.n;
+              T.kcap = d.kcap;
+              const int kl = std::min(w, kend - c0);
+              T.Kcap = split ? d.kcap + kl : kaca;
+              Term t{};
+              t.dense = 0;
+              t.ro = 0;
+              t.mr = d.m;
+              t.co = 0;
+              t.nc = d.n;
+              t.U = A.buf.as<double>() + A.uo[q] + (size_t)d.m * c0;
+              t.ldu = d.m;
+              t.W = A.buf.as<double>() + A.vo[q] + (size_t)d.n * c0;
+              t.ldw = d.n;
+              t.k = A.rank.as<int32_t>() + q;
+              t.sign = 1.0;
+              if (split) {
+                t.kofs = c0;
+                t.klim = kl;
+              }
+              if ((int)tgs.size() <= piece) {
+                tgs.resize(piece + 1);
+                tl.resize(piece + 1);
+                ovf.resize(piece + 1);
+              }
+              tgs[piece].push_back(T);
+              tl[piece].push_back({t});
+              ovf[piece].push_back(op->ovf.as<int32_t>());
+            }
           }
         }
-        // every problem's overflow counter: targets carry their own below
-        std::vector<int> where = B.emit_lflush(tgs, tl, kv.first);
-        size_t q0 = 0;
-        for (int32_t i : kv.second) {
-          for (size_t q = 0; q < aca[i]->lr_ids.size(); ++q) P.ltg[where[q0 + q]].overflow = ops[i]->ovf.as<int32_t>();
-          q0 += aca[i]->lr_ids.size();
+        for (size_t piece = 0; piece < tgs.size(); ++piece) {
+          // every problem's overflow counter: targets carry their own below
+          std::vector<int> where = B.emit_lflush(tgs[piece], tl[piece], kv.first);
+          for (size_t q = 0; q < where.size(); ++q) P.ltg[where[q]].overflow = ovf[piece][q];
         }
       }
       P.upload_all(s);
