@@ -166,7 +166,11 @@ hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream);
  * triangular factors, truncating every low-rank addition at lu_tol.
  * prec = HLEVY_PREC_FP64 keeps FP64 factors; HLEVY_PREC_MIXED stores the
  * inverse factors in FP32 for the refinement preconditioner.  The factor
- * keeps a reference to `op` (op must outlive it).  Synchronises `stream`. */
+ * keeps a reference to `op` (op must outlive it).  Independent parts of the
+ * factorisation run on two further streams that the library keeps per host
+ * thread and device (default priority, created on first use, never
+ * destroyed); their work joins `stream` before the call returns.
+ * Synchronises `stream`. */
 hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu_tol,
                           void* stream, hlevy_fac** out);
 
@@ -179,8 +183,9 @@ hlevy_status hlevy_factor(const hlevy_op* op, double dt, int32_t prec, double lu
  * fits `workspace_bytes` (0 = 48 GiB); each group is one plan.  prec and
  * lu_tol as for hlevy_factor, common to all problems.  out[i] receives
  * problem i's factor (each used and destroyed on its own).  A group shares
- * its zero-pivot flag and rank-overflow count.  On error every out[i] is
- * NULL and nothing is leaked.  Synchronises `stream`. */
+ * its zero-pivot flag and rank-overflow count.  Uses the library's two
+ * further streams as hlevy_factor does.  On error every out[i] is NULL and
+ * nothing is leaked.  Synchronises `stream`. */
 hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, int32_t count,
                                   int32_t prec, double lu_tol, size_t workspace_bytes,
                                   void* stream, hlevy_fac** out);
