@@ -288,8 +288,8 @@ def bench_serving(H, torch, seconds, frac_1d, sweeps, lu_tol):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a multi-GPU run is not "
-              "part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU "
+              "path.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1812_08324_amd import hlevy as H

@@ -114,7 +114,7 @@ def test_block_tree_counts_match_enumeration(H, dim, n):
     assert info["max_leaf_points"] <= leaf
 
 
-def test_survey_scale_counts(H):
+def test_full_scale_counts(H):
     # 1D N = 65536, leaf 64, eta = 1, N_max = N/4: 3070 dense + 6078 low-rank leaves
     info = H.plan_info(H.make_problem(1, 65536, -1.0, 1.0, 0.75), H.make_hparams())
     assert (info["n_dense"], info["n_lowrank"], info["depth"]) == (3070, 6078, 10)
