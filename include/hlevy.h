@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HLEVY_ABI_VERSION 1
+#define HLEVY_ABI_VERSION 2
 
 typedef enum {
   HLEVY_OK = 0,
@@ -81,15 +81,32 @@ typedef struct {
   int32_t max_rank;  /* rank capacity of a low-rank block, 4..32 */
 } hlevy_hparams;
 
+/* Iterative refinement of a solve M x = b preconditioned by the H-LU
+ * (Sec. 5.1 uses the H-LU inverse as a preconditioner): after the direct
+ * solve x = U^{-1} L^{-1} b, `sweeps` sweeps x <- x + U^{-1} L^{-1} (b - M x)
+ * with the FP64 operator in the residual.  At a check the relative residual
+ * ||b - M x||_2 / ||b||_2 of the current x is measured on the device (one
+ * more product with G, read back on the host); while it is above `tol`
+ * further sweeps run, up to `max_sweeps` sweeps in all, and a check that
+ * still misses `tol` fails the call with HLEVY_ERR_NOT_CONVERGED. */
 typedef struct {
-  double tol;          /* relative residual target ||b - M x|| / ||b|| (mixed path) */
-  int32_t sweeps;      /* refinement sweeps per solve (fixed count, graph friendly) */
+  double tol;          /* relative residual target; <= 0: no target (checks only measure) */
+  int32_t sweeps;      /* sweeps per solve / per Crank-Nicolson step (fixed count) */
+  int32_t check_every; /* hlevy_step: check every k-th step and the last; 0: the last step only */
+  int32_t max_sweeps;  /* most sweeps at a check that misses tol (values below `sweeps` mean `sweeps`) */
+  int32_t pad;
 } hlevy_refine;
 
+/* Outcome of a solve or stepping call.  Filling it synchronises the stream. */
 typedef struct {
-  int64_t steps_done;
-  double last_rel_residual;   /* of the last step, if measured (else -1) */
-  int32_t rank_overflows;     /* low-rank blocks truncated at their capacity */
+  int64_t steps_done;          /* completed steps (solves: right-hand sides) */
+  double last_rel_residual;    /* at the last check, -1 when none was made */
+  double max_rel_residual;     /* largest measured in the call, -1 when none */
+  int32_t checks;              /* residual checks made */
+  int32_t max_sweeps_used;     /* most sweeps a checked solve or step took */
+  int32_t rank_overflows;      /* low-rank blocks of the factor truncated at their capacity */
+  int32_t pad;
+  double seconds;              /* host wall time of the call */
 } hlevy_stats;
 
 /* Structure summary, computed on the host (no device needed). */
@@ -109,11 +126,35 @@ typedef struct {
   int64_t lowrank_entries;    /* stored entries sum (m+n)*k over low-rank leaves */
   int32_t max_rank;
   double mean_rank;
-  int32_t rank_overflows;
+  int32_t rank_overflows;     /* low-rank blocks truncated at their capacity (0: see subdivided_blocks) */
+  int32_t subdivided_blocks;  /* admissible blocks subdivided or kept dense for the rank cap */
+  size_t device_bytes;        /* device memory the operator holds */
 } hlevy_op_info_t;
+
+typedef struct {
+  size_t device_bytes;        /* device memory the factor holds (the operator's not included) */
+  int32_t rank_overflows;     /* rounded additions of the H-LU truncated at the rank capacity */
+  int32_t max_rank;           /* largest rank of a low-rank block of L^{-1} or U^{-1} */
+  double product_bytes[3];    /* stored bytes read by one product with G, L^{-1}, U^{-1} */
+  double lu_tol, dt;
+  int32_t prec, pad;
+} hlevy_fac_info_t;
 
 typedef struct hlevy_op hlevy_op;
 typedef struct hlevy_fac hlevy_fac;
+
+/* Device memory supplied by the caller: alloc(bytes, ctx) returns device
+ * memory aligned to 256 bytes, or NULL on failure (the call then fails with
+ * HLEVY_ERR_OOM); free(p, ctx) releases it.  An operator assembled with an
+ * allocator takes all its storage and the transient buffers of its calls
+ * from it, and so does every factor of that operator; buffers are freed
+ * through the same allocator when the handle is destroyed.  The allocator
+ * must stay valid until then.  NULL: hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* p, void* ctx);
+  void* ctx;
+} hlevy_allocator;
 
 /* Library ABI version (HLEVY_ABI_VERSION). */
 int32_t hlevy_abi_version(void);
@@ -128,14 +169,28 @@ const char* hlevy_last_error(void);
 hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp,
                              hlevy_plan_info_t* out);
 
+/* Resident device bytes of an operator assembled from (prob, hp) plus one
+ * factor of precision prec: the memory hlevy_assemble and hlevy_factor keep
+ * until the handles are destroyed (hlevy_op_info / hlevy_fac_info report
+ * the actual bytes).  The transient workspace of a factorisation (at most
+ * workspace_bytes of hlevy_factor_batched) is not included.  Computed on the
+ * host from the block structure (App. B.1) with every low-rank block at its
+ * rank capacity, so it bounds the actual bytes from above.  Errors:
+ * HLEVY_ERR_INVALID_ARG for an invalid descriptor or precision. */
+hlevy_status hlevy_footprint(const hlevy_problem* prob, const hlevy_hparams* hp, int32_t prec,
+                             size_t* bytes_out);
+
 /* Assemble the generator G as an H-matrix on the device: quadrature constants
  * (Sec. 4, equ:I1approx - equ:I3approx), dense near-field leaves (Sec. 4 row
  * form, eq. equ:Aij local terms), partially pivoted ACA of every admissible
- * block followed by truncation to aca_tol (App. B.1).  *out receives a new
- * handle.  The call returns after the host-side trees are built; device work
- * is enqueued on `stream`. */
+ * block followed by truncation to aca_tol (App. B.1).  A block whose
+ * truncation needs more than max_rank columns is subdivided into its four
+ * sub-blocks (admissible in turn), or stored dense when its clusters are
+ * leaves, and the problem is assembled again with that structure, so no
+ * block is truncated at its capacity.  *out receives a new handle.  alloc:
+ * the caller's allocator or NULL.  Synchronises `stream`. */
 hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp,
-                            void* stream, hlevy_op** out);
+                            const hlevy_allocator* alloc, void* stream, hlevy_op** out);
 
 /* Batched worklist: assemble `count` problems (probs[i] with hps[i]) as
  * hlevy_assemble does, with the quadrature, near-field and ACA kernels of
@@ -144,7 +199,7 @@ hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp,
  * is the same operator hlevy_assemble gives.  On error every out[i] is NULL
  * and nothing is leaked.  Synchronises `stream`. */
 hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hparams* hps, int32_t count,
-                                    void* stream, hlevy_op** out);
+                                    const hlevy_allocator* alloc, void* stream, hlevy_op** out);
 
 /* Copy the four quadrature constants S0, S2, C2, T (Sec. 4) to host `out`.
  * Synchronises `stream`. */
@@ -152,6 +207,9 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream)
 
 /* Storage summary of the assembled operator.  Synchronises `stream`. */
 hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream);
+
+/* Storage summary of a factor.  Synchronises `stream`. */
+hlevy_status hlevy_fac_info(const hlevy_fac* fac, hlevy_fac_info_t* out, void* stream);
 
 /* y = G x (App. B.2: dense leaves by GEMV, low-rank leaves as U (V^T x)).
  * x, y: device, length N, natural order, must not alias. */
@@ -190,38 +248,50 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
                                   int32_t prec, double lu_tol, size_t workspace_bytes,
                                   void* stream, hlevy_fac** out);
 
-/* Solve M x = b: x = U^{-1} (L^{-1} b) through the inverse factors (forward
- * then backward solve), then refine->sweeps sweeps of
- * x <- x + U^{-1} L^{-1} (b - M x) with the residual in FP64.  refine may
- * be NULL: 2 sweeps (mixed)
- * or 1 sweep (FP64; products with explicit inverse factors lose accuracy
- * like eps cond(L) cond(U), about 1e-6 relative residual at N = 65536, and
- * one sweep restores about 1e-12).  b, x: device, natural order, must not
- * alias. */
-hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x,
-                         const hlevy_refine* refine, void* stream);
+/* Solve M X = B for nrhs right-hand sides (App. B.3 forward and backward
+ * solve): x = U^{-1} (L^{-1} b) through the H-inverses of the factors, then
+ * iterative refinement as hlevy_refine describes.  b, x: device, natural
+ * order, column c at b + c*ld (ld >= N), must not overlap.  Right-hand
+ * sides are taken up to four at a time: each product then reads the factor
+ * once for all of them.  refine may be NULL: 2 sweeps (mixed) or 1 sweep
+ * (FP64; products with explicit inverse factors lose accuracy like
+ * eps cond(L) cond(U), about 1e-6 relative residual at N = 65536, and one
+ * sweep restores about 1e-12), no target.  A check is made on every column
+ * when refine->tol > 0 or stats is given; stats reports the largest
+ * residual over the columns.  On HLEVY_ERR_NOT_CONVERGED x is unchanged. */
+hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x, int64_t nrhs, int64_t ld,
+                         const hlevy_refine* refine, hlevy_stats* stats, void* stream);
 
 /* Advance u (device, natural order, in/out) by nsteps Crank-Nicolson steps
  * of eq. equ:scheme with forcing f(x, t_n) = phi[n] g(x):
  *   M u^{n+1} = (I + dt/2 G) u^n + dt/2 (phi[n] + phi[n+1]) g.
  * g: device vector or NULL (no forcing); phi: host array of nsteps+1 values
- * (ignored when g is NULL).  stats may be NULL; when given, the call
- * synchronises and reports the last relative residual of the mixed path. */
+ * (ignored when g is NULL).  Each step solves M w = 2 u^n + F_n with
+ * refinement (hlevy_refine) and sets u^{n+1} = w - u^n.  Residual checks
+ * (refine->tol > 0, or stats given) run on every check_every-th step and on
+ * the last one.  A step whose check misses refine->tol after max_sweeps
+ * sweeps is not applied: the call returns HLEVY_ERR_NOT_CONVERGED with u at
+ * the last completed step and stats->steps_done counting the completed
+ * steps.  stats may be NULL. */
 hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double* g,
                         const double* phi, const hlevy_refine* refine,
                         hlevy_stats* stats, void* stream);
 
 /* Batched worklist: advance u[i] (device, natural order, in/out) of the
- * `count` problems facs[i] by nsteps Crank-Nicolson steps each, without
+ * `count` problems facs[i] by nsteps[i] Crank-Nicolson steps each, without
  * forcing (eq. equ:scheme with f = 0), each with its own dt.  Every product
  * of a step is one projection and one gather launch over all problems (per
  * group of equal rank bucket), so small problems share the chip.  Sweeps
  * per step: refine->sweeps, or when refine is NULL the largest default of
  * hlevy_step among the factors.  The factors must be distinct (each one's
  * work vectors are used); the result of each problem is the same as
- * hlevy_step on it alone.  Synchronises `stream`. */
-hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_t count,
-                                int64_t nsteps, const hlevy_refine* refine, void* stream);
+ * hlevy_step on it alone.  With refine->tol > 0 or stats given, the last
+ * step of every problem measures its relative residual (no further sweeps);
+ * stats reports the largest, and the call returns HLEVY_ERR_NOT_CONVERGED
+ * when one is above refine->tol (every u[i] is advanced all the same).
+ * Synchronises `stream`. */
+hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, const int64_t* nsteps, int32_t count,
+                                const hlevy_refine* refine, hlevy_stats* stats, void* stream);
 
 /* Serving loop.  Requests (a problem, dt, a horizon of nsteps unforced
  * Crank-Nicolson steps, u0) arrive at any time; each hlevy_server_poll is
@@ -238,7 +308,9 @@ hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_
  *     min(chunk, its steps left) steps in one batched loop
  *     (hlevy_step_batched's products; each request keeps its own vectors;
  *     a request whose steps are done sits out the rest of the loop);
- *  4. finished requests get u^{nsteps} written to their u_out.
+ *  4. finished requests get u^{nsteps} written to their u_out; the last
+ *     step of every request measures its relative residual (stats).
+ * Submission validates the problem as hlevy_assemble does.
  * A request's result equals hlevy_step with a factor of the same
  * parameters (same arithmetic, summation order of the batched products).
  * The server's calls are not thread safe. */
@@ -249,14 +321,18 @@ typedef struct {
   int32_t sweeps;      /* refinement sweeps per step */
   int32_t chunk;       /* CN steps per scheduling round, >= 1 */
   int32_t max_active;  /* most requests advanced together, >= 1 */
+  double tol;          /* relative residual target of a request's last step; <= 0: measured only */
 } hlevy_server_config;
 
 typedef struct {
   int64_t submitted, completed, active, queued;
   int64_t cache_hits, cache_misses, evictions, cached_operators;
   int64_t problem_steps;        /* CN steps advanced, summed over requests */
-  size_t bytes_in_use;          /* resident bytes by the server's estimate */
+  size_t bytes_in_use;          /* resident bytes (hlevy_footprint of the cached operators, request state) */
   double assemble_seconds, factor_seconds, step_seconds;
+  int64_t failed;               /* requests whose operator could not be built */
+  int64_t not_converged;        /* completed requests whose last-step residual missed tol */
+  double max_rel_residual;      /* largest last-step residual of a completed request, -1 before any */
 } hlevy_server_stats;
 
 typedef struct hlevy_server hlevy_server;
@@ -277,6 +353,12 @@ hlevy_status hlevy_server_submit(hlevy_server* srv, const hlevy_problem* prob, c
  * `cap` ids of finished requests to done_ids and their count to *ndone
  * (more are returned by later calls). */
 hlevy_status hlevy_server_poll(hlevy_server* srv, int64_t* done_ids, int32_t cap, int32_t* ndone);
+
+/* Requests that failed: when the assembly or factorisation of the operators
+ * new in a round fails, hlevy_server_poll returns that error and those
+ * requests leave the server (their u_out is not written).  Writes up to
+ * `cap` of their ids to ids and the count to *n. */
+hlevy_status hlevy_server_take_failed(hlevy_server* srv, int64_t* ids, int32_t cap, int32_t* n);
 
 /* Counters of the server. */
 hlevy_status hlevy_server_stats_get(hlevy_server* srv, hlevy_server_stats* out);

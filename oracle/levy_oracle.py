@@ -315,3 +315,77 @@ def cn_run(G: np.ndarray, dt: float, steps: int, u0: np.ndarray,
         if keep_norms:
             norms.append(float(np.linalg.norm(u)))
     return CNResult(u=u, norms=norms)
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson at full size with a single N x N array (Sec. 3.2, equ:scheme)
+# ---------------------------------------------------------------------------
+def cn_run_lean(p: Problem, dt: float, steps: int, u0: np.ndarray,
+                g: np.ndarray | None = None, phi: np.ndarray | None = None,
+                keep_norms: bool = False, log=None) -> CNResult:
+    """The recursion of ``cn_run`` for N where two dense N x N arrays do not
+    fit in host memory (N = 65536 needs 34 GB per array).
+
+    The rows of M = I - dt/2 G are written, one generator row at a time, into
+    one row-major array.  Read in column-major order the same memory holds
+    M^T, which LAPACK getrf factors in place: M^T = P L U.  Hence
+    M = U^T L^T P^T, and each step is the plain recursion
+
+        rhs     = 2 u^n - M u^n + dt/2 (f^n + f^{n+1})     (M_+ = 2 I - M)
+        u^{n+1} = M^{-1} rhs
+
+    with M u^n = U^T (L^T (P^T u^n)) formed by two BLAS triangular products
+    on the factors, and M^{-1} rhs by the transposed getrs solve.
+
+    Returns a CNResult whose ``timings`` attribute holds the seconds spent in
+    assembly, factorisation and the step loop.
+    """
+    import time
+    from scipy.linalg import blas
+
+    say = log if log is not None else (lambda msg: None)
+    N = p.N
+    t0 = time.perf_counter()
+    consts = quadrature_constants(p)
+    A = np.empty((N, N), dtype=np.float64)          # row-major: row i of M
+    for i in range(N):
+        row = generator_row(p, i, consts)
+        row *= -0.5 * dt
+        row[i] += 1.0
+        A[i] = row
+        if (i + 1) % 8192 == 0:
+            say(f"assembled {i + 1}/{N} rows")
+    t1 = time.perf_counter()
+    Mt = A.T                                        # column-major view of M^T
+    lu, piv = sla.lu_factor(Mt, overwrite_a=True, check_finite=False)
+    if not np.shares_memory(lu, A):
+        raise RuntimeError("getrf copied the matrix; the lean path needs it in place")
+    del Mt
+    t2 = time.perf_counter()
+    say(f"factored in {t2 - t1:.1f}s")
+
+    def m_times(v):
+        w = np.array(v, dtype=np.float64, copy=True)
+        for i in range(N):                          # P^T v: the interchanges in order
+            j = piv[i]
+            if j != i:
+                w[i], w[j] = w[j], w[i]
+        w = blas.dtrmv(lu, w, lower=1, trans=1, diag=1)     # L^T (unit diagonal)
+        return blas.dtrmv(lu, w, lower=0, trans=1)          # U^T
+
+    u = np.array(u0, dtype=np.float64, copy=True)
+    norms = [float(np.linalg.norm(u))] if keep_norms else []
+    for n in range(steps):
+        rhs = 2.0 * u - m_times(u)
+        if g is not None:
+            rhs = rhs + 0.5 * dt * (phi[n] + phi[n + 1]) * g
+        u = sla.lu_solve((lu, piv), rhs, trans=1, check_finite=False)
+        if keep_norms:
+            norms.append(float(np.linalg.norm(u)))
+        if (n + 1) % 10 == 0:
+            say(f"step {n + 1}/{steps} |u| {np.linalg.norm(u):.15e} "
+                f"{(time.perf_counter() - t2) / (n + 1):.3f}s/step")
+    t3 = time.perf_counter()
+    res = CNResult(u=u, norms=norms)
+    res.timings = dict(assembly_s=t1 - t0, factor_s=t2 - t1, steps_s=t3 - t2)
+    return res

@@ -3,7 +3,9 @@
 #pragma once
 
 #include <cstdint>
+#include <set>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hlevy.h"
@@ -52,11 +54,19 @@ struct Structure {
   // leaf cluster position containing index i: i -> position (size N)
   int32_t n_dense = 0, n_lr = 0;
   int64_t dense_entries = 0;
+  // admissible blocks (row cluster, column cluster) not stored low rank:
+  // subdivided, or dense at the leaf level (R16: ACA over the rank cap)
+  std::set<std::pair<int32_t, int32_t>> split;
 };
+
+// Largest side of an admissible (low-rank) block: the ACA kernel keeps its
+// used pivot rows in an LDS bitmap of this many bits.
+constexpr int32_t LR_ROWS_MAX = 16384;
 
 // Validates the descriptor and builds every host structure.  Returns an
 // error message on failure (empty on success).
-std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Structure& s);
+std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Structure& s,
+                            const std::set<std::pair<int32_t, int32_t>>* split = nullptr);
 
 // Whether the leaf is strictly below / above the diagonal.
 inline bool leaf_lower(const LeafInfo& l) { return l.clo + l.n <= l.rlo; }

@@ -35,6 +35,13 @@ hipError_t launch_residual(double* r, const double* b, const double* x, const do
                            int N, hipStream_t s);
 hipError_t launch_add(double* x, const double* d, int N, hipStream_t s);
 hipError_t launch_sumsq(const double* x, int N, double* partial, int nblocks, double* out, hipStream_t s);
+// Refinement check: out[0] = ||r||^2, out[1] = ||alpha u + cg g||^2 (g may be
+// null); partial holds 2 * check_blocks(N) doubles.  Deterministic.
+int check_blocks(int N);
+hipError_t launch_check_norms(const double* r, const double* u, double alpha, const double* g, double cg, int N,
+                              double* partial, double* out, hipStream_t s);
+// u = w - u
+hipError_t launch_wsub(double* u, const double* w, int N, hipStream_t s);
 hipError_t launch_densify(const LeafDesc* L, const int32_t* rank, int nleaves, const int32_t* perm,
                           int N, double* dense, hipStream_t s);
 hipError_t init_kernel_attributes();

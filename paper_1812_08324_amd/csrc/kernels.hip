@@ -2,6 +2,7 @@
 // Crank-Nicolson library.  Host-side launchers are at the end of the file.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "hl_jobs.h"
@@ -307,13 +308,13 @@ __global__ void __launch_bounds__(HL_BLOCK) k_aca(ProblemDev P, const int32_t* p
   __shared__ int ri[4];
   __shared__ double coef[KMAX];
   __shared__ double dots[2 * KMAX];
-  __shared__ uint32_t used[512];   // up to 16384 rows
+  __shared__ uint32_t used[LR_ROWS_MAX / 32];   // one bit per row of the block
   const LeafDesc d = L[ids[blockIdx.x]];
   double* U = Ubuf + uoff[blockIdx.x];
   double* V = Vbuf + voff[blockIdx.x];
   const int m = d.m, n = d.n;
   const int kmax = min(kcap, min(m, n));
-  for (int q = threadIdx.x; q < 512; q += blockDim.x) used[q] = 0u;
+  for (int q = threadIdx.x; q < LR_ROWS_MAX / 32; q += blockDim.x) used[q] = 0u;
   __syncthreads();
   int i = 0, k = 0;
   double normS2 = 0.0;
@@ -1143,14 +1144,20 @@ __device__ __forceinline__ void radd_fetch_tile(const RaddCols& cs, int side, in
 #pragma unroll
   for (int u = 0; u < RA_NE; ++u) {
     const int e = threadIdx.x + u * HL_BLOCK;
-    const int rr = e & 63, j = e >> 6;
-    const int jj = j < K ? j : 0;
-    const int len = cs.len[side][jj];
-    int i = base + rr - cs.off[side][jj];
-    const bool ok = j < K && rr < rows && i >= 0 && i < len;
-    i = min(max(i, 0), len - 1);   // every column has len >= 1: the load stays in bounds
-    const double x = cs.p[side][jj][i];
-    v[u] = ok ? cs.sign[side][jj] * x : 0.0;
+    const int rr = e & 63, j = e >> 6;   // j is uniform across a wavefront
+    v[u] = 0.0;
+    // only columns j < K have sources (radd_cols writes no others, so with
+    // K = 0 nothing is loaded); a column of zero length loads nothing
+    if (j < K) {
+      const int len = cs.len[side][j];
+      if (len > 0) {
+        int i = base + rr - cs.off[side][j];
+        const bool ok = rr < rows && i >= 0 && i < len;
+        i = min(max(i, 0), len - 1);   // in bounds for every lane: loads stay unconditional
+        const double x = cs.p[side][j][i];
+        v[u] = ok ? cs.sign[side][j] * x : 0.0;
+      }
+    }
   }
 }
 constexpr int RA_TS = 65;   // column stride of a staged row block (odd: no LDS bank conflicts across columns)
@@ -1555,19 +1562,24 @@ __device__ __forceinline__ void df_fetch(const Term& tm, int kin, int q0, double
     const bool left = e < 64 * DF_KC;
     const int f = left ? e : e - 64 * DF_KC;
     const int x = f & 63, q = q0 + (f >> 6);
+    // a term of inner dimension 0 (rank 0) or of no rows / columns loads
+    // nothing: the clamped indices below need at least one element
+    const bool live = kin > 0 && tm.mr > 0 && tm.nc > 0;
     const int qc = min(q, kin - 1);
-    double val;
-    bool ok;
-    if (left) {
-      const int i = x - tm.ro;
-      ok = i >= 0 && i < tm.mr && q < kin;
-      val = tm.U[min(max(i, 0), tm.mr - 1) + (size_t)tm.ldu * qc];
-      val *= tm.sign;
-    } else {
-      const int j = x - tm.co;
-      ok = j >= 0 && j < tm.nc && q < kin;
-      const int jc = min(max(j, 0), tm.nc - 1);
-      val = tm.dense == 2 ? tm.W[qc + (size_t)tm.ldw * jc] : tm.W[jc + (size_t)tm.ldw * qc];
+    double val = 0.0;
+    bool ok = false;
+    if (live) {
+      if (left) {
+        const int i = x - tm.ro;
+        ok = i >= 0 && i < tm.mr && q < kin;
+        val = tm.U[min(max(i, 0), tm.mr - 1) + (size_t)tm.ldu * qc];
+        val *= tm.sign;
+      } else {
+        const int j = x - tm.co;
+        ok = j >= 0 && j < tm.nc && q < kin;
+        const int jc = min(max(j, 0), tm.nc - 1);
+        val = tm.dense == 2 ? tm.W[qc + (size_t)tm.ldw * jc] : tm.W[jc + (size_t)tm.ldw * qc];
+      }
     }
     v[u] = ok ? val : 0.0;
   }
@@ -2125,6 +2137,47 @@ __global__ void __launch_bounds__(HL_BLOCK) k_sum_final(const double* partial, i
   if (threadIdx.x == 0) *out = s;
 }
 
+// Residual check of a refinement: partial[2 b] = sum of r_i^2 and
+// partial[2 b + 1] = sum of (alpha u_i + cg g_i)^2 over block b's slice (the
+// right-hand side of the system whose residual r is; g may be null), then
+// one block adds the partials in a fixed order into out[0], out[1]
+// (deterministic: the grid depends on N only).
+__global__ void __launch_bounds__(HL_BLOCK) k_check_partial(const double* r, const double* u, double alpha,
+                                                            const double* g, double cg, int N, double* partial) {
+  __shared__ double red[4];
+  double sr = 0.0, sb = 0.0;
+  for (int i = blockIdx.x * HL_BLOCK + threadIdx.x; i < N; i += gridDim.x * HL_BLOCK) {
+    const double b = alpha * u[i] + (g ? cg * g[i] : 0.0);
+    sr += r[i] * r[i];
+    sb += b * b;
+  }
+  sr = block_sum(sr, red);
+  sb = block_sum(sb, red);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sr;
+    partial[2 * blockIdx.x + 1] = sb;
+  }
+}
+__global__ void __launch_bounds__(HL_BLOCK) k_check_final(const double* partial, int n, double* out) {
+  __shared__ double red[4];
+  double sr = 0.0, sb = 0.0;
+  for (int i = threadIdx.x; i < n; i += HL_BLOCK) {
+    sr += partial[2 * i];
+    sb += partial[2 * i + 1];
+  }
+  sr = block_sum(sr, red);
+  sb = block_sum(sb, red);
+  if (threadIdx.x == 0) {
+    out[0] = sr;
+    out[1] = sb;
+  }
+}
+// u = w - u  (Crank-Nicolson: u^{n+1} = w - u^n)
+__global__ void k_wsub(double* u, const double* w, int N) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) u[i] = w[i] - u[i];
+}
+
 // densify: every leaf writes its block into the natural-order dense matrix
 __global__ void __launch_bounds__(HL_BLOCK) k_densify(const LeafDesc* L, const int32_t* rank,
                                                       const int32_t* perm, int N, double* dense) {
@@ -2248,6 +2301,18 @@ hipError_t launch_add(double* x, const double* d, int N, hipStream_t s) {
 hipError_t launch_sumsq(const double* x, int N, double* partial, int nblocks, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sumsq_partial, dim3(nblocks), dim3(HL_BLOCK), 0, s, x, N, partial);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(HL_BLOCK), 0, s, partial, nblocks, out);
+  return post();
+}
+int check_blocks(int N) { return std::max(1, std::min(256, (N + 1023) / 1024)); }
+hipError_t launch_check_norms(const double* r, const double* u, double alpha, const double* g, double cg, int N,
+                              double* partial, double* out, hipStream_t s) {
+  const int nb = check_blocks(N);
+  hipLaunchKernelGGL(k_check_partial, dim3(nb), dim3(HL_BLOCK), 0, s, r, u, alpha, g, cg, N, partial);
+  hipLaunchKernelGGL(k_check_final, dim3(1), dim3(HL_BLOCK), 0, s, partial, nb, out);
+  return post();
+}
+hipError_t launch_wsub(double* u, const double* w, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_wsub, grid1(N), dim3(HL_BLOCK), 0, s, u, w, N);
   return post();
 }
 hipError_t launch_densify(const LeafDesc* L, const int32_t* rank, int nleaves, const int32_t* perm,

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <deque>
+#include <functional>
 #include <map>
 #include <set>
 #include <memory>
@@ -65,27 +66,64 @@ struct OomError {
 // ---------------------------------------------------------------------------
 // device memory helpers
 // ---------------------------------------------------------------------------
+// Device memory goes through the caller's allocator when one was given to
+// hlevy_assemble (the factor takes its operator's), else hipMalloc/hipFree.
+// A buffer keeps the allocator and the byte counter of the handle that
+// owns it from the scope active when it was allocated, so it is freed
+// through the same allocator and uncounted from the same handle.
+struct AllocCtx {
+  hlevy_allocator al{};     // al.alloc == nullptr: hipMalloc / hipFree
+  size_t* count = nullptr;  // resident bytes of the owning handle (nullptr: transient)
+};
+thread_local const AllocCtx* g_actx = nullptr;
+struct AllocScope {
+  const AllocCtx* prev;
+  explicit AllocScope(const AllocCtx* c) : prev(g_actx) { g_actx = c; }
+  ~AllocScope() { g_actx = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+static void* dev_alloc(size_t b, const AllocCtx& c) {
+  void* p = nullptr;
+  if (c.al.alloc) {
+    p = c.al.alloc(b, c.al.ctx);
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255)) {
+      c.al.free(p, c.al.ctx);
+      throw DeviceError("the caller's allocator returned memory not aligned to 256 bytes");
+    }
+  } else if (hipMalloc(&p, b) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p && c.count) *c.count += b;
+  return p;
+}
+static void dev_free(void* p, size_t b, const AllocCtx& c) {
+  if (!p) return;
+  if (c.al.alloc) c.al.free(p, c.al.ctx);
+  else (void)hipFree(p);
+  if (c.count) *c.count -= b;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  AllocCtx ctx{};
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    dev_free(p, bytes, ctx);
     p = nullptr;
     bytes = 0;
   }
   void alloc(size_t b) {
     reset();
     if (b == 0) b = 8;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw OomError{"hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e)};
-    }
+    ctx = g_actx ? *g_actx : AllocCtx{};
+    p = dev_alloc(b, ctx);
+    if (!p) throw OomError{"device allocation of " + std::to_string(b) + " bytes failed"};
     bytes = b;
   }
   template <class T>
@@ -107,9 +145,10 @@ struct WsStack {
   std::vector<Slab> slabs;
   size_t cur = 0, off = 0;
   size_t peak = 0, used_total = 0;
+  AllocCtx ctx = g_actx ? *g_actx : AllocCtx{};
   static constexpr size_t SLAB = (size_t)256 << 20;
   ~WsStack() {
-    for (auto& s : slabs) (void)hipFree(s.p);
+    for (auto& s : slabs) dev_free(s.p, s.cap, ctx);
   }
   struct Mark {
     size_t cur, off, used;
@@ -139,12 +178,8 @@ struct WsStack {
       }
       if (cur >= slabs.size() || slabs[cur].cap < bytes) {
         size_t cap = std::max(SLAB, bytes);
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, cap);
-        if (e != hipSuccess) {
-          (void)hipGetLastError();
-          throw OomError{"workspace allocation failed"};
-        }
+        void* p = dev_alloc(cap, ctx);
+        if (!p) throw OomError{"workspace allocation failed"};
         if (cur < slabs.size()) slabs.insert(slabs.begin() + cur, Slab{(char*)p, cap});
         else slabs.push_back(Slab{(char*)p, cap});
         off = 0;
@@ -347,7 +382,65 @@ struct Plan {
   std::vector<LuInvItem> luinv;
   DevBuf djobs, dproj, dgath, ddprod, dterms, ddflush, dltg, dlgram, dlexp, dcopies, dgetrf, dluinv;
 
+  // Host-side check of the plan before it reaches the device: every phase's
+  // item range lies inside its array, every term of a rounded addition or
+  // dense flush has at least one row and one column inside its target and
+  // non-null factors.  Violations are planner bugs: they become an error
+  // instead of an out-of-bounds access on the device.
+  void validate() const {
+    auto bad = [](const std::string& what) { throw DeviceError("internal: plan check failed: " + what); };
+    auto in_range = [&](int b, int n, size_t size, const char* what) {
+      if (b < 0 || n < 0 || (size_t)b + (size_t)n > size) bad(std::string(what) + " item range");
+    };
+    auto check_terms = [&](int tbeg, int tcount, int m, int n) {
+      in_range(tbeg, tcount, terms.size(), "term");
+      for (int t = tbeg; t < tbeg + tcount; ++t) {
+        const Term& tm = terms[t];
+        if (tm.mr < 1 || tm.nc < 1 || tm.ro < 0 || tm.co < 0 || tm.ro + tm.mr > m || tm.co + tm.nc > n)
+          bad("term outside its target");
+        if (!tm.U || (tm.dense != 1 && !tm.W)) bad("null term factor");
+        if (tm.dense == 2 && tm.kfix < 1) bad("product term without inner dimension");
+        if (tm.dense == 0 && !tm.k && tm.kfix < 0) bad("negative term rank");
+      }
+    };
+    for (const LFlushTarget& T : ltg) {
+      if (T.m < 1 || T.n < 1 || !T.U || !T.V || T.kcap < 0 || T.Kcap > KMAX || !T.info) bad("low-rank target");
+      if (T.tcount > 64) bad("more than 64 terms in one rounded addition");
+      check_terms(T.tbeg, T.tcount, T.m, T.n);
+    }
+    for (const DFlushItem& D : dflush) {
+      if (D.m < 1 || D.n < 1 || D.m > 64 || D.n > 64 || !D.D) bad("dense target");
+      check_terms(D.tbeg, D.tcount, D.m, D.n);
+    }
+    for (const ChunkItem& c : lgram)
+      if (c.tgt < 0 || c.r0 < 0 || c.r1 <= c.r0) bad("Gram chunk");
+    for (const ChunkItem& c : lexp)
+      if (c.tgt < 0 || c.r0 < 0 || c.r1 <= c.r0) bad("expand chunk");
+    for (const Phase& p : ph) {
+      switch (p.type) {
+        case PH_APPLY: in_range(p.b0, p.n0, proj.size(), "projection"); in_range(p.b1, p.n1, gath.size(), "gather"); break;
+        case PH_DPROD: in_range(p.b0, p.n0, dprod.size(), "product"); break;
+        case PH_DFLUSH: in_range(p.b0, p.n0, dflush.size(), "dense flush"); break;
+        case PH_LFLUSH:
+          in_range(p.b0, p.n0, ltg.size(), "low-rank target");
+          in_range(p.b1, p.n1, lgram.size(), "Gram chunk");
+          in_range(p.b2, p.n2, lexp.size(), "expand chunk");
+          for (int q = p.b1; q < p.b1 + p.n1; ++q)
+            if (lgram[q].tgt >= p.n0) bad("Gram chunk target");
+          for (int q = p.b2; q < p.b2 + p.n2; ++q)
+            if (lexp[q].tgt >= p.n0) bad("expand chunk target");
+          break;
+        case PH_RADD: in_range(p.b0, p.n0, ltg.size(), "fused target"); in_range(p.b1, p.n1, dflush.size(), "dense flush"); break;
+        case PH_COPY: in_range(p.b0, p.n0, copies.size(), "copy"); break;
+        case PH_GETRF: in_range(p.b0, p.n0, getrf.size(), "leaf factorisation"); break;
+        case PH_LUINV: in_range(p.b0, p.n0, luinv.size(), "diagonal node"); break;
+        default: break;
+      }
+    }
+  }
+
   void upload_all(hipStream_t s) {
+    validate();
     upload(djobs, jobs, s);
     upload(dproj, proj, s);
     upload(dgath, gath, s);
@@ -1373,6 +1466,73 @@ struct MvPlan {
   void run(const double* x, const MvEpi& e, hipStream_t s) const { HL_CHECK(mv_launch(dev, x, e, s)); }
 };
 
+// Bytes MvPlan::create allocates for a matrix of layout M with every
+// low-rank leaf at rank kcap (the most it can hold), maximised over the
+// rank buckets the plan may choose: an upper bound of the actual plan.
+static size_t mvplan_bytes_bound(const Structure& S, const HMat& M, bool f32) {
+  auto round8 = [](size_t b) { return std::max<size_t>(b, 8); };
+  size_t best = 0;
+  for (int kb : {8, 16, 32}) {
+    int64_t ntiles = 0, nents = 0, nslots = 0;
+    std::vector<int32_t> np(S.lf.size(), 0);
+    for (size_t l = 0; l < S.lf.size(); ++l) {
+      const LeafDesc& d = M.L[l];
+      if (d.kind != K_LR || d.kcap == 0) continue;
+      const int k = d.kcap;
+      const int rpp = project_rows_per_pass(kb, f32);
+      const int npass = (d.n + rpp - 1) / rpp;
+      const int per = (npass + MV_PMAX - 1) / MV_PMAX;
+      const int P = (npass + per - 1) / per;
+      np[l] = P;
+      const int nch = (k + kb - 1) / kb;
+      const int tw = project_width(kb);
+      for (int ch = 0; ch < nch; ++ch) {
+        const int kc = std::min(kb, k - ch * kb);
+        ntiles += (int64_t)P * ((kc + tw - 1) / tw);
+      }
+      nslots += (int64_t)nch * P;
+    }
+    for (size_t q = 0; q < S.leafcl.size(); ++q)
+      for (int e = S.rowptr[q]; e < S.rowptr[q + 1]; ++e) {
+        const LeafDesc& d = M.L[S.rowidx[e]];
+        if (d.kind == K_DENSE) nents += (d.n + MV_DCOLS - 1) / MV_DCOLS;
+        else if (d.kind == K_LR && d.kcap > 0) nents += (d.kcap + kb - 1) / kb;
+      }
+    size_t b = round8(ntiles * sizeof(MvTile)) + round8(nents * sizeof(MvEntry)) +
+               round8(S.leafcl.size() * sizeof(MvRow)) + (size_t)std::max<int64_t>(nslots, 1) * kb * sizeof(double);
+    best = std::max(best, b);
+  }
+  if (f32) best += std::max<size_t>(M.pool_doubles, 1) * sizeof(float);
+  return best;
+}
+
+// Resident bytes of an operator (G with its structure lists, product plan
+// and work vectors) and of one factor (the inverse factors, their product
+// plans with FP32 copies on the mixed path, the G plan and work vectors):
+// the allocations of assemble_ops and factor_group, with every low-rank
+// block at its rank capacity.
+static size_t footprint_bytes(const Structure& S, int kcap, bool mixed) {
+  auto round8 = [](size_t b) { return std::max<size_t>(b, 8); };
+  const size_t P = S.leafcl.size(), nl = S.lf.size(), N = S.N;
+  auto hmat = [&](const HMat& t) {
+    return round8(t.pool_doubles * sizeof(double)) + round8(nl * sizeof(LeafDesc)) + round8(nl * sizeof(int32_t));
+  };
+  size_t b = 0;
+  // structure lists, constants, overflow counter
+  b += 2 * round8((P + 1) * 4) + round8(S.rowidx.size() * 4) + round8(S.colidx.size() * 4) + 2 * round8(P * 4) +
+       round8(N * 4) + 64 * 64 * sizeof(double) + 32 + 8;
+  HMat g;
+  g.layout(S, kcap, FULL, false);
+  b += hmat(g) + 2 * N * sizeof(double) + mvplan_bytes_bound(S, g, false);
+  // the factor
+  HMat li, ui;
+  li.layout(S, kcap, LOWER, false);
+  ui.layout(S, kcap, UPPER, false);
+  b += hmat(li) + hmat(ui) + 7 * N * sizeof(double);
+  b += mvplan_bytes_bound(S, g, false) + mvplan_bytes_bound(S, li, mixed) + mvplan_bytes_bound(S, ui, mixed);
+  return b;
+}
+
 // Products with one matrix kind (G, L^{-1} or U^{-1}) of every problem of a
 // batch: problems grouped by rank bucket, dense precision and member bound
 // (1, 2 or the most a launch takes), one projection and one gather launch
@@ -1441,6 +1601,8 @@ static std::vector<int32_t> read_ranks(const HMat& M, hipStream_t s) {
 using namespace hl;
 
 struct hlevy_op {
+  size_t bytes = 0;    // resident device bytes (declared first: freed last)
+  AllocCtx actx{};     // the caller's allocator and this handle's byte counter
   hlevy_problem prob{};
   hlevy_hparams hp{};
   Structure S;
@@ -1453,6 +1615,8 @@ struct hlevy_op {
 };
 
 struct hlevy_fac {
+  size_t bytes = 0;    // resident device bytes (declared first: freed last)
+  AllocCtx actx{};     // the operator's allocator and this handle's byte counter
   const hlevy_op* op = nullptr;
   double dt = 0, lu_tol = 0;
   int prec = 0;
@@ -1483,16 +1647,45 @@ static double frac_constant(int d, double s) {
   return std::pow(4.0, s) * std::tgamma(d / 2.0 + s) / (std::pow(M_PI, d / 2.0) * std::fabs(std::tgamma(-s)));
 }
 
+// Device slots of the residual checks of a call: (||r||^2, ||b||^2) per
+// check, plus the partial sums of the norm kernels (reused in stream order).
+struct CheckBuf {
+  DevBuf slots, partial;
+  int cap = 0;
+  void reserve(int count, int N) {
+    cap = std::max(count, 1);
+    slots.alloc((size_t)2 * cap * sizeof(double));
+    partial.alloc((size_t)2 * check_blocks(N) * sizeof(double));
+  }
+  double* slot(int i) const { return slots.as<double>() + 2 * (size_t)i; }
+  // waits for the stream
+  std::vector<double> read(int count, hipStream_t s) const {
+    std::vector<double> v((size_t)2 * count);
+    if (count > 0)
+      HL_CHECK(hipMemcpyAsync(v.data(), slots.p, v.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HL_CHECK(hipStreamSynchronize(s));
+    return v;
+  }
+};
+static double rel_residual(double r2, double b2) {
+  if (b2 > 0.0) return std::sqrt(r2 / b2);
+  return r2 > 0.0 ? INFINITY : 0.0;
+}
+
 // One problem advanced by step_states: its factor, its vectors (cluster
 // order: u^n, the iterate w, two temporaries), optionally its own
 // projection partial buffers for G, L^{-1}, U^{-1} (null: the plans' own;
 // problems that share a factor in one batch need buffers of their own) and
 // its number of steps (negative: all steps of the call).
+// check: the state's last step measures the relative residual of its
+// final iterate (one more product with G) into *rel (host).
 struct StepState {
   hlevy_fac* f;
   double *uc, *w, *z, *r;
   double *partG, *partL, *partU;
   int64_t steps = -1;
+  bool check = false;
+  double* rel = nullptr;
 };
 
 // Unforced Crank-Nicolson steps of every state (hlevy_step's recursion:
@@ -1500,8 +1693,11 @@ struct StepState {
 // one batched launch pair over all states.  States of one factor that have
 // partial buffers of their own are taken as members of one batched problem
 // (up to the launch's member bound, longest remaining first), so that their
-// products read the factor once.  Synchronises `s` before return (the
-// tables are freed here).
+// products read the factor once.  The last step of a checking state runs
+// after the loop, with every checking state together: its last sweep
+// updates w (the same arithmetic as the fused update of u^{n+1}), the
+// residual of w is measured, then u^{n+1} = w - u^n.  Synchronises `s`
+// before return (the tables are freed here).
 static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sweeps, hipStream_t s) {
   if (st.empty() || nsteps == 0) return;
   if (nsteps > INT32_MAX) throw DeviceError("internal: too many steps in one batched call");
@@ -1545,7 +1741,11 @@ static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sw
   bL.create(pl, nrs, s);
   bU.create(pu, nrs, s);
   enum { T_AXPY, T_SUB, T_W, T_RES, T_LI, T_ADD, T_NEXT, T_COUNT };
-  std::vector<std::vector<MvInst>> tab(T_COUNT);
+  // tab: the loop (a checking state's last step left out); fin: the last
+  // step of the checking states (the others sit out)
+  std::vector<std::vector<MvInst>> tab(T_COUNT), fin(T_COUNT);
+  bool any_check = false;
+  for (const StepState& x : st) any_check = any_check || (x.check && steps_of(x) > 0);
   for (auto& pr : probs) {
     hlevy_fac* f = st[pr[0]].f;
     std::vector<MvInst> t(T_COUNT);
@@ -1560,7 +1760,7 @@ static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sw
       double* pL = x.partL ? x.partL : f->mvLi.dev.part;
       double* pU = x.partU ? x.partU : f->mvUi.dev.part;
       for (int k = 0; k < T_COUNT; ++k) {
-        t[k].steps[m] = steps_of(x);
+        t[k].steps[m] = steps_of(x) - (x.check && steps_of(x) > 0 ? 1 : 0);
         t[k].part[m] = (k == T_RES) ? pG : ((k == T_AXPY || k == T_LI) ? pL : pU);
         t[k].epi[m] = MvEpi{};
       }
@@ -1599,11 +1799,21 @@ static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sw
       t[T_NEXT].epi[m].u = x.uc;
       t[T_NEXT].epi[m].y = x.uc;
     }
-    for (int k = 0; k < T_COUNT; ++k) tab[k].push_back(t[k]);
+    for (int k = 0; k < T_COUNT; ++k) {
+      tab[k].push_back(t[k]);
+      for (size_t m = 0; m < pr.size(); ++m) {
+        const StepState& x = st[pr[m]];
+        t[k].steps[m] = (x.check && steps_of(x) > 0) ? 1 : 0;
+      }
+      fin[k].push_back(t[k]);
+    }
   }
-  std::vector<DevBuf> dtab(T_COUNT);
+  std::vector<DevBuf> dtab(T_COUNT), dfin(T_COUNT);
   for (int k = 0; k < T_COUNT; ++k) upload(dtab[k], tab[k], s);
+  if (any_check)
+    for (int k = 0; k < T_COUNT; ++k) upload(dfin[k], fin[k], s);
   auto T = [&](int k) { return dtab[k].as<MvInst>(); };
+  auto F = [&](int k) { return dfin[k].as<MvInst>(); };
   for (int64_t n = 0; n < nsteps; ++n) {
     const int k = (int)n;
     bL.run(T(T_AXPY), k, s);
@@ -1617,6 +1827,36 @@ static void step_states(const std::vector<StepState>& st, int64_t nsteps, int sw
       bL.run(T(T_LI), k, s);
       bU.run(T(it + 1 < sweeps ? T_ADD : T_NEXT), k, s);
     }
+  }
+  if (any_check) {
+    // the checking states' last step: w by `sweeps` updates, the residual
+    // of w, its norms, then u^{n+1} = w - u^n
+    bL.run(F(T_AXPY), 0, s);
+    bU.run(F(T_W), 0, s);
+    for (int it = 0; it < sweeps; ++it) {
+      bG.run(F(T_RES), 0, s);
+      bL.run(F(T_LI), 0, s);
+      bU.run(F(T_ADD), 0, s);
+    }
+    bG.run(F(T_RES), 0, s);
+    std::vector<int> chk;
+    int nmax = 1;
+    for (size_t i = 0; i < st.size(); ++i)
+      if (st[i].check && steps_of(st[i]) > 0) {
+        chk.push_back((int)i);
+        nmax = std::max(nmax, st[i].f->op->S.N);
+      }
+    CheckBuf cb;
+    cb.reserve((int)chk.size(), nmax);
+    for (size_t q = 0; q < chk.size(); ++q) {
+      const StepState& x = st[chk[q]];
+      const int N = x.f->op->S.N;
+      HL_CHECK(launch_check_norms(x.r, x.uc, 2.0, nullptr, 0.0, N, cb.partial.as<double>(), cb.slot((int)q), s));
+      HL_CHECK(launch_wsub(x.uc, x.w, N, s));
+    }
+    const std::vector<double> v = cb.read((int)chk.size(), s);
+    for (size_t q = 0; q < chk.size(); ++q)
+      if (st[chk[q]].rel) *st[chk[q]].rel = rel_residual(v[2 * q], v[2 * q + 1]);
   }
   // the tables and maps are freed on return: wait for the device first
   HL_CHECK(hipStreamSynchronize(s));
@@ -1680,8 +1920,11 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
     w->Li.create_in(arena, S, kc, LOWER, s, dmax);
     w->Ui.create_in(arena, S, kc, UPPER, s, dmax);
     w->TMP.create_in(arena, S, kc, FULL, s, dmax);
-    f->Li.create(S, kc, LOWER, s);
-    f->Ui.create(S, kc, UPPER, s);
+    {
+      AllocScope own(&f->actx);
+      f->Li.create(S, kc, LOWER, s);
+      f->Ui.create(S, kc, UPPER, s);
+    }
     w->ctx = LuCtx{&f->LU, &w->Li, &w->Ui, &w->TMP};
     wk.push_back(std::move(w));
   }
@@ -1779,11 +2022,19 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
   HL_CHECK(hipMemcpy(&zp, zpb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
   HL_CHECK(hipMemcpy(&ovf, ovfb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (zp) return fail(HLEVY_ERR_ZERO_PIVOT, "zero pivot in a diagonal leaf of the H-LU");
+  // FP64 factors are the direct solver: a rounded addition truncated at the
+  // rank capacity makes them less accurate than lu_tol says.  The mixed
+  // path's factors only precondition the refinement, which the residual
+  // checks guard; their overflows are reported (hlevy_fac_info, stats).
+  if (ovf > 0 && prec == HLEVY_PREC_FP64)
+    return fail(HLEVY_ERR_RANK_CAP, std::to_string(ovf) + " rounded additions of the FP64 H-LU needed more than "
+                                        "the rank capacity (raise max_rank or lu_tol, or factor in mixed precision)");
   const bool mixed = prec == HLEVY_PREC_MIXED;
   for (hlevy_fac* f : fs) {
     f->rank_overflows = ovf;
     const Structure& S = f->op->S;
     const size_t Nb = (size_t)S.N * sizeof(double);
+    AllocScope own(&f->actx);
     for (DevBuf* b : {&f->w_u, &f->w_y, &f->w_b, &f->w_z, &f->w_r, &f->w_d, &f->w_g}) b->alloc(Nb);
     // residual operator in FP64 on both paths: with the far field in FP32
     // the operator applied to smooth states is off by ~1e-7 relative (the
@@ -1838,192 +2089,300 @@ hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp,
   }
 }
 
-hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, void* stream, hlevy_op** out) {
-  if (!prob || !hp || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  return hlevy_assemble_batched(prob, hp, 1, stream, out);
-}
+}  // extern "C"
 
-hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hparams* hps, int32_t count,
-                                    void* stream, hlevy_op** out) {
-  if (!probs || !hps || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (count < 1) return fail(HLEVY_ERR_INVALID_ARG, "count must be >= 1");
-  for (int32_t i = 0; i < count; ++i) out[i] = nullptr;
-  std::vector<std::unique_ptr<hlevy_op>> ops(count);
-  hlevy_status st = guarded([&]() -> hlevy_status {
-    hipStream_t s = as_stream(stream);
-    HL_CHECK(init_kernel_attributes());
-    // 1. trees on the host; constants, near field and ACA of every problem
-    //    enqueued back to back
-    struct Aca {
-      std::vector<int32_t> lr_ids;
-      std::vector<int64_t> uo, vo;
-      DevBuf buf, rank, dids, lids, duo, dvo;
-    };
-    std::vector<std::unique_ptr<Aca>> aca(count);
-    const int kaca = KMAX;
-    for (int32_t i = 0; i < count; ++i) {
-      const hlevy_problem* prob = probs + i;
-      const hlevy_hparams* hp = hps + i;
-      if (!(prob->r0 < prob->hi - prob->lo)) return fail(HLEVY_ERR_INVALID_ARG, "r0 must be smaller than the domain");
-      auto op = std::make_unique<hlevy_op>();
-      std::string e = build_structure(*prob, *hp, op->S);
-      if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
-      const Structure& S = op->S;
-      for (auto& l : S.lf)
-        if (l.kind == K_LR && std::max(l.m, l.n) > 16384)
-          return fail(HLEVY_ERR_INVALID_ARG, "low-rank blocks are limited to 16384 rows (raise n_block)");
-      op->prob = *prob;
-      op->hp = *hp;
-      ProblemDev& pd = op->pd;
-      pd.dim = prob->dim;
-      pd.n = prob->n;
-      pd.N = S.N;
-      pd.h = S.h;
-      pd.a = prob->a;
-      pd.b0 = prob->b[0];
-      pd.b1 = prob->dim == 2 ? prob->b[1] : 0.0;
-      pd.c = prob->c;
-      pd.s = prob->s;
-      pd.lam = prob->lambda;
-      pd.C = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, prob->s);
-      pd.r0 = prob->r0;
+using SplitSet = std::set<std::pair<int32_t, int32_t>>;
+
+// Assembly of `count` problems (hlevy_assemble_batched).  splits[i]: the
+// admissible blocks of problem i not stored low rank.  After the truncation
+// the per-block overflow counts come back; a problem with blocks whose
+// compression needed more than the rank capacity is assembled again with
+// those blocks subdivided (dense at the leaf level), until none overflows.
+static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams* hps, const SplitSet* splits,
+                                 int32_t count, const hlevy_allocator* al, hipStream_t s,
+                                 std::vector<std::unique_ptr<hlevy_op>>& ops) {
+  ops.clear();
+  ops.resize(count);
+  // 1. trees on the host; constants, near field and ACA of every problem
+  //    enqueued back to back
+  struct Aca {
+    std::vector<int32_t> lr_ids;
+    std::vector<int64_t> uo, vo;
+    DevBuf buf, rank, dids, lids, duo, dvo, blkovf;
+  };
+  std::vector<std::unique_ptr<Aca>> aca(count);
+  const int kaca = KMAX;
+  for (int32_t i = 0; i < count; ++i) {
+    const hlevy_problem* prob = probs + i;
+    const hlevy_hparams* hp = hps + i;
+    auto op = std::make_unique<hlevy_op>();
+    if (al) op->actx.al = *al;
+    op->actx.count = &op->bytes;
+    std::string e = build_structure(*prob, *hp, op->S, splits ? &splits[i] : nullptr);
+    if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
+    const Structure& S = op->S;
+    op->prob = *prob;
+    op->hp = *hp;
+    ProblemDev& pd = op->pd;
+    pd.dim = prob->dim;
+    pd.n = prob->n;
+    pd.N = S.N;
+    pd.h = S.h;
+    pd.a = prob->a;
+    pd.b0 = prob->b[0];
+    pd.b1 = prob->dim == 2 ? prob->b[1] : 0.0;
+    pd.c = prob->c;
+    pd.s = prob->s;
+    pd.lam = prob->lambda;
+    pd.C = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, prob->s);
+    pd.r0 = prob->r0;
+    {
+      AllocScope own(&op->actx);
       op->ds.create(S, s);
       op->cst.alloc(4 * sizeof(double));
       op->ovf.alloc(sizeof(int32_t));
-      HL_CHECK(hipMemsetAsync(op->ovf.p, 0, sizeof(int32_t), s));
-      HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
       op->G.create(S, hp->max_rank, FULL, s);
-      // dense near field
-      auto A = std::make_unique<Aca>();
-      std::vector<int32_t> dense_ids;
-      for (size_t l = 0; l < S.lf.size(); ++l) (S.lf[l].kind == K_DENSE ? dense_ids : A->lr_ids).push_back((int)l);
-      upload(A->dids, dense_ids, s);
-      upload(A->lids, A->lr_ids, s);
-      HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
-                                 A->dids.as<int32_t>(), (int)dense_ids.size(), s));
-      // far field: ACA into scratch (truncated into G below)
-      int64_t tot = 0;
-      for (int l : A->lr_ids) {
-        A->uo.push_back(tot);
-        tot += (int64_t)S.lf[l].m * kaca;
-        A->vo.push_back(tot);
-        tot += (int64_t)S.lf[l].n * kaca;
-      }
-      A->buf.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
-      upload(A->duo, A->uo, s);
-      upload(A->dvo, A->vo, s);
-      A->rank.alloc(std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t));
-      HL_CHECK(launch_aca(pd, op->ds.perm.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(), (int)A->lr_ids.size(),
-                          A->buf.as<double>(), A->buf.as<double>(), A->duo.as<int64_t>(), A->dvo.as<int64_t>(),
-                          A->rank.as<int32_t>(), kaca, 0.1 * hp->aca_tol, s));
-      aca[i] = std::move(A);
-      ops[i] = std::move(op);
     }
-    // 2. truncation of every ACA block to its tolerance: one plan for all
-    //    problems (problems of equal tolerance share launches).  The ACA
-    //    ranks come back first (one synchronisation): with double-double
-    //    parts the fast cores take 48 columns, so an ACA term of rank k is
-    //    split into ceil(k / (48 - kcap)) column pieces, piece p of every
-    //    block applied in round p.
-    std::vector<std::vector<int32_t>> aca_rank(count);
-    for (int32_t i = 0; i < count; ++i) {
-      aca_rank[i].resize(aca[i]->lr_ids.size());
-      if (!aca_rank[i].empty())
-        HL_CHECK(hipMemcpyAsync(aca_rank[i].data(), aca[i]->rank.as<int32_t>(), aca_rank[i].size() * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, s));
+    HL_CHECK(hipMemsetAsync(op->ovf.p, 0, sizeof(int32_t), s));
+    HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
+    // dense near field
+    auto A = std::make_unique<Aca>();
+    std::vector<int32_t> dense_ids;
+    for (size_t l = 0; l < S.lf.size(); ++l) (S.lf[l].kind == K_DENSE ? dense_ids : A->lr_ids).push_back((int)l);
+    upload(A->dids, dense_ids, s);
+    upload(A->lids, A->lr_ids, s);
+    HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
+                               A->dids.as<int32_t>(), (int)dense_ids.size(), s));
+    // far field: ACA into scratch (truncated into G below)
+    int64_t tot = 0;
+    for (int l : A->lr_ids) {
+      A->uo.push_back(tot);
+      tot += (int64_t)S.lf[l].m * kaca;
+      A->vo.push_back(tot);
+      tot += (int64_t)S.lf[l].n * kaca;
     }
-    HL_CHECK(hipStreamSynchronize(s));
-    {
-      std::map<double, std::vector<int32_t>> by_tol;
-      for (int32_t i = 0; i < count; ++i) by_tol[ops[i]->hp.aca_tol].push_back(i);
-      Plan P;
-      WsStack ws;
-      Builder B(P, ws, ops[0]->ds.ident.as<double>(), ops[0]->ovf.as<int32_t>(), hps[0].aca_tol);
-      for (auto& kv : by_tol) {
-        const bool split = radd_dd(kv.first);
-        std::vector<std::vector<LFlushTarget>> tgs(1);
-        std::vector<std::vector<std::vector<Term>>> tl(1);
-        std::vector<std::vector<int32_t*>> ovf(1);
-        for (int32_t i : kv.second) {
-          hlevy_op* op = ops[i].get();
-          const Aca& A = *aca[i];
-          for (size_t q = 0; q < A.lr_ids.size(); ++q) {
-            const LeafDesc& d = op->G.L[A.lr_ids[q]];
-            const int w = split ? std::min(kaca, 48 - d.kcap) : kaca;
-            if (w <= 0) throw DeviceError("internal: rank capacity above 47 with double-double parts");
-            const int kr = aca_rank[i][q];
-            if (kr < 0 || kr > kaca) throw DeviceError("internal: ACA rank out of range");
-            // at least one piece: a block of rank 0 is still truncated (to rank 0)
-            const int kend = split ? std::max(kr, 1) : kaca;
-            for (int c0 = 0, piece = 0; c0 < kend; c0 += w, ++piece) {
-              LFlushTarget T{};
-              T.U = d.A;
-              T.V = d.B;
-              T.rank = op->G.rank + A.lr_ids[q];
-              T.m = d.m;
-              T.n = d.n;
-              T.kcap = d.kcap;
-              const int kl = std::min(w, kend - c0);
-              T.Kcap = split ? d.kcap + kl : kaca;
-              Term t{};
-              t.dense = 0;
-              t.ro = 0;
-              t.mr = d.m;
-              t.co = 0;
-              t.nc = d.n;
-              t.U = A.buf.as<double>() + A.uo[q] + (size_t)d.m * c0;
-              t.ldu = d.m;
-              t.W = A.buf.as<double>() + A.vo[q] + (size_t)d.n * c0;
-              t.ldw = d.n;
-              t.k = A.rank.as<int32_t>() + q;
-              t.sign = 1.0;
-              if (split) {
-                t.kofs = c0;
-                t.klim = kl;
-              }
-              if ((int)tgs.size() <= piece) {
-                tgs.resize(piece + 1);
-                tl.resize(piece + 1);
-                ovf.resize(piece + 1);
-              }
-              tgs[piece].push_back(T);
-              tl[piece].push_back({t});
-              ovf[piece].push_back(op->ovf.as<int32_t>());
+    A->buf.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
+    upload(A->duo, A->uo, s);
+    upload(A->dvo, A->vo, s);
+    A->rank.alloc(std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t));
+    // per-block overflow counts of the truncation
+    A->blkovf.alloc(std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t));
+    HL_CHECK(hipMemsetAsync(A->blkovf.p, 0, std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t), s));
+    HL_CHECK(launch_aca(pd, op->ds.perm.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(), (int)A->lr_ids.size(),
+                        A->buf.as<double>(), A->buf.as<double>(), A->duo.as<int64_t>(), A->dvo.as<int64_t>(),
+                        A->rank.as<int32_t>(), kaca, 0.1 * hp->aca_tol, s));
+    aca[i] = std::move(A);
+    ops[i] = std::move(op);
+  }
+  // 2. truncation of every ACA block to its tolerance: one plan for all
+  //    problems (problems of equal tolerance share launches).  The ACA
+  //    ranks come back first (one synchronisation): with double-double
+  //    parts the fast cores take 48 columns, so an ACA term of rank k is
+  //    split into ceil(k / (48 - kcap)) column pieces, piece p of every
+  //    block applied in round p.
+  std::vector<std::vector<int32_t>> aca_rank(count);
+  for (int32_t i = 0; i < count; ++i) {
+    aca_rank[i].resize(aca[i]->lr_ids.size());
+    if (!aca_rank[i].empty())
+      HL_CHECK(hipMemcpyAsync(aca_rank[i].data(), aca[i]->rank.as<int32_t>(), aca_rank[i].size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+  }
+  HL_CHECK(hipStreamSynchronize(s));
+  {
+    std::map<double, std::vector<int32_t>> by_tol;
+    for (int32_t i = 0; i < count; ++i) by_tol[ops[i]->hp.aca_tol].push_back(i);
+    Plan P;
+    WsStack ws;
+    Builder B(P, ws, ops[0]->ds.ident.as<double>(), ops[0]->ovf.as<int32_t>(), hps[0].aca_tol);
+    for (auto& kv : by_tol) {
+      const bool split = radd_dd(kv.first);
+      std::vector<std::vector<LFlushTarget>> tgs(1);
+      std::vector<std::vector<std::vector<Term>>> tl(1);
+      std::vector<std::vector<int32_t*>> ovf(1);
+      for (int32_t i : kv.second) {
+        hlevy_op* op = ops[i].get();
+        const Aca& A = *aca[i];
+        for (size_t q = 0; q < A.lr_ids.size(); ++q) {
+          const LeafDesc& d = op->G.L[A.lr_ids[q]];
+          const int w = split ? std::min(kaca, 48 - d.kcap) : kaca;
+          if (w <= 0) throw DeviceError("internal: rank capacity above 47 with double-double parts");
+          const int kr = aca_rank[i][q];
+          if (kr < 0 || kr > kaca) throw DeviceError("internal: ACA rank out of range");
+          // at least one piece: a block of rank 0 is still truncated (to rank 0)
+          const int kend = split ? std::max(kr, 1) : kaca;
+          for (int c0 = 0, piece = 0; c0 < kend; c0 += w, ++piece) {
+            LFlushTarget T{};
+            T.U = d.A;
+            T.V = d.B;
+            T.rank = op->G.rank + A.lr_ids[q];
+            T.m = d.m;
+            T.n = d.n;
+            T.kcap = d.kcap;
+            const int kl = std::min(w, kend - c0);
+            T.Kcap = split ? d.kcap + kl : kaca;
+            Term t{};
+            t.dense = 0;
+            t.ro = 0;
+            t.mr = d.m;
+            t.co = 0;
+            t.nc = d.n;
+            t.U = A.buf.as<double>() + A.uo[q] + (size_t)d.m * c0;
+            t.ldu = d.m;
+            t.W = A.buf.as<double>() + A.vo[q] + (size_t)d.n * c0;
+            t.ldw = d.n;
+            t.k = A.rank.as<int32_t>() + q;
+            t.sign = 1.0;
+            if (split) {
+              t.kofs = c0;
+              t.klim = kl;
             }
+            if ((int)tgs.size() <= piece) {
+              tgs.resize(piece + 1);
+              tl.resize(piece + 1);
+              ovf.resize(piece + 1);
+            }
+            tgs[piece].push_back(T);
+            tl[piece].push_back({t});
+            ovf[piece].push_back(A.blkovf.as<int32_t>() + q);
           }
         }
-        for (size_t piece = 0; piece < tgs.size(); ++piece) {
-          // every problem's overflow counter: targets carry their own below
-          std::vector<int> where = B.emit_lflush(tgs[piece], tl[piece], kv.first);
-          for (size_t q = 0; q < where.size(); ++q) P.ltg[where[q]].overflow = ovf[piece][q];
-        }
       }
-      P.upload_all(s);
-      P.run(nullptr, s);
-      HL_CHECK(hipStreamSynchronize(s));
+      for (size_t piece = 0; piece < tgs.size(); ++piece) {
+        // each target counts its overflows in its block's own counter
+        std::vector<int> where = B.emit_lflush(tgs[piece], tl[piece], kv.first);
+        for (size_t q = 0; q < where.size(); ++q) P.ltg[where[q]].overflow = ovf[piece][q];
+      }
     }
-    // 3. ranks back in one round, then the per-step product plans
-    std::vector<std::vector<int32_t>> rk(count);
-    for (int32_t i = 0; i < count; ++i) {
-      rk[i].resize(ops[i]->G.L.size());
-      if (!rk[i].empty())
-        HL_CHECK(hipMemcpyAsync(rk[i].data(), ops[i]->G.rank, rk[i].size() * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                s));
-    }
+    P.upload_all(s);
+    P.run(nullptr, s);
     HL_CHECK(hipStreamSynchronize(s));
-    for (int32_t i = 0; i < count; ++i) {
-      hlevy_op* op = ops[i].get();
-      op->xbuf.alloc((size_t)op->S.N * sizeof(double));
-      op->ybuf.alloc((size_t)op->S.N * sizeof(double));
-      op->mv.create(op->S, op->G, rk[i], false, false, s);
+  }
+  // 3. blocks over the rank capacity: their problems are assembled again
+  //    with those blocks subdivided
+  std::vector<int32_t> redo;
+  std::vector<SplitSet> redo_split;
+  for (int32_t i = 0; i < count; ++i) {
+    const Aca& A = *aca[i];
+    std::vector<int32_t> bo(A.lr_ids.size(), 0);
+    if (!bo.empty())
+      HL_CHECK(hipMemcpy(bo.data(), A.blkovf.p, bo.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    SplitSet sp = ops[i]->S.split;
+    bool more = false;
+    for (size_t q = 0; q < bo.size(); ++q)
+      if (bo[q] > 0) {
+        const LeafInfo& li = ops[i]->S.lf[A.lr_ids[q]];
+        more = sp.insert({li.r, li.c}).second || more;
+      }
+    if (more) {
+      redo.push_back(i);
+      redo_split.push_back(std::move(sp));
     }
-    aca.clear();
-    HL_CHECK(hipStreamSynchronize(s));
-    return HLEVY_OK;
+  }
+  if (!redo.empty()) {
+    std::vector<hlevy_problem> rp;
+    std::vector<hlevy_hparams> rh;
+    for (int32_t i : redo) {
+      rp.push_back(probs[i]);
+      rh.push_back(hps[i]);
+    }
+    std::vector<std::unique_ptr<hlevy_op>> again;
+    hlevy_status st = assemble_ops(rp.data(), rh.data(), redo_split.data(), (int32_t)redo.size(), al, s, again);
+    if (st != HLEVY_OK) return st;
+    for (size_t q = 0; q < redo.size(); ++q) {
+      ops[redo[q]] = std::move(again[q]);
+      aca[redo[q]].reset();
+    }
+  }
+  // 4. ranks back in one round, then the per-step product plans
+  std::vector<std::vector<int32_t>> rk(count);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!aca[i]) continue;   // assembled again above
+    rk[i].resize(ops[i]->G.L.size());
+    if (!rk[i].empty())
+      HL_CHECK(hipMemcpyAsync(rk[i].data(), ops[i]->G.rank, rk[i].size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              s));
+  }
+  HL_CHECK(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < count; ++i) {
+    if (!aca[i]) continue;
+    hlevy_op* op = ops[i].get();
+    AllocScope own(&op->actx);
+    op->xbuf.alloc((size_t)op->S.N * sizeof(double));
+    op->ybuf.alloc((size_t)op->S.N * sizeof(double));
+    op->mv.create(op->S, op->G, rk[i], false, false, s);
+  }
+  aca.clear();
+  HL_CHECK(hipStreamSynchronize(s));
+  return HLEVY_OK;
+}
+
+extern "C" {
+
+hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp, const hlevy_allocator* al,
+                            void* stream, hlevy_op** out) {
+  if (!prob || !hp || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  return hlevy_assemble_batched(prob, hp, 1, al, stream, out);
+}
+
+hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hparams* hps, int32_t count,
+                                    const hlevy_allocator* al, void* stream, hlevy_op** out) {
+  if (!probs || !hps || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (count < 1) return fail(HLEVY_ERR_INVALID_ARG, "count must be >= 1");
+  if (al && (!al->alloc || !al->free)) return fail(HLEVY_ERR_INVALID_ARG, "allocator needs alloc and free");
+  for (int32_t i = 0; i < count; ++i) out[i] = nullptr;
+  std::vector<std::unique_ptr<hlevy_op>> ops;
+  hlevy_status st = guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    HL_CHECK(init_kernel_attributes());
+    // transient buffers of the call go through the caller's allocator too
+    AllocCtx call{};
+    if (al) call.al = *al;
+    AllocScope sc(&call);
+    return assemble_ops(probs, hps, nullptr, count, al, s, ops);
   });
   if (st != HLEVY_OK) return st;
   for (int32_t i = 0; i < count; ++i) out[i] = ops[i].release();
   return HLEVY_OK;
+}
+
+hlevy_status hlevy_footprint(const hlevy_problem* prob, const hlevy_hparams* hp, int32_t prec, size_t* bytes_out) {
+  if (!prob || !hp || !bytes_out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
+  try {
+    Structure S;
+    std::string e = build_structure(*prob, *hp, S);
+    if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
+    *bytes_out = footprint_bytes(S, hp->max_rank, prec == HLEVY_PREC_MIXED);
+    return HLEVY_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(HLEVY_ERR_OOM, "host allocation failed");
+  }
+}
+
+hlevy_status hlevy_fac_info(const hlevy_fac* f, hlevy_fac_info_t* out, void* stream) {
+  if (!f || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  return guarded([&]() -> hlevy_status {
+    std::memset(out, 0, sizeof(*out));
+    out->device_bytes = f->bytes;
+    out->rank_overflows = f->rank_overflows;
+    int mx = 0;
+    for (const HMat* M : {&f->Li, &f->Ui}) {
+      std::vector<int32_t> rk(M->L.size());
+      if (!rk.empty())
+        HL_CHECK(hipMemcpyAsync(rk.data(), M->rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                as_stream(stream)));
+      HL_CHECK(hipStreamSynchronize(as_stream(stream)));
+      for (size_t l = 0; l < rk.size(); ++l)
+        if (M->L[l].kind == K_LR) mx = std::max(mx, rk[l]);
+    }
+    out->max_rank = mx;
+    const MvPlan* pl[3] = {&f->mvG, &f->mvLi, &f->mvUi};
+    for (int w = 0; w < 3; ++w) out->product_bytes[w] = (double)pl[w]->matrix_bytes;
+    out->lu_tol = f->lu_tol;
+    out->dt = f->dt;
+    out->prec = f->prec;
+    return HLEVY_OK;
+  });
 }
 
 hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream) {
@@ -2063,6 +2422,8 @@ hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* strea
     out->max_rank = mx;
     out->mean_rank = cnt ? sum / cnt : 0.0;
     out->rank_overflows = ov;
+    out->device_bytes = op->bytes;
+    out->subdivided_blocks = (int32_t)op->S.split.size();
     return HLEVY_OK;
   });
 }
@@ -2111,8 +2472,12 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
   std::vector<std::unique_ptr<hlevy_fac>> fs(count);
   hlevy_status st = guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
+    // transient buffers of the call: the first operator's allocator
+    AllocCtx call{ops[0]->actx.al, nullptr};
+    AllocScope sc(&call);
     for (int32_t i = 0; i < count; ++i) {
       fs[i] = std::make_unique<hlevy_fac>();
+      fs[i]->actx = AllocCtx{ops[i]->actx.al, &fs[i]->bytes};
       fs[i]->op = ops[i];
       fs[i]->dt = dt[i];
       fs[i]->prec = prec;
@@ -2145,33 +2510,6 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
   return HLEVY_OK;
 }
 
-// y = U^{-1} (L^{-1} x): forward then backward solve through the inverse
-// factors (cluster order); `add` accumulates into y instead (y = u + ...).
-static void fac_apply_inverse(hlevy_fac* f, const double* x, double* y, const double* add_to, hipStream_t s) {
-  f->mvLi.run(x, epi_plain(f->w_z.as<double>()), s);
-  MvEpi e = epi_plain(y);
-  if (add_to) {
-    e.kind = MV_EPI_ADD;
-    e.u = add_to;
-  }
-  f->mvUi.run(f->w_z.as<double>(), e, s);
-}
-
-// Refinement sweeps for M x = b (x in/out, cluster order):
-// x <- x + U^{-1} L^{-1} (b - M x), residual with the operator G.
-static void refine_sweeps(hlevy_fac* f, const double* b, double* x, int sweeps, hipStream_t s) {
-  for (int it = 0; it < sweeps; ++it) {
-    MvEpi r{};
-    r.kind = MV_EPI_RESID;
-    r.hdt = 0.5 * f->dt;
-    r.u = x;
-    r.b = b;
-    r.y = f->w_y.as<double>();
-    f->mvG.run(x, r, s);
-    fac_apply_inverse(f, f->w_y.as<double>(), x, x, s);
-  }
-}
-
 // Refinement sweeps when the caller gives none.  FP64 factors take one
 // sweep too: products with the explicit inverse factors lose accuracy like
 // eps * cond(L) * cond(U), which grows like N^2 on diffusion-dominated
@@ -2182,18 +2520,212 @@ static int default_sweeps(const hlevy_fac* f, const hlevy_refine* refine) {
   return f->prec == HLEVY_PREC_MIXED ? 2 : 1;
 }
 
-hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, const hlevy_refine* refine, void* stream) {
+static const char* refine_error(const hlevy_refine* r) {
+  if (!r) return nullptr;
+  if (r->sweeps < 0 || r->sweeps > 64) return "sweeps in [0, 64]";
+  if (r->max_sweeps < 0 || r->max_sweeps > 64) return "max_sweeps in [0, 64]";
+  if (r->check_every < 0) return "check_every must be >= 0";
+  if (std::isnan(r->tol) || std::isinf(r->tol)) return "tol must be finite";
+  return nullptr;
+}
+
+struct CheckLog {
+  hlevy_stats* st;
+  void begin(const hlevy_fac* f) {
+    if (!st) return;
+    std::memset(st, 0, sizeof(*st));
+    st->last_rel_residual = -1.0;
+    st->max_rel_residual = -1.0;
+    st->rank_overflows = f->rank_overflows;
+  }
+  void note(double rel, int sweeps) {
+    if (!st) return;
+    st->checks++;
+    st->last_rel_residual = rel;
+    if (!(st->max_rel_residual >= rel)) st->max_rel_residual = rel;
+    st->max_sweeps_used = std::max(st->max_sweeps_used, sweeps);
+  }
+};
+
+hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, int64_t nrhs, int64_t ld,
+                         const hlevy_refine* refine, hlevy_stats* stats, void* stream) {
   if (!f || !b || !x) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (b == x) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not alias");
-  if (refine && (refine->sweeps < 0 || refine->sweeps > 64)) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
+  const int64_t N = f->op->S.N;
+  if (nrhs < 1) return fail(HLEVY_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (ld < N) return fail(HLEVY_ERR_INVALID_ARG, "ld must be >= N");
+  {
+    const double* bl = b;
+    const double* bh = b + (size_t)(nrhs - 1) * ld + N;
+    const double* xl = x;
+    const double* xh = x + (size_t)(nrhs - 1) * ld + N;
+    if (bl < xh && xl < bh) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not overlap");
+  }
+  if (const char* e = refine_error(refine)) return fail(HLEVY_ERR_INVALID_ARG, e);
+  const double t_start = now_s();
+  CheckLog log{stats};
+  log.begin(f);
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
-    const int N = f->op->S.N;
     const int32_t* perm = f->op->ds.perm.as<int32_t>();
-    HL_CHECK(launch_perm_gather(f->w_r.as<double>(), b, perm, N, s));
-    fac_apply_inverse(f, f->w_r.as<double>(), f->w_d.as<double>(), nullptr, s);
-    refine_sweeps(f, f->w_r.as<double>(), f->w_d.as<double>(), default_sweeps(f, refine), s);
-    HL_CHECK(launch_perm_scatter(x, f->w_d.as<double>(), perm, N, s));
+    const int sweeps = default_sweeps(f, refine);
+    const double tol = refine ? refine->tol : 0.0;
+    const int maxsw = std::max(sweeps, refine ? refine->max_sweeps : 0);
+    const bool checking = stats || tol > 0.0;
+    const double hdt = 0.5 * f->dt;
+    // right-hand sides in groups of rm members of one batched problem:
+    // every product reads the factor once for the whole group
+    const int rm = nrhs == 1 ? 1
+                             : std::min({mv_batch_rmax(f->mvG.dev.kb), mv_batch_rmax(f->mvLi.dev.kb),
+                                         mv_batch_rmax(f->mvUi.dev.kb), MV_RMAX});
+    const int R = (int)std::min<int64_t>(rm, nrhs);
+    // per member: b, x, z, r in cluster order, and partial buffers
+    const size_t nG = (size_t)std::max<int64_t>(f->mvG.nslots, 1) * f->mvG.dev.kb;
+    const size_t nL = (size_t)std::max<int64_t>(f->mvLi.nslots, 1) * f->mvLi.dev.kb;
+    const size_t nU = (size_t)std::max<int64_t>(f->mvUi.nslots, 1) * f->mvUi.dev.kb;
+    const size_t per = 4 * (size_t)N + (R > 1 ? nG + nL + nU : 0);
+    DevBuf work;
+    work.alloc(per * R * sizeof(double));
+    CheckBuf cb;
+    if (checking) cb.reserve(R, (int)N);
+    struct Mem { double *b, *x, *z, *r, *pG, *pL, *pU; };
+    std::vector<Mem> mem(R);
+    for (int m = 0; m < R; ++m) {
+      double* p = work.as<double>() + per * m;
+      mem[m] = Mem{p, p + N, p + 2 * N, p + 3 * N, nullptr, nullptr, nullptr};
+      if (R > 1) {
+        mem[m].pG = p + 4 * N;
+        mem[m].pL = mem[m].pG + nG;
+        mem[m].pU = mem[m].pL + nL;
+      }
+    }
+    // the batched tables of a group (R > 1)
+    enum { S_L0, S_U0, S_RES, S_L1, S_ADD, S_COUNT };
+    MvBatch bG, bL, bU;
+    if (R > 1) {
+      bG.create({&f->mvG}, {R}, s);
+      bL.create({&f->mvLi}, {R}, s);
+      bU.create({&f->mvUi}, {R}, s);
+    }
+    std::vector<DevBuf> dtab(S_COUNT);
+    int64_t written = 0;
+    for (int64_t c0 = 0; c0 < nrhs; c0 += R) {
+      const int nr = (int)std::min<int64_t>(R, nrhs - c0);
+      for (int m = 0; m < nr; ++m)
+        HL_CHECK(launch_perm_gather(mem[m].b, b + (size_t)(c0 + m) * ld, perm, (int)N, s));
+      std::function<void(int)> run;   // runs product kind k for the group
+      if (R == 1) {
+        const Mem& q = mem[0];
+        run = [&, q](int k) {
+          MvEpi e{};
+          switch (k) {
+            case S_L0: f->mvLi.run(q.b, epi_plain(q.z), s); break;
+            case S_U0: f->mvUi.run(q.z, epi_plain(q.x), s); break;
+            case S_RES:
+              e.kind = MV_EPI_RESID;   // r = b - (x - dt/2 G x)
+              e.hdt = hdt;
+              e.u = q.x;
+              e.b = q.b;
+              e.y = q.r;
+              f->mvG.run(q.x, e, s);
+              break;
+            case S_L1: f->mvLi.run(q.r, epi_plain(q.z), s); break;
+            case S_ADD:
+              e.kind = MV_EPI_ADD;   // x += U^{-1} z
+              e.u = q.x;
+              e.y = q.x;
+              f->mvUi.run(q.z, e, s);
+              break;
+          }
+        };
+      } else {
+        std::vector<MvInst> t(S_COUNT);
+        for (int k = 0; k < S_COUNT; ++k) {
+          t[k] = MvInst{};
+          t[k].nr = nr;
+          t[k].dev = k == S_RES ? f->mvG.dev : ((k == S_L0 || k == S_L1) ? f->mvLi.dev : f->mvUi.dev);
+          for (int m = 0; m < nr; ++m) {
+            const Mem& q = mem[m];
+            t[k].steps[m] = 1;
+            t[k].part[m] = k == S_RES ? q.pG : ((k == S_L0 || k == S_L1) ? q.pL : q.pU);
+            MvEpi e{};
+            switch (k) {
+              case S_L0: t[k].x[m] = q.b; e = epi_plain(q.z); break;
+              case S_U0: t[k].x[m] = q.z; e = epi_plain(q.x); break;
+              case S_RES:
+                t[k].x[m] = q.x;
+                e.kind = MV_EPI_RESID;
+                e.hdt = hdt;
+                e.u = q.x;
+                e.b = q.b;
+                e.y = q.r;
+                break;
+              case S_L1: t[k].x[m] = q.r; e = epi_plain(q.z); break;
+              case S_ADD:
+                t[k].x[m] = q.z;
+                e.kind = MV_EPI_ADD;
+                e.u = q.x;
+                e.y = q.x;
+                break;
+            }
+            t[k].epi[m] = e;
+          }
+        }
+        for (int k = 0; k < S_COUNT; ++k) upload(dtab[k], std::vector<MvInst>{t[k]}, s);
+        run = [&](int k) {
+          const MvBatch& B = k == S_RES ? bG : ((k == S_L0 || k == S_L1) ? bL : bU);
+          B.run(dtab[k].as<MvInst>(), 0, s);
+        };
+      }
+      run(S_L0);
+      run(S_U0);
+      for (int it = 0; it < sweeps; ++it) {
+        run(S_RES);
+        run(S_L1);
+        run(S_ADD);
+      }
+      if (checking) {
+        int used = sweeps;
+        for (;;) {
+          run(S_RES);
+          for (int m = 0; m < nr; ++m)
+            HL_CHECK(launch_check_norms(mem[m].r, mem[m].b, 1.0, nullptr, 0.0, (int)N, cb.partial.as<double>(),
+                                        cb.slot(m), s));
+          const std::vector<double> v = cb.read(nr, s);
+          double worst = 0.0;
+          for (int m = 0; m < nr; ++m) {
+            const double rel = rel_residual(v[2 * m], v[2 * m + 1]);
+            worst = (rel > worst || std::isnan(rel)) ? rel : worst;
+          }
+          const bool ok = !(tol > 0.0) || worst <= tol;
+          if (ok || used >= maxsw) {
+            log.note(worst, used);
+            if (!ok) {
+              if (stats) {
+                stats->steps_done = written;
+                stats->seconds = now_s() - t_start;
+              }
+              return fail(HLEVY_ERR_NOT_CONVERGED,
+                          "refinement reached a relative residual of " + std::to_string(worst) + " after " +
+                              std::to_string(used) + " sweeps (tol " + std::to_string(tol) + ") in columns " +
+                              std::to_string(c0) + ".." + std::to_string(c0 + nr - 1));
+            }
+            break;
+          }
+          run(S_L1);
+          run(S_ADD);
+          ++used;
+        }
+      }
+      for (int m = 0; m < nr; ++m)
+        HL_CHECK(launch_perm_scatter(x + (size_t)(c0 + m) * ld, mem[m].x, perm, (int)N, s));
+      written += nr;
+    }
+    // the work vectors are freed on return: wait for the device first
+    HL_CHECK(hipStreamSynchronize(s));
+    if (stats) {
+      stats->steps_done = written;
+      stats->seconds = now_s() - t_start;
+    }
     return HLEVY_OK;
   });
 }
@@ -2203,16 +2735,25 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
   if (!f || !u) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
   if (g && !phi) return fail(HLEVY_ERR_INVALID_ARG, "phi is required with g");
-  if (refine && (refine->sweeps < 0 || refine->sweeps > 64)) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
+  if (const char* e = refine_error(refine)) return fail(HLEVY_ERR_INVALID_ARG, e);
   if (g)
     for (int64_t i = 0; i <= nsteps; ++i)
       if (!std::isfinite(phi[i])) return fail(HLEVY_ERR_INVALID_ARG, "non-finite phi");
+  const double t_start = now_s();
+  CheckLog log{stats};
+  log.begin(f);
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
     const int N = f->op->S.N;
     const int32_t* perm = f->op->ds.perm.as<int32_t>();
     const double hdt = 0.5 * f->dt;
     const int sweeps = default_sweeps(f, refine);
+    const double tol = refine ? refine->tol : 0.0;
+    const int every = refine ? refine->check_every : 0;
+    const int maxsw = std::max(sweeps, refine ? refine->max_sweeps : 0);
+    const bool checking = stats || tol > 0.0;
+    CheckBuf cb;
+    if (checking) cb.reserve(1, N);
     // Since I + dt/2 G = 2 I - M, each step solves M w = 2 u^n + F_n
     // (F_n = dt/2 (phi_n + phi_{n+1}) g) and sets u^{n+1} = w - u^n: one
     // product with G per refinement sweep and none for the right side.
@@ -2227,8 +2768,28 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
       HL_CHECK(launch_perm_gather(gc, g, perm, N, s));
       f->mvLi.run(gc, epi_plain(lg), s);
     }
+    auto cn_residual = [&](double cg) {
+      MvEpi e3{};
+      e3.kind = MV_EPI_CNRES;   // r = 2 u^n + F_n - (w - dt/2 G w)
+      e3.hdt = hdt;
+      e3.cg = cg;
+      e3.u = uc;
+      e3.g = g ? gc : nullptr;
+      e3.b = w;
+      e3.y = r;
+      f->mvG.run(w, e3, s);
+    };
+    auto add_update = [&]() {
+      MvEpi e4{};
+      e4.kind = MV_EPI_ADD;   // w += U^{-1} L^{-1} r
+      e4.u = w;
+      e4.y = w;
+      f->mvLi.run(r, epi_plain(z), s);
+      f->mvUi.run(z, e4, s);
+    };
     for (int64_t n = 0; n < nsteps; ++n) {
       const double cg = g ? hdt * (phi[n] + phi[n + 1]) : 0.0;
+      const bool chk = checking && (n + 1 == nsteps || (every > 0 && (n + 1) % every == 0));
       // z = L^{-1} (2 u^n + F_n) = 2 L^{-1} u^n + cg L^{-1} g
       MvEpi e{};
       e.kind = MV_EPI_AXPY;
@@ -2237,7 +2798,7 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
       e.g = g ? lg : nullptr;
       e.y = z;
       f->mvLi.run(uc, e, s);
-      if (sweeps == 0) {
+      if (sweeps == 0 && !chk) {
         MvEpi e2{};
         e2.kind = MV_EPI_SUB;   // u^{n+1} = U^{-1} z - u^n
         e2.u = uc;
@@ -2247,68 +2808,118 @@ hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g
       }
       f->mvUi.run(z, epi_plain(w), s);
       for (int it = 0; it < sweeps; ++it) {
-        MvEpi e3{};
-        e3.kind = MV_EPI_CNRES;   // r = 2 u^n + F_n - (w - dt/2 G w)
-        e3.hdt = hdt;
-        e3.cg = cg;
-        e3.u = uc;
-        e3.g = g ? gc : nullptr;
-        e3.b = w;
-        e3.y = r;
-        f->mvG.run(w, e3, s);
-        f->mvLi.run(r, epi_plain(z), s);
-        MvEpi e4{};
-        if (it + 1 < sweeps) {
-          e4.kind = MV_EPI_ADD;   // w += U^{-1} L^{-1} r
-          e4.u = w;
-          e4.y = w;
+        cn_residual(cg);
+        if (it + 1 < sweeps || chk) {
+          add_update();
         } else {
+          f->mvLi.run(r, epi_plain(z), s);
+          MvEpi e4{};
           e4.kind = MV_EPI_NEXT;   // u^{n+1} = w + U^{-1} L^{-1} r - u^n
           e4.b = w;
           e4.u = uc;
           e4.y = uc;
+          f->mvUi.run(z, e4, s);
         }
-        f->mvUi.run(z, e4, s);
+      }
+      if (chk) {
+        // the residual of the final iterate w (one more product with G);
+        // further sweeps while it misses the target
+        int used = sweeps;
+        double rel = 0.0;
+        for (;;) {
+          cn_residual(cg);
+          HL_CHECK(launch_check_norms(r, uc, 2.0, g ? gc : nullptr, cg, N, cb.partial.as<double>(), cb.slot(0), s));
+          const std::vector<double> v = cb.read(1, s);
+          rel = rel_residual(v[0], v[1]);
+          if (!(tol > 0.0) || rel <= tol || used >= maxsw) break;
+          add_update();
+          ++used;
+        }
+        log.note(rel, used);
+        if (tol > 0.0 && !(rel <= tol)) {
+          // step n is not applied: u keeps u^n, the last completed step
+          HL_CHECK(launch_perm_scatter(u, uc, perm, N, s));
+          HL_CHECK(hipStreamSynchronize(s));
+          if (stats) {
+            stats->steps_done = n;
+            stats->seconds = now_s() - t_start;
+          }
+          return fail(HLEVY_ERR_NOT_CONVERGED, "step " + std::to_string(n) + ": relative residual " +
+                                                   std::to_string(rel) + " after " + std::to_string(used) +
+                                                   " sweeps (tol " + std::to_string(tol) + ")");
+        }
+        HL_CHECK(launch_wsub(uc, w, N, s));   // u^{n+1} = w - u^n
       }
     }
     HL_CHECK(launch_perm_scatter(u, uc, perm, N, s));
     if (stats) {
       HL_CHECK(hipStreamSynchronize(s));
       stats->steps_done = nsteps;
-      stats->last_rel_residual = -1.0;
-      stats->rank_overflows = f->rank_overflows;
+      stats->seconds = now_s() - t_start;
     }
     return HLEVY_OK;
   });
 }
 
-hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, int32_t count, int64_t nsteps,
-                                const hlevy_refine* refine, void* stream) {
-  if (!facs || !u) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, const int64_t* nsteps, int32_t count,
+                                const hlevy_refine* refine, hlevy_stats* stats, void* stream) {
+  if (!facs || !u || !nsteps) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   if (count < 1) return fail(HLEVY_ERR_INVALID_ARG, "count must be >= 1");
-  if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
-  if (refine && (refine->sweeps < 0 || refine->sweeps > 64)) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
+  if (const char* e = refine_error(refine)) return fail(HLEVY_ERR_INVALID_ARG, e);
+  int64_t nmax = 0, total = 0;
   {
     std::set<const hlevy_fac*> seen;
     for (int32_t i = 0; i < count; ++i) {
       if (!facs[i] || !u[i]) return fail(HLEVY_ERR_INVALID_ARG, "null factor or vector");
+      if (nsteps[i] < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
       if (!seen.insert(facs[i]).second) return fail(HLEVY_ERR_INVALID_ARG, "a factor appears twice in the batch");
+      nmax = std::max(nmax, nsteps[i]);
+      total += nsteps[i];
     }
+  }
+  const double t_start = now_s();
+  CheckLog log{stats};
+  log.begin(facs[0]);
+  if (stats) {
+    stats->rank_overflows = 0;
+    for (int32_t i = 0; i < count; ++i) stats->rank_overflows = std::max(stats->rank_overflows, facs[i]->rank_overflows);
   }
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
     int sweeps = 0;
     for (int32_t i = 0; i < count; ++i) sweeps = std::max(sweeps, default_sweeps(facs[i], refine));
+    const double tol = refine ? refine->tol : 0.0;
+    const bool checking = stats || tol > 0.0;
+    std::vector<double> rel(count, -1.0);
     std::vector<StepState> st;
     for (int32_t i = 0; i < count; ++i) {
       hlevy_fac* f = facs[i];
-      st.push_back(StepState{f, f->w_u.as<double>(), f->w_d.as<double>(), f->w_z.as<double>(), f->w_y.as<double>(),
-                             nullptr, nullptr, nullptr});
+      StepState x{f, f->w_u.as<double>(), f->w_d.as<double>(), f->w_z.as<double>(), f->w_y.as<double>(),
+                  nullptr, nullptr, nullptr, nsteps[i]};
+      x.check = checking && nsteps[i] > 0;
+      x.rel = &rel[i];
+      st.push_back(x);
       HL_CHECK(launch_perm_gather(st.back().uc, u[i], f->op->ds.perm.as<int32_t>(), f->op->S.N, s));
     }
-    step_states(st, nsteps, sweeps, s);
+    step_states(st, nmax, sweeps, s);
     for (int32_t i = 0; i < count; ++i)
       HL_CHECK(launch_perm_scatter(u[i], st[i].uc, facs[i]->op->ds.perm.as<int32_t>(), facs[i]->op->S.N, s));
+    HL_CHECK(hipStreamSynchronize(s));
+    int worst = -1;
+    for (int32_t i = 0; i < count; ++i) {
+      if (rel[i] < 0.0 && !std::isnan(rel[i])) continue;
+      log.note(rel[i], sweeps);
+      if (worst < 0 || !(rel[worst] >= rel[i])) worst = i;
+    }
+    if (stats) {
+      if (worst >= 0) stats->last_rel_residual = rel[worst];
+      stats->steps_done = total;
+      stats->seconds = now_s() - t_start;
+    }
+    if (tol > 0.0 && worst >= 0 && !(rel[worst] <= tol))
+      return fail(HLEVY_ERR_NOT_CONVERGED, "problem " + std::to_string(worst) + ": relative residual " +
+                                               std::to_string(rel[worst]) + " of its last step (tol " +
+                                               std::to_string(tol) + ")");
     return HLEVY_OK;
   });
 }
@@ -2408,6 +3019,7 @@ struct SrvReq {
   SrvEntry* e = nullptr;
   int64_t nsteps = 0, done = 0;
   int N = 0;
+  double rel = -1.0;           // relative residual of the last step
   double* out = nullptr;
   DevBuf u0;                   // staged initial condition (natural order)
   DevBuf vec, pG, pL, pU;      // state while active
@@ -2429,16 +3041,6 @@ static std::string srv_key(const hlevy_problem& p, const hlevy_hparams& hp, doub
   return k;
 }
 
-// resident bytes of an operator and its factor (G, the inverse factors with
-// their FP32 copies on the mixed path, product plans, work vectors)
-static size_t srv_entry_bytes(const Structure& S, int max_rank, bool mixed) {
-  HMat t;
-  const size_t g = t.layout(S, max_rank, FULL, false);
-  const size_t lu = t.layout(S, max_rank, LOWER, false) + t.layout(S, max_rank, UPPER, false);
-  size_t b = g * 8 + lu * (mixed ? 12 : 8) + (size_t)S.N * 8 * 12 + S.lf.size() * 256;
-  return b + b / 16;
-}
-
 }  // namespace hl
 
 struct hlevy_server {
@@ -2450,7 +3052,7 @@ struct hlevy_server {
   std::map<std::string, std::unique_ptr<SrvEntry>> cache;
   std::deque<std::unique_ptr<SrvReq>> queue;
   std::vector<std::unique_ptr<SrvReq>> active;
-  std::deque<int64_t> finished;
+  std::deque<int64_t> finished, failed;
   hlevy_server_stats st{};
 };
 
@@ -2462,9 +3064,11 @@ hlevy_status hlevy_server_create(const hlevy_server_config* cfg, void* stream, h
   if (!(cfg->lu_tol > 0.0 && cfg->lu_tol < 1.0)) return fail(HLEVY_ERR_INVALID_ARG, "lu_tol must be in (0, 1)");
   if (cfg->sweeps < 0 || cfg->sweeps > 64) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
   if (cfg->chunk < 1 || cfg->max_active < 1) return fail(HLEVY_ERR_INVALID_ARG, "chunk and max_active must be >= 1");
+  if (std::isnan(cfg->tol) || std::isinf(cfg->tol)) return fail(HLEVY_ERR_INVALID_ARG, "tol must be finite");
   return guarded([&]() -> hlevy_status {
     auto v = std::make_unique<hlevy_server>();
     v->cfg = *cfg;
+    v->st.max_rel_residual = -1.0;
     if (v->cfg.hbm_budget == 0) v->cfg.hbm_budget = (size_t)64 << 30;
     v->s = as_stream(stream);
     *out = v.release();
@@ -2495,7 +3099,7 @@ hlevy_status hlevy_server_submit(hlevy_server* v, const hlevy_problem* prob, con
       en->prob = *prob;
       en->hp = *hp;
       en->dt = dt;
-      en->bytes = srv_entry_bytes(S, hp->max_rank, v->cfg.prec == HLEVY_PREC_MIXED);
+      en->bytes = footprint_bytes(S, hp->max_rank, v->cfg.prec == HLEVY_PREC_MIXED);
       // not resident until admitted; kept so that later requests find it
       v->cache.emplace(r->key, std::move(en));
     }
@@ -2551,6 +3155,8 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
     // 2. operators not in the cache: assembly, then one joint factorisation
     if (!fresh.empty()) {
       const double t0 = now_s();
+      double t1 = t0;
+      hlevy_status st = HLEVY_OK;
       {
         std::vector<hlevy_problem> pr;
         std::vector<hlevy_hparams> hv;
@@ -2559,22 +3165,54 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
           hv.push_back(e->hp);
         }
         std::vector<hlevy_op*> oo(fresh.size(), nullptr);
-        hlevy_status st = hlevy_assemble_batched(pr.data(), hv.data(), (int32_t)pr.size(), s, oo.data());
-        if (st != HLEVY_OK) return st;
-        for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->op.reset(oo[q]);
+        st = hlevy_assemble_batched(pr.data(), hv.data(), (int32_t)pr.size(), nullptr, s, oo.data());
+        if (st == HLEVY_OK)
+          for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->op.reset(oo[q]);
       }
-      const double t1 = now_s();
-      std::vector<const hlevy_op*> ops;
-      std::vector<double> dts;
-      for (SrvEntry* e : fresh) {
-        ops.push_back(e->op.get());
-        dts.push_back(e->dt);
+      if (st == HLEVY_OK) {
+        t1 = now_s();
+        std::vector<const hlevy_op*> ops;
+        std::vector<double> dts;
+        for (SrvEntry* e : fresh) {
+          ops.push_back(e->op.get());
+          dts.push_back(e->dt);
+        }
+        std::vector<hlevy_fac*> fo(fresh.size(), nullptr);
+        st = hlevy_factor_batched(ops.data(), dts.data(), (int32_t)ops.size(), v->cfg.prec, v->cfg.lu_tol, 0, s,
+                                  fo.data());
+        if (st == HLEVY_OK)
+          for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->fac.reset(fo[q]);
       }
-      std::vector<hlevy_fac*> fo(fresh.size(), nullptr);
-      hlevy_status st = hlevy_factor_batched(ops.data(), dts.data(), (int32_t)ops.size(), v->cfg.prec, v->cfg.lu_tol,
-                                             0, s, fo.data());
-      if (st != HLEVY_OK) return st;
-      for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->fac.reset(fo[q]);
+      if (st != HLEVY_OK) {
+        // the new operators could not be built: their requests leave the
+        // server as failed (hlevy_server_take_failed), their memory is
+        // returned and the entries stay non-resident; the other active
+        // requests are untouched
+        const std::string msg = g_last_error;
+        std::vector<std::unique_ptr<SrvReq>> keep;
+        std::string ids;
+        for (auto& r : v->active) {
+          if (std::find(fresh.begin(), fresh.end(), r->e) == fresh.end()) {
+            keep.push_back(std::move(r));
+            continue;
+          }
+          r->e->refs--;
+          v->used -= r->bytes;
+          v->failed.push_back(r->id);
+          v->st.failed++;
+          ids += (ids.empty() ? "" : ",") + std::to_string(r->id);
+        }
+        v->active.swap(keep);
+        for (SrvEntry* e : fresh) {
+          e->fac.reset();
+          e->op.reset();
+          v->used -= e->bytes;
+        }
+        v->st.active = (int64_t)v->active.size();
+        v->st.queued = (int64_t)v->queue.size();
+        *ndone = 0;
+        return fail(st, msg + " (requests " + ids + " failed)");
+      }
       v->st.assemble_seconds += t1 - t0;
       v->st.factor_seconds += now_s() - t1;
     }
@@ -2600,6 +3238,9 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
         double* b = r->vec.as<double>();
         sts.push_back(StepState{r->e->fac.get(), b, b + r->N, b + 2 * (size_t)r->N, b + 3 * (size_t)r->N,
                                 r->pG.as<double>(), r->pL.as<double>(), r->pU.as<double>(), k});
+        // a request's last step measures its residual
+        sts.back().check = r->done + k == r->nsteps;
+        sts.back().rel = &r->rel;
         c = std::max(c, k);
         total += k;
       }
@@ -2626,6 +3267,10 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
       v->used -= r->bytes;
       v->finished.push_back(r->id);
       v->st.completed++;
+      if (r->rel >= 0.0 || std::isnan(r->rel)) {
+        if (!(v->st.max_rel_residual >= r->rel)) v->st.max_rel_residual = r->rel;
+        if (v->cfg.tol > 0.0 && !(r->rel <= v->cfg.tol)) v->st.not_converged++;
+      }
     }
     v->active.swap(keep);
     HL_CHECK(hipStreamSynchronize(s));
@@ -2639,6 +3284,17 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
     v->st.queued = (int64_t)v->queue.size();
     return HLEVY_OK;
   });
+}
+
+hlevy_status hlevy_server_take_failed(hlevy_server* v, int64_t* ids, int32_t cap, int32_t* n) {
+  if (!v || !n || cap < 0 || (cap > 0 && !ids)) return fail(HLEVY_ERR_INVALID_ARG, "bad argument");
+  int32_t k = 0;
+  while (k < cap && !v->failed.empty()) {
+    ids[k++] = v->failed.front();
+    v->failed.pop_front();
+  }
+  *n = k;
+  return HLEVY_OK;
 }
 
 hlevy_status hlevy_server_stats_get(hlevy_server* v, hlevy_server_stats* out) {

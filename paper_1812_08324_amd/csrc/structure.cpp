@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <string>
 #include <sstream>
 
 #include "hl_internal.h"
@@ -94,7 +95,11 @@ int build_block(Structure& s, int r, int c) {
   const Cluster& C = s.cl[c];
   bool adm = std::min(diam(s, R), diam(s, C)) <= s.eta * dist(s, R, C);
   int sz = std::max(R.hi - R.lo, C.hi - C.lo);
-  if (adm && sz <= s.nmax && r != c) {
+  // an admissible block whose compression needed more than the rank
+  // capacity is subdivided (its children are admissible too), or kept
+  // dense when its clusters are leaves
+  const bool over = s.split.count({r, c}) > 0;
+  if (adm && sz <= s.nmax && r != c && !over) {
     b.kind = K_LR;
   } else if (R.child[0] < 0 || C.child[0] < 0) {
     b.kind = K_DENSE;
@@ -129,7 +134,8 @@ void number_leaves(Structure& s, int id) {
 
 }  // namespace
 
-std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Structure& s) {
+std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Structure& s,
+                            const std::set<std::pair<int32_t, int32_t>>* overcap) {
   std::ostringstream err;
   if (p.dim != 1 && p.dim != 2) err << "dim must be 1 or 2";
   else if (p.n < 2) err << "n must be >= 2";
@@ -140,6 +146,7 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   else if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) err << "lambda must be >= 0";
   else if (!std::isfinite(p.b[0]) || !std::isfinite(p.b[1]) || !std::isfinite(p.C)) err << "non-finite drift or C";
   else if (!(p.r0 > 0.0) || !std::isfinite(p.r0)) err << "r0 must be > 0";
+  else if (!(p.r0 < p.hi - p.lo)) err << "r0 must be smaller than the domain";
   else if (hp.leaf < 16 || hp.leaf > 64) err << "leaf must be in [16, 64]";
   else if (!(hp.eta > 0.0)) err << "eta must be > 0";
   else if (hp.n_block < 1) err << "n_block must be >= 1";
@@ -151,6 +158,7 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   if (N64 < 2 * (int64_t)hp.leaf) return "N must be at least twice the leaf size";
 
   s = Structure{};
+  if (overcap) s.split = *overcap;
   s.dim = p.dim;
   s.n = p.n;
   s.N = (int32_t)N64;
@@ -214,6 +222,9 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
       s.dense_entries += (int64_t)l.m * l.n;
     } else {
       s.n_lr++;
+      // the ACA kernel marks used pivot rows in a bitmap of LR_ROWS_MAX bits
+      if (std::max(l.m, l.n) > LR_ROWS_MAX)
+        return "low-rank blocks are limited to " + std::to_string(LR_ROWS_MAX) + " rows (raise n_block)";
     }
   }
   // per-leaf-cluster lists

@@ -32,12 +32,19 @@ class HParams(C.Structure):
 
 
 class Refine(C.Structure):
-    _fields_ = [("tol", C.c_double), ("sweeps", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("sweeps", C.c_int32), ("check_every", C.c_int32),
+                ("max_sweeps", C.c_int32), ("pad", C.c_int32)]
 
 
 class Stats(C.Structure):
-    _fields_ = [("steps_done", C.c_int64), ("last_rel_residual", C.c_double),
-                ("rank_overflows", C.c_int32)]
+    _fields_ = [("steps_done", C.c_int64), ("last_rel_residual", C.c_double), ("max_rel_residual", C.c_double),
+                ("checks", C.c_int32), ("max_sweeps_used", C.c_int32), ("rank_overflows", C.c_int32),
+                ("pad", C.c_int32), ("seconds", C.c_double)]
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)), ("ctx", C.c_void_p)]
 
 
 class PlanInfo(C.Structure):
@@ -48,7 +55,14 @@ class PlanInfo(C.Structure):
 
 class OpInfo(C.Structure):
     _fields_ = [("dense_entries", C.c_int64), ("lowrank_entries", C.c_int64), ("max_rank", C.c_int32),
-                ("mean_rank", C.c_double), ("rank_overflows", C.c_int32)]
+                ("mean_rank", C.c_double), ("rank_overflows", C.c_int32), ("subdivided_blocks", C.c_int32),
+                ("device_bytes", C.c_size_t)]
+
+
+class FacInfo(C.Structure):
+    _fields_ = [("device_bytes", C.c_size_t), ("rank_overflows", C.c_int32), ("max_rank", C.c_int32),
+                ("product_bytes", C.c_double * 3), ("lu_tol", C.c_double), ("dt", C.c_double),
+                ("prec", C.c_int32), ("pad", C.c_int32)]
 
 
 class KernelTimes(C.Structure):
@@ -58,24 +72,25 @@ class KernelTimes(C.Structure):
                 ("v_bytes", C.c_double * 3), ("partial_bytes", C.c_double * 3)]
 
 
-EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_assemble", "hlevy_assemble_batched",
-           "hlevy_op_constants", "hlevy_op_info", "hlevy_matvec", "hlevy_op_densify",
-           "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_step", "hlevy_step_batched",
-           "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
-           "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_stats_get",
-           "hlevy_server_destroy"]
+EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
+           "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
+           "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_step",
+           "hlevy_step_batched", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
+           "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_take_failed",
+           "hlevy_server_stats_get", "hlevy_server_destroy"]
 
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("prec", C.c_int32), ("lu_tol", C.c_double), ("sweeps", C.c_int32),
-                ("chunk", C.c_int32), ("max_active", C.c_int32)]
+                ("chunk", C.c_int32), ("max_active", C.c_int32), ("tol", C.c_double)]
 
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("active", C.c_int64), ("queued", C.c_int64),
                 ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("evictions", C.c_int64),
                 ("cached_operators", C.c_int64), ("problem_steps", C.c_int64), ("bytes_in_use", C.c_size_t),
-                ("assemble_seconds", C.c_double), ("factor_seconds", C.c_double), ("step_seconds", C.c_double)]
+                ("assemble_seconds", C.c_double), ("factor_seconds", C.c_double), ("step_seconds", C.c_double),
+                ("failed", C.c_int64), ("not_converged", C.c_int64), ("max_rel_residual", C.c_double)]
 
 
 def _load():
@@ -87,17 +102,21 @@ def _load():
         "hlevy_abi_version": ([], C.c_int32),
         "hlevy_last_error": ([], C.c_char_p),
         "hlevy_plan_info": ([C.POINTER(Problem), C.POINTER(HParams), C.POINTER(PlanInfo)], st),
-        "hlevy_assemble": ([C.POINTER(Problem), C.POINTER(HParams), vp, C.POINTER(vp)], st),
-        "hlevy_assemble_batched": ([C.POINTER(Problem), C.POINTER(HParams), C.c_int32, vp, C.POINTER(vp)], st),
+        "hlevy_footprint": ([C.POINTER(Problem), C.POINTER(HParams), C.c_int32, C.POINTER(C.c_size_t)], st),
+        "hlevy_assemble": ([C.POINTER(Problem), C.POINTER(HParams), C.POINTER(Allocator), vp, C.POINTER(vp)], st),
+        "hlevy_assemble_batched": ([C.POINTER(Problem), C.POINTER(HParams), C.c_int32, C.POINTER(Allocator), vp,
+                                    C.POINTER(vp)], st),
         "hlevy_op_constants": ([vp, C.POINTER(C.c_double), vp], st),
         "hlevy_op_info": ([vp, C.POINTER(OpInfo), vp], st),
+        "hlevy_fac_info": ([vp, C.POINTER(FacInfo), vp], st),
         "hlevy_matvec": ([vp, vp, vp, vp], st),
         "hlevy_op_densify": ([vp, vp, vp], st),
         "hlevy_factor": ([vp, C.c_double, C.c_int32, C.c_double, vp, C.POINTER(vp)], st),
         "hlevy_factor_batched": ([C.POINTER(vp), C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_double,
                                   C.c_size_t, vp, C.POINTER(vp)], st),
-        "hlevy_solve": ([vp, vp, vp, C.POINTER(Refine), vp], st),
-        "hlevy_step_batched": ([C.POINTER(vp), C.POINTER(vp), C.c_int32, C.c_int64, C.POINTER(Refine), vp], st),
+        "hlevy_solve": ([vp, vp, vp, C.c_int64, C.c_int64, C.POINTER(Refine), C.POINTER(Stats), vp], st),
+        "hlevy_step_batched": ([C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(Refine),
+                                C.POINTER(Stats), vp], st),
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
                         C.POINTER(Stats), vp], st),
         "hlevy_fac_kernel_times": ([vp, C.c_int32, vp, C.POINTER(KernelTimes)], st),
@@ -106,6 +125,7 @@ def _load():
         "hlevy_server_submit": ([vp, C.POINTER(Problem), C.POINTER(HParams), C.c_double, C.c_int64, vp, vp,
                                  C.POINTER(C.c_int64)], st),
         "hlevy_server_poll": ([vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
+        "hlevy_server_take_failed": ([vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
         "hlevy_server_stats_get": ([vp, C.POINTER(ServerStats)], st),
         "hlevy_server_destroy": ([vp], None),
         "hlevy_op_destroy": ([vp], None),
@@ -167,6 +187,36 @@ def make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16) -> HPa
     return h
 
 
+def footprint(prob: Problem, hp: HParams, prec: int = PREC_FP64) -> int:
+    """Resident device bytes of an operator plus one factor (hlevy_footprint)."""
+    out = C.c_size_t()
+    _check(lib.hlevy_footprint(C.byref(prob), C.byref(hp), int(prec), C.byref(out)), "hlevy_footprint")
+    return out.value
+
+
+class TorchAllocator:
+    """hlevy_allocator backed by torch's caching allocator: the library's
+    device memory then shows in torch.cuda.memory_allocated().  Keep the
+    object alive as long as the handles that used it."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self._a = Allocator._fields_[0][1](self._alloc)
+        self._f = Allocator._fields_[1][1](self._free)
+        self.c = Allocator(self._a, self._f, None)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            return self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+        except RuntimeError:
+            return None
+
+    def _free(self, p, ctx):
+        self._torch.cuda.caching_allocator_delete(p)
+
+
 def plan_info(prob: Problem, hp: HParams) -> dict:
     out = PlanInfo()
     _check(lib.hlevy_plan_info(C.byref(prob), C.byref(hp), C.byref(out)), "hlevy_plan_info")
@@ -189,11 +239,13 @@ def fac_kernel_times(fac, reps: int = 20, stream=None) -> dict:
 class Op:
     """Assembled H-matrix of the generator G (handle owner)."""
 
-    def __init__(self, prob: Problem, hp: HParams, stream=None, handle=None):
+    def __init__(self, prob: Problem, hp: HParams, stream=None, handle=None, allocator=None):
         if handle is None:
             handle = C.c_void_p()
-            _check(lib.hlevy_assemble(C.byref(prob), C.byref(hp), _stream(stream), C.byref(handle)),
+            al = C.byref(allocator.c) if allocator is not None else None
+            _check(lib.hlevy_assemble(C.byref(prob), C.byref(hp), al, _stream(stream), C.byref(handle)),
                    "hlevy_assemble")
+        self.allocator = allocator   # must outlive the handle
         self.h = handle
         self.N = prob.n if prob.dim == 1 else prob.n * prob.n
         self.prob, self.hp = prob, hp
@@ -224,8 +276,8 @@ class Fac:
             self.h = None
 
 
-def assemble(prob: Problem, hp: HParams, stream=None) -> Op:
-    return Op(prob, hp, stream)
+def assemble(prob: Problem, hp: HParams, stream=None, allocator=None) -> Op:
+    return Op(prob, hp, stream, allocator=allocator)
 
 
 def assemble_batched(probs, hps, stream=None) -> list:
@@ -237,7 +289,7 @@ def assemble_batched(probs, hps, stream=None) -> list:
     pa = (Problem * n)(*probs)
     ha = (HParams * n)(*hps)
     out = (C.c_void_p * n)()
-    _check(lib.hlevy_assemble_batched(pa, ha, n, _stream(stream), out), "hlevy_assemble_batched")
+    _check(lib.hlevy_assemble_batched(pa, ha, n, None, _stream(stream), out), "hlevy_assemble_batched")
     return [Op(p, hp, handle=C.c_void_p(out[i])) for i, (p, hp) in enumerate(zip(probs, hps))]
 
 
@@ -251,6 +303,14 @@ def op_info(op: Op, stream=None) -> dict:
     out = OpInfo()
     _check(lib.hlevy_op_info(op.h, C.byref(out), _stream(stream)), "hlevy_op_info")
     return {k: getattr(out, k) for k, _ in OpInfo._fields_}
+
+
+def fac_info(fac, stream=None) -> dict:
+    out = FacInfo()
+    _check(lib.hlevy_fac_info(fac.h, C.byref(out), _stream(stream)), "hlevy_fac_info")
+    d = {k: getattr(out, k) for k, _ in FacInfo._fields_}
+    d["product_bytes"] = list(out.product_bytes)
+    return d
 
 
 def matvec(op: Op, x, y, stream=None):
@@ -279,15 +339,26 @@ def factor_batched(ops, dts, prec: int = PREC_FP64, lu_tol: float = 1e-12, works
     return [Fac(o, d, prec, lu_tol, handle=C.c_void_p(out[i])) for i, (o, d) in enumerate(zip(ops, dts))]
 
 
-def step_batched(facs, us, nsteps: int, refine=None, stream=None):
-    """nsteps unforced Crank-Nicolson steps of every problem (hlevy_step_batched)."""
+def _stats_dict(st):
+    return {k: getattr(st, k) for k, _ in Stats._fields_ if k != "pad"}
+
+
+def step_batched(facs, us, nsteps, refine=None, stats=False, stream=None):
+    """Unforced Crank-Nicolson steps of every problem (hlevy_step_batched);
+    nsteps: one count for all, or one per problem."""
     n = len(facs)
     if len(us) != n or n == 0:
         raise ValueError("one vector per factor, at least one factor")
+    steps = [int(nsteps)] * n if isinstance(nsteps, int) else [int(k) for k in nsteps]
+    if len(steps) != n:
+        raise ValueError("one step count per problem")
     hs = (C.c_void_p * n)(*[f.h.value for f in facs])
     up = (C.c_void_p * n)(*[_dptr(u, f.N).value for f, u in zip(facs, us)])
-    _check(lib.hlevy_step_batched(hs, up, n, int(nsteps), _refine(refine), _stream(stream)),
-           "hlevy_step_batched")
+    ks = (C.c_int64 * n)(*steps)
+    st = Stats() if stats else None
+    _check(lib.hlevy_step_batched(hs, up, ks, n, _refine(refine), C.byref(st) if st is not None else None,
+                                  _stream(stream)), "hlevy_step_batched")
+    return _stats_dict(st) if st is not None else None
 
 
 def _refine(refine):
@@ -296,6 +367,8 @@ def _refine(refine):
     r = Refine()
     r.tol = float(refine.get("tol", 0.0))
     r.sweeps = int(refine.get("sweeps", 2))
+    r.check_every = int(refine.get("check_every", 0))
+    r.max_sweeps = int(refine.get("max_sweeps", 0))
     return C.byref(r)
 
 
@@ -306,9 +379,16 @@ def fac_apply(fac: Fac, which: int, x, y, stream=None):
            "hlevy_fac_apply")
 
 
-def solve(fac: Fac, b, x, refine=None, stream=None):
-    _check(lib.hlevy_solve(fac.h, _dptr(b, fac.N), _dptr(x, fac.N), _refine(refine), _stream(stream)),
-           "hlevy_solve")
+def solve(fac: Fac, b, x, refine=None, stats=False, stream=None):
+    """Solve M x = b (hlevy_solve).  b, x: (N,) or (nrhs, N) contiguous
+    float64 CUDA tensors; row c of a 2-D tensor is right-hand side c."""
+    if b.shape != x.shape or b.dim() not in (1, 2) or b.shape[-1] != fac.N:
+        raise ValueError("b and x must both be (N,) or (nrhs, N)")
+    nrhs = 1 if b.dim() == 1 else int(b.shape[0])
+    st = Stats() if stats else None
+    _check(lib.hlevy_solve(fac.h, _dptr(b), _dptr(x), nrhs, fac.N, _refine(refine),
+                           C.byref(st) if st is not None else None, _stream(stream)), "hlevy_solve")
+    return _stats_dict(st) if st is not None else None
 
 
 def step(fac: Fac, u, nsteps: int, g=None, phi=None, refine=None, stats=False, stream=None):
@@ -322,7 +402,7 @@ def step(fac: Fac, u, nsteps: int, g=None, phi=None, refine=None, stats=False, s
     _check(lib.hlevy_step(fac.h, _dptr(u, fac.N), int(nsteps), gp, php, _refine(refine),
                           C.byref(st) if st is not None else None, _stream(stream)), "hlevy_step")
     if st is not None:
-        return {k: getattr(st, k) for k, _ in Stats._fields_}
+        return _stats_dict(st)
     return None
 
 
@@ -331,8 +411,9 @@ class Server:
     scheduling rounds, collect finished ids."""
 
     def __init__(self, prec: int = PREC_MIXED, lu_tol: float = 1e-6, sweeps: int = 1, chunk: int = 10,
-                 max_active: int = 256, hbm_budget: int = 0, stream=None):
-        cfg = ServerConfig(int(hbm_budget), int(prec), float(lu_tol), int(sweeps), int(chunk), int(max_active))
+                 max_active: int = 256, hbm_budget: int = 0, tol: float = 0.0, stream=None):
+        cfg = ServerConfig(int(hbm_budget), int(prec), float(lu_tol), int(sweeps), int(chunk), int(max_active),
+                           float(tol))
         h = C.c_void_p()
         _check(lib.hlevy_server_create(C.byref(cfg), _stream(stream), C.byref(h)), "hlevy_server_create")
         self.h = h
@@ -350,6 +431,15 @@ class Server:
         ids = (C.c_int64 * cap)()
         nd = C.c_int32()
         _check(lib.hlevy_server_poll(self.h, ids, int(cap), C.byref(nd)), "hlevy_server_poll")
+        out = [ids[i] for i in range(nd.value)]
+        for i in out:
+            self._keep.pop(i, None)
+        return out
+
+    def take_failed(self, cap: int = 4096) -> list:
+        ids = (C.c_int64 * cap)()
+        nd = C.c_int32()
+        _check(lib.hlevy_server_take_failed(self.h, ids, int(cap), C.byref(nd)), "hlevy_server_take_failed")
         out = [ids[i] for i in range(nd.value)]
         for i in out:
             self._keep.pop(i, None)

@@ -1,0 +1,249 @@
+"""GPU tests of the boundary's contract (through the C ABI): multi-RHS
+solves, residual checks of the refinement (tolerance, check points, the
+not-converged status), per-problem step counts of the batched call, the
+rank-cap fallback of the assembly, the caller's allocator and the
+footprint, and the serving loop's failure path."""
+import numpy as np
+import pytest
+
+from oracle.levy_oracle import Problem, cn_run, generator_dense
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_08324_amd import hlevy
+    return hlevy
+
+
+def oracle_problem(w):
+    return Problem(dim=w.dim, n=w.n, lo=w.lo, hi=w.hi, a=w.a, b=tuple(w.b), c=w.c, s=w.s,
+                   lam=w.lam, C=w.C, r0=w.r0)
+
+
+def lib_problem(H, w):
+    return H.make_problem(w.dim, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def tempered(H):
+    """Tempered 1D workload at N = 2000 (ragged leaves): operator, FP64 and
+    mixed factors, and the dense M of the oracle."""
+    w = W.config2(n=2000, steps=30)
+    op = H.assemble(lib_problem(H, w), H.make_hparams(aca_tol=1e-10, max_rank=16))
+    f64 = H.factor(op, w.dt, H.PREC_FP64, 1e-12)
+    fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    M = np.eye(w.N) - 0.5 * w.dt * generator_dense(oracle_problem(w))
+    return w, op, f64, fmx, M
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_rhs_solve(H, tempered, prec):
+    """Six right-hand sides in one call (a group of four sharing every
+    product, then two): each column equals the dense solve, and the columns
+    agree with one-column calls to rounding; stats report one check per
+    column group's worst residual."""
+    w, op, f64, fmx, M = tempered
+    fac = f64 if prec == "fp64" else fmx
+    rng = np.random.Generator(np.random.PCG64(21))
+    xt = rng.standard_normal((6, w.N))
+    B = (M @ xt.T).T
+    X = torch.zeros(6, w.N, dtype=torch.float64, device="cuda")
+    st = H.solve(fac, dev(B), X, refine={"sweeps": 2, "tol": 1e-11}, stats=True)
+    Xh = host(X)
+    for c in range(6):
+        err = np.linalg.norm(Xh[c] - xt[c]) / np.linalg.norm(xt[c])
+        assert err < 1e-9, (c, err)
+        x1 = torch.zeros(w.N, dtype=torch.float64, device="cuda")
+        H.solve(fac, dev(B[c]), x1, refine={"sweeps": 2})
+        assert np.allclose(host(x1), Xh[c], rtol=0, atol=1e-12 * np.abs(Xh[c]).max())
+    assert st["steps_done"] == 6
+    assert st["checks"] == 2
+    assert 0.0 <= st["max_rel_residual"] <= 1e-11
+    assert st["rank_overflows"] == 0
+
+
+def test_solve_not_converged_leaves_x(H, tempered):
+    """An unreachable tolerance: the extra sweeps run up to max_sweeps, the
+    call fails with NOT_CONVERGED and x keeps its contents."""
+    w, op, f64, fmx, M = tempered
+    b = dev(np.ones(w.N))
+    x = torch.full((w.N,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HlevyError) as e:
+        H.solve(fmx, b, x, refine={"sweeps": 0, "tol": 1e-300, "max_sweeps": 2})
+    assert e.value.status == -4
+    assert np.all(host(x) == 7.0)
+
+
+def test_step_checks_do_not_change_the_trajectory(H, tempered):
+    """Residual checks every 7 steps (and at the last) leave the trajectory
+    bit for bit as without them, and report checks 7, 14, 21, 28 and 30."""
+    w, op, f64, fmx, M = tempered
+    ua, ub = dev(w.u0), dev(w.u0)
+    H.step(fmx, ua, w.steps, refine={"sweeps": 1})
+    st = H.step(fmx, ub, w.steps, refine={"sweeps": 1, "tol": 1e-10, "check_every": 7}, stats=True)
+    assert torch.equal(ua, ub)
+    assert st["checks"] == 5 and st["steps_done"] == w.steps
+    assert 0.0 <= st["last_rel_residual"] <= st["max_rel_residual"] <= 1e-10
+    assert st["max_sweeps_used"] == 1
+
+
+def test_step_not_converged_keeps_last_completed_step(H, tempered):
+    """A step whose check misses the target is not applied: u holds the
+    last completed step, which equals a plain run of that many steps."""
+    w, op, f64, fmx, M = tempered
+    u = dev(w.u0)
+    with pytest.raises(H.HlevyError) as e:
+        H.step(fmx, u, 20, refine={"sweeps": 1, "tol": 1e-300, "check_every": 5, "max_sweeps": 3})
+    assert e.value.status == -4
+    ref = dev(w.u0)
+    H.step(fmx, ref, 4, refine={"sweeps": 1})
+    assert torch.equal(u, ref)
+
+
+def test_step_stats_fp64_against_oracle(H, tempered):
+    """Stats on the FP64 path: the last step's residual is measured, and the
+    trajectory matches the dense oracle to 1e-10."""
+    w, op, f64, fmx, M = tempered
+    u = dev(w.u0)
+    st = H.step(f64, u, w.steps, stats=True)
+    assert st["checks"] == 1 and 0.0 <= st["last_rel_residual"] < 1e-12
+    ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0).u
+    assert np.linalg.norm(host(u) - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_step_batched_per_problem_steps(H):
+    """Per-problem step counts and stats in the batched call: every problem
+    equals hlevy_step on it alone (bit for bit), the residual of each last
+    step is measured, and a zero count leaves its vector untouched."""
+    ws = [W.config2(n=n, steps=10) for n in (700, 1024, 1500)]
+    ops = [H.assemble(lib_problem(H, w), H.make_hparams(aca_tol=1e-10, max_rank=16)) for w in ws]
+    facs = H.factor_batched(ops, [w.dt for w in ws], H.PREC_MIXED, 1e-6)
+    steps = [10, 3, 0]
+    us = [dev(w.u0) for w in ws]
+    st = H.step_batched(facs, us, steps, refine={"sweeps": 1, "tol": 1e-9}, stats=True)
+    assert st["steps_done"] == 13 and st["checks"] == 2
+    assert 0.0 <= st["max_rel_residual"] <= 1e-9
+    for f, u, w, k in zip(facs, us, ws, steps):
+        v = dev(w.u0)
+        if k:
+            H.step(f, v, k, refine={"sweeps": 1})
+        assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("dim,n", [(1, 2048), (2, 40)])
+def test_rank_cap_subdivides(H, dim, n):
+    """A rank capacity of 4 at ACA tolerance 1e-10: blocks that need more are
+    subdivided (dense at the leaf level), none is truncated, and the operator
+    still matches the dense generator to the ACA tolerance; the products run
+    on the changed structure."""
+    w = W.config2(n=n, steps=5) if dim == 1 else W.config3(s=0.75, n=n, steps=5)
+    hp = H.make_hparams(leaf=64 if dim == 1 else 32, aca_tol=1e-10, max_rank=4)
+    op = H.assemble(lib_problem(H, w), hp)
+    info = H.op_info(op)
+    assert info["subdivided_blocks"] > 0 and info["rank_overflows"] == 0 and info["max_rank"] <= 4
+    dense = torch.zeros(w.N * w.N, dtype=torch.float64, device="cuda")
+    H.op_densify(op, dense)
+    G = generator_dense(oracle_problem(w))
+    assert np.linalg.norm(host(dense).reshape(w.N, w.N) - G) / np.linalg.norm(G) < 1e-9
+    x = np.random.Generator(np.random.PCG64(3)).standard_normal(w.N)
+    y = torch.empty(w.N, dtype=torch.float64, device="cuda")
+    H.matvec(op, dev(x), y)
+    assert np.linalg.norm(host(y) - G @ x) / np.linalg.norm(G @ x) < 1e-9
+    fac = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    u = dev(w.u0)
+    H.step(fac, u, w.steps, refine={"sweeps": 2})
+    ref = cn_run(G, w.dt, w.steps, w.u0).u
+    assert np.linalg.norm(host(u) - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_fp64_factor_over_rank_cap_fails(H):
+    """FP64 factors are the direct solver: an H-LU that needs more than the
+    rank capacity fails with RANK_CAP; the mixed path reports the overflows
+    and its refinement still meets the tolerance."""
+    w = W.config2(n=2048, steps=10)
+    op = H.assemble(lib_problem(H, w), H.make_hparams(aca_tol=1e-10, max_rank=4))
+    with pytest.raises(H.HlevyError) as e:
+        H.factor(op, w.dt, H.PREC_FP64, 1e-12)
+    assert e.value.status == -5
+    fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-12)
+    assert H.fac_info(fmx)["rank_overflows"] > 0
+    u = dev(w.u0)
+    st = H.step(fmx, u, w.steps, refine={"sweeps": 3, "tol": 1e-11, "max_sweeps": 8}, stats=True)
+    assert st["last_rel_residual"] <= 1e-11
+
+
+def test_torch_allocator_and_footprint(H):
+    """Operator and factor storage through torch's caching allocator: torch
+    counts exactly the bytes the handles report, results equal those of the
+    default allocator bit for bit, and hlevy_footprint bounds the resident
+    bytes from above (within 25 %)."""
+    w = W.config2(n=4096, steps=5)
+    prob, hp = lib_problem(H, w), H.make_hparams(aca_tol=1e-10, max_rank=16)
+    torch.cuda.synchronize()
+    al = H.TorchAllocator()
+    before = torch.cuda.memory_allocated()
+    op = H.assemble(prob, hp, allocator=al)
+    fac = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    torch.cuda.synchronize()
+    grown = torch.cuda.memory_allocated() - before
+    resident = H.op_info(op)["device_bytes"] + H.fac_info(fac)["device_bytes"]
+    assert resident <= grown <= resident + 512 * 256   # torch rounds each block up to 512 bytes
+    fp = H.footprint(prob, hp, H.PREC_MIXED)
+    assert resident <= fp <= 1.25 * resident
+    op2 = H.assemble(prob, hp)
+    fac2 = H.factor(op2, w.dt, H.PREC_MIXED, 1e-6)
+    ua, ub = dev(w.u0), dev(w.u0)
+    H.step(fac, ua, w.steps, refine={"sweeps": 1})
+    H.step(fac2, ub, w.steps, refine={"sweeps": 1})
+    assert torch.equal(ua, ub)
+    del fac, op
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+
+
+def test_server_failed_operator_leaves_others(H):
+    """A request whose FP64 factorisation fails (rank cap) leaves the server
+    as failed, its memory returned; a valid request submitted with it still
+    completes, and its last-step residual is recorded."""
+    srv = H.Server(prec=H.PREC_FP64, lu_tol=1e-12, sweeps=1, chunk=5, max_active=8, tol=1e-9)
+    wb = W.config2(n=2048, steps=10)
+    good = W.config2(n=1024, steps=10)
+    out_bad = torch.zeros(wb.N, dtype=torch.float64, device="cuda")
+    out_good = torch.zeros(good.N, dtype=torch.float64, device="cuda")
+    rb = srv.submit(lib_problem(H, wb), H.make_hparams(aca_tol=1e-10, max_rank=4), wb.dt, 10, dev(wb.u0), out_bad)
+    with pytest.raises(H.HlevyError) as e:
+        srv.poll()
+    assert e.value.status == -5
+    assert srv.take_failed() == [rb]
+    st = srv.stats()
+    assert st["failed"] == 1 and st["active"] == 0 and st["bytes_in_use"] == 0
+    rg = srv.submit(lib_problem(H, good), H.make_hparams(aca_tol=1e-10, max_rank=16), good.dt, 10, dev(good.u0),
+                    out_good)
+    done = []
+    for _ in range(10):
+        done += srv.poll()
+        if rg in done:
+            break
+    assert rg in done
+    ref = dev(good.u0)
+    op = H.assemble(lib_problem(H, good), H.make_hparams(aca_tol=1e-10, max_rank=16))
+    H.step(H.factor(op, good.dt, H.PREC_FP64, 1e-12), ref, 10, refine={"sweeps": 1})
+    assert torch.equal(out_good, ref)
+    st = srv.stats()
+    assert 0.0 <= st["max_rel_residual"] <= 1e-9 and st["not_converged"] == 0

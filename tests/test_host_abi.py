@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(H):
     for name in names:
         assert hasattr(lib, name), name
     assert set(H.EXPORTS) == set(names)
-    assert H.lib.hlevy_abi_version() == 1
+    assert H.lib.hlevy_abi_version() == 2
 
 
 # ---------------------------------------------------------------------------
@@ -148,3 +148,120 @@ def test_null_arguments_rejected(H):
     assert lib.hlevy_matvec(None, None, None, None) == -1
     assert lib.hlevy_step(None, None, 1, None, None, None, None, None) == -1
     assert b"null" in lib.hlevy_last_error()
+
+
+# ---------------------------------------------------------------------------
+# host-side contract of the calls added with the refinement checks
+# ---------------------------------------------------------------------------
+def test_lowrank_block_row_limit(H):
+    """Admissible blocks are limited to 16384 rows (the ACA kernel's pivot-row
+    bitmap): N = 2^17 with N_max = N/4 is rejected by every entry point that
+    builds the trees, and accepted once n_block keeps blocks within the limit."""
+    p = H.make_problem(1, 1 << 17, -1.0, 1.0, 0.5)
+    with pytest.raises(H.HlevyError) as e:
+        H.plan_info(p, H.make_hparams())
+    assert e.value.status == -1 and "16384" in str(e.value)
+    with pytest.raises(H.HlevyError):
+        H.footprint(p, H.make_hparams())
+    info = H.plan_info(p, H.make_hparams(n_block=8))
+    assert info["N"] == 1 << 17
+
+
+def test_window_radius_must_fit_the_domain(H):
+    p = H.make_problem(1, 1024, -1.0, 1.0, 0.5, r0=2.5)
+    with pytest.raises(H.HlevyError) as e:
+        H.plan_info(p, H.make_hparams())
+    assert e.value.status == -1 and "r0" in str(e.value)
+
+
+def test_server_submit_validates_like_assembly(H):
+    """Submission runs the structure validation before touching the device:
+    an over-limit problem is rejected at submit, not later in a poll."""
+    lib = H.lib
+    cfg = H.ServerConfig(0, H.PREC_MIXED, 1e-6, 1, 10, 16, 0.0)
+    srv = ctypes.c_void_p()
+    assert lib.hlevy_server_create(ctypes.byref(cfg), None, ctypes.byref(srv)) == 0
+    try:
+        rid = ctypes.c_int64()
+        fake = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+        for prob, hp in [(H.make_problem(1, 1 << 17, -1.0, 1.0, 0.5), H.make_hparams()),
+                         (H.make_problem(1, 1024, -1.0, 1.0, 0.5, r0=3.0), H.make_hparams())]:
+            st = lib.hlevy_server_submit(srv, ctypes.byref(prob), ctypes.byref(hp), 1e-3, 10, fake, fake,
+                                         ctypes.byref(rid))
+            assert st == -1
+        stats = H.ServerStats()
+        assert lib.hlevy_server_stats_get(srv, ctypes.byref(stats)) == 0
+        assert stats.submitted == 0 and stats.failed == 0 and stats.max_rel_residual == -1.0
+        n = ctypes.c_int32(5)
+        ids = (ctypes.c_int64 * 4)()
+        assert lib.hlevy_server_take_failed(srv, ids, 4, ctypes.byref(n)) == 0 and n.value == 0
+    finally:
+        lib.hlevy_server_destroy(srv)
+
+
+def test_server_config_rejects_nonfinite_tol(H):
+    cfg = H.ServerConfig(0, H.PREC_MIXED, 1e-6, 1, 10, 16, float("nan"))
+    srv = ctypes.c_void_p()
+    assert H.lib.hlevy_server_create(ctypes.byref(cfg), None, ctypes.byref(srv)) == -1
+
+
+def _lr_blocks(pts, tree, eta, nmax):
+    """(rows, cols) of every admissible leaf of the block tree (equ:adm on
+    bounding boxes, size at most nmax)."""
+    out = []
+
+    def box(idx):
+        p = pts[idx]
+        return p.min(0), p.max(0)
+
+    def rec(lv, a, b):
+        ia, ib = tree[lv][a], tree[lv][b]
+        (la, ha), (lb, hb) = box(ia), box(ib)
+        diam = min(np.linalg.norm(ha - la), np.linalg.norm(hb - lb))
+        gap = np.maximum(0.0, np.maximum(la - hb, lb - ha))
+        dist = np.linalg.norm(gap)
+        if a != b and diam <= eta * dist and max(len(ia), len(ib)) <= nmax:
+            out.append((len(ia), len(ib)))
+        elif lv + 1 < len(tree):
+            for i in (2 * a, 2 * a + 1):
+                for j in (2 * b, 2 * b + 1):
+                    rec(lv + 1, i, j)
+
+    rec(0, 0, 0)
+    return out
+
+
+@pytest.mark.parametrize("dim,n,kcap", [(1, 4096, 16), (2, 48, 32)])
+def test_footprint_bounds_the_stored_factors(H, dim, n, kcap):
+    """hlevy_footprint covers at least the three H-matrices a factor keeps
+    (G, L^{-1}, U^{-1}), each with every admissible block at its rank
+    capacity, and the mixed path's FP32 copies of the inverse factors; and
+    it stays within a few percent of those bytes (the rest is plans and
+    vectors).  The block list comes from the independent enumeration."""
+    lo, hi = (-1.0, 1.0) if dim == 1 else (0.0, 1.0)
+    h = (hi - lo) / (n + 1)
+    x1 = lo + h * np.arange(1, n + 1)
+    if dim == 1:
+        pts = x1[:, None]
+    else:
+        X, Y = np.meshgrid(x1, x1, indexing="ij")
+        pts = np.stack([X.ravel(), Y.ravel()], 1)
+    leaf = 64 if dim == 1 else 32
+    N = pts.shape[0]
+    tree = _clusters(pts, leaf)
+    lr = _lr_blocks(pts, tree, 1.0, math.ceil(N / 4))
+    hp = H.make_hparams(leaf=leaf, max_rank=kcap, aca_tol=1e-8)
+    prob = H.make_problem(dim, n, lo, hi, 0.5)
+    info = H.plan_info(prob, hp)
+    assert len(lr) == info["n_lowrank"]
+    lr_entries = sum((m + k) * min(kcap, m, k) for m, k in lr)
+    # G holds every block; L^{-1} and U^{-1} the lower / upper halves and both the diagonal
+    diag = N * leaf   # dense diagonal leaves: at most one leaf x leaf block per leaf cluster
+    g_bytes = 8 * (info["dense_entries"] + lr_entries)
+    inv_bytes = 8 * (info["dense_entries"] + lr_entries + diag)
+    f64 = H.footprint(prob, hp, H.PREC_FP64)
+    mixed = H.footprint(prob, hp, H.PREC_MIXED)
+    assert f64 >= g_bytes + 8 * (info["dense_entries"] + lr_entries)
+    assert f64 <= 1.25 * (g_bytes + inv_bytes) + 64 * N
+    # FP32 copies of both inverse factors on the mixed path
+    assert mixed - f64 >= 4 * (info["dense_entries"] + lr_entries)

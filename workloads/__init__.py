@@ -19,7 +19,7 @@ from dataclasses import dataclass, field, replace
 import numpy as np
 
 __all__ = ["Workload", "config1", "config2", "config3", "config4_instances", "serving_pool", "serving_trace", "request_u0",
-           "grid_points", "bump_1d", "ball_power", "gaussians_2d"]
+           "grid_points", "bump_1d", "ball_power", "gaussians_2d", "workload_key"]
 
 
 @dataclass
@@ -204,3 +204,19 @@ def request_u0(req: dict) -> np.ndarray:
     w = req["w"]
     x = grid_points(w.dim, w.n, w.lo, w.hi)
     return bump_1d(x, 0.1) if w.dim == 1 else gaussians_2d(x, req["seed"])
+
+
+def workload_key(w: Workload) -> str:
+    """A hash of everything that fixes a workload's CN trajectory: the problem
+    parameters, the step size and count, and the bytes of u0, g and phi.
+    Stored results are keyed by it, so a changed recipe cannot be compared
+    with a result made for the old one."""
+    import hashlib
+    import json
+    h = hashlib.sha256()
+    scal = {k: getattr(w, k) for k in ("dim", "n", "lo", "hi", "s", "lam", "C", "a", "c", "r0", "dt", "steps")}
+    scal["b"] = list(w.b)
+    h.update(json.dumps(scal, sort_keys=True).encode())
+    for arr in (w.u0, w.g, w.phi):
+        h.update(b"-" if arr is None else np.ascontiguousarray(arr, dtype=np.float64).tobytes())
+    return h.hexdigest()[:16]
