@@ -320,6 +320,28 @@ def cn_run(G: np.ndarray, dt: float, steps: int, u0: np.ndarray,
 # ---------------------------------------------------------------------------
 # Crank-Nicolson at full size with a single N x N array (Sec. 3.2, equ:scheme)
 # ---------------------------------------------------------------------------
+def _getrf_in_place(A: np.ndarray):
+    """LAPACK getrf (partial pivoting) of the column-major matrix whose
+    memory is the row-major array A (that is, of A^T), overwriting A.
+
+    The call goes to the getrf of torch's CPU LAPACK (MKL) with its output
+    aliased to its input, which factors in place.  The OpenBLAS getrf that
+    scipy links faults (a write past one of its packing buffers) on a
+    65536 x 65536 matrix.  Returns (lu, piv) in scipy's lu_factor form:
+    lu the column-major factors (a view of A's memory), piv 0-based."""
+    import torch
+    T = torch.from_numpy(A)                         # shares A's memory
+    LU = T.T                                        # column-major view of A^T
+    piv = torch.empty(A.shape[0], dtype=torch.int32)
+    info = torch.empty((), dtype=torch.int32)
+    torch.linalg.lu_factor_ex(LU, out=(LU, piv, info))
+    if LU.data_ptr() != T.data_ptr():
+        raise RuntimeError("getrf copied the matrix; the lean path needs it in place")
+    if int(info) != 0:
+        raise RuntimeError(f"getrf: info = {int(info)}")
+    return A.T, piv.numpy().astype(np.int64) - 1
+
+
 def cn_run_lean(p: Problem, dt: float, steps: int, u0: np.ndarray,
                 g: np.ndarray | None = None, phi: np.ndarray | None = None,
                 keep_norms: bool = False, log=None) -> CNResult:
@@ -328,7 +350,8 @@ def cn_run_lean(p: Problem, dt: float, steps: int, u0: np.ndarray,
 
     The rows of M = I - dt/2 G are written, one generator row at a time, into
     one row-major array.  Read in column-major order the same memory holds
-    M^T, which LAPACK getrf factors in place: M^T = P L U.  Hence
+    M^T, which LAPACK getrf factors in place (``_getrf_in_place``):
+    M^T = P L U.  Hence
     M = U^T L^T P^T, and each step is the plain recursion
 
         rhs     = 2 u^n - M u^n + dt/2 (f^n + f^{n+1})     (M_+ = 2 I - M)
@@ -356,11 +379,7 @@ def cn_run_lean(p: Problem, dt: float, steps: int, u0: np.ndarray,
         if (i + 1) % 8192 == 0:
             say(f"assembled {i + 1}/{N} rows")
     t1 = time.perf_counter()
-    Mt = A.T                                        # column-major view of M^T
-    lu, piv = sla.lu_factor(Mt, overwrite_a=True, check_finite=False)
-    if not np.shares_memory(lu, A):
-        raise RuntimeError("getrf copied the matrix; the lean path needs it in place")
-    del Mt
+    lu, piv = _getrf_in_place(A)
     t2 = time.perf_counter()
     say(f"factored in {t2 - t1:.1f}s")
 

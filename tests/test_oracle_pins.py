@@ -13,9 +13,9 @@ import scipy.integrate as integrate
 import scipy.linalg as sla
 import scipy.special as sp
 
-from oracle.levy_oracle import (Problem, ball_const, cn_run, frac_const,
+from oracle.levy_oracle import (Problem, ball_const, cn_run, cn_run_lean, frac_const,
                                 gauss_const, generator_dense, generator_row,
-                                grid, quadrature_constants)
+                                grid, kernel_nu, quadrature_constants)
 
 
 def _order(e1, e2):
@@ -324,3 +324,54 @@ def test_manufactured_ball_solution():
         errs.append(np.max(np.abs(u - ex)[mid]))
     assert errs[1] < 1.2e-4
     assert errs[1] < errs[0]
+
+
+# ---------------------------------------------------------------------------
+# 2D tempered constants (lambda > 0): the polar-coordinate forms of C2 and T
+# against their lambda -> 0 limits (the closed forms of the fractional
+# kernel) and against plain Cartesian quadrature of the defining integrals
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_tempered_2d_constants_small_lambda_limit(s):
+    base = dict(dim=2, n=30, lo=0.0, hi=1.0, s=s, C=frac_const(2, s))
+    c0 = quadrature_constants(Problem(lam=0.0, **base))
+    lam = 1e-12
+    cl = quadrature_constants(Problem(lam=lam, **base))
+    # C2 moves by O(lam r); T by O(lam^{min(1, 2s)})
+    assert cl["C2"] == pytest.approx(c0["C2"], rel=1e-9)
+    assert cl["T"] == pytest.approx(c0["T"], rel=10 * lam ** min(1.0, 2 * s) + 1e-11)
+    assert cl["S0"] == pytest.approx(c0["S0"], rel=1e-9)
+
+
+@pytest.mark.parametrize("s,lam", [(0.25, 1.5), (0.75, 1.5), (0.6, 4.0)])
+def test_tempered_2d_constants_cartesian_quadrature(s, lam):
+    p = Problem(dim=2, n=30, lo=0.0, hi=1.0, s=s, lam=lam, C=frac_const(2, s))
+    c = quadrature_constants(p)
+    nu = lambda x, y: kernel_nu(p, math.hypot(x, y))
+    r, LW = c["r"], c["LW"]
+    # C2 = int over the square window [-r, r]^2 of nu(y) y_1^2: four equal quadrants
+    q, _ = integrate.dblquad(lambda y, x: nu(x, y) * x * x, 0.0, r, 0.0, r, epsabs=0.0, epsrel=1e-11)
+    assert c["C2"] == pytest.approx(4.0 * q, rel=1e-10)
+    # T = int over |y|_inf > L_W of nu: eight equal octants {x > L_W, 0 <= y <= x}
+    t, _ = integrate.dblquad(lambda y, x: nu(x, y), LW, np.inf, 0.0, lambda x: x, epsabs=0.0, epsrel=1e-11)
+    assert c["T"] == pytest.approx(8.0 * t, rel=1e-10)
+
+
+def test_lean_cn_equals_plain_cn():
+    """The full-size recursion (one array, factors in place, M u^n from the
+    factors) against the plain one, 1D with drift, diffusion and forcing and
+    2D, at sizes where both run."""
+    cases = []
+    p1 = Problem(dim=1, n=300, lo=-1.0, hi=1.0, a=0.05, b=(0.5, 0.0), s=0.75, lam=1.0,
+                 C=frac_const(1, 0.75))
+    x = grid(p1)[:, 0]
+    g = np.cos(x)
+    phi = np.exp(-1e-3 * np.arange(31))
+    cases.append((p1, 1e-3, 30, np.exp(-x ** 2 / 0.02), g, phi))
+    p2 = Problem(dim=2, n=16, lo=0.0, hi=1.0, s=0.25, C=frac_const(2, 0.25))
+    X = grid(p2)
+    cases.append((p2, 1e-3, 20, np.exp(-((X - 0.4) ** 2).sum(1) / 0.02), None, None))
+    for p, dt, steps, u0, g, phi in cases:
+        a = cn_run_lean(p, dt, steps, u0, g, phi).u
+        b = cn_run(generator_dense(p), dt, steps, u0, g, phi).u
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
