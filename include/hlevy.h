@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HLEVY_ABI_VERSION 2
+#define HLEVY_ABI_VERSION 3
 
 typedef enum {
   HLEVY_OK = 0,
@@ -72,13 +72,22 @@ typedef struct {
 
 /* H-matrix parameters (App. B.1): leaf size N_min, admissibility eta
  * (eq. equ:adm), N_block = ceil(N/N_max), ACA tolerance and rank capacity
- * of a low-rank block. */
+ * of a low-rank block; the tile shapes of the per-step products (0 picks
+ * them from the operator; hlevy_autotune times the alternatives), and what
+ * a factorisation does when a rounded addition needs more than the rank
+ * capacity. */
 typedef struct {
   int32_t leaf;      /* max points per leaf cluster (N_min), 16..64 */
   double eta;        /* admissibility constant, > 0 */
   int32_t n_block;   /* N_max = ceil(N / n_block); >= 1 */
   double aca_tol;    /* relative Frobenius tolerance of the far-field blocks */
   int32_t max_rank;  /* rank capacity of a low-rank block, 4..32 */
+  int32_t gather_waves;    /* wavefronts per gather workgroup: 0 (8 single, 4 batched), 4 or 8 */
+  int32_t rank_bucket;     /* register width of the low-rank product kernels: 0 (from the ranks), 8, 16 or 32 */
+  int32_t strict_rank_cap; /* 1: an FP64 factorisation whose rounded additions overflow the rank
+                              capacity fails with HLEVY_ERR_RANK_CAP; 0: the blocks are truncated
+                              at the capacity, counted in hlevy_fac_info.rank_overflows, and the
+                              refinement's residual checks guard the solutions */
 } hlevy_hparams;
 
 /* Iterative refinement of a solve M x = b preconditioned by the H-LU

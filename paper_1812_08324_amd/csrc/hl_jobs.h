@@ -11,9 +11,11 @@ namespace hl {
 
 constexpr int KMAX = 64;       // widest concatenation handled by one rounded addition
 // Rounded additions below this truncation tolerance carry double-double
-// parts through the Gram products; without them the LDS of the fused kernel
-// takes concatenations of KMAX columns, with them 48.
-constexpr double RADD_DD_TOL = 1e-9;
+// parts through the Gram products (a Gram in FP64 resolves the truncation
+// error only down to about sqrt(eps) = 1.5e-8 of the sum: at 1e-9 the
+// measured per-block error was 3e-9); without them the LDS of the fused
+// kernel takes concatenations of KMAX columns, with them 48.
+constexpr double RADD_DD_TOL = 1e-8;
 constexpr bool radd_dd(double tol) { return tol < RADD_DD_TOL; }
 constexpr int fused_width(double tol) { return radd_dd(tol) ? 48 : KMAX; }
 constexpr int LEAFMAX = 64;    // largest leaf cluster

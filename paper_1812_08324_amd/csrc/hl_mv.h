@@ -73,8 +73,9 @@ struct MvDev {
   const MvRow* rows;
   double* part;        // projection partials, kb doubles per slot
   int32_t ntiles, nrows;
-  int32_t kb;          // rank bucket of the matrix: 8, 16 or 32 (>= every leaf rank)
+  int32_t kb;          // rank bucket of the matrix: 8, 16 or 32 (leaves above it are split into kb-column chunks)
   int32_t dense_f32;   // dense leaves stored in FP32 (else FP64)
+  int32_t gw, gwb;     // wavefronts per gather workgroup: single-problem and batched launches (4 or 8)
 };
 
 // One problem of a batched product: its plan and nr <= MV_RMAX members
@@ -99,13 +100,13 @@ struct MvRef {
 };
 
 hipError_t mv_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s);
-// Batched product over problems of one rank bucket kb, dense precision and
+// Batched product over problems of one rank bucket kb, dense precision,
 // member bound rmax (1, 2 or mv_batch_rmax(kb); every problem of the launch
-// has nr <= rmax): wmap[w] names the tile of projection wavefront w (nw of
+// has nr <= rmax) and gather width gwb (4 or 8 wavefronts): wmap[w] names the tile of projection wavefront w (nw of
 // them), rmap[b] the leaf cluster of gather workgroup b (nr of them).
 // Members with steps <= step sit out.
 hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
-                           bool dense_f32, int rmax, int step, hipStream_t s);
+                           bool dense_f32, int rmax, int gwb, int step, hipStream_t s);
 // largest member count of a batched problem with rank bucket kb
 int mv_batch_rmax(int kb);
 // the two kernels of mv_launch separately; non-null events are attached to

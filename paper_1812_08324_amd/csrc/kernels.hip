@@ -15,23 +15,30 @@ typedef double double4v __attribute__((ext_vector_type(4)));
 #define HL_BLOCK 256
 
 // ---------------------------------------------------------------------------
-// double-double helpers (error-free transformations; FMA for products)
+// double-double helpers (error-free transformations; FMA for products).
+// Every helper forbids floating-point contraction: a product rounded in one
+// helper must not be fused into an addition of another after inlining (an
+// fma there would add the exact product while the low part assumes the
+// rounded one, and the pair would lose every bit beyond FP64).
 // ---------------------------------------------------------------------------
 struct dd {
   double hi, lo;
 };
 
 __device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
   double s = a + b;
   double bb = s - a;
   double e = (a - (s - bb)) + (b - bb);
   return {s, e};
 }
 __device__ __forceinline__ dd quick_two_sum(double a, double b) {
+#pragma clang fp contract(off)
   double s = a + b;
   return {s, b - (s - a)};
 }
 __device__ __forceinline__ dd dd_add(dd a, dd b) {
+#pragma clang fp contract(off)
   dd s = two_sum(a.hi, b.hi);
   dd t = two_sum(a.lo, b.lo);
   s.lo += t.hi;
@@ -41,16 +48,19 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
 }
 __device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
 __device__ __forceinline__ dd dd_mul(dd a, dd b) {
+#pragma clang fp contract(off)
   double p = a.hi * b.hi;
   double e = fma(a.hi, b.hi, -p);
   e += a.hi * b.lo + a.lo * b.hi;
   return quick_two_sum(p, e);
 }
 __device__ __forceinline__ dd dd_mul_d(double a, double b) {
+#pragma clang fp contract(off)
   double p = a * b;
   return {p, fma(a, b, -p)};
 }
 __device__ __forceinline__ dd dd_div(dd a, dd b) {
+#pragma clang fp contract(off)
   double q1 = a.hi / b.hi;
   dd r = dd_add(a, dd_neg(dd_mul({q1, 0.0}, b)));
   double q2 = r.hi / b.hi;
@@ -60,6 +70,7 @@ __device__ __forceinline__ dd dd_div(dd a, dd b) {
   return dd_add(q, {q3, 0.0});
 }
 __device__ __forceinline__ dd dd_sqrt(dd a) {
+#pragma clang fp contract(off)
   if (a.hi <= 0.0) return {0.0, 0.0};
   double x = sqrt(a.hi);
   dd xx = dd_mul_d(x, x);
@@ -627,7 +638,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_flush_core(const LFlushTarget* tg,
     const double cut = fmax(1e-16, 1e-2 * tol);
     // double-double only where the tolerance needs digits below sqrt(eps)
     rk[side] = pivoted_cholesky(Gh, Gl, side == 0 ? RA : RB, K, ks, sel, rowh, rowl, sint,
-                                fmax(cut * cut, 1e-32), tol < 1e-9);
+                                fmax(cut * cut, 1e-32), radd_dd(tol));
   }
   const int rA = rk[0], rB = rk[1];
   // M (rA x rB) and Z (rB x rB), column-major with stride ld
@@ -911,7 +922,7 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
                          double* Yh, double* Yl, double* Zh, double* Zl, double* YU, double* YV, int* pivB,
                          int* pivM, double* sref, bool b_orth = false) {
   const int tid = threadIdx.x;
-  const bool use_dd = tol < 1e-9;
+  const bool use_dd = radd_dd(tol);
   // 1. G_B = R_B^T R_B; directions below 1e-2 tol of the largest are dropped
   const double cut = fmax(1e-16, 1e-2 * tol);
   int rB;
@@ -997,7 +1008,39 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
   }
   // 4. Y_U^T = R_MJ^{-T} R_B[J,:]  and  Y_V = T1[:, J] R_MJ^{-1}; each thread
   //    solves for its own rows q (R_MJ[i][c] = row pivM[i] of the in-place
-  //    factor at column pivM[c]), no barrier between the columns
+  //    factor at column pivM[c]), no barrier between the columns.  R_MJ is
+  //    as ill-conditioned as the kept singular values are spread (up to
+  //    1/tol): with double-double parts the solves run in double-double too,
+  //    else the new factors lose their orthogonality (and C its accuracy)
+  //    by about eps / tol.
+  if (use_dd) {
+    for (int q = tid; q < K; q += HL_BLOCK) {
+      double* yu = YU + q * RA_YS;
+      double* yv = YV + q * RA_YS;
+      dd su[RA_YS], sv[RA_YS];   // r <= the rank capacity <= RA_YS
+      for (int c = 0; c < r; ++c) {
+        const int pc = pivM[c];
+        dd u = {Xh[pivB[pc] * ks + q], Xl[pivB[pc] * ks + q]};
+        dd v = {Zh[q * ks + pc], Zl[q * ks + pc]};
+        for (int i = 0; i < c; ++i) {
+          const dd rmic = {Yh[pivM[i] * ks + pc], Yl[pivM[i] * ks + pc]};
+          u = dd_add(u, dd_neg(dd_mul(rmic, su[i])));
+          v = dd_add(v, dd_neg(dd_mul(rmic, sv[i])));
+        }
+        const dd dg = {Yh[pc * ks + pc], Yl[pc * ks + pc]};
+        su[c] = dd_div(u, dg);
+        sv[c] = dd_div(v, dg);
+        yu[c] = su[c].hi;
+        yv[c] = sv[c].hi;
+      }
+      for (int c = r; c < RA_YS; ++c) {
+        yu[c] = 0.0;
+        yv[c] = 0.0;
+      }
+    }
+    __syncthreads();
+    return r;
+  }
   for (int q = tid; q < K; q += HL_BLOCK) {
     double* yu = YU + q * RA_YS;
     double* yv = YV + q * RA_YS;
@@ -1255,7 +1298,7 @@ __device__ __forceinline__ void expand_block_mfma(const double* tile, const doub
 }
 
 // Partial Gram of rows [r0, r1) of one side of a bucketed rounded
-// addition, packed upper triangle (double-double below 1e-9, else on the
+// addition, packed upper triangle (double-double below RADD_DD_TOL, else on the
 // matrix cores).
 __global__ void __launch_bounds__(HL_BLOCK) k_flush_gram(const LFlushTarget* tg, const Term* terms,
                                                          const ChunkItem* items, double tol) {
@@ -2221,7 +2264,7 @@ hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, c
   if (ntg == 0) return hipSuccess;
   hipLaunchKernelGGL(k_flush_gram, dim3(ngram), dim3(HL_BLOCK), 0, s, tg, terms, gram, tol);
   // the pivoted-Cholesky core: up to 48 columns with double-double parts,
-  // up to KMAX without (tolerances >= 1e-9)
+  // up to KMAX without (tolerances >= RADD_DD_TOL)
   if (ks <= 48 || (!radd_needs_dd(tol) && ks <= KMAX)) {
     hipLaunchKernelGGL(k_flush_core_fast, dim3(ntg), dim3(HL_BLOCK), radd_core_lds(ks, radd_needs_dd(tol)), s, tg,
                        terms, tol, ks);

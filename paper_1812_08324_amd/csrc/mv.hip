@@ -282,14 +282,14 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
   }
 }
 
-template <typename TD, int KB>
-__global__ void __launch_bounds__(64 * MV_GW) k_mv_gather(const MvRow* __restrict__ rows,
-                                                          const MvEntry* __restrict__ ents,
-                                                          const double* __restrict__ x,
-                                                          const double* __restrict__ part, MvEpi epi) {
-  __shared__ GatherLds<> L;
+template <typename TD, int KB, int GW>
+__global__ void __launch_bounds__(64 * GW) k_mv_gather(const MvRow* __restrict__ rows,
+                                                       const MvEntry* __restrict__ ents,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ part, MvEpi epi) {
+  __shared__ GatherLds<GW> L;
   const MvRow R = rows[blockIdx.x];
-  gather_rows<TD, KB>(R, ents, x, part, epi, L);
+  gather_rows<TD, KB, GW>(R, ents, x, part, epi, L);
 }
 
 int project_rows_per_pass(int kb, bool f32) {
@@ -311,16 +311,25 @@ static void project_t(const MvDev& M, const double* x, hipStream_t s, hipEvent_t
     hipLaunchKernelGGL((k_mv_project<PK, KB>), grid, dim3(256), 0, s, M.tiles, M.ntiles, x, M.part);
 }
 
+template <typename TD, int KB, int GW>
+static void gather_w(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1) {
+  const dim3 grid(M.nrows), block(64 * GW);
+  const double* part = M.part;
+  if (e0)
+    hipExtLaunchKernelGGL((k_mv_gather<TD, KB, GW>), grid, block, 0, s, e0, e1, 0, M.rows, M.ents, x, part, epi);
+  else
+    hipLaunchKernelGGL((k_mv_gather<TD, KB, GW>), grid, block, 0, s, M.rows, M.ents, x, part, epi);
+}
+
 template <typename TD, int KB>
 static void gather_t(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
                      hipEvent_t e1) {
   if (M.nrows <= 0) return;
-  const dim3 grid(M.nrows), block(64 * MV_GW);
-  const double* part = M.part;
-  if (e0)
-    hipExtLaunchKernelGGL((k_mv_gather<TD, KB>), grid, block, 0, s, e0, e1, 0, M.rows, M.ents, x, part, epi);
+  if (M.gw == 4)
+    gather_w<TD, KB, 4>(M, x, epi, s, e0, e1);
   else
-    hipLaunchKernelGGL((k_mv_gather<TD, KB>), grid, block, 0, s, M.rows, M.ents, x, part, epi);
+    gather_w<TD, KB, MV_GW>(M, x, epi, s, e0, e1);
 }
 
 template <typename TD>
@@ -349,6 +358,7 @@ hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEve
 hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
   if (M.kb != 8 && M.kb != 16 && M.kb != 32) return hipErrorInvalidValue;
+  if (M.gw != 4 && M.gw != MV_GW) return hipErrorInvalidValue;
   if (M.dense_f32)
     gather_kb<float>(M, x, epi, s, e0, e1);
   else
@@ -443,23 +453,25 @@ __global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__
 }
 
 // Batches mostly hold small problems with a few entries per leaf cluster,
-// so the gather workgroups are half as wide as in the single-problem kernel
-// and twice as many stay resident per CU.
+// so the gather workgroups are by default half as wide as in the
+// single-problem kernel (MV_GWB wavefronts) and twice as many stay resident
+// per CU.
 constexpr int MV_GWB = 4;
 
-template <int KB, int R>
+template <int KB, int R, int GWB>
 struct GatherLdsR {
   static constexpr int E = MV_EMAX / R;   // entries staged per round
-  double red[R][MV_GWB][64];
+  double red[R][GWB][64];
   MvEntry se[E];
   double ts[R][E * KB];
 };
 
-template <typename TD, int KB, int R>
-__global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __restrict__ inst,
-                                                             const MvRef* __restrict__ map, int step) {
-  __shared__ GatherLdsR<KB, R> L;
-  constexpr int E = GatherLdsR<KB, R>::E;
+template <typename TD, int KB, int R, int GWB>
+__global__ void __launch_bounds__(64 * GWB) k_mv_gather_b(const MvInst* __restrict__ inst,
+                                                          const MvRef* __restrict__ map, int step) {
+  constexpr int MV_GWB = GWB;
+  __shared__ GatherLdsR<KB, R, GWB> L;
+  constexpr int E = GatherLdsR<KB, R, GWB>::E;
   const MvRef m = map[blockIdx.x];
   const MvRow Rw = *reinterpret_cast<const MvRow*>(m.p);
   const MvInst& P = inst[wuni(m.inst)];
@@ -556,30 +568,38 @@ __global__ void __launch_bounds__(64 * MV_GWB) k_mv_gather_b(const MvInst* __res
   }
 }
 
+template <typename TD, int KB, int R>
+static void gather_b(const MvInst* inst, const MvRef* rmap, int nr, int gwb, int step, hipStream_t s) {
+  if (gwb == 8)
+    hipLaunchKernelGGL((k_mv_gather_b<TD, KB, R, 8>), dim3(nr), dim3(64 * 8), 0, s, inst, rmap, step);
+  else
+    hipLaunchKernelGGL((k_mv_gather_b<TD, KB, R, MV_GWB>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
+}
+
 template <int KB, int R>
 static void batch_t(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
-                    int step, hipStream_t s) {
+                    int gwb, int step, hipStream_t s) {
   // tiles of project_width(KB) columns into KB-wide partial slots
   constexpr int PK = project_width(KB);
   if (nw > 0)
     hipLaunchKernelGGL((k_mv_project_b<PK, R, KB>), dim3((nw + 3) / 4), dim3(256), 0, s, inst, wmap, nw, step);
   if (nr > 0) {
     if (dense_f32)
-      hipLaunchKernelGGL((k_mv_gather_b<float, KB, R>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
+      gather_b<float, KB, R>(inst, rmap, nr, gwb, step, s);
     else
-      hipLaunchKernelGGL((k_mv_gather_b<double, KB, R>), dim3(nr), dim3(64 * MV_GWB), 0, s, inst, rmap, step);
+      gather_b<double, KB, R>(inst, rmap, nr, gwb, step, s);
   }
 }
 
 template <int KB>
 static hipError_t batch_r(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, bool dense_f32,
-                          int rmax, int step, hipStream_t s) {
+                          int rmax, int gwb, int step, hipStream_t s) {
   if (rmax == 1)
-    batch_t<KB, 1>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
+    batch_t<KB, 1>(inst, wmap, nw, rmap, nr, dense_f32, gwb, step, s);
   else if (rmax == 2)
-    batch_t<KB, 2>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
+    batch_t<KB, 2>(inst, wmap, nw, rmap, nr, dense_f32, gwb, step, s);
   else if (rmax == 4 && KB <= 16)
-    batch_t<KB, (KB <= 16 ? 4 : 2)>(inst, wmap, nw, rmap, nr, dense_f32, step, s);
+    batch_t<KB, (KB <= 16 ? 4 : 2)>(inst, wmap, nw, rmap, nr, dense_f32, gwb, step, s);
   else
     return hipErrorInvalidValue;
   return hipSuccess;
@@ -588,14 +608,15 @@ static hipError_t batch_r(const MvInst* inst, const MvRef* wmap, int nw, const M
 int mv_batch_rmax(int kb) { return kb <= 16 ? 4 : 2; }
 
 hipError_t mv_batch_launch(const MvInst* inst, const MvRef* wmap, int nw, const MvRef* rmap, int nr, int kb,
-                           bool dense_f32, int rmax, int step, hipStream_t s) {
+                           bool dense_f32, int rmax, int gwb, int step, hipStream_t s) {
+  if (gwb != MV_GWB && gwb != 8) return hipErrorInvalidValue;
   hipError_t e;
   if (kb == 8)
-    e = batch_r<8>(inst, wmap, nw, rmap, nr, dense_f32, rmax, step, s);
+    e = batch_r<8>(inst, wmap, nw, rmap, nr, dense_f32, rmax, gwb, step, s);
   else if (kb == 16)
-    e = batch_r<16>(inst, wmap, nw, rmap, nr, dense_f32, rmax, step, s);
+    e = batch_r<16>(inst, wmap, nw, rmap, nr, dense_f32, rmax, gwb, step, s);
   else if (kb == 32)
-    e = batch_r<32>(inst, wmap, nw, rmap, nr, dense_f32, rmax, step, s);
+    e = batch_r<32>(inst, wmap, nw, rmap, nr, dense_f32, rmax, gwb, step, s);
   else
     return hipErrorInvalidValue;
   if (e != hipSuccess) return e;

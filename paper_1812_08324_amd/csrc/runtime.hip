@@ -405,7 +405,6 @@ struct Plan {
     };
     for (const LFlushTarget& T : ltg) {
       if (T.m < 1 || T.n < 1 || !T.U || !T.V || T.kcap < 0 || T.Kcap > KMAX || !T.info) bad("low-rank target");
-      if (T.tcount > 64) bad("more than 64 terms in one rounded addition");
       check_terms(T.tbeg, T.tcount, T.m, T.n);
     }
     for (const DFlushItem& D : dflush) {
@@ -425,6 +424,11 @@ struct Plan {
           in_range(p.b0, p.n0, ltg.size(), "low-rank target");
           in_range(p.b1, p.n1, lgram.size(), "Gram chunk");
           in_range(p.b2, p.n2, lexp.size(), "expand chunk");
+          // the chunked kernels take a target's whole term list as one
+          // concatenation (at most 64 terms); the fused kernel takes any
+          // number of terms in concatenations of its own
+          for (int q = p.b0; q < p.b0 + p.n0; ++q)
+            if (ltg[q].tcount > 64) bad("more than 64 terms in one chunked rounded addition");
           for (int q = p.b1; q < p.b1 + p.n1; ++q)
             if (lgram[q].tgt >= p.n0) bad("Gram chunk target");
           for (int q = p.b2; q < p.b2 + p.n2; ++q)
@@ -1328,8 +1332,10 @@ struct MvPlan {
 
   // lr_f32: low-rank leaves in FP32, except those with at most lr64_rows
   // rows and columns, which stay FP64
+  // force_kb: the rank bucket (0: chosen from the ranks below); gather_waves:
+  // wavefronts per gather workgroup (0: 8 single-problem, 4 batched)
   void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, bool lr_f32,
-              hipStream_t s, int lr64_rows = 0) {
+              hipStream_t s, int force_kb = 0, int gather_waves = 0, int lr64_rows = 0) {
     const double* base = M.mem;
     const float* fbase = nullptr;
     if (dense_f32 || lr_f32) {
@@ -1355,7 +1361,7 @@ struct MvPlan {
         extra16 += (rk[l] + 15) / 16 - 1;
       }
     if (kmax > 32) throw std::runtime_error("internal: rank above 32 in a product plan");
-    const int kb = 2 * extra8 <= nlr ? 8 : (10 * extra16 <= nlr ? 16 : 32);
+    const int kb = force_kb ? force_kb : (2 * extra8 <= nlr ? 8 : (10 * extra16 <= nlr ? 16 : 32));
     // projection tiles: a leaf's V rows split into at most MV_PMAX tiles of
     // whole passes; partial slots of one leaf are consecutive
     std::vector<MvTile> tiles;
@@ -1461,7 +1467,8 @@ struct MvPlan {
     upload(drows, rows, s);
     dpart.alloc(std::max<int64_t>(nslots, 1) * kb * sizeof(double));
     dev = MvDev{dtiles.as<MvTile>(), dents.as<MvEntry>(), drows.as<MvRow>(), dpart.as<double>(),
-                (int)tiles.size(), (int)rows.size(), kb, dense_f32 ? 1 : 0};
+                (int)tiles.size(), (int)rows.size(), kb, dense_f32 ? 1 : 0,
+                gather_waves ? gather_waves : 8, gather_waves ? gather_waves : 4};
   }
   void run(const double* x, const MvEpi& e, hipStream_t s) const { HL_CHECK(mv_launch(dev, x, e, s)); }
 };
@@ -1540,22 +1547,22 @@ static size_t footprint_bytes(const Structure& S, int kcap, bool mixed) {
 // each launch's work is spread over the whole chip.
 struct MvBatch {
   struct Group {
-    int kb, f32, rmax, w0, nw, r0, nr;
+    int kb, f32, rmax, gwb, w0, nw, r0, nr;
   };
   std::vector<Group> groups;
   DevBuf dw, dr;
   void create(const std::vector<const MvPlan*>& plans, const std::vector<int>& nrs, hipStream_t s) {
-    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
     for (size_t i = 0; i < plans.size(); ++i) {
       const int kb = plans[i]->dev.kb;
       const int rb = nrs[i] <= 1 ? 1 : (nrs[i] <= 2 ? 2 : mv_batch_rmax(kb));
       if (nrs[i] > rb) throw DeviceError("internal: too many members in a batched problem");
-      by[{kb, plans[i]->dev.dense_f32, rb}].push_back((int)i);
+      by[{kb, plans[i]->dev.dense_f32, rb, plans[i]->dev.gwb}].push_back((int)i);
     }
     std::vector<MvRef> w, r;
     for (auto& kv : by) {
-      Group g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), (int)w.size(), 0,
-              (int)r.size(), 0};
+      Group g{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+              (int)w.size(), 0, (int)r.size(), 0};
       int tmax = 0, rmax = 0;
       for (int i : kv.second) {
         tmax = std::max(tmax, plans[i]->dev.ntiles);
@@ -1577,7 +1584,7 @@ struct MvBatch {
   void run(const MvInst* inst, int step, hipStream_t s) const {
     for (const Group& g : groups)
       HL_CHECK(mv_batch_launch(inst, dw.as<MvRef>() + g.w0, g.nw, dr.as<MvRef>() + g.r0, g.nr, g.kb, g.f32 != 0,
-                               g.rmax, step, s));
+                               g.rmax, g.gwb, step, s));
   }
 };
 
@@ -2022,11 +2029,14 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
   HL_CHECK(hipMemcpy(&zp, zpb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
   HL_CHECK(hipMemcpy(&ovf, ovfb.p, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (zp) return fail(HLEVY_ERR_ZERO_PIVOT, "zero pivot in a diagonal leaf of the H-LU");
-  // FP64 factors are the direct solver: a rounded addition truncated at the
-  // rank capacity makes them less accurate than lu_tol says.  The mixed
-  // path's factors only precondition the refinement, which the residual
-  // checks guard; their overflows are reported (hlevy_fac_info, stats).
-  if (ovf > 0 && prec == HLEVY_PREC_FP64)
+  // A rounded addition truncated at the rank capacity leaves the factors
+  // less accurate than lu_tol says.  Such overflows are reported
+  // (hlevy_fac_info, stats) and the refinement's residual checks guard the
+  // solutions; operators assembled with strict_rank_cap refuse FP64 factors
+  // that overflow (the direct solver must then meet lu_tol).
+  bool strict = false;
+  for (hlevy_fac* f : fs) strict = strict || f->op->hp.strict_rank_cap;
+  if (ovf > 0 && prec == HLEVY_PREC_FP64 && strict)
     return fail(HLEVY_ERR_RANK_CAP, std::to_string(ovf) + " rounded additions of the FP64 H-LU needed more than "
                                         "the rank capacity (raise max_rank or lu_tol, or factor in mixed precision)");
   const bool mixed = prec == HLEVY_PREC_MIXED;
@@ -2041,9 +2051,10 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
     // far-field sums are large and cancel against the near field), which
     // adds up to ~1e-8..1e-7 over 1000 steps; preconditioner (inverse
     // factors): FP32 on the mixed path
-    f->mvG.create(S, f->op->G, read_ranks(f->op->G, s), false, false, s);
-    f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s);
-    f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s);
+    const hlevy_hparams& hp = f->op->hp;
+    f->mvG.create(S, f->op->G, read_ranks(f->op->G, s), false, false, s, hp.rank_bucket, hp.gather_waves);
+    f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s, hp.rank_bucket, hp.gather_waves);
+    f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s, hp.rank_bucket, hp.gather_waves);
     // the LU's storage is the arena's, reused by the next group
     f->LU.L.clear();
     f->LU.mem = nullptr;
@@ -2309,7 +2320,7 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     AllocScope own(&op->actx);
     op->xbuf.alloc((size_t)op->S.N * sizeof(double));
     op->ybuf.alloc((size_t)op->S.N * sizeof(double));
-    op->mv.create(op->S, op->G, rk[i], false, false, s);
+    op->mv.create(op->S, op->G, rk[i], false, false, s, op->hp.rank_bucket, op->hp.gather_waves);
   }
   aca.clear();
   HL_CHECK(hipStreamSynchronize(s));
@@ -2547,6 +2558,64 @@ struct CheckLog {
   }
 };
 
+// One right-hand side of hlevy_solve.  b, x: the caller's vectors (natural
+// order); work: 4 N doubles (b, x, z, r in cluster order); chk: 2 check slots
+// followed by 2 * check_blocks(N) partial sums (used when checking).  The
+// products are those of the one-column solve: x = U^{-1} L^{-1} b, `sweeps`
+// sweeps x += U^{-1} L^{-1} (b - M x), then at a check further sweeps while
+// the relative residual misses tol, up to maxsw.  x is written only when the
+// column is accepted.  Synchronises `s` only when checking.
+static hlevy_status solve_column(hlevy_fac* f, const double* b, double* x, double* work, double* chk, int sweeps,
+                                 double tol, int maxsw, bool checking, CheckLog& log, hipStream_t s) {
+  const int N = f->op->S.N;
+  const int32_t* perm = f->op->ds.perm.as<int32_t>();
+  const double hdt = 0.5 * f->dt;
+  double *qb = work, *qx = work + N, *qz = work + 2 * (size_t)N, *qr = work + 3 * (size_t)N;
+  HL_CHECK(launch_perm_gather(qb, b, perm, N, s));
+  MvEpi res{};               // r = b - (x - dt/2 G x)
+  res.kind = MV_EPI_RESID;
+  res.hdt = hdt;
+  res.u = qx;
+  res.b = qb;
+  res.y = qr;
+  MvEpi add{};               // x += U^{-1} z
+  add.kind = MV_EPI_ADD;
+  add.u = qx;
+  add.y = qx;
+  f->mvLi.run(qb, epi_plain(qz), s);
+  f->mvUi.run(qz, epi_plain(qx), s);
+  for (int it = 0; it < sweeps; ++it) {
+    f->mvG.run(qx, res, s);
+    f->mvLi.run(qr, epi_plain(qz), s);
+    f->mvUi.run(qz, add, s);
+  }
+  if (checking) {
+    int used = sweeps;
+    for (;;) {
+      f->mvG.run(qx, res, s);
+      HL_CHECK(launch_check_norms(qr, qb, 1.0, nullptr, 0.0, N, chk + 2, chk, s));
+      double v[2];
+      HL_CHECK(hipMemcpyAsync(v, chk, sizeof(v), hipMemcpyDeviceToHost, s));
+      HL_CHECK(hipStreamSynchronize(s));
+      const double rel = rel_residual(v[0], v[1]);
+      const bool ok = !(tol > 0.0) || rel <= tol;
+      if (ok || used >= maxsw) {
+        log.note(rel, used);
+        if (!ok)
+          return fail(HLEVY_ERR_NOT_CONVERGED, "refinement reached a relative residual of " + std::to_string(rel) +
+                                                   " after " + std::to_string(used) + " sweeps (tol " +
+                                                   std::to_string(tol) + ")");
+        break;
+      }
+      f->mvLi.run(qr, epi_plain(qz), s);
+      f->mvUi.run(qz, add, s);
+      ++used;
+    }
+  }
+  HL_CHECK(launch_perm_scatter(x, qx, perm, N, s));
+  return HLEVY_OK;
+}
+
 hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, int64_t nrhs, int64_t ld,
                          const hlevy_refine* refine, hlevy_stats* stats, void* stream) {
   if (!f || !b || !x) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
@@ -2578,6 +2647,30 @@ hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, int64_t nrhs,
                              : std::min({mv_batch_rmax(f->mvG.dev.kb), mv_batch_rmax(f->mvLi.dev.kb),
                                          mv_batch_rmax(f->mvUi.dev.kb), MV_RMAX});
     const int R = (int)std::min<int64_t>(rm, nrhs);
+    if (R == 1) {
+      // one column at a time: the work vectors and the check slots of the
+      // single-column solve
+      DevBuf work;
+      work.alloc((4 * (size_t)N + 2 + 2 * (size_t)check_blocks((int)N)) * sizeof(double));
+      for (int64_t c = 0; c < nrhs; ++c) {
+        const hlevy_status st = solve_column(f, b + (size_t)c * ld, x + (size_t)c * ld, work.as<double>(),
+                                             work.as<double>() + 4 * (size_t)N, sweeps, tol, maxsw, checking, log, s);
+        if (st != HLEVY_OK) {
+          if (stats) {
+            stats->steps_done = c;
+            stats->seconds = now_s() - t_start;
+          }
+          return st;
+        }
+      }
+      // the work vectors are freed on return: wait for the device first
+      HL_CHECK(hipStreamSynchronize(s));
+      if (stats) {
+        stats->steps_done = nrhs;
+        stats->seconds = now_s() - t_start;
+      }
+      return HLEVY_OK;
+    }
     // per member: b, x, z, r in cluster order, and partial buffers
     const size_t nG = (size_t)std::max<int64_t>(f->mvG.nslots, 1) * f->mvG.dev.kb;
     const size_t nL = (size_t)std::max<int64_t>(f->mvLi.nslots, 1) * f->mvLi.dev.kb;
@@ -2613,31 +2706,7 @@ hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, int64_t nrhs,
       for (int m = 0; m < nr; ++m)
         HL_CHECK(launch_perm_gather(mem[m].b, b + (size_t)(c0 + m) * ld, perm, (int)N, s));
       std::function<void(int)> run;   // runs product kind k for the group
-      if (R == 1) {
-        const Mem& q = mem[0];
-        run = [&, q](int k) {
-          MvEpi e{};
-          switch (k) {
-            case S_L0: f->mvLi.run(q.b, epi_plain(q.z), s); break;
-            case S_U0: f->mvUi.run(q.z, epi_plain(q.x), s); break;
-            case S_RES:
-              e.kind = MV_EPI_RESID;   // r = b - (x - dt/2 G x)
-              e.hdt = hdt;
-              e.u = q.x;
-              e.b = q.b;
-              e.y = q.r;
-              f->mvG.run(q.x, e, s);
-              break;
-            case S_L1: f->mvLi.run(q.r, epi_plain(q.z), s); break;
-            case S_ADD:
-              e.kind = MV_EPI_ADD;   // x += U^{-1} z
-              e.u = q.x;
-              e.y = q.x;
-              f->mvUi.run(q.z, e, s);
-              break;
-          }
-        };
-      } else {
+      {
         std::vector<MvInst> t(S_COUNT);
         for (int k = 0; k < S_COUNT; ++k) {
           t[k] = MvInst{};
@@ -3037,6 +3106,9 @@ static std::string srv_key(const hlevy_problem& p, const hlevy_hparams& hp, doub
   put(&hp.n_block, 4);
   put(&hp.aca_tol, 8);
   put(&hp.max_rank, 4);
+  put(&hp.gather_waves, 4);
+  put(&hp.rank_bucket, 4);
+  put(&hp.strict_rank_cap, 4);
   put(&dt, 8);
   return k;
 }

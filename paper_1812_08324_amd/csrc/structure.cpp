@@ -152,6 +152,10 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   else if (hp.n_block < 1) err << "n_block must be >= 1";
   else if (!(hp.aca_tol > 0.0 && hp.aca_tol < 1.0)) err << "aca_tol must be in (0, 1)";
   else if (hp.max_rank < 4 || hp.max_rank > 32) err << "max_rank must be in [4, 32]";
+  else if (hp.gather_waves != 0 && hp.gather_waves != 4 && hp.gather_waves != 8) err << "gather_waves must be 0, 4 or 8";
+  else if (hp.rank_bucket != 0 && hp.rank_bucket != 8 && hp.rank_bucket != 16 && hp.rank_bucket != 32)
+    err << "rank_bucket must be 0, 8, 16 or 32";
+  else if (hp.strict_rank_cap != 0 && hp.strict_rank_cap != 1) err << "strict_rank_cap must be 0 or 1";
   if (!err.str().empty()) return err.str();
   int64_t N64 = p.dim == 1 ? (int64_t)p.n : (int64_t)p.n * p.n;
   if (N64 > (int64_t)1 << 26) return "N too large (max 2^26)";

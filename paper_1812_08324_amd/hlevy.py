@@ -28,7 +28,8 @@ class Problem(C.Structure):
 
 class HParams(C.Structure):
     _fields_ = [("leaf", C.c_int32), ("eta", C.c_double), ("n_block", C.c_int32),
-                ("aca_tol", C.c_double), ("max_rank", C.c_int32)]
+                ("aca_tol", C.c_double), ("max_rank", C.c_int32), ("gather_waves", C.c_int32),
+                ("rank_bucket", C.c_int32), ("strict_rank_cap", C.c_int32)]
 
 
 class Refine(C.Structure):
@@ -181,9 +182,11 @@ def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0
     return p
 
 
-def make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16) -> HParams:
+def make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16, gather_waves=0, rank_bucket=0,
+                 strict_rank_cap=0) -> HParams:
     h = HParams()
     h.leaf, h.eta, h.n_block, h.aca_tol, h.max_rank = int(leaf), float(eta), int(n_block), float(aca_tol), int(max_rank)
+    h.gather_waves, h.rank_bucket, h.strict_rank_cap = int(gather_waves), int(rank_bucket), int(strict_rank_cap)
     return h
 
 

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(H):
     for name in names:
         assert hasattr(lib, name), name
     assert set(H.EXPORTS) == set(names)
-    assert H.lib.hlevy_abi_version() == 2
+    assert H.lib.hlevy_abi_version() == 3
 
 
 # ---------------------------------------------------------------------------
@@ -133,7 +133,9 @@ def test_invalid_problem_rejected(H, field, value):
 
 
 @pytest.mark.parametrize("field,value", [("leaf", 8), ("leaf", 128), ("eta", 0.0), ("n_block", 0),
-                                         ("aca_tol", 0.0), ("max_rank", 64)])
+                                         ("aca_tol", 0.0), ("max_rank", 64), ("gather_waves", 2),
+                                         ("gather_waves", 16), ("rank_bucket", 12), ("rank_bucket", 64),
+                                         ("strict_rank_cap", 2)])
 def test_invalid_hparams_rejected(H, field, value):
     hp = H.make_hparams()
     setattr(hp, field, value)
