@@ -271,6 +271,21 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
 hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x, int64_t nrhs, int64_t ld,
                          const hlevy_refine* refine, hlevy_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): hlevy_solve for
+ * one right-hand side (nrhs = 1) that allocates nothing.  Its work vectors
+ * and check slots live in a static device array of the library,
+ * 4 * HLEVY_NOALLOC_MAX_N + 514 doubles (about 8 MiB) on every device it
+ * runs on, held until the process ends; N above HLEVY_NOALLOC_MAX_N fails
+ * with HLEVY_ERR_INVALID_ARG.  Every call on a device shares that array:
+ * calls that overlap on one device (other streams, other host threads)
+ * race and must be serialised by the caller.  b, x, refine, stats and the
+ * result are as for hlevy_solve with nrhs = 1 (the same kernels, the same
+ * arithmetic); synchronises `stream` only when a residual check is made. */
+#define HLEVY_NOALLOC_MAX_N 262144
+hlevy_status hlevy_solve_noalloc(hlevy_fac* fac, const double* b, double* x, const hlevy_refine* refine,
+                                 hlevy_stats* stats, void* stream);
+
 /* Advance u (device, natural order, in/out) by nsteps Crank-Nicolson steps
  * of eq. equ:scheme with forcing f(x, t_n) = phi[n] g(x):
  *   M u^{n+1} = (I + dt/2 G) u^n + dt/2 (phi[n] + phi[n+1]) g.

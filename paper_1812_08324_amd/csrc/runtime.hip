@@ -13,6 +13,7 @@
 #include <map>
 #include <set>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <chrono>
@@ -1607,6 +1608,31 @@ static std::vector<int32_t> read_ranks(const HMat& M, hipStream_t s) {
 
 using namespace hl;
 
+// Scratch of hlevy_solve_noalloc: the four work vectors, the two check slots
+// and the check partial sums of one single-column solve.  Each device holds
+// its own copy until the process ends.  Host code never uses the array's
+// name as an address: the device address is taken with hipGetSymbolAddress,
+// once per device (assembly is the set-up call), and kept here.
+static constexpr size_t kScratchDoubles = 4 * (size_t)HLEVY_NOALLOC_MAX_N + 2 + 2 * 256;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_ptr;   // device ordinal -> address of `scratch` there
+
+// Device address of `scratch` on the current device (resolved on the first
+// call per device).
+static double* scratch_ptr() {
+  int dev = 0;
+  HL_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  HL_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw DeviceError("hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_ptr.emplace(dev, static_cast<double*>(p));
+  return static_cast<double*>(p);
+}
+
 struct hlevy_op {
   size_t bytes = 0;    // resident device bytes (declared first: freed last)
   AllocCtx actx{};     // the caller's allocator and this handle's byte counter
@@ -2345,6 +2371,7 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
   hlevy_status st = guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
     HL_CHECK(init_kernel_attributes());
+    (void)scratch_ptr();   // set-up of hlevy_solve_noalloc on this device
     // transient buffers of the call go through the caller's allocator too
     AllocCtx call{};
     if (al) call.al = *al;
@@ -2796,6 +2823,34 @@ hlevy_status hlevy_solve(hlevy_fac* f, const double* b, double* x, int64_t nrhs,
       stats->seconds = now_s() - t_start;
     }
     return HLEVY_OK;
+  });
+}
+
+hlevy_status hlevy_solve_noalloc(hlevy_fac* f, const double* b, double* x, const hlevy_refine* refine,
+                                 hlevy_stats* stats, void* stream) {
+  if (!f || !b || !x) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  const int64_t N = f->op->S.N;
+  if (N > HLEVY_NOALLOC_MAX_N)
+    return fail(HLEVY_ERR_INVALID_ARG, "hlevy_solve_noalloc takes N <= " + std::to_string(HLEVY_NOALLOC_MAX_N) +
+                                           " (its scratch size); use hlevy_solve");
+  if (b < x + N && x < b + N) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not overlap");
+  if (const char* e = refine_error(refine)) return fail(HLEVY_ERR_INVALID_ARG, e);
+  const double t_start = now_s();
+  CheckLog log{stats};
+  log.begin(f);
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    double* work = scratch_ptr();
+    const int sweeps = default_sweeps(f, refine);
+    const double tol = refine ? refine->tol : 0.0;
+    const int maxsw = std::max(sweeps, refine ? refine->max_sweeps : 0);
+    const hlevy_status st = solve_column(f, b, x, work, work + 4 * (size_t)N, sweeps, tol, maxsw,
+                                         stats || tol > 0.0, log, s);
+    if (stats) {
+      stats->steps_done = st == HLEVY_OK ? 1 : 0;
+      stats->seconds = now_s() - t_start;
+    }
+    return st;
   });
 }
 

@@ -75,7 +75,7 @@ class KernelTimes(C.Structure):
 
 EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
            "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
-           "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_step",
+           "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_solve_noalloc", "hlevy_step",
            "hlevy_step_batched", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
            "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_take_failed",
            "hlevy_server_stats_get", "hlevy_server_destroy"]
@@ -116,6 +116,7 @@ def _load():
         "hlevy_factor_batched": ([C.POINTER(vp), C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_double,
                                   C.c_size_t, vp, C.POINTER(vp)], st),
         "hlevy_solve": ([vp, vp, vp, C.c_int64, C.c_int64, C.POINTER(Refine), C.POINTER(Stats), vp], st),
+        "hlevy_solve_noalloc": ([vp, vp, vp, C.POINTER(Refine), C.POINTER(Stats), vp], st),
         "hlevy_step_batched": ([C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(Refine),
                                 C.POINTER(Stats), vp], st),
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
@@ -391,6 +392,16 @@ def solve(fac: Fac, b, x, refine=None, stats=False, stream=None):
     st = Stats() if stats else None
     _check(lib.hlevy_solve(fac.h, _dptr(b), _dptr(x), nrhs, fac.N, _refine(refine),
                            C.byref(st) if st is not None else None, _stream(stream)), "hlevy_solve")
+    return _stats_dict(st) if st is not None else None
+
+
+def solve_noalloc(fac: Fac, b, x, refine=None, stats=False, stream=None):
+    """Solve M x = b for one right-hand side without device allocations
+    (hlevy_solve_noalloc).  b, x: (N,) contiguous float64 CUDA tensors."""
+    st = Stats() if stats else None
+    _check(lib.hlevy_solve_noalloc(fac.h, _dptr(b, fac.N), _dptr(x, fac.N), _refine(refine),
+                                   C.byref(st) if st is not None else None, _stream(stream)),
+           "hlevy_solve_noalloc")
     return _stats_dict(st) if st is not None else None
 
 
