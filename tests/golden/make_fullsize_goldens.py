@@ -1,7 +1,10 @@
 """Writes the oracle's CN results at the benchmark sizes into this folder.
 
 Calls only ``oracle/`` (the memory-lean dense CN of ``cn_run_lean``) and the
-seeded input recipes of ``workloads``.  Each result is ``<name>.npz`` (u at
+seeded input recipes of ``workloads``.  The LU goes through MKL (torch's CPU
+LAPACK, threads from OMP_NUM_THREADS), the step loop's triangular products
+and solves through scipy's OpenBLAS (OPENBLAS_NUM_THREADS); the runs stored
+here used 6 threads each on an 8-core host.  Each result is ``<name>.npz`` (u at
 the final step and the per-step 2-norms) plus ``<name>.json`` (the workload
 key, the oracle's assembly, factorisation and stepping times, and the host
 they were measured on).  One N = 65536 run holds one 34 GB array.
@@ -52,6 +55,11 @@ def host_info():
     except Exception:
         pass
     info["blas_threads"] = os.environ.get("OPENBLAS_NUM_THREADS", "default (all cores)")
+    try:
+        import torch
+        info["lu_lapack"] = f"MKL getrf through torch {torch.__version__}, {torch.get_num_threads()} threads"
+    except Exception:
+        pass
     return info
 
 

@@ -1,13 +1,17 @@
 """GPU parity at the sizes the benchmark runs (through the C ABI).
 
-The dense oracle cannot factor N = 65536 in seconds, so at that size the
-operator is compared with the oracle row by row on sampled rows, and the
-solves and the trajectory through properties that hold at any size: the
-residual of M x = b measured with that operator, and the mixed-precision
-trajectory against the FP64 one.  The full CN trajectory is compared with
-the dense oracle at N = 4096 with the same operator parameters (tempered
-s = 0.75, lambda = 1, drift 0.5, sigma^2 = 0.1, dt = 1e-4).
+The full CN trajectories of the N = 65536 tempered workload (1000 steps)
+and of the 256 x 256 fractional workloads (s = 0.75 and 0.25, 200 steps)
+are compared with the dense oracle's, computed once on the CPU by
+tests/golden/make_fullsize_goldens.py (a single N x N array factored in
+place) and stored there with the hash of the workload they belong to.  The
+operator is also compared with oracle rows, and the solves through the
+residual of M x = b measured with that operator.  The trajectory at
+N = 4096 is compared with the dense oracle computed here.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -38,6 +42,26 @@ def lib(H, w, max_rank=16):
     return p, hp
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name, w):
+    """u at the last step from the stored full-size oracle run `name`, after
+    checking that it was made for this workload (same hash)."""
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {name} (tests/golden/make_fullsize_goldens.py writes it)")
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        meta = json.load(f)
+    assert meta["key"] == W.workload_key(w), "stored oracle result made for another workload"
+    with np.load(path) as z:
+        return z["u"]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 def dev(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
@@ -66,8 +90,10 @@ def residual(H, w, op, x, b):
 
 
 def test_operator_rows_at_full_size(H, full):
-    """y = G x at N = 65536 against oracle rows (sampled, boundaries included):
-    each row within the ACA tolerance, |y_i - g_i . x| <= 10 aca_tol |g_i| |x|."""
+    """y = G x at N = 65536 against oracle rows (sampled, boundaries included),
+    |y_i - g_i . x| <= 10 aca_tol |g_i| |x|.  The 1/h^2 near field dominates
+    this bound; the far field is held to the ACA tolerance block by block
+    in test_gpu_far_field.py."""
     w, op, _, _ = full
     rng = np.random.Generator(np.random.PCG64(65536))
     x = rng.standard_normal(w.N)
@@ -113,16 +139,20 @@ def test_mixed_solve_residual_at_full_size(H, full):
     assert res[1] < 1e-9 and res[2] < 1e-9, res
 
 
-def test_mixed_trajectory_at_full_size(H, full):
-    """1000 CN steps at N = 65536: the mixed path (one sweep per step) within
-    rel-L2 1e-8 of the FP64 path."""
+@pytest.mark.parametrize("path", ["fp64_plain", "fp64", "mixed"])
+def test_trajectory_vs_fullsize_oracle(H, full, path):
+    """1000 CN steps at N = 65536 against the dense oracle's trajectory:
+    the FP64 direct H-solve (no refinement) and with one refinement sweep
+    within rel-L2 1e-10, the mixed path (one sweep per step) within 1e-8."""
     w, op, f64, fmx = full
-    ua = dev(w.u0)
-    ub = dev(w.u0)
-    H.step(f64, ua, w.steps)
-    H.step(fmx, ub, w.steps, refine={"sweeps": 1})
-    err = float(torch.linalg.norm(ua - ub) / torch.linalg.norm(ua))
-    assert err <= 1e-8, err
+    ref = golden("tempered1d_s0.75_n65536", w)
+    fac, sweeps, bar = {"fp64_plain": (f64, 0, 1e-10), "fp64": (f64, 1, 1e-10), "mixed": (fmx, 1, 1e-8)}[path]
+    u = dev(w.u0)
+    st = H.step(fac, u, w.steps, refine={"sweeps": sweeps}, stats=True)
+    err = rel(host(u), ref)
+    print(f"{path}: rel-L2 vs oracle {err:.3e}, last residual {st['last_rel_residual']:.2e}")
+    assert err <= bar, err
+    assert st["rank_overflows"] == 0
 
 
 def test_tempered_trajectory_vs_oracle_n4096(H):
@@ -145,13 +175,14 @@ def test_tempered_trajectory_vs_oracle_n4096(H):
     assert emx <= 1e-8, emx
 
 
-@pytest.fixture(scope="module")
-def full2d(H):
-    """The 2D workload at full size: 256 x 256 grid, s = 0.75, ACA rank <= 32
-    at 1e-8; FP64 factors (lu_tol 1e-10) and mixed factors (1e-6)."""
-    w = W.config3(s=0.75, n=256)
+@pytest.fixture(scope="module", params=[0.75, 0.25], ids=["s0.75", "s0.25"])
+def full2d(H, request):
+    """The 2D workload at full size: 256 x 256 grid, s = 0.75 and 0.25, ACA
+    rank <= 32 at 1e-8; FP64 factors (lu_tol 1e-10) and mixed factors (1e-6)."""
+    w = W.config3(s=request.param, n=256)
     p, hp = lib(H, w, max_rank=w.max_rank)
     op = H.assemble(p, hp)
+    assert H.op_info(op)["rank_overflows"] == 0
     f64 = H.factor(op, w.dt, H.PREC_FP64, w.lu_tol)
     fmx = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
     return w, op, f64, fmx
@@ -191,13 +222,19 @@ def test_2d_solve_residuals_at_full_size(H, full2d):
     assert residual(H, w, op, x, b) < 1e-10
 
 
-def test_2d_mixed_trajectory_at_full_size(H, full2d):
-    """200 CN steps on the 256 x 256 grid: the mixed path (one sweep) within
-    1e-8 of the FP64 path."""
+def test_2d_trajectories_vs_fullsize_oracle(H, full2d):
+    """200 CN steps on the 256 x 256 grid against the dense oracle's
+    trajectory: the FP64 path (one sweep: its factors overflow the rank
+    capacity, which the sweep repairs) within 1e-10, the mixed path (one
+    sweep) within 1e-8."""
     w, op, f64, fmx = full2d
+    ref = golden(w.name, w)
     ua = dev(w.u0)
     ub = dev(w.u0)
-    H.step(f64, ua, w.steps)
+    H.step(f64, ua, w.steps, refine={"sweeps": 1})
     H.step(fmx, ub, w.steps, refine={"sweeps": 1})
-    err = float(torch.linalg.norm(ua - ub) / torch.linalg.norm(ua))
-    assert err <= 1e-8, err
+    e64, emx = rel(host(ua), ref), rel(host(ub), ref)
+    print(f"{w.name}: FP64 {e64:.3e}, mixed {emx:.3e} (FP64 factor overflows "
+          f"{H.fac_info(f64)['rank_overflows']})")
+    assert e64 <= 1e-10, e64
+    assert emx <= 1e-8, emx
