@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_mv_gather_G_tempered1d_n65536.txt")
+TUNE_CACHE = os.path.join(ROOT, "paper_1812_08324_amd", "tuning", "mi355x.json")
 WORKLOADS = {
     "tempered1d_n65536": dict(kind="config2", n=65536, steps=1000),
     "tempered1d_n16384": dict(kind="config2", n=16384, steps=1000),
@@ -46,6 +47,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison job")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-worklist measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache of the batched workload ('' = tune every run, keep nothing)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival window of the serving measurement (0 = skip)")
     ap.add_argument("--serve-frac-1d", type=float, default=1.0,
@@ -110,28 +113,60 @@ def cpu_baseline(w, sample_n=4096, sample_steps=50):
     }
 
 
-def bench_batched(H, torch, sweeps, lu_tol):
+def tune_batched(H, ws, probs, hp, lu_tol, cache):
+    """Leaf size and tile shapes of the batched workload from the autotuner:
+    one tuning per power-of-two bucket of N (its median-N instance, the
+    batched entry points on copies of it), read from the cache when the
+    bucket is there.  Returns the per-instance parameters and a summary."""
+    import math
+    import numpy as np
+    buckets = {}
+    for i, w in enumerate(ws):
+        buckets.setdefault(int(round(math.log2(w.n))), []).append(i)
+    per, summary = [None] * len(ws), {}
+    t0 = time.perf_counter()
+    for b, idx in sorted(buckets.items()):
+        rep = sorted(idx, key=lambda i: ws[i].n)[len(idx) // 2]
+        tuned, res = H.autotune(probs[rep], hp, ws[rep].dt, H.PREC_MIXED, lu_tol, ws[rep].steps, batch=len(idx),
+                                cache=cache or None)
+        for i in idx:
+            per[i] = tuned
+        summary[f"2^{b}"] = {"problems": len(idx), "tuned_on_n": ws[rep].n, "leaf": res["leaf"],
+                             "gather_waves": res["gather_waves"], "rank_bucket": res["rank_bucket"],
+                             "from_cache": res["from_cache"], "seconds_per_problem": res["seconds"],
+                             "default_seconds_per_problem": res["default_seconds"],
+                             "gain_vs_default": res["default_seconds"] / res["seconds"]}
+    return per, {"cache": os.path.relpath(cache, ROOT) if cache else None, "tune_s": time.perf_counter() - t0,
+                 "buckets": summary,
+                 "note": "objective: whole job per problem (assembly + factorisation + 100 steps) timed by the "
+                         "autotuner on the device; default = leaf 64, tile shapes chosen from the ranks"}
+
+
+def bench_batched(H, torch, sweeps, lu_tol, tune_cache):
     """The batched worklist: 512 independent 1D tempered problems (N
     log-uniform in [2^10, 2^15], s, drift, sigma^2, lambda drawn with PCG64
-    seed 8324), mixed precision, 100 CN steps of dt = 1e-3 each.  Whole job =
-    assembly of every operator, one joint factorisation plan, the batched
-    steps; inputs resident in HBM before timing.  Assembly, factorisation
-    and stepping are each one batched call."""
+    seed 8324), mixed precision, 100 CN steps of dt = 1e-3 each, leaf size
+    and tile shapes from the autotuner.  Whole job = assembly of every
+    operator, one joint factorisation plan, the batched steps; inputs
+    resident in HBM before timing.  Assembly, factorisation and stepping are
+    each one batched call."""
     import workloads as W
     ws = W.config4_instances()
-    hp = H.make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16)
+    hp0 = H.make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16)
     probs = [H.make_problem(1, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
              for w in ws]
+    hps, tune = tune_batched(H, ws, probs, hp0, lu_tol, tune_cache)
+    progress(f"batched autotune: {tune['tune_s']:.1f}s")
     u0 = [torch.tensor(w.u0, dtype=torch.float64, device="cuda") for w in ws]
     steps = ws[0].steps
     # warm the batched kernels on a few problems
-    ops = [H.assemble(p, hp) for p in probs[:4]]
+    ops = [H.assemble(p, h) for p, h in zip(probs[:4], hps[:4])]
     fs = H.factor_batched(ops, [w.dt for w in ws[:4]], H.PREC_MIXED, lu_tol)
     H.step_batched(fs, [u.clone() for u in u0[:4]], 2, refine={"sweeps": sweeps})
     del fs, ops
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ops = H.assemble_batched(probs, [hp] * len(probs))
+    ops = H.assemble_batched(probs, hps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     facs = H.factor_batched(ops, [w.dt for w in ws], H.PREC_MIXED, lu_tol)
@@ -185,6 +220,7 @@ def bench_batched(H, torch, sweeps, lu_tol):
                                        f"scaled by unknowns ({l1 - l0:.2f}s measured)"},
         "step": {"bytes": step_bytes, "ms": 1e3 * (t4 - t3) / steps, "GBps": gbps, "frac": gbps / HBM_PEAK_GBS,
                  "note": "all kernels of a batched step (projections, gathers) over its algorithmic bytes"},
+        "autotune": tune,
     }
 
 
@@ -455,7 +491,7 @@ def main():
     del fac, op
     progress("headline job done")
     if not args.no_batched:
-        line["batched"] = bench_batched(H, torch, args.sweeps, args.lu_tol_mixed)
+        line["batched"] = bench_batched(H, torch, args.sweeps, args.lu_tol_mixed, args.tune_cache)
         progress("batched workload done")
     if not args.no_2d:
         line["frac2d"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed)

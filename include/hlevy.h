@@ -286,6 +286,39 @@ hlevy_status hlevy_solve(hlevy_fac* fac, const double* b, double* x, int64_t nrh
 hlevy_status hlevy_solve_noalloc(hlevy_fac* fac, const double* b, double* x, const hlevy_refine* refine,
                                  hlevy_stats* stats, void* stream);
 
+/* Autotuner of the leaf size and the tile shapes of the per-step products
+ * (the batched worklist's "autotuned leaf and tile sizes"): for the problem
+ * and the caller's parameters `base`, every candidate of leaf {64, 32} x
+ * gather_waves {0, 4, 8} x rank_bucket {0, 16} (base's own values first)
+ * is assembled, factored (prec, lu_tol) and stepped on the device; the
+ * objective is the whole job per problem, assembly + factorisation +
+ * nsteps steps at the measured rate (one refinement sweep per step).  With
+ * batch > 1 the candidates run through the batched entry points on
+ * min(batch, 8) copies, so the batched kernels are the ones timed.  The
+ * fastest candidate is returned in out (leaf, gather_waves, rank_bucket;
+ * the other fields of base are kept by the caller) with its objective and
+ * that of base.  cache_path (NULL: none) names a JSON file of earlier
+ * choices keyed by dimension, N rounded to a power of two, precision and
+ * batched-or-single: a key found there is returned without device work
+ * (from_cache = 1), a new choice is added to it.  Synchronises `stream`.
+ * Errors: HLEVY_ERR_INVALID_ARG for invalid arguments or an unwritable
+ * cache; errors of the trial calls as they return them. */
+#define HLEVY_TUNE_MAX_CAND 16
+typedef struct {
+  int32_t leaf, gather_waves, rank_bucket; /* the fastest candidate */
+  int32_t from_cache;                      /* 1: read from the cache, nothing timed */
+  int32_t ncand, pad;                      /* candidates timed */
+  double seconds;                          /* its whole job per problem */
+  double default_seconds;                  /* base's whole job per problem */
+  int32_t cand_leaf[HLEVY_TUNE_MAX_CAND], cand_gather_waves[HLEVY_TUNE_MAX_CAND],
+      cand_rank_bucket[HLEVY_TUNE_MAX_CAND];
+  double cand_seconds[HLEVY_TUNE_MAX_CAND];
+} hlevy_tune_result;
+
+hlevy_status hlevy_autotune(const hlevy_problem* prob, const hlevy_hparams* base, double dt, int32_t prec,
+                            double lu_tol, int64_t nsteps, int32_t batch, const char* cache_path, void* stream,
+                            hlevy_tune_result* out);
+
 /* Advance u (device, natural order, in/out) by nsteps Crank-Nicolson steps
  * of eq. equ:scheme with forcing f(x, t_n) = phi[n] g(x):
  *   M u^{n+1} = (I + dt/2 G) u^n + dt/2 (phi[n] + phi[n+1]) g.

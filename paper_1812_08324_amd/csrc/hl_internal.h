@@ -68,6 +68,9 @@ constexpr int32_t LR_ROWS_MAX = 16384;
 std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Structure& s,
                             const std::set<std::pair<int32_t, int32_t>>* split = nullptr);
 
+// Sets the thread-local message hlevy_last_error() returns.
+void set_last_error(const std::string& msg);
+
 // Whether the leaf is strictly below / above the diagonal.
 inline bool leaf_lower(const LeafInfo& l) { return l.clo + l.n <= l.rlo; }
 inline bool leaf_upper(const LeafInfo& l) { return l.rlo + l.m <= l.clo; }

@@ -44,6 +44,8 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 static hlevy_status fail(hlevy_status st, const std::string& msg) {
   g_last_error = msg;
   return st;

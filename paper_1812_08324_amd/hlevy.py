@@ -73,7 +73,15 @@ class KernelTimes(C.Structure):
                 ("v_bytes", C.c_double * 3), ("partial_bytes", C.c_double * 3)]
 
 
-EXPORTS = ["hlevy_abi_version", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
+class TuneResult(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("gather_waves", C.c_int32), ("rank_bucket", C.c_int32),
+                ("from_cache", C.c_int32), ("ncand", C.c_int32), ("pad", C.c_int32),
+                ("seconds", C.c_double), ("default_seconds", C.c_double),
+                ("cand_leaf", C.c_int32 * 16), ("cand_gather_waves", C.c_int32 * 16),
+                ("cand_rank_bucket", C.c_int32 * 16), ("cand_seconds", C.c_double * 16)]
+
+
+EXPORTS = ["hlevy_abi_version", "hlevy_autotune", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
            "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
            "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_solve_noalloc", "hlevy_step",
            "hlevy_step_batched", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
@@ -123,6 +131,8 @@ def _load():
                         C.POINTER(Stats), vp], st),
         "hlevy_fac_kernel_times": ([vp, C.c_int32, vp, C.POINTER(KernelTimes)], st),
         "hlevy_fac_apply": ([vp, C.c_int32, vp, vp, vp], st),
+        "hlevy_autotune": ([C.POINTER(Problem), C.POINTER(HParams), C.c_double, C.c_int32, C.c_double, C.c_int64,
+                            C.c_int32, C.c_char_p, vp, C.POINTER(TuneResult)], st),
         "hlevy_server_create": ([C.POINTER(ServerConfig), vp, C.POINTER(vp)], st),
         "hlevy_server_submit": ([vp, C.POINTER(Problem), C.POINTER(HParams), C.c_double, C.c_int64, vp, vp,
                                  C.POINTER(C.c_int64)], st),
@@ -219,6 +229,26 @@ class TorchAllocator:
 
     def _free(self, p, ctx):
         self._torch.cuda.caching_allocator_delete(p)
+
+
+def autotune(prob: Problem, hp: HParams, dt: float, prec: int, lu_tol: float, nsteps: int, batch: int = 1,
+             cache=None, stream=None):
+    """hlevy_autotune: returns (HParams with the chosen leaf and tile shapes,
+    the result as a dict).  With a cache file whose key matches, no device
+    work runs (and no stream is needed)."""
+    out = TuneResult()
+    path = None if cache is None else os.fsencode(cache)
+    _check(lib.hlevy_autotune(C.byref(prob), C.byref(hp), float(dt), int(prec), float(lu_tol), int(nsteps),
+                              int(batch), path, _stream(stream), C.byref(out)), "hlevy_autotune")
+    n = out.ncand
+    res = {"leaf": out.leaf, "gather_waves": out.gather_waves, "rank_bucket": out.rank_bucket,
+           "from_cache": bool(out.from_cache), "seconds": out.seconds, "default_seconds": out.default_seconds,
+           "candidates": [{"leaf": out.cand_leaf[i], "gather_waves": out.cand_gather_waves[i],
+                           "rank_bucket": out.cand_rank_bucket[i], "seconds": out.cand_seconds[i]}
+                          for i in range(n)]}
+    tuned = HParams.from_buffer_copy(hp)
+    tuned.leaf, tuned.gather_waves, tuned.rank_bucket = out.leaf, out.gather_waves, out.rank_bucket
+    return tuned, res
 
 
 def plan_info(prob: Problem, hp: HParams) -> dict:

@@ -284,3 +284,28 @@ def test_tile_shapes_keep_results(H, leaf, gw, kb):
         for v, r in zip(us, refs):
             err = np.linalg.norm(host(v) - r) / np.linalg.norm(r)
             assert err <= bar, (prec, "batched", err)
+
+
+def test_autotune_times_candidates_and_reuses_its_cache(H, tmp_path):
+    """The autotuner times the candidates on the device (batched entry
+    points), picks the fastest whole job, writes its choice to the cache and
+    returns it from there on the next call (also for another N of the same
+    power-of-two bucket); the tuned parameters give the oracle's trajectory."""
+    w = W.config2(n=3000, steps=30)
+    prob, hp = lib_problem(H, w), H.make_hparams(aca_tol=1e-10, max_rank=16)
+    path = tmp_path / "tune.json"
+    tuned, res = H.autotune(prob, hp, w.dt, H.PREC_MIXED, 1e-6, 100, batch=4, cache=str(path))
+    assert not res["from_cache"] and len(res["candidates"]) == 12
+    assert res["seconds"] == min(c["seconds"] for c in res["candidates"]) <= res["default_seconds"]
+    assert res["candidates"][0]["leaf"] == 64 and res["candidates"][0]["seconds"] == res["default_seconds"]
+    assert path.exists()
+    w2 = W.config2(n=3500, steps=30)
+    tuned2, res2 = H.autotune(lib_problem(H, w2), hp, w.dt, H.PREC_MIXED, 1e-6, 100, batch=4, cache=str(path))
+    assert res2["from_cache"] and (res2["leaf"], res2["gather_waves"], res2["rank_bucket"]) == \
+        (res["leaf"], res["gather_waves"], res["rank_bucket"])
+    op = H.assemble(prob, tuned)
+    f = H.factor(op, w.dt, H.PREC_MIXED, 1e-6)
+    u = dev(w.u0)
+    H.step(f, u, w.steps, refine={"sweeps": 1})
+    ref = cn_run(generator_dense(oracle_problem(w)), w.dt, w.steps, w.u0).u
+    assert np.linalg.norm(host(u) - ref) / np.linalg.norm(ref) <= 1e-8

@@ -267,3 +267,22 @@ def test_footprint_bounds_the_stored_factors(H, dim, n, kcap):
     assert f64 <= 1.25 * (g_bytes + inv_bytes) + 64 * N
     # FP32 copies of both inverse factors on the mixed path
     assert mixed - f64 >= 4 * (info["dense_entries"] + lr_entries)
+
+
+def test_autotune_cache_hit_needs_no_device(H, tmp_path):
+    """A tuning cache entry for the problem's key (dimension, N rounded to a
+    power of two, precision, batched) is returned as stored, without device
+    work; other keys, other precisions and the single path miss it."""
+    path = tmp_path / "tune.json"
+    path.write_text('{"version": 1, "entries": {"d1_n13_p1_batched": {"leaf": 32, "gather_waves": 4, '
+                    '"rank_bucket": 16, "seconds": 0.0125, "default_seconds": 0.015}}}\n')
+    prob = H.make_problem(1, 9000, -1.0, 1.0, 0.4, lam=0.5, a=0.01, b=(0.3, 0.0))
+    hp = H.make_hparams(aca_tol=1e-10, max_rank=16)
+    tuned, res = H.autotune(prob, hp, 1e-3, H.PREC_MIXED, 1e-6, 100, batch=8, cache=str(path), stream=0)
+    assert res["from_cache"] and (res["leaf"], res["gather_waves"], res["rank_bucket"]) == (32, 4, 16)
+    assert res["seconds"] == 0.0125 and res["default_seconds"] == 0.015
+    assert (tuned.leaf, tuned.gather_waves, tuned.rank_bucket) == (32, 4, 16)
+    assert tuned.max_rank == 16 and tuned.aca_tol == 1e-10
+    with pytest.raises(H.HlevyError) as e:      # invalid arguments are rejected before the cache
+        H.autotune(prob, hp, -1.0, H.PREC_MIXED, 1e-6, 100, batch=8, cache=str(path), stream=0)
+    assert e.value.status == -1
