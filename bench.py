@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--lu-tol-fp64", type=float, default=1e-12)
     ap.add_argument("--sweeps", type=int, default=1, help="refinement sweeps per CN step (mixed)")
     ap.add_argument("--sweeps-fp64", type=int, default=1, help="refinement sweeps per CN step (FP64 job)")
+    ap.add_argument("--sweeps-bf16", type=int, default=4, help="refinement sweeps per CN step (BF16 job)")
     ap.add_argument("--max-rank", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison job")
@@ -224,17 +225,19 @@ def bench_batched(H, torch, sweeps, lu_tol, tune_cache):
     }
 
 
-def bench_2d(H, torch, sweeps, lu_tol_mixed):
+def bench_2d(H, torch, sweeps, lu_tol_mixed, s=0.75, kernel_times=True):
     """The 2D fractional-Laplacian workload: unit square, 256 x 256 grid
-    (N = 65536), s = 0.75, ACA rank <= 32 at 1e-8, dt = 1e-3, 200 CN steps,
-    seeded 8-Gaussian u0; mixed precision (FP32 inverse factors at 1e-6, FP64
-    refinement) against the FP64 factors (lu_tol 1e-10)."""
+    (N = 65536), s = 0.75 or 0.25, ACA rank <= 32 at 1e-8, dt = 1e-3, 200 CN
+    steps, seeded 8-Gaussian u0; mixed precision (FP32 inverse factors at
+    1e-6, FP64 refinement) against the FP64 factors (lu_tol 1e-10, one
+    refinement sweep), both against the stored full-size oracle run."""
     import workloads as W
-    w = W.config3(s=0.75, n=256)
+    w = W.config3(s=s, n=256)
+    ref, _ = oracle_result(w.name, w)
     prob = H.make_problem(2, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
     hp = H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol, max_rank=w.max_rank)
     u0 = torch.tensor(w.u0, dtype=torch.float64, device="cuda")
-    out = {"workload": "frac2d_s0.75_256x256", "N": w.N, "cn_steps": w.steps, "dt": w.dt}
+    out = {"workload": w.name, "N": w.N, "cn_steps": w.steps, "dt": w.dt}
     res = {}
     for name, prec, tol, sw in (("mixed", H.PREC_MIXED, lu_tol_mixed, sweeps), ("fp64", H.PREC_FP64, w.lu_tol, 1)):
         torch.cuda.synchronize()
@@ -252,8 +255,9 @@ def bench_2d(H, torch, sweeps, lu_tol_mixed):
         res[name] = u
         out[name] = {"cn_steps_per_s": w.steps / (t3 - t0), "lu_tol": tol, "sweeps": sw,
                      "phases_s": {"assemble": t1 - t0, "factor": t2 - t1, "steps": t3 - t2},
-                     "steady_cn_steps_per_s": w.steps / (t3 - t2)}
-        if name == "mixed":
+                     "steady_cn_steps_per_s": w.steps / (t3 - t2), "rel_l2_vs_oracle": rel_to(u, ref),
+                     "factor_rank_overflows": H.fac_info(fac)["rank_overflows"]}
+        if name == "mixed" and kernel_times:
             kt = H.fac_kernel_times(fac, reps=5)
             g = kt["G"]
             gb = g["dense_bytes"] + g["u_bytes"] + 16.0 * w.N
@@ -264,7 +268,7 @@ def bench_2d(H, torch, sweeps, lu_tol_mixed):
             out["matvec_G"] = {"bytes": mvb, "ms": mvms, "GBps": mvb / (mvms * 1e-3) / 1e9,
                                "frac": mvb / (mvms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del fac, op
-        progress(f"2D {name} job done")
+        progress(f"2D {w.name} {name} job done")
     out["rel_l2_mixed_vs_fp64"] = float(torch.linalg.norm(res["mixed"] - res["fp64"]) / torch.linalg.norm(res["fp64"]))
     out["speedup_mixed_vs_fp64"] = out["mixed"]["cn_steps_per_s"] / out["fp64"]["cn_steps_per_s"]
     return out
@@ -289,6 +293,35 @@ def counted_traffic(key, algorithmic_bytes=None):
         return float(fields[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_result(name, w):
+    """u at the last step of the stored full-size oracle run `name` and its
+    metadata (timings, host), or (None, None) when it is absent or was made
+    for another workload."""
+    import numpy as np
+    import workloads as W
+    try:
+        with open(os.path.join(GOLDEN, name + ".json")) as f:
+            meta = json.load(f)
+        if meta["key"] != W.workload_key(w):
+            return None, None
+        with np.load(os.path.join(GOLDEN, name + ".npz")) as z:
+            return z["u"], meta
+    except (OSError, KeyError, ValueError):
+        return None, None
+
+
+def rel_to(u, ref):
+    """rel-L2 of a device vector against an oracle array (None without one)."""
+    import numpy as np
+    if ref is None:
+        return None
+    a = u.detach().cpu().numpy()
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
 
 
 def progress(msg):
@@ -392,6 +425,8 @@ def main():
         print(json.dumps({"metric": "CN steps/s", "value": value, "elapsed_s": elapsed}))
         return
 
+    ref, ref_meta = oracle_result("tempered1d_s0.75_n65536", w) if args.workload == "tempered1d_n65536" \
+        else (None, None)
     # phase split and steady-state stepping of the mixed path
     torch.cuda.synchronize()
     s0 = time.perf_counter()
@@ -428,8 +463,18 @@ def main():
             "fp64_steady_cn_steps_per_s": w.steps / (f2 - f1),
             "speedup_mixed_vs_fp64": value / (w.steps / (f1 - f0)),
             "rel_l2_mixed_vs_fp64": diff,
+            "rel_l2_fp64_vs_oracle": rel_to(u64, ref),
         }
         del fac64, op64
+    # BF16 low-rank leaves of the inverse factors (same job, more sweeps)
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
+    ubf, _, _ = job(H.PREC_MIXED_BF16, args.lu_tol_mixed, args.sweeps_bf16)
+    torch.cuda.synchronize()
+    b1 = time.perf_counter()
+    extra["bf16"] = {"cn_steps_per_s": w.steps / (b1 - b0), "sweeps": args.sweeps_bf16,
+                     "rel_l2_vs_oracle": rel_to(ubf, ref),
+                     "note": "low-rank leaves of the inverse factors in BF16, dense leaves FP32"}
 
     # roofline of the dominant per-step kernel (largest share of a step's
     # kernel time; a mixed step with one sweep runs each product twice).
@@ -477,6 +522,10 @@ def main():
                    "aca_tol": w.aca_tol, "lu_tol_mixed": args.lu_tol_mixed, "sweeps": args.sweeps,
                    "lu_tol_fp64": args.lu_tol_fp64, "sweeps_fp64": args.sweeps_fp64,
                    "max_rank": args.max_rank},
+        "rel_l2_vs_oracle": rel_to(u_mixed, ref),
+        "oracle": None if ref_meta is None else {
+            "stored": "tests/golden/tempered1d_s0.75_n65536", "timings_s": ref_meta["timings"],
+            "host": ref_meta["host"]},
         "phases_s": {"assemble": s1 - s0, "factor_mixed": s2 - s1, "steps_mixed": s3 - s2},
         "steady_cn_steps_per_s_mixed": steady_mixed,
         "operator": {"max_rank": opinfo["max_rank"], "mean_rank": opinfo["mean_rank"],
@@ -494,7 +543,8 @@ def main():
         line["batched"] = bench_batched(H, torch, args.sweeps, args.lu_tol_mixed, args.tune_cache)
         progress("batched workload done")
     if not args.no_2d:
-        line["frac2d"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed)
+        line["frac2d"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed, s=0.75)
+        line["frac2d_s0.25"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed, s=0.25, kernel_times=False)
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.sweeps,
                                         args.lu_tol_mixed)
@@ -517,6 +567,13 @@ def main():
                 "unit": "problem CN steps/s (whole job, extrapolated)", "cores": cb["cores"], "kind": "oracle",
                 "sample": f"dense oracle timings at N={t['n']} scaled to the 512 problems ({tot:.0f}s per job)"}
         line["cpu_baseline"].pop("_parts", None)
+        if ref_meta is not None:
+            t = ref_meta["timings"]
+            full = t["assembly_s"] + t["factor_s"] + t["steps_s"]
+            line["cpu_baseline"]["full_size_measured"] = {
+                "value": w.steps / full, "unit": "CN steps/s (whole job)", "seconds": full,
+                "timings_s": t, "host": ref_meta["host"],
+                "note": "the same oracle run once at the full size on the build host (not the GPU box)"}
     print(json.dumps(line))
 
 

@@ -51,8 +51,10 @@ typedef enum {
 } hlevy_status;
 
 typedef enum {
-  HLEVY_PREC_FP64 = 0,   /* FP64 factors, plain forward/backward solve */
-  HLEVY_PREC_MIXED = 1   /* FP32 factors as a preconditioner + FP64 iterative refinement */
+  HLEVY_PREC_FP64 = 0,        /* FP64 factors, plain forward/backward solve */
+  HLEVY_PREC_MIXED = 1,       /* FP32 inverse factors as a preconditioner + FP64 iterative refinement */
+  HLEVY_PREC_MIXED_BF16 = 2   /* as MIXED with the low-rank leaves of the inverse factors in BF16
+                                 (dense leaves FP32, every product accumulating in FP64) */
 } hlevy_precision;
 
 /* The model problem (Sec. 3.1 eq. equ:ut; Sec. 4 eqs. equ:ny2 and the
@@ -232,7 +234,9 @@ hlevy_status hlevy_op_densify(const hlevy_op* op, double* dense, void* stream);
 /* Factor M = I - dt/2 G by H-LU (App. B.3) and form the H-inverses of its
  * triangular factors, truncating every low-rank addition at lu_tol.
  * prec = HLEVY_PREC_FP64 keeps FP64 factors; HLEVY_PREC_MIXED stores the
- * inverse factors in FP32 for the refinement preconditioner.  The factor
+ * inverse factors in FP32 for the refinement preconditioner,
+ * HLEVY_PREC_MIXED_BF16 their low-rank leaves in BF16 (the factorisation
+ * itself runs in FP64 arithmetic on every path).  The factor
  * keeps a reference to `op` (op must outlive it).  Independent parts of the
  * factorisation run on two further streams that the library keeps per host
  * thread and device (default priority, created on first use, never

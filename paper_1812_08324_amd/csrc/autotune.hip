@@ -231,8 +231,8 @@ hlevy_status hlevy_autotune(const hlevy_problem* prob, const hlevy_hparams* base
     hl::set_last_error("null argument");
     return HLEVY_ERR_INVALID_ARG;
   }
-  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED) {
-    hl::set_last_error("precision must be HLEVY_PREC_FP64 or HLEVY_PREC_MIXED");
+  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED && prec != HLEVY_PREC_MIXED_BF16) {
+    hl::set_last_error("bad precision");
     return HLEVY_ERR_INVALID_ARG;
   }
   if (!(dt > 0.0) || !std::isfinite(dt) || !(lu_tol > 0.0 && lu_tol < 1.0) || nsteps < 1 || batch < 1) {

@@ -21,9 +21,12 @@ constexpr int MV_DCOLS = 16;  // columns per dense gather entry (a dense leaf is
 // columns of one projection tile for a plan of rank bucket kb
 constexpr int project_width(int kb) { return kb <= 8 ? kb : (kb == 16 ? 8 : 16); }
 
+// storage formats of a low-rank factor read by the products
+enum { MV_FMT_F64 = 0, MV_FMT_F32 = 1, MV_FMT_BF16 = 2 };
+
 struct MvTile {
   int32_t n, k, ld, xoff;
-  int32_t slot, f32;   // f32: V stored in FP32 (else FP64)
+  int32_t slot, f32;   // storage format of V (MV_FMT_*)
   int32_t col0, pad;
   const void* V;       // row r0, column col0
 };
@@ -33,7 +36,7 @@ struct MvTile {
 // Low rank: rows of U for rho (ptr at that row, ld, rank k); its projection
 // t = V^T x is the sum of np partials starting at slot `slot`.
 struct MvEntry {
-  int32_t kind;   // 0 dense, 1 low rank (FP64 U), 2 low rank (FP32 U)
+  int32_t kind;   // 0 dense, 1 low rank (FP64 U), 2 low rank (FP32 U), 3 low rank (BF16 U)
   int32_t n;      // dense: columns; low rank: number of partials
   int32_t xoff, k, slot, pad, ld, pad2;
   const void* ptr;
@@ -115,8 +118,10 @@ hipError_t project_launch(const MvDev& M, const double* x, hipStream_t s, hipEve
                           hipEvent_t e1 = nullptr);
 hipError_t gather_launch(const MvDev& M, const double* x, const MvEpi& epi, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-// rows of V one projection wavefront covers per pass (64 lanes x rows per lane)
-int project_rows_per_pass(int kb, bool f32);
+// rows of V one projection wavefront covers per pass (64 lanes x rows per
+// lane); narrow: FP32 or BF16 storage
+int project_rows_per_pass(int kb, bool narrow);
 hipError_t launch_convert_f32(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_convert_bf16(const double* in, uint16_t* out, size_t n, hipStream_t s);
 
 }  // namespace hl

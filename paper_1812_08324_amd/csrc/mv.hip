@@ -75,10 +75,17 @@ __device__ __forceinline__ gptr<T> wuni_ptr(const void* p) {
   return (gptr<T>)(((unsigned long long)hi << 32) | lo);
 }
 
+// A BF16 value is stored as the high 16 bits of an FP32 and widened exactly
+// on use; the products accumulate in FP64 like the other precisions.
+using bf16 = uint16_t;
+__device__ __forceinline__ double to_d(double v) { return v; }
+__device__ __forceinline__ double to_d(float v) { return (double)v; }
+__device__ __forceinline__ double to_d(bf16 v) { return (double)__uint_as_float((uint32_t)v << 16); }
+
 template <typename TL, int KB>
 constexpr int rows_per_lane() {
-  // 64 VGPRs of loads in flight per lane
-  return (sizeof(TL) == 4 ? 64 : 32) / KB;
+  // 64 VGPRs of loads in flight per lane (a BF16 value takes one register too)
+  return (sizeof(TL) <= 4 ? 64 : 32) / KB;
 }
 
 // one projection tile (V in precision TL): the k partial sums of the
@@ -111,7 +118,7 @@ __device__ __forceinline__ void project_tile(const MvTile& T, const double* __re
 #pragma unroll
     for (int u = 0; u < RPL; ++u)
 #pragma unroll
-      for (int q = 0; q < KB; ++q) acc[q] += (double)v[u][q] * xv[u];
+      for (int q = 0; q < KB; ++q) acc[q] += to_d(v[u][q]) * xv[u];
   }
   ColReduce<KB, 32>::run(acc, lane);
   constexpr int G = 64 / KB;
@@ -124,8 +131,10 @@ __device__ __forceinline__ void project_any(const MvTile& T, const double* __res
                                             double* __restrict__ part, int lane) {
   // tiles of at most 64 rows (leaves of the finest level) take one row per
   // lane: the full pass would load RPL - 1 rows that are never used
-  const bool f32 = wuni(T.f32), short_tile = wuni(T.n) <= 64;
-  if (f32)
+  const int fmt = wuni(T.f32), short_tile = wuni(T.n) <= 64;
+  if (fmt == MV_FMT_BF16)
+    short_tile ? project_tile<bf16, KB, SB, 1>(T, x, part, lane) : project_tile<bf16, KB, SB>(T, x, part, lane);
+  else if (fmt == MV_FMT_F32)
     short_tile ? project_tile<float, KB, SB, 1>(T, x, part, lane) : project_tile<float, KB, SB>(T, x, part, lane);
   else
     short_tile ? project_tile<double, KB, SB, 1>(T, x, part, lane) : project_tile<double, KB, SB>(T, x, part, lane);
@@ -210,7 +219,7 @@ __device__ __forceinline__ double gather_lowrank_self(const MvEntry& E, int ii, 
   const gptr<TL> U = wuni_ptr<TL>(E.ptr);
   double uv[KB];
 #pragma unroll
-  for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
+  for (int q = 0; q < KB; ++q) uv[q] = to_d(U[(unsigned)(ii + ld * min(q, ek - 1))]);
   const int q = lane % KB, c0 = (lane / KB) * PPG;
   const double* pp = part + (size_t)wuni(E.slot) * KB + q;
   double t = 0.0;   // zero past the rank: the products below multiply by it
@@ -261,15 +270,17 @@ __device__ __forceinline__ void gather_rows(const MvRow& R, const MvEntry* __res
       for (; j + 16 <= en; j += 16) {
         double dv[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) dv[q] = (double)D[(unsigned)(ii + ld * (j + q))];
+        for (int q = 0; q < 16; ++q) dv[q] = to_d(D[(unsigned)(ii + ld * (j + q))]);
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc += dv[q] * bcast_lane(xl, j + q);
       }
-      for (; j < en; ++j) acc += (double)D[(unsigned)(ii + ld * j)] * bcast_lane(xl, j);
+      for (; j < en; ++j) acc += to_d(D[(unsigned)(ii + ld * j)]) * bcast_lane(xl, j);
     } else if (kind == 1) {
       acc += gather_lowrank_self<double, KB>(E, ii, i, part);
-    } else {
+    } else if (kind == 2) {
       acc += gather_lowrank_self<float, KB>(E, ii, i, part);
+    } else {
+      acc += gather_lowrank_self<bf16, KB>(E, ii, i, part);
     }
   }
   L.red[g][i] = acc;
@@ -292,8 +303,8 @@ __global__ void __launch_bounds__(64 * GW) k_mv_gather(const MvRow* __restrict__
   gather_rows<TD, KB, GW>(R, ents, x, part, epi, L);
 }
 
-int project_rows_per_pass(int kb, bool f32) {
-  const int vals = f32 ? 64 : 32;
+int project_rows_per_pass(int kb, bool narrow) {
+  const int vals = narrow ? 64 : 32;
   return 64 * (vals / project_width(kb));
 }
 
@@ -421,7 +432,7 @@ __device__ __forceinline__ void project_tile_r(const MvTile& T, const MvInst& P,
     for (int u = 0; u < RPL; ++u)
 #pragma unroll
       for (int q = 0; q < KB; ++q) {
-        const double vv = (double)v[u][q];
+        const double vv = to_d(v[u][q]);
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r][q] += vv * xv[r][u];
       }
@@ -446,7 +457,10 @@ __global__ void __launch_bounds__(256) k_mv_project_b(const MvInst* __restrict__
   const MvInst& P = inst[wuni(m.inst)];
   const unsigned mask = member_mask(P, step);
   if (mask == 0) return;
-  if (wuni(T.f32))
+  const int fmt = wuni(T.f32);
+  if (fmt == MV_FMT_BF16)
+    project_tile_r<bf16, KB, R, SB>(T, P, mask, threadIdx.x & 63);
+  else if (fmt == MV_FMT_F32)
     project_tile_r<float, KB, R, SB>(T, P, mask, threadIdx.x & 63);
   else
     project_tile_r<double, KB, R, SB>(T, P, mask, threadIdx.x & 63);
@@ -520,14 +534,14 @@ __global__ void __launch_bounds__(64 * GWB) k_mv_gather_b(const MvInst* __restri
         for (; j + 16 <= en; j += 16) {
           double dv[16];
 #pragma unroll
-          for (int q = 0; q < 16; ++q) dv[q] = (double)D[(unsigned)(ii + ld * (j + q))];
+          for (int q = 0; q < 16; ++q) dv[q] = to_d(D[(unsigned)(ii + ld * (j + q))]);
 #pragma unroll
           for (int q = 0; q < 16; ++q)
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] += dv[q] * bcast_lane(xl[r], j + q);
         }
         for (; j < en; ++j) {
-          const double dv = (double)D[(unsigned)(ii + ld * j)];
+          const double dv = to_d(D[(unsigned)(ii + ld * j)]);
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] += dv * bcast_lane(xl[r], j);
         }
@@ -537,10 +551,14 @@ __global__ void __launch_bounds__(64 * GWB) k_mv_gather_b(const MvInst* __restri
           const gptr<double> U = wuni_ptr<double>(L.se[e].ptr);
 #pragma unroll
           for (int q = 0; q < KB; ++q) uv[q] = U[(unsigned)(ii + ld * min(q, ek - 1))];
-        } else {
+        } else if (kind == 2) {
           const gptr<float> U = wuni_ptr<float>(L.se[e].ptr);
 #pragma unroll
-          for (int q = 0; q < KB; ++q) uv[q] = (double)U[(unsigned)(ii + ld * min(q, ek - 1))];
+          for (int q = 0; q < KB; ++q) uv[q] = to_d(U[(unsigned)(ii + ld * min(q, ek - 1))]);
+        } else {
+          const gptr<bf16> U = wuni_ptr<bf16>(L.se[e].ptr);
+#pragma unroll
+          for (int q = 0; q < KB; ++q) uv[q] = to_d(U[(unsigned)(ii + ld * min(q, ek - 1))]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -627,6 +645,23 @@ __global__ void k_convert_f32(const double* in, float* out, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) out[i] = (float)in[i];
+}
+
+// FP64 -> BF16, rounded to nearest even (finite inputs)
+__global__ void k_convert_bf16(const double* in, uint16_t* out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const uint32_t u = __float_as_uint((float)in[i]);
+    out[i] = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+}
+
+hipError_t launch_convert_bf16(const double* in, uint16_t* out, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_convert_bf16, dim3((unsigned)blocks), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_convert_f32(const double* in, float* out, size_t n, hipStream_t s) {

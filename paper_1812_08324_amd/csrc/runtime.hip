@@ -1325,7 +1325,7 @@ static void hluinv_joint(Builder& B, const std::vector<LuNode>& items, int H) {
 // Per-step matrix-vector plan of one H-matrix: projection tiles, the
 // per-leaf-cluster entry lists and (optionally) FP32 copies of the factors.
 struct MvPlan {
-  DevBuf dtiles, dents, drows, dpart, f32pool;
+  DevBuf dtiles, dents, drows, dpart, f32pool, bf16pool;
   MvDev dev{};
   int64_t matrix_bytes = 0;   // stored bytes read per product
   int64_t lr_bytes = 0, dense_bytes = 0;
@@ -1333,22 +1333,37 @@ struct MvPlan {
   int64_t lr_entries = 0, dense_entries = 0;
   int64_t nslots = 0;
 
-  // lr_f32: low-rank leaves in FP32, except those with at most lr64_rows
-  // rows and columns, which stay FP64
+  // lr_fmt: storage of the low-rank leaves (MV_FMT_F64, _F32 or _BF16),
+  // except those with at most lr64_rows rows and columns, which stay FP64;
   // force_kb: the rank bucket (0: chosen from the ranks below); gather_waves:
   // wavefronts per gather workgroup (0: 8 single-problem, 4 batched)
-  void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, bool lr_f32,
+  void create(const Structure& S, const HMat& M, const std::vector<int32_t>& rk, bool dense_f32, int lr_fmt,
               hipStream_t s, int force_kb = 0, int gather_waves = 0, int lr64_rows = 0) {
     const double* base = M.mem;
     const float* fbase = nullptr;
-    if (dense_f32 || lr_f32) {
+    const uint16_t* hbase = nullptr;
+    if (dense_f32 || lr_fmt == MV_FMT_F32) {
       f32pool.alloc(std::max<size_t>(M.pool_doubles, 1) * sizeof(float));
       HL_CHECK(launch_convert_f32(base, f32pool.as<float>(), M.pool_doubles, s));
       fbase = f32pool.as<float>();
     }
+    if (lr_fmt == MV_FMT_BF16) {
+      bf16pool.alloc(std::max<size_t>(M.pool_doubles, 1) * sizeof(uint16_t));
+      HL_CHECK(launch_convert_bf16(base, bf16pool.as<uint16_t>(), M.pool_doubles, s));
+      hbase = bf16pool.as<uint16_t>();
+    }
     auto fptr = [&](const double* p) -> const void* { return fbase + (p - base); };
     const size_t d_elt = dense_f32 ? sizeof(float) : sizeof(double);
-    auto leaf_f32 = [&](const LeafDesc& d) { return lr_f32 && std::max(d.m, d.n) > lr64_rows; };
+    // format of a low-rank leaf, its element size and the address of a value
+    auto leaf_fmt = [&](const LeafDesc& d) {
+      return std::max(d.m, d.n) > lr64_rows ? lr_fmt : (int)MV_FMT_F64;
+    };
+    auto fmt_elt = [](int f) { return f == MV_FMT_F64 ? sizeof(double) : (f == MV_FMT_F32 ? sizeof(float) : 2); };
+    auto lr_ptr = [&](int f, const double* p) -> const void* {
+      if (f == MV_FMT_F32) return fptr(p);
+      if (f == MV_FMT_BF16) return hbase + (p - base);
+      return p;
+    };
     // rank bucket kb: 8 when leaves of higher rank (split below into
     // kb-column chunks, each with its own tiles, partial slots and gather
     // entries) add at most 50 % more low-rank entries, else 16 when they add
@@ -1377,9 +1392,9 @@ struct MvPlan {
       }
       if (d.kind != K_LR || rk[l] == 0) continue;
       const int k = rk[l];
-      const bool f32 = leaf_f32(d);
-      const size_t lr_elt = f32 ? sizeof(float) : sizeof(double);
-      const int rpp = project_rows_per_pass(kb, f32);
+      const int fmt = leaf_fmt(d);
+      const size_t lr_elt = fmt_elt(fmt);
+      const int rpp = project_rows_per_pass(kb, fmt != MV_FMT_F64);
       lr_bytes += (int64_t)(d.m + d.n) * k * lr_elt;
       u_bytes += (int64_t)d.m * k * lr_elt;
       v_bytes += (int64_t)d.n * k * lr_elt;
@@ -1404,10 +1419,10 @@ struct MvPlan {
             T.ld = d.n;
             T.xoff = d.clo + r0;
             T.slot = (int32_t)(nslots + ch * P + t);
-            T.f32 = f32 ? 1 : 0;
+            T.f32 = fmt;
             T.col0 = c0;
             const double* p = d.B + r0 + (size_t)d.n * (ch * kb + c0);
-            T.V = f32 ? fptr(p) : (const void*)p;
+            T.V = lr_ptr(fmt, p);
             tiles.push_back(T);
           }
         }
@@ -1441,17 +1456,17 @@ struct MvPlan {
           }
         } else if (d.kind == K_LR && rk[l] > 0) {
           // one entry per kb-column chunk of the factor
-          const bool f32 = leaf_f32(d);
+          const int fmt = leaf_fmt(d);
           for (int ch = 0; ch * kb < rk[l]; ++ch) {
             MvEntry L{};
-            L.kind = f32 ? 2 : 1;
+            L.kind = fmt == MV_FMT_F64 ? 1 : (fmt == MV_FMT_F32 ? 2 : 3);
             L.n = np[l];
             L.k = std::min(kb, rk[l] - ch * kb);
             L.slot = slot0[l] + ch * np[l];
             L.ld = d.m;
             const double* p = d.A + (c.lo - d.rlo) + (size_t)d.m * ch * kb;
-            L.ptr = f32 ? fptr(p) : (const void*)p;
-            row.emplace_back((int64_t)L.k * (f32 ? sizeof(float) : sizeof(double)), L);
+            L.ptr = lr_ptr(fmt, p);
+            row.emplace_back((int64_t)L.k * (int64_t)fmt_elt(fmt), L);
           }
         }
       }
@@ -1479,7 +1494,8 @@ struct MvPlan {
 // Bytes MvPlan::create allocates for a matrix of layout M with every
 // low-rank leaf at rank kcap (the most it can hold), maximised over the
 // rank buckets the plan may choose: an upper bound of the actual plan.
-static size_t mvplan_bytes_bound(const Structure& S, const HMat& M, bool f32) {
+static size_t mvplan_bytes_bound(const Structure& S, const HMat& M, int lr_fmt) {
+  const bool f32 = lr_fmt != MV_FMT_F64;   // narrow storage: the passes of a projection tile
   auto round8 = [](size_t b) { return std::max<size_t>(b, 8); };
   size_t best = 0;
   for (int kb : {8, 16, 32}) {
@@ -1512,7 +1528,10 @@ static size_t mvplan_bytes_bound(const Structure& S, const HMat& M, bool f32) {
                round8(S.leafcl.size() * sizeof(MvRow)) + (size_t)std::max<int64_t>(nslots, 1) * kb * sizeof(double);
     best = std::max(best, b);
   }
+  // the FP32 copy (dense leaves of the mixed paths, low-rank leaves in FP32)
+  // and the BF16 copy of the pool
   if (f32) best += std::max<size_t>(M.pool_doubles, 1) * sizeof(float);
+  if (lr_fmt == MV_FMT_BF16) best += std::max<size_t>(M.pool_doubles, 1) * sizeof(uint16_t);
   return best;
 }
 
@@ -1521,7 +1540,11 @@ static size_t mvplan_bytes_bound(const Structure& S, const HMat& M, bool f32) {
 // plans with FP32 copies on the mixed path, the G plan and work vectors):
 // the allocations of assemble_ops and factor_group, with every low-rank
 // block at its rank capacity.
-static size_t footprint_bytes(const Structure& S, int kcap, bool mixed) {
+static int prec_lr_fmt(int prec) {
+  return prec == HLEVY_PREC_FP64 ? MV_FMT_F64 : (prec == HLEVY_PREC_MIXED ? MV_FMT_F32 : MV_FMT_BF16);
+}
+
+static size_t footprint_bytes(const Structure& S, int kcap, int prec) {
   auto round8 = [](size_t b) { return std::max<size_t>(b, 8); };
   const size_t P = S.leafcl.size(), nl = S.lf.size(), N = S.N;
   auto hmat = [&](const HMat& t) {
@@ -1533,13 +1556,14 @@ static size_t footprint_bytes(const Structure& S, int kcap, bool mixed) {
        round8(N * 4) + 64 * 64 * sizeof(double) + 32 + 8;
   HMat g;
   g.layout(S, kcap, FULL, false);
-  b += hmat(g) + 2 * N * sizeof(double) + mvplan_bytes_bound(S, g, false);
+  b += hmat(g) + 2 * N * sizeof(double) + mvplan_bytes_bound(S, g, MV_FMT_F64);
   // the factor
   HMat li, ui;
   li.layout(S, kcap, LOWER, false);
   ui.layout(S, kcap, UPPER, false);
   b += hmat(li) + hmat(ui) + 7 * N * sizeof(double);
-  b += mvplan_bytes_bound(S, g, false) + mvplan_bytes_bound(S, li, mixed) + mvplan_bytes_bound(S, ui, mixed);
+  b += mvplan_bytes_bound(S, g, MV_FMT_F64) + mvplan_bytes_bound(S, li, prec_lr_fmt(prec)) +
+       mvplan_bytes_bound(S, ui, prec_lr_fmt(prec));
   return b;
 }
 
@@ -2067,7 +2091,8 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
   if (ovf > 0 && prec == HLEVY_PREC_FP64 && strict)
     return fail(HLEVY_ERR_RANK_CAP, std::to_string(ovf) + " rounded additions of the FP64 H-LU needed more than "
                                         "the rank capacity (raise max_rank or lu_tol, or factor in mixed precision)");
-  const bool mixed = prec == HLEVY_PREC_MIXED;
+  const bool mixed = prec != HLEVY_PREC_FP64;
+  const int lr_fmt = prec_lr_fmt(prec);
   for (hlevy_fac* f : fs) {
     f->rank_overflows = ovf;
     const Structure& S = f->op->S;
@@ -2078,11 +2103,12 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
     // the operator applied to smooth states is off by ~1e-7 relative (the
     // far-field sums are large and cancel against the near field), which
     // adds up to ~1e-8..1e-7 over 1000 steps; preconditioner (inverse
-    // factors): FP32 on the mixed path
+    // factors): FP32 on the mixed paths, with BF16 low-rank leaves on the
+    // BF16 one
     const hlevy_hparams& hp = f->op->hp;
-    f->mvG.create(S, f->op->G, read_ranks(f->op->G, s), false, false, s, hp.rank_bucket, hp.gather_waves);
-    f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, mixed, s, hp.rank_bucket, hp.gather_waves);
-    f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, mixed, s, hp.rank_bucket, hp.gather_waves);
+    f->mvG.create(S, f->op->G, read_ranks(f->op->G, s), false, MV_FMT_F64, s, hp.rank_bucket, hp.gather_waves);
+    f->mvLi.create(S, f->Li, read_ranks(f->Li, s), mixed, lr_fmt, s, hp.rank_bucket, hp.gather_waves);
+    f->mvUi.create(S, f->Ui, read_ranks(f->Ui, s), mixed, lr_fmt, s, hp.rank_bucket, hp.gather_waves);
     // the LU's storage is the arena's, reused by the next group
     f->LU.L.clear();
     f->LU.mem = nullptr;
@@ -2348,7 +2374,7 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     AllocScope own(&op->actx);
     op->xbuf.alloc((size_t)op->S.N * sizeof(double));
     op->ybuf.alloc((size_t)op->S.N * sizeof(double));
-    op->mv.create(op->S, op->G, rk[i], false, false, s, op->hp.rank_bucket, op->hp.gather_waves);
+    op->mv.create(op->S, op->G, rk[i], false, MV_FMT_F64, s, op->hp.rank_bucket, op->hp.gather_waves);
   }
   aca.clear();
   HL_CHECK(hipStreamSynchronize(s));
@@ -2387,12 +2413,13 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
 
 hlevy_status hlevy_footprint(const hlevy_problem* prob, const hlevy_hparams* hp, int32_t prec, size_t* bytes_out) {
   if (!prob || !hp || !bytes_out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
+  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED && prec != HLEVY_PREC_MIXED_BF16)
+    return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
   try {
     Structure S;
     std::string e = build_structure(*prob, *hp, S);
     if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
-    *bytes_out = footprint_bytes(S, hp->max_rank, prec == HLEVY_PREC_MIXED);
+    *bytes_out = footprint_bytes(S, hp->max_rank, prec);
     return HLEVY_OK;
   } catch (const std::bad_alloc&) {
     return fail(HLEVY_ERR_OOM, "host allocation failed");
@@ -2507,7 +2534,8 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(HLEVY_ERR_INVALID_ARG, "dt must be > 0");
   }
   if (!(lu_tol > 0.0 && lu_tol < 1.0)) return fail(HLEVY_ERR_INVALID_ARG, "lu_tol must be in (0, 1)");
-  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
+  if (prec != HLEVY_PREC_FP64 && prec != HLEVY_PREC_MIXED && prec != HLEVY_PREC_MIXED_BF16)
+    return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
   const size_t budget = workspace_bytes ? workspace_bytes : kDefaultFactorWorkspace;
   std::vector<std::unique_ptr<hlevy_fac>> fs(count);
   hlevy_status st = guarded([&]() -> hlevy_status {
@@ -2557,7 +2585,7 @@ hlevy_status hlevy_factor_batched(const hlevy_op* const* ops, const double* dt, 
 // FP64 operator brings the residual back to about 1e-12.
 static int default_sweeps(const hlevy_fac* f, const hlevy_refine* refine) {
   if (refine) return refine->sweeps;
-  return f->prec == HLEVY_PREC_MIXED ? 2 : 1;
+  return f->prec == HLEVY_PREC_FP64 ? 1 : 2;
 }
 
 static const char* refine_error(const hlevy_refine* r) {
@@ -3189,7 +3217,8 @@ extern "C" {
 
 hlevy_status hlevy_server_create(const hlevy_server_config* cfg, void* stream, hlevy_server** out) {
   if (!cfg || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (cfg->prec != HLEVY_PREC_FP64 && cfg->prec != HLEVY_PREC_MIXED) return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
+  if (cfg->prec != HLEVY_PREC_FP64 && cfg->prec != HLEVY_PREC_MIXED && cfg->prec != HLEVY_PREC_MIXED_BF16)
+    return fail(HLEVY_ERR_INVALID_ARG, "bad precision");
   if (!(cfg->lu_tol > 0.0 && cfg->lu_tol < 1.0)) return fail(HLEVY_ERR_INVALID_ARG, "lu_tol must be in (0, 1)");
   if (cfg->sweeps < 0 || cfg->sweeps > 64) return fail(HLEVY_ERR_INVALID_ARG, "sweeps in [0, 64]");
   if (cfg->chunk < 1 || cfg->max_active < 1) return fail(HLEVY_ERR_INVALID_ARG, "chunk and max_active must be >= 1");
@@ -3228,7 +3257,7 @@ hlevy_status hlevy_server_submit(hlevy_server* v, const hlevy_problem* prob, con
       en->prob = *prob;
       en->hp = *hp;
       en->dt = dt;
-      en->bytes = footprint_bytes(S, hp->max_rank, v->cfg.prec == HLEVY_PREC_MIXED);
+      en->bytes = footprint_bytes(S, hp->max_rank, v->cfg.prec);
       // not resident until admitted; kept so that later requests find it
       v->cache.emplace(r->key, std::move(en));
     }

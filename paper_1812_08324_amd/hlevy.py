@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhlevy.so")
 HLEVY_OK = 0
 PREC_FP64 = 0
 PREC_MIXED = 1
+PREC_MIXED_BF16 = 2
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "NOT_CONVERGED",
           -5: "RANK_CAP", -6: "BAD_HANDLE", -7: "ZERO_PIVOT"}
 

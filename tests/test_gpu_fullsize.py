@@ -157,7 +157,8 @@ def test_trajectory_vs_fullsize_oracle(H, full, path):
 
 def test_tempered_trajectory_vs_oracle_n4096(H):
     """The tempered workload's operator at N = 4096, 200 CN steps: FP64 path
-    within 1e-10 and mixed path within 1e-8 of the dense oracle."""
+    within 1e-10, mixed path (FP32 inverse factors, one sweep) and BF16 path
+    (BF16 low-rank leaves, two sweeps) within 1e-8 of the dense oracle."""
     w = W.config2(n=4096, steps=200)
     p, hp = lib(H, w)
     op = H.assemble(p, hp)
@@ -171,8 +172,17 @@ def test_tempered_trajectory_vs_oracle_n4096(H):
     u = dev(w.u0)
     H.step(fmx, u, w.steps, refine={"sweeps": 1})
     emx = np.linalg.norm(host(u) - ref) / nref
+    # BF16 low-rank leaves of the inverse factors: a coarser preconditioner,
+    # two sweeps per step
+    fbf = H.factor(op, w.dt, H.PREC_MIXED_BF16, 1e-6)
+    u = dev(w.u0)
+    H.step(fbf, u, w.steps, refine={"sweeps": 2})
+    ebf = np.linalg.norm(host(u) - ref) / nref
     assert e64 <= 1e-10, e64
     assert emx <= 1e-8, emx
+    assert ebf <= 1e-8, ebf
+    fi, fb = H.fac_info(fmx), H.fac_info(fbf)
+    assert fb["product_bytes"][1] < fi["product_bytes"][1] and fb["product_bytes"][2] < fi["product_bytes"][2]
 
 
 @pytest.fixture(scope="module", params=[0.75, 0.25], ids=["s0.75", "s0.25"])
