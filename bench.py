@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--lu-tol-fp64", type=float, default=1e-12)
     ap.add_argument("--sweeps", type=int, default=1, help="refinement sweeps per CN step (mixed)")
     ap.add_argument("--sweeps-fp64", type=int, default=1, help="refinement sweeps per CN step (FP64 job)")
+    ap.add_argument("--serve-sweeps", type=int, default=2,
+                    help="refinement sweeps per CN step of a served request (mixed; one sweep leaves up to "
+                         "5e-8 on 1D problems near N = 53000 over their horizon)")
     ap.add_argument("--sweeps-bf16", type=int, default=4, help="refinement sweeps per CN step (BF16 job)")
     ap.add_argument("--max-rank", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -52,8 +55,10 @@ def parse():
                     help="autotuner cache of the batched workload ('' = tune every run, keep nothing)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival window of the serving measurement (0 = skip)")
-    ap.add_argument("--serve-frac-1d", type=float, default=1.0,
+    ap.add_argument("--serve-frac-1d", type=float, default=0.7,
                     help="share of 1D requests in the served trace (the rest 2D)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving measurement (its own JSON line; e.g. --serve-seconds 60)")
     ap.add_argument("--job-only", action="store_true", help="run warmup + timed jobs only (profiling)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="with --factor-only: CN steps of the mixed path after the factorisation")
@@ -336,12 +341,24 @@ def bench_serving(H, torch, seconds, frac_1d, sweeps, lu_tol):
     import workloads as W
     from paper_1812_08324_amd.serve import replay
     tr = W.serving_trace(duration=seconds, frac_1d=frac_1d)
+    import numpy as np
+    # resident budget: 200 GiB of the 288 GB of HBM for cached operators,
+    # their factors and request state (the rest: factorisation workspace)
     res = replay(H, torch, tr, W.request_u0, realtime=True, prec=H.PREC_MIXED, lu_tol=lu_tol, sweeps=sweeps,
-                 chunk=10, max_active=1024, log=progress)
+                 chunk=10, max_active=1024, log=progress, hbm_budget=200 << 30)
     st = res["server"]
     offered = sum(r["steps"] for r in tr) / seconds
+    lat = res["latencies"]
+    per_dim = {}
+    for d in (1, 2):
+        sel = np.array([r["w"].dim == d for r in tr])
+        if sel.any():
+            per_dim[f"{d}d"] = {"requests": int(sel.sum()), "latency_p50_s": float(np.percentile(lat[sel], 50)),
+                                "latency_p99_s": float(np.percentile(lat[sel], 99))}
     return {
         "workload": f"serve_poisson200_{seconds:g}s_1d{frac_1d:g}",
+        "per_dim": per_dim,
+        "max_rel_residual": st["max_rel_residual"], "not_converged": st["not_converged"],
         "requests": res["requests"], "arrival_window_s": seconds, "wall_s": res["wall_s"],
         "latency_p50_s": res["latency_p50_s"], "latency_p99_s": res["latency_p99_s"],
         "latency_mean_s": res["latency_mean_s"],
@@ -374,6 +391,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.serve_only:
+        line = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.serve_sweeps, args.lu_tol_mixed)
+        line["command"] = "python bench.py " + " ".join(sys.argv[1:])
+        print(json.dumps(line))
+        return
     w = make_workload(args.workload)
     two_d = WORKLOADS[args.workload]["kind"] == "config3"
     if two_d and not args.factor_only:
@@ -546,7 +568,7 @@ def main():
         line["frac2d"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed, s=0.75)
         line["frac2d_s0.25"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed, s=0.25, kernel_times=False)
     if args.serve_seconds > 0:
-        line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.sweeps,
+        line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.serve_sweeps,
                                         args.lu_tol_mixed)
         progress("serving done")
     if not args.no_cpu_baseline:

@@ -364,7 +364,11 @@ hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, const 
  *     else is active);
  *  2. operators not in the cache are assembled and factored in one joint
  *     plan (hlevy_factor_batched); requests with equal problem, hparams and
- *     dt share one cached factor;
+ *     dt share one cached factor.  When the device runs out of memory here,
+ *     every idle cached operator is evicted and the factorisation runs once
+ *     more; if that fails too while other requests are active, the round's
+ *     new requests return to the head of the queue and no new operator is
+ *     admitted until a cached one falls idle;
  *  3. every active request (at most max_active) advances by
  *     min(chunk, its steps left) steps in one batched loop
  *     (hlevy_step_batched's products; each request keeps its own vectors;
@@ -376,7 +380,9 @@ hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, const 
  * parameters (same arithmetic, summation order of the batched products).
  * The server's calls are not thread safe. */
 typedef struct {
-  size_t hbm_budget;   /* resident bytes allowed; 0 = 64 GiB */
+  size_t hbm_budget;   /* resident bytes allowed; 0 = 64 GiB.  A round that factors new operators
+                          also takes a transient workspace from the memory then free (at most
+                          48 GiB), so the budget should leave room for it */
   int32_t prec;        /* HLEVY_PREC_MIXED or HLEVY_PREC_FP64 */
   double lu_tol;       /* H-LU truncation of the factors */
   int32_t sweeps;      /* refinement sweeps per step */
@@ -389,7 +395,8 @@ typedef struct {
   int64_t submitted, completed, active, queued;
   int64_t cache_hits, cache_misses, evictions, cached_operators;
   int64_t problem_steps;        /* CN steps advanced, summed over requests */
-  size_t bytes_in_use;          /* resident bytes (hlevy_footprint of the cached operators, request state) */
+  size_t bytes_in_use;          /* resident bytes: cached operators with their factors (the hlevy_footprint
+                                   estimate until built, then the bytes allocated) and request state */
   double assemble_seconds, factor_seconds, step_seconds;
   int64_t failed;               /* requests whose operator could not be built */
   int64_t not_converged;        /* completed requests whose last-step residual missed tol */
@@ -416,7 +423,8 @@ hlevy_status hlevy_server_submit(hlevy_server* srv, const hlevy_problem* prob, c
 hlevy_status hlevy_server_poll(hlevy_server* srv, int64_t* done_ids, int32_t cap, int32_t* ndone);
 
 /* Requests that failed: when the assembly or factorisation of the operators
- * new in a round fails, hlevy_server_poll returns that error and those
+ * new in a round fails (other than for device memory while other requests
+ * are active, see above), hlevy_server_poll returns that error and those
  * requests leave the server (their u_out is not written).  Writes up to
  * `cap` of their ids to ids and the count to *n. */
 hlevy_status hlevy_server_take_failed(hlevy_server* srv, int64_t* ids, int32_t cap, int32_t* n);

@@ -3211,6 +3211,9 @@ struct hlevy_server {
   std::vector<std::unique_ptr<SrvReq>> active;
   std::deque<int64_t> finished, failed;
   hlevy_server_stats st{};
+  // a round ran out of device memory building new operators: no new
+  // operator is admitted until a resident one falls idle
+  bool fresh_wait = false;
 };
 
 extern "C" {
@@ -3280,6 +3283,13 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
       SrvEntry* e = v->cache.at(r->key).get();
       const size_t req_bytes = (size_t)r->N * 8 * 4 + 65536;
       const bool pending_fresh = std::find(fresh.begin(), fresh.end(), e) != fresh.end();
+      if (!e->op && !pending_fresh && v->fresh_wait && !v->active.empty()) {
+        bool idle_op = false;
+        for (auto& kv : v->cache)
+          if (kv.second->op && kv.second->refs == 0) idle_op = true;
+        if (!idle_op) break;   // wait for an operator to fall idle
+        v->fresh_wait = false;
+      }
       const size_t need = req_bytes + ((e->op || pending_fresh) ? 0 : e->bytes);
       while (v->used + need > v->cfg.hbm_budget) {
         // evict the least recently used idle resident operator (not the
@@ -3335,19 +3345,65 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
           ops.push_back(e->op.get());
           dts.push_back(e->dt);
         }
+        // the joint factorisation's transient workspace comes on top of the
+        // resident bytes: the arena takes half of what the device has free
+        // beyond the new factors' own storage and a margin (the product
+        // workspace grows beside it), at most the default budget
+        auto workspace = [&]() -> size_t {
+          size_t free_b = 0, total_b = 0;
+          if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+          }
+          size_t need = (size_t)2 << 30;
+          for (SrvEntry* e : fresh) need += e->bytes;
+          const size_t floor_b = (size_t)1 << 30;
+          return free_b > need + 2 * floor_b ? std::min(kDefaultFactorWorkspace, (free_b - need) / 2) : floor_b;
+        };
         std::vector<hlevy_fac*> fo(fresh.size(), nullptr);
-        st = hlevy_factor_batched(ops.data(), dts.data(), (int32_t)ops.size(), v->cfg.prec, v->cfg.lu_tol, 0, s,
-                                  fo.data());
+        st = hlevy_factor_batched(ops.data(), dts.data(), (int32_t)ops.size(), v->cfg.prec, v->cfg.lu_tol,
+                                  workspace(), s, fo.data());
+        if (st == HLEVY_ERR_OOM) {
+          // the device ran out before the budget did (allocator caches and
+          // fragmentation are not in the count): every idle resident
+          // operator leaves and the factorisation runs once more
+          HL_CHECK(hipStreamSynchronize(s));
+          for (auto& kv : v->cache) {
+            SrvEntry* c = kv.second.get();
+            if (c->op && c->refs == 0 && std::find(fresh.begin(), fresh.end(), c) == fresh.end()) {
+              c->fac.reset();
+              c->op.reset();
+              v->used -= c->bytes;
+              v->st.evictions++;
+            }
+          }
+          st = hlevy_factor_batched(ops.data(), dts.data(), (int32_t)ops.size(), v->cfg.prec, v->cfg.lu_tol,
+                                    workspace(), s, fo.data());
+        }
         if (st == HLEVY_OK)
-          for (size_t q = 0; q < fresh.size(); ++q) fresh[q]->fac.reset(fo[q]);
+          for (size_t q = 0; q < fresh.size(); ++q) {
+            fresh[q]->fac.reset(fo[q]);
+            // admission counted the estimate at rank capacity; from now on
+            // the entry holds what was actually allocated
+            const size_t actual = fresh[q]->op->bytes + fresh[q]->fac->bytes;
+            v->used = v->used - fresh[q]->bytes + actual;
+            fresh[q]->bytes = actual;
+          }
       }
       if (st != HLEVY_OK) {
-        // the new operators could not be built: their requests leave the
-        // server as failed (hlevy_server_take_failed), their memory is
-        // returned and the entries stay non-resident; the other active
-        // requests are untouched
+        // the new operators could not be built.  Out of device memory while
+        // other requests hold theirs: the new requests go back to the head
+        // of the queue, in order, and wait until an operator falls idle.
+        // Otherwise they leave the server as failed
+        // (hlevy_server_take_failed).  Either way their memory is returned,
+        // the entries stay non-resident and the other active requests are
+        // untouched
         const std::string msg = g_last_error;
-        std::vector<std::unique_ptr<SrvReq>> keep;
+        bool others = false;
+        for (auto& r : v->active)
+          if (std::find(fresh.begin(), fresh.end(), r->e) == fresh.end()) others = true;
+        const bool requeue = st == HLEVY_ERR_OOM && others;
+        std::vector<std::unique_ptr<SrvReq>> keep, back;
         std::string ids;
         for (auto& r : v->active) {
           if (std::find(fresh.begin(), fresh.end(), r->e) == fresh.end()) {
@@ -3356,6 +3412,12 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
           }
           r->e->refs--;
           v->used -= r->bytes;
+          if (requeue) {
+            r->e = nullptr;
+            r->bytes = 0;
+            back.push_back(std::move(r));
+            continue;
+          }
           v->failed.push_back(r->id);
           v->st.failed++;
           ids += (ids.empty() ? "" : ",") + std::to_string(r->id);
@@ -3366,13 +3428,24 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
           e->op.reset();
           v->used -= e->bytes;
         }
+        if (requeue) {
+          // admission counted one miss per new operator and a hit for each
+          // further request of it; they are counted again when readmitted
+          v->st.cache_misses -= (int64_t)fresh.size();
+          v->st.cache_hits -= (int64_t)(back.size() - fresh.size());
+          for (auto it = back.rbegin(); it != back.rend(); ++it) v->queue.push_front(std::move(*it));
+          v->fresh_wait = true;
+        }
         v->st.active = (int64_t)v->active.size();
         v->st.queued = (int64_t)v->queue.size();
-        *ndone = 0;
-        return fail(st, msg + " (requests " + ids + " failed)");
+        if (!requeue) {
+          *ndone = 0;
+          return fail(st, msg + " (requests " + ids + " failed)");
+        }
+      } else {
+        v->st.assemble_seconds += t1 - t0;
+        v->st.factor_seconds += now_s() - t1;
       }
-      v->st.assemble_seconds += t1 - t0;
-      v->st.factor_seconds += now_s() - t1;
     }
     // 3. state of newly active requests
     for (auto& r : v->active) {

@@ -44,6 +44,11 @@ def test_serving_trace_deterministic_and_poisson():
     # parameter sets repeat: every request's operator comes from the pool
     names = {w.name for w in pool["1d"] + pool["2d"]}
     assert all(r["w"].name in names for r in tr)
+    # 2D operators take the batched workload's parameter ranges
+    p2 = pool["2d"]
+    assert all(64 <= w.n <= 256 and 0.1 <= w.s <= 0.9 and 0.0 <= w.lam <= 2.0 and 0.0 <= w.a <= 0.1
+               and abs(w.b[0]) <= 1.0 and abs(w.b[1]) <= 1.0 for w in p2)
+    assert len({w.lam for w in p2}) == 64 and len({w.b[1] for w in p2}) == 64
 
 
 def test_serving_request_u0_seeded():

@@ -154,9 +154,10 @@ def config4_instances(count: int = 512, seed: int = 8324, nmin_log2: float = 10.
 def serving_pool(seed: int = 356, size: int = 64, n1d_log2=(12.0, 16.0), side=(64, 256)) -> dict:
     """Operator configurations requests draw from (so that parameter sets
     repeat): `size` 1D tempered problems (N log-uniform, s, drift, sigma^2,
-    lambda as in the batched workload) and `size` 2D fractional problems on
-    the unit square (side uniform in [side[0], side[1]], s ~ U(0.1, 0.9),
-    ACA at 1e-8 with rank <= 32).  Returns {"1d": [...], "2d": [...]}."""
+    lambda as in the batched workload) and `size` 2D tempered problems on the
+    unit square (side uniform in [side[0], side[1]]; s, lambda, sigma^2 as in
+    the batched workload, each drift component ~ U(-1, 1); ACA at 1e-8 with
+    rank <= 32).  Returns {"1d": [...], "2d": [...]}."""
     rng = np.random.Generator(np.random.PCG64(seed))
     p1, p2 = [], []
     for i in range(size):
@@ -170,8 +171,11 @@ def serving_pool(seed: int = 356, size: int = 64, n1d_log2=(12.0, 16.0), side=(6
     for i in range(size):
         n = int(rng.integers(side[0], side[1] + 1))
         s = float(rng.uniform(0.1, 0.9))
-        p2.append(Workload(name="pool2d_%d" % i, dim=2, n=n, lo=0.0, hi=1.0, s=s, dt=1e-3, aca_tol=1e-8,
-                           max_rank=32, lu_tol=1e-6))
+        b = (float(rng.uniform(-1.0, 1.0)), float(rng.uniform(-1.0, 1.0)))
+        sig2 = float(rng.uniform(0.0, 0.2))
+        lam = float(rng.uniform(0.0, 2.0))
+        p2.append(Workload(name="pool2d_%d" % i, dim=2, n=n, lo=0.0, hi=1.0, s=s, lam=lam, a=0.5 * sig2, b=b,
+                           dt=1e-3, aca_tol=1e-8, max_rank=32, lu_tol=1e-6))
     return {"1d": p1, "2d": p2}
 
 
