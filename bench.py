@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuner cache of the batched workload ('' = tune every run, keep nothing)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="arrival window of the serving measurement (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="arrival window of the serving measurement (0 = skip); the 200 requests/s trace "
+                         "saturates the GPU, so a window of w seconds takes roughly 30 w seconds to serve")
     ap.add_argument("--serve-frac-1d", type=float, default=0.7,
                     help="share of 1D requests in the served trace (the rest 2D)")
     ap.add_argument("--serve-only", action="store_true",
