@@ -14,7 +14,10 @@ What it computes (Xu & Darve, arXiv 1812.08324):
   as a plain dense matrix, one row at a time;
 * the Crank-Nicolson recursion (Sec. 3.2, eq. equ:scheme) with the
   trapezoidal forcing term, solved by dense LU with partial pivoting
-  (LAPACK getrf/getrs through scipy).
+  (LAPACK getrf/getrs through scipy);
+* the steady problems (shift I - G) u = f that the H-LU preconditions in an
+  iteration (Sec. 5.1; the fractional Poisson problem of Sec. 5.3 is
+  shift = 0 with the fractional generator), solved by the same dense LU.
 
 Nothing here is blocked, compressed or reordered: the H-matrix method must
 reproduce these results up to its truncation tolerance.
@@ -35,6 +38,10 @@ Readings of the paper taken here (the paper is garbled or silent on them):
   the zero-exterior condition (Sec. 4, closing remark).
 * In 2D the singularity subtraction uses ``int rho nu y_i y_j = delta_ij C2``
   (radial kernel, square window), giving the 5-point Laplacian.
+* The closed-form solution of the 1D fractional Poisson problem (Sec. 5.3):
+  the paper prints the factor 2^{2s} Gamma(1+s) Gamma((1+2s)/2)/Gamma(1/2)
+  in front of (1-x^2)^s.  That factor is (-Delta)^s of (1-x^2)^s (the ball
+  constant), so the solution of (-Delta)^s u = 1 carries its reciprocal.
 """
 from __future__ import annotations
 
@@ -49,7 +56,7 @@ import scipy.special as sp
 __all__ = [
     "Problem", "frac_const", "ball_const", "gauss_const", "grid", "h_of",
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
-    "cn_run", "kernel_nu",
+    "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
 ]
 
 
@@ -315,6 +322,33 @@ def cn_run(G: np.ndarray, dt: float, steps: int, u0: np.ndarray,
         if keep_norms:
             norms.append(float(np.linalg.norm(u)))
     return CNResult(u=u, norms=norms)
+
+
+# ---------------------------------------------------------------------------
+# Steady problems (Sec. 5.1 preconditioned solves; Sec. 5.3 fractional Poisson)
+# ---------------------------------------------------------------------------
+def steady_solve(G: np.ndarray, shift: float, f: np.ndarray) -> np.ndarray:
+    """u with (shift I - G) u = f, by dense LU with partial pivoting
+    (LAPACK getrf/getrs).  With shift = 0 and the fractional generator this
+    is (-Delta)^s u = f with zero exterior (Sec. 5.3)."""
+    A = shift * np.eye(G.shape[0]) - G
+    return sla.lu_solve(sla.lu_factor(A), f)
+
+
+def steady_residual(G: np.ndarray, shift: float, u: np.ndarray, f: np.ndarray) -> float:
+    """||(shift I - G) u - f||_2 / ||f||_2, the relative error the paper
+    tracks over the iterations of a preconditioned solve (Sec. 5.4,
+    eq. equ:relative_error)."""
+    r = shift * u - G @ u - f
+    return float(np.linalg.norm(r) / np.linalg.norm(f))
+
+
+def fractional_poisson_exact(d: int, s: float, x: np.ndarray) -> np.ndarray:
+    """(1 - |x|^2)_+^s / K(d, s): the solution of (-Delta)^s u = 1 on the
+    unit ball with zero exterior, K = ball_const (Sec. 5.3; see the reading
+    of its constant in the module docstring).  x: points, shape (N, d)."""
+    r2 = np.sum(np.asarray(x, dtype=np.float64).reshape(len(x), -1) ** 2, axis=1)
+    return np.maximum(1.0 - r2, 0.0) ** s / ball_const(d, s)
 
 
 # ---------------------------------------------------------------------------

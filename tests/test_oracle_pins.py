@@ -15,7 +15,8 @@ import scipy.special as sp
 
 from oracle.levy_oracle import (Problem, ball_const, cn_run, cn_run_lean, frac_const,
                                 gauss_const, generator_dense, generator_row,
-                                grid, kernel_nu, quadrature_constants)
+                                grid, kernel_nu, quadrature_constants, steady_solve, steady_residual,
+                                fractional_poisson_exact)
 
 
 def _order(e1, e2):
@@ -375,3 +376,43 @@ def test_lean_cn_equals_plain_cn():
         a = cn_run_lean(p, dt, steps, u0, g, phi).u
         b = cn_run(generator_dense(p), dt, steps, u0, g, phi).u
         assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75])
+def test_fractional_poisson_converges_to_closed_form(s):
+    """Sec. 5.3: (-Delta)^s u = 1 on [-1, 1] with zero exterior has the
+    solution (1 - x^2)^s / K(1, s).  The oracle's steady solve with the
+    fractional generator approaches it at a first-order-or-less rate (the
+    paper reports order 1.0 or less): relative L2 error falling by at least
+    2^0.6 per halving of h, below 3e-3 at N = 1023, and the centre value
+    times K within 1e-3 of one.  The paper's printed constant (K instead of
+    1/K) would be off by a factor K^2 (0.79 to 1.8)."""
+    errs = []
+    for n in (255, 511, 1023):
+        p = Problem(dim=1, n=n, lo=-1.0, hi=1.0, s=s)
+        x = grid(p)
+        u = steady_solve(generator_dense(p), 0.0, np.ones(n))
+        ex = fractional_poisson_exact(1, s, x)
+        errs.append(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+    assert errs[2] < 3e-3, errs
+    assert errs[0] / errs[1] > 2 ** 0.6 and errs[1] / errs[2] > 2 ** 0.6, errs
+    assert abs(u[n // 2] * ball_const(1, s) - 1.0) < 1e-3
+
+
+def test_steady_solve_special_cases():
+    """Without jumps and drift the generator is a I Lap_h + c I: with a = 0
+    the steady solve is f / (shift - c) exactly; with diffusion only it is
+    the 3-point Poisson problem, whose solution for f = 1 on [-1, 1] is the
+    parabola (1 - x^2) / (2 a) at the nodes (the central difference is exact
+    on quadratics).  steady_residual of the solution is at rounding level."""
+    n = 101
+    f = np.cos(np.arange(n))
+    p = Problem(dim=1, n=n, lo=-1.0, hi=1.0, s=0.5, C=0.0, c=-0.3)
+    G = generator_dense(p)
+    u = steady_solve(G, 2.0, f)
+    assert np.allclose(u, f / 2.3, rtol=1e-14, atol=0)
+    assert steady_residual(G, 2.0, u, f) < 1e-14
+    p = Problem(dim=1, n=n, lo=-1.0, hi=1.0, s=0.5, C=0.0, a=0.25)
+    x = grid(p)[:, 0]
+    u = steady_solve(generator_dense(p), 0.0, np.ones(n))
+    assert np.allclose(u, (1.0 - x ** 2) / 0.5, rtol=1e-10, atol=1e-12)
