@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison job")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-worklist measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
+    ap.add_argument("--no-steady", action="store_true", help="skip the steady (Krylov) measurement")
+    ap.add_argument("--steady-only", action="store_true", help="only the steady measurement (its own JSON line)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuner cache of the batched workload ('' = tune every run, keep nothing)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -280,6 +282,63 @@ def bench_2d(H, torch, sweeps, lu_tol_mixed, s=0.75, kernel_times=True):
     return out
 
 
+def bench_steady(H, torch, n=65536, s=0.5):
+    """The steady fractional Poisson problem (-Delta)^s u = 1 on [-1, 1]
+    at N = n (Sec. 5.3): conjugate gradients preconditioned by the mixed
+    factor (Sec. 5.1) against conjugate gradients alone, both to a relative
+    residual of 1e-12, and the error of the solution against the closed form
+    (1 - x^2)^s / K(1, s), K = 2^{2s} Gamma(1+s) Gamma(1/2+s) / Gamma(1/2)
+    (a discretisation error, not a solver error)."""
+    import math
+    import numpy as np
+    import workloads as W
+    w = W.steady_poisson(n, s)
+    p = H.make_problem(w.dim, w.n, w.lo, w.hi, w.s, lam=w.lam, C_=w.C, a=w.a, b=w.b, c=w.c, r0=w.r0)
+    hp = H.make_hparams(leaf=w.leaf, eta=w.eta, n_block=w.n_block, aca_tol=w.aca_tol, max_rank=w.max_rank)
+    f = torch.tensor(w.g, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(f)
+    out = {"workload": w.name, "N": w.N}
+    for rep in range(2):      # the first pass warms the allocator and the code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = H.assemble(p, hp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fac = H.factor(op, w.dt, H.PREC_MIXED, w.lu_tol)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        x.zero_()
+        st = H.krylov_solve(fac, f, x, method=H.KRYLOV_CG, max_iter=100, tol=1e-12)
+        t3 = time.perf_counter()
+        if rep == 0:
+            del fac, op
+    xg = np.linspace(w.lo, w.hi, w.n + 2)[1:-1]
+    K = 4.0 ** s * math.gamma(1.0 + s) * math.gamma(0.5 + s) / math.gamma(0.5)
+    exact = (1.0 - xg ** 2) ** s / K
+    got = x.cpu().numpy()
+    out.update({
+        "assemble_s": t1 - t0, "factor_s": t2 - t1,
+        "pcg": {"iterations": st["iterations"], "seconds": t3 - t2, "rel_residual": st["rel_residual"],
+                "ms_per_iteration": 1e3 * (t3 - t2) / max(1, st["iterations"])},
+        "whole_solve_s": t3 - t0,
+        "rel_l2_vs_closed_form": float(np.linalg.norm(got - exact) / np.linalg.norm(exact)),
+    })
+    y = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    s0 = H.krylov_solve(fac, f, y, method=H.KRYLOV_CG, max_iter=20000, tol=1e-12, precondition=False,
+                        raise_not_converged=False)
+    t5 = time.perf_counter()
+    out["cg_without_preconditioner"] = {"iterations": s0["iterations"], "seconds": t5 - t4,
+                                        "converged": s0["converged"], "rel_residual": s0["rel_residual"],
+                                        "ms_per_iteration": 1e3 * (t5 - t4) / max(1, s0["iterations"])}
+    out["speedup_pcg_vs_cg"] = (t5 - t4) / (t3 - t2)
+    out["note"] = ("preconditioner: mixed factor of I - dt/2 G, dt = 1e4, lu_tol 1e-6; both iterations use "
+                   "the FP64 H-matrix product with G; error against the closed form is the discretisation's")
+    del fac, op
+    return out
+
+
 def counted_traffic(key, algorithmic_bytes=None):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
     summary, or None when the product kernels' sources have changed since
@@ -392,6 +451,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.steady_only:
+        line = bench_steady(H, torch)
+        line["command"] = "python bench.py " + " ".join(sys.argv[1:])
+        print(json.dumps(line))
+        return
     if args.serve_only:
         line = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.serve_sweeps, args.lu_tol_mixed)
         line["command"] = "python bench.py " + " ".join(sys.argv[1:])
@@ -568,6 +632,9 @@ def main():
     if not args.no_2d:
         line["frac2d"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed, s=0.75)
         line["frac2d_s0.25"] = bench_2d(H, torch, args.sweeps, args.lu_tol_mixed, s=0.25, kernel_times=False)
+    if not args.no_steady:
+        line["steady"] = bench_steady(H, torch)
+        progress("steady solve done")
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.serve_sweeps,
                                         args.lu_tol_mixed)

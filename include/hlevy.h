@@ -354,6 +354,46 @@ hlevy_status hlevy_step(hlevy_fac* fac, double* u, int64_t nsteps, const double*
 hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, const int64_t* nsteps, int32_t count,
                                 const hlevy_refine* refine, hlevy_stats* stats, void* stream);
 
+/* Steady solves (shift I - G) x = b by a Krylov iteration that the factor
+ * preconditions: Sec. 5.1 uses the factorised H-matrix as the
+ * preconditioner of an iteration with the H-matrix, Sec. 5.3 solves the
+ * fractional Poisson problem (shift = 0, fractional generator) by conjugate
+ * gradients, Sec. 5.4 tracks the relative residual of eq.
+ * equ:relative_error over the iterations.  The operator products use G in
+ * FP64 (the factor's operator); the preconditioner is z = U^{-1} L^{-1} r
+ * with the factor's inverse factors, a good one when the factor's
+ * M = I - dt/2 G is close to a multiple of shift I - G, i.e. 2/dt near
+ * shift (for shift = 0: dt large against 1/lambda_min(-G)).  Methods:
+ * HLEVY_KRYLOV_CG for a symmetric positive definite shift I - G (symmetric
+ * jump kernel, no drift), HLEVY_KRYLOV_BICGSTAB for any operator.
+ * Deterministic: every reduction runs in a fixed order. */
+typedef enum { HLEVY_KRYLOV_CG = 0, HLEVY_KRYLOV_BICGSTAB = 1 } hlevy_krylov_method;
+typedef struct {
+  int32_t method;        /* hlevy_krylov_method */
+  int32_t max_iter;      /* >= 1 */
+  double tol;            /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual), A = shift I - G */
+  double shift;
+  int32_t precondition;  /* 1: with the factor's inverse factors; 0: none (for comparison) */
+  int32_t use_guess;     /* 1: x holds the initial guess on entry; 0: start from x = 0 */
+} hlevy_krylov;
+typedef struct {
+  int32_t iterations;    /* iterations taken (a BiCGSTAB iteration is two products with G) */
+  int32_t converged;     /* 1 when tol was met */
+  double rel_residual;   /* ||b - A x||_2 / ||b||_2 recomputed from the returned x */
+  double seconds;        /* wall time of the call */
+} hlevy_krylov_stats;
+
+/* b, x: device, length N, natural order, must not overlap.  history: NULL
+ * or a host array of max_iter + 1 doubles that receives the recursive
+ * relative residual before the first iteration and after each one (entries
+ * past the last iteration are not written).  x receives the last iterate
+ * also when tol is not met; the call then returns HLEVY_ERR_NOT_CONVERGED
+ * (stats filled).  A zero right-hand side gives x = 0 after no iteration.
+ * Errors: HLEVY_ERR_INVALID_ARG for a bad option or overlapping b and x.
+ * Synchronises `stream` once per iteration (twice for BiCGSTAB). */
+hlevy_status hlevy_krylov_solve(hlevy_fac* fac, const double* b, double* x, const hlevy_krylov* opt,
+                                hlevy_krylov_stats* stats, double* history, void* stream);
+
 /* Serving loop.  Requests (a problem, dt, a horizon of nsteps unforced
  * Crank-Nicolson steps, u0) arrive at any time; each hlevy_server_poll is
  * one scheduling round:

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlevy.so")
 
-SOURCES = ["structure.cpp", "kernels.hip", "mv.hip", "runtime.hip", "autotune.hip"]
+SOURCES = ["structure.cpp", "kernels.hip", "mv.hip", "runtime.hip", "autotune.hip", "krylov.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
     # no packed-FP32 instructions anywhere in the device code

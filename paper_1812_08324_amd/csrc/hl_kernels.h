@@ -46,6 +46,39 @@ hipError_t launch_densify(const LeafDesc* L, const int32_t* rank, int nleaves, c
                           int N, double* dense, hipStream_t s);
 hipError_t init_kernel_attributes();
 
+// Krylov iterations (krylov.hip).  Scalars live in a device array sc.
+// A coefficient is mul * sc[idx] (idx >= 0) or the constant mul (idx < 0).
+struct KrCoef {
+  int32_t idx;
+  int32_t pad;
+  double mul;
+};
+constexpr int KR_MAXDOT = 3;
+// up to KR_MAXDOT dot products a_k . b_k, written to sc[out[k]]
+struct KrDots {
+  const double* a[KR_MAXDOT];
+  const double* b[KR_MAXDOT];
+  int32_t out[KR_MAXDOT];
+  int32_t n;
+};
+// sc[dst] = sc[num] / sc[den] (times sc[num2] / sc[den2] when num2 >= 0);
+// after that, sc[copy_to] = sc[copy_from] when copy_from >= 0
+struct KrRatio {
+  int32_t dst, num, den, num2, den2, copy_from, copy_to, pad;
+};
+constexpr int KR_MAXRATIO = 4;
+struct KrRatios {
+  KrRatio r[KR_MAXRATIO];
+  int32_t n, pad;
+};
+// partial holds KR_MAXDOT * kr_blocks(N) doubles
+int kr_blocks(int N);
+hipError_t launch_kr_dots(const KrDots& d, int N, double* partial, double* sc, hipStream_t s);
+hipError_t launch_kr_scalars(const KrRatios& q, double* sc, hipStream_t s);
+// out = c0 x0 + c1 x1 + c2 x2 (x1, x2 may be null)
+hipError_t launch_kr_comb(double* out, const double* x0, KrCoef c0, const double* x1, KrCoef c1,
+                          const double* x2, KrCoef c2, const double* sc, int N, hipStream_t s);
+
 inline int npairs_host(int K) { return K * (K + 1) / 2; }
 
 }  // namespace hl

@@ -2884,6 +2884,200 @@ hlevy_status hlevy_solve_noalloc(hlevy_fac* f, const double* b, double* x, const
   });
 }
 
+// Steady solves (shift I - G) x = b by conjugate gradients or BiCGSTAB, the
+// factor's inverse factors as the preconditioner (Sec. 5.1, 5.3, 5.4).
+// Vectors are in cluster order; the scalars of the iteration stay in a
+// device array (see krylov.hip) and the host reads them once per half
+// iteration for the stopping test.
+hlevy_status hlevy_krylov_solve(hlevy_fac* f, const double* b, double* x, const hlevy_krylov* opt,
+                                hlevy_krylov_stats* stats, double* history, void* stream) {
+  if (!f || !b || !x || !opt) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  const int N = f->op->S.N;
+  if (b < x + N && x < b + N) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not overlap");
+  if (opt->method != HLEVY_KRYLOV_CG && opt->method != HLEVY_KRYLOV_BICGSTAB)
+    return fail(HLEVY_ERR_INVALID_ARG, "method must be HLEVY_KRYLOV_CG or HLEVY_KRYLOV_BICGSTAB");
+  if (opt->max_iter < 1) return fail(HLEVY_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (!(opt->tol >= 0.0) || !std::isfinite(opt->tol)) return fail(HLEVY_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (!std::isfinite(opt->shift)) return fail(HLEVY_ERR_INVALID_ARG, "shift must be finite");
+  if ((opt->precondition != 0 && opt->precondition != 1) || (opt->use_guess != 0 && opt->use_guess != 1))
+    return fail(HLEVY_ERR_INVALID_ARG, "precondition and use_guess are 0 or 1");
+  const double t_start = now_s();
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    const int32_t* perm = f->op->ds.perm.as<int32_t>();
+    enum { V_B, V_X, V_R, V_P, V_Q, V_Z, V_T, V_S, V_RH, V_W, NV };
+    enum { S_ONE, S_BB, S_RR, S_RZ, S_RZOLD, S_PQ, S_ALPHA, S_BETA, S_BW, S_OMEGA, S_RHO, S_RHOOLD, S_RV, S_TS,
+           S_TT, S_SS, NS = 32 };
+    const size_t nd = (size_t)KR_MAXDOT * kr_blocks(N);
+    DevBuf work;
+    work.alloc((NV * (size_t)N + nd + NS) * sizeof(double));
+    double* v[NV];
+    for (int i = 0; i < NV; ++i) v[i] = work.as<double>() + (size_t)i * N;
+    double* partial = work.as<double>() + NV * (size_t)N;
+    double* sc = partial + nd;
+    double init[NS] = {};
+    init[S_ONE] = 1.0;
+    HL_CHECK(hipMemcpyAsync(sc, init, sizeof(init), hipMemcpyHostToDevice, s));
+    const KrCoef one{-1, 0, 1.0}, none{-1, 0, 0.0}, minus{-1, 0, -1.0};
+    auto sc_coef = [](int idx, double mul) { return KrCoef{idx, 0, mul}; };
+    auto comb = [&](double* out, const double* a, KrCoef ca, const double* b1 = nullptr, KrCoef cb = KrCoef{},
+                    const double* c1 = nullptr, KrCoef cc = KrCoef{}) {
+      HL_CHECK(launch_kr_comb(out, a, ca, b1, cb, c1, cc, sc, N, s));
+    };
+    struct DotReq {
+      const double* a;
+      const double* b;
+      int out;
+    };
+    auto dots = [&](std::initializer_list<DotReq> l) {
+      KrDots d{};
+      for (const DotReq& e : l) {
+        d.a[d.n] = e.a;
+        d.b[d.n] = e.b;
+        d.out[d.n] = e.out;
+        ++d.n;
+      }
+      HL_CHECK(launch_kr_dots(d, N, partial, sc, s));
+    };
+    auto dot_to = [](const double* a, const double* b1, int out) { return DotReq{a, b1, out}; };
+    auto ratios = [&](std::initializer_list<KrRatio> l) {
+      KrRatios q{};
+      for (const auto& r : l) q.r[q.n++] = r;
+      HL_CHECK(launch_kr_scalars(q, sc, s));
+    };
+    double host[NS];
+    auto read = [&]() {
+      HL_CHECK(hipMemcpyAsync(host, sc, sizeof(host), hipMemcpyDeviceToHost, s));
+      HL_CHECK(hipStreamSynchronize(s));
+    };
+    // A y = shift y - G y (FP64 operator)
+    auto apply_A = [&](const double* y, double* out) {
+      MvEpi e{};
+      e.kind = MV_EPI_AXPY;
+      e.hdt = -1.0;
+      e.cg = opt->shift;
+      e.g = y;
+      e.y = out;
+      f->mvG.run(y, e, s);
+    };
+    auto precond = [&](const double* y, double* out) {
+      if (!opt->precondition) {
+        comb(out, y, one);
+        return;
+      }
+      f->mvLi.run(y, epi_plain(v[V_W]), s);
+      f->mvUi.run(v[V_W], epi_plain(out), s);
+    };
+    HL_CHECK(launch_perm_gather(v[V_B], b, perm, N, s));
+    if (opt->use_guess) {
+      HL_CHECK(launch_perm_gather(v[V_X], x, perm, N, s));
+      apply_A(v[V_X], v[V_Q]);
+      comb(v[V_R], v[V_B], one, v[V_Q], minus);
+    } else {
+      comb(v[V_X], v[V_B], none);
+      comb(v[V_R], v[V_B], one);
+    }
+    dots({dot_to(v[V_B], v[V_B], S_BB), dot_to(v[V_R], v[V_R], S_RR)});
+    read();
+    const double bnorm = std::sqrt(host[S_BB]);
+    int it = 0;
+    bool converged = false;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+      comb(v[V_X], v[V_B], none);   // b = 0: x = 0
+      converged = true;
+    } else {
+      rel = std::sqrt(host[S_RR]) / bnorm;
+      if (history) history[0] = rel;
+      converged = rel <= opt->tol;
+      const double tol = opt->tol;
+      auto check = [&](double rr) {
+        rel = std::sqrt(rr) / bnorm;
+        if (history) history[it] = rel;
+        return std::isfinite(rel) && rel <= tol;
+      };
+      if (opt->method == HLEVY_KRYLOV_CG) {
+        double *r = v[V_R], *p = v[V_P], *q = v[V_Q], *z = v[V_Z], *xv = v[V_X];
+        precond(r, z);
+        dots({dot_to(r, z, S_RZ)});
+        comb(p, z, one);
+        while (!converged && it < opt->max_iter && std::isfinite(rel)) {
+          ++it;
+          apply_A(p, q);
+          dots({dot_to(p, q, S_PQ)});
+          ratios({KrRatio{S_ALPHA, S_RZ, S_PQ, -1, -1, S_RZ, S_RZOLD, 0}});
+          comb(xv, xv, one, p, sc_coef(S_ALPHA, 1.0));
+          comb(r, r, one, q, sc_coef(S_ALPHA, -1.0));
+          precond(r, z);
+          dots({dot_to(r, r, S_RR), dot_to(r, z, S_RZ)});
+          read();
+          converged = check(host[S_RR]);
+          if (converged || !std::isfinite(rel)) break;
+          ratios({KrRatio{S_BETA, S_RZ, S_RZOLD, -1, -1, -1, -1, 0}});
+          comb(p, z, one, p, sc_coef(S_BETA, 1.0));
+        }
+      } else {
+        double *r = v[V_R], *p = v[V_P], *vv = v[V_Q], *y = v[V_Z], *t = v[V_T], *sv = v[V_S], *rh = v[V_RH],
+               *xv = v[V_X];
+        comb(rh, r, one);
+        dots({dot_to(rh, r, S_RHO), dot_to(rh, r, S_RHOOLD)});
+        while (!converged && it < opt->max_iter && std::isfinite(rel)) {
+          ++it;
+          if (it == 1) {
+            comb(p, r, one);
+          } else {
+            // beta = (rho_i / rho_{i-1}) (alpha / omega); p = r + beta (p - omega v)
+            ratios({KrRatio{S_BETA, S_RHO, S_RHOOLD, S_ALPHA, S_OMEGA, -1, -1, 0},
+                    KrRatio{S_BW, S_RHO, S_RHOOLD, S_ALPHA, S_ONE, S_RHO, S_RHOOLD, 0}});
+            comb(p, r, one, p, sc_coef(S_BETA, 1.0), vv, sc_coef(S_BW, -1.0));
+          }
+          precond(p, y);
+          apply_A(y, vv);
+          dots({dot_to(rh, vv, S_RV)});
+          ratios({KrRatio{S_ALPHA, S_RHO, S_RV, -1, -1, -1, -1, 0}});
+          comb(sv, r, one, vv, sc_coef(S_ALPHA, -1.0));
+          comb(xv, xv, one, y, sc_coef(S_ALPHA, 1.0));
+          dots({dot_to(sv, sv, S_SS)});
+          read();
+          if (check(host[S_SS]) || !std::isfinite(rel)) {
+            converged = std::isfinite(rel);
+            comb(r, sv, one);
+            break;
+          }
+          precond(sv, y);
+          apply_A(y, t);
+          dots({dot_to(t, sv, S_TS), dot_to(t, t, S_TT)});
+          ratios({KrRatio{S_OMEGA, S_TS, S_TT, -1, -1, -1, -1, 0}});
+          comb(xv, xv, one, y, sc_coef(S_OMEGA, 1.0));
+          comb(r, sv, one, t, sc_coef(S_OMEGA, -1.0));
+          dots({dot_to(r, r, S_RR), dot_to(rh, r, S_RHO)});
+          read();
+          converged = check(host[S_RR]);
+        }
+      }
+      // the residual of the returned x, with the FP64 operator
+      apply_A(v[V_X], v[V_Q]);
+      comb(v[V_T], v[V_B], one, v[V_Q], minus);
+      dots({dot_to(v[V_T], v[V_T], S_RR)});
+      read();
+      rel = std::sqrt(host[S_RR]) / bnorm;
+    }
+    HL_CHECK(launch_perm_scatter(x, v[V_X], perm, N, s));
+    HL_CHECK(hipStreamSynchronize(s));
+    if (stats) {
+      stats->iterations = it;
+      stats->converged = converged ? 1 : 0;
+      stats->rel_residual = rel;
+      stats->seconds = now_s() - t_start;
+    }
+    if (!converged)
+      return fail(HLEVY_ERR_NOT_CONVERGED, "Krylov iteration reached a relative residual of " + std::to_string(rel) +
+                                               " after " + std::to_string(it) + " iterations (tol " +
+                                               std::to_string(opt->tol) + ")");
+    return HLEVY_OK;
+  });
+}
+
 hlevy_status hlevy_step(hlevy_fac* f, double* u, int64_t nsteps, const double* g, const double* phi,
                         const hlevy_refine* refine, hlevy_stats* stats, void* stream) {
   if (!f || !u) return fail(HLEVY_ERR_INVALID_ARG, "null argument");

@@ -84,10 +84,23 @@ class TuneResult(C.Structure):
 
 EXPORTS = ["hlevy_abi_version", "hlevy_autotune", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
            "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
-           "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_solve_noalloc", "hlevy_step",
+           "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_solve_noalloc", "hlevy_krylov_solve", "hlevy_step",
            "hlevy_step_batched", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
            "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_take_failed",
            "hlevy_server_stats_get", "hlevy_server_destroy"]
+
+
+KRYLOV_CG, KRYLOV_BICGSTAB = 0, 1
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("shift", C.c_double),
+                ("precondition", C.c_int32), ("use_guess", C.c_int32)]
+
+
+class KrylovStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double),
+                ("seconds", C.c_double)]
 
 
 class ServerConfig(C.Structure):
@@ -126,6 +139,8 @@ def _load():
                                   C.c_size_t, vp, C.POINTER(vp)], st),
         "hlevy_solve": ([vp, vp, vp, C.c_int64, C.c_int64, C.POINTER(Refine), C.POINTER(Stats), vp], st),
         "hlevy_solve_noalloc": ([vp, vp, vp, C.POINTER(Refine), C.POINTER(Stats), vp], st),
+        "hlevy_krylov_solve": ([vp, vp, vp, C.POINTER(KrylovOpts), C.POINTER(KrylovStats), C.POINTER(C.c_double),
+                                vp], st),
         "hlevy_step_batched": ([C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, C.POINTER(Refine),
                                 C.POINTER(Stats), vp], st),
         "hlevy_step": ([vp, vp, C.c_int64, vp, C.POINTER(C.c_double), C.POINTER(Refine),
@@ -434,6 +449,27 @@ def solve_noalloc(fac: Fac, b, x, refine=None, stats=False, stream=None):
                                    C.byref(st) if st is not None else None, _stream(stream)),
            "hlevy_solve_noalloc")
     return _stats_dict(st) if st is not None else None
+
+
+def krylov_solve(fac: Fac, b, x, method: int = KRYLOV_CG, max_iter: int = 200, tol: float = 1e-12,
+                 shift: float = 0.0, precondition: bool = True, use_guess: bool = False,
+                 raise_not_converged: bool = True, stream=None):
+    """Solve (shift I - G) x = b by a Krylov iteration preconditioned with
+    the factor (hlevy_krylov_solve).  b, x: (N,) contiguous float64 CUDA
+    tensors.  Returns a dict with iterations, converged, rel_residual,
+    seconds and the per-iteration relative residuals (history).  When tol
+    is not met x holds the last iterate, and HlevyError (NOT_CONVERGED) is
+    raised unless raise_not_converged is False."""
+    o = KrylovOpts(int(method), int(max_iter), float(tol), float(shift), int(bool(precondition)),
+                   int(bool(use_guess)))
+    st = KrylovStats()
+    hist = (C.c_double * (int(max_iter) + 1))()
+    rc = lib.hlevy_krylov_solve(fac.h, _dptr(b, fac.N), _dptr(x, fac.N), C.byref(o), C.byref(st), hist,
+                                _stream(stream))
+    if rc != -4 or raise_not_converged:   # -4: HLEVY_ERR_NOT_CONVERGED
+        _check(rc, "hlevy_krylov_solve")
+    return {"iterations": st.iterations, "converged": bool(st.converged), "rel_residual": st.rel_residual,
+            "seconds": st.seconds, "history": [hist[i] for i in range(st.iterations + 1)]}
 
 
 def step(fac: Fac, u, nsteps: int, g=None, phi=None, refine=None, stats=False, stream=None):

@@ -131,6 +131,17 @@ def config3(s: float = 0.75, n: int = 256, steps: int = 200, seed: int = 1812) -
     return w
 
 
+def steady_poisson(n: int = 65536, s: float = 0.5, dt: float = 1e4) -> Workload:
+    """Steady fractional Poisson problem (-Delta)^s u = 1 on [-1, 1] with
+    zero exterior (Sec. 5.3): right-hand side f = 1 (kept in ``g``); the
+    preconditioning factor is that of I - dt/2 G with dt = 1e4 (far above
+    1/lambda_min of -G, so the factor is nearly proportional to -G)."""
+    w = Workload(name="frac_poisson1d_s%g_n%d" % (s, n), dim=1, n=n, lo=-1.0, hi=1.0, s=s, dt=dt,
+                 steps=0, aca_tol=1e-10, max_rank=16, lu_tol=1e-6)
+    w.g = np.ones(n)
+    return w
+
+
 def config4_instances(count: int = 512, seed: int = 8324, nmin_log2: float = 10.0,
                       nmax_log2: float = 15.0, steps: int = 100) -> list:
     """Independent 1D tempered instances: N log-uniform, s ~ U(0.1, 0.9),
