@@ -57,6 +57,7 @@ __all__ = [
     "Problem", "frac_const", "ball_const", "gauss_const", "grid", "h_of",
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
     "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
+    "taylor_terms", "taylor_factors",
 ]
 
 
@@ -88,8 +89,12 @@ class Problem:
     """Model equation u_t = a Lap u + b.grad u + c u + L u on a box with zero
     exterior (Sec. 3.1 eq. equ:ut; Sec. 4 closing remark).
 
-    Jump kernel nu(y) = C exp(-lam |y|) / |y|^{d+2s}; C = None selects c_{d,s}
-    (then lam = 0 is exactly the fractional Laplacian, Sec. 4).
+    Jump kernel (kernel = "tempered") nu(y) = C exp(-lam |y|) / |y|^{d+2s};
+    C = None selects c_{d,s} (then lam = 0 is exactly the fractional
+    Laplacian, Sec. 4).  kernel = "gaussian": the Gaussian (Merton) jump
+    density nu(y) = C exp(-eps2 |y|^2) (Sec. 3.3), C = None selects 1; it is
+    bounded, so the generator is the plain trapezoid rule of Sec. 3.2
+    (eqs. equ:dl, equ:Aij) without singularity subtraction.
     """
     dim: int
     n: int                       # interior points per axis
@@ -103,6 +108,8 @@ class Problem:
     C: float | None = None
     r0: float = 0.2              # window radius before snapping to the grid
     jumps: bool = True           # False drops the jump operator (nu = 0)
+    kernel: str = "tempered"     # or "gaussian"
+    eps2: float = 0.0            # Gaussian kernel: nu(y) = C exp(-eps2 |y|^2)
 
     @property
     def N(self) -> int:
@@ -110,7 +117,9 @@ class Problem:
 
     @property
     def Cval(self) -> float:
-        return frac_const(self.dim, self.s) if self.C is None else float(self.C)
+        if self.C is not None:
+            return float(self.C)
+        return 1.0 if self.kernel == "gaussian" else frac_const(self.dim, self.s)
 
 
 def h_of(p: Problem) -> float:
@@ -131,6 +140,8 @@ def grid(p: Problem) -> np.ndarray:
 def kernel_nu(p: Problem, r):
     """nu at distance r > 0."""
     r = np.asarray(r, dtype=np.float64)
+    if p.kernel == "gaussian":
+        return p.Cval * np.exp(-p.eps2 * r * r)
     return p.Cval * np.exp(-p.lam * r) / r ** (p.dim + 2.0 * p.s)
 
 
@@ -180,6 +191,21 @@ def quadrature_constants(p: Problem) -> dict:
     C, s, lam, d = p.Cval, p.s, p.lam, p.dim
     if not p.jumps:
         return dict(S0=0.0, S2=0.0, C2=0.0, T=0.0, h=h, NW=NW, m=m, r=r, LW=LW)
+    if p.kernel == "gaussian":
+        # Sec. 3.2 (equ:dl): the coefficient of -u_i is h^d sum' nu(kh) over
+        # the whole lattice (the exterior holds u = 0, but u_i leaves to
+        # every offset); no singularity subtraction, no window terms.  Terms
+        # below 1e-18 nu(0) are dropped.
+        K = int(math.ceil(math.sqrt(41.5 / p.eps2) / h)) + 1
+        k = np.arange(-K, K + 1)
+        if d == 1:
+            kk = k[k != 0]
+            S0 = h * math.fsum(kernel_nu(p, np.abs(kk) * h))
+        else:
+            K1, K2 = np.meshgrid(k, k, indexing="ij")
+            sel = (K1 != 0) | (K2 != 0)
+            S0 = h * h * math.fsum(kernel_nu(p, np.hypot(K1[sel] * h, K2[sel] * h)))
+        return dict(S0=S0, S2=0.0, C2=0.0, T=0.0, h=h, NW=NW, m=m, r=r, LW=LW)
     k = np.arange(-NW, NW + 1)
     nz = k != 0
     if d == 1:
@@ -285,6 +311,55 @@ def generator_dense(p: Problem) -> np.ndarray:
     for i in range(p.N):
         G[i] = generator_row(p, i, consts)
     return G
+
+
+# ---------------------------------------------------------------------------
+# Fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3)
+# ---------------------------------------------------------------------------
+def taylor_terms(dim: int, rank: int) -> list:
+    """Exponents of the first `rank` terms of the expansion: 1D n = 0, 1,
+    ...; 2D the products (n1, n2) of the 1D series in order of total degree
+    n1 + n2, then of n2."""
+    if dim == 1:
+        return [(n,) for n in range(rank)]
+    out, deg = [], 0
+    while len(out) < rank:
+        for n2 in range(deg + 1):
+            if len(out) < rank:
+                out.append((deg - n2, n2))
+        deg += 1
+    return out
+
+
+def taylor_factors(p: Problem, rows, cols, rank: int):
+    """U (m x rank), V (n x rank) with U V^T approximating the generator's
+    block h^d nu(x_j - x_i) (i in rows, j in cols) for the Gaussian kernel,
+    from the Taylor expansion about the centre xbar of the row points'
+    bounding box (Sec. 3.3): with t0 = x - xbar and t = y - xbar per axis,
+    alpha_n(t0) = (2 eps2)^n exp(-eps2 t0^2) t0^n / n! and
+    beta_n(t) = exp(-eps2 t^2) t^n, so that exp(-eps2 (x - y)^2) is
+    sum_n alpha_n(t0) beta_n(t); in 2D a term is the product of one 1D term
+    per axis.  U carries the factor h^d C."""
+    pts = grid(p)
+    X = pts[np.asarray(rows)]
+    Y = pts[np.asarray(cols)]
+    xbar = 0.5 * (X.min(axis=0) + X.max(axis=0))
+    t0 = X - xbar
+    t = Y - xbar
+    h = h_of(p)
+    e = p.eps2
+    terms = taylor_terms(p.dim, rank)
+    U = np.empty((len(X), rank))
+    V = np.empty((len(Y), rank))
+    for q, ns in enumerate(terms):
+        a = np.full(len(X), (h ** p.dim) * p.Cval)
+        b = np.ones(len(Y))
+        for ax, n in enumerate(ns):
+            a = a * (2.0 * e) ** n * np.exp(-e * t0[:, ax] ** 2) * t0[:, ax] ** n / math.factorial(n)
+            b = b * np.exp(-e * t[:, ax] ** 2) * t[:, ax] ** n
+        U[:, q] = a
+        V[:, q] = b
+    return U, V
 
 
 # ---------------------------------------------------------------------------

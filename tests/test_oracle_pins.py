@@ -15,8 +15,8 @@ import scipy.special as sp
 
 from oracle.levy_oracle import (Problem, ball_const, cn_run, cn_run_lean, frac_const,
                                 gauss_const, generator_dense, generator_row,
-                                grid, kernel_nu, quadrature_constants, steady_solve, steady_residual,
-                                fractional_poisson_exact)
+                                grid, h_of, kernel_nu, quadrature_constants, steady_solve, steady_residual,
+                                fractional_poisson_exact, taylor_factors, taylor_terms)
 
 
 def _order(e1, e2):
@@ -416,3 +416,73 @@ def test_steady_solve_special_cases():
     x = grid(p)[:, 0]
     u = steady_solve(generator_dense(p), 0.0, np.ones(n))
     assert np.allclose(u, (1.0 - x ** 2) / 0.5, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Gaussian (Merton) kernel (Sec. 3.3) and the semi-heavy scheme (Sec. 3.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(1, 255), (2, 31)])
+def test_gaussian_lattice_constant(dim, n):
+    """h^d sum over the lattice without 0 of exp(-eps2 |kh|^2) equals
+    (pi/eps2)^{d/2} - h^d up to exponentially small terms (Poisson
+    summation: the trapezoid rule is exact to rounding for the Gaussian)."""
+    for eps2, C in ((5.0, 1.0), (0.7, 2.5)):
+        p = Problem(dim=dim, n=n, kernel="gaussian", eps2=eps2, C=C)
+        c = quadrature_constants(p)
+        h = c["h"]
+        want = C * ((math.pi / eps2) ** (dim / 2.0) - h ** dim)
+        assert c["S0"] == pytest.approx(want, rel=1e-13)
+        assert c["S2"] == 0.0 and c["C2"] == 0.0 and c["T"] == 0.0
+
+
+@pytest.mark.parametrize("dim,n", [(1, 511), (2, 63)])
+def test_gaussian_generator_on_gaussian(dim, n):
+    """The model problems of Sec. 5.1 / 5.2 (nu = exp(-5|y|^2) on [-1, 1]^d,
+    zero exterior): applied to u = exp(-50|x|^2), which vanishes to 1e-21 at
+    the boundary, the generator equals the continuous operator
+    int (u(x+y) - u(x)) nu(y) dy = (pi/(50+5))^{d/2} exp(-250/55 |x|^2)
+    - u(x) (pi/5)^{d/2} to 1e-10 of its size."""
+    p = Problem(dim=dim, n=n, kernel="gaussian", eps2=5.0)
+    x = grid(p)
+    r2 = np.sum(x ** 2, axis=1)
+    u = np.exp(-50.0 * r2)
+    Lu = (math.pi / 55.0) ** (dim / 2.0) * np.exp(-250.0 / 55.0 * r2) - u * (math.pi / 5.0) ** (dim / 2.0)
+    Gu = generator_dense(p) @ u
+    assert np.max(np.abs(Gu - Lu)) <= 1e-10 * np.max(np.abs(Lu))
+
+
+def test_taylor_factors_converge_and_meet_lemma_bound():
+    """Sec. 3.3: the Taylor factors of a block converge to the kernel block
+    as the rank grows (1D and, with products of the 1D series ordered by
+    total degree, 2D), and with r above the bound of Lemma 1 (eq. equ:r;
+    terms n = 0..r) the error is below delta everywhere."""
+    p = Problem(dim=1, n=255, kernel="gaussian", eps2=5.0)
+    h = h_of(p)
+    rows, cols = np.arange(0, 64), np.arange(128, 255)
+    x = grid(p)[:, 0]
+    exact = h * np.exp(-5.0 * (x[rows, None] - x[None, cols]) ** 2)
+    errs = []
+    for r in (4, 10, 20, 40):
+        U, V = taylor_factors(p, rows, cols, r)
+        errs.append(np.abs(U @ V.T - exact).max() / np.abs(exact).max())
+    assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-13, errs
+    # Lemma 1 with eps2 = 0.1, D = 2, delta = 1e-6
+    q = Problem(dim=1, n=255, kernel="gaussian", eps2=0.1)
+    eps2, D, delta = 0.1, 2.0, 1e-6
+    rb = max(math.log2(math.exp(2 * eps2 * D * D) / delta) - 1.0, 12 * eps2 * D * D - 1.0)
+    r = int(math.floor(rb)) + 1
+    U, V = taylor_factors(q, rows, cols, r + 1)
+    k = np.exp(-eps2 * (x[rows, None] - x[None, cols]) ** 2)
+    assert np.abs(U @ V.T / h - k).max() < delta
+    # 2D: rank 66 = every product term of total degree <= 10
+    p2 = Problem(dim=2, n=15, kernel="gaussian", eps2=5.0)
+    X = grid(p2)
+    rows2 = np.where((X[:, 0] < -0.5) & (X[:, 1] < -0.5))[0]
+    cols2 = np.where((X[:, 0] > 0.3) & (X[:, 1] > 0.0))[0]
+    ex2 = h_of(p2) ** 2 * np.exp(-5.0 * np.sum((X[rows2, None, :] - X[None, cols2, :]) ** 2, axis=2))
+    e2 = []
+    for r in (10, 28, 66):
+        U2, V2 = taylor_factors(p2, rows2, cols2, r)
+        e2.append(np.abs(U2 @ V2.T - ex2).max())
+    assert e2[0] > e2[1] > e2[2] and e2[2] < 1e-4 * np.abs(ex2).max(), e2
+    assert taylor_terms(2, 10) == [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1), (1, 2), (0, 3)]
