@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D workload")
     ap.add_argument("--no-steady", action="store_true", help="skip the steady (Krylov) measurement")
     ap.add_argument("--steady-only", action="store_true", help="only the steady measurement (its own JSON line)")
+    ap.add_argument("--no-gaussian", action="store_true", help="skip the Gaussian-kernel (paper workload) timings")
+    ap.add_argument("--gaussian-only", action="store_true", help="only the Gaussian-kernel timings")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuner cache of the batched workload ('' = tune every run, keep nothing)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -339,6 +341,74 @@ def bench_steady(H, torch, n=65536, s=0.5):
     return out
 
 
+# The paper's own timings of its Gaussian-kernel workload (Xeon E7-8890 v3,
+# Julia 1.0.2, no explicit parallelism; Sec. 5.1 fig:g1d, Sec. 5.2 fig:g2d),
+# in seconds: construction, H-matvec, H-LU, H-solve (one right-hand side).
+PAPER_GAUSSIAN = {
+    ("1d", 65536): {"construction": 4.224, "matvec": 0.0886, "lu": 4.970, "solve": 0.0881},
+    ("2d", 65536): {"construction": 48.78, "matvec": 0.2325, "lu": 22.97, "solve": 0.1036},
+}
+
+
+def bench_gaussian(H, torch):
+    """The paper's timed workload: the Gaussian (Merton) jump kernel
+    nu(y) = exp(-5|y|^2) on [-1, 1]^d with zero exterior, rank-10 Taylor
+    far field (Sec. 3.3), leaf 64, eta = 1.  Per size: H-matrix
+    construction, one H-matvec, the H-LU (FP64, lu_tol 1e-10) and one
+    H-solve (forward and backward product with the inverse factors, no
+    refinement), each beside the paper's time for the same operation."""
+    import numpy as np
+    out = {}
+    for dim, n, n_block in ((1, 65536, 4), (2, 256, 4)):
+        N = n ** dim
+        prob = H.make_problem(dim, n, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=5.0)
+        hp = H.make_hparams(leaf=64, eta=1.0, n_block=n_block, max_rank=16, taylor_rank=10)
+        t = {}
+        for rep in range(2):    # the first pass warms the code paths
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            op = H.assemble(prob, hp)
+            torch.cuda.synchronize()
+            t["construction"] = time.perf_counter() - t0
+            if rep == 0:
+                del op
+        x = torch.tensor(np.random.Generator(np.random.PCG64(5)).standard_normal(N), dtype=torch.float64,
+                         device="cuda")
+        y = torch.empty_like(x)
+        H.matvec(op, x, y)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            H.matvec(op, x, y)
+        torch.cuda.synchronize()
+        t["matvec"] = (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = H.factor(op, 1.0, H.PREC_FP64, 1e-10)
+        torch.cuda.synchronize()
+        t["lu"] = time.perf_counter() - t0
+        z = torch.empty_like(x)
+        H.solve(fac, x, z, refine={"sweeps": 0})
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            H.solve(fac, x, z, refine={"sweeps": 0})
+        torch.cuda.synchronize()
+        t["solve"] = (time.perf_counter() - t0) / reps
+        paper = PAPER_GAUSSIAN[("%dd" % dim, N)]
+        key = "gauss%dd_n%d" % (dim, N)
+        out[key] = {"N": N, "seconds": t, "paper_seconds": paper,
+                    "speedup_vs_paper": {k: paper[k] / t[k] for k in t},
+                    "operator_MB": H.op_info(op)["device_bytes"] / 1e6, "n_block": n_block}
+        del fac, op
+        progress(f"Gaussian kernel {key} done")
+    out["note"] = ("M = I - dt/2 G with dt = 1 for the H-LU (the paper factors the system matrix of its "
+                   "scheme); the paper's times are a single Xeon core in Julia, context only; 2D rank 10 = "
+                   "products of the 1D Taylor series up to total degree 3")
+    return out
+
+
 def counted_traffic(key, algorithmic_bytes=None):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
     summary, or None when the product kernels' sources have changed since
@@ -451,6 +521,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.gaussian_only:
+        line = bench_gaussian(H, torch)
+        line["command"] = "python bench.py " + " ".join(sys.argv[1:])
+        print(json.dumps(line))
+        return
     if args.steady_only:
         line = bench_steady(H, torch)
         line["command"] = "python bench.py " + " ".join(sys.argv[1:])
@@ -635,6 +710,8 @@ def main():
     if not args.no_steady:
         line["steady"] = bench_steady(H, torch)
         progress("steady solve done")
+    if not args.no_gaussian:
+        line["gaussian_kernel"] = bench_gaussian(H, torch)
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_frac_1d, args.serve_sweeps,
                                         args.lu_tol_mixed)

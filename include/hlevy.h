@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HLEVY_ABI_VERSION 3
+#define HLEVY_ABI_VERSION 4
 
 typedef enum {
   HLEVY_OK = 0,
@@ -57,6 +57,15 @@ typedef enum {
                                  (dense leaves FP32, every product accumulating in FP64) */
 } hlevy_precision;
 
+/* Jump kernels.  TEMPERED: nu(y) = C exp(-lambda |y|) / |y|^{d+2s} (Sec. 4
+ * eq. equ:ny2; lambda = 0 with C = c_{d,s} is the fractional Laplacian),
+ * discretised with the singularity subtraction of Sec. 4.  GAUSSIAN: the
+ * Merton jump density nu(y) = C exp(-eps2 |y|^2) (Sec. 3.3), bounded, so
+ * discretised by the plain trapezoid rule of Sec. 3.2 (eqs. equ:dl and
+ * equ:Aij): off-diagonal entries h^d nu(x_j - x_i), diagonal
+ * -h^d sum over the lattice without 0 of nu(kh) (u = 0 outside the box). */
+typedef enum { HLEVY_KERNEL_TEMPERED = 0, HLEVY_KERNEL_GAUSSIAN = 1 } hlevy_kernel;
+
 /* The model problem (Sec. 3.1 eq. equ:ut; Sec. 4 eqs. equ:ny2 and the
  * zero-exterior remark).  Domain: the box [lo, hi]^dim, u = 0 outside. */
 typedef struct {
@@ -70,6 +79,9 @@ typedef struct {
   double lambda;     /* tempering rate >= 0; 0 = fractional Laplacian kernel */
   double C;          /* kernel constant; C <= 0 selects c_{d,s} = 4^s G(d/2+s)/(pi^{d/2}|G(-s)|) */
   double r0;         /* singular window radius rho (snapped to round(r0/h) h); Sec. 5.3 uses 0.2 */
+  int32_t kernel;    /* hlevy_kernel; GAUSSIAN ignores s, lambda and r0, and C <= 0 selects 1 */
+  int32_t pad;
+  double eps2;       /* GAUSSIAN: eps^2 > 0 of nu(y) = C exp(-eps2 |y|^2) */
 } hlevy_problem;
 
 /* H-matrix parameters (App. B.1): leaf size N_min, admissibility eta
@@ -90,6 +102,15 @@ typedef struct {
                               capacity fails with HLEVY_ERR_RANK_CAP; 0: the blocks are truncated
                               at the capacity, counted in hlevy_fac_info.rank_overflows, and the
                               refinement's residual checks guard the solutions */
+  int32_t taylor_rank;     /* GAUSSIAN kernel only: > 0 builds every admissible block from the first
+                              taylor_rank terms of the Taylor expansion of Sec. 3.3 about its row
+                              cluster's centre (2D: products of the 1D series in order of total
+                              degree), stored at that fixed rank without truncation (the paper's
+                              fixed-rank construction); <= max_rank.  Required (> 0) for the
+                              Gaussian kernel: partially pivoted ACA, whose stopping rule looks at
+                              the last cross only, stops early on its 2D blocks (4.9 % block error
+                              measured at eps2 = 5); 0 for the tempered kernel (ACA) */
+  int32_t pad;
 } hlevy_hparams;
 
 /* Iterative refinement of a solve M x = b preconditioned by the H-LU

@@ -161,6 +161,8 @@ struct GetrfItem {
 struct ProblemDev {
   int32_t dim, n, N;
   double h, a, b0, b1, c, s, lam, C, r0;
+  int32_t kernel, pad;   // HLEVY_KERNEL_TEMPERED or HLEVY_KERNEL_GAUSSIAN
+  double eps2;           // Gaussian: nu(r) = C exp(-eps2 r^2)
 };
 
 }  // namespace hl

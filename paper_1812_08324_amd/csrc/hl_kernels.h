@@ -13,6 +13,10 @@ hipError_t launch_fill_dense(const ProblemDev& P, const double* cst, const int32
 hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids,
                       int n, double* U, double* V, const int64_t* uoff, const int64_t* voff,
                       int32_t* ranks, int kcap, double eps, hipStream_t s);
+// Fixed-rank Taylor factors of the Gaussian kernel straight into the
+// admissible leaves ids[0..n) (rank set to r)
+hipError_t launch_taylor(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids, int n,
+                         int32_t* rank, int r, hipStream_t s);
 hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, const ChunkItem* gram,
                            int ngram, const ChunkItem* expand, int nexp, double tol, int ks, hipStream_t s);
 hipError_t launch_flush_dense(const DFlushItem* items, int n, const Term* terms, hipStream_t s);

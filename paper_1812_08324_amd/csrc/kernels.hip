@@ -98,10 +98,24 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Maximum over the block (blockDim.x == 256); result valid in every thread.
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return m;
+}
+
 // ---------------------------------------------------------------------------
 // kernel of the jump measure and quadrature constants (Sec. 4)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double nu_at(const ProblemDev& P, double r) {
+  if (P.kernel == HLEVY_KERNEL_GAUSSIAN) return P.C * exp(-P.eps2 * r * r);
   return P.C * exp(-P.lam * r) / pow(r, (double)P.dim + 2.0 * P.s);
 }
 
@@ -172,6 +186,30 @@ __device__ void gauss_legendre(int n, int i, double* x, double* w) {
 __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* out) {
   __shared__ double red[4];
   __shared__ double glx[32], glw[32];
+  if (P.kernel == HLEVY_KERNEL_GAUSSIAN) {
+    // Bounded kernel (Sec. 3.2, equ:dl): the coefficient of -u_i is
+    // h^d sum over the lattice without 0 of nu(kh).  The lattice sum of the
+    // Gaussian factorises over the axes: theta = sum_k exp(-eps2 (kh)^2)
+    // over k in Z, S0 = C h^d (theta^d - 1).  Terms below 1e-18 are dropped.
+    const double h = P.h;
+    const int K = (int)ceil(sqrt(41.5 / P.eps2) / h) + 1;
+    double t = 0.0, tc = 0.0;
+    for (int k = K - (int)threadIdx.x; k >= 1; k -= blockDim.x) {   // small terms first
+      const double v = exp(-P.eps2 * (k * h) * (k * h));
+      const double y = v - tc, z = t + y;
+      tc = (z - t) - y;
+      t = z;
+    }
+    const double half = block_sum(t, red) - block_sum(tc, red);   // sum over k >= 1
+    if (threadIdx.x == 0) {
+      const double theta = 1.0 + 2.0 * half;
+      out[0] = P.dim == 1 ? P.C * h * (2.0 * half) : P.C * h * h * (theta * theta - 1.0);
+      out[1] = 0.0;
+      out[2] = 0.0;
+      out[3] = 0.0;
+    }
+    return;
+  }
   const int NW = P.n + 1;
   const double h = P.h;
   const int m = (int)floor(P.r0 / h + 0.5);   // nearest grid multiple, ties up
@@ -290,6 +328,91 @@ __device__ __forceinline__ double far_entry(const ProblemDev& P, const int32_t* 
   }
   double rr = P.h * sqrt((double)k1 * k1 + (double)k2 * k2);
   return (P.dim == 1 ? P.h : P.h * P.h) * nu_at(P, rr);
+}
+
+// Fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3), one block per
+// admissible leaf: with xbar the centre of the row cluster's bounding box,
+// t0 = x_i - xbar and t = y_j - xbar per axis, column q holds
+// U_iq = h^d C prod_ax (2 eps2)^n exp(-eps2 t0^2) t0^n / n! and
+// V_jq = prod_ax exp(-eps2 t^2) t^n, the exponents n of term q taken in
+// order of total degree (1D: n = q).  Coordinates are grid multiples
+// (k + 1) h; the box origin cancels in the differences.  The rank is set to
+// r (columns r.. of the capacity are left untouched).
+__device__ __forceinline__ void taylor_exponents(int dim, int q, int& n1, int& n2) {
+  if (dim == 1) {
+    n1 = q;
+    n2 = 0;
+    return;
+  }
+  int deg = 0;
+  while (q > deg) {
+    q -= deg + 1;
+    ++deg;
+  }
+  n2 = q;
+  n1 = deg - q;
+}
+__device__ __forceinline__ double taylor_alpha(double e2, double t0, int n) {
+  double v = exp(-e2 * t0 * t0);
+  for (int k = 1; k <= n; ++k) v *= 2.0 * e2 * t0 / k;
+  return v;
+}
+__device__ __forceinline__ double taylor_beta(double e2, double t, int n) {
+  double v = exp(-e2 * t * t);
+  for (int k = 1; k <= n; ++k) v *= t;
+  return v;
+}
+__global__ void __launch_bounds__(HL_BLOCK) k_taylor(ProblemDev P, const int32_t* perm, const LeafDesc* L,
+                                                     const int32_t* ids, int32_t* rank, int r) {
+  __shared__ double red[4];
+  __shared__ double cen[2];
+  const int leaf = ids[blockIdx.x];
+  const LeafDesc d = L[leaf];
+  const double h = P.h;
+  // bounding box of the row cluster, per axis
+  for (int ax = 0; ax < P.dim; ++ax) {
+    double mn = 1e300, mx = -1e300;
+    for (int i = threadIdx.x; i < d.m; i += HL_BLOCK) {
+      const int pi = perm[d.rlo + i];
+      const int g = P.dim == 1 ? pi : (ax == 0 ? pi / P.n : pi % P.n);
+      const double x = (g + 1) * h;
+      mn = fmin(mn, x);
+      mx = fmax(mx, x);
+    }
+    const double lo = -block_max(-mn, red);
+    const double hi = block_max(mx, red);
+    if (threadIdx.x == 0) cen[ax] = 0.5 * (lo + hi);
+    __syncthreads();
+  }
+  const double scale = (P.dim == 1 ? h : h * h) * P.C;
+  const double e2 = P.eps2;
+  for (int e = threadIdx.x; e < d.m * r; e += HL_BLOCK) {
+    const int i = e % d.m, q = e / d.m;
+    int n1, n2;
+    taylor_exponents(P.dim, q, n1, n2);
+    const int pi = perm[d.rlo + i];
+    double v;
+    if (P.dim == 1) {
+      v = taylor_alpha(e2, (pi + 1) * h - cen[0], n1);
+    } else {
+      v = taylor_alpha(e2, (pi / P.n + 1) * h - cen[0], n1) * taylor_alpha(e2, (pi % P.n + 1) * h - cen[1], n2);
+    }
+    d.A[i + (size_t)d.m * q] = scale * v;
+  }
+  for (int e = threadIdx.x; e < d.n * r; e += HL_BLOCK) {
+    const int j = e % d.n, q = e / d.n;
+    int n1, n2;
+    taylor_exponents(P.dim, q, n1, n2);
+    const int pj = perm[d.clo + j];
+    double v;
+    if (P.dim == 1) {
+      v = taylor_beta(e2, (pj + 1) * h - cen[0], n1);
+    } else {
+      v = taylor_beta(e2, (pj / P.n + 1) * h - cen[0], n1) * taylor_beta(e2, (pj % P.n + 1) * h - cen[1], n2);
+    }
+    d.B[j + (size_t)d.n * q] = v;
+  }
+  if (threadIdx.x == 0) rank[leaf] = r;
 }
 
 // one block per dense leaf: fill G entries (col-major)
@@ -2249,6 +2372,12 @@ hipError_t launch_fill_dense(const ProblemDev& P, const double* cst, const int32
                              const LeafDesc* L, const int32_t* ids, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_dense, dim3(n), dim3(HL_BLOCK), 0, s, P, cst, perm, L, ids);
+  return post();
+}
+hipError_t launch_taylor(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids, int n,
+                         int32_t* rank, int r, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_taylor, dim3(n), dim3(HL_BLOCK), 0, s, P, perm, L, ids, rank, r);
   return post();
 }
 hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids,

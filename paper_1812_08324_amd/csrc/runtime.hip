@@ -2199,7 +2199,9 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     pd.c = prob->c;
     pd.s = prob->s;
     pd.lam = prob->lambda;
-    pd.C = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, prob->s);
+    pd.kernel = prob->kernel;
+    pd.eps2 = prob->eps2;
+    pd.C = prob->C > 0.0 ? prob->C : (prob->kernel == HLEVY_KERNEL_GAUSSIAN ? 1.0 : frac_constant(prob->dim, prob->s));
     pd.r0 = prob->r0;
     {
       AllocScope own(&op->actx);
@@ -2218,6 +2220,13 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     upload(A->lids, A->lr_ids, s);
     HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
                                A->dids.as<int32_t>(), (int)dense_ids.size(), s));
+    if (hp->taylor_rank > 0) {
+      // the fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3) go
+      // straight into G: no ACA, no truncation
+      HL_CHECK(launch_taylor(pd, op->ds.perm.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(),
+                             (int)A->lr_ids.size(), op->G.rank, hp->taylor_rank, s));
+      A->lr_ids.clear();
+    }
     // far field: ACA into scratch (truncated into G below)
     int64_t tot = 0;
     for (int l : A->lr_ids) {
@@ -3379,7 +3388,9 @@ static std::string srv_key(const hlevy_problem& p, const hlevy_hparams& hp, doub
   auto put = [&](const void* v, size_t n) { k.append(reinterpret_cast<const char*>(v), n); };
   put(&p.dim, 4);
   put(&p.n, 4);
-  for (double v : {p.lo, p.hi, p.a, p.b[0], p.dim == 2 ? p.b[1] : 0.0, p.c, p.s, p.lambda, p.C, p.r0}) put(&v, 8);
+  for (double v : {p.lo, p.hi, p.a, p.b[0], p.dim == 2 ? p.b[1] : 0.0, p.c, p.s, p.lambda, p.C, p.r0, p.eps2})
+    put(&v, 8);
+  put(&p.kernel, 4);
   put(&hp.leaf, 4);
   put(&hp.eta, 8);
   put(&hp.n_block, 4);
@@ -3388,6 +3399,7 @@ static std::string srv_key(const hlevy_problem& p, const hlevy_hparams& hp, doub
   put(&hp.gather_waves, 4);
   put(&hp.rank_bucket, 4);
   put(&hp.strict_rank_cap, 4);
+  put(&hp.taylor_rank, 4);
   put(&dt, 8);
   return k;
 }

@@ -140,13 +140,18 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   if (p.dim != 1 && p.dim != 2) err << "dim must be 1 or 2";
   else if (p.n < 2) err << "n must be >= 2";
   else if (!(p.hi > p.lo) || !std::isfinite(p.lo) || !std::isfinite(p.hi)) err << "need lo < hi (finite)";
-  else if (!(p.s > 0.0 && p.s < 1.0)) err << "s must lie in (0, 1)";
+  else if (p.kernel != HLEVY_KERNEL_TEMPERED && p.kernel != HLEVY_KERNEL_GAUSSIAN)
+    err << "kernel must be HLEVY_KERNEL_TEMPERED or HLEVY_KERNEL_GAUSSIAN";
+  else if (p.kernel == HLEVY_KERNEL_TEMPERED && !(p.s > 0.0 && p.s < 1.0)) err << "s must lie in (0, 1)";
+  else if (p.kernel == HLEVY_KERNEL_GAUSSIAN && (!(p.eps2 > 0.0) || !std::isfinite(p.eps2)))
+    err << "eps2 must be > 0 for the Gaussian kernel";
   else if (!(p.a >= 0.0) || !std::isfinite(p.a)) err << "a must be >= 0";
   else if (!(p.c <= 0.0) || !std::isfinite(p.c)) err << "c must be <= 0";
-  else if (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)) err << "lambda must be >= 0";
+  else if (p.kernel == HLEVY_KERNEL_TEMPERED && (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)))
+    err << "lambda must be >= 0";
   else if (!std::isfinite(p.b[0]) || !std::isfinite(p.b[1]) || !std::isfinite(p.C)) err << "non-finite drift or C";
-  else if (!(p.r0 > 0.0) || !std::isfinite(p.r0)) err << "r0 must be > 0";
-  else if (!(p.r0 < p.hi - p.lo)) err << "r0 must be smaller than the domain";
+  else if (p.kernel == HLEVY_KERNEL_TEMPERED && (!(p.r0 > 0.0) || !std::isfinite(p.r0))) err << "r0 must be > 0";
+  else if (p.kernel == HLEVY_KERNEL_TEMPERED && !(p.r0 < p.hi - p.lo)) err << "r0 must be smaller than the domain";
   else if (hp.leaf < 16 || hp.leaf > 64) err << "leaf must be in [16, 64]";
   else if (!(hp.eta > 0.0)) err << "eta must be > 0";
   else if (hp.n_block < 1) err << "n_block must be >= 1";
@@ -156,6 +161,11 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   else if (hp.rank_bucket != 0 && hp.rank_bucket != 8 && hp.rank_bucket != 16 && hp.rank_bucket != 32)
     err << "rank_bucket must be 0, 8, 16 or 32";
   else if (hp.strict_rank_cap != 0 && hp.strict_rank_cap != 1) err << "strict_rank_cap must be 0 or 1";
+  else if (hp.taylor_rank < 0 || hp.taylor_rank > hp.max_rank) err << "taylor_rank must be in [0, max_rank]";
+  else if (hp.taylor_rank > 0 && p.kernel != HLEVY_KERNEL_GAUSSIAN)
+    err << "taylor_rank needs the Gaussian kernel (the Taylor factors are those of exp(-eps2 |y|^2))";
+  else if (hp.taylor_rank == 0 && p.kernel == HLEVY_KERNEL_GAUSSIAN)
+    err << "the Gaussian kernel needs taylor_rank > 0 (partially pivoted ACA misses parts of its blocks)";
   if (!err.str().empty()) return err.str();
   int64_t N64 = p.dim == 1 ? (int64_t)p.n : (int64_t)p.n * p.n;
   if (N64 > (int64_t)1 << 26) return "N too large (max 2^26)";

@@ -24,13 +24,15 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "NOT_CONVERGE
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
                 ("a", C.c_double), ("b", C.c_double * 2), ("c", C.c_double), ("s", C.c_double),
-                ("lam", C.c_double), ("C", C.c_double), ("r0", C.c_double)]
+                ("lam", C.c_double), ("C", C.c_double), ("r0", C.c_double), ("kernel", C.c_int32),
+                ("pad", C.c_int32), ("eps2", C.c_double)]
 
 
 class HParams(C.Structure):
     _fields_ = [("leaf", C.c_int32), ("eta", C.c_double), ("n_block", C.c_int32),
                 ("aca_tol", C.c_double), ("max_rank", C.c_int32), ("gather_waves", C.c_int32),
-                ("rank_bucket", C.c_int32), ("strict_rank_cap", C.c_int32)]
+                ("rank_bucket", C.c_int32), ("strict_rank_cap", C.c_int32), ("taylor_rank", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Refine(C.Structure):
@@ -199,21 +201,27 @@ def _dptr(t, n=None):
     return C.c_void_p(t.data_ptr())
 
 
-def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0, r0=0.2) -> Problem:
+KERNEL_TEMPERED, KERNEL_GAUSSIAN = 0, 1
+
+
+def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0, r0=0.2, kernel=0,
+                 eps2=0.0) -> Problem:
     p = Problem()
     p.dim, p.n, p.lo, p.hi = int(dim), int(n), float(lo), float(hi)
     p.a, p.c, p.s, p.lam = float(a), float(c), float(s), float(lam)
     p.b[0], p.b[1] = float(b[0]), float(b[1] if len(b) > 1 else 0.0)
     p.C = -1.0 if C_ is None else float(C_)
     p.r0 = float(r0)
+    p.kernel, p.eps2 = int(kernel), float(eps2)
     return p
 
 
 def make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16, gather_waves=0, rank_bucket=0,
-                 strict_rank_cap=0) -> HParams:
+                 strict_rank_cap=0, taylor_rank=0) -> HParams:
     h = HParams()
     h.leaf, h.eta, h.n_block, h.aca_tol, h.max_rank = int(leaf), float(eta), int(n_block), float(aca_tol), int(max_rank)
     h.gather_waves, h.rank_bucket, h.strict_rank_cap = int(gather_waves), int(rank_bucket), int(strict_rank_cap)
+    h.taylor_rank = int(taylor_rank)
     return h
 
 

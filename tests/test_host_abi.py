@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(H):
     for name in names:
         assert hasattr(lib, name), name
     assert set(H.EXPORTS) == set(names)
-    assert H.lib.hlevy_abi_version() == 3
+    assert H.lib.hlevy_abi_version() == 4
 
 
 # ---------------------------------------------------------------------------
@@ -286,3 +286,19 @@ def test_autotune_cache_hit_needs_no_device(H, tmp_path):
     with pytest.raises(H.HlevyError) as e:      # invalid arguments are rejected before the cache
         H.autotune(prob, hp, -1.0, H.PREC_MIXED, 1e-6, 100, batch=8, cache=str(path), stream=0)
     assert e.value.status == -1
+
+
+def test_gaussian_validation(H):
+    """Gaussian kernel needs eps2 > 0 and the Taylor construction; taylor_rank
+    needs the Gaussian kernel and at most max_rank."""
+    ok = H.make_hparams(taylor_rank=10)
+    with pytest.raises(H.HlevyError, match="eps2"):
+        H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=0.0), ok)
+    with pytest.raises(H.HlevyError, match="taylor_rank"):
+        H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5), ok)
+    with pytest.raises(H.HlevyError, match="taylor_rank"):
+        H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=5.0),
+                    H.make_hparams(taylor_rank=20, max_rank=16))
+    with pytest.raises(H.HlevyError, match="taylor_rank > 0"):
+        H.plan_info(H.make_problem(2, 40, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=5.0),
+                    H.make_hparams(taylor_rank=0))
