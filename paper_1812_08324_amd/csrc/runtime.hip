@@ -353,6 +353,11 @@ struct Phase {
 struct ForkJoin {
   hipStream_t side = nullptr, deferred = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, dfork = nullptr, djoin = nullptr;
+  // plan segments are copied to the device on their own stream: a copy from
+  // pageable memory waits for its stream to drain, which on the caller's
+  // stream would hold the host until every earlier segment had run
+  hipStream_t upload = nullptr;
+  hipEvent_t uploaded = nullptr;
 };
 static ForkJoin& fork_join() {
   static thread_local std::map<int, ForkJoin> per_device;
@@ -366,6 +371,8 @@ static ForkJoin& fork_join() {
     HL_CHECK(hipEventCreateWithFlags(&f.join, hipEventDisableTiming));
     HL_CHECK(hipEventCreateWithFlags(&f.dfork, hipEventDisableTiming));
     HL_CHECK(hipEventCreateWithFlags(&f.djoin, hipEventDisableTiming));
+    HL_CHECK(hipStreamCreateWithFlags(&f.upload, hipStreamNonBlocking));
+    HL_CHECK(hipEventCreateWithFlags(&f.uploaded, hipEventDisableTiming));
   }
   return f;
 }
@@ -384,6 +391,33 @@ struct Plan {
   std::vector<GetrfItem> getrf;
   std::vector<LuInvItem> luinv;
   DevBuf djobs, dproj, dgath, ddprod, dterms, ddflush, dltg, dlgram, dlexp, dcopies, dgetrf, dluinv;
+
+  // Exchanges the whole plan (host arrays and device copies) with o.
+  void swap_contents(Plan& o) {
+    ph.swap(o.ph);
+    jobs.swap(o.jobs);
+    proj.swap(o.proj);
+    gath.swap(o.gath);
+    dprod.swap(o.dprod);
+    terms.swap(o.terms);
+    dflush.swap(o.dflush);
+    ltg.swap(o.ltg);
+    lgram.swap(o.lgram);
+    lexp.swap(o.lexp);
+    copies.swap(o.copies);
+    getrf.swap(o.getrf);
+    luinv.swap(o.luinv);
+    for (auto pr : {std::make_pair(&djobs, &o.djobs), std::make_pair(&dproj, &o.dproj),
+                    std::make_pair(&dgath, &o.dgath), std::make_pair(&ddprod, &o.ddprod),
+                    std::make_pair(&dterms, &o.dterms), std::make_pair(&ddflush, &o.ddflush),
+                    std::make_pair(&dltg, &o.dltg), std::make_pair(&dlgram, &o.dlgram),
+                    std::make_pair(&dlexp, &o.dlexp), std::make_pair(&dcopies, &o.dcopies),
+                    std::make_pair(&dgetrf, &o.dgetrf), std::make_pair(&dluinv, &o.dluinv)}) {
+      std::swap(pr.first->p, pr.second->p);
+      std::swap(pr.first->bytes, pr.second->bytes);
+      std::swap(pr.first->ctx, pr.second->ctx);
+    }
+  }
 
   // Host-side check of the plan before it reaches the device: every phase's
   // item range lies inside its array, every term of a rounded addition or
@@ -602,6 +636,12 @@ struct Builder {
   };
   WsStack::Mark mk{};
   bool in_batch = false;
+  // inside a PH_DEFER_BEGIN .. PH_DEFER_END region
+  bool in_defer = false;
+  // called after every batch outside a deferred region: the point where the
+  // plan built so far may be handed to the device (nothing built later
+  // refers to its items by index)
+  std::function<void()> after_batch;
 
   Builder(Plan& p, WsStack& w, const double* id, int32_t* ovf, double t)
       : P(p), ws(w), ident(id), overflow(ovf), tol(t) {}
@@ -1116,11 +1156,16 @@ struct Builder {
     pterms.clear();
     if (!keep_ws) ws.release(mk);
     in_batch = false;
+    if (after_batch && !in_defer && !keep_ws) after_batch();
     return mk;
   }
 
   void release_kept(const WsStack::Mark& m) { ws.release(m); }
-  void phase_marker(int type) { P.ph.push_back(Phase{type, 0, 0, 0, 0, 0, 0, 0.0}); }
+  void phase_marker(int type) {
+    P.ph.push_back(Phase{type, 0, 0, 0, 0, 0, 0, 0.0});
+    if (type == PH_DEFER_BEGIN) in_defer = true;
+    if (type == PH_DEFER_END) in_defer = false;
+  }
 
   // Copies of leaves (add_copies) between copy_begin() and copy_end() go to
   // one phase.
@@ -2008,7 +2053,29 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
       roots.push_back({&w->ctx, 0});
       H = std::max(H, lu_height(w->ctx, 0));
     }
+    // The plan goes to the device in segments at batch boundaries while the
+    // rest is being built, so the device starts after the first segment's
+    // planning instead of the whole plan's.  Segments run in order on the
+    // same streams as one plan would (the deferred stream's join and the
+    // workspace reuse keep their order); each stays alive until the end.
+    std::vector<std::unique_ptr<Plan>> segs;
+    size_t next_flush = 64;
+    auto launch_segment = [&]() {
+      ForkJoin& fj = fork_join();
+      P.upload_all(fj.upload);
+      HL_CHECK(hipEventRecord(fj.uploaded, fj.upload));
+      HL_CHECK(hipStreamWaitEvent(s, fj.uploaded, 0));
+      P.run(zpb.as<int32_t>(), s);
+    };
+    B.after_batch = [&]() {
+      if (P.ph.size() < next_flush) return;
+      launch_segment();
+      segs.push_back(std::make_unique<Plan>());
+      P.swap_contents(*segs.back());
+      next_flush = 1536;
+    };
     hluinv_joint(B, roots, H);
+    B.after_batch = nullptr;
     // inverse factors in the operator's block format: dense leaf-level
     // blocks of the workspace are truncated back to low rank
     cb = B.copy_begin();
@@ -2064,17 +2131,16 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
       }
     B.emit_lflush(tgs, tl, lu_tol);
     const double t1 = now_s();
-    P.upload_all(s);
-    HL_CHECK(hipStreamSynchronize(s));
-    const double t2 = now_s();
-    P.run(zpb.as<int32_t>(), s);
+    const double t2 = t1;
+    launch_segment();
     const double t3 = now_s();
     HL_CHECK(hipStreamSynchronize(s));
     const double t4 = now_s();
     if (verbose())
-      std::fprintf(stderr, "[hlevy] factor %zu problem(s): alloc %.3fs plan %.3fs (%zu phases, %zu lr targets, "
-                   "ws peak %.1f MB) upload %.3fs enqueue %.3fs device-tail %.3fs\n", fs.size(), t0 - ta, t1 - t0,
-                   P.ph.size(), P.ltg.size(), ws.peak / 1048576.0, t2 - t1, t3 - t2, t4 - t3);
+      std::fprintf(stderr, "[hlevy] factor %zu problem(s): alloc %.3fs plan+early segments %.3fs (%zu segments "
+                   "before the last: its %zu phases, %zu lr targets, ws peak %.1f MB) upload %.3fs enqueue %.3fs "
+                   "device-tail %.3fs\n", fs.size(), t0 - ta, t1 - t0, segs.size(), P.ph.size(), P.ltg.size(),
+                   ws.peak / 1048576.0, t2 - t1, t3 - t2, t4 - t3);
     tpost = now_s();
   }
   int32_t zp = 0, ovf = 0;
