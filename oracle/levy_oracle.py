@@ -38,6 +38,13 @@ Readings of the paper taken here (the paper is garbled or silent on them):
   the zero-exterior condition (Sec. 4, closing remark).
 * In 2D the singularity subtraction uses ``int rho nu y_i y_j = delta_ij C2``
   (radial kernel, square window), giving the 5-point Laplacian.
+* Asymmetric 1D measures (rate lam for y > 0, lam_neg for y < 0): the
+  generator keeps the compensator of equ:I1approx, L u = int (u(x+y) - u(x)
+  - rho(y) y u'(x)) nu(y) dy, so the u' sum of I1 is not added back; it is
+  discretised with the trapezoid weights and the central difference
+  (u_{i+1} - u_{i-1}) / (2h) (the printed /h without weights is
+  dimensionally off).  Another compensator differs by a drift, which the
+  caller can fold into b.
 * The closed-form solution of the 1D fractional Poisson problem (Sec. 5.3):
   the paper prints the factor 2^{2s} Gamma(1+s) Gamma((1+2s)/2)/Gamma(1/2)
   in front of (1-x^2)^s.  That factor is (-Delta)^s of (1-x^2)^s (the ball
@@ -57,7 +64,7 @@ __all__ = [
     "Problem", "frac_const", "ball_const", "gauss_const", "grid", "h_of",
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
     "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
-    "taylor_terms", "taylor_factors",
+    "taylor_terms", "taylor_factors", "kernel_nu_signed",
 ]
 
 
@@ -110,6 +117,7 @@ class Problem:
     jumps: bool = True           # False drops the jump operator (nu = 0)
     kernel: str = "tempered"     # or "gaussian"
     eps2: float = 0.0            # Gaussian kernel: nu(y) = C exp(-eps2 |y|^2)
+    lam_neg: float | None = None  # 1D tempered kernel: tempering rate for y < 0 (None: lam, symmetric)
 
     @property
     def N(self) -> int:
@@ -135,6 +143,15 @@ def grid(p: Problem) -> np.ndarray:
         return x1[:, None]
     X, Y = np.meshgrid(x1, x1, indexing="ij")
     return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def kernel_nu_signed(p: Problem, y):
+    """The 1D tempered kernel at the signed jump y != 0: rate lam for y > 0,
+    lam_neg for y < 0 (an asymmetric, CGMY-type measure when they differ)."""
+    y = np.asarray(y, dtype=np.float64)
+    lneg = p.lam if p.lam_neg is None else p.lam_neg
+    rate = np.where(y > 0, p.lam, lneg)
+    return p.Cval * np.exp(-rate * np.abs(y)) / np.abs(y) ** (1.0 + 2.0 * p.s)
 
 
 def kernel_nu(p: Problem, r):
@@ -208,6 +225,29 @@ def quadrature_constants(p: Problem) -> dict:
         return dict(S0=S0, S2=0.0, C2=0.0, T=0.0, h=h, NW=NW, m=m, r=r, LW=LW)
     k = np.arange(-NW, NW + 1)
     nz = k != 0
+    if d == 1 and p.lam_neg is not None:
+        # asymmetric measure (NEXT-3 reading): every sum and integral takes
+        # each side with its own rate; S1 = sum' W_k rho_k nu(kh) (kh) is the
+        # coefficient of the u' term of equ:I1approx, zero for symmetric nu
+        kk = k[nz]
+        w = _trap_w(kk, NW, h)
+        nu = kernel_nu_signed(p, kk * h)
+        rw = _rho_w(kk, m)
+        S0 = math.fsum(w * nu)
+        S2 = math.fsum(w * rw * nu * (kk * h) ** 2)
+        S1 = math.fsum(w * rw * nu * (kk * h))
+        a2 = 2.0 - 2.0 * s
+        C2 = T = 0.0
+        for rate in (lam, p.lam_neg):
+            if rate == 0.0:
+                C2 += C * r ** a2 / a2
+                T += C * LW ** (-2.0 * s) / (2.0 * s)
+            else:
+                C2 += C * rate ** (-a2) * sp.gammainc(a2, rate * r) * sp.gamma(a2)
+                val, _ = integrate.quad(lambda y: np.exp(-rate * y) * y ** (-1.0 - 2.0 * s),
+                                        LW, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
+                T += C * val
+        return dict(S0=S0, S2=S2, C2=C2, T=T, S1=S1, h=h, NW=NW, m=m, r=r, LW=LW)
     if d == 1:
         kk = k[nz]
         w = _trap_w(kk, NW, h)
@@ -281,11 +321,16 @@ def generator_row(p: Problem, i: int, consts: dict | None = None) -> np.ndarray:
         k = j - i
         if p.jumps:
             off = k != 0
-            row[off] = h * kernel_nu(p, np.abs(k[off]) * h)
+            if p.lam_neg is None:
+                row[off] = h * kernel_nu(p, np.abs(k[off]) * h)
+            else:
+                row[off] = h * kernel_nu_signed(p, k[off] * h)
+        # the u' term of equ:I1approx: -S1 u'(x_i) by the central difference
+        s1 = consts.get("S1", 0.0)
         for kk, sgn in ((-1, -1.0), (1, 1.0)):
             jj = i + kk
             if 0 <= jj < n:
-                row[jj] += (beta + p.a) / h ** 2 + sgn * p.b[0] / (2.0 * h)
+                row[jj] += (beta + p.a) / h ** 2 + sgn * (p.b[0] - s1) / (2.0 * h)
         row[i] = -consts["S0"] - consts["T"] - 2.0 * (beta + p.a) / h ** 2 + p.c
         return row
     # 2D, index = p1*n + q1 (first coordinate slowest)

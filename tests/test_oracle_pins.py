@@ -513,3 +513,48 @@ def test_gaussian_time_convergence_matches_paper_table():
             assert ours[a] / ours[b] == pytest.approx(paper[a] / paper[b], rel=5e-3)
     scale = ours / paper
     assert np.ptp(scale) <= 2e-3 * scale.mean() and 0.16 < scale.mean() < 0.18, scale
+
+
+# ---------------------------------------------------------------------------
+# Asymmetric 1D tempered measure (NEXT-3 reading: compensator rho)
+# ---------------------------------------------------------------------------
+def test_asymmetric_measure_reduces_to_symmetric():
+    """lam_neg = lam gives the symmetric generator exactly (S1 = 0)."""
+    q = Problem(dim=1, n=200, s=0.6, lam=1.0, lam_neg=1.0, C=0.3)
+    r = Problem(dim=1, n=200, s=0.6, lam=1.0, C=0.3)
+    assert quadrature_constants(q)["S1"] == 0.0
+    assert np.array_equal(generator_dense(q), generator_dense(r))
+
+
+def test_asymmetric_generator_converges_to_quadrature():
+    """Rates 0.5 (y > 0) and 3 (y < 0), s = 0.6: the generator applied to a
+    Gaussian bump (zero at the boundary to 1e-10) converges at second order
+    to the direct quadrature of int (u(x+y) - u(x) - rho(y) y u'(x)) nu(y) dy
+    with rho the indicator of |y| <= r0 (r0 a grid multiple), at five interior
+    points.  A wrong sign or factor of the u' term (S1) breaks the order."""
+    import warnings
+    s, lp, ln, C, r0 = 0.6, 0.5, 3.0, 0.4, 0.25
+    u = lambda x: np.exp(-(x / 0.2) ** 2)
+    du = lambda x: -2.0 * x / 0.04 * np.exp(-(x / 0.2) ** 2)
+
+    def Lu(x):
+        nu = lambda y: C * np.exp(-(lp if y > 0 else ln) * abs(y)) / abs(y) ** (1.0 + 2.0 * s)
+        f = lambda y: (u(x + y) - u(x) - (y * du(x) if abs(y) <= r0 else 0.0)) * nu(y)
+        tot = 0.0
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            for a, b in ((-np.inf, -r0), (-r0, 0.0), (0.0, r0), (r0, np.inf)):
+                tot += integrate.quad(f, a, b, epsabs=1e-14, epsrel=1e-12, limit=400)[0]
+        return tot
+
+    xs = [-0.3, -0.1, 0.0, 0.15, 0.3]
+    ref = np.array([Lu(x) for x in xs])
+    errs = []
+    for k in (20, 40, 80):
+        p = Problem(dim=1, n=8 * k - 1, lo=-1.0, hi=1.0, s=s, lam=lp, lam_neg=ln, C=C, r0=r0)
+        x = grid(p)[:, 0]
+        Gu = generator_dense(p) @ u(x)
+        idx = [int(np.argmin(np.abs(x - xx))) for xx in xs]
+        assert np.allclose(x[idx], xs, atol=1e-12)
+        errs.append(np.abs(Gu[idx] - ref).max() / np.abs(ref).max())
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5 and errs[2] < 2e-4, errs
