@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HLEVY_ABI_VERSION 4
+#define HLEVY_ABI_VERSION 5
 
 typedef enum {
   HLEVY_OK = 0,
@@ -64,7 +64,13 @@ typedef enum {
  * discretised by the plain trapezoid rule of Sec. 3.2 (eqs. equ:dl and
  * equ:Aij): off-diagonal entries h^d nu(x_j - x_i), diagonal
  * -h^d sum over the lattice without 0 of nu(kh) (u = 0 outside the box). */
-typedef enum { HLEVY_KERNEL_TEMPERED = 0, HLEVY_KERNEL_GAUSSIAN = 1 } hlevy_kernel;
+typedef enum { HLEVY_KERNEL_TEMPERED = 0, HLEVY_KERNEL_GAUSSIAN = 1, HLEVY_KERNEL_TEMPERED_ASYM = 2 } hlevy_kernel;
+/* TEMPERED_ASYM (1D only): the tempered kernel with rate lambda for jumps
+ * y > 0 and lambda_neg for y < 0 (a CGMY-type measure; Sec. 2 and Sec. 4 allow
+ * asymmetric measures).  The generator keeps the compensator of
+ * equ:I1approx, int (u(x+y) - u(x) - rho(y) y u'(x)) nu(y) dy, whose u' sum
+ * S1 = sum' w_k rho_k nu(kh) kh no longer vanishes: it enters the nearest
+ * neighbours as a drift -S1 (central difference). */
 
 /* The model problem (Sec. 3.1 eq. equ:ut; Sec. 4 eqs. equ:ny2 and the
  * zero-exterior remark).  Domain: the box [lo, hi]^dim, u = 0 outside. */
@@ -82,6 +88,7 @@ typedef struct {
   int32_t kernel;    /* hlevy_kernel; GAUSSIAN ignores s, lambda and r0, and C <= 0 selects 1 */
   int32_t pad;
   double eps2;       /* GAUSSIAN: eps^2 > 0 of nu(y) = C exp(-eps2 |y|^2) */
+  double lambda_neg; /* TEMPERED_ASYM: tempering rate >= 0 of the jumps y < 0 (lambda: y > 0) */
 } hlevy_problem;
 
 /* H-matrix parameters (App. B.1): leaf size N_min, admissibility eta
@@ -233,9 +240,9 @@ hlevy_status hlevy_assemble(const hlevy_problem* prob, const hlevy_hparams* hp,
 hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hparams* hps, int32_t count,
                                     const hlevy_allocator* alloc, void* stream, hlevy_op** out);
 
-/* Copy the four quadrature constants S0, S2, C2, T (Sec. 4) to host `out`.
- * Synchronises `stream`. */
-hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream);
+/* Copy the quadrature constants S0, S2, C2, T (Sec. 4) and S1 (the u' sum of
+ * an asymmetric measure, 0 otherwise) to host `out`.  Synchronises `stream`. */
+hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream);
 
 /* Storage summary of the assembled operator.  Synchronises `stream`. */
 hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream);

@@ -161,8 +161,9 @@ struct GetrfItem {
 struct ProblemDev {
   int32_t dim, n, N;
   double h, a, b0, b1, c, s, lam, C, r0;
-  int32_t kernel, pad;   // HLEVY_KERNEL_TEMPERED or HLEVY_KERNEL_GAUSSIAN
+  int32_t kernel, pad;   // hlevy_kernel
   double eps2;           // Gaussian: nu(r) = C exp(-eps2 r^2)
+  double lam_neg;        // asymmetric tempered kernel: rate of the jumps y < 0 (lam: y > 0)
 };
 
 }  // namespace hl

@@ -118,6 +118,14 @@ __device__ __forceinline__ double nu_at(const ProblemDev& P, double r) {
   if (P.kernel == HLEVY_KERNEL_GAUSSIAN) return P.C * exp(-P.eps2 * r * r);
   return P.C * exp(-P.lam * r) / pow(r, (double)P.dim + 2.0 * P.s);
 }
+// nu at the 1D jump y = k h (k != 0): the asymmetric kernel takes the rate
+// of its side, every other kernel is even
+__device__ __forceinline__ double nu_jump1(const ProblemDev& P, int k) {
+  const double r = fabs((double)k) * P.h;
+  if (P.kernel == HLEVY_KERNEL_TEMPERED_ASYM)
+    return P.C * exp(-(k > 0 ? P.lam : P.lam_neg) * r) / pow(r, 1.0 + 2.0 * P.s);
+  return nu_at(P, r);
+}
 
 // lower incomplete gamma gamma(a, x) by its power series (x moderate)
 __device__ double lower_gamma(double a, double x) {
@@ -207,6 +215,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
       out[1] = 0.0;
       out[2] = 0.0;
       out[3] = 0.0;
+      out[4] = 0.0;
     }
     return;
   }
@@ -220,7 +229,21 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
     if (fabs(s) >= fabs(v)) c += (s - t) + v; else c += (v - t) + s;
     s = t;
   };
-  if (P.dim == 1) {
+  double s1 = 0.0, s1c = 0.0;   // u' sum of an asymmetric measure
+  if (P.dim == 1 && P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) {
+    for (int k = 1 + threadIdx.x; k <= NW; k += blockDim.x) {
+      double w = (k == NW) ? 0.5 * h : h;
+      const double np = nu_jump1(P, k), nn = nu_jump1(P, -k);
+      acc(s0, s0c, w * np);
+      acc(s0, s0c, w * nn);
+      if (k <= m) {
+        double rho = (k < m) ? 1.0 : 0.5;
+        acc(s2, s2c, w * rho * np * (k * h) * (k * h));
+        acc(s2, s2c, w * rho * nn * (k * h) * (k * h));
+        acc(s1, s1c, w * rho * (np - nn) * (k * h));
+      }
+    }
+  } else if (P.dim == 1) {
     for (int k = 1 + threadIdx.x; k <= NW; k += blockDim.x) {
       double w = (k == NW) ? 0.5 * h : h;
       double nu = nu_at(P, k * h);
@@ -248,12 +271,25 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
   }
   double S0 = block_sum(s0, red) + block_sum(s0c, red);
   double S2 = block_sum(s2, red) + block_sum(s2c, red);
+  const double S1 = block_sum(s1, red) + block_sum(s1c, red);
   if (threadIdx.x < 32) gauss_legendre(32, threadIdx.x, &glx[threadIdx.x], &glw[threadIdx.x]);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double s = P.s, C = P.C, lam = P.lam, a2 = 2.0 - 2.0 * s;
     double C2 = 0.0, T = 0.0;
-    if (P.dim == 1) {
+    if (P.dim == 1 && P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) {
+      // each side with its own rate
+      for (int side = 0; side < 2; ++side) {
+        const double rate = side == 0 ? lam : P.lam_neg;
+        if (rate == 0.0) {
+          C2 += C * pow(r, a2) / a2;
+          T += C * pow(LW, -2.0 * s) / (2.0 * s);
+        } else {
+          C2 += C * pow(rate, -a2) * lower_gamma(a2, rate * r);
+          T += C * pow(rate, 2.0 * s) * upper_gamma(-2.0 * s, rate * LW);
+        }
+      }
+    } else if (P.dim == 1) {
       if (lam == 0.0) {
         C2 = 2.0 * C * pow(r, a2) / a2;
         T = C * pow(LW, -2.0 * s) / s;
@@ -288,6 +324,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
     out[1] = S2;
     out[2] = C2;
     out[3] = T;
+    out[4] = S1;
   }
 }
 
@@ -306,11 +343,19 @@ __device__ __forceinline__ double gen_entry(const ProblemDev& P, const double* c
   }
   if (k1 == 0 && k2 == 0)
     return -cst[0] - cst[3] - 2.0 * P.dim * (beta + P.a) / (h * h) + P.c;
-  double rr = h * sqrt((double)k1 * k1 + (double)k2 * k2);
-  double v = (P.dim == 1 ? h : h * h) * nu_at(P, rr);
+  double v;
+  if (P.dim == 1) {
+    v = h * nu_jump1(P, k1);
+  } else {
+    const double rr = h * sqrt((double)k1 * k1 + (double)k2 * k2);
+    v = h * h * nu_at(P, rr);
+  }
   if (abs(k1) + abs(k2) == 1) {
     v += (beta + P.a) / (h * h);
-    if (k1 != 0) v += (k1 > 0 ? 1.0 : -1.0) * P.b0 / (2.0 * h);
+    // drift by the central difference; an asymmetric measure adds -S1 (the
+    // u' sum of equ:I1approx, cst[4], zero otherwise)
+    const double b0 = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM ? P.b0 - cst[4] : P.b0;
+    if (k1 != 0) v += (k1 > 0 ? 1.0 : -1.0) * b0 / (2.0 * h);
     else v += (k2 > 0 ? 1.0 : -1.0) * P.b1 / (2.0 * h);
   }
   return v;
@@ -326,8 +371,9 @@ __device__ __forceinline__ double far_entry(const ProblemDev& P, const int32_t* 
     k1 = pj / P.n - pi / P.n;
     k2 = pj % P.n - pi % P.n;
   }
+  if (P.dim == 1) return P.h * nu_jump1(P, k1);
   double rr = P.h * sqrt((double)k1 * k1 + (double)k2 * k2);
-  return (P.dim == 1 ? P.h : P.h * P.h) * nu_at(P, rr);
+  return P.h * P.h * nu_at(P, rr);
 }
 
 // Fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3), one block per

@@ -1598,7 +1598,7 @@ static size_t footprint_bytes(const Structure& S, int kcap, int prec) {
   size_t b = 0;
   // structure lists, constants, overflow counter
   b += 2 * round8((P + 1) * 4) + round8(S.rowidx.size() * 4) + round8(S.colidx.size() * 4) + 2 * round8(P * 4) +
-       round8(N * 4) + 64 * 64 * sizeof(double) + 32 + 8;
+       round8(N * 4) + 64 * 64 * sizeof(double) + 40 + 8;
   HMat g;
   g.layout(S, kcap, FULL, false);
   b += hmat(g) + 2 * N * sizeof(double) + mvplan_bytes_bound(S, g, MV_FMT_F64);
@@ -2267,12 +2267,13 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     pd.lam = prob->lambda;
     pd.kernel = prob->kernel;
     pd.eps2 = prob->eps2;
+    pd.lam_neg = prob->lambda_neg;
     pd.C = prob->C > 0.0 ? prob->C : (prob->kernel == HLEVY_KERNEL_GAUSSIAN ? 1.0 : frac_constant(prob->dim, prob->s));
     pd.r0 = prob->r0;
     {
       AllocScope own(&op->actx);
       op->ds.create(S, s);
-      op->cst.alloc(4 * sizeof(double));
+      op->cst.alloc(5 * sizeof(double));
       op->ovf.alloc(sizeof(int32_t));
       op->G.create(S, hp->max_rank, FULL, s);
     }
@@ -2527,10 +2528,10 @@ hlevy_status hlevy_fac_info(const hlevy_fac* f, hlevy_fac_info_t* out, void* str
   });
 }
 
-hlevy_status hlevy_op_constants(const hlevy_op* op, double out[4], void* stream) {
+hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream) {
   if (!op || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   return guarded([&]() -> hlevy_status {
-    HL_CHECK(hipMemcpyAsync(out, op->cst.p, 4 * sizeof(double), hipMemcpyDeviceToHost, as_stream(stream)));
+    HL_CHECK(hipMemcpyAsync(out, op->cst.p, 5 * sizeof(double), hipMemcpyDeviceToHost, as_stream(stream)));
     HL_CHECK(hipStreamSynchronize(as_stream(stream)));
     return HLEVY_OK;
   });
@@ -3454,7 +3455,8 @@ static std::string srv_key(const hlevy_problem& p, const hlevy_hparams& hp, doub
   auto put = [&](const void* v, size_t n) { k.append(reinterpret_cast<const char*>(v), n); };
   put(&p.dim, 4);
   put(&p.n, 4);
-  for (double v : {p.lo, p.hi, p.a, p.b[0], p.dim == 2 ? p.b[1] : 0.0, p.c, p.s, p.lambda, p.C, p.r0, p.eps2})
+  for (double v : {p.lo, p.hi, p.a, p.b[0], p.dim == 2 ? p.b[1] : 0.0, p.c, p.s, p.lambda, p.C, p.r0, p.eps2,
+                   p.lambda_neg})
     put(&v, 8);
   put(&p.kernel, 4);
   put(&hp.leaf, 4);

@@ -140,18 +140,22 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   if (p.dim != 1 && p.dim != 2) err << "dim must be 1 or 2";
   else if (p.n < 2) err << "n must be >= 2";
   else if (!(p.hi > p.lo) || !std::isfinite(p.lo) || !std::isfinite(p.hi)) err << "need lo < hi (finite)";
-  else if (p.kernel != HLEVY_KERNEL_TEMPERED && p.kernel != HLEVY_KERNEL_GAUSSIAN)
-    err << "kernel must be HLEVY_KERNEL_TEMPERED or HLEVY_KERNEL_GAUSSIAN";
-  else if (p.kernel == HLEVY_KERNEL_TEMPERED && !(p.s > 0.0 && p.s < 1.0)) err << "s must lie in (0, 1)";
+  else if (p.kernel != HLEVY_KERNEL_TEMPERED && p.kernel != HLEVY_KERNEL_GAUSSIAN &&
+           p.kernel != HLEVY_KERNEL_TEMPERED_ASYM)
+    err << "kernel must be HLEVY_KERNEL_TEMPERED, HLEVY_KERNEL_GAUSSIAN or HLEVY_KERNEL_TEMPERED_ASYM";
+  else if (p.kernel == HLEVY_KERNEL_TEMPERED_ASYM && p.dim != 1) err << "the asymmetric kernel is 1D only";
+  else if (p.kernel == HLEVY_KERNEL_TEMPERED_ASYM && (!(p.lambda_neg >= 0.0) || !std::isfinite(p.lambda_neg)))
+    err << "lambda_neg must be >= 0";
+  else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && !(p.s > 0.0 && p.s < 1.0)) err << "s must lie in (0, 1)";
   else if (p.kernel == HLEVY_KERNEL_GAUSSIAN && (!(p.eps2 > 0.0) || !std::isfinite(p.eps2)))
     err << "eps2 must be > 0 for the Gaussian kernel";
   else if (!(p.a >= 0.0) || !std::isfinite(p.a)) err << "a must be >= 0";
   else if (!(p.c <= 0.0) || !std::isfinite(p.c)) err << "c must be <= 0";
-  else if (p.kernel == HLEVY_KERNEL_TEMPERED && (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)))
+  else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && (!(p.lambda >= 0.0) || !std::isfinite(p.lambda)))
     err << "lambda must be >= 0";
   else if (!std::isfinite(p.b[0]) || !std::isfinite(p.b[1]) || !std::isfinite(p.C)) err << "non-finite drift or C";
-  else if (p.kernel == HLEVY_KERNEL_TEMPERED && (!(p.r0 > 0.0) || !std::isfinite(p.r0))) err << "r0 must be > 0";
-  else if (p.kernel == HLEVY_KERNEL_TEMPERED && !(p.r0 < p.hi - p.lo)) err << "r0 must be smaller than the domain";
+  else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && (!(p.r0 > 0.0) || !std::isfinite(p.r0))) err << "r0 must be > 0";
+  else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && !(p.r0 < p.hi - p.lo)) err << "r0 must be smaller than the domain";
   else if (hp.leaf < 16 || hp.leaf > 64) err << "leaf must be in [16, 64]";
   else if (!(hp.eta > 0.0)) err << "eta must be > 0";
   else if (hp.n_block < 1) err << "n_block must be >= 1";

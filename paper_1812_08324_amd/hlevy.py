@@ -25,7 +25,7 @@ class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
                 ("a", C.c_double), ("b", C.c_double * 2), ("c", C.c_double), ("s", C.c_double),
                 ("lam", C.c_double), ("C", C.c_double), ("r0", C.c_double), ("kernel", C.c_int32),
-                ("pad", C.c_int32), ("eps2", C.c_double)]
+                ("pad", C.c_int32), ("eps2", C.c_double), ("lam_neg", C.c_double)]
 
 
 class HParams(C.Structure):
@@ -201,11 +201,13 @@ def _dptr(t, n=None):
     return C.c_void_p(t.data_ptr())
 
 
-KERNEL_TEMPERED, KERNEL_GAUSSIAN = 0, 1
+KERNEL_TEMPERED, KERNEL_GAUSSIAN, KERNEL_TEMPERED_ASYM = 0, 1, 2
 
 
 def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0, r0=0.2, kernel=0,
-                 eps2=0.0) -> Problem:
+                 eps2=0.0, lam_neg=None) -> Problem:
+    """lam_neg: the tempering rate of the jumps y < 0 (1D); given, the kernel
+    is HLEVY_KERNEL_TEMPERED_ASYM with lam for y > 0."""
     p = Problem()
     p.dim, p.n, p.lo, p.hi = int(dim), int(n), float(lo), float(hi)
     p.a, p.c, p.s, p.lam = float(a), float(c), float(s), float(lam)
@@ -213,6 +215,8 @@ def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0
     p.C = -1.0 if C_ is None else float(C_)
     p.r0 = float(r0)
     p.kernel, p.eps2 = int(kernel), float(eps2)
+    if lam_neg is not None:
+        p.kernel, p.lam_neg = KERNEL_TEMPERED_ASYM, float(lam_neg)
     return p
 
 
@@ -352,7 +356,8 @@ def assemble_batched(probs, hps, stream=None) -> list:
 
 
 def op_constants(op: Op, stream=None):
-    out = (C.c_double * 4)()
+    """[S0, S2, C2, T, S1]."""
+    out = (C.c_double * 5)()
     _check(lib.hlevy_op_constants(op.h, out, _stream(stream)), "hlevy_op_constants")
     return list(out)
 

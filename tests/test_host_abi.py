@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(H):
     for name in names:
         assert hasattr(lib, name), name
     assert set(H.EXPORTS) == set(names)
-    assert H.lib.hlevy_abi_version() == 4
+    assert H.lib.hlevy_abi_version() == 5
 
 
 # ---------------------------------------------------------------------------
@@ -302,3 +302,13 @@ def test_gaussian_validation(H):
     with pytest.raises(H.HlevyError, match="taylor_rank > 0"):
         H.plan_info(H.make_problem(2, 40, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=5.0),
                     H.make_hparams(taylor_rank=0))
+
+
+def test_asymmetric_kernel_validation(H):
+    """The asymmetric tempered kernel is 1D only and needs lambda_neg >= 0."""
+    hp = H.make_hparams()
+    H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, lam=0.5, lam_neg=3.0), hp)
+    with pytest.raises(H.HlevyError, match="1D only"):
+        H.plan_info(H.make_problem(2, 40, 0.0, 1.0, 0.5, lam=0.5, lam_neg=3.0), hp)
+    with pytest.raises(H.HlevyError, match="lambda_neg"):
+        H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, lam=0.5, lam_neg=-1.0), hp)
