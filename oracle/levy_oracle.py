@@ -64,7 +64,7 @@ __all__ = [
     "Problem", "frac_const", "ball_const", "gauss_const", "grid", "h_of",
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
     "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
-    "taylor_terms", "taylor_factors", "kernel_nu_signed",
+    "taylor_terms", "taylor_factors", "kernel_nu_signed", "exterior_forcing",
 ]
 
 
@@ -356,6 +356,50 @@ def generator_dense(p: Problem) -> np.ndarray:
     for i in range(p.N):
         G[i] = generator_row(p, i, consts)
     return G
+
+
+# ---------------------------------------------------------------------------
+# Non-zero exterior (Sec. 4: the window terms that reach outside the box)
+# ---------------------------------------------------------------------------
+def exterior_forcing(p: Problem, u_ext: np.ndarray) -> np.ndarray:
+    """The generator's action on exterior values, 1D: with u = u_ext outside
+    the box, row i of the scheme (equ:I1approx - equ:I3approx) also takes
+    the window offsets k (|k| <= NW = n + 1) whose point x_i + kh lies
+    outside, each with its trapezoid weight W_k nu(kh), and the local terms
+    (diffusion, drift, the u'' and u' corrections) on the exterior
+    neighbours x_{-1} = lo and x_n = hi.  u_ext: the NW values left of the
+    box (lattice indices -NW .. -1, ascending) followed by the NW values
+    right of it (indices n .. 2n).  Returns g (length n) such that the
+    scheme on the box with this exterior is G u + g.  The far field beyond
+    the window (|y| > L_W) is not included: its integral of u_ext is the
+    caller's (its -u T part is in the diagonal of G)."""
+    if p.dim != 1:
+        raise ValueError("exterior forcing is 1D")
+    c = quadrature_constants(p)
+    h, NW, n = c["h"], c["NW"], p.n
+    beta = 0.5 * (c["C2"] - c["S2"])
+    s1 = c.get("S1", 0.0)
+    u_ext = np.asarray(u_ext, dtype=np.float64)
+    if u_ext.shape != (2 * NW,):
+        raise ValueError("u_ext holds 2 (n + 1) values")
+    g = np.zeros(n)
+    for i in range(n):
+        acc = 0.0
+        for q in range(2 * NW):
+            j = q - NW if q < NW else n + (q - NW)      # lattice index of the exterior point
+            k = j - i
+            if abs(k) > NW:
+                continue
+            w = 0.5 * h if abs(k) == NW else h
+            nu = (kernel_nu_signed(p, k * h) if p.lam_neg is not None else kernel_nu(p, abs(k) * h))
+            v = w * float(nu)
+            if k == -1:
+                v += (beta + p.a) / h ** 2 - (p.b[0] - s1) / (2.0 * h)
+            if k == 1:
+                v += (beta + p.a) / h ** 2 + (p.b[0] - s1) / (2.0 * h)
+            acc += v * u_ext[q]
+        g[i] = acc
+    return g
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,7 @@ import scipy.special as sp
 from oracle.levy_oracle import (Problem, ball_const, cn_run, cn_run_lean, frac_const,
                                 gauss_const, generator_dense, generator_row,
                                 grid, h_of, kernel_nu, quadrature_constants, steady_solve, steady_residual,
-                                fractional_poisson_exact, taylor_factors, taylor_terms)
+                                fractional_poisson_exact, taylor_factors, taylor_terms, exterior_forcing)
 
 
 def _order(e1, e2):
@@ -558,3 +558,50 @@ def test_asymmetric_generator_converges_to_quadrature():
         assert np.allclose(x[idx], xs, atol=1e-12)
         errs.append(np.abs(Gu[idx] - ref).max() / np.abs(ref).max())
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5 and errs[2] < 2e-4, errs
+
+
+@pytest.mark.parametrize("asym", [False, True])
+def test_exterior_forcing_of_a_constant(asym):
+    """A constant u = 1 inside and outside: the generator annihilates it up
+    to the part of the measure beyond the window, so G 1 + g(1) = -T in every
+    row (the window offsets and local terms of the interior and the exterior
+    together are the whole lattice sum S0).  With drift, diffusion and, for
+    the asymmetric measure, its u' term."""
+    kw = dict(lam=0.5, lam_neg=3.0) if asym else dict(lam=1.0)
+    p = Problem(dim=1, n=120, lo=-1.0, hi=1.0, s=0.6, C=0.4, a=0.05, b=(0.3, 0.0), **kw)
+    c = quadrature_constants(p)
+    G = generator_dense(p)
+    g = exterior_forcing(p, np.ones(2 * (p.n + 1)))
+    assert np.allclose(G.sum(axis=1) + g, -c["T"], rtol=0, atol=1e-9 * np.abs(G).max())
+
+
+def test_exterior_forcing_equals_a_larger_box():
+    """The box [-1, 1] with the exterior values of a smooth function U:
+    G u + g equals, row for row, the scheme's terms written out over the
+    whole window lattice (every offset |k| <= NW with its weight, the local
+    u'' and drift terms, the diagonal -(S0 + T) u_i), so g supplies exactly
+    the offsets and neighbours that fall outside the box."""
+    n = 60
+    p = Problem(dim=1, n=n, lo=-1.0, hi=1.0, s=0.5, lam=1.0, C=0.3, a=0.02, b=(0.2, 0.0))
+    h = h_of(p)
+    NW = n + 1
+    U = lambda x: np.exp(-x ** 2) * (1.0 + 0.3 * x)
+    xi = grid(p)[:, 0]
+    left = p.lo + h * np.arange(-NW + 1, 1)            # lattice indices -NW .. -1
+    right = p.hi + h * np.arange(0, NW)                 # indices n .. 2n
+    g = exterior_forcing(p, np.concatenate([U(left), U(right)]))
+    got = generator_dense(p) @ U(xi) + g
+    # the same rows by the direct sum over the whole window lattice
+    c = quadrature_constants(p)
+    beta = 0.5 * (c["C2"] - c["S2"])
+    want = np.empty(n)
+    for i in range(n):
+        k = np.arange(-NW, NW + 1)
+        k = k[k != 0]
+        w = np.where(np.abs(k) == NW, 0.5 * h, h)
+        xs = xi[i] + k * h
+        jump = np.sum(w * kernel_nu(p, np.abs(k) * h) * U(xs))
+        local = (beta + p.a) * (U(xi[i] + h) - 2 * U(xi[i]) + U(xi[i] - h)) / h ** 2 \
+            + p.b[0] * (U(xi[i] + h) - U(xi[i] - h)) / (2 * h)
+        want[i] = jump + local - (c["S0"] + c["T"]) * U(xi[i])
+    assert np.allclose(got, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
