@@ -244,7 +244,22 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
  * an asymmetric measure, 0 otherwise) to host `out`.  Synchronises `stream`. */
 hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream);
 
-/* Storage summary of the assembled operator.  Synchronises `stream`. */
+/* Forcing of a non-zero exterior, 1D tempered kernels (Sec. 4: the terms of
+ * equ:I1approx - equ:I3approx that reach outside the box; the far-field term
+ * f^{L_W} of equ:I2approx collects what lies beyond the window).  For
+ * u = u_ext outside the box, the scheme on the box is G u + g: g (device,
+ * natural order, length n) takes, in row i, the window offsets k
+ * (|k| <= NW = n + 1) whose point x_i + kh is exterior, each with W_k nu(kh)
+ * (W_k = h, h/2 at |k| = NW), and the local terms on the exterior neighbours
+ * lo and hi.  u_ext (device, 2 NW values): lattice points lo - (NW-1)h .. lo
+ * ascending, then hi .. hi + (NW-1)h.  The integral of u_ext beyond the
+ * window (|y| > L_W) is not included (its -u T part is in G).  A time-
+ * independent exterior enters hlevy_step as g with phi = 1.  Errors:
+ * HLEVY_ERR_INVALID_ARG for a 2D or Gaussian operator or overlapping
+ * buffers.  Synchronises `stream`. */
+hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream);
+
+/* Storage summary of the assembled operator.  Synchronises `stream`. *//* Storage summary of the assembled operator.  Synchronises `stream`. */
 hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream);
 
 /* Storage summary of a factor.  Synchronises `stream`. */

@@ -13,6 +13,10 @@ hipError_t launch_fill_dense(const ProblemDev& P, const double* cst, const int32
 hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids,
                       int n, double* U, double* V, const int64_t* uoff, const int64_t* voff,
                       int32_t* ranks, int kcap, double eps, hipStream_t s);
+// Forcing of a non-zero exterior (1D): tab holds 2 (n + 1) + 1 doubles of
+// workspace, g is written in natural order (length n)
+hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double* u_ext, double* tab, double* g,
+                           hipStream_t s);
 // Fixed-rank Taylor factors of the Gaussian kernel straight into the
 // admissible leaves ids[0..n) (rank set to r)
 hipError_t launch_taylor(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids, int n,

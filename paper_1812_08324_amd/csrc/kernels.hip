@@ -376,6 +376,46 @@ __device__ __forceinline__ double far_entry(const ProblemDev& P, const int32_t* 
   return P.h * P.h * nu_at(P, rr);
 }
 
+// Non-zero exterior, 1D (Sec. 4: the window terms that reach outside the
+// box).  tab[k + NW] (|k| <= NW, k != 0) is the coefficient of u(x_i + kh) in
+// row i: the trapezoid jump entry W_k nu(kh) (W_k = h, h/2 at |k| = NW), plus
+// on k = +-1 the local terms (diffusion and the u'' correction, the drift and
+// an asymmetric measure's u' sum).
+__global__ void __launch_bounds__(HL_BLOCK) k_ext_table(ProblemDev P, const double* cst, double* tab) {
+  const int NW = P.n + 1;
+  const int q = blockIdx.x * HL_BLOCK + threadIdx.x;
+  if (q > 2 * NW) return;
+  const int k = q - NW;
+  if (k == 0) {
+    tab[q] = 0.0;
+    return;
+  }
+  const double h = P.h;
+  double v = (abs(k) == NW ? 0.5 * h : h) * nu_jump1(P, k);
+  if (abs(k) == 1) {
+    const double beta = 0.5 * (cst[2] - cst[1]);
+    const double b0 = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM ? P.b0 - cst[4] : P.b0;
+    v += (beta + P.a) / (h * h) + (k > 0 ? 1.0 : -1.0) * b0 / (2.0 * h);
+  }
+  tab[q] = v;
+}
+// g[i] = sum over the exterior lattice points within the window of row i of
+// tab[j - i + NW] u_ext: u_ext[0 .. NW) are lattice indices -NW .. -1,
+// u_ext[NW .. 2 NW) indices n .. 2n.  One block per row, fixed-order sum.
+__global__ void __launch_bounds__(HL_BLOCK) k_ext_apply(const double* tab, const double* u_ext, int n,
+                                                        double* g) {
+  __shared__ double red[4];
+  const int NW = n + 1, i = blockIdx.x;
+  double acc = 0.0;
+  // left: j = q - NW >= i - NW, i.e. q >= i
+  for (int q = i + threadIdx.x; q < NW; q += HL_BLOCK) acc += tab[q - NW - i + NW] * u_ext[q];
+  // right: j = n + q - NW <= i + NW, i.e. q <= i + 2 NW - n
+  const int qend = min(2 * NW, i + 2 * NW - n + 1);
+  for (int q = NW + threadIdx.x; q < qend; q += HL_BLOCK) acc += tab[n + q - NW - i + NW] * u_ext[q];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) g[i] = acc;
+}
+
 // Fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3), one block per
 // admissible leaf: with xbar the centre of the row cluster's bounding box,
 // t0 = x_i - xbar and t = y_j - xbar per axis, column q holds
@@ -2418,6 +2458,13 @@ hipError_t launch_fill_dense(const ProblemDev& P, const double* cst, const int32
                              const LeafDesc* L, const int32_t* ids, int n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_dense, dim3(n), dim3(HL_BLOCK), 0, s, P, cst, perm, L, ids);
+  return post();
+}
+hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double* u_ext, double* tab, double* g,
+                           hipStream_t s) {
+  const int NW = P.n + 1;
+  hipLaunchKernelGGL(k_ext_table, dim3((2 * NW + 1 + HL_BLOCK - 1) / HL_BLOCK), dim3(HL_BLOCK), 0, s, P, cst, tab);
+  hipLaunchKernelGGL(k_ext_apply, dim3(P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, g);
   return post();
 }
 hipError_t launch_taylor(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids, int n,

@@ -2537,6 +2537,27 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream)
   });
 }
 
+hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream) {
+  if (!op || !u_ext || !g) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
+  if (op->prob.dim != 1) return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing is 1D");
+  if (op->prob.kernel == HLEVY_KERNEL_GAUSSIAN)
+    return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing follows the window scheme (tempered kernels)");
+  const int n = op->prob.n;
+  {
+    const double* ul = u_ext;
+    const double* uh = u_ext + 2 * (size_t)(n + 1);
+    if (g < uh && ul < g + n) return fail(HLEVY_ERR_INVALID_ARG, "u_ext and g must not overlap");
+  }
+  return guarded([&]() -> hlevy_status {
+    hipStream_t s = as_stream(stream);
+    DevBuf tab;
+    tab.alloc((2 * (size_t)(n + 1) + 1) * sizeof(double));
+    HL_CHECK(launch_exterior(op->pd, op->cst.as<double>(), u_ext, tab.as<double>(), g, s));
+    HL_CHECK(hipStreamSynchronize(s));
+    return HLEVY_OK;
+  });
+}
+
 hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream) {
   if (!op || !out) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   return guarded([&]() -> hlevy_status {

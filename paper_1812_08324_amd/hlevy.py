@@ -85,7 +85,7 @@ class TuneResult(C.Structure):
 
 
 EXPORTS = ["hlevy_abi_version", "hlevy_autotune", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
-           "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
+           "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_exterior_forcing", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
            "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_solve_noalloc", "hlevy_krylov_solve", "hlevy_step",
            "hlevy_step_batched", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
            "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_take_failed",
@@ -133,6 +133,7 @@ def _load():
                                     C.POINTER(vp)], st),
         "hlevy_op_constants": ([vp, C.POINTER(C.c_double), vp], st),
         "hlevy_op_info": ([vp, C.POINTER(OpInfo), vp], st),
+        "hlevy_exterior_forcing": ([vp, vp, vp, vp], st),
         "hlevy_fac_info": ([vp, C.POINTER(FacInfo), vp], st),
         "hlevy_matvec": ([vp, vp, vp, vp], st),
         "hlevy_op_densify": ([vp, vp, vp], st),
@@ -360,6 +361,14 @@ def op_constants(op: Op, stream=None):
     out = (C.c_double * 5)()
     _check(lib.hlevy_op_constants(op.h, out, _stream(stream)), "hlevy_op_constants")
     return list(out)
+
+
+def exterior_forcing(op: Op, u_ext, g, stream=None):
+    """g = the forcing of the exterior values u_ext (hlevy_exterior_forcing;
+    1D: u_ext holds 2 (n + 1) values, g n values, both float64 CUDA)."""
+    n = op.N
+    _check(lib.hlevy_exterior_forcing(op.h, _dptr(u_ext, 2 * (n + 1)), _dptr(g, n), _stream(stream)),
+           "hlevy_exterior_forcing")
 
 
 def op_info(op: Op, stream=None) -> dict:
