@@ -182,7 +182,7 @@ struct WsStack {
       if (cur >= slabs.size() || slabs[cur].cap < bytes) {
         size_t cap = std::max(SLAB, bytes);
         void* p = dev_alloc(cap, ctx);
-        if (!p) throw OomError{"workspace allocation failed"};
+        if (!p) throw OomError{"workspace allocation of " + std::to_string(cap) + " bytes failed"};
         if (cur < slabs.size()) slabs.insert(slabs.begin() + cur, Slab{(char*)p, cap});
         else slabs.push_back(Slab{(char*)p, cap});
         off = 0;
