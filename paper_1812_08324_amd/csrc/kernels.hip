@@ -1223,24 +1223,33 @@ __device__ int radd_core(const LFlushTarget& T, int kC, int K, double tol, int k
   //    else the new factors lose their orthogonality (and C its accuracy)
   //    by about eps / tol.
   if (use_dd) {
+    // The high parts of row q of Y_U and Y_V go to YU and YV, their low parts
+    // to the slots of X (column q) and Z (row q) that this thread has read
+    // already: no other thread reads those, and neither matrix is needed
+    // after this step.  No per-thread arrays, hence no scratch memory (a
+    // kernel with scratch cannot be dispatched once the device memory is
+    // exhausted).
     for (int q = tid; q < K; q += HL_BLOCK) {
       double* yu = YU + q * RA_YS;
       double* yv = YV + q * RA_YS;
-      dd su[RA_YS], sv[RA_YS];   // r <= the rank capacity <= RA_YS
       for (int c = 0; c < r; ++c) {
         const int pc = pivM[c];
         dd u = {Xh[pivB[pc] * ks + q], Xl[pivB[pc] * ks + q]};
         dd v = {Zh[q * ks + pc], Zl[q * ks + pc]};
         for (int i = 0; i < c; ++i) {
-          const dd rmic = {Yh[pivM[i] * ks + pc], Yl[pivM[i] * ks + pc]};
-          u = dd_add(u, dd_neg(dd_mul(rmic, su[i])));
-          v = dd_add(v, dd_neg(dd_mul(rmic, sv[i])));
+          const int pi = pivM[i];
+          const dd rmic = {Yh[pi * ks + pc], Yl[pi * ks + pc]};
+          const dd sui = {yu[i], Xl[pivB[pi] * ks + q]};
+          const dd svi = {yv[i], Zl[q * ks + pi]};
+          u = dd_add(u, dd_neg(dd_mul(rmic, sui)));
+          v = dd_add(v, dd_neg(dd_mul(rmic, svi)));
         }
         const dd dg = {Yh[pc * ks + pc], Yl[pc * ks + pc]};
-        su[c] = dd_div(u, dg);
-        sv[c] = dd_div(v, dg);
-        yu[c] = su[c].hi;
-        yv[c] = sv[c].hi;
+        const dd su = dd_div(u, dg), sv = dd_div(v, dg);
+        yu[c] = su.hi;
+        yv[c] = sv.hi;
+        Xl[pivB[pc] * ks + q] = su.lo;
+        Zl[q * ks + pc] = sv.lo;
       }
       for (int c = r; c < RA_YS; ++c) {
         yu[c] = 0.0;

@@ -3642,15 +3642,17 @@ hlevy_status hlevy_server_poll(hlevy_server* v, int64_t* done_ids, int32_t cap, 
         }
         // the joint factorisation's transient workspace comes on top of the
         // resident bytes: the arena takes half of what the device has free
-        // beyond the new factors' own storage and a margin (the product
-        // workspace grows beside it), at most the default budget
+        // beyond the new factors' own storage and an 8 GiB margin (the
+        // product workspace grows beside it), at most the default budget
         auto workspace = [&]() -> size_t {
           size_t free_b = 0, total_b = 0;
           if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
             (void)hipGetLastError();
             return 0;
           }
-          size_t need = (size_t)2 << 30;
+          // the margin covers what the runtime allocates beside the library
+          // (the callers' tensors, kernel scratch, the plan's arrays)
+          size_t need = (size_t)8 << 30;
           for (SrvEntry* e : fresh) need += e->bytes;
           const size_t floor_b = (size_t)1 << 30;
           return free_b > need + 2 * floor_b ? std::min(kDefaultFactorWorkspace, (free_b - need) / 2) : floor_b;
