@@ -45,6 +45,11 @@ Readings of the paper taken here (the paper is garbled or silent on them):
   (u_{i+1} - u_{i-1}) / (2h) (the printed /h without weights is
   dimensionally off).  Another compensator differs by a drift, which the
   caller can fold into b.
+* Variable jump index (Sec. 5.4): the paper applies the discretisation of
+  Sec. 4 to -(-Delta)^{s(x)} without writing it out.  Read here: the row of
+  x_i is the constant-order row with s = s(x_i) and kernel constant
+  c_{d,s(x_i)} (its own quadrature constants), and u = 0 on the grid points
+  outside the L-shaped domain, so those columns drop out.
 * The closed-form solution of the 1D fractional Poisson problem (Sec. 5.3):
   the paper prints the factor 2^{2s} Gamma(1+s) Gamma((1+2s)/2)/Gamma(1/2)
   in front of (1-x^2)^s.  That factor is (-Delta)^s of (1-x^2)^s (the ball
@@ -53,7 +58,7 @@ Readings of the paper taken here (the paper is garbled or silent on them):
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 import scipy.integrate as integrate
@@ -64,7 +69,7 @@ __all__ = [
     "Problem", "frac_const", "ball_const", "gauss_const", "grid", "h_of",
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
     "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
-    "taylor_terms", "taylor_factors", "kernel_nu_signed", "exterior_forcing",
+    "taylor_terms", "taylor_factors", "kernel_nu_signed", "exterior_forcing", "variable_order_generator",
 ]
 
 
@@ -355,6 +360,34 @@ def generator_dense(p: Problem) -> np.ndarray:
     G = np.empty((p.N, p.N), dtype=np.float64)
     for i in range(p.N):
         G[i] = generator_row(p, i, consts)
+    return G
+
+
+def variable_order_generator(p: Problem, mask=None, s_field=None) -> np.ndarray:
+    """Generator of a variable jump index on a masked grid (Sec. 5.4,
+    eq. equ:2dmodel: -(-Delta)^{s(x)} on the L-shaped domain, discretised
+    row by row as in Sec. 4).
+
+    The unknowns are the grid points the mask keeps (mask None: all), in
+    grid order.  The row of the unknown at grid point g, whose jump index is
+    s_g, is row g of the box generator of the same problem with s = s_g
+    (kernel constant c_{d,s_g} when p.C is None) restricted to the columns
+    of the unknowns: u = 0 on the grid points the mask drops, as outside
+    the box, and the diagonal keeps the whole-lattice sums of that row's
+    kernel.  s_field: one jump index per unknown (None: p.s everywhere)."""
+    full = p.n if p.dim == 1 else p.n * p.n
+    idx = np.arange(full) if mask is None else np.flatnonzero(np.asarray(mask).reshape(-1))
+    svals = np.full(len(idx), p.s) if s_field is None else np.asarray(s_field, dtype=np.float64)
+    if svals.shape != (len(idx),):
+        raise ValueError("s_field holds one value per unknown")
+    G = np.empty((len(idx), len(idx)), dtype=np.float64)
+    consts = {}
+    for r, g in enumerate(idx):
+        s = float(svals[r])
+        q = replace(p, s=s)
+        if s not in consts:
+            consts[s] = quadrature_constants(q)
+        G[r] = generator_row(q, int(g), consts[s])[idx]
     return G
 
 

@@ -16,7 +16,8 @@ import scipy.special as sp
 from oracle.levy_oracle import (Problem, ball_const, cn_run, cn_run_lean, frac_const,
                                 gauss_const, generator_dense, generator_row,
                                 grid, h_of, kernel_nu, quadrature_constants, steady_solve, steady_residual,
-                                fractional_poisson_exact, taylor_factors, taylor_terms, exterior_forcing)
+                                fractional_poisson_exact, taylor_factors, taylor_terms, exterior_forcing,
+                                variable_order_generator)
 
 
 def _order(e1, e2):
@@ -605,3 +606,101 @@ def test_exterior_forcing_equals_a_larger_box():
             + p.b[0] * (U(xi[i] + h) - U(xi[i] - h)) / (2 * h)
         want[i] = jump + local - (c["S0"] + c["T"]) * U(xi[i])
     assert np.allclose(got, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+
+
+# ---------------------------------------------------------------------------
+# variable jump index on a masked grid (Sec. 5.4)
+# ---------------------------------------------------------------------------
+def test_variable_order_constant_field_is_the_box_generator():
+    """A constant field without a mask gives the constant-order generator."""
+    for p in (Problem(dim=1, n=40, s=0.6, lam=0.5, a=0.02, b=(0.3, 0.0)),
+              Problem(dim=2, n=10, lo=-1.0, hi=1.0, s=0.35)):
+        G = variable_order_generator(p, None, np.full(p.N, p.s))
+        assert np.array_equal(G, generator_dense(p))
+
+
+def test_variable_order_lshape_is_the_principal_submatrix():
+    """Zero exterior: with a constant index the L-shaped domain's generator is
+    the box generator's rows and columns of the kept points."""
+    from workloads import lshape_mask
+    p = Problem(dim=2, n=12, lo=-1.0, hi=1.0, s=0.7)
+    mask = lshape_mask(12)
+    idx = np.flatnonzero(mask.reshape(-1))
+    assert len(idx) == 3 * 12 * 12 // 4
+    G = variable_order_generator(p, mask, None)
+    assert np.array_equal(G, generator_dense(p)[np.ix_(idx, idx)])
+
+
+def test_variable_order_rows_take_their_own_index():
+    """Row r is the constant-order row at s_r (the whole constant-order
+    generator assembled separately for each value), so the matrix is not
+    symmetric; swapping two values swaps only what those two rows hold."""
+    rng = np.random.default_rng(5)
+    p = Problem(dim=1, n=30, s=0.5, lam=0.3)
+    sf = rng.uniform(0.2, 0.9, p.N)
+    G = variable_order_generator(p, None, sf)
+    for r in (0, 7, 29):
+        Gr = generator_dense(Problem(dim=1, n=30, s=float(sf[r]), lam=0.3))
+        assert np.array_equal(G[r], Gr[r])
+    assert not np.allclose(G, G.T)
+    sw = sf.copy()
+    sw[[3, 20]] = sw[[20, 3]]
+    H = variable_order_generator(p, None, sw)
+    keep = np.setdiff1d(np.arange(p.N), [3, 20])
+    assert np.array_equal(H[keep], G[keep])
+    assert not np.allclose(H[3], G[3])
+
+
+def test_variable_order_lshape_rows_annihilate_constants():
+    """Each row of -(-Delta)^{s(x)} on the L-shaped domain, applied to u = 1
+    on the whole lattice with the far field of u = 1, gives 0: the row sum
+    plus the window weights of the offsets that leave the domain (outside
+    the box or in the removed quadrant), each with that row's kernel
+    c_{2,s_i} |y|^{-2-2s_i}, the local Laplacian terms of the missing
+    neighbours, and that row's tail T_i vanish."""
+    from workloads import variable_order_lshape
+    w = variable_order_lshape(16)
+    p = Problem(dim=2, n=16, lo=-1.0, hi=1.0, s=0.5)
+    G = variable_order_generator(p, w["mask"], w["s"])
+    idx = np.flatnonzero(w["mask"].reshape(-1))
+    kept = set(idx.tolist())
+    n = p.n
+    for r in (0, 40, 100, len(idx) - 1):
+        s = float(w["s"][r])
+        cst = quadrature_constants(Problem(dim=2, n=n, lo=-1.0, hi=1.0, s=s))
+        h, NW = cst["h"], cst["NW"]
+        p1, q1 = divmod(int(idx[r]), n)
+        k = np.arange(-NW, NW + 1)
+        K1, K2 = np.meshgrid(k, k, indexing="ij")
+        wt = np.where(np.abs(k) == NW, 0.5 * h, h)
+        W = np.outer(wt, wt)
+        P1, Q1 = p1 + K1, q1 + K2
+        inside = (P1 >= 0) & (P1 < n) & (Q1 >= 0) & (Q1 < n)
+        gidx = np.where(inside, P1 * n + Q1, -1)
+        lost_mask = np.array([[g not in kept for g in row] for row in gidx]) & ((K1 != 0) | (K2 != 0))
+        rr = np.hypot(K1[lost_mask] * h, K2[lost_mask] * h)
+        lost = np.sum(W[lost_mask] * frac_const(2, s) / rr ** (2 + 2 * s))
+        # and the local Laplacian term (C2 - S2) / (2 h^2) of every missing
+        # nearest neighbour
+        for d1, d2 in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            a1, a2 = p1 + d1, q1 + d2
+            if not (0 <= a1 < n and 0 <= a2 < n) or (a1 * n + a2) not in kept:
+                lost += 0.5 * (cst["C2"] - cst["S2"]) / h ** 2
+        total = G[r].sum() + lost + cst["T"]
+        assert abs(total) < 1e-11 * cst["S0"], (r, total)
+
+
+def test_lshape_distance_brute_force():
+    """The input field's d(x): distance to a fine sampling of the L-shape's
+    boundary (outer square and the two inner edges)."""
+    from workloads import lshape_distance, variable_order_lshape
+    x = variable_order_lshape(20)["x"]
+    t = np.linspace(-1.0, 1.0, 4001)
+    u = np.linspace(0.0, 1.0, 2001)
+    bd = np.concatenate([np.stack([t, -np.ones_like(t)], 1), np.stack([t, np.ones_like(t)], 1),
+                         np.stack([-np.ones_like(t), t], 1), np.stack([np.ones_like(t), t], 1),
+                         np.stack([np.zeros_like(u), u], 1), np.stack([u, np.zeros_like(u)], 1)])
+    brute = np.sqrt(((x[:, None, :] - bd[None, :, :]) ** 2).sum(-1)).min(1)
+    assert np.abs(lshape_distance(x) - brute).max() < 1e-3
+    s = 0.9 - 0.8 * lshape_distance(x)
+    assert s.min() > 0.4 and s.max() < 0.9

@@ -19,7 +19,8 @@ from dataclasses import dataclass, field, replace
 import numpy as np
 
 __all__ = ["Workload", "config1", "config2", "config3", "config4_instances", "serving_pool", "serving_trace", "request_u0",
-           "grid_points", "bump_1d", "ball_power", "gaussians_2d", "workload_key"]
+           "grid_points", "bump_1d", "ball_power", "gaussians_2d", "workload_key", "lshape_mask", "lshape_distance",
+           "variable_order_lshape"]
 
 
 @dataclass
@@ -140,6 +141,50 @@ def steady_poisson(n: int = 65536, s: float = 0.5, dt: float = 1e4) -> Workload:
                  steps=0, aca_tol=1e-10, max_rank=16, lu_tol=1e-6)
     w.g = np.ones(n)
     return w
+
+
+def lshape_mask(n: int) -> np.ndarray:
+    """Grid points of the L-shaped domain [-1, 1]^2 without [0, 1]^2 (Sec. 5.4)
+    on the n x n interior grid of [-1, 1]^2: True where the point is not in
+    the removed quadrant (x1 >= 0 and x2 >= 0).  Even n puts no grid point on
+    the two inner edges, so N = 3 n^2 / 4 (675, 1200, 2700, 4800, 7500 for
+    n = 30, 40, 60, 80, 100: the sizes the paper reports)."""
+    x = grid_points(2, n, -1.0, 1.0)
+    return ~((x[:, 0] >= 0.0) & (x[:, 1] >= 0.0)).reshape(n, n)
+
+
+def _segment_distance(x: np.ndarray, a, b) -> np.ndarray:
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    ab = b - a
+    t = np.clip(((x - a) @ ab) / (ab @ ab), 0.0, 1.0)
+    return np.linalg.norm(x - (a + t[:, None] * ab), axis=1)
+
+
+def lshape_distance(x: np.ndarray) -> np.ndarray:
+    """Distance d(x) of points of the L-shaped domain to its boundary: the
+    outer square's four sides and the inner edges {0} x [0, 1] and
+    [0, 1] x {0}."""
+    outer = np.minimum.reduce([1.0 - x[:, 0], 1.0 + x[:, 0], 1.0 - x[:, 1], 1.0 + x[:, 1]])
+    inner = np.minimum(_segment_distance(x, (0.0, 0.0), (0.0, 1.0)), _segment_distance(x, (0.0, 0.0), (1.0, 0.0)))
+    return np.minimum(outer, inner)
+
+
+def variable_order_lshape(n: int = 100) -> dict:
+    """The variable-order fractional Poisson problem of Sec. 5.4
+    (eq. equ:2dmodel): -(-Delta)^{s(x)} u = f on the L-shaped domain, u = 0
+    outside; s(x) = 0.9 - 0.8 d(x); f the sum of three Gaussians
+    exp(-10 |x - x_k|^2) at (-0.5, 0.5), (0.5, -0.5), (-0.5, -0.5).  The
+    paper's tolerances: eps1 = 1e-4 for the construction (aca_tol), eps2 =
+    1e-10 for the H-LU (lu_tol).  Returns the mask, the points of the
+    unknowns (grid order), s and f on them."""
+    mask = lshape_mask(n)
+    x = grid_points(2, n, -1.0, 1.0)[mask.reshape(-1)]
+    s = 0.9 - 0.8 * lshape_distance(x)
+    f = np.zeros(len(x))
+    for c in ((-0.5, 0.5), (0.5, -0.5), (-0.5, -0.5)):
+        f += np.exp(-10.0 * ((x - np.asarray(c)) ** 2).sum(axis=1))
+    return {"name": "varorder_lshape_n%d" % n, "n": n, "N": int(mask.sum()), "mask": mask, "x": x, "s": s,
+            "f": f, "aca_tol": 1e-4, "lu_tol": 1e-10}
 
 
 def config4_instances(count: int = 512, seed: int = 8324, nmin_log2: float = 10.0,
