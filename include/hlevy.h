@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define HLEVY_ABI_VERSION 5
+#define HLEVY_ABI_VERSION 6
 
 typedef enum {
   HLEVY_OK = 0,
@@ -64,19 +64,39 @@ typedef enum {
  * discretised by the plain trapezoid rule of Sec. 3.2 (eqs. equ:dl and
  * equ:Aij): off-diagonal entries h^d nu(x_j - x_i), diagonal
  * -h^d sum over the lattice without 0 of nu(kh) (u = 0 outside the box). */
-typedef enum { HLEVY_KERNEL_TEMPERED = 0, HLEVY_KERNEL_GAUSSIAN = 1, HLEVY_KERNEL_TEMPERED_ASYM = 2 } hlevy_kernel;
+typedef enum {
+  HLEVY_KERNEL_TEMPERED = 0,
+  HLEVY_KERNEL_GAUSSIAN = 1,
+  HLEVY_KERNEL_TEMPERED_ASYM = 2,
+  HLEVY_KERNEL_VARIABLE_ORDER = 3
+} hlevy_kernel;
 /* TEMPERED_ASYM (1D only): the tempered kernel with rate lambda for jumps
  * y > 0 and lambda_neg for y < 0 (a CGMY-type measure; Sec. 2 and Sec. 4 allow
  * asymmetric measures).  The generator keeps the compensator of
  * equ:I1approx, int (u(x+y) - u(x) - rho(y) y u'(x)) nu(y) dy, whose u' sum
  * S1 = sum' w_k rho_k nu(kh) kh no longer vanishes: it enters the nearest
  * neighbours as a drift -S1 (central difference). */
+/* VARIABLE_ORDER: the row of the point x_i takes its own jump index
+ * s_i = s_field[i]: nu_i(y) = C_i exp(-lambda |y|) / |y|^{d+2 s_i} with
+ * C_i = C when C > 0, else c_{d,s_i} (lambda = 0: the variable-order
+ * fractional Laplacian -(-Delta)^{s(x)} of Sec. 5.4, eq. equ:2dmodel).  Each
+ * row is the TEMPERED row of Sec. 4 at its own s_i (quadrature constants
+ * S0, S2, C2, T computed once per distinct value of s_field), so the
+ * generator is neither Toeplitz nor symmetric.  The field p.s is ignored. */
 
 /* The model problem (Sec. 3.1 eq. equ:ut; Sec. 4 eqs. equ:ny2 and the
- * zero-exterior remark).  Domain: the box [lo, hi]^dim, u = 0 outside. */
+ * zero-exterior remark).  Domain: the box [lo, hi]^dim, u = 0 outside; in 2D
+ * a mask can take grid points out of the domain (u = 0 there too: the
+ * generator of a masked domain is the box generator's rows and columns of
+ * the points kept), e.g. the L-shaped domain [-1, 1]^2 without [0, 1]^2 of
+ * Sec. 5.4.  With a mask the unknowns are the kept points in increasing
+ * grid index p*n + q, N = number of kept points, and every vector of the
+ * other calls is in that order.  mask and s_field are host arrays the
+ * library reads during the call that takes the problem (it keeps copies);
+ * the hlevy_server and hlevy_exterior_forcing calls take neither. */
 typedef struct {
   int32_t dim;       /* 1 or 2 */
-  int32_t n;         /* interior grid points per axis, h = (hi - lo)/(n + 1); N = n^dim */
+  int32_t n;         /* interior grid points per axis, h = (hi - lo)/(n + 1); N = n^dim (mask: kept points) */
   double lo, hi;     /* box */
   double a;          /* diffusion coefficient (a >= 0): sigma^2/2 of the Levy triplet */
   double b[2];       /* drift (b[1] ignored in 1D) */
@@ -89,6 +109,8 @@ typedef struct {
   int32_t pad;
   double eps2;       /* GAUSSIAN: eps^2 > 0 of nu(y) = C exp(-eps2 |y|^2) */
   double lambda_neg; /* TEMPERED_ASYM: tempering rate >= 0 of the jumps y < 0 (lambda: y > 0) */
+  const uint8_t* mask;   /* NULL, or (2D) n*n bytes in grid order, nonzero = point in the domain */
+  const double* s_field; /* VARIABLE_ORDER: N jump indices in (0, 1), natural order; else NULL */
 } hlevy_problem;
 
 /* H-matrix parameters (App. B.1): leaf size N_min, admissibility eta
@@ -117,8 +139,21 @@ typedef struct {
                               Gaussian kernel: partially pivoted ACA, whose stopping rule looks at
                               the last cross only, stops early on its 2D blocks (4.9 % block error
                               measured at eps2 = 5); 0 for the tempered kernel (ACA) */
-  int32_t pad;
+  int32_t cluster;         /* hlevy_cluster: how a cluster is split in two (both keep the order of
+                              the points inside each half) */
 } hlevy_hparams;
+
+/* Splitting rule of the cluster tree (App. B.1; Sec. 5.4 reorders by
+ * recursive K-means with two clusters).  BISECT: 1D halves the index
+ * range, 2D halves the longest side of the bounding box (ties: first
+ * axis).  KMEANS: Lloyd's iteration for two centres on the integer grid
+ * coordinates of the cluster's points, started from the first point of
+ * smallest and the first of largest coordinate along the longest side;
+ * a point joins the second centre only when strictly nearer to it; at most
+ * 64 iterations, stopping when no point moves; distances compared exactly
+ * (integer arithmetic), so the tree does not depend on rounding.  KMEANS
+ * needs N <= 2^22. */
+typedef enum { HLEVY_CLUSTER_BISECT = 0, HLEVY_CLUSTER_KMEANS = 1 } hlevy_cluster;
 
 /* Iterative refinement of a solve M x = b preconditioned by the H-LU
  * (Sec. 5.1 uses the H-LU inverse as a preconditioner): after the direct
@@ -418,6 +453,10 @@ typedef struct {
   double shift;
   int32_t precondition;  /* 1: with the factor's inverse factors; 0: none (for comparison) */
   int32_t use_guess;     /* 1: x holds the initial guess on entry; 0: start from x = 0 */
+  const hlevy_op* op;    /* the operator G of A: NULL = the factor's own; else an operator of the same
+                            cluster tree ordering (same problem and tree parameters, e.g. a tighter
+                            aca_tol), so that a coarse factor preconditions an accurate operator as
+                            in Sec. 5.4 (preconditioner from eps1 = 1e-4, iteration on A) */
 } hlevy_krylov;
 typedef struct {
   int32_t iterations;    /* iterations taken (a BiCGSTAB iteration is two products with G) */

@@ -42,6 +42,12 @@ struct Structure {
   int32_t dim = 1, n = 0, N = 0, leaf = 64, depth = 0, nmax = 0;
   double lo = -1, hi = 1, h = 0, eta = 1;
   std::vector<int32_t> perm;    // cluster position -> natural index
+  std::vector<int32_t> lat;     // cluster position -> grid index (1D: i; 2D: p*n + q); = perm without a mask
+  // variable-order kernel: the distinct jump indices (ascending) and, per
+  // cluster position, the index of its row's value among them
+  std::vector<double> var_s;
+  std::vector<int32_t> var_row;
+  int32_t cluster = 0;          // hlevy_cluster
   std::vector<double> pts;      // coordinates in cluster order (N * dim)
   std::vector<Cluster> cl;      // cl[0] is the root
   std::vector<int32_t> leafcl;  // leaf clusters in index order

@@ -164,6 +164,14 @@ struct ProblemDev {
   int32_t kernel, pad;   // hlevy_kernel
   double eps2;           // Gaussian: nu(r) = C exp(-eps2 r^2)
   double lam_neg;        // asymmetric tempered kernel: rate of the jumps y < 0 (lam: y > 0)
+  // variable-order kernel: per distinct jump index its value, kernel
+  // constant and five quadrature constants; per cluster position (row) the
+  // index of its value
+  const double* var_s;
+  const double* var_C;
+  const double* var_cst;
+  const int32_t* var_row;
+  int32_t nvar, pad2;
 };
 
 }  // namespace hl

@@ -8,6 +8,8 @@
 namespace hl {
 
 hipError_t launch_constants(const ProblemDev& P, double* out, hipStream_t s);
+// variable-order kernel: 5 constants per distinct jump index (P.nvar blocks)
+hipError_t launch_constants_var(const ProblemDev& P, double* out, hipStream_t s);
 hipError_t launch_fill_dense(const ProblemDev& P, const double* cst, const int32_t* perm,
                              const LeafDesc* L, const int32_t* ids, int n, hipStream_t s);
 hipError_t launch_aca(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids,

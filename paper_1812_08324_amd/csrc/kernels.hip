@@ -114,9 +114,13 @@ __device__ double block_max(double v, double* red) {
 // ---------------------------------------------------------------------------
 // kernel of the jump measure and quadrature constants (Sec. 4)
 // ---------------------------------------------------------------------------
+// the tempered kernel at distance r with jump index s and constant C
+__device__ __forceinline__ double nu_sc(const ProblemDev& P, double r, double s, double C) {
+  return C * exp(-P.lam * r) / pow(r, (double)P.dim + 2.0 * s);
+}
 __device__ __forceinline__ double nu_at(const ProblemDev& P, double r) {
   if (P.kernel == HLEVY_KERNEL_GAUSSIAN) return P.C * exp(-P.eps2 * r * r);
-  return P.C * exp(-P.lam * r) / pow(r, (double)P.dim + 2.0 * P.s);
+  return nu_sc(P, r, P.s, P.C);
 }
 // nu at the 1D jump y = k h (k != 0): the asymmetric kernel takes the rate
 // of its side, every other kernel is even
@@ -185,13 +189,14 @@ __device__ void gauss_legendre(int n, int i, double* x, double* w) {
   *w = 2.0 / ((1.0 - z * z) * pp * pp);
 }
 
-// out = {S0, S2, C2, T}.  One block.
+// out = {S0, S2, C2, T, S1} for the jump index s and kernel constant C
+// (the tempered family; the Gaussian kernel reads P).  One block.
 //   S0 = sum' W_k nu(kh) over the window |k|_inf <= NW = n + 1 (L_W = (n+1)h),
 //        trapezoid weights h (h/2 on the window edge) per axis;
 //   S2 = sum' W_k rho_k nu(kh) (k_1 h)^2 with rho the grid window of radius
 //        m = round(r0/h) (weight 1/2 on its edge);
 //   C2 = int rho nu y_1^2 dy,  T = int_{|y|_inf > L_W} nu dy.
-__global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* out) {
+__device__ void constants_of(const ProblemDev& P, const double s_, const double C_, double* out) {
   __shared__ double red[4];
   __shared__ double glx[32], glw[32];
   if (P.kernel == HLEVY_KERNEL_GAUSSIAN) {
@@ -246,7 +251,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
   } else if (P.dim == 1) {
     for (int k = 1 + threadIdx.x; k <= NW; k += blockDim.x) {
       double w = (k == NW) ? 0.5 * h : h;
-      double nu = nu_at(P, k * h);
+      double nu = nu_sc(P, k * h, s_, C_);
       acc(s0, s0c, 2.0 * w * nu);
       if (k <= m) {
         double rho = (k < m) ? 1.0 : 0.5;
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
       if (k1 == 0 && k2 == 0) continue;
       double w = ((abs(k1) == NW) ? 0.5 * h : h) * ((abs(k2) == NW) ? 0.5 * h : h);
       double rr = h * sqrt((double)k1 * k1 + (double)k2 * k2);
-      double nu = nu_at(P, rr);
+      double nu = nu_sc(P, rr, s_, C_);
       acc(s0, s0c, w * nu);
       if (abs(k1) <= m && abs(k2) <= m) {
         double rho = ((abs(k1) < m) ? 1.0 : 0.5) * ((abs(k2) < m) ? 1.0 : 0.5);
@@ -275,7 +280,7 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
   if (threadIdx.x < 32) gauss_legendre(32, threadIdx.x, &glx[threadIdx.x], &glw[threadIdx.x]);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double s = P.s, C = P.C, lam = P.lam, a2 = 2.0 - 2.0 * s;
+    const double s = s_, C = C_, lam = P.lam, a2 = 2.0 - 2.0 * s;
     double C2 = 0.0, T = 0.0;
     if (P.dim == 1 && P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) {
       // each side with its own rate
@@ -328,10 +333,29 @@ __global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* ou
   }
 }
 
+__global__ void __launch_bounds__(HL_BLOCK) k_constants(ProblemDev P, double* out) {
+  constants_of(P, P.s, P.C, out);
+}
+
+// variable-order kernel: block q computes the constants of the q-th
+// distinct jump index into out[5 q .. 5 q + 4]
+__global__ void __launch_bounds__(HL_BLOCK) k_constants_var(ProblemDev P, double* out) {
+  const int q = blockIdx.x;
+  constants_of(P, P.var_s[q], P.var_C[q], out + 5 * (size_t)q);
+}
+
 // Generator entry G_ij (cluster-ordered i, j) from integer grid offsets.
 __device__ __forceinline__ double gen_entry(const ProblemDev& P, const double* cst,
                                             const int32_t* perm, int i, int j) {
   const double h = P.h;
+  const bool var = P.kernel == HLEVY_KERNEL_VARIABLE_ORDER;
+  double s = P.s, C = P.C;
+  if (var) {   // row i's own jump index and constants
+    const int q = P.var_row[i];
+    s = P.var_s[q];
+    C = P.var_C[q];
+    cst = P.var_cst + 5 * (size_t)q;
+  }
   const double beta = 0.5 * (cst[2] - cst[1]);
   int k1, k2 = 0;
   if (P.dim == 1) {
@@ -345,10 +369,10 @@ __device__ __forceinline__ double gen_entry(const ProblemDev& P, const double* c
     return -cst[0] - cst[3] - 2.0 * P.dim * (beta + P.a) / (h * h) + P.c;
   double v;
   if (P.dim == 1) {
-    v = h * nu_jump1(P, k1);
+    v = h * (var ? nu_sc(P, fabs((double)k1) * h, s, C) : nu_jump1(P, k1));
   } else {
     const double rr = h * sqrt((double)k1 * k1 + (double)k2 * k2);
-    v = h * h * nu_at(P, rr);
+    v = h * h * (var ? nu_sc(P, rr, s, C) : nu_at(P, rr));
   }
   if (abs(k1) + abs(k2) == 1) {
     v += (beta + P.a) / (h * h);
@@ -370,6 +394,11 @@ __device__ __forceinline__ double far_entry(const ProblemDev& P, const int32_t* 
     int pi = perm[i], pj = perm[j];
     k1 = pj / P.n - pi / P.n;
     k2 = pj % P.n - pi % P.n;
+  }
+  if (P.kernel == HLEVY_KERNEL_VARIABLE_ORDER) {   // row i's own jump index
+    const int q = P.var_row[i];
+    const double r = P.h * sqrt((double)k1 * k1 + (double)k2 * k2);
+    return (P.dim == 1 ? P.h : P.h * P.h) * nu_sc(P, r, P.var_s[q], P.var_C[q]);
   }
   if (P.dim == 1) return P.h * nu_jump1(P, k1);
   double rr = P.h * sqrt((double)k1 * k1 + (double)k2 * k2);
@@ -2458,6 +2487,12 @@ __global__ void __launch_bounds__(HL_BLOCK) k_densify(const LeafDesc* L, const i
 // launchers
 // ---------------------------------------------------------------------------
 static inline hipError_t post() { return hipGetLastError(); }
+
+hipError_t launch_constants_var(const ProblemDev& P, double* out, hipStream_t s) {
+  if (P.nvar < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_constants_var, dim3(P.nvar), dim3(HL_BLOCK), 0, s, P, out);
+  return post();
+}
 
 hipError_t launch_constants(const ProblemDev& P, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_constants, dim3(1), dim3(HL_BLOCK), 0, s, P, out);

@@ -301,7 +301,7 @@ struct HMat {
 
 // Device copies of the structure lists.
 struct DevStructure {
-  DevBuf rowptr, rowidx, colptr, colidx, lclo, lchi, perm, ident;
+  DevBuf rowptr, rowidx, colptr, colidx, lclo, lchi, perm, lat, ident;
   DevLists lists{};
   void create(const Structure& S, hipStream_t s) {
     upload(rowptr, S.rowptr, s);
@@ -316,6 +316,7 @@ struct DevStructure {
     upload(lclo, lo, s);
     upload(lchi, hi, s);
     upload(perm, S.perm, s);
+    upload(lat, S.lat, s);
     std::vector<double> I(64 * 64, 0.0);
     for (int i = 0; i < 64; ++i) I[i + 64 * i] = 1.0;
     upload(ident, I, s);
@@ -1714,6 +1715,7 @@ struct hlevy_op {
   DevStructure ds;
   HMat G;
   DevBuf cst, ovf;
+  DevBuf var_s, var_C, var_cst, var_row;   // variable-order kernel (ProblemDev)
   DevBuf xbuf, ybuf;   // cluster-order work vectors for hlevy_matvec
   MvPlan mv;           // FP64 product with G
 };
@@ -2253,6 +2255,8 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     if (!e.empty()) return fail(HLEVY_ERR_INVALID_ARG, e);
     const Structure& S = op->S;
     op->prob = *prob;
+    op->prob.mask = nullptr;      // the caller's arrays: the structure keeps what it needs
+    op->prob.s_field = nullptr;
     op->hp = *hp;
     ProblemDev& pd = op->pd;
     pd.dim = prob->dim;
@@ -2278,19 +2282,44 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
       op->G.create(S, hp->max_rank, FULL, s);
     }
     HL_CHECK(hipMemsetAsync(op->ovf.p, 0, sizeof(int32_t), s));
-    HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
+    if (prob->kernel == HLEVY_KERNEL_VARIABLE_ORDER) {
+      // constants of every distinct jump index; hlevy_op_constants reports
+      // those of the first point (natural order)
+      std::vector<double> vC(S.var_s.size());
+      for (size_t q = 0; q < vC.size(); ++q) vC[q] = prob->C > 0.0 ? prob->C : frac_constant(prob->dim, S.var_s[q]);
+      {
+        AllocScope own(&op->actx);
+        upload(op->var_s, S.var_s, s);
+        upload(op->var_C, vC, s);
+        upload(op->var_row, S.var_row, s);
+        op->var_cst.alloc(5 * sizeof(double) * S.var_s.size());
+      }
+      pd.var_s = op->var_s.as<double>();
+      pd.var_C = op->var_C.as<double>();
+      pd.var_row = op->var_row.as<int32_t>();
+      pd.var_cst = op->var_cst.as<double>();
+      pd.nvar = (int32_t)S.var_s.size();
+      HL_CHECK(launch_constants_var(pd, op->var_cst.as<double>(), s));
+      int first = 0;
+      for (int k = 0; k < S.N; ++k)
+        if (S.perm[k] == 0) first = S.var_row[k];
+      HL_CHECK(hipMemcpyAsync(op->cst.p, op->var_cst.as<double>() + 5 * (size_t)first, 5 * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    } else {
+      HL_CHECK(launch_constants(pd, op->cst.as<double>(), s));
+    }
     // dense near field
     auto A = std::make_unique<Aca>();
     std::vector<int32_t> dense_ids;
     for (size_t l = 0; l < S.lf.size(); ++l) (S.lf[l].kind == K_DENSE ? dense_ids : A->lr_ids).push_back((int)l);
     upload(A->dids, dense_ids, s);
     upload(A->lids, A->lr_ids, s);
-    HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.perm.as<int32_t>(), op->G.dev(),
+    HL_CHECK(launch_fill_dense(pd, op->cst.as<double>(), op->ds.lat.as<int32_t>(), op->G.dev(),
                                A->dids.as<int32_t>(), (int)dense_ids.size(), s));
     if (hp->taylor_rank > 0) {
       // the fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3) go
       // straight into G: no ACA, no truncation
-      HL_CHECK(launch_taylor(pd, op->ds.perm.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(),
+      HL_CHECK(launch_taylor(pd, op->ds.lat.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(),
                              (int)A->lr_ids.size(), op->G.rank, hp->taylor_rank, s));
       A->lr_ids.clear();
     }
@@ -2309,7 +2338,7 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     // per-block overflow counts of the truncation
     A->blkovf.alloc(std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t));
     HL_CHECK(hipMemsetAsync(A->blkovf.p, 0, std::max<size_t>(A->lr_ids.size(), 1) * sizeof(int32_t), s));
-    HL_CHECK(launch_aca(pd, op->ds.perm.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(), (int)A->lr_ids.size(),
+    HL_CHECK(launch_aca(pd, op->ds.lat.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(), (int)A->lr_ids.size(),
                         A->buf.as<double>(), A->buf.as<double>(), A->duo.as<int64_t>(), A->dvo.as<int64_t>(),
                         A->rank.as<int32_t>(), kaca, 0.1 * hp->aca_tol, s));
     aca[i] = std::move(A);
@@ -2540,6 +2569,8 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream)
 hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream) {
   if (!op || !u_ext || !g) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   if (op->prob.dim != 1) return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing is 1D");
+  if (op->prob.kernel == HLEVY_KERNEL_VARIABLE_ORDER)
+    return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing takes a constant jump index");
   if (op->prob.kernel == HLEVY_KERNEL_GAUSSIAN)
     return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing follows the window scheme (tempered kernels)");
   const int n = op->prob.n;
@@ -2998,6 +3029,11 @@ hlevy_status hlevy_krylov_solve(hlevy_fac* f, const double* b, double* x, const 
   if (!std::isfinite(opt->shift)) return fail(HLEVY_ERR_INVALID_ARG, "shift must be finite");
   if ((opt->precondition != 0 && opt->precondition != 1) || (opt->use_guess != 0 && opt->use_guess != 1))
     return fail(HLEVY_ERR_INVALID_ARG, "precondition and use_guess are 0 or 1");
+  // the iteration's operator: the factor's own, or one with its ordering
+  const hlevy_op* aop = opt->op ? opt->op : f->op;
+  if (aop != f->op && (aop->S.N != N || aop->S.perm != f->op->S.perm))
+    return fail(HLEVY_ERR_INVALID_ARG, "op must have the factor's points in the factor's cluster order");
+  const MvPlan& mvA = aop == f->op ? f->mvG : aop->mv;
   const double t_start = now_s();
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
@@ -3055,7 +3091,7 @@ hlevy_status hlevy_krylov_solve(hlevy_fac* f, const double* b, double* x, const 
       e.cg = opt->shift;
       e.g = y;
       e.y = out;
-      f->mvG.run(y, e, s);
+      mvA.run(y, e, s);
     };
     auto precond = [&](const double* y, double* out) {
       if (!opt->precondition) {
@@ -3537,6 +3573,8 @@ hlevy_status hlevy_server_submit(hlevy_server* v, const hlevy_problem* prob, con
   if (!v || !prob || !hp || !u0 || !u_out || !id) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HLEVY_ERR_INVALID_ARG, "dt must be > 0");
   if (nsteps < 0) return fail(HLEVY_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (prob->mask || prob->s_field)
+    return fail(HLEVY_ERR_INVALID_ARG, "the server takes box problems (no mask, no s_field)");
   return guarded([&]() -> hlevy_status {
     Structure S;
     std::string e = build_structure(*prob, *hp, S);

@@ -42,34 +42,96 @@ double dist(const Structure& s, const Cluster& x, const Cluster& y) {
   return std::sqrt(acc);
 }
 
-// Split cluster `id` into two children: 1D halves the index range
-// (floor(n/2), n - floor(n/2)); 2D bisects the longest side of the bounding
-// box at its midpoint (ties: first axis), keeping the order inside halves.
+// Two centres of Lloyd's iteration (Sec. 5.4: recursive K-means with two
+// clusters) over the points [lo, hi) of a 2D cluster, on their integer grid
+// coordinates.  Centre A = SA / nA.  A point goes to B only when strictly
+// nearer: |nB p - SB|^2 nA^2 < |nA p - SA|^2 nB^2, compared exactly (the
+// factors stay below 2^115 for n <= 8192 and N <= 2^22).  Returns the side
+// of every point (true: B) after at most 64 assignment passes, stopping when
+// no point moves; a pass that would empty a side is discarded.
+std::vector<char> kmeans2(const Structure& s, int lo, int hi) {
+  using i128 = __int128;
+  const int cnt = hi - lo;
+  std::vector<int64_t> g(2 * (size_t)cnt);
+  for (int i = 0; i < cnt; ++i) {
+    g[2 * i] = s.lat[lo + i] / s.n;
+    g[2 * i + 1] = s.lat[lo + i] % s.n;
+  }
+  int64_t mn[2] = {g[0], g[1]}, mx[2] = {g[0], g[1]};
+  for (int i = 1; i < cnt; ++i)
+    for (int a = 0; a < 2; ++a) {
+      mn[a] = std::min(mn[a], g[2 * i + a]);
+      mx[a] = std::max(mx[a], g[2 * i + a]);
+    }
+  const int ax = (mx[1] - mn[1] > mx[0] - mn[0]) ? 1 : 0;
+  int ia = -1, ib = -1;
+  for (int i = 0; i < cnt; ++i) {
+    if (ia < 0 && g[2 * i + ax] == mn[ax]) ia = i;
+    if (ib < 0 && g[2 * i + ax] == mx[ax]) ib = i;
+  }
+  int64_t SA[2] = {g[2 * ia], g[2 * ia + 1]}, SB[2] = {g[2 * ib], g[2 * ib + 1]};
+  int64_t nA = 1, nB = 1;
+  std::vector<char> prev, cur(cnt);
+  for (int it = 0; it < 64; ++it) {
+    int64_t inB = 0;
+    for (int i = 0; i < cnt; ++i) {
+      i128 dA = 0, dB = 0;
+      for (int a = 0; a < 2; ++a) {
+        const i128 ea = (i128)nA * g[2 * i + a] - SA[a], eb = (i128)nB * g[2 * i + a] - SB[a];
+        dA += ea * ea;
+        dB += eb * eb;
+      }
+      cur[i] = dB * ((i128)nA * nA) < dA * ((i128)nB * nB);
+      inB += cur[i];
+    }
+    if (cur == prev) break;
+    if (inB == 0 || inB == cnt) break;   // keeps prev (the first pass never empties a side)
+    prev = cur;
+    SA[0] = SA[1] = SB[0] = SB[1] = 0;
+    nA = nB = 0;
+    for (int i = 0; i < cnt; ++i) {
+      int64_t* S = cur[i] ? SB : SA;
+      S[0] += g[2 * i];
+      S[1] += g[2 * i + 1];
+      (cur[i] ? nB : nA) += 1;
+    }
+  }
+  return prev;
+}
+
+// Split cluster `id` into two children, keeping the order inside halves.
+// BISECT: 1D halves the index range (floor(n/2), n - floor(n/2)); 2D
+// bisects the longest side of the bounding box at its midpoint (ties: first
+// axis).  KMEANS (2D): the two clusters of kmeans2.
 void split(Structure& s, int id) {
   Cluster c = s.cl[id];
   int nl;
   if (s.dim == 1) {
     nl = (c.hi - c.lo) / 2;
   } else {
-    int ax = (c.bmax[1] - c.bmin[1] > c.bmax[0] - c.bmin[0]) ? 1 : 0;
-    double mid = 0.5 * (c.bmin[ax] + c.bmax[ax]);
-    std::vector<int32_t> left, right;
+    std::vector<char> side;
+    if (s.cluster == HLEVY_CLUSTER_KMEANS) side = kmeans2(s, c.lo, c.hi);
+    if (side.empty()) {
+      int ax = (c.bmax[1] - c.bmin[1] > c.bmax[0] - c.bmin[0]) ? 1 : 0;
+      double mid = 0.5 * (c.bmin[ax] + c.bmax[ax]);
+      side.resize(c.hi - c.lo);
+      for (int i = c.lo; i < c.hi; ++i) side[i - c.lo] = !(s.pts[(size_t)i * 2 + ax] < mid);
+    }
+    std::vector<int32_t> left, right, ll, lr;
     std::vector<double> pl, pr;
     for (int i = c.lo; i < c.hi; ++i) {
-      double v = s.pts[(size_t)i * 2 + ax];
-      if (v < mid) {
-        left.push_back(s.perm[i]);
-        pl.push_back(s.pts[(size_t)i * 2]);
-        pl.push_back(s.pts[(size_t)i * 2 + 1]);
-      } else {
-        right.push_back(s.perm[i]);
-        pr.push_back(s.pts[(size_t)i * 2]);
-        pr.push_back(s.pts[(size_t)i * 2 + 1]);
-      }
+      const bool r = side[i - c.lo];
+      (r ? right : left).push_back(s.perm[i]);
+      (r ? lr : ll).push_back(s.lat[i]);
+      std::vector<double>& P = r ? pr : pl;
+      P.push_back(s.pts[(size_t)i * 2]);
+      P.push_back(s.pts[(size_t)i * 2 + 1]);
     }
     nl = (int)left.size();
     std::copy(left.begin(), left.end(), s.perm.begin() + c.lo);
     std::copy(right.begin(), right.end(), s.perm.begin() + c.lo + nl);
+    std::copy(ll.begin(), ll.end(), s.lat.begin() + c.lo);
+    std::copy(lr.begin(), lr.end(), s.lat.begin() + c.lo + nl);
     std::copy(pl.begin(), pl.end(), s.pts.begin() + (size_t)c.lo * 2);
     std::copy(pr.begin(), pr.end(), s.pts.begin() + (size_t)(c.lo + nl) * 2);
   }
@@ -141,12 +203,21 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   else if (p.n < 2) err << "n must be >= 2";
   else if (!(p.hi > p.lo) || !std::isfinite(p.lo) || !std::isfinite(p.hi)) err << "need lo < hi (finite)";
   else if (p.kernel != HLEVY_KERNEL_TEMPERED && p.kernel != HLEVY_KERNEL_GAUSSIAN &&
-           p.kernel != HLEVY_KERNEL_TEMPERED_ASYM)
-    err << "kernel must be HLEVY_KERNEL_TEMPERED, HLEVY_KERNEL_GAUSSIAN or HLEVY_KERNEL_TEMPERED_ASYM";
+           p.kernel != HLEVY_KERNEL_TEMPERED_ASYM && p.kernel != HLEVY_KERNEL_VARIABLE_ORDER)
+    err << "kernel must be HLEVY_KERNEL_TEMPERED, HLEVY_KERNEL_GAUSSIAN, HLEVY_KERNEL_TEMPERED_ASYM or "
+           "HLEVY_KERNEL_VARIABLE_ORDER";
+  else if (p.mask && p.dim != 2) err << "a mask needs dim 2";
+  else if (p.kernel == HLEVY_KERNEL_VARIABLE_ORDER && !p.s_field) err << "the variable-order kernel needs s_field";
+  else if (p.kernel != HLEVY_KERNEL_VARIABLE_ORDER && p.s_field)
+    err << "s_field is for the variable-order kernel only";
+  else if (hp.cluster != HLEVY_CLUSTER_BISECT && hp.cluster != HLEVY_CLUSTER_KMEANS)
+    err << "cluster must be HLEVY_CLUSTER_BISECT or HLEVY_CLUSTER_KMEANS";
+  else if (hp.cluster == HLEVY_CLUSTER_KMEANS && p.dim != 2) err << "KMEANS clustering is 2D only";
   else if (p.kernel == HLEVY_KERNEL_TEMPERED_ASYM && p.dim != 1) err << "the asymmetric kernel is 1D only";
   else if (p.kernel == HLEVY_KERNEL_TEMPERED_ASYM && (!(p.lambda_neg >= 0.0) || !std::isfinite(p.lambda_neg)))
     err << "lambda_neg must be >= 0";
-  else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && !(p.s > 0.0 && p.s < 1.0)) err << "s must lie in (0, 1)";
+  else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && p.kernel != HLEVY_KERNEL_VARIABLE_ORDER && !(p.s > 0.0 && p.s < 1.0))
+    err << "s must lie in (0, 1)";
   else if (p.kernel == HLEVY_KERNEL_GAUSSIAN && (!(p.eps2 > 0.0) || !std::isfinite(p.eps2)))
     err << "eps2 must be > 0 for the Gaussian kernel";
   else if (!(p.a >= 0.0) || !std::isfinite(p.a)) err << "a must be >= 0";
@@ -171,9 +242,21 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   else if (hp.taylor_rank == 0 && p.kernel == HLEVY_KERNEL_GAUSSIAN)
     err << "the Gaussian kernel needs taylor_rank > 0 (partially pivoted ACA misses parts of its blocks)";
   if (!err.str().empty()) return err.str();
-  int64_t N64 = p.dim == 1 ? (int64_t)p.n : (int64_t)p.n * p.n;
-  if (N64 > (int64_t)1 << 26) return "N too large (max 2^26)";
+  const int64_t grid = p.dim == 1 ? (int64_t)p.n : (int64_t)p.n * p.n;
+  if (grid > (int64_t)1 << 26) return "grid too large (max 2^26 points)";
+  // unknowns: the grid points in grid order, or those the mask keeps
+  std::vector<int32_t> kept;
+  if (p.mask) {
+    for (int64_t g = 0; g < grid; ++g)
+      if (p.mask[g]) kept.push_back((int32_t)g);
+  }
+  int64_t N64 = p.mask ? (int64_t)kept.size() : grid;
   if (N64 < 2 * (int64_t)hp.leaf) return "N must be at least twice the leaf size";
+  if (hp.cluster == HLEVY_CLUSTER_KMEANS && N64 > (int64_t)1 << 22) return "KMEANS clustering needs N <= 2^22";
+  if (p.kernel == HLEVY_KERNEL_VARIABLE_ORDER)
+    for (int64_t i = 0; i < N64; ++i)
+      if (!(p.s_field[i] > 0.0 && p.s_field[i] < 1.0))
+        return "s_field[" + std::to_string(i) + "] must lie in (0, 1)";
 
   s = Structure{};
   if (overcap) s.split = *overcap;
@@ -186,19 +269,21 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   s.h = (p.hi - p.lo) / (p.n + 1);
   s.eta = hp.eta;
   s.nmax = (int32_t)((N64 + hp.n_block - 1) / hp.n_block);
+  s.cluster = hp.cluster;
   const int N = s.N;
   s.perm.resize(N);
   std::iota(s.perm.begin(), s.perm.end(), 0);
+  if (p.mask) s.lat = kept;
+  else s.lat = s.perm;
   s.pts.resize((size_t)N * s.dim);
   if (s.dim == 1) {
     for (int i = 0; i < N; ++i) s.pts[i] = p.lo + (i + 1) * s.h;
   } else {
-    for (int i = 0; i < s.n; ++i)
-      for (int j = 0; j < s.n; ++j) {
-        size_t k = (size_t)i * s.n + j;
-        s.pts[2 * k] = p.lo + (i + 1) * s.h;
-        s.pts[2 * k + 1] = p.lo + (j + 1) * s.h;
-      }
+    for (int k = 0; k < N; ++k) {
+      const int g = s.lat[k];
+      s.pts[2 * (size_t)k] = p.lo + (g / s.n + 1) * s.h;
+      s.pts[2 * (size_t)k + 1] = p.lo + (g % s.n + 1) * s.h;
+    }
   }
   Cluster root{};
   root.lo = 0; root.hi = N; root.level = 0; root.child[0] = root.child[1] = -1;
@@ -232,6 +317,16 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   for (size_t q = 0; q < frontier.size(); ++q)
     if (s.cl[frontier[q]].hi - s.cl[frontier[q]].lo < 1) return "empty leaf cluster";
 
+  if (p.kernel == HLEVY_KERNEL_VARIABLE_ORDER) {
+    // distinct jump indices, ascending; each cluster position's row
+    s.var_s.assign(p.s_field, p.s_field + N);
+    std::sort(s.var_s.begin(), s.var_s.end());
+    s.var_s.erase(std::unique(s.var_s.begin(), s.var_s.end()), s.var_s.end());
+    s.var_row.resize(N);
+    for (int k = 0; k < N; ++k)
+      s.var_row[k] = (int32_t)(std::lower_bound(s.var_s.begin(), s.var_s.end(), p.s_field[s.perm[k]]) -
+                               s.var_s.begin());
+  }
   build_block(s, 0, 0);
   number_leaves(s, 0);
   for (auto& l : s.lf) {

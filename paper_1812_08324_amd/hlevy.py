@@ -25,14 +25,15 @@ class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
                 ("a", C.c_double), ("b", C.c_double * 2), ("c", C.c_double), ("s", C.c_double),
                 ("lam", C.c_double), ("C", C.c_double), ("r0", C.c_double), ("kernel", C.c_int32),
-                ("pad", C.c_int32), ("eps2", C.c_double), ("lam_neg", C.c_double)]
+                ("pad", C.c_int32), ("eps2", C.c_double), ("lam_neg", C.c_double),
+                ("mask", C.POINTER(C.c_uint8)), ("s_field", C.POINTER(C.c_double))]
 
 
 class HParams(C.Structure):
     _fields_ = [("leaf", C.c_int32), ("eta", C.c_double), ("n_block", C.c_int32),
                 ("aca_tol", C.c_double), ("max_rank", C.c_int32), ("gather_waves", C.c_int32),
                 ("rank_bucket", C.c_int32), ("strict_rank_cap", C.c_int32), ("taylor_rank", C.c_int32),
-                ("pad", C.c_int32)]
+                ("cluster", C.c_int32)]
 
 
 class Refine(C.Structure):
@@ -97,7 +98,7 @@ KRYLOV_CG, KRYLOV_BICGSTAB = 0, 1
 
 class KrylovOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("shift", C.c_double),
-                ("precondition", C.c_int32), ("use_guess", C.c_int32)]
+                ("precondition", C.c_int32), ("use_guess", C.c_int32), ("op", C.c_void_p)]
 
 
 class KrylovStats(C.Structure):
@@ -202,13 +203,17 @@ def _dptr(t, n=None):
     return C.c_void_p(t.data_ptr())
 
 
-KERNEL_TEMPERED, KERNEL_GAUSSIAN, KERNEL_TEMPERED_ASYM = 0, 1, 2
+KERNEL_TEMPERED, KERNEL_GAUSSIAN, KERNEL_TEMPERED_ASYM, KERNEL_VARIABLE_ORDER = 0, 1, 2, 3
+CLUSTER_BISECT, CLUSTER_KMEANS = 0, 1
 
 
 def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0, r0=0.2, kernel=0,
-                 eps2=0.0, lam_neg=None) -> Problem:
+                 eps2=0.0, lam_neg=None, mask=None, s_field=None) -> Problem:
     """lam_neg: the tempering rate of the jumps y < 0 (1D); given, the kernel
-    is HLEVY_KERNEL_TEMPERED_ASYM with lam for y > 0."""
+    is HLEVY_KERNEL_TEMPERED_ASYM with lam for y > 0.  mask (2D): n x n
+    array, nonzero = grid point in the domain.  s_field: one jump index per
+    unknown (natural order); given, the kernel is HLEVY_KERNEL_VARIABLE_ORDER.
+    The problem keeps its own copies of both arrays."""
     p = Problem()
     p.dim, p.n, p.lo, p.hi = int(dim), int(n), float(lo), float(hi)
     p.a, p.c, p.s, p.lam = float(a), float(c), float(s), float(lam)
@@ -218,15 +223,37 @@ def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0
     p.kernel, p.eps2 = int(kernel), float(eps2)
     if lam_neg is not None:
         p.kernel, p.lam_neg = KERNEL_TEMPERED_ASYM, float(lam_neg)
+    if mask is not None:
+        m = (C.c_uint8 * (int(n) * int(n)))(*[1 if v else 0 for v in _flat(mask)])
+        p._mask_arr, p._N = m, sum(m)
+        p.mask = C.cast(m, C.POINTER(C.c_uint8))
+    if s_field is not None:
+        vals = [float(v) for v in _flat(s_field)]
+        f = (C.c_double * len(vals))(*vals)
+        p._s_arr = f
+        p.s_field = C.cast(f, C.POINTER(C.c_double))
+        p.kernel = KERNEL_VARIABLE_ORDER
     return p
 
 
+def _flat(a):
+    return a.reshape(-1).tolist() if hasattr(a, "reshape") else list(a)
+
+
+def problem_N(prob: Problem) -> int:
+    """Unknowns of a problem: n^dim, or the points its mask keeps."""
+    n = getattr(prob, "_N", None)
+    if n is not None:
+        return int(n)
+    return prob.n if prob.dim == 1 else prob.n * prob.n
+
+
 def make_hparams(leaf=64, eta=1.0, n_block=4, aca_tol=1e-10, max_rank=16, gather_waves=0, rank_bucket=0,
-                 strict_rank_cap=0, taylor_rank=0) -> HParams:
+                 strict_rank_cap=0, taylor_rank=0, cluster=CLUSTER_BISECT) -> HParams:
     h = HParams()
     h.leaf, h.eta, h.n_block, h.aca_tol, h.max_rank = int(leaf), float(eta), int(n_block), float(aca_tol), int(max_rank)
     h.gather_waves, h.rank_bucket, h.strict_rank_cap = int(gather_waves), int(rank_bucket), int(strict_rank_cap)
-    h.taylor_rank = int(taylor_rank)
+    h.taylor_rank, h.cluster = int(taylor_rank), int(cluster)
     return h
 
 
@@ -310,7 +337,7 @@ class Op:
                    "hlevy_assemble")
         self.allocator = allocator   # must outlive the handle
         self.h = handle
-        self.N = prob.n if prob.dim == 1 else prob.n * prob.n
+        self.N = problem_N(prob)
         self.prob, self.hp = prob, hp
 
     def __del__(self):
@@ -475,15 +502,17 @@ def solve_noalloc(fac: Fac, b, x, refine=None, stats=False, stream=None):
 
 def krylov_solve(fac: Fac, b, x, method: int = KRYLOV_CG, max_iter: int = 200, tol: float = 1e-12,
                  shift: float = 0.0, precondition: bool = True, use_guess: bool = False,
-                 raise_not_converged: bool = True, stream=None):
+                 raise_not_converged: bool = True, op: Op | None = None, stream=None):
     """Solve (shift I - G) x = b by a Krylov iteration preconditioned with
     the factor (hlevy_krylov_solve).  b, x: (N,) contiguous float64 CUDA
     tensors.  Returns a dict with iterations, converged, rel_residual,
     seconds and the per-iteration relative residuals (history).  When tol
     is not met x holds the last iterate, and HlevyError (NOT_CONVERGED) is
-    raised unless raise_not_converged is False."""
+    raised unless raise_not_converged is False.  op: the operator G of the
+    iteration (default: the factor's own), e.g. a tighter compression of the
+    same problem, which the factor then preconditions."""
     o = KrylovOpts(int(method), int(max_iter), float(tol), float(shift), int(bool(precondition)),
-                   int(bool(use_guess)))
+                   int(bool(use_guess)), op.h.value if op is not None else None)
     st = KrylovStats()
     hist = (C.c_double * (int(max_iter) + 1))()
     rc = lib.hlevy_krylov_solve(fac.h, _dptr(b, fac.N), _dptr(x, fac.N), C.byref(o), C.byref(st), hist,
@@ -523,7 +552,7 @@ class Server:
         self._keep = {}   # id -> (u0, u_out): the output must outlive the request
 
     def submit(self, prob: Problem, hp: HParams, dt: float, nsteps: int, u0, u_out) -> int:
-        n = prob.n if prob.dim == 1 else prob.n * prob.n
+        n = problem_N(prob)
         rid = C.c_int64()
         _check(lib.hlevy_server_submit(self.h, C.byref(prob), C.byref(hp), float(dt), int(nsteps),
                                        _dptr(u0, n), _dptr(u_out, n), C.byref(rid)), "hlevy_server_submit")

@@ -1,5 +1,6 @@
 """Independent enumeration of the cluster tree and the block tree (test
-infrastructure): balanced bisection of the grid points, admissibility of
+infrastructure): balanced bisection (or recursive 2-means) of the grid
+points, admissibility of
 eq. equ:adm on point bounding boxes (App. B.1), N_max = ceil(N / N_block).
 Written from the definitions, sharing nothing with the library."""
 import math
@@ -17,11 +18,47 @@ def grid_points(dim, n, lo, hi):
     return np.stack([X.ravel(), Y.ravel()], 1)
 
 
-def clusters(points, leaf):
+def two_means(coords):
+    """Lloyd's iteration for two centres (Sec. 5.4, recursive K-means) on
+    integer coordinates (rows of `coords`, Python ints so every comparison
+    is exact).  Start: the first point of smallest and the first of largest
+    coordinate along the longest side (ties: first axis).  A point joins
+    the second centre only when strictly nearer; at most 64 passes, until
+    no point moves; a pass that empties a side is dropped.  Returns a
+    boolean array (True: second centre)."""
+    pts = [(int(a), int(b)) for a, b in coords]
+    ext = [max(p[a] for p in pts) - min(p[a] for p in pts) for a in (0, 1)]
+    ax = 1 if ext[1] > ext[0] else 0
+    vals = [p[ax] for p in pts]
+    ia, ib = vals.index(min(vals)), vals.index(max(vals))
+    cA, cB = [pts[ia], 1], [pts[ib], 1]      # (coordinate sums, count)
+
+    def sq(p, c):
+        (sx, sy), k = c
+        return (k * p[0] - sx) ** 2 + (k * p[1] - sy) ** 2
+
+    prev = None
+    for _ in range(64):
+        cur = [sq(p, cB) * cA[1] ** 2 < sq(p, cA) * cB[1] ** 2 for p in pts]
+        if cur == prev:
+            break
+        if not any(cur) or all(cur):
+            break
+        prev = cur
+        A = [p for p, c in zip(pts, cur) if not c]
+        B = [p for p, c in zip(pts, cur) if c]
+        cA = [(sum(p[0] for p in A), sum(p[1] for p in A)), len(A)]
+        cB = [(sum(p[0] for p in B), sum(p[1] for p in B)), len(B)]
+    return np.array(prev, dtype=bool)
+
+
+def clusters(points, leaf, coords=None):
     """Levels of the balanced cluster tree: every cluster of a level is split
     until all leaves hold at most `leaf` points.  1D: index halving
     (floor(n/2) first); 2D: the longest box side at its midpoint (ties: the
-    first axis).  Each cluster is an array of natural indices."""
+    first axis), or, with `coords` (integer grid coordinates of the points),
+    two_means of the cluster.  Each cluster is an array of natural indices
+    (the order inside a cluster is kept)."""
     N, d = points.shape
     level = [np.arange(N)]
     tree = [level]
@@ -31,6 +68,9 @@ def clusters(points, leaf):
             if d == 1:
                 h = len(idx) // 2
                 nxt += [idx[:h], idx[h:]]
+            elif coords is not None:
+                m = ~two_means(coords[idx])
+                nxt += [idx[m], idx[~m]]
             else:
                 p = points[idx]
                 lo, hi = p.min(0), p.max(0)

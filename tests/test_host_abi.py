@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(H):
     for name in names:
         assert hasattr(lib, name), name
     assert set(H.EXPORTS) == set(names)
-    assert H.lib.hlevy_abi_version() == 5
+    assert H.lib.hlevy_abi_version() == 6
 
 
 # ---------------------------------------------------------------------------
@@ -186,8 +186,10 @@ def test_server_submit_validates_like_assembly(H):
     try:
         rid = ctypes.c_int64()
         fake = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+        from workloads import lshape_mask
         for prob, hp in [(H.make_problem(1, 1 << 17, -1.0, 1.0, 0.5), H.make_hparams()),
-                         (H.make_problem(1, 1024, -1.0, 1.0, 0.5, r0=3.0), H.make_hparams())]:
+                         (H.make_problem(1, 1024, -1.0, 1.0, 0.5, r0=3.0), H.make_hparams()),
+                         (H.make_problem(2, 40, -1.0, 1.0, 0.5, mask=lshape_mask(40)), H.make_hparams())]:
             st = lib.hlevy_server_submit(srv, ctypes.byref(prob), ctypes.byref(hp), 1e-3, 10, fake, fake,
                                          ctypes.byref(rid))
             assert st == -1
@@ -312,3 +314,77 @@ def test_asymmetric_kernel_validation(H):
         H.plan_info(H.make_problem(2, 40, 0.0, 1.0, 0.5, lam=0.5, lam_neg=3.0), hp)
     with pytest.raises(H.HlevyError, match="lambda_neg"):
         H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, lam=0.5, lam_neg=-1.0), hp)
+
+
+# ---------------------------------------------------------------------------
+# masked domains, 2-means clustering, variable jump index (Sec. 5.4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,leaf,kmeans", [(16, 16, True), (30, 32, True), (40, 32, True), (40, 32, False),
+                                           (60, 64, True)])
+def test_lshape_tree_matches_enumeration(H, n, leaf, kmeans):
+    """The L-shaped domain's cluster and block trees (recursive 2-means on
+    the integer grid coordinates, or bisection) equal the independent
+    enumeration of tests/blocktree.py: depth, dense and low-rank leaves."""
+    from blocktree import blocks, clusters
+    from workloads import lshape_mask, variable_order_lshape
+    w = variable_order_lshape(n)
+    g = np.flatnonzero(lshape_mask(n).reshape(-1))
+    coords = np.stack([g // n, g % n], 1) if kmeans else None
+    tree = clusters(w["x"], leaf, coords)
+    bl = blocks(w["x"], tree)
+    prob = H.make_problem(2, n, -1.0, 1.0, 0.5, mask=w["mask"], s_field=w["s"])
+    info = H.plan_info(prob, H.make_hparams(leaf=leaf, cluster=H.CLUSTER_KMEANS if kmeans else H.CLUSTER_BISECT))
+    assert info["N"] == w["N"] == 3 * n * n // 4
+    assert info["depth"] == len(tree) - 1
+    assert info["n_dense"] == sum(1 for *_, a in bl if not a)
+    assert info["n_lowrank"] == sum(1 for *_, a in bl if a)
+    assert info["max_leaf_points"] == max(len(c) for c in tree[-1])
+    assert info["min_leaf_points"] == min(len(c) for c in tree[-1])
+
+
+def test_two_means_is_a_lloyd_fixed_point():
+    """Each split of the test enumeration's 2-means leaves every point with
+    the nearer of the two centres (ties with the first) and both sides
+    non-empty, and the first split of the L-shape separates its two arms."""
+    from blocktree import two_means
+    from workloads import lshape_mask
+    n = 30
+    g = np.flatnonzero(lshape_mask(n).reshape(-1))
+    coords = np.stack([g // n, g % n], 1)
+    side = two_means(coords)
+    assert side.any() and not side.all()
+    ca, cb = coords[~side].mean(0), coords[side].mean(0)
+    da = ((coords - ca) ** 2).sum(1)
+    db = ((coords - cb) ** 2).sum(1)
+    assert np.all(side == (db < da))
+
+
+def test_variable_order_validation(H):
+    """The variable-order kernel needs one index in (0, 1) per unknown; a
+    mask needs 2D; KMEANS is 2D; the server takes no mask."""
+    from workloads import lshape_mask
+    hp = H.make_hparams()
+    mask = lshape_mask(40)
+    ok = H.make_problem(2, 40, -1.0, 1.0, 0.5, mask=mask, s_field=np.full(1200, 0.5))
+    assert H.plan_info(ok, hp)["N"] == 1200
+    bad = H.make_problem(2, 40, -1.0, 1.0, 0.5, mask=mask, s_field=np.r_[np.full(1199, 0.5), 1.0])
+    with pytest.raises(H.HlevyError, match=r"s_field\[1199\]"):
+        H.plan_info(bad, hp)
+    p = H.make_problem(2, 40, -1.0, 1.0, 0.5)
+    p.kernel = H.KERNEL_VARIABLE_ORDER
+    with pytest.raises(H.HlevyError, match="needs s_field"):
+        H.plan_info(p, hp)
+    with pytest.raises(H.HlevyError, match="variable-order kernel only"):
+        q = H.make_problem(1, 256, -1.0, 1.0, 0.5, s_field=np.full(256, 0.5))
+        q.kernel = H.KERNEL_TEMPERED
+        H.plan_info(q, hp)
+    with pytest.raises(H.HlevyError, match="mask needs dim 2"):
+        H.plan_info(H.make_problem(1, 4, -1.0, 1.0, 0.5, mask=np.ones((4, 4))), hp)
+    with pytest.raises(H.HlevyError, match="2D only"):
+        H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5), H.make_hparams(cluster=H.CLUSTER_KMEANS))
+    with pytest.raises(H.HlevyError, match="cluster must be"):
+        H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5), H.make_hparams(cluster=2))
+    few = np.zeros((40, 40), dtype=bool)
+    few[0, :10] = True
+    with pytest.raises(H.HlevyError, match="twice the leaf"):
+        H.plan_info(H.make_problem(2, 40, -1.0, 1.0, 0.5, mask=few), hp)
