@@ -349,7 +349,9 @@ def bench_steady(H, torch, n=65536, s=0.5):
 # in seconds: construction, H-matvec, H-LU, H-solve (one right-hand side).
 PAPER_GAUSSIAN = {
     ("1d", 65536): {"construction": 4.224, "matvec": 0.0886, "lu": 4.970, "solve": 0.0881},
+    ("1d", 1048576): {"construction": 81.86, "matvec": 1.7325, "lu": 125.12, "solve": 1.4913},
     ("2d", 65536): {"construction": 48.78, "matvec": 0.2325, "lu": 22.97, "solve": 0.1036},
+    ("2d", 262144): {"construction": 272.11, "matvec": 1.3271, "lu": 95.65, "solve": 0.3101},
 }
 
 
@@ -362,7 +364,7 @@ def bench_gaussian(H, torch):
     refinement), each beside the paper's time for the same operation."""
     import numpy as np
     out = {}
-    for dim, n, n_block in ((1, 65536, 4), (2, 256, 4)):
+    for dim, n, n_block in ((1, 65536, 4), (1, 1 << 20, 4), (2, 256, 4), (2, 512, 4)):
         N = n ** dim
         prob = H.make_problem(dim, n, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=5.0)
         hp = H.make_hparams(leaf=64, eta=1.0, n_block=n_block, max_rank=16, taylor_rank=10)
@@ -403,7 +405,8 @@ def bench_gaussian(H, torch):
         key = "gauss%dd_n%d" % (dim, N)
         out[key] = {"N": N, "seconds": t, "paper_seconds": paper,
                     "speedup_vs_paper": {k: paper[k] / t[k] for k in t},
-                    "operator_MB": H.op_info(op)["device_bytes"] / 1e6, "n_block": n_block}
+                    "operator_MB": H.op_info(op)["device_bytes"] / 1e6,
+                    "factor_MB": H.fac_info(fac)["device_bytes"] / 1e6, "n_block": n_block}
         del fac, op
         progress(f"Gaussian kernel {key} done")
     out["note"] = ("M = I - dt/2 G with dt = 1 for the H-LU (the paper factors the system matrix of its "
@@ -476,13 +479,27 @@ def bench_varorder(H, torch):
         s0 = H.krylov_solve(fac, b, u0, method=H.KRYLOV_BICGSTAB, max_iter=5000, tol=1e-12, precondition=False,
                             op=fine, raise_not_converged=False)
         t["bicgstab_plain"] = time.perf_counter() - t0
+        # the mixed factor (FP32 inverse factors, lu_tol 1e-6) as the
+        # preconditioner instead of the FP64 one at eps2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fm = H.factor(coarse, dt, H.PREC_MIXED, 1e-6)
+        torch.cuda.synchronize()
+        t["h_lu_mixed"] = time.perf_counter() - t0
+        um = torch.zeros_like(f)
+        t0 = time.perf_counter()
+        sm = H.krylov_solve(fm, b, um, method=H.KRYLOV_BICGSTAB, max_iter=100, tol=1e-12, op=fine)
+        t["bicgstab_mixed_preconditioned"] = time.perf_counter() - t0
+        del fm
         uh = -0.5 * dt * x.cpu().numpy()
         ua = u.cpu().numpy()
         pd_, ph = PAPER_VARORDER[N]
         out["varorder_lshape_n%d" % N] = {
             "N": N, "seconds": t,
             "iterations": {"preconditioned": st["iterations"], "plain": s0["iterations"],
-                           "plain_converged": s0["converged"]},
+                           "plain_converged": s0["converged"], "mixed_preconditioned": sm["iterations"]},
+            "rel_l2_mixed_vs_fp64_preconditioned": float(np.linalg.norm(um.cpu().numpy() - u.cpu().numpy())
+                                                         / np.linalg.norm(u.cpu().numpy())),
             "rel_residual": st["rel_residual"],
             "h_solve_error": float(np.linalg.norm(uh - ua) / np.linalg.norm(ua)),
             "paper_solve_seconds": {"dense_lu": pd_, "h_lu": ph},

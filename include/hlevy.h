@@ -122,7 +122,8 @@ typedef struct {
 typedef struct {
   int32_t leaf;      /* max points per leaf cluster (N_min), 16..64 */
   double eta;        /* admissibility constant, > 0 */
-  int32_t n_block;   /* N_max = ceil(N / n_block); >= 1 */
+  int32_t n_block;   /* N_max = ceil(N / n_block); >= 1.  With ACA (taylor_rank 0) an admissible
+                        block has at most 16384 rows, so n_block >= N / 16384 */
   double aca_tol;    /* relative Frobenius tolerance of the far-field blocks */
   int32_t max_rank;  /* rank capacity of a low-rank block, 4..32 */
   int32_t gather_waves;    /* wavefronts per gather workgroup: 0 (8 single, 4 batched), 4 or 8 */

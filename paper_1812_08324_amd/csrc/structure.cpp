@@ -336,7 +336,8 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
     } else {
       s.n_lr++;
       // the ACA kernel marks used pivot rows in a bitmap of LR_ROWS_MAX bits
-      if (std::max(l.m, l.n) > LR_ROWS_MAX)
+      // (the Taylor construction runs no ACA)
+      if (hp.taylor_rank == 0 && std::max(l.m, l.n) > LR_ROWS_MAX)
         return "low-rank blocks are limited to " + std::to_string(LR_ROWS_MAX) + " rows (raise n_block)";
     }
   }
