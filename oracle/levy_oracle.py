@@ -70,6 +70,7 @@ __all__ = [
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
     "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
     "taylor_terms", "taylor_factors", "kernel_nu_signed", "exterior_forcing", "variable_order_generator",
+    "far_field",
 ]
 
 
@@ -433,6 +434,47 @@ def exterior_forcing(p: Problem, u_ext: np.ndarray) -> np.ndarray:
             acc += v * u_ext[q]
         g[i] = acc
     return g
+
+
+def far_field(p: Problem, u_ext: np.ndarray, next_: int, tail_left: float, tail_right: float) -> np.ndarray:
+    """The far-field term f^{L_W} of equ:I2approx (eq. equ:fxy) for an
+    exterior given on an extended lattice, 1D: row i takes
+    int_{|y| > L_W} u_ext(x_i + y) nu(y) dy by the trapezoid rule on the
+    lattice offsets k = NW .. next_ (NW = n + 1; weights h, h/2 at both
+    ends; nothing when next_ = NW), plus, beyond next_ h, the constant
+    tail_right (y > 0) or tail_left (y < 0) times the exact integral of nu
+    over that half-line (adaptive quadrature).  u_ext: next_ values left of
+    the box (lattice indices -next_ .. -1, ascending), then next_ right of
+    it (indices n .. n + next_ - 1)."""
+    if p.dim != 1:
+        raise ValueError("the far field is 1D")
+    c = quadrature_constants(p)
+    h, NW, n = c["h"], c["NW"], p.n
+    if next_ < NW:
+        raise ValueError("next_ must be at least n + 1")
+    u_ext = np.asarray(u_ext, dtype=np.float64)
+    if u_ext.shape != (2 * next_,):
+        raise ValueError("u_ext holds 2 next_ values")
+    left, right = u_ext[:next_], u_ext[next_:]
+
+    def nu(y):
+        return float(kernel_nu_signed(p, y) if p.lam_neg is not None else kernel_nu(p, abs(y)))
+
+    def tail(sign):
+        val, _ = integrate.quad(lambda y: nu(sign * y), next_ * h, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
+        return val
+
+    tp, tm = tail(1.0), tail(-1.0)
+    f = np.zeros(n)
+    for i in range(n):
+        acc = 0.0
+        if next_ > NW:
+            for k in range(NW, next_ + 1):
+                w = 0.5 * h if k in (NW, next_) else h
+                acc += w * nu(k * h) * right[i + k - n]          # lattice index i + k >= n
+                acc += w * nu(-k * h) * left[i - k + next_]      # lattice index i - k <= -1
+        f[i] = acc + tail_right * tp + tail_left * tm
+    return f
 
 
 # ---------------------------------------------------------------------------

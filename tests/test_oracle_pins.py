@@ -17,7 +17,7 @@ from oracle.levy_oracle import (Problem, ball_const, cn_run, cn_run_lean, frac_c
                                 gauss_const, generator_dense, generator_row,
                                 grid, h_of, kernel_nu, quadrature_constants, steady_solve, steady_residual,
                                 fractional_poisson_exact, taylor_factors, taylor_terms, exterior_forcing,
-                                variable_order_generator)
+                                variable_order_generator, far_field)
 
 
 def _order(e1, e2):
@@ -704,3 +704,65 @@ def test_lshape_distance_brute_force():
     assert np.abs(lshape_distance(x) - brute).max() < 1e-3
     s = 0.9 - 0.8 * lshape_distance(x)
     assert s.min() > 0.4 and s.max() < 0.9
+
+
+# ---------------------------------------------------------------------------
+# far field f^{L_W} of a non-zero exterior (Sec. 4, eqs. equ:fxy, equ:I2approx)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam_neg", [None, 2.5])
+def test_far_field_completes_the_constant(lam_neg):
+    """With constant tails beyond the window the far field is the tail
+    constant times the measure beyond the window, T of the quadrature
+    constants (per side for an asymmetric measure); with the window forcing
+    of the same constant, every row of G c + g + f vanishes."""
+    p = Problem(dim=1, n=60, s=0.65, lam=0.8, lam_neg=lam_neg, a=0.02, b=(0.3, 0.0))
+    NW = p.n + 1
+    c = 1.7
+    f = far_field(p, np.full(2 * NW, c), NW, c, c)
+    T = quadrature_constants(p)["T"]
+    assert np.allclose(f, c * T, rtol=1e-12, atol=0)
+    g = exterior_forcing(p, np.full(2 * NW, c))
+    G = generator_dense(p)
+    tot = G @ np.full(p.n, c) + g + f
+    assert np.abs(tot).max() <= 1e-12 * np.abs(G).max() * c
+
+
+def test_far_field_trapezoid_converges_to_the_integral():
+    """A smooth exterior u(x) = exp(-x^2) (negligible past the lattice):
+    the far field of a row converges at second order in h to the integral
+    over |y| > L_W of u(x_i + y) nu(y), done by adaptive quadrature."""
+    errs = []
+    for n in (40, 80, 160):
+        p = Problem(dim=1, n=n, s=0.6, lam=0.5)
+        h = h_of(p)
+        nx = int(math.ceil(9.0 / h))
+        xl = p.lo + h * (np.arange(-nx, 0) + 1)
+        xr = p.lo + h * (np.arange(n, n + nx) + 1)
+        u = lambda x: np.exp(-np.asarray(x) ** 2)
+        f = far_field(p, np.concatenate([u(xl), u(xr)]), nx, 0.0, 0.0)
+        i = n // 4
+        xi = p.lo + (i + 1) * h
+        LW = (n + 1) * h
+        nu = lambda y: p.Cval * math.exp(-p.lam * y) / y ** (1 + 2 * p.s)
+        ex = sum(integrate.quad(lambda y: nu(y) * float(u(xi + sg * y)), LW, np.inf, epsabs=0.0, epsrel=1e-12,
+                                limit=400)[0] for sg in (1.0, -1.0))
+        errs.append(abs(f[i] - ex) / abs(ex))
+    assert _order(errs[0], errs[1]) > 1.8 and _order(errs[1], errs[2]) > 1.8
+    assert errs[-1] < 1e-3      # h = 2/161: the trapezoid's h^2/12 scale
+
+
+def test_far_field_takes_each_side_with_its_rate():
+    """An exterior that is zero on the left: the asymmetric measure's far
+    field equals that of the symmetric measure with the right side's rate;
+    zero on the right, that of the left side's rate."""
+    n, nx = 30, 90
+    rng = np.random.default_rng(4)
+    ur = rng.uniform(0.0, 1.0, nx)
+    asym = Problem(dim=1, n=n, s=0.4, lam=0.7, lam_neg=3.0)
+    for side in ("right", "left"):
+        u = np.concatenate([np.zeros(nx), ur]) if side == "right" else np.concatenate([ur, np.zeros(nx)])
+        tl, tr = (0.0, 0.6) if side == "right" else (0.6, 0.0)
+        sym = Problem(dim=1, n=n, s=0.4, lam=0.7 if side == "right" else 3.0)
+        a = far_field(asym, u, nx, tl, tr)
+        b = far_field(sym, u, nx, tl, tr)
+        assert np.allclose(a, b, rtol=1e-12, atol=0), side
