@@ -93,7 +93,7 @@ typedef enum {
  * grid index p*n + q, N = number of kept points, and every vector of the
  * other calls is in that order.  mask and s_field are host arrays the
  * library reads during the call that takes the problem (it keeps copies);
- * the hlevy_server and hlevy_exterior_forcing calls take neither. */
+ * the hlevy_server and hlevy_exterior_forcing* calls take neither. */
 typedef struct {
   int32_t dim;       /* 1 or 2 */
   int32_t n;         /* interior grid points per axis, h = (hi - lo)/(n + 1); N = n^dim (mask: kept points) */
@@ -295,7 +295,26 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream)
  * buffers.  Synchronises `stream`. */
 hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream);
 
-/* Storage summary of the assembled operator.  Synchronises `stream`. *//* Storage summary of the assembled operator.  Synchronises `stream`. */
+/* Forcing of a non-zero exterior with its far field, 1D tempered kernels:
+ * g + f, with g as hlevy_exterior_forcing (from the n + 1 values of each
+ * side nearest the box) and f the far-field term f^{L_W} of equ:I2approx
+ * (eq. equ:fxy), which the paper leaves to an input or a quadrature.  Row i
+ * takes the trapezoid rule over the lattice offsets k = NW .. next
+ * (NW = n + 1), each side with its own kernel (nu(kh) to the right,
+ * nu(-kh) to the left) and weights h, h/2 at k = NW and k = next (nothing
+ * when next = NW); beyond next h the exterior is the constant tail_right
+ * (y > 0) or tail_left (y < 0), times the integral of nu over that half
+ * line (incomplete gamma function, each side with its rate).  u_ext
+ * (device, 2 next values): lattice points lo - (next-1)h .. lo ascending,
+ * then hi .. hi + (next-1)h; n + 1 <= next <= 2^26.  With next = n + 1 and
+ * zero tails the result is hlevy_exterior_forcing's; with a constant
+ * exterior c (tails c) G c + g + f = 0 in every row.  Errors as
+ * hlevy_exterior_forcing, and HLEVY_ERR_INVALID_ARG for next out of range
+ * or non-finite tails.  Synchronises `stream`. */
+hlevy_status hlevy_exterior_forcing_far(const hlevy_op* op, const double* u_ext, int32_t next, double tail_left,
+                                        double tail_right, double* g, void* stream);
+
+/* Storage summary of the assembled operator.  Synchronises `stream`. */
 hlevy_status hlevy_op_info(const hlevy_op* op, hlevy_op_info_t* out, void* stream);
 
 /* Storage summary of a factor.  Synchronises `stream`. */

@@ -21,6 +21,10 @@ hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double*
                            hipStream_t s);
 // Fixed-rank Taylor factors of the Gaussian kernel straight into the
 // admissible leaves ids[0..n) (rank set to r)
+// g += far field of an exterior on an extended lattice (1D); tab holds
+// 2 (next - n) + 2 doubles
+hipError_t launch_far_field(const ProblemDev& P, const double* u_ext, int next, double tail_left,
+                            double tail_right, double* tab, double* g, hipStream_t s);
 hipError_t launch_taylor(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids, int n,
                          int32_t* rank, int r, hipStream_t s);
 hipError_t launch_flush_lr(const LFlushTarget* tg, int ntg, const Term* terms, const ChunkItem* gram,

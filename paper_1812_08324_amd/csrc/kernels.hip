@@ -445,6 +445,51 @@ __global__ void __launch_bounds__(HL_BLOCK) k_ext_apply(const double* tab, const
   if (threadIdx.x == 0) g[i] = acc;
 }
 
+// Far field f^{L_W} (eq. equ:fxy) of an exterior on an extended lattice, 1D.
+// tab[2 (k - NW)] = W_k nu(kh), tab[2 (k - NW) + 1] = W_k nu(-kh) for
+// k = NW .. next (W_k = h, h/2 at both ends), and after them the integrals
+// of nu over y > next h and y < -next h.
+__device__ double tail_of_nu(const ProblemDev& P, double rate, double R) {
+  const double s = P.s;
+  if (rate == 0.0) return P.C * pow(R, -2.0 * s) / (2.0 * s);
+  return P.C * pow(rate, 2.0 * s) * upper_gamma(-2.0 * s, rate * R);
+}
+__global__ void __launch_bounds__(HL_BLOCK) k_far_table(ProblemDev P, int next, double* tab) {
+  const int NW = P.n + 1, cnt = next - NW + 1;
+  const int q = blockIdx.x * HL_BLOCK + threadIdx.x;
+  const double h = P.h;
+  if (q < cnt && next > NW) {
+    const int k = NW + q;
+    const double w = (k == NW || k == next) ? 0.5 * h : h;
+    tab[2 * q] = w * nu_jump1(P, k);
+    tab[2 * q + 1] = w * nu_jump1(P, -k);
+  }
+  if (q == 0) {
+    const double R = next * h;
+    const double rneg = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM ? P.lam_neg : P.lam;
+    tab[2 * cnt] = tail_of_nu(P, P.lam, R);
+    tab[2 * cnt + 1] = tail_of_nu(P, rneg, R);
+  }
+}
+// g[i] += the far field of row i: u_ext[0 .. next) are lattice indices
+// -next .. -1, u_ext[next .. 2 next) indices n .. n + next - 1.  One block
+// per row, fixed-order sum.
+__global__ void __launch_bounds__(HL_BLOCK) k_far_apply(const double* tab, const double* u_ext, int n, int next,
+                                                        double tail_left, double tail_right, double* g) {
+  __shared__ double red[4];
+  const int NW = n + 1, i = blockIdx.x, cnt = next - NW + 1;
+  const double* left = u_ext;
+  const double* right = u_ext + next;
+  double acc = 0.0;
+  if (next > NW)
+    for (int q = threadIdx.x; q < cnt; q += HL_BLOCK) {
+      const int k = NW + q;
+      acc += tab[2 * q] * right[i + k - n] + tab[2 * q + 1] * left[i - k + next];
+    }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) g[i] += acc + tail_right * tab[2 * cnt] + tail_left * tab[2 * cnt + 1];
+}
+
 // Fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3), one block per
 // admissible leaf: with xbar the centre of the row cluster's bounding box,
 // t0 = x_i - xbar and t = y_j - xbar per axis, column q holds
@@ -2509,6 +2554,13 @@ hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double*
   const int NW = P.n + 1;
   hipLaunchKernelGGL(k_ext_table, dim3((2 * NW + 1 + HL_BLOCK - 1) / HL_BLOCK), dim3(HL_BLOCK), 0, s, P, cst, tab);
   hipLaunchKernelGGL(k_ext_apply, dim3(P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, g);
+  return post();
+}
+hipError_t launch_far_field(const ProblemDev& P, const double* u_ext, int next, double tail_left,
+                            double tail_right, double* tab, double* g, hipStream_t s) {
+  const int cnt = next - (P.n + 1) + 1;
+  hipLaunchKernelGGL(k_far_table, dim3((cnt + HL_BLOCK - 1) / HL_BLOCK), dim3(HL_BLOCK), 0, s, P, next, tab);
+  hipLaunchKernelGGL(k_far_apply, dim3(P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, next, tail_left, tail_right, g);
   return post();
 }
 hipError_t launch_taylor(const ProblemDev& P, const int32_t* perm, const LeafDesc* L, const int32_t* ids, int n,

@@ -86,7 +86,7 @@ class TuneResult(C.Structure):
 
 
 EXPORTS = ["hlevy_abi_version", "hlevy_autotune", "hlevy_last_error", "hlevy_plan_info", "hlevy_footprint", "hlevy_assemble",
-           "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_exterior_forcing", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
+           "hlevy_assemble_batched", "hlevy_op_constants", "hlevy_exterior_forcing", "hlevy_exterior_forcing_far", "hlevy_op_info", "hlevy_fac_info", "hlevy_matvec",
            "hlevy_op_densify", "hlevy_factor", "hlevy_factor_batched", "hlevy_solve", "hlevy_solve_noalloc", "hlevy_krylov_solve", "hlevy_step",
            "hlevy_step_batched", "hlevy_fac_kernel_times", "hlevy_fac_apply", "hlevy_op_destroy", "hlevy_fac_destroy",
            "hlevy_server_create", "hlevy_server_submit", "hlevy_server_poll", "hlevy_server_take_failed",
@@ -135,6 +135,7 @@ def _load():
         "hlevy_op_constants": ([vp, C.POINTER(C.c_double), vp], st),
         "hlevy_op_info": ([vp, C.POINTER(OpInfo), vp], st),
         "hlevy_exterior_forcing": ([vp, vp, vp, vp], st),
+        "hlevy_exterior_forcing_far": ([vp, vp, C.c_int32, C.c_double, C.c_double, vp, vp], st),
         "hlevy_fac_info": ([vp, C.POINTER(FacInfo), vp], st),
         "hlevy_matvec": ([vp, vp, vp, vp], st),
         "hlevy_op_densify": ([vp, vp, vp], st),
@@ -396,6 +397,16 @@ def exterior_forcing(op: Op, u_ext, g, stream=None):
     n = op.N
     _check(lib.hlevy_exterior_forcing(op.h, _dptr(u_ext, 2 * (n + 1)), _dptr(g, n), _stream(stream)),
            "hlevy_exterior_forcing")
+
+
+def exterior_forcing_far(op: Op, u_ext, next_: int, tail_left: float, tail_right: float, g, stream=None):
+    """g = the exterior forcing with the far field f^{L_W}
+    (hlevy_exterior_forcing_far; 1D: u_ext holds next_ values left of the
+    box and next_ right of it, beyond them the constant tails)."""
+    n = op.N
+    _check(lib.hlevy_exterior_forcing_far(op.h, _dptr(u_ext, 2 * int(next_)), int(next_), float(tail_left),
+                                          float(tail_right), _dptr(g, n), _stream(stream)),
+           "hlevy_exterior_forcing_far")
 
 
 def op_info(op: Op, stream=None) -> dict:

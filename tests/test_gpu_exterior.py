@@ -7,7 +7,7 @@ against the oracle's CN with the same forcing (FP64 1e-10, mixed 1e-8).
 import numpy as np
 import pytest
 
-from oracle.levy_oracle import Problem, cn_run, exterior_forcing, generator_dense, quadrature_constants
+from oracle.levy_oracle import Problem, cn_run, exterior_forcing, far_field, generator_dense, quadrature_constants
 
 pytestmark = pytest.mark.gpu
 
@@ -107,3 +107,58 @@ def test_exterior_forcing_rejects(H):
     op2 = H.assemble(H.make_problem(2, 24, 0.0, 1.0, 0.5), H.make_hparams(aca_tol=1e-8, max_rank=32))
     out = torch.zeros(24 * 24, dtype=torch.float64, device="cuda")
     assert H.lib.hlevy_exterior_forcing(op2.h, buf.data_ptr(), out.data_ptr(), None) == -1
+
+
+FAR = {
+    "tempered_n400": Problem(dim=1, n=400, lo=-1.0, hi=1.0, s=0.75, lam=1.0, C=0.3, a=0.05, b=(0.5, 0.0)),
+    "asym_n377": Problem(dim=1, n=377, lo=-1.0, hi=1.0, s=0.6, lam=0.5, lam_neg=3.0, C=0.4, a=0.02, b=(0.3, 0.0)),
+}
+
+
+def extended_profile(p, nxt):
+    """The payoff-like exterior on next lattice points per side."""
+    h = (p.hi - p.lo) / (p.n + 1)
+    left = p.lo + h * np.arange(-nxt + 1, 1)
+    right = p.hi + h * np.arange(0, nxt)
+    return np.concatenate([1.0 - np.exp(left), np.exp(-right) - 1.0])
+
+
+@pytest.mark.parametrize("name", list(FAR))
+def test_far_field_matches_oracle(H, name):
+    """hlevy_exterior_forcing_far against the oracle's window forcing plus
+    far field (extended lattice of 2 (n + 1) + 5 points per side, tails 1 on
+    the left and -1 on the right: the profile's limits)."""
+    p = FAR[name]
+    op = assemble(H, p)
+    nxt = 2 * (p.n + 1) + 5
+    ue = extended_profile(p, nxt)
+    g = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    H.exterior_forcing_far(op, dev(ue), nxt, 1.0, -1.0, g)
+    NW = p.n + 1
+    ref = exterior_forcing(p, ue[nxt - NW: nxt + NW]) + far_field(p, ue, nxt, 1.0, -1.0)
+    assert rel(host(g), ref) <= 1e-13
+
+
+def test_far_field_edges_and_constant(H):
+    """next = n + 1 with zero tails is hlevy_exterior_forcing bit for bit; a
+    constant exterior with the same constant tails completes G c + g + f = 0;
+    next below n + 1 and non-finite tails are refused."""
+    p = FAR["asym_n377"]
+    op = assemble(H, p)
+    NW = p.n + 1
+    ue = dev(exterior_profile(p))
+    a = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    H.exterior_forcing(op, ue, a)
+    H.exterior_forcing_far(op, ue, NW, 0.0, 0.0, b)
+    assert torch.equal(a, b)
+    c = 0.7
+    H.exterior_forcing_far(op, dev(np.full(2 * NW, c)), NW, c, c, b)
+    y = torch.empty_like(a)
+    H.matvec(op, dev(np.full(p.n, c)), y)
+    scale = float(np.abs(host(b)).max())
+    assert np.abs(host(y) + host(b)).max() <= 1e-9 * scale
+    with pytest.raises(H.HlevyError, match="next"):
+        H.exterior_forcing_far(op, dev(np.zeros(2 * p.n)), p.n, 0.0, 0.0, b)
+    with pytest.raises(H.HlevyError, match="tail"):
+        H.exterior_forcing_far(op, ue, NW, float("nan"), 0.0, b)
