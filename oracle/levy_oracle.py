@@ -70,7 +70,7 @@ __all__ = [
     "quadrature_constants", "generator_row", "generator_dense", "cn_matrices",
     "cn_run", "kernel_nu", "steady_solve", "steady_residual", "fractional_poisson_exact",
     "taylor_terms", "taylor_factors", "kernel_nu_signed", "exterior_forcing", "variable_order_generator",
-    "far_field",
+    "far_field", "kernel_nu_tilted",
 ]
 
 
@@ -123,7 +123,7 @@ class Problem:
     jumps: bool = True           # False drops the jump operator (nu = 0)
     kernel: str = "tempered"     # or "gaussian"
     eps2: float = 0.0            # Gaussian kernel: nu(y) = C exp(-eps2 |y|^2)
-    lam_neg: float | None = None  # 1D tempered kernel: tempering rate for y < 0 (None: lam, symmetric)
+    lam_neg: float | None = None  # tempered kernel: rate of the jumps y_1 < 0 (None: lam, symmetric); 2D: tilted
 
     @property
     def N(self) -> int:
@@ -158,6 +158,19 @@ def kernel_nu_signed(p: Problem, y):
     lneg = p.lam if p.lam_neg is None else p.lam_neg
     rate = np.where(y > 0, p.lam, lneg)
     return p.Cval * np.exp(-rate * np.abs(y)) / np.abs(y) ** (1.0 + 2.0 * p.s)
+
+
+def kernel_nu_tilted(p: Problem, y1, y2):
+    """The 2D asymmetric tempered kernel at the jump (y1, y2) != 0: the
+    symmetric kernel tilted along the first axis,
+    C exp(-lam0 |y| + theta y1) / |y|^{2+2s} with lam0 = (lam + lam_neg)/2 and
+    theta = (lam_neg - lam)/2, so that the rate along the first axis is lam
+    for y1 > 0 and lam_neg for y1 < 0, as the 1D asymmetric kernel."""
+    y1 = np.asarray(y1, dtype=np.float64)
+    y2 = np.asarray(y2, dtype=np.float64)
+    lam0, th = 0.5 * (p.lam + p.lam_neg), 0.5 * (p.lam_neg - p.lam)
+    r = np.hypot(y1, y2)
+    return p.Cval * np.exp(-lam0 * r + th * y1) / r ** (2.0 + 2.0 * p.s)
 
 
 def kernel_nu(p: Problem, r):
@@ -254,6 +267,44 @@ def quadrature_constants(p: Problem) -> dict:
                                         LW, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
                 T += C * val
         return dict(S0=S0, S2=S2, C2=C2, T=T, S1=S1, h=h, NW=NW, m=m, r=r, LW=LW)
+    if d == 2 and p.lam_neg is not None:
+        # 2D asymmetric (tilted) measure: the u' sum S1 (first axis; the
+        # second vanishes by the y2 -> -y2 symmetry) and the u'' sums and
+        # integrals per axis (S2, C2 first axis, S2y, C2y second); the mixed
+        # ones vanish by the same symmetry
+        K1, K2 = np.meshgrid(k, k, indexing="ij")
+        K1 = K1.ravel(); K2 = K2.ravel()
+        nz2 = (K1 != 0) | (K2 != 0)
+        K1 = K1[nz2]; K2 = K2[nz2]
+        W = _trap_w(K1, NW, h) * _trap_w(K2, NW, h)
+        nu = kernel_nu_tilted(p, K1 * h, K2 * h)
+        rw = _rho_w(K1, m) * _rho_w(K2, m)
+        S0 = math.fsum(W * nu)
+        S2 = math.fsum(W * rw * nu * (K1 * h) ** 2)
+        S2y = math.fsum(W * rw * nu * (K2 * h) ** 2)
+        S1 = math.fsum(W * rw * nu * (K1 * h))
+        lam0, th = 0.5 * (p.lam + p.lam_neg), 0.5 * (p.lam_neg - p.lam)
+        a2 = 2.0 - 2.0 * s
+
+        def radial_c2(t):
+            # int_0^{r R(t)} C e^{-mu q} q^{1 - 2s} dq along the direction t
+            mu, R = lam0 - th * math.cos(t), r * _Rtheta(t)
+            if mu == 0.0:
+                return R ** a2 / a2
+            return mu ** (-a2) * sp.gammainc(a2, mu * R) * sp.gamma(a2)
+
+        def radial_t(t):
+            mu, R = lam0 - th * math.cos(t), LW * _Rtheta(t)
+            if mu == 0.0:
+                return R ** (-2.0 * s) / (2.0 * s)
+            v, _ = integrate.quad(lambda q: np.exp(-mu * q) * q ** (-1.0 - 2.0 * s), R, np.inf,
+                                  epsabs=0.0, epsrel=1e-13, limit=400)
+            return v
+
+        C2 = C * _quad_theta(lambda t: math.cos(t) ** 2 * radial_c2(t))
+        C2y = C * _quad_theta(lambda t: math.sin(t) ** 2 * radial_c2(t))
+        T = C * _quad_theta(radial_t)
+        return dict(S0=S0, S2=S2, C2=C2, T=T, S1=S1, S2y=S2y, C2y=C2y, h=h, NW=NW, m=m, r=r, LW=LW)
     if d == 1:
         kk = k[nz]
         w = _trap_w(kk, NW, h)
@@ -339,19 +390,30 @@ def generator_row(p: Problem, i: int, consts: dict | None = None) -> np.ndarray:
                 row[jj] += (beta + p.a) / h ** 2 + sgn * (p.b[0] - s1) / (2.0 * h)
         row[i] = -consts["S0"] - consts["T"] - 2.0 * (beta + p.a) / h ** 2 + p.c
         return row
-    # 2D, index = p1*n + q1 (first coordinate slowest)
+    # 2D, index = p1*n + q1 (first coordinate slowest).  An asymmetric
+    # measure has its own u'' coefficient per axis and the u' sum S1 of the
+    # first axis as a drift (symmetric: the same beta twice, S1 = 0)
     p1, q1 = divmod(i, n)
     P, Q = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     K1 = (P - p1).ravel(); K2 = (Q - q1).ravel()
     if p.jumps:
         off = (K1 != 0) | (K2 != 0)
-        row[off] = h * h * kernel_nu(p, np.hypot(K1[off] * h, K2[off] * h))
+        if p.lam_neg is None:
+            row[off] = h * h * kernel_nu(p, np.hypot(K1[off] * h, K2[off] * h))
+        else:
+            row[off] = h * h * kernel_nu_tilted(p, K1[off] * h, K2[off] * h)
+    betas = (beta, 0.5 * (consts["C2y"] - consts["S2y"]) if "C2y" in consts else beta)
+    drift = (p.b[0] - consts.get("S1", 0.0), p.b[1])
     for axis in (0, 1):
         for sgn in (-1, 1):
             pp, qq = p1 + (sgn if axis == 0 else 0), q1 + (sgn if axis == 1 else 0)
             if 0 <= pp < n and 0 <= qq < n:
-                row[pp * n + qq] += (beta + p.a) / h ** 2 + sgn * p.b[axis] / (2.0 * h)
-    row[i] = -consts["S0"] - consts["T"] - 4.0 * (beta + p.a) / h ** 2 + p.c
+                row[pp * n + qq] += (betas[axis] + p.a) / h ** 2 + sgn * drift[axis] / (2.0 * h)
+    if "C2y" in consts:
+        row[i] = (-consts["S0"] - consts["T"] - 2.0 * (betas[0] + p.a) / h ** 2 - 2.0 * (betas[1] + p.a) / h ** 2
+                  + p.c)
+    else:
+        row[i] = -consts["S0"] - consts["T"] - 4.0 * (beta + p.a) / h ** 2 + p.c
     return row
 
 

@@ -766,3 +766,75 @@ def test_far_field_takes_each_side_with_its_rate():
         a = far_field(asym, u, nx, tl, tr)
         b = far_field(sym, u, nx, tl, tr)
         assert np.allclose(a, b, rtol=1e-12, atol=0), side
+
+
+# ---------------------------------------------------------------------------
+# 2D asymmetric (tilted) measure (NEXT-3 reading)
+# ---------------------------------------------------------------------------
+def test_tilted_2d_reduces_to_symmetric_and_breaks_symmetry():
+    """lam_neg = lam: the constants and the generator of the symmetric 2D
+    kernel; lam_neg != lam: a u' sum on the first axis only, different u''
+    sums per axis, and a nonsymmetric generator."""
+    base = dict(dim=2, n=14, lo=-1.0, hi=1.0, s=0.55, lam=1.2, C=0.5, r0=0.3)
+    sym = quadrature_constants(Problem(**base))
+    eq = quadrature_constants(Problem(**base, lam_neg=1.2))
+    for key in ("S0", "S2", "C2", "T"):
+        assert eq[key] == pytest.approx(sym[key], rel=1e-11), key
+    assert eq["S1"] == 0.0 and eq["S2y"] == pytest.approx(sym["S2"], rel=1e-13)
+    assert eq["C2y"] == pytest.approx(sym["C2"], rel=1e-11)
+    Gs = generator_dense(Problem(**base))
+    Ge = generator_dense(Problem(**base, lam_neg=1.2))
+    assert np.abs(Ge - Gs).max() <= 1e-11 * np.abs(Gs).max()
+    q = quadrature_constants(Problem(**base, lam_neg=3.0))
+    assert q["S1"] > 0.0                      # more mass at y1 > 0 (rate 1.2 < 3)
+    assert abs(q["S2y"] - q["S2"]) > 1e-3 * q["S2"] and abs(q["C2y"] - q["C2"]) > 1e-3 * q["C2"]
+    G = generator_dense(Problem(**base, lam_neg=3.0))
+    assert not np.allclose(G, G.T)
+
+
+def test_tilted_2d_generator_converges_to_quadrature():
+    """Rates 0.5 (y1 > 0) and 2.5 (y1 < 0) along the first axis, s = 0.6:
+    the generator applied to a Gaussian bump (zero at the boundary to 1e-10)
+    converges at second order to the direct polar quadrature of
+    int (u(x+y) - u(x) - rho(y) y.grad u(x)) nu(y) dy, rho the indicator of
+    the square |y|_inf <= r0, at two grid points.  A wrong sign of S1 or a
+    swapped pair of per-axis u'' coefficients breaks the order."""
+    import warnings
+    s, lp, ln, C, r0 = 0.6, 0.5, 2.5, 0.4, 0.25
+    lam0, th = 0.5 * (lp + ln), 0.5 * (ln - lp)
+    u = lambda x1, x2: math.exp(-(x1 * x1 + x2 * x2) / 0.04)
+
+    def Lu(x1, x2):
+        g1, g2 = -2.0 * x1 / 0.04 * u(x1, x2), -2.0 * x2 / 0.04 * u(x1, x2)
+
+        def radial(phi):
+            c, sn = math.cos(phi), math.sin(phi)
+            R = r0 / max(abs(c), abs(sn))
+            f = lambda q: ((u(x1 + q * c, x2 + q * sn) - u(x1, x2) - (q * (c * g1 + sn * g2) if q <= R else 0.0))
+                           * C * math.exp(-lam0 * q + th * q * c) / q ** (1.0 + 2.0 * s))
+            tot = 0.0
+            for a, b in ((0.0, R), (R, 1.0), (1.0, np.inf)):
+                tot += integrate.quad(f, a, b, epsabs=1e-13, epsrel=1e-11, limit=200)[0]
+            return tot
+
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            return sum(integrate.quad(radial, q * math.pi / 4, (q + 1) * math.pi / 4, epsabs=1e-12, epsrel=1e-10,
+                                      limit=100)[0] for q in range(8))
+
+    pts = [(0.0, 0.0), (0.25, -0.25)]
+    ref = np.array([Lu(*x) for x in pts])
+    errs = []
+    for k in (5, 10, 20):
+        p = Problem(dim=2, n=8 * k - 1, lo=-1.0, hi=1.0, s=s, lam=lp, lam_neg=ln, C=C, r0=r0)
+        X = grid(p)
+        uu = np.exp(-(X ** 2).sum(1) / 0.04)
+        cst = quadrature_constants(p)
+        vals = []
+        for x in pts:
+            i = int(np.argmin(((X - np.asarray(x)) ** 2).sum(1)))
+            assert np.allclose(X[i], x, atol=1e-12)
+            vals.append(generator_row(p, i, cst) @ uu)
+        errs.append(np.abs(np.array(vals) - ref).max() / np.abs(ref).max())
+    print("tilted 2D errors", errs)
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0 and errs[2] < 1e-2, errs
