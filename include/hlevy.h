@@ -70,12 +70,16 @@ typedef enum {
   HLEVY_KERNEL_TEMPERED_ASYM = 2,
   HLEVY_KERNEL_VARIABLE_ORDER = 3
 } hlevy_kernel;
-/* TEMPERED_ASYM (1D only): the tempered kernel with rate lambda for jumps
- * y > 0 and lambda_neg for y < 0 (a CGMY-type measure; Sec. 2 and Sec. 4 allow
- * asymmetric measures).  The generator keeps the compensator of
- * equ:I1approx, int (u(x+y) - u(x) - rho(y) y u'(x)) nu(y) dy, whose u' sum
- * S1 = sum' w_k rho_k nu(kh) kh no longer vanishes: it enters the nearest
- * neighbours as a drift -S1 (central difference). */
+/* TEMPERED_ASYM: the tempered kernel with rate lambda for jumps y > 0 and
+ * lambda_neg for y < 0 (a CGMY-type measure; Sec. 2 and Sec. 4 allow
+ * asymmetric measures); in 2D the symmetric kernel tilted along the first
+ * axis, nu(y) = C exp(-lam0 |y| + theta y_1) / |y|^{2+2s} with
+ * lam0 = (lambda + lambda_neg)/2, theta = (lambda_neg - lambda)/2 (the same
+ * two rates along that axis).  The generator keeps the compensator of
+ * equ:I1approx, int (u(x+y) - u(x) - rho(y) y.grad u(x)) nu(y) dy, whose u'
+ * sum S1 = sum' w_k rho_k nu(kh) k_1 h no longer vanishes: it enters the
+ * nearest neighbours along the first axis as a drift -S1 (central
+ * difference); in 2D each axis has its own u'' coefficient (C2 - S2)/2. */
 /* VARIABLE_ORDER: the row of the point x_i takes its own jump index
  * s_i = s_field[i]: nu_i(y) = C_i exp(-lambda |y|) / |y|^{d+2 s_i} with
  * C_i = C when C > 0, else c_{d,s_i} (lambda = 0: the variable-order
@@ -277,7 +281,8 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
                                     const hlevy_allocator* alloc, void* stream, hlevy_op** out);
 
 /* Copy the quadrature constants S0, S2, C2, T (Sec. 4) and S1 (the u' sum of
- * an asymmetric measure, 0 otherwise) to host `out`.  Synchronises `stream`. */
+ * an asymmetric measure, 0 otherwise) to host `out`; for a 2D asymmetric
+ * measure S2 and C2 are those of the first axis.  Synchronises `stream`. */
 hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream);
 
 /* Forcing of a non-zero exterior, 1D tempered kernels (Sec. 4: the terms of

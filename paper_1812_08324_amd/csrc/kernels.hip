@@ -131,6 +131,16 @@ __device__ __forceinline__ double nu_jump1(const ProblemDev& P, int k) {
   return nu_at(P, r);
 }
 
+// 2D asymmetric tempered kernel at the jump (k1 h, k2 h): the symmetric
+// kernel tilted along the first axis, C exp(-lam0 |y| + theta y1) /
+// |y|^{2+2s}, lam0 = (lam + lam_neg)/2, theta = (lam_neg - lam)/2 (rates lam
+// and lam_neg along the first axis, as in 1D)
+__device__ __forceinline__ double nu_tilt2(const ProblemDev& P, int k1, int k2) {
+  const double r = P.h * sqrt((double)k1 * k1 + (double)k2 * k2);
+  const double lam0 = 0.5 * (P.lam + P.lam_neg), th = 0.5 * (P.lam_neg - P.lam);
+  return P.C * exp(-lam0 * r + th * (k1 * P.h)) / pow(r, 2.0 + 2.0 * P.s);
+}
+
 // lower incomplete gamma gamma(a, x) by its power series (x moderate)
 __device__ double lower_gamma(double a, double x) {
   if (x <= 0.0) return 0.0;
@@ -235,6 +245,7 @@ __device__ void constants_of(const ProblemDev& P, const double s_, const double 
     s = t;
   };
   double s1 = 0.0, s1c = 0.0;   // u' sum of an asymmetric measure
+  double s2y = 0.0, s2yc = 0.0; // u'' sum of the second axis (2D asymmetric)
   if (P.dim == 1 && P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) {
     for (int k = 1 + threadIdx.x; k <= NW; k += blockDim.x) {
       double w = (k == NW) ? 0.5 * h : h;
@@ -258,6 +269,24 @@ __device__ void constants_of(const ProblemDev& P, const double s_, const double 
         acc(s2, s2c, 2.0 * w * rho * nu * (k * h) * (k * h));
       }
     }
+  } else if (P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) {
+    // tilted 2D kernel: the u' sum S1 of the first axis, the u'' sums of
+    // both axes (the second axis's in s2y)
+    const int side = 2 * NW + 1;
+    const long total = (long)side * side;
+    for (long idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      int k1 = (int)(idx / side) - NW, k2 = (int)(idx % side) - NW;
+      if (k1 == 0 && k2 == 0) continue;
+      double w = ((abs(k1) == NW) ? 0.5 * h : h) * ((abs(k2) == NW) ? 0.5 * h : h);
+      double nu = nu_tilt2(P, k1, k2);
+      acc(s0, s0c, w * nu);
+      if (abs(k1) <= m && abs(k2) <= m) {
+        double rho = ((abs(k1) < m) ? 1.0 : 0.5) * ((abs(k2) < m) ? 1.0 : 0.5);
+        acc(s2, s2c, w * rho * nu * (k1 * h) * (k1 * h));
+        acc(s2y, s2yc, w * rho * nu * (k2 * h) * (k2 * h));
+        acc(s1, s1c, w * rho * nu * (k1 * h));
+      }
+    }
   } else {
     const int side = 2 * NW + 1;
     const long total = (long)side * side;
@@ -277,6 +306,7 @@ __device__ void constants_of(const ProblemDev& P, const double s_, const double 
   double S0 = block_sum(s0, red) + block_sum(s0c, red);
   double S2 = block_sum(s2, red) + block_sum(s2c, red);
   const double S1 = block_sum(s1, red) + block_sum(s1c, red);
+  const double S2y = block_sum(s2y, red) + block_sum(s2yc, red);
   if (threadIdx.x < 32) gauss_legendre(32, threadIdx.x, &glx[threadIdx.x], &glw[threadIdx.x]);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -294,6 +324,34 @@ __device__ void constants_of(const ProblemDev& P, const double s_, const double 
           T += C * pow(rate, 2.0 * s) * upper_gamma(-2.0 * s, rate * LW);
         }
       }
+    } else if (P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) {
+      // tilted 2D kernel: full circle, eight octants of 32 Gauss-Legendre
+      // nodes (R(phi) = 1 / max(|cos|, |sin|) is smooth inside each); along
+      // phi the rate is mu = lam0 - theta cos(phi)
+      const double lam0 = 0.5 * (lam + P.lam_neg), th = 0.5 * (P.lam_neg - lam);
+      double cx = 0.0, cy = 0.0, tt = 0.0;
+      for (int oct = 0; oct < 8; ++oct)
+        for (int q = 0; q < 32; ++q) {
+          const double ph = 0.125 * M_PI * (glx[q] + 1.0) + 0.25 * M_PI * oct, w = 0.125 * M_PI * glw[q];
+          const double c = cos(ph), sn = sin(ph);
+          const double R = 1.0 / fmax(fabs(c), fabs(sn));
+          const double mu = lam0 - th * c;
+          double rc, rt;
+          if (mu == 0.0) {
+            rc = pow(r * R, a2) / a2;
+            rt = pow(LW * R, -2.0 * s) / (2.0 * s);
+          } else {
+            rc = pow(mu, -a2) * lower_gamma(a2, mu * r * R);
+            rt = pow(mu, 2.0 * s) * upper_gamma(-2.0 * s, mu * LW * R);
+          }
+          cx += w * c * c * rc;
+          cy += w * sn * sn * rc;
+          tt += w * rt;
+        }
+      C2 = C * cx;
+      T = C * tt;
+      out[5] = S2y;
+      out[6] = C * cy;
     } else if (P.dim == 1) {
       if (lam == 0.0) {
         C2 = 2.0 * C * pow(r, a2) / a2;
@@ -357,6 +415,9 @@ __device__ __forceinline__ double gen_entry(const ProblemDev& P, const double* c
     cst = P.var_cst + 5 * (size_t)q;
   }
   const double beta = 0.5 * (cst[2] - cst[1]);
+  // 2D asymmetric measure: the second axis has its own u'' coefficient
+  const bool asym2 = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM && P.dim == 2;
+  const double beta_y = asym2 ? 0.5 * (cst[6] - cst[5]) : beta;
   int k1, k2 = 0;
   if (P.dim == 1) {
     k1 = j - i;
@@ -365,17 +426,21 @@ __device__ __forceinline__ double gen_entry(const ProblemDev& P, const double* c
     k1 = pj / P.n - pi / P.n;
     k2 = pj % P.n - pi % P.n;
   }
-  if (k1 == 0 && k2 == 0)
+  if (k1 == 0 && k2 == 0) {
+    if (asym2) return -cst[0] - cst[3] - 2.0 * (beta + P.a) / (h * h) - 2.0 * (beta_y + P.a) / (h * h) + P.c;
     return -cst[0] - cst[3] - 2.0 * P.dim * (beta + P.a) / (h * h) + P.c;
+  }
   double v;
   if (P.dim == 1) {
     v = h * (var ? nu_sc(P, fabs((double)k1) * h, s, C) : nu_jump1(P, k1));
+  } else if (asym2) {
+    v = h * h * nu_tilt2(P, k1, k2);
   } else {
     const double rr = h * sqrt((double)k1 * k1 + (double)k2 * k2);
     v = h * h * (var ? nu_sc(P, rr, s, C) : nu_at(P, rr));
   }
   if (abs(k1) + abs(k2) == 1) {
-    v += (beta + P.a) / (h * h);
+    v += ((k1 == 0 ? beta_y : beta) + P.a) / (h * h);
     // drift by the central difference; an asymmetric measure adds -S1 (the
     // u' sum of equ:I1approx, cst[4], zero otherwise)
     const double b0 = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM ? P.b0 - cst[4] : P.b0;
@@ -401,6 +466,7 @@ __device__ __forceinline__ double far_entry(const ProblemDev& P, const int32_t* 
     return (P.dim == 1 ? P.h : P.h * P.h) * nu_sc(P, r, P.var_s[q], P.var_C[q]);
   }
   if (P.dim == 1) return P.h * nu_jump1(P, k1);
+  if (P.kernel == HLEVY_KERNEL_TEMPERED_ASYM) return P.h * P.h * nu_tilt2(P, k1, k2);
   double rr = P.h * sqrt((double)k1 * k1 + (double)k2 * k2);
   return P.h * P.h * nu_at(P, rr);
 }

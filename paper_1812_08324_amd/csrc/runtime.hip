@@ -1597,9 +1597,11 @@ static size_t footprint_bytes(const Structure& S, int kcap, int prec) {
     return round8(t.pool_doubles * sizeof(double)) + round8(nl * sizeof(LeafDesc)) + round8(nl * sizeof(int32_t));
   };
   size_t b = 0;
-  // structure lists, constants, overflow counter
+  // structure lists, point maps, constants, overflow counter
   b += 2 * round8((P + 1) * 4) + round8(S.rowidx.size() * 4) + round8(S.colidx.size() * 4) + 2 * round8(P * 4) +
-       round8(N * 4) + 64 * 64 * sizeof(double) + 40 + 8;
+       2 * round8(N * 4) + 64 * 64 * sizeof(double) + 7 * sizeof(double) + 8;
+  if (!S.var_s.empty())   // variable order: values, kernel constants, quadrature constants, row map
+    b += 2 * round8(S.var_s.size() * 8) + round8(S.var_s.size() * 5 * 8) + round8(N * 4);
   HMat g;
   g.layout(S, kcap, FULL, false);
   b += hmat(g) + 2 * N * sizeof(double) + mvplan_bytes_bound(S, g, MV_FMT_F64);
@@ -2277,7 +2279,7 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
     {
       AllocScope own(&op->actx);
       op->ds.create(S, s);
-      op->cst.alloc(5 * sizeof(double));
+      op->cst.alloc(7 * sizeof(double));   // S0, S2, C2, T, S1 (+ S2, C2 of the second axis, 2D asymmetric)
       op->ovf.alloc(sizeof(int32_t));
       op->G.create(S, hp->max_rank, FULL, s);
     }

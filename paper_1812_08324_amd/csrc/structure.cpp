@@ -213,7 +213,6 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   else if (hp.cluster != HLEVY_CLUSTER_BISECT && hp.cluster != HLEVY_CLUSTER_KMEANS)
     err << "cluster must be HLEVY_CLUSTER_BISECT or HLEVY_CLUSTER_KMEANS";
   else if (hp.cluster == HLEVY_CLUSTER_KMEANS && p.dim != 2) err << "KMEANS clustering is 2D only";
-  else if (p.kernel == HLEVY_KERNEL_TEMPERED_ASYM && p.dim != 1) err << "the asymmetric kernel is 1D only";
   else if (p.kernel == HLEVY_KERNEL_TEMPERED_ASYM && (!(p.lambda_neg >= 0.0) || !std::isfinite(p.lambda_neg)))
     err << "lambda_neg must be >= 0";
   else if (p.kernel != HLEVY_KERNEL_GAUSSIAN && p.kernel != HLEVY_KERNEL_VARIABLE_ORDER && !(p.s > 0.0 && p.s < 1.0))

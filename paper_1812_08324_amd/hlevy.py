@@ -210,8 +210,9 @@ CLUSTER_BISECT, CLUSTER_KMEANS = 0, 1
 
 def make_problem(dim, n, lo, hi, s, lam=0.0, C_=None, a=0.0, b=(0.0, 0.0), c=0.0, r0=0.2, kernel=0,
                  eps2=0.0, lam_neg=None, mask=None, s_field=None) -> Problem:
-    """lam_neg: the tempering rate of the jumps y < 0 (1D); given, the kernel
-    is HLEVY_KERNEL_TEMPERED_ASYM with lam for y > 0.  mask (2D): n x n
+    """lam_neg: the tempering rate of the jumps y < 0 (2D: y_1 < 0, the kernel
+    tilted along the first axis); given, the kernel is
+    HLEVY_KERNEL_TEMPERED_ASYM with lam for y > 0.  mask (2D): n x n
     array, nonzero = grid point in the domain.  s_field: one jump index per
     unknown (natural order); given, the kernel is HLEVY_KERNEL_VARIABLE_ORDER.
     The problem keeps its own copies of both arrays."""

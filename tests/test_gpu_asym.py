@@ -102,3 +102,53 @@ def test_asym_trajectories_and_steady_solve(H):
     st = H.krylov_solve(fac, dev(b), y, method=H.KRYLOV_BICGSTAB, max_iter=50, tol=1e-12, shift=2.0 / dt)
     assert st["converged"] and st["iterations"] <= 5, st
     assert rel(host(y), steady_solve(G, 2.0 / dt, b)) <= 1e-10
+
+
+def test_asym_2d_tilted(H):
+    """The 2D asymmetric measure (tilted along the first axis, rates 0.5 and
+    3 on it) on 30^2: the five constants, every near-field entry (which
+    holds the second axis's u'' coefficient) and every admissible block
+    (ACA at 1e-8, as the 2D workloads) against the oracle; Crank-Nicolson trajectories (FP64 1e-10, mixed
+    1e-8) and a BiCGSTAB steady solve (1e-10)."""
+    p = Problem(dim=2, n=30, lo=-1.0, hi=1.0, s=0.6, lam=0.5, lam_neg=3.0, C=0.4, a=0.02, b=(0.3, -0.1))
+    prob = H.make_problem(2, p.n, p.lo, p.hi, p.s, lam=p.lam, C_=p.C, a=p.a, b=p.b, c=p.c, r0=p.r0,
+                          lam_neg=p.lam_neg)
+    op = H.assemble(prob, H.make_hparams(aca_tol=1e-8, max_rank=32))   # the 2D workloads' tolerance
+    ref = quadrature_constants(p)
+    for g, key in zip(H.op_constants(op), ("S0", "S2", "C2", "T", "S1")):
+        assert g == pytest.approx(ref[key], rel=1e-11), key
+    assert abs(ref["S2y"] - ref["S2"]) > 1e-3 * ref["S2"]
+    N = p.N
+    dense = torch.empty(N * N, dtype=torch.float64, device="cuda")
+    H.op_densify(op, dense)
+    Hd = dense.view(N, N).cpu().numpy()
+    G = generator_dense(p)
+    pts = grid_points(2, p.n, p.lo, p.hi)
+    worst = 0.0
+    for I, J, adm in blocks(pts, clusters(pts, 64)):
+        A = G[np.ix_(I, J)]
+        E = Hd[np.ix_(I, J)] - A
+        if adm:
+            e = np.linalg.norm(E) / np.linalg.norm(A)
+            worst = max(worst, e)
+            assert e <= 10 * 1e-8, (I[0], J[0], e)
+        else:
+            assert np.abs(E).max() <= 1e-12 * np.abs(A).max(), (I[0], J[0])
+    x = pts
+    u0 = np.exp(-(x ** 2).sum(1) / 0.05)
+    dt, steps = 1e-3, 30
+    cn = cn_run(G, dt, steps, u0).u
+    for prec, lu_tol, bar in ((H.PREC_FP64, 1e-12, 1e-10), (H.PREC_MIXED, 1e-6, 1e-8)):
+        f = H.factor(op, dt, prec, lu_tol)
+        u = dev(u0)
+        H.step(f, u, steps, refine={"sweeps": 1})
+        err = rel(host(u), cn)
+        print(f"2D asym trajectory prec {prec}: {err:.2e}")
+        assert err <= bar, (prec, err)
+    fac = H.factor(op, dt, H.PREC_MIXED, 1e-6)
+    b = np.cos(2 * x[:, 0]) * np.sin(3 * x[:, 1] + 0.2)
+    y = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st = H.krylov_solve(fac, dev(b), y, method=H.KRYLOV_BICGSTAB, max_iter=50, tol=1e-12, shift=2.0 / dt)
+    assert st["converged"] and st["iterations"] <= 5, st
+    assert rel(host(y), steady_solve(G, 2.0 / dt, b)) <= 1e-10
+    print(f"2D asym: S1 {ref['S1']:.4e}, worst admissible block {worst:.2e}")

@@ -307,11 +307,11 @@ def test_gaussian_validation(H):
 
 
 def test_asymmetric_kernel_validation(H):
-    """The asymmetric tempered kernel is 1D only and needs lambda_neg >= 0."""
+    """The asymmetric tempered kernel (1D, and 2D tilted along the first
+    axis) needs lambda_neg >= 0."""
     hp = H.make_hparams()
     H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, lam=0.5, lam_neg=3.0), hp)
-    with pytest.raises(H.HlevyError, match="1D only"):
-        H.plan_info(H.make_problem(2, 40, 0.0, 1.0, 0.5, lam=0.5, lam_neg=3.0), hp)
+    assert H.plan_info(H.make_problem(2, 40, 0.0, 1.0, 0.5, lam=0.5, lam_neg=3.0), hp)["N"] == 1600
     with pytest.raises(H.HlevyError, match="lambda_neg"):
         H.plan_info(H.make_problem(1, 256, -1.0, 1.0, 0.5, lam=0.5, lam_neg=-1.0), hp)
 
