@@ -468,9 +468,12 @@ hlevy_status hlevy_step_batched(hlevy_fac* const* facs, double* const* u, const 
  * M = I - dt/2 G is close to a multiple of shift I - G, i.e. 2/dt near
  * shift (for shift = 0: dt large against 1/lambda_min(-G)).  Methods:
  * HLEVY_KRYLOV_CG for a symmetric positive definite shift I - G (symmetric
- * jump kernel, no drift), HLEVY_KRYLOV_BICGSTAB for any operator.
- * Deterministic: every reduction runs in a fixed order. */
-typedef enum { HLEVY_KRYLOV_CG = 0, HLEVY_KRYLOV_BICGSTAB = 1 } hlevy_krylov_method;
+ * jump kernel, no drift), HLEVY_KRYLOV_BICGSTAB and HLEVY_KRYLOV_GMRES
+ * (restarted, right-preconditioned: the residual it minimises is that of
+ * the unpreconditioned system; Gram-Schmidt applied twice; the Givens
+ * rotations and the small least-squares problem on the host) for any
+ * operator.  Deterministic: every reduction runs in a fixed order. */
+typedef enum { HLEVY_KRYLOV_CG = 0, HLEVY_KRYLOV_BICGSTAB = 1, HLEVY_KRYLOV_GMRES = 2 } hlevy_krylov_method;
 typedef struct {
   int32_t method;        /* hlevy_krylov_method */
   int32_t max_iter;      /* >= 1 */
@@ -482,6 +485,8 @@ typedef struct {
                             cluster tree ordering (same problem and tree parameters, e.g. a tighter
                             aca_tol), so that a coarse factor preconditions an accurate operator as
                             in Sec. 5.4 (preconditioner from eps1 = 1e-4, iteration on A) */
+  int32_t restart;       /* GMRES: Arnoldi steps per cycle, 1..64 (0: 30); ignored otherwise */
+  int32_t pad;
 } hlevy_krylov;
 typedef struct {
   int32_t iterations;    /* iterations taken (a BiCGSTAB iteration is two products with G) */
@@ -497,7 +502,8 @@ typedef struct {
  * also when tol is not met; the call then returns HLEVY_ERR_NOT_CONVERGED
  * (stats filled).  A zero right-hand side gives x = 0 after no iteration.
  * Errors: HLEVY_ERR_INVALID_ARG for a bad option or overlapping b and x.
- * Synchronises `stream` once per iteration (twice for BiCGSTAB). */
+ * Synchronises `stream` once per iteration (twice for BiCGSTAB; GMRES once
+ * per Arnoldi step and once per restart). */
 hlevy_status hlevy_krylov_solve(hlevy_fac* fac, const double* b, double* x, const hlevy_krylov* opt,
                                 hlevy_krylov_stats* stats, double* history, void* stream);
 

@@ -86,6 +86,12 @@ struct KrRatios {
   int32_t n, pad;
 };
 // partial holds KR_MAXDOT * kr_blocks(N) doubles
+// GMRES: out[c] = (V column c, w) for c < ncol (fixed-order reduction;
+// partial holds ncol * kr_blocks(N) doubles), and out = base + sign V coef
+hipError_t launch_gm_dots(const double* V, int ld, int ncol, const double* w, int N, double* partial, double* out,
+                          hipStream_t s);
+hipError_t launch_gm_comb(double* out, const double* base, const double* V, int ld, int ncol, const double* coef,
+                          double sign, int N, hipStream_t s);
 int kr_blocks(int N);
 hipError_t launch_kr_dots(const KrDots& d, int N, double* partial, double* sc, hipStream_t s);
 hipError_t launch_kr_scalars(const KrRatios& q, double* sc, hipStream_t s);

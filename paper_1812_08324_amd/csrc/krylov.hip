@@ -92,7 +92,58 @@ __global__ void __launch_bounds__(KB) k_kr_comb(double* out, const double* x0, K
   out[i] = v;
 }
 
+// GMRES (classical Gram-Schmidt, applied twice): partial[c * gridDim.x +
+// block] = sum over the block's rows of V[c ld + i] w[i], c < ncol
+__global__ void __launch_bounds__(KB) k_gm_dot_partial(const double* V, int ld, int ncol, const double* w, int N,
+                                                       double* partial) {
+  __shared__ double red[4];
+  for (int c = 0; c < ncol; ++c) {
+    const double* vc = V + (size_t)c * ld;
+    double acc = 0.0;
+    for (int i = blockIdx.x * KB + threadIdx.x; i < N; i += gridDim.x * KB) acc += vc[i] * w[i];
+    const double tsum = block_total(acc, red);
+    if (threadIdx.x == 0) partial[(size_t)c * gridDim.x + blockIdx.x] = tsum;
+  }
+}
+
+// out[c] = sum of the nb partials of column c, in block order
+__global__ void __launch_bounds__(KB) k_gm_dot_final(const double* partial, int nb, int ncol, double* out) {
+  __shared__ double red[4];
+  for (int c = 0; c < ncol; ++c) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += KB) a += partial[(size_t)c * nb + i];
+    const double tsum = block_total(a, red);
+    if (threadIdx.x == 0) out[c] = tsum;
+  }
+}
+
+// out[i] = (base ? base[i] : 0) + sign * sum_{c < ncol} coef[c] V[c ld + i]
+// (c in increasing order; out may alias base)
+__global__ void __launch_bounds__(KB) k_gm_comb(double* out, const double* base, const double* V, int ld, int ncol,
+                                                const double* coef, double sign, int N) {
+  const int i = blockIdx.x * KB + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0.0;
+  for (int c = 0; c < ncol; ++c) acc += coef[c] * V[(size_t)c * ld + i];
+  out[i] = (base ? base[i] : 0.0) + sign * acc;
+}
+
 }  // namespace
+
+hipError_t launch_gm_dots(const double* V, int ld, int ncol, const double* w, int N, double* partial, double* out,
+                          hipStream_t s) {
+  if (ncol < 1) return hipErrorInvalidValue;
+  const int nb = kr_blocks(N);
+  hipLaunchKernelGGL(k_gm_dot_partial, dim3(nb), dim3(KB), 0, s, V, ld, ncol, w, N, partial);
+  hipLaunchKernelGGL(k_gm_dot_final, dim3(1), dim3(KB), 0, s, partial, nb, ncol, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_comb(double* out, const double* base, const double* V, int ld, int ncol, const double* coef,
+                          double sign, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_comb, dim3((N + KB - 1) / KB), dim3(KB), 0, s, out, base, V, ld, ncol, coef, sign, N);
+  return hipGetLastError();
+}
 
 int kr_blocks(int N) { return std::min(512, std::max(1, (N + KB - 1) / KB)); }
 

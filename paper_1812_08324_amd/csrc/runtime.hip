@@ -3055,8 +3055,10 @@ hlevy_status hlevy_krylov_solve(hlevy_fac* f, const double* b, double* x, const 
   if (!f || !b || !x || !opt) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
   const int N = f->op->S.N;
   if (b < x + N && x < b + N) return fail(HLEVY_ERR_INVALID_ARG, "b and x must not overlap");
-  if (opt->method != HLEVY_KRYLOV_CG && opt->method != HLEVY_KRYLOV_BICGSTAB)
-    return fail(HLEVY_ERR_INVALID_ARG, "method must be HLEVY_KRYLOV_CG or HLEVY_KRYLOV_BICGSTAB");
+  if (opt->method != HLEVY_KRYLOV_CG && opt->method != HLEVY_KRYLOV_BICGSTAB && opt->method != HLEVY_KRYLOV_GMRES)
+    return fail(HLEVY_ERR_INVALID_ARG, "method must be HLEVY_KRYLOV_CG, HLEVY_KRYLOV_BICGSTAB or HLEVY_KRYLOV_GMRES");
+  if (opt->method == HLEVY_KRYLOV_GMRES && (opt->restart < 0 || opt->restart > 64))
+    return fail(HLEVY_ERR_INVALID_ARG, "restart must lie in [0, 64]");
   if (opt->max_iter < 1) return fail(HLEVY_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (!(opt->tol >= 0.0) || !std::isfinite(opt->tol)) return fail(HLEVY_ERR_INVALID_ARG, "tol must be finite and >= 0");
   if (!std::isfinite(opt->shift)) return fail(HLEVY_ERR_INVALID_ARG, "shift must be finite");
@@ -3181,6 +3183,84 @@ hlevy_status hlevy_krylov_solve(hlevy_fac* f, const double* b, double* x, const 
           if (converged || !std::isfinite(rel)) break;
           ratios({KrRatio{S_BETA, S_RZ, S_RZOLD, -1, -1, -1, -1, 0}});
           comb(p, z, one, p, sc_coef(S_BETA, 1.0));
+        }
+      } else if (opt->method == HLEVY_KRYLOV_GMRES) {
+        // restarted GMRES, right-preconditioned: Arnoldi on A M^{-1} with
+        // classical Gram-Schmidt applied twice (coefficients reduced on the
+        // device, read back once per step with the new vector's norm), the
+        // Givens rotations and the least-squares solve on the host, and
+        // x += M^{-1} V y at the end of each cycle
+        const int m = opt->restart > 0 ? opt->restart : 30;
+        const int nbk = kr_blocks(N);
+        DevBuf gw;
+        gw.alloc(((size_t)(m + 1) * N + (size_t)(m + 1) * nbk + 3 * (size_t)(m + 1)) * sizeof(double));
+        double* V = gw.as<double>();
+        double* gpart = V + (size_t)(m + 1) * N;
+        double* h1 = gpart + (size_t)(m + 1) * nbk;   // first pass coefficients, then the norm at [j + 1]
+        double* h2 = h1 + (m + 1);                     // second pass
+        double* yc = h2 + (m + 1);                     // the cycle's solution coefficients
+        double *xv = v[V_X], *r = v[V_R], *w = v[V_Q], *z = v[V_Z], *pz = v[V_P];
+        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hb(2 * (m + 1)), y(m);
+        double beta = std::sqrt(host[S_RR]);
+        while (!converged && it < opt->max_iter && std::isfinite(rel) && beta > 0.0) {
+          comb(V, r, KrCoef{-1, 0, 1.0 / beta});
+          std::fill(g.begin(), g.end(), 0.0);
+          g[0] = beta;
+          int jend = 0;
+          for (int j = 0; j < m && it < opt->max_iter; ++j) {
+            ++it;
+            double* vj = V + (size_t)j * N;
+            precond(vj, z);
+            apply_A(z, w);
+            HL_CHECK(launch_gm_dots(V, N, j + 1, w, N, gpart, h1, s));
+            HL_CHECK(launch_gm_comb(w, w, V, N, j + 1, h1, -1.0, N, s));
+            HL_CHECK(launch_gm_dots(V, N, j + 1, w, N, gpart, h2, s));
+            HL_CHECK(launch_gm_comb(w, w, V, N, j + 1, h2, -1.0, N, s));
+            HL_CHECK(launch_gm_dots(w, N, 1, w, N, gpart, h1 + j + 1, s));
+            HL_CHECK(hipMemcpyAsync(hb.data(), h1, 2 * (m + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HL_CHECK(hipStreamSynchronize(s));
+            double* hc = H.data() + (size_t)j * (m + 1);   // column j of the Hessenberg matrix
+            for (int i = 0; i <= j; ++i) hc[i] = hb[i] + hb[(m + 1) + i];
+            const double hn = std::sqrt(hb[j + 1]);
+            hc[j + 1] = hn;
+            jend = j + 1;
+            if (hn > 0.0) comb(V + (size_t)(j + 1) * N, w, KrCoef{-1, 0, 1.0 / hn});
+            for (int i = 0; i < j; ++i) {   // earlier rotations
+              const double a0 = hc[i], a1 = hc[i + 1];
+              hc[i] = cs[i] * a0 + sn[i] * a1;
+              hc[i + 1] = -sn[i] * a0 + cs[i] * a1;
+            }
+            const double den = std::hypot(hc[j], hc[j + 1]);
+            cs[j] = den > 0.0 ? hc[j] / den : 1.0;
+            sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
+            hc[j] = den;
+            hc[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            rel = std::fabs(g[j + 1]) / bnorm;
+            if (history) history[it] = rel;
+            converged = std::isfinite(rel) && rel <= tol;
+            if (converged || !std::isfinite(rel) || hn == 0.0) break;
+          }
+          // y = R^{-1} g (back substitution), x += M^{-1} V y
+          for (int i = jend - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)k * (m + 1) + i] * y[k];
+            y[i] = acc / H[(size_t)i * (m + 1) + i];
+          }
+          HL_CHECK(hipMemcpyAsync(yc, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, s));
+          HL_CHECK(launch_gm_comb(w, nullptr, V, N, jend, yc, 1.0, N, s));
+          precond(w, pz);
+          comb(xv, xv, one, pz, one);
+          if (converged || !std::isfinite(rel) || it >= opt->max_iter) break;
+          // restart from the true residual
+          apply_A(xv, w);
+          comb(r, v[V_B], one, w, minus);
+          dots({dot_to(r, r, S_RR)});
+          read();
+          beta = std::sqrt(host[S_RR]);
+          rel = beta / bnorm;
+          converged = rel <= tol;
         }
       } else {
         double *r = v[V_R], *p = v[V_P], *vv = v[V_Q], *y = v[V_Z], *t = v[V_T], *sv = v[V_S], *rh = v[V_RH],

@@ -93,12 +93,13 @@ EXPORTS = ["hlevy_abi_version", "hlevy_autotune", "hlevy_last_error", "hlevy_pla
            "hlevy_server_stats_get", "hlevy_server_destroy"]
 
 
-KRYLOV_CG, KRYLOV_BICGSTAB = 0, 1
+KRYLOV_CG, KRYLOV_BICGSTAB, KRYLOV_GMRES = 0, 1, 2
 
 
 class KrylovOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double), ("shift", C.c_double),
-                ("precondition", C.c_int32), ("use_guess", C.c_int32), ("op", C.c_void_p)]
+                ("precondition", C.c_int32), ("use_guess", C.c_int32), ("op", C.c_void_p),
+                ("restart", C.c_int32), ("pad", C.c_int32)]
 
 
 class KrylovStats(C.Structure):
@@ -514,7 +515,7 @@ def solve_noalloc(fac: Fac, b, x, refine=None, stats=False, stream=None):
 
 def krylov_solve(fac: Fac, b, x, method: int = KRYLOV_CG, max_iter: int = 200, tol: float = 1e-12,
                  shift: float = 0.0, precondition: bool = True, use_guess: bool = False,
-                 raise_not_converged: bool = True, op: Op | None = None, stream=None):
+                 raise_not_converged: bool = True, op: Op | None = None, restart: int = 0, stream=None):
     """Solve (shift I - G) x = b by a Krylov iteration preconditioned with
     the factor (hlevy_krylov_solve).  b, x: (N,) contiguous float64 CUDA
     tensors.  Returns a dict with iterations, converged, rel_residual,
@@ -522,9 +523,10 @@ def krylov_solve(fac: Fac, b, x, method: int = KRYLOV_CG, max_iter: int = 200, t
     is not met x holds the last iterate, and HlevyError (NOT_CONVERGED) is
     raised unless raise_not_converged is False.  op: the operator G of the
     iteration (default: the factor's own), e.g. a tighter compression of the
-    same problem, which the factor then preconditions."""
+    same problem, which the factor then preconditions.  restart: GMRES
+    cycle length (0: 30)."""
     o = KrylovOpts(int(method), int(max_iter), float(tol), float(shift), int(bool(precondition)),
-                   int(bool(use_guess)), op.h.value if op is not None else None)
+                   int(bool(use_guess)), op.h.value if op is not None else None, int(restart), 0)
     st = KrylovStats()
     hist = (C.c_double * (int(max_iter) + 1))()
     rc = lib.hlevy_krylov_solve(fac.h, _dptr(b, fac.N), _dptr(x, fac.N), C.byref(o), C.byref(st), hist,
