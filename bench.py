@@ -338,6 +338,14 @@ def bench_steady(H, torch, n=65536, s=0.5):
                                         "converged": s0["converged"], "rel_residual": s0["rel_residual"],
                                         "ms_per_iteration": 1e3 * (t5 - t4) / max(1, s0["iterations"])}
     out["speedup_pcg_vs_cg"] = (t5 - t4) / (t3 - t2)
+    # the same system by preconditioned GMRES (restart 30)
+    g = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    sg = H.krylov_solve(fac, f, g, method=H.KRYLOV_GMRES, max_iter=100, tol=1e-12)
+    t7 = time.perf_counter()
+    out["pgmres"] = {"iterations": sg["iterations"], "seconds": t7 - t6, "rel_residual": sg["rel_residual"],
+                     "rel_l2_vs_pcg": float(np.linalg.norm(g.cpu().numpy() - got) / np.linalg.norm(got))}
     out["note"] = ("preconditioner: mixed factor of I - dt/2 G, dt = 1e4, lu_tol 1e-6; both iterations use "
                    "the FP64 H-matrix product with G; error against the closed form is the discretisation's")
     del fac, op
@@ -477,6 +485,10 @@ def bench_varorder(H, torch):
         t0 = time.perf_counter()
         st = H.krylov_solve(fac, b, u, method=H.KRYLOV_BICGSTAB, max_iter=100, tol=1e-12, op=fine)
         t["bicgstab_preconditioned"] = time.perf_counter() - t0
+        ug = torch.zeros_like(f)
+        t0 = time.perf_counter()
+        sgm = H.krylov_solve(fac, b, ug, method=H.KRYLOV_GMRES, max_iter=100, tol=1e-12, op=fine)
+        t["gmres_preconditioned"] = time.perf_counter() - t0
         u0 = torch.zeros_like(f)
         t0 = time.perf_counter()
         s0 = H.krylov_solve(fac, b, u0, method=H.KRYLOV_BICGSTAB, max_iter=5000, tol=1e-12, precondition=False,
@@ -500,7 +512,8 @@ def bench_varorder(H, torch):
         out["varorder_lshape_n%d" % N] = {
             "N": N, "seconds": t,
             "iterations": {"preconditioned": st["iterations"], "plain": s0["iterations"],
-                           "plain_converged": s0["converged"], "mixed_preconditioned": sm["iterations"]},
+                           "plain_converged": s0["converged"], "mixed_preconditioned": sm["iterations"],
+                           "gmres_preconditioned": sgm["iterations"]},
             "rel_l2_mixed_vs_fp64_preconditioned": float(np.linalg.norm(um.cpu().numpy() - u.cpu().numpy())
                                                          / np.linalg.norm(u.cpu().numpy())),
             "rel_residual": st["rel_residual"],
