@@ -2248,16 +2248,29 @@ __global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t
   const int m1 = it.m1, m2 = it.m2, n = m1 + m2;
   const int tid = threadIdx.x, ty = tid / LI_G, tx = tid % LI_G;
 
-  for (int e = tid; e < LUINV_N * LUINV_N; e += LI_T) {
-    const int i = e % LUINV_N, j = e / LUINV_N;
-    double v = i == j ? 1.0 : 0.0;
-    if (i < n && j < n) {
-      if (i < m1)
-        v = j < m1 ? it.A11[i + m1 * j] : it.A12[i + m1 * (j - m1)];
-      else
-        v = j < m1 ? it.A21[(i - m1) + m2 * j] : it.A22[(i - m1) + m2 * (j - m1)];
+  // every thread's 16 loads are issued before the first LDS store: a fixed
+  // trip count and no branches (the source block and offset are selected;
+  // an entry of the identity padding loads A11[0], which always exists, and
+  // discards it), so nothing waits between the loads
+  {
+    constexpr int LI_E = LUINV_N * LUINV_N / LI_T;
+    double vals[LI_E];
+#pragma unroll
+    for (int u = 0; u < LI_E; ++u) {
+      const int e = tid + u * LI_T;
+      const int i = e % LUINV_N, j = e / LUINV_N;
+      const bool in = i < n && j < n, top = i < m1, left = j < m1;
+      const double* src = !in ? it.A11 : (top ? (left ? it.A11 : it.A12) : (left ? it.A21 : it.A22));
+      const size_t off =
+          !in ? 0 : (size_t)(top ? i : i - m1) + (size_t)(top ? m1 : m2) * (size_t)(left ? j : j - m1);
+      const double x = src[off];
+      vals[u] = in ? x : (i == j ? 1.0 : 0.0);
     }
-    stage[i + LI_S * j] = v;
+#pragma unroll
+    for (int u = 0; u < LI_E; ++u) {
+      const int e = tid + u * LI_T;
+      stage[(e % LUINV_N) + LI_S * (e / LUINV_N)] = vals[u];
+    }
   }
   __syncthreads();
   double a[LI_R][LI_R], z[LI_R][LI_R];
