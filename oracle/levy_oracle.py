@@ -468,9 +468,10 @@ def exterior_forcing(p: Problem, u_ext: np.ndarray) -> np.ndarray:
     right of it (indices n .. 2n).  Returns g (length n) such that the
     scheme on the box with this exterior is G u + g.  The far field beyond
     the window (|y| > L_W) is not included: its integral of u_ext is the
-    caller's (its -u T part is in the diagonal of G)."""
-    if p.dim != 1:
-        raise ValueError("exterior forcing is 1D")
+    caller's (its -u T part is in the diagonal of G).  2D: see
+    _exterior_forcing_2d."""
+    if p.dim == 2:
+        return _exterior_forcing_2d(p, u_ext)
     c = quadrature_constants(p)
     h, NW, n = c["h"], c["NW"], p.n
     beta = 0.5 * (c["C2"] - c["S2"])
@@ -537,6 +538,51 @@ def far_field(p: Problem, u_ext: np.ndarray, next_: int, tail_left: float, tail_
                 acc += w * nu(-k * h) * left[i - k + next_]      # lattice index i - k <= -1
         f[i] = acc + tail_right * tp + tail_left * tm
     return f
+
+
+def _exterior_forcing_2d(p: Problem, u_ext: np.ndarray) -> np.ndarray:
+    """2D: u_ext holds the values on the extended lattice of indices
+    -NW .. n - 1 + NW per axis ((n + 2 NW)^2 values, first coordinate
+    slowest; the n^2 interior entries are ignored).  Row (p1, q1) takes every
+    exterior lattice point of its window (|k|_inf <= NW) with the trapezoid
+    weights W_k1 W_k2 and the row's kernel, and the local terms (diffusion,
+    the u'' correction of its axis, the drift and an asymmetric measure's
+    u' sum) on its exterior nearest neighbours."""
+    c = quadrature_constants(p)
+    h, NW, n = c["h"], c["NW"], p.n
+    side = n + 2 * NW
+    u_ext = np.asarray(u_ext, dtype=np.float64)
+    if u_ext.shape != (side * side,):
+        raise ValueError("u_ext holds (n + 2 (n + 1))^2 values")
+    U = u_ext.reshape(side, side)
+    betas = (0.5 * (c["C2"] - c["S2"]), 0.5 * (c["C2y"] - c["S2y"]) if "C2y" in c else 0.5 * (c["C2"] - c["S2"]))
+    drift = (p.b[0] - c.get("S1", 0.0), p.b[1])
+    w1 = lambda k: 0.5 * h if abs(k) == NW else h
+    g = np.zeros(n * n)
+    for p1 in range(n):
+        for q1 in range(n):
+            acc = 0.0
+            for k1 in range(-NW, NW + 1):
+                a1 = p1 + k1
+                for k2 in range(-NW, NW + 1):
+                    a2 = q1 + k2
+                    if 0 <= a1 < n and 0 <= a2 < n:
+                        continue              # interior point
+                    if p.jumps:
+                        if p.lam_neg is None:
+                            nu = float(kernel_nu(p, math.hypot(k1 * h, k2 * h)))
+                        else:
+                            nu = float(kernel_nu_tilted(p, k1 * h, k2 * h))
+                        v = w1(k1) * w1(k2) * nu
+                    else:
+                        v = 0.0
+                    if abs(k1) + abs(k2) == 1:
+                        ax = 0 if k1 != 0 else 1
+                        sg = k1 if k1 != 0 else k2
+                        v += (betas[ax] + p.a) / h ** 2 + sg * drift[ax] / (2.0 * h)
+                    acc += v * U[a1 + NW, a2 + NW]
+            g[p1 * n + q1] = acc
+    return g
 
 
 # ---------------------------------------------------------------------------

@@ -838,3 +838,35 @@ def test_tilted_2d_generator_converges_to_quadrature():
         errs.append(np.abs(np.array(vals) - ref).max() / np.abs(ref).max())
     print("tilted 2D errors", errs)
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0 and errs[2] < 1e-2, errs
+
+
+@pytest.mark.parametrize("lam_neg", [None, 2.2])
+def test_exterior_forcing_2d_of_a_constant(lam_neg):
+    """2D, u = 1 inside and outside: every row of G 1 + g(1) is -T (the
+    measure beyond the window), for the symmetric and the tilted kernel,
+    with diffusion and drift."""
+    p = Problem(dim=2, n=9, lo=-1.0, hi=1.0, s=0.55, lam=0.6, lam_neg=lam_neg, C=0.5, a=0.03, b=(0.2, -0.3))
+    NW = p.n + 1
+    side = p.n + 2 * NW
+    g = exterior_forcing(p, np.ones(side * side))
+    G = generator_dense(p)
+    T = quadrature_constants(p)["T"]
+    tot = G @ np.ones(p.N) + g
+    assert np.allclose(tot, -T, rtol=1e-11, atol=1e-11 * np.abs(G).max())
+
+
+def test_exterior_forcing_2d_linear_local_terms():
+    """Without jumps, u = x1 + 2 x2 on the whole lattice: the discrete
+    diffusion vanishes and the central drift is exact, so G u + g equals
+    b0 + 2 b1 + c u in every row, the rows next to the boundary included."""
+    p = Problem(dim=2, n=7, lo=-1.0, hi=1.0, a=0.1, b=(0.3, -0.2), c=-0.4, jumps=False)
+    n, NW = p.n, p.n + 1
+    h = h_of(p)
+    idx = np.arange(-NW, n + NW)
+    A1, A2 = np.meshgrid(idx, idx, indexing="ij")
+    u_all = (p.lo + (A1 + 1) * h) + 2.0 * (p.lo + (A2 + 1) * h)
+    g = exterior_forcing(p, u_all.ravel())
+    X = grid(p)
+    u = X[:, 0] + 2.0 * X[:, 1]
+    lhs = generator_dense(p) @ u + g
+    assert np.allclose(lhs, 0.3 + 2.0 * (-0.2) + p.c * u, rtol=0, atol=1e-11)
