@@ -293,11 +293,16 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream)
  * (|k| <= NW = n + 1) whose point x_i + kh is exterior, each with W_k nu(kh)
  * (W_k = h, h/2 at |k| = NW), and the local terms on the exterior neighbours
  * lo and hi.  u_ext (device, 2 NW values): lattice points lo - (NW-1)h .. lo
- * ascending, then hi .. hi + (NW-1)h.  The integral of u_ext beyond the
- * window (|y| > L_W) is not included (its -u T part is in G).  A time-
- * independent exterior enters hlevy_step as g with phi = 1.  Errors:
- * HLEVY_ERR_INVALID_ARG for a 2D or Gaussian operator or overlapping
- * buffers.  Synchronises `stream`. */
+ * ascending, then hi .. hi + (NW-1)h.  2D: u_ext holds the extended lattice
+ * of indices -NW .. n - 1 + NW per axis, (3n + 2)^2 values in grid order
+ * (first coordinate slowest; the n^2 interior entries are ignored), and row
+ * (p, q) takes every exterior point of its window (|k|_inf <= NW) with
+ * W_k1 W_k2 nu(kh) and the local terms of its exterior nearest neighbours.
+ * The integral of u_ext beyond the window (|y| > L_W) is not included (its
+ * -u T part is in G; 1D: hlevy_exterior_forcing_far).  A time-independent
+ * exterior enters hlevy_step as g with phi = 1.  Errors:
+ * HLEVY_ERR_INVALID_ARG for a Gaussian, variable-order or masked operator
+ * or overlapping buffers.  Synchronises `stream`. */
 hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream);
 
 /* Forcing of a non-zero exterior with its far field, 1D tempered kernels:

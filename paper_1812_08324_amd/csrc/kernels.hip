@@ -153,8 +153,41 @@ __device__ double lower_gamma(double a, double x) {
   return sum * exp(a * log(x) - x);
 }
 
-// upper incomplete gamma Gamma(a, x) for a in (-2, 1], x > 0
+// exponential integral E1(x) = Gamma(0, x), x > 0: the power series
+// -gamma_E - ln x - sum_k (-x)^k / (k k!) below 1, above it the continued
+// fraction 1 / (x + 1 - 1 / (x + 3 - 4 / (x + 5 - ...))) times e^{-x}
+// (modified Lentz)
+__device__ double expint_e1(double x) {
+  if (x <= 1.0) {
+    double sum = 0.0, term = 1.0;
+    for (int k = 1; k < 60; ++k) {
+      term *= -x / k;
+      const double add = term / k;
+      sum += add;
+      if (fabs(add) < 1e-17 * fabs(sum)) break;
+    }
+    return -0.57721566490153286061 - log(x) - sum;
+  }
+  double b = x + 1.0, c = 1e300, d = 1.0 / b, f = d;
+  for (int i = 1; i < 300; ++i) {
+    const double an = -(double)i * i;
+    b += 2.0;
+    d = an * d + b;
+    if (fabs(d) < 1e-300) d = 1e-300;
+    c = b + an / c;
+    if (fabs(c) < 1e-300) c = 1e-300;
+    d = 1.0 / d;
+    const double del = c * d;
+    f *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  return f * exp(-x);
+}
+
+// upper incomplete gamma Gamma(a, x) for a in (-2, 1], x > 0 (a = 0 and
+// a = -1, i.e. s = 1/2, go through E1)
 __device__ double upper_gamma(double a, double x) {
+  if (a == 0.0) return expint_e1(x);
   if (a > 0.0) {
     if (x > 30.0) {
       // continued fraction (Lentz) for large x
@@ -509,6 +542,54 @@ __global__ void __launch_bounds__(HL_BLOCK) k_ext_apply(const double* tab, const
   for (int q = NW + threadIdx.x; q < qend; q += HL_BLOCK) acc += tab[n + q - NW - i + NW] * u_ext[q];
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) g[i] = acc;
+}
+
+// 2D exterior: tab[(k1 + NW)(2 NW + 1) + k2 + NW] is the coefficient of
+// u(x_i + kh) in row i for |k|_inf <= NW, k != 0: W_k1 W_k2 nu(kh) with the
+// row's kernel (tilted for an asymmetric measure), plus on the four nearest
+// neighbours the local terms of their axis (diffusion, the u'' correction,
+// the drift and an asymmetric measure's u' sum on the first axis).
+__global__ void __launch_bounds__(HL_BLOCK) k_ext2_table(ProblemDev P, const double* cst, double* tab) {
+  const int NW = P.n + 1, side = 2 * NW + 1;
+  const long q = (long)blockIdx.x * HL_BLOCK + threadIdx.x;
+  if (q >= (long)side * side) return;
+  const int k1 = (int)(q / side) - NW, k2 = (int)(q % side) - NW;
+  if (k1 == 0 && k2 == 0) {
+    tab[q] = 0.0;
+    return;
+  }
+  const double h = P.h;
+  const double w = ((abs(k1) == NW) ? 0.5 * h : h) * ((abs(k2) == NW) ? 0.5 * h : h);
+  const bool asym2 = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM;
+  double v = w * (asym2 ? nu_tilt2(P, k1, k2) : nu_at(P, h * sqrt((double)k1 * k1 + (double)k2 * k2)));
+  if (abs(k1) + abs(k2) == 1) {
+    const double beta = 0.5 * (cst[2] - cst[1]);
+    const double beta_y = asym2 ? 0.5 * (cst[6] - cst[5]) : beta;
+    if (k1 != 0) {
+      const double b0 = asym2 ? P.b0 - cst[4] : P.b0;
+      v += (beta + P.a) / (h * h) + (k1 > 0 ? 1.0 : -1.0) * b0 / (2.0 * h);
+    } else {
+      v += (beta_y + P.a) / (h * h) + (k2 > 0 ? 1.0 : -1.0) * P.b1 / (2.0 * h);
+    }
+  }
+  tab[q] = v;
+}
+// g[p n + q] = sum over the exterior lattice points of the window of row
+// (p, q) of tab u_ext; u_ext is the extended lattice -NW .. n - 1 + NW per
+// axis, first coordinate slowest.  One block per row, fixed-order sum.
+__global__ void __launch_bounds__(HL_BLOCK) k_ext2_apply(const double* tab, const double* u_ext, int n, double* g) {
+  __shared__ double red[4];
+  const int NW = n + 1, side = 2 * NW + 1, ext = n + 2 * NW;
+  const int p = blockIdx.x / n, q = blockIdx.x % n;
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < (long)side * side; e += HL_BLOCK) {
+    const int k1 = (int)(e / side) - NW, k2 = (int)(e % side) - NW;
+    const int a1 = p + k1, a2 = q + k2;
+    if (a1 >= 0 && a1 < n && a2 >= 0 && a2 < n) continue;   // interior point
+    acc += tab[e] * u_ext[(size_t)(a1 + NW) * ext + (a2 + NW)];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) g[blockIdx.x] = acc;
 }
 
 // Far field f^{L_W} (eq. equ:fxy) of an exterior on an extended lattice, 1D.
@@ -2633,6 +2714,14 @@ hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double*
   const int NW = P.n + 1;
   hipLaunchKernelGGL(k_ext_table, dim3((2 * NW + 1 + HL_BLOCK - 1) / HL_BLOCK), dim3(HL_BLOCK), 0, s, P, cst, tab);
   hipLaunchKernelGGL(k_ext_apply, dim3(P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, g);
+  return post();
+}
+hipError_t launch_exterior2(const ProblemDev& P, const double* cst, const double* u_ext, double* tab, double* g,
+                            hipStream_t s) {
+  const long side = 2 * (long)(P.n + 1) + 1;
+  hipLaunchKernelGGL(k_ext2_table, dim3((unsigned)((side * side + HL_BLOCK - 1) / HL_BLOCK)), dim3(HL_BLOCK), 0, s,
+                     P, cst, tab);
+  hipLaunchKernelGGL(k_ext2_apply, dim3(P.n * P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, g);
   return post();
 }
 hipError_t launch_far_field(const ProblemDev& P, const double* u_ext, int next, double tail_left,

@@ -2570,22 +2570,26 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream)
 
 hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream) {
   if (!op || !u_ext || !g) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (op->prob.dim != 1) return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing is 1D");
   if (op->prob.kernel == HLEVY_KERNEL_VARIABLE_ORDER)
     return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing takes a constant jump index");
   if (op->prob.kernel == HLEVY_KERNEL_GAUSSIAN)
     return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing follows the window scheme (tempered kernels)");
+  if (op->S.N != (op->prob.dim == 1 ? op->prob.n : op->prob.n * op->prob.n))
+    return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing needs the whole box (no mask)");
   const int n = op->prob.n;
-  {
-    const double* ul = u_ext;
-    const double* uh = u_ext + 2 * (size_t)(n + 1);
-    if (g < uh && ul < g + n) return fail(HLEVY_ERR_INVALID_ARG, "u_ext and g must not overlap");
-  }
+  const size_t next = op->prob.dim == 1 ? 2 * (size_t)(n + 1) : (size_t)(3 * n + 2) * (3 * n + 2);
+  const size_t N = op->S.N;
+  if (g < u_ext + next && u_ext < g + N) return fail(HLEVY_ERR_INVALID_ARG, "u_ext and g must not overlap");
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
     DevBuf tab;
-    tab.alloc((2 * (size_t)(n + 1) + 1) * sizeof(double));
-    HL_CHECK(launch_exterior(op->pd, op->cst.as<double>(), u_ext, tab.as<double>(), g, s));
+    if (op->prob.dim == 1) {
+      tab.alloc((2 * (size_t)(n + 1) + 1) * sizeof(double));
+      HL_CHECK(launch_exterior(op->pd, op->cst.as<double>(), u_ext, tab.as<double>(), g, s));
+    } else {
+      tab.alloc((size_t)(2 * n + 3) * (2 * n + 3) * sizeof(double));
+      HL_CHECK(launch_exterior2(op->pd, op->cst.as<double>(), u_ext, tab.as<double>(), g, s));
+    }
     HL_CHECK(hipStreamSynchronize(s));
     return HLEVY_OK;
   });

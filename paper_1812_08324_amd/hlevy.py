@@ -395,9 +395,11 @@ def op_constants(op: Op, stream=None):
 
 def exterior_forcing(op: Op, u_ext, g, stream=None):
     """g = the forcing of the exterior values u_ext (hlevy_exterior_forcing;
-    1D: u_ext holds 2 (n + 1) values, g n values, both float64 CUDA)."""
-    n = op.N
-    _check(lib.hlevy_exterior_forcing(op.h, _dptr(u_ext, 2 * (n + 1)), _dptr(g, n), _stream(stream)),
+    1D: u_ext holds 2 (n + 1) values; 2D: (3 n + 2)^2 values on the extended
+    lattice, interior entries ignored; g holds N values; float64 CUDA)."""
+    n = op.prob.n
+    ne = 2 * (n + 1) if op.prob.dim == 1 else (3 * n + 2) ** 2
+    _check(lib.hlevy_exterior_forcing(op.h, _dptr(u_ext, ne), _dptr(g, op.N), _stream(stream)),
            "hlevy_exterior_forcing")
 
 

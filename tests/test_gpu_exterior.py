@@ -99,14 +99,50 @@ def test_cn_with_exterior_forcing(H):
 
 
 def test_exterior_forcing_rejects(H):
-    """Overlapping u_ext and g, and a 2D operator, are refused before any
-    device work."""
+    """Overlapping u_ext and g, and a masked 2D operator, are refused before
+    any device work."""
     op = assemble(H, CASES["tempered_n1000"])
     buf = torch.zeros(2 * 1001 + 1000, dtype=torch.float64, device="cuda")
     assert H.lib.hlevy_exterior_forcing(op.h, buf.data_ptr(), buf.data_ptr() + 8 * 10, None) == -1
-    op2 = H.assemble(H.make_problem(2, 24, 0.0, 1.0, 0.5), H.make_hparams(aca_tol=1e-8, max_rank=32))
-    out = torch.zeros(24 * 24, dtype=torch.float64, device="cuda")
-    assert H.lib.hlevy_exterior_forcing(op2.h, buf.data_ptr(), out.data_ptr(), None) == -1
+    from workloads import lshape_mask
+    op2 = H.assemble(H.make_problem(2, 24, -1.0, 1.0, 0.5, mask=lshape_mask(24)),
+                     H.make_hparams(leaf=32, aca_tol=1e-8, max_rank=32))
+    big = torch.zeros(74 * 74, dtype=torch.float64, device="cuda")
+    out = torch.zeros(op2.N, dtype=torch.float64, device="cuda")
+    assert H.lib.hlevy_exterior_forcing(op2.h, big.data_ptr(), out.data_ptr(), None) == -1
+
+
+EXT2 = {
+    "tempered2d_n20": Problem(dim=2, n=20, lo=-1.0, hi=1.0, s=0.6, lam=0.8, C=0.4, a=0.02, b=(0.3, -0.2)),
+    "tilted2d_n17": Problem(dim=2, n=17, lo=-1.0, hi=1.0, s=0.5, lam=0.5, lam_neg=2.5, C=0.4, a=0.02,
+                            b=(0.1, 0.2)),
+}
+
+
+@pytest.mark.parametrize("name", list(EXT2))
+def test_exterior_forcing_2d(H, name):
+    """2D exterior forcing on the extended lattice against the oracle (a
+    smooth payoff-like exterior), and the constant identity G 1 + g(1) = -T
+    through the H-matrix."""
+    p = EXT2[name]
+    prob = H.make_problem(2, p.n, p.lo, p.hi, p.s, lam=p.lam, C_=p.C, a=p.a, b=p.b, c=p.c, r0=p.r0,
+                          lam_neg=p.lam_neg)
+    op = H.assemble(prob, H.make_hparams(aca_tol=1e-8, max_rank=32))
+    n, NW = p.n, p.n + 1
+    h = (p.hi - p.lo) / (n + 1)
+    idx = np.arange(-NW, n + NW)
+    A1, A2 = np.meshgrid(p.lo + (idx + 1) * h, p.lo + (idx + 1) * h, indexing="ij")
+    ue = (np.exp(-0.5 * (A1 ** 2 + A2 ** 2)) * np.cos(A1 - 0.3 * A2)).ravel()
+    g = torch.empty(p.N, dtype=torch.float64, device="cuda")
+    H.exterior_forcing(op, dev(ue), g)
+    ref = exterior_forcing(p, ue)
+    assert rel(host(g), ref) <= 1e-13
+    H.exterior_forcing(op, dev(np.ones_like(ue)), g)
+    y = torch.empty_like(g)
+    H.matvec(op, dev(np.ones(p.N)), y)
+    T = quadrature_constants(p)["T"]
+    scale = float(np.abs(host(g)).max())
+    assert np.abs(host(y) + host(g) + T).max() <= 1e-7 * scale
 
 
 FAR = {
@@ -162,3 +198,19 @@ def test_far_field_edges_and_constant(H):
         H.exterior_forcing_far(op, dev(np.zeros(2 * p.n)), p.n, 0.0, 0.0, b)
     with pytest.raises(H.HlevyError, match="tail"):
         H.exterior_forcing_far(op, ue, NW, float("nan"), 0.0, b)
+
+
+
+@pytest.mark.parametrize("dim,lam_neg", [(1, None), (1, 2.0), (2, None), (2, 2.5)])
+def test_tempered_half_index_tail(H, dim, lam_neg):
+    """s = 1/2 with tempering: the measure beyond the window needs
+    Gamma(-1, x), which the recursion of the incomplete gamma function takes
+    through Gamma(0, x) = E1(x); the constants against the oracle's
+    quadrature."""
+    n = 300 if dim == 1 else 20
+    p = Problem(dim=dim, n=n, lo=-1.0, hi=1.0, s=0.5, lam=0.7, lam_neg=lam_neg, C=0.4)
+    prob = H.make_problem(dim, n, p.lo, p.hi, 0.5, lam=0.7, C_=0.4, lam_neg=lam_neg)
+    op = H.assemble(prob, H.make_hparams(aca_tol=1e-8, max_rank=32))
+    ref = quadrature_constants(p)
+    for v, key in zip(H.op_constants(op), ("S0", "S2", "C2", "T")):
+        assert v == pytest.approx(ref[key], rel=1e-11), key
