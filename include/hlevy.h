@@ -140,7 +140,8 @@ typedef struct {
                               taylor_rank terms of the Taylor expansion of Sec. 3.3 about its row
                               cluster's centre (2D: products of the 1D series in order of total
                               degree), stored at that fixed rank without truncation (the paper's
-                              fixed-rank construction); <= max_rank.  Required (> 0) for the
+                              fixed-rank construction); <= max_rank.  Admissible blocks with fewer
+                              than taylor_rank rows or columns are stored dense.  Required (> 0) for the
                               Gaussian kernel: partially pivoted ACA, whose stopping rule looks at
                               the last cross only, stops early on its 2D blocks (4.9 % block error
                               measured at eps2 = 5); 0 for the tempered kernel (ACA) */

@@ -48,6 +48,7 @@ struct Structure {
   std::vector<double> var_s;
   std::vector<int32_t> var_row;
   int32_t cluster = 0;          // hlevy_cluster
+  int32_t taylor_rank = 0;      // > 0: admissible blocks with fewer rows or columns are dense
   std::vector<double> pts;      // coordinates in cluster order (N * dim)
   std::vector<Cluster> cl;      // cl[0] is the root
   std::vector<int32_t> leafcl;  // leaf clusters in index order

@@ -2320,7 +2320,10 @@ static hlevy_status assemble_ops(const hlevy_problem* probs, const hlevy_hparams
                                A->dids.as<int32_t>(), (int)dense_ids.size(), s));
     if (hp->taylor_rank > 0) {
       // the fixed-rank Taylor factors of the Gaussian kernel (Sec. 3.3) go
-      // straight into G: no ACA, no truncation
+      // straight into G: no ACA, no truncation.  Every low-rank leaf holds
+      // taylor_rank columns (the structure keeps thinner blocks dense).
+      for (int l : A->lr_ids)
+        if (op->G.L[l].kcap < hp->taylor_rank) throw DeviceError("internal: a Taylor block above its rank capacity");
       HL_CHECK(launch_taylor(pd, op->ds.lat.as<int32_t>(), op->G.dev(), A->lids.as<int32_t>(),
                              (int)A->lr_ids.size(), op->G.rank, hp->taylor_rank, s));
       A->lr_ids.clear();

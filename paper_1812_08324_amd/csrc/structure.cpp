@@ -161,7 +161,10 @@ int build_block(Structure& s, int r, int c) {
   // capacity is subdivided (its children are admissible too), or kept
   // dense when its clusters are leaves
   const bool over = s.split.count({r, c}) > 0;
-  if (adm && sz <= s.nmax && r != c && !over) {
+  // a fixed-rank Taylor block needs at least taylor_rank rows and columns
+  // (below that a dense block is both exact and smaller)
+  const bool thin = s.taylor_rank > 0 && std::min(R.hi - R.lo, C.hi - C.lo) < s.taylor_rank;
+  if (adm && sz <= s.nmax && r != c && !over && !thin) {
     b.kind = K_LR;
   } else if (R.child[0] < 0 || C.child[0] < 0) {
     b.kind = K_DENSE;
@@ -269,6 +272,7 @@ std::string build_structure(const hlevy_problem& p, const hlevy_hparams& hp, Str
   s.eta = hp.eta;
   s.nmax = (int32_t)((N64 + hp.n_block - 1) / hp.n_block);
   s.cluster = hp.cluster;
+  s.taylor_rank = hp.taylor_rank;
   const int N = s.N;
   s.perm.resize(N);
   std::iota(s.perm.begin(), s.perm.end(), 0);

@@ -83,11 +83,12 @@ def clusters(points, leaf, coords=None):
     return tree
 
 
-def blocks(points, tree, eta=1.0, n_block=4):
+def blocks(points, tree, eta=1.0, n_block=4, min_lr=0):
     """Leaves of the block tree as (I, J, admissible) with I, J natural
     index arrays: a block is admissible when min(diam) <= eta dist of the
-    two boxes and both clusters have at most N_max points; inadmissible
-    blocks are split down to the leaf level, where they are dense."""
+    two boxes, both clusters have at most N_max points and (min_lr, the
+    fixed Taylor rank) at least min_lr points; inadmissible blocks are split
+    down to the leaf level, where they are dense."""
     N = points.shape[0]
     nmax = math.ceil(N / n_block)
     box = lambda idx: (points[idx].min(0), points[idx].max(0))
@@ -107,7 +108,7 @@ def blocks(points, tree, eta=1.0, n_block=4):
         I, J = tree[lv][i], tree[lv][j]
         bi, bj = box(I), box(J)
         adm = i != j and min(diam(bi), diam(bj)) <= eta * dist(bi, bj)
-        if adm and max(len(I), len(J)) <= nmax:
+        if adm and max(len(I), len(J)) <= nmax and min(len(I), len(J)) >= min_lr:
             out.append((I, J, True))
         elif lv == depth:
             out.append((I, J, False))

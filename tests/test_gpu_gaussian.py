@@ -59,7 +59,7 @@ def oracle_hmatrix(p, rank):
     `rank`."""
     G = generator_dense(p)
     pts = grid_points(p.dim, p.n, p.lo, p.hi)
-    bl = blocks(pts, clusters(pts, 64))
+    bl = blocks(pts, clusters(pts, 64), min_lr=rank)
     Hm = G.copy()
     for I, J, adm in bl:
         if adm:
@@ -149,7 +149,7 @@ def test_gaussian_1d_full_size_2p20(H):
     H.matvec(op, xd, y)
     got = host(y)
     pts = grid_points(1, n, p.lo, p.hi)
-    bl = blocks(pts, clusters(pts, 64))
+    bl = blocks(pts, clusters(pts, 64), min_lr=10)
     cst = quadrature_constants(p)
     for i in (0, 12345, n // 2, n - 1):
         g = generator_row(p, i, cst)
@@ -169,3 +169,40 @@ def test_gaussian_1d_full_size_2p20(H):
     st = H.solve(fac, xd, z, refine={"sweeps": 1, "tol": 1e-10}, stats=True)
     print(f"2^20: last rel residual {st['last_rel_residual']:.2e}, factor {H.fac_info(fac)['device_bytes'] / 1e9:.1f} GB")
     assert st["last_rel_residual"] <= 1e-10
+
+
+def test_gaussian_on_the_lshape(H):
+    """The Gaussian kernel on the L-shaped domain (mask, 2-means tree, leaf
+    clusters down to 8 points): every near-field entry against the oracle's
+    masked generator, every admissible block against the oracle's Taylor
+    factors of that block (the row cluster's centre from the grid coordinates
+    of its points); blocks thinner than the Taylor rank are dense."""
+    from oracle.levy_oracle import variable_order_generator
+    from workloads import lshape_mask, variable_order_lshape
+    n = 30
+    w = variable_order_lshape(n)
+    p = model(2, n)
+    prob = H.make_problem(2, n, -1.0, 1.0, 0.5, kernel=H.KERNEL_GAUSSIAN, eps2=p.eps2, mask=w["mask"])
+    op = H.assemble(prob, H.make_hparams(leaf=32, max_rank=16, taylor_rank=10, cluster=H.CLUSTER_KMEANS))
+    N = w["N"]
+    dense = torch.empty(N * N, dtype=torch.float64, device="cuda")
+    H.op_densify(op, dense)
+    Hd = host(dense).reshape(N, N)
+    G = variable_order_generator(p, w["mask"], None)
+    gi = np.flatnonzero(lshape_mask(n).reshape(-1))
+    coords = np.stack([gi // n, gi % n], 1)
+    nadm = 0
+    bl = blocks(w["x"], clusters(w["x"], 32, coords), min_lr=10)
+    assert sum(1 for *_, a in bl if a) == H.plan_info(prob, H.make_hparams(leaf=32, max_rank=16, taylor_rank=10,
+                                                                            cluster=H.CLUSTER_KMEANS))["n_lowrank"]
+    for I, J, adm in bl:
+        got = Hd[np.ix_(I, J)]
+        if adm:
+            U, V = taylor_factors(p, gi[I], gi[J], 10)
+            want = U @ V.T
+            assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max() + 1e-300, (I[0], J[0])
+            nadm += 1
+        else:
+            A = G[np.ix_(I, J)]
+            assert np.abs(got - A).max() <= 1e-13 * np.abs(A).max(), (I[0], J[0])
+    assert nadm > 0
