@@ -255,7 +255,10 @@ hlevy_status hlevy_plan_info(const hlevy_problem* prob, const hlevy_hparams* hp,
  * the actual bytes).  The transient workspace of a factorisation (at most
  * workspace_bytes of hlevy_factor_batched) is not included.  Computed on the
  * host from the block structure (App. B.1) with every low-rank block at its
- * rank capacity, so it bounds the actual bytes from above.  Errors:
+ * rank capacity, so it bounds the actual bytes from above, unless the
+ * assembly subdivides blocks whose compression needs more than the rank
+ * capacity (hlevy_op_info.subdivided_blocks > 0): those are known only after
+ * the ACA and their dense storage is not included.  Errors:
  * HLEVY_ERR_INVALID_ARG for an invalid descriptor or precision. */
 hlevy_status hlevy_footprint(const hlevy_problem* prob, const hlevy_hparams* hp, int32_t prec,
                              size_t* bytes_out);

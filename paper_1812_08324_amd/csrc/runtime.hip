@@ -1981,7 +1981,7 @@ static size_t factor_footprint(const hlevy_op& op) {
   HMat t;
   size_t d = 0;
   d += 2 * t.layout(op.S, kc, FULL, true);
-  d += 2 * t.layout(op.S, kc, LOWER, true);
+  d += t.layout(op.S, kc, LOWER, true) + t.layout(op.S, kc, UPPER, true);
   d += t.layout(op.S, kc, LOWER, false) + t.layout(op.S, kc, UPPER, false);
   return d * sizeof(double) + (d * sizeof(double)) / 2;
 }
@@ -2011,8 +2011,11 @@ static hlevy_status factor_group(std::vector<hlevy_fac*>& fs, Arena& arena, WsSt
       HMat t;
       const size_t nl = f->op->S.lf.size();
       const int kc = f->op->hp.max_rank;
+      // LU and TMP full, L^{-1} lower, U^{-1} upper: the two triangles can
+      // differ when the rank cap subdivided a block but not its transpose
       need += 2 * HMat::arena_bytes(t.layout(f->op->S, kc, FULL, true), nl);
-      need += 2 * HMat::arena_bytes(t.layout(f->op->S, kc, LOWER, true), nl);
+      need += HMat::arena_bytes(t.layout(f->op->S, kc, LOWER, true), nl);
+      need += HMat::arena_bytes(t.layout(f->op->S, kc, UPPER, true), nl);
     }
     arena.reserve(need);
   }

@@ -194,3 +194,57 @@ def test_varorder_batched_equals_single(H):
         v = dev(np.exp(-(w["x"] ** 2).sum(1) / 0.05))
         H.step(f, v, steps, refine={"sweeps": 1})
         assert rel(host(u), host(v)) <= 1e-12, w["name"]
+
+
+@pytest.mark.parametrize("varorder", [True, False])
+def test_varorder_footprint_and_caller_allocator(H, varorder):
+    """A masked operator (variable order or not) and its factor through a
+    caller's allocator: the live bytes it handed out are exactly the bytes
+    the handles report (the point maps and per-order arrays included),
+    the results equal the default allocator's bit for bit.  At rank
+    capacity 16 and ACA 1e-8 some blocks are subdivided but not their
+    transposes, so the triangles of the factor differ in size (the
+    factorisation workspace covers both); at capacity 32 nothing is
+    subdivided and hlevy_footprint bounds the resident bytes."""
+    w = variable_order_lshape(40)
+    prob = H.make_problem(2, 40, -1.0, 1.0, 0.5, mask=w["mask"], s_field=w["s"] if varorder else None)
+    hp = H.make_hparams(leaf=32, aca_tol=1e-8, max_rank=16, cluster=H.CLUSTER_KMEANS)
+
+    class Counting(H.TorchAllocator):   # the bytes requested by live blocks
+        def __init__(self):
+            self.sizes = {}
+            super().__init__()
+
+        def _alloc(self, nbytes, ctx):
+            p = super()._alloc(nbytes, ctx)
+            if p:
+                self.sizes[p] = nbytes
+            return p
+
+        def _free(self, p, ctx):
+            self.sizes.pop(p, None)
+            super()._free(p, ctx)
+
+    al = Counting()
+    op = H.assemble(prob, hp, allocator=al)
+    fac = H.factor(op, 1e-3, H.PREC_MIXED, 1e-6)
+    torch.cuda.synchronize()
+    resident = H.op_info(op)["device_bytes"] + H.fac_info(fac)["device_bytes"]
+    assert sum(al.sizes.values()) == resident
+    sub = H.op_info(op)["subdivided_blocks"]
+    assert sub > 0                       # the rank cap subdivided blocks here
+    # the footprint is computed before the ACA: with capacity 32 nothing is
+    # subdivided and it bounds the resident bytes
+    hp32 = H.make_hparams(leaf=32, aca_tol=1e-8, max_rank=32, cluster=H.CLUSTER_KMEANS)
+    op32 = H.assemble(prob, hp32)
+    f32 = H.factor(op32, 1e-3, H.PREC_MIXED, 1e-6)
+    assert H.op_info(op32)["subdivided_blocks"] == 0
+    assert H.op_info(op32)["device_bytes"] + H.fac_info(f32)["device_bytes"] <= H.footprint(prob, hp32, H.PREC_MIXED)
+    print(f"varorder {varorder}: subdivided blocks {sub}, resident {resident}")
+    op2 = H.assemble(prob, hp)
+    fac2 = H.factor(op2, 1e-3, H.PREC_MIXED, 1e-6)
+    u0 = np.exp(-(w["x"] ** 2).sum(1) / 0.05)
+    ua, ub = dev(u0), dev(u0)
+    H.step(fac, ua, 5, refine={"sweeps": 1})
+    H.step(fac2, ub, 5, refine={"sweeps": 1})
+    assert torch.equal(ua, ub)
