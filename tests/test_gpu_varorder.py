@@ -248,3 +248,36 @@ def test_varorder_footprint_and_caller_allocator(H, varorder):
     H.step(fac, ua, 5, refine={"sweeps": 1})
     H.step(fac2, ub, 5, refine={"sweeps": 1})
     assert torch.equal(ua, ub)
+
+
+def test_varorder_autotune_bf16_and_noalloc(H):
+    """The other entry points on the masked variable-order problem: the
+    autotuner picks a configuration (keeping the 2-means tree) and its
+    operator steps like the default one, up to the two operators' ACA
+    tolerance; the BF16 factor with four sweeps and the mixed factor give the same
+    trajectory within the refinement's reach; the no-allocation solve equals
+    hlevy_solve bit for bit."""
+    w = variable_order_lshape(40)
+    prob = H.make_problem(2, 40, -1.0, 1.0, 0.5, mask=w["mask"], s_field=w["s"])
+    hp = H.make_hparams(leaf=32, aca_tol=1e-8, max_rank=32, cluster=H.CLUSTER_KMEANS)
+    dt, steps = 1e-3, 20
+    u0 = np.exp(-(w["x"] ** 2).sum(1) / 0.05)
+    hpt, res = H.autotune(prob, hp, dt, H.PREC_MIXED, 1e-6, 10)
+    assert hpt.cluster == H.CLUSTER_KMEANS and res["seconds"] > 0.0
+    op = H.assemble(prob, hp)
+    opt = H.assemble(prob, hpt)
+    fm = H.factor(op, dt, H.PREC_MIXED, 1e-6)
+    ft = H.factor(opt, dt, H.PREC_MIXED, 1e-6)
+    fb = H.factor(op, dt, H.PREC_MIXED_BF16, 1e-6)
+    ua, ut, ub = dev(u0), dev(u0), dev(u0)
+    H.step(fm, ua, steps, refine={"sweeps": 2})
+    H.step(ft, ut, steps, refine={"sweeps": 2})
+    H.step(fb, ub, steps, refine={"sweeps": 4})
+    assert rel(host(ut), host(ua)) <= 1e-7     # another leaf size: two ACA approximations at 1e-8
+    assert rel(host(ub), host(ua)) <= 1e-8     # the same operator
+    b = dev(np.cos(3 * w["x"][:, 0]) * np.sin(2 * w["x"][:, 1]))
+    x1 = torch.zeros_like(b)
+    x2 = torch.full_like(b, float("nan"))
+    H.solve(fm, b, x1, refine={"sweeps": 2})
+    H.solve_noalloc(fm, b, x2, refine={"sweeps": 2})
+    assert torch.equal(x1, x2)
