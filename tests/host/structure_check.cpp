@@ -5,8 +5,11 @@
 // its parent's, the leaves tile the N x N index square exactly once, and the
 // per-leaf-cluster row and column lists name exactly the leaves that touch each
 // leaf cluster.  It then subdivides a seeded selection of admissible blocks
-// (the rank-cap path) and checks the tiling again, and feeds invalid
+// (the rank-cap path) and checks the tiling again; builds masked 2D domains
+// (L-shape, random, disc) with bisection and 2-means trees, variable-order
+// fields and Taylor blocks and checks their maps; and feeds invalid
 // descriptors that must be rejected.  Exit status 0 when every check holds.
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -99,6 +102,84 @@ void invariants(const hl::Structure& S, const hlevy_problem& p, const hlevy_hpar
   check(lists, "row lists name the leaves over each leaf cluster", p, hp);
 }
 
+// masked domains, 2-means trees, variable order and Taylor blocks: the
+// grid-index map holds exactly the kept points, in natural order through
+// perm; every row's order index names its own value; no low-rank block is
+// thinner than the Taylor rank
+void masked_invariants(const hl::Structure& S, const std::vector<int32_t>& kept, const std::vector<double>& sf,
+                       int taylor_rank, const hlevy_problem& p, const hlevy_hparams& hp) {
+  bool lat_ok = S.lat.size() == (size_t)S.N && kept.size() == (size_t)S.N;
+  for (int k = 0; lat_ok && k < S.N; ++k) lat_ok = S.lat[k] == kept[S.perm[k]];
+  check(lat_ok, "grid index of every cluster position", p, hp);
+  if (!sf.empty()) {
+    bool var_ok = S.var_row.size() == (size_t)S.N;
+    for (int k = 0; var_ok && k < S.N; ++k)
+      var_ok = S.var_row[k] >= 0 && S.var_row[k] < (int)S.var_s.size() && S.var_s[S.var_row[k]] == sf[S.perm[k]];
+    check(var_ok, "order index of every row", p, hp);
+  }
+  if (taylor_rank > 0) {
+    bool thick = true;
+    for (const hl::LeafInfo& l : S.lf) thick = thick && (l.kind != hl::K_LR || std::min(l.m, l.n) >= taylor_rank);
+    check(thick, "no low-rank block thinner than the Taylor rank", p, hp);
+  }
+}
+
+int masked_cases() {
+  int built = 0;
+  uint64_t state = 88172645463325252ull;   // xorshift64
+  auto rnd = [&]() {
+    state ^= state << 13;
+    state ^= state >> 7;
+    state ^= state << 17;
+    return state;
+  };
+  for (int n : {16, 30, 31, 40, 61}) {
+    for (int shape = 0; shape < 3; ++shape) {
+      // 0: L-shape (the quadrant x >= 0, y >= 0 removed), 1: random 70 %, 2: a disc
+      std::vector<uint8_t> mask((size_t)n * n);
+      const double h = 2.0 / (n + 1);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          const double x = -1.0 + (i + 1) * h, y = -1.0 + (j + 1) * h;
+          uint8_t m = 1;
+          if (shape == 0) m = !(x >= 0.0 && y >= 0.0);
+          if (shape == 1) m = (rnd() % 10) < 7;
+          if (shape == 2) m = x * x + y * y < 0.8;
+          mask[(size_t)i * n + j] = m;
+        }
+      std::vector<int32_t> kept;
+      for (int g = 0; g < n * n; ++g)
+        if (mask[g]) kept.push_back(g);
+      std::vector<double> sf(kept.size());
+      for (size_t k = 0; k < sf.size(); ++k) sf[k] = 0.1 + 0.8 * ((rnd() % 1000) / 1000.0) + 1e-4;
+      for (int cluster : {HLEVY_CLUSTER_BISECT, HLEVY_CLUSTER_KMEANS})
+        for (int leaf : {16, 32})
+          for (int variant = 0; variant < 3; ++variant) {
+            hlevy_problem p = problem(2, n);
+            hlevy_hparams hp = hparams(leaf, 1.0, 4);
+            hp.cluster = cluster;
+            p.mask = mask.data();
+            int tr = 0;
+            if (variant == 1) {
+              p.kernel = HLEVY_KERNEL_VARIABLE_ORDER;
+              p.s_field = sf.data();
+            } else if (variant == 2) {
+              p.kernel = HLEVY_KERNEL_GAUSSIAN;
+              p.eps2 = 5.0;
+              hp.taylor_rank = tr = 10;
+            }
+            hl::Structure S;
+            const std::string e = hl::build_structure(p, hp, S);
+            if (!e.empty()) continue;   // e.g. fewer than two leaves
+            ++built;
+            invariants(S, p, hp);
+            masked_invariants(S, kept, variant == 1 ? sf : std::vector<double>{}, tr, p, hp);
+          }
+    }
+  }
+  return built;
+}
+
 }  // namespace
 
 int main() {
@@ -130,9 +211,14 @@ int main() {
             }
           }
   }
+  const int masked = masked_cases();
+  built += masked;
   // invalid descriptors must be rejected, not crash
   int rejected = 0, bad = 0;
-  for (int variant = 0; variant < 12; ++variant) {
+  std::vector<uint8_t> mask4(16, 1);
+  std::vector<double> sbad(1024, 0.5);
+  sbad[77] = 1.0;
+  for (int variant = 0; variant < 16; ++variant) {
     hlevy_problem p = problem(1, 1024);
     hlevy_hparams hp = hparams(64, 1.0, 4);
     switch (variant) {
@@ -148,6 +234,10 @@ int main() {
       case 9: p.n = 100; break;   // fewer than two leaves of 64
       case 10: p.kernel = 7; break;
       case 11: p.kernel = HLEVY_KERNEL_GAUSSIAN; p.eps2 = 0.0; hp.taylor_rank = 10; break;
+      case 12: p.n = 4; p.mask = mask4.data(); break;                                // a mask in 1D
+      case 13: hp.cluster = HLEVY_CLUSTER_KMEANS; break;                             // 2-means in 1D
+      case 14: p.kernel = HLEVY_KERNEL_VARIABLE_ORDER; p.s_field = sbad.data(); break;  // s outside (0, 1)
+      case 15: p.kernel = HLEVY_KERNEL_VARIABLE_ORDER; break;                        // no s_field
     }
     hl::Structure S;
     if (!hl::build_structure(p, hp, S).empty()) ++rejected; else ++bad;
@@ -156,6 +246,7 @@ int main() {
     ++failures;
     std::fprintf(stderr, "FAIL %d invalid descriptors accepted\n", bad);
   }
-  std::printf("structures built %d, invalid rejected %d, failures %d\n", built, rejected, failures);
-  return failures == 0 && built > 50 ? 0 : 1;
+  std::printf("structures built %d (masked %d), invalid rejected %d, failures %d\n", built, masked, rejected,
+              failures);
+  return failures == 0 && built > 50 && masked > 50 ? 0 : 1;
 }
