@@ -509,8 +509,8 @@ def far_field(p: Problem, u_ext: np.ndarray, next_: int, tail_left: float, tail_
     over that half-line (adaptive quadrature).  u_ext: next_ values left of
     the box (lattice indices -next_ .. -1, ascending), then next_ right of
     it (indices n .. n + next_ - 1)."""
-    if p.dim != 1:
-        raise ValueError("the far field is 1D")
+    if p.dim == 2:
+        return _far_field_2d(p, u_ext, next_, tail_left, tail_right)
     c = quadrature_constants(p)
     h, NW, n = c["h"], c["NW"], p.n
     if next_ < NW:
@@ -583,6 +583,60 @@ def _exterior_forcing_2d(p: Problem, u_ext: np.ndarray) -> np.ndarray:
                     acc += v * U[a1 + NW, a2 + NW]
             g[p1 * n + q1] = acc
     return g
+
+
+def _far_field_2d(p: Problem, u_ext, next_: int, tail_left: float, tail_right: float) -> np.ndarray:
+    """2D far field: u_ext holds the extended lattice of indices
+    -next_ .. n - 1 + next_ per axis ((n + 2 next_)^2 values, first coordinate
+    slowest; entries inside the window of every row are not read).  Row i
+    takes the product trapezoid rule over the square |k|_inf <= next_ (weights
+    h, h/2 at |k_a| = next_) less the window's (|k|_inf <= NW, h/2 at
+    |k_a| = NW), so only points with |k|_inf >= NW enter, all exterior; beyond
+    the square the constant tail_right (y1 > 0) or tail_left (y1 < 0) times
+    the measure of that half of the region |y|_inf > next_ h (adaptive
+    quadrature in polar coordinates)."""
+    c = quadrature_constants(p)
+    h, NW, n = c["h"], c["NW"], p.n
+    if next_ < NW:
+        raise ValueError("next_ must be at least n + 1")
+    side = n + 2 * next_
+    U = np.asarray(u_ext, dtype=np.float64).reshape(side, side)
+    k = np.arange(-next_, next_ + 1)
+    K1, K2 = np.meshgrid(k, k, indexing="ij")
+    wb = np.where(np.abs(k) == next_, 0.5 * h, h)
+    ww = np.where(np.abs(k) == NW, 0.5 * h, np.where(np.abs(k) < NW, h, 0.0))
+    W = np.outer(wb, wb) - np.outer(ww, ww)
+    W[(np.abs(K1) < NW) & (np.abs(K2) < NW)] = 0.0      # the window's inside: nothing
+    nz = (K1 != 0) | (K2 != 0)
+    nu = np.zeros_like(W)
+    if p.lam_neg is None:
+        nu[nz] = kernel_nu(p, np.hypot(K1[nz] * h, K2[nz] * h))
+    else:
+        nu[nz] = kernel_nu_tilted(p, K1[nz] * h, K2[nz] * h)
+    coef = W * nu
+    R = next_ * h
+
+    def half(sign):
+        def radial(phi):
+            cs, sn = math.cos(phi), math.sin(phi)
+            r0 = R / max(abs(cs), abs(sn))
+            if p.lam_neg is None:
+                f = lambda r: float(kernel_nu(p, r)) * r
+            else:
+                f = lambda r: float(kernel_nu_tilted(p, r * cs, r * sn)) * r
+            return integrate.quad(f, r0, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)[0]
+        # y1 > 0: phi in (-pi/2, pi/2), octants split at the square's corners
+        base = -math.pi / 2 if sign > 0 else math.pi / 2
+        return sum(integrate.quad(radial, base + q * math.pi / 4, base + (q + 1) * math.pi / 4, epsabs=0.0,
+                                  epsrel=1e-12, limit=200)[0] for q in range(4))
+
+    tp, tm = half(1.0), half(-1.0)
+    f = np.zeros(n * n)
+    for p1 in range(n):
+        for q1 in range(n):
+            blk = U[p1:p1 + 2 * next_ + 1, q1:q1 + 2 * next_ + 1]
+            f[p1 * n + q1] = float(np.sum(coef * np.where(W != 0.0, blk, 0.0)))
+    return f + tail_right * tp + tail_left * tm
 
 
 # ---------------------------------------------------------------------------

@@ -870,3 +870,60 @@ def test_exterior_forcing_2d_linear_local_terms():
     u = X[:, 0] + 2.0 * X[:, 1]
     lhs = generator_dense(p) @ u + g
     assert np.allclose(lhs, 0.3 + 2.0 * (-0.2) + p.c * u, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("lam_neg", [None, 2.2])
+def test_far_field_2d_completes_the_constant(lam_neg):
+    """2D: with the tails equal to the exterior constant and no extended
+    lattice, the far field is the constant times the measure beyond the
+    window T (the two half-plane tails add up to it, the heavier side being
+    the one of the smaller rate), and every row of G c + g + f vanishes."""
+    p = Problem(dim=2, n=8, lo=-1.0, hi=1.0, s=0.55, lam=0.6, lam_neg=lam_neg, C=0.5, a=0.03, b=(0.2, -0.3))
+    NW = p.n + 1
+    side = p.n + 2 * NW
+    c = 1.3
+    f = far_field(p, np.full(side * side, c), NW, c, c)
+    T = quadrature_constants(p)["T"]
+    assert np.allclose(f, c * T, rtol=1e-10, atol=0)
+    fr = far_field(p, np.zeros(side * side), NW, 0.0, 1.0)
+    fl = far_field(p, np.zeros(side * side), NW, 1.0, 0.0)
+    if lam_neg is None:
+        assert fr[0] == pytest.approx(fl[0], rel=1e-10)
+    else:
+        assert fr[0] > 1.05 * fl[0]
+    g = exterior_forcing(p, np.full(side * side, c))
+    G = generator_dense(p)
+    assert np.abs(G @ np.full(p.N, c) + g + f).max() <= 1e-10 * np.abs(G).max() * c
+
+
+def test_far_field_2d_trapezoid_converges_to_the_integral():
+    """A smooth exterior u(x) = exp(-|x|^2 / 0.5) on a lattice reaching past
+    where it matters: the far field of a row converges at second order in h
+    to the polar quadrature of the integral over |y|_inf > L_W of
+    u(x_i + y) nu(y)."""
+    import warnings
+    errs = []
+    for n in (9, 19, 39):
+        p = Problem(dim=2, n=n, lo=-1.0, hi=1.0, s=0.6, lam=0.5)
+        h = h_of(p)
+        nx = int(math.ceil(5.0 / h))
+        idx = np.arange(-nx, n + nx)
+        A1, A2 = np.meshgrid(p.lo + (idx + 1) * h, p.lo + (idx + 1) * h, indexing="ij")
+        u = lambda x1, x2: np.exp(-(x1 * x1 + x2 * x2) / 0.5)
+        f = far_field(p, u(A1, A2).ravel(), nx, 0.0, 0.0)
+        i1, i2 = n // 3, (2 * n) // 3
+        x1, x2 = p.lo + (i1 + 1) * h, p.lo + (i2 + 1) * h
+        LW = (n + 1) * h
+
+        def radial(phi):
+            cs, sn = math.cos(phi), math.sin(phi)
+            r0 = LW / max(abs(cs), abs(sn))
+            g = lambda r: float(u(x1 + r * cs, x2 + r * sn)) * p.Cval * math.exp(-p.lam * r) / r ** (1 + 2 * p.s)
+            return integrate.quad(g, r0, np.inf, epsabs=0.0, epsrel=1e-12, limit=400)[0]
+
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            ex = sum(integrate.quad(radial, q * math.pi / 4, (q + 1) * math.pi / 4, epsabs=0.0, epsrel=1e-11,
+                                    limit=200)[0] for q in range(8))
+        errs.append(abs(f[i1 * n + i2] - ex) / abs(ex))
+    assert _order(errs[0], errs[1]) > 1.7 and _order(errs[1], errs[2]) > 1.7, errs
