@@ -289,7 +289,7 @@ hlevy_status hlevy_assemble_batched(const hlevy_problem* probs, const hlevy_hpar
  * measure S2 and C2 are those of the first axis.  Synchronises `stream`. */
 hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream);
 
-/* Forcing of a non-zero exterior, 1D tempered kernels (Sec. 4: the terms of
+/* Forcing of a non-zero exterior, tempered kernels (Sec. 4: the terms of
  * equ:I1approx - equ:I3approx that reach outside the box; the far-field term
  * f^{L_W} of equ:I2approx collects what lies beyond the window).  For
  * u = u_ext outside the box, the scheme on the box is G u + g: g (device,
@@ -303,28 +303,39 @@ hlevy_status hlevy_op_constants(const hlevy_op* op, double out[5], void* stream)
  * (p, q) takes every exterior point of its window (|k|_inf <= NW) with
  * W_k1 W_k2 nu(kh) and the local terms of its exterior nearest neighbours.
  * The integral of u_ext beyond the window (|y| > L_W) is not included (its
- * -u T part is in G; 1D: hlevy_exterior_forcing_far).  A time-independent
+ * -u T part is in G; hlevy_exterior_forcing_far adds it).  A time-independent
  * exterior enters hlevy_step as g with phi = 1.  Errors:
  * HLEVY_ERR_INVALID_ARG for a Gaussian, variable-order or masked operator
  * or overlapping buffers.  Synchronises `stream`. */
 hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, double* g, void* stream);
 
-/* Forcing of a non-zero exterior with its far field, 1D tempered kernels:
- * g + f, with g as hlevy_exterior_forcing (from the n + 1 values of each
- * side nearest the box) and f the far-field term f^{L_W} of equ:I2approx
- * (eq. equ:fxy), which the paper leaves to an input or a quadrature.  Row i
- * takes the trapezoid rule over the lattice offsets k = NW .. next
- * (NW = n + 1), each side with its own kernel (nu(kh) to the right,
- * nu(-kh) to the left) and weights h, h/2 at k = NW and k = next (nothing
- * when next = NW); beyond next h the exterior is the constant tail_right
- * (y > 0) or tail_left (y < 0), times the integral of nu over that half
- * line (incomplete gamma function, each side with its rate).  u_ext
- * (device, 2 next values): lattice points lo - (next-1)h .. lo ascending,
- * then hi .. hi + (next-1)h; n + 1 <= next <= 2^26.  With next = n + 1 and
- * zero tails the result is hlevy_exterior_forcing's; with a constant
- * exterior c (tails c) G c + g + f = 0 in every row.  Errors as
- * hlevy_exterior_forcing, and HLEVY_ERR_INVALID_ARG for next out of range
- * or non-finite tails.  Synchronises `stream`. */
+/* Forcing of a non-zero exterior with its far field, tempered kernels:
+ * g + f, with g as hlevy_exterior_forcing (from the lattice points of the
+ * window nearest the box) and f the far-field term f^{L_W} of equ:I2approx
+ * (eq. equ:fxy), which the paper leaves to an input or a quadrature.
+ * 1D: row i takes the trapezoid rule over the lattice offsets
+ * k = NW .. next (NW = n + 1), each side with its own kernel (nu(kh) to the
+ * right, nu(-kh) to the left) and weights h, h/2 at k = NW and k = next
+ * (nothing when next = NW); beyond next h the exterior is the constant
+ * tail_right (y > 0) or tail_left (y < 0), times the integral of nu over
+ * that half line (incomplete gamma function, each side with its rate).
+ * u_ext (device, 2 next values): lattice points lo - (next-1)h .. lo
+ * ascending, then hi .. hi + (next-1)h; n + 1 <= next <= 2^26.
+ * 2D: row (p, q) takes the product trapezoid rule over the square
+ * |k|_inf <= next (weights h, h/2 at |k_a| = next) less the window's
+ * (|k|_inf <= NW, h/2 at |k_a| = NW), so only lattice points with
+ * |k|_inf >= NW enter; beyond the square the exterior is the constant
+ * tail_right (y1 > 0) or tail_left (y1 < 0), times the measure of that
+ * half of the region |y|_inf > next h (polar coordinates: Gauss-Legendre
+ * in the angle, the incomplete gamma function in the radius; the tilted
+ * measure with its angle-dependent rate).  u_ext (device,
+ * (n + 2 next)^2 values): the extended lattice of indices
+ * -next .. n - 1 + next per axis, first coordinate slowest; entries inside
+ * the box are not read; n + 1 <= next <= 2^13.
+ * With next = n + 1 and zero tails the result is hlevy_exterior_forcing's;
+ * with a constant exterior c (tails c) G c + g + f = 0 in every row.
+ * Errors as hlevy_exterior_forcing, and HLEVY_ERR_INVALID_ARG for next out
+ * of range or non-finite tails.  Synchronises `stream`. */
 hlevy_status hlevy_exterior_forcing_far(const hlevy_op* op, const double* u_ext, int32_t next, double tail_left,
                                         double tail_right, double* g, void* stream);
 

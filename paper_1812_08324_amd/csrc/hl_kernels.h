@@ -21,9 +21,13 @@ hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double*
                            hipStream_t s);
 // Fixed-rank Taylor factors of the Gaussian kernel straight into the
 // admissible leaves ids[0..n) (rank set to r)
-// 2D exterior forcing; tab holds (2 n + 3)^2 doubles
-hipError_t launch_exterior2(const ProblemDev& P, const double* cst, const double* u_ext, double* tab, double* g,
-                            hipStream_t s);
+// 2D exterior forcing (u_ext: lattice index a at a + org per axis, ld per
+// row); tab holds (2 n + 3)^2 doubles
+hipError_t launch_exterior2(const ProblemDev& P, const double* cst, const double* u_ext, int ld, int org,
+                            double* tab, double* g, hipStream_t s);
+// g += 2D far field; tab holds (2 next + 1)^2 + 2 doubles
+hipError_t launch_far_field2(const ProblemDev& P, const double* u_ext, int next, double tail_left,
+                             double tail_right, double* tab, double* g, hipStream_t s);
 // g += far field of an exterior on an extended lattice (1D); tab holds
 // 2 (next - n) + 2 doubles
 hipError_t launch_far_field(const ProblemDev& P, const double* u_ext, int next, double tail_left,

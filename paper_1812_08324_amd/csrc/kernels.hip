@@ -575,21 +575,89 @@ __global__ void __launch_bounds__(HL_BLOCK) k_ext2_table(ProblemDev P, const dou
   tab[q] = v;
 }
 // g[p n + q] = sum over the exterior lattice points of the window of row
-// (p, q) of tab u_ext; u_ext is the extended lattice -NW .. n - 1 + NW per
-// axis, first coordinate slowest.  One block per row, fixed-order sum.
-__global__ void __launch_bounds__(HL_BLOCK) k_ext2_apply(const double* tab, const double* u_ext, int n, double* g) {
+// (p, q) of tab u_ext; u_ext is an extended lattice, first coordinate
+// slowest, lattice index a at position a + org per axis, ld per row.  One
+// block per row, fixed-order sum.
+__global__ void __launch_bounds__(HL_BLOCK) k_ext2_apply(const double* tab, const double* u_ext, int n, int ld,
+                                                         int org, double* g) {
   __shared__ double red[4];
-  const int NW = n + 1, side = 2 * NW + 1, ext = n + 2 * NW;
+  const int NW = n + 1, side = 2 * NW + 1;
   const int p = blockIdx.x / n, q = blockIdx.x % n;
   double acc = 0.0;
   for (long e = threadIdx.x; e < (long)side * side; e += HL_BLOCK) {
     const int k1 = (int)(e / side) - NW, k2 = (int)(e % side) - NW;
     const int a1 = p + k1, a2 = q + k2;
     if (a1 >= 0 && a1 < n && a2 >= 0 && a2 < n) continue;   // interior point
-    acc += tab[e] * u_ext[(size_t)(a1 + NW) * ext + (a2 + NW)];
+    acc += tab[e] * u_ext[(size_t)(a1 + org) * ld + (a2 + org)];
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) g[blockIdx.x] = acc;
+}
+
+// 2D far field: tab[(k1 + next)(2 next + 1) + k2 + next] = (W_big - W_win)
+// nu(kh), the product trapezoid weights of the square |k|_inf <= next (h/2 at
+// |k_a| = next) less the window's (h/2 at |k_a| = NW), zero inside the
+// window; the row's kernel (tilted for an asymmetric measure).
+__global__ void __launch_bounds__(HL_BLOCK) k_far2_table(ProblemDev P, int next, double* tab) {
+  const int NW = P.n + 1, side = 2 * next + 1;
+  const long e = (long)blockIdx.x * HL_BLOCK + threadIdx.x;
+  if (e >= (long)side * side) return;
+  const int k1 = (int)(e / side) - next, k2 = (int)(e % side) - next;
+  const double h = P.h;
+  if (max(abs(k1), abs(k2)) < NW) {
+    tab[e] = 0.0;
+    return;
+  }
+  auto wb = [&](int k) { return abs(k) == next ? 0.5 * h : h; };
+  auto ww = [&](int k) { return abs(k) == NW ? 0.5 * h : (abs(k) < NW ? h : 0.0); };
+  const double w = wb(k1) * wb(k2) - ww(k1) * ww(k2);
+  const double nu = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM ? nu_tilt2(P, k1, k2)
+                                                            : nu_at(P, h * sqrt((double)k1 * k1 + (double)k2 * k2));
+  tab[e] = w * nu;
+}
+// out[0], out[1]: the measure of the region |y|_inf > R on the side y1 > 0,
+// y1 < 0 (polar coordinates: four octants of 32 Gauss-Legendre nodes per
+// side, the radial integral by the incomplete gamma function).  One block
+// of 32 threads.
+__global__ void k_far2_tails(ProblemDev P, double R, double* out) {
+  __shared__ double glx[32], glw[32];
+  gauss_legendre(32, threadIdx.x, &glx[threadIdx.x], &glw[threadIdx.x]);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double s = P.s, C = P.C;
+  const bool tilt = P.kernel == HLEVY_KERNEL_TEMPERED_ASYM;
+  const double lam0 = tilt ? 0.5 * (P.lam + P.lam_neg) : P.lam, th = tilt ? 0.5 * (P.lam_neg - P.lam) : 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const double base = side == 0 ? -0.5 * M_PI : 0.5 * M_PI;
+    double acc = 0.0;
+    for (int oct = 0; oct < 4; ++oct)
+      for (int q = 0; q < 32; ++q) {
+        const double ph = base + 0.25 * M_PI * oct + 0.125 * M_PI * (glx[q] + 1.0), w = 0.125 * M_PI * glw[q];
+        const double c = cos(ph), sn = sin(ph);
+        const double r0 = R / fmax(fabs(c), fabs(sn));
+        const double mu = lam0 - th * c;
+        acc += w * (mu == 0.0 ? pow(r0, -2.0 * s) / (2.0 * s) : pow(mu, 2.0 * s) * upper_gamma(-2.0 * s, mu * r0));
+      }
+    out[side] = C * acc;
+  }
+}
+// g[p n + q] += the far field of row (p, q): u_ext the extended lattice of
+// indices -next .. n - 1 + next per axis; tails[0], tails[1] the measures of
+// the two halves beyond the square.  One block per row, fixed-order sum.
+__global__ void __launch_bounds__(HL_BLOCK) k_far2_apply(const double* tab, const double* tails, const double* u_ext,
+                                                         int n, int next, double tail_left, double tail_right,
+                                                         double* g) {
+  __shared__ double red[4];
+  const int NW = n + 1, side = 2 * next + 1, ld = n + 2 * next;
+  const int p = blockIdx.x / n, q = blockIdx.x % n;
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < (long)side * side; e += HL_BLOCK) {
+    const int k1 = (int)(e / side) - next, k2 = (int)(e % side) - next;
+    if (max(abs(k1), abs(k2)) < NW) continue;   // inside the window (interior values are not read)
+    acc += tab[e] * u_ext[(size_t)(p + k1 + next) * ld + (q + k2 + next)];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) g[blockIdx.x] += acc + tail_right * tails[0] + tail_left * tails[1];
 }
 
 // Far field f^{L_W} (eq. equ:fxy) of an exterior on an extended lattice, 1D.
@@ -2716,12 +2784,23 @@ hipError_t launch_exterior(const ProblemDev& P, const double* cst, const double*
   hipLaunchKernelGGL(k_ext_apply, dim3(P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, g);
   return post();
 }
-hipError_t launch_exterior2(const ProblemDev& P, const double* cst, const double* u_ext, double* tab, double* g,
-                            hipStream_t s) {
+hipError_t launch_exterior2(const ProblemDev& P, const double* cst, const double* u_ext, int ld, int org,
+                            double* tab, double* g, hipStream_t s) {
   const long side = 2 * (long)(P.n + 1) + 1;
   hipLaunchKernelGGL(k_ext2_table, dim3((unsigned)((side * side + HL_BLOCK - 1) / HL_BLOCK)), dim3(HL_BLOCK), 0, s,
                      P, cst, tab);
-  hipLaunchKernelGGL(k_ext2_apply, dim3(P.n * P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, g);
+  hipLaunchKernelGGL(k_ext2_apply, dim3(P.n * P.n), dim3(HL_BLOCK), 0, s, tab, u_ext, P.n, ld, org, g);
+  return post();
+}
+hipError_t launch_far_field2(const ProblemDev& P, const double* u_ext, int next, double tail_left,
+                             double tail_right, double* tab, double* g, hipStream_t s) {
+  const long side = 2 * (long)next + 1;
+  double* tails = tab + side * side;
+  hipLaunchKernelGGL(k_far2_table, dim3((unsigned)((side * side + HL_BLOCK - 1) / HL_BLOCK)), dim3(HL_BLOCK), 0, s,
+                     P, next, tab);
+  hipLaunchKernelGGL(k_far2_tails, dim3(1), dim3(32), 0, s, P, next * P.h, tails);
+  hipLaunchKernelGGL(k_far2_apply, dim3(P.n * P.n), dim3(HL_BLOCK), 0, s, tab, tails, u_ext, P.n, next, tail_left,
+                     tail_right, g);
   return post();
 }
 hipError_t launch_far_field(const ProblemDev& P, const double* u_ext, int next, double tail_left,

@@ -2594,7 +2594,7 @@ hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, dou
       HL_CHECK(launch_exterior(op->pd, op->cst.as<double>(), u_ext, tab.as<double>(), g, s));
     } else {
       tab.alloc((size_t)(2 * n + 3) * (2 * n + 3) * sizeof(double));
-      HL_CHECK(launch_exterior2(op->pd, op->cst.as<double>(), u_ext, tab.as<double>(), g, s));
+      HL_CHECK(launch_exterior2(op->pd, op->cst.as<double>(), u_ext, 3 * n + 2, n + 1, tab.as<double>(), g, s));
     }
     HL_CHECK(hipStreamSynchronize(s));
     return HLEVY_OK;
@@ -2604,29 +2604,36 @@ hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, dou
 hlevy_status hlevy_exterior_forcing_far(const hlevy_op* op, const double* u_ext, int32_t next, double tail_left,
                                         double tail_right, double* g, void* stream) {
   if (!op || !u_ext || !g) return fail(HLEVY_ERR_INVALID_ARG, "null argument");
-  if (op->prob.dim != 1) return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing is 1D");
   if (op->prob.kernel == HLEVY_KERNEL_VARIABLE_ORDER)
     return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing takes a constant jump index");
   if (op->prob.kernel == HLEVY_KERNEL_GAUSSIAN)
     return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing follows the window scheme (tempered kernels)");
-  const int n = op->prob.n;
-  if (next < n + 1 || next > (1 << 26)) return fail(HLEVY_ERR_INVALID_ARG, "next must lie in [n + 1, 2^26]");
+  const int n = op->prob.n, dim = op->prob.dim;
+  if (op->S.N != (dim == 1 ? n : n * n))
+    return fail(HLEVY_ERR_INVALID_ARG, "the exterior forcing needs the whole box (no mask)");
+  const int nmax = dim == 1 ? (1 << 26) : (1 << 13);
+  if (next < n + 1 || next > nmax)
+    return fail(HLEVY_ERR_INVALID_ARG, dim == 1 ? "next must lie in [n + 1, 2^26]" : "next must lie in [n + 1, 2^13]");
   if (!std::isfinite(tail_left) || !std::isfinite(tail_right)) return fail(HLEVY_ERR_INVALID_ARG, "non-finite tail");
-  {
-    const double* ul = u_ext;
-    const double* uh = u_ext + 2 * (size_t)next;
-    if (g < uh && ul < g + n) return fail(HLEVY_ERR_INVALID_ARG, "u_ext and g must not overlap");
-  }
+  const size_t next_vals = dim == 1 ? 2 * (size_t)next : (size_t)(n + 2 * next) * (n + 2 * next);
+  const size_t N = op->S.N;
+  if (g < u_ext + next_vals && u_ext < g + N) return fail(HLEVY_ERR_INVALID_ARG, "u_ext and g must not overlap");
   return guarded([&]() -> hlevy_status {
     hipStream_t s = as_stream(stream);
-    DevBuf tab;
-    tab.alloc((2 * (size_t)(n + 1) + 1) * sizeof(double));
-    // the window part from the n + 1 values of each side nearest the box
-    // (contiguous in u_ext), then the far field added row by row
-    HL_CHECK(launch_exterior(op->pd, op->cst.as<double>(), u_ext + (next - (n + 1)), tab.as<double>(), g, s));
-    DevBuf far;
-    far.alloc((2 * (size_t)(next - n) + 2) * sizeof(double));
-    HL_CHECK(launch_far_field(op->pd, u_ext, next, tail_left, tail_right, far.as<double>(), g, s));
+    DevBuf tab, far;
+    if (dim == 1) {
+      // the window part from the n + 1 values of each side nearest the box
+      // (contiguous in u_ext), then the far field added row by row
+      tab.alloc((2 * (size_t)(n + 1) + 1) * sizeof(double));
+      HL_CHECK(launch_exterior(op->pd, op->cst.as<double>(), u_ext + (next - (n + 1)), tab.as<double>(), g, s));
+      far.alloc((2 * (size_t)(next - n) + 2) * sizeof(double));
+      HL_CHECK(launch_far_field(op->pd, u_ext, next, tail_left, tail_right, far.as<double>(), g, s));
+    } else {
+      tab.alloc((size_t)(2 * n + 3) * (2 * n + 3) * sizeof(double));
+      HL_CHECK(launch_exterior2(op->pd, op->cst.as<double>(), u_ext, n + 2 * next, next, tab.as<double>(), g, s));
+      far.alloc(((size_t)(2 * next + 1) * (2 * next + 1) + 2) * sizeof(double));
+      HL_CHECK(launch_far_field2(op->pd, u_ext, next, tail_left, tail_right, far.as<double>(), g, s));
+    }
     HL_CHECK(hipStreamSynchronize(s));
     return HLEVY_OK;
   });

@@ -406,9 +406,11 @@ def exterior_forcing(op: Op, u_ext, g, stream=None):
 def exterior_forcing_far(op: Op, u_ext, next_: int, tail_left: float, tail_right: float, g, stream=None):
     """g = the exterior forcing with the far field f^{L_W}
     (hlevy_exterior_forcing_far; 1D: u_ext holds next_ values left of the
-    box and next_ right of it, beyond them the constant tails)."""
+    box and next_ right of it; 2D: the extended lattice of
+    (n + 2 next_)^2 values; beyond it the constant tails)."""
     n = op.N
-    _check(lib.hlevy_exterior_forcing_far(op.h, _dptr(u_ext, 2 * int(next_)), int(next_), float(tail_left),
+    m = 2 * int(next_) if op.prob.dim == 1 else (op.prob.n + 2 * int(next_)) ** 2
+    _check(lib.hlevy_exterior_forcing_far(op.h, _dptr(u_ext, m), int(next_), float(tail_left),
                                           float(tail_right), _dptr(g, n), _stream(stream)),
            "hlevy_exterior_forcing_far")
 

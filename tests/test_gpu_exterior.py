@@ -201,6 +201,64 @@ def test_far_field_edges_and_constant(H):
 
 
 
+def _assemble2(H, p):
+    prob = H.make_problem(2, p.n, p.lo, p.hi, p.s, lam=p.lam, C_=p.C, a=p.a, b=p.b, c=p.c, r0=p.r0,
+                          lam_neg=p.lam_neg)
+    return H.assemble(prob, H.make_hparams(aca_tol=1e-8, max_rank=32))
+
+
+def _extended2(p, nxt):
+    """A smooth exterior on the 2D lattice of indices -nxt .. n - 1 + nxt."""
+    h = (p.hi - p.lo) / (p.n + 1)
+    idx = np.arange(-nxt, p.n + nxt)
+    A1, A2 = np.meshgrid(p.lo + (idx + 1) * h, p.lo + (idx + 1) * h, indexing="ij")
+    return (np.exp(-0.3 * (A1 ** 2 + A2 ** 2)) * np.cos(A1 - 0.3 * A2)).ravel()
+
+
+@pytest.mark.parametrize("name", list(EXT2))
+def test_far_field_2d_matches_oracle(H, name):
+    """2D hlevy_exterior_forcing_far against the oracle's window forcing plus
+    far field: an extended lattice reaching 9 points past the window, tails
+    0.3 (y1 < 0) and -0.2 (y1 > 0).  FP64 on both sides; the GPU takes the
+    half-plane tails by a 32-node Gauss-Legendre rule per octant of an
+    analytic integrand, the oracle by adaptive quadrature."""
+    p = EXT2[name]
+    op = _assemble2(H, p)
+    n, NW = p.n, p.n + 1
+    nxt = NW + 9
+    ue = _extended2(p, nxt)
+    g = torch.empty(p.N, dtype=torch.float64, device="cuda")
+    H.exterior_forcing_far(op, dev(ue), nxt, 0.3, -0.2, g)
+    side = n + 2 * nxt
+    o = nxt - NW
+    win = ue.reshape(side, side)[o:o + 3 * n + 2, o:o + 3 * n + 2].ravel()
+    ref = exterior_forcing(p, win) + far_field(p, ue, nxt, 0.3, -0.2)
+    assert rel(host(g), ref) <= 1e-12
+
+
+def test_far_field_2d_edges_and_constant(H):
+    """2D: next = n + 1 with zero tails is hlevy_exterior_forcing bit for
+    bit; a constant exterior with the same constant tails completes
+    G c + g + f = 0 through the H-matrix; next below n + 1 is refused."""
+    p = EXT2["tilted2d_n17"]
+    op = _assemble2(H, p)
+    n, NW = p.n, p.n + 1
+    ue = dev(_extended2(p, NW))
+    a = torch.empty(p.N, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    H.exterior_forcing(op, ue, a)
+    H.exterior_forcing_far(op, ue, NW, 0.0, 0.0, b)
+    assert torch.equal(a, b)
+    c = 0.7
+    H.exterior_forcing_far(op, dev(np.full((3 * n + 2) ** 2, c)), NW, c, c, b)
+    y = torch.empty_like(a)
+    H.matvec(op, dev(np.full(p.N, c)), y)
+    scale = float(np.abs(host(b)).max())
+    assert np.abs(host(y) + host(b)).max() <= 1e-7 * scale
+    with pytest.raises(H.HlevyError, match="next"):
+        H.exterior_forcing_far(op, dev(np.zeros((3 * n) ** 2)), n, 0.0, 0.0, b)
+
+
 @pytest.mark.parametrize("dim,lam_neg", [(1, None), (1, 2.0), (2, None), (2, 2.5)])
 def test_tempered_half_index_tail(H, dim, lam_neg):
     """s = 1/2 with tempering: the measure beyond the window needs
