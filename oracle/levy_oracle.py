@@ -17,7 +17,12 @@ What it computes (Xu & Darve, arXiv 1812.08324):
   (LAPACK getrf/getrs through scipy);
 * the steady problems (shift I - G) u = f that the H-LU preconditions in an
   iteration (Sec. 5.1; the fractional Poisson problem of Sec. 5.3 is
-  shift = 0 with the fractional generator), solved by the same dense LU.
+  shift = 0 with the fractional generator), solved by the same dense LU;
+* the forcing of a non-zero exterior (Sec. 4: the window terms that reach
+  outside the box, 1D and 2D) and the far-field term f^{L_W} of
+  equ:I2approx (eq. equ:fxy) on an extended lattice with constant tails;
+* the fixed-rank Taylor factors of the Gaussian kernel's admissible blocks
+  (Sec. 3.3, Lemma 1).
 
 Nothing here is blocked, compressed or reordered: the H-matrix method must
 reproduce these results up to its truncation tolerance.
@@ -35,7 +40,8 @@ Readings of the paper taken here (the paper is garbled or silent on them):
   used here.  Net local term: ``(C2 - S2)/2 * Laplacian_h u``.
 * The window half-width ``L_W`` equals the domain extent, so every in-domain
   offset lies inside the window and the far field ``f^{L_W}`` is zero under
-  the zero-exterior condition (Sec. 4, closing remark).
+  the zero-exterior condition (Sec. 4, closing remark); a non-zero exterior
+  enters through the exterior forcing and the far field below.
 * In 2D the singularity subtraction uses ``int rho nu y_i y_j = delta_ij C2``
   (radial kernel, square window), giving the 5-point Laplacian.
 * Asymmetric 1D measures (rate lam for y > 0, lam_neg for y < 0): the
@@ -50,6 +56,15 @@ Readings of the paper taken here (the paper is garbled or silent on them):
   x_i is the constant-order row with s = s(x_i) and kernel constant
   c_{d,s(x_i)} (its own quadrature constants), and u = 0 on the grid points
   outside the L-shaped domain, so those columns drop out.
+* 2D asymmetric measures: the symmetric kernel tilted along the first
+  axis, C exp(-lam0 |y| + theta y1) / |y|^(2+2s) with lam0 = (lam +
+  lam_neg)/2 and theta = (lam_neg - lam)/2, so that the rates along that
+  axis are those of the 1D measure; the compensator is kept as in 1D and
+  each axis takes its own u'' coefficient.
+* The far field f^{L_W} (which the paper leaves to an input or a
+  quadrature): the trapezoid rule on the extended lattice beyond the window
+  and, past the lattice, a constant per side (1D) or per half-plane of the
+  first axis (2D) times the measure of that region.
 * The closed-form solution of the 1D fractional Poisson problem (Sec. 5.3):
   the paper prints the factor 2^{2s} Gamma(1+s) Gamma((1+2s)/2)/Gamma(1/2)
   in front of (1-x^2)^s.  That factor is (-Delta)^s of (1-x^2)^s (the ball
