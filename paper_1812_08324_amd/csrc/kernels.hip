@@ -2450,42 +2450,63 @@ __global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t
       double* row = col + LUINV_N;
       double* xr = row + LUINV_N;
       double* yc = xr + LUINV_N;
+      // Row i = ty + 32 r of register block r lies below k for r > cb and
+      // above it for r < cb (likewise columns), so only block cb compares
+      // at run time; the pivot's owner forms 1 / U[k, k] once for all.
       if (tx == kk) {
 #pragma unroll
         for (int r = 0; r < LI_R; ++r) {
           const int i = ty + LI_G * r;
-          if (i >= k) col[i] = a[r][cb];
-          if (i < k) yc[i] = z[r][cb];
+          if (r > cb || (r == cb && ty >= kk)) col[i] = a[r][cb];
+          if (r < cb || (r == cb && ty < kk)) yc[i] = z[r][cb];
+        }
+        if (ty == kk) {
+          const double piv = a[cb][cb];
+          zp = zp || piv == 0.0;
+          dinv[k] = 1.0 / piv;
         }
       }
       if (ty == kk) {
 #pragma unroll
         for (int c = 0; c < LI_R; ++c) {
           const int j = tx + LI_G * c;
-          if (j > k) row[j] = a[cb][c];
-          if (j < k) xr[j] = z[cb][c];
+          if (c > cb || (c == cb && tx > kk)) row[j] = a[cb][c];
+          if (c < cb || (c == cb && tx < kk)) xr[j] = z[cb][c];
         }
       }
       __syncthreads();
-      const double piv = col[k];
-      zp = zp || piv == 0.0;
-      const double rinv = 1.0 / piv;
-      if (tid == 0) dinv[k] = rinv;
+      const double rinv = dinv[k];
       double l[LI_R], yk[LI_R], u[LI_R], ub[LI_R], xk[LI_R];
 #pragma unroll
       for (int r = 0; r < LI_R; ++r) {
         const int i = ty + LI_G * r;
-        const double cv = col[i], yv = yc[i];
-        l[r] = i > k ? cv * rinv : 0.0;
-        yk[r] = i < k ? yv : (i == k ? 1.0 : 0.0);
+        if (r > cb) {
+          l[r] = col[i] * rinv;
+          yk[r] = 0.0;
+        } else if (r < cb) {
+          l[r] = 0.0;
+          yk[r] = yc[i];
+        } else {
+          const double cv = col[i], yv = yc[i];
+          l[r] = ty > kk ? cv * rinv : 0.0;
+          yk[r] = ty < kk ? yv : (ty == kk ? 1.0 : 0.0);
+        }
       }
 #pragma unroll
       for (int c = 0; c < LI_R; ++c) {
         const int j = tx + LI_G * c;
-        const double rv = row[j], xv = xr[j];
-        u[c] = j > k ? rv : 0.0;
+        if (c > cb) {
+          u[c] = row[j];
+          xk[c] = 0.0;
+        } else if (c < cb) {
+          u[c] = 0.0;
+          xk[c] = xr[j];
+        } else {
+          const double rv = row[j], xv = xr[j];
+          u[c] = tx > kk ? rv : 0.0;
+          xk[c] = tx < kk ? xv : (tx == kk ? 1.0 : 0.0);
+        }
         ub[c] = u[c] * rinv;
-        xk[c] = j < k ? xv : (j == k ? 1.0 : 0.0);
       }
       // register block (r, c) holds rows ty + 32 r, columns tx + 32 c: rows
       // of blocks r < cb and columns of blocks c < cb are <= k, those of
@@ -2549,7 +2570,7 @@ __global__ void __launch_bounds__(LI_T) k_lu_inv(const LuInvItem* items, int32_t
         it.U22[(i - m1) + m2 * (j - m1)] = v;
     }
   }
-  if (tid == 0 && zp) atomicAdd(zero_pivot, 1);
+  if (zp) atomicAdd(zero_pivot, 1);   // the owner of a zero pivot
 }
 
 // ---------------------------------------------------------------------------
