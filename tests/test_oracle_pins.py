@@ -927,3 +927,50 @@ def test_far_field_2d_trapezoid_converges_to_the_integral():
                                     limit=200)[0] for q in range(8))
         errs.append(abs(f[i1 * n + i2] - ex) / abs(ex))
     assert _order(errs[0], errs[1]) > 1.7 and _order(errs[1], errs[2]) > 1.7, errs
+
+
+def _upper_gamma_neg(a: float, x: float) -> float:
+    """Gamma(a, x) for -2 < a < 0 by Gamma(b + 1, x) = b Gamma(b, x) + x^b e^-x
+    from a positive index (scipy's regularised gammaincc), or E1 at a = 0."""
+    def g(b):
+        if b > 0:
+            return sp.gammaincc(b, x) * sp.gamma(b)
+        if b == 0:
+            return sp.exp1(x)
+        return (g(b + 1) - x ** b * math.exp(-x)) / b
+    return g(a)
+
+
+@pytest.mark.parametrize("lam_neg", [None, 2.2])
+def test_far_field_2d_half_plane_tails_closed_form(lam_neg):
+    """2D: each half-plane tail of the far field (zero lattice, tail 1 on one
+    side) equals the measure of that half of |y|_inf > next h written with
+    the radial integral in closed form, C mu^{2s} Gamma(-2s, mu r0(phi))
+    with mu = lam0 - theta cos(phi) and r0 = next h / max(|cos|, |sin|),
+    and a 64-node Gauss-Legendre rule in the angle on each of the four
+    octants; the oracle integrates the kernel itself adaptively."""
+    p = Problem(dim=2, n=8, lo=-1.0, hi=1.0, s=0.55, lam=0.6, lam_neg=lam_neg, C=0.5, a=0.03, b=(0.2, -0.3))
+    NW = p.n + 1
+    nxt = NW + 3
+    side = p.n + 2 * nxt
+    h = h_of(p)
+    R = nxt * h
+    lam0 = 0.5 * (p.lam + lam_neg) if lam_neg is not None else p.lam
+    th = 0.5 * (lam_neg - p.lam) if lam_neg is not None else 0.0
+    x, w = np.polynomial.legendre.leggauss(64)
+
+    def half(base):
+        acc = 0.0
+        for q in range(4):
+            for xg, wg in zip(x, w):
+                phi = base + q * math.pi / 4 + math.pi / 8 * (xg + 1.0)
+                cs, sn = math.cos(phi), math.sin(phi)
+                mu = lam0 - th * cs
+                r0 = R / max(abs(cs), abs(sn))
+                acc += math.pi / 8 * wg * mu ** (2 * p.s) * _upper_gamma_neg(-2 * p.s, mu * r0)
+        return p.Cval * acc
+
+    right = far_field(p, np.zeros(side * side), nxt, 0.0, 1.0)
+    left = far_field(p, np.zeros(side * side), nxt, 1.0, 0.0)
+    assert np.allclose(right, half(-math.pi / 2), rtol=1e-10, atol=0)   # y1 > 0
+    assert np.allclose(left, half(math.pi / 2), rtol=1e-10, atol=0)     # y1 < 0
