@@ -331,7 +331,9 @@ hlevy_status hlevy_exterior_forcing(const hlevy_op* op, const double* u_ext, dou
  * measure with its angle-dependent rate).  u_ext (device,
  * (n + 2 next)^2 values): the extended lattice of indices
  * -next .. n - 1 + next per axis, first coordinate slowest; entries inside
- * the box are not read; n + 1 <= next <= 2^13.
+ * the box are not read; n + 1 <= next <= 2^13.  Work: O(n * next) in 1D,
+ * O(n^2 * next^2) in 2D (every row sums its whole extended square), and a
+ * device table of (2 next + 1)^2 doubles in 2D.
  * With next = n + 1 and zero tails the result is hlevy_exterior_forcing's;
  * with a constant exterior c (tails c) G c + g + f = 0 in every row.
  * Errors as hlevy_exterior_forcing, and HLEVY_ERR_INVALID_ARG for next out
